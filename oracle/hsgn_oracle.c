@@ -1,0 +1,1018 @@
+/*
+ * hsgn_oracle.c -- plain FP64 CPU oracle of the HSGN/SWE time step.
+ *
+ * TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the CPU
+ * baseline timing of the benchmark load this file's library.  It shares no
+ * source, header, table or helper with the GPU library.
+ *
+ * Everything here is written for a reader holding the paper:
+ *   model      Sec. 3, eq. (HSGN), written in 2D with u = (u, v) and the
+ *              scalar sigma = -h div(u) (Sec. 2 notes that the 2D extension
+ *              is straightforward);
+ *   splitting  Sec. 4: hyperbolic part and algebraic source are split
+ *              (Strang by default, Lie selectable);
+ *   hyperbolic Sec. 4, eq. (total fluctuation): f-wave decomposition of
+ *              F(Q_R) - F(Q_L) plus one-point (Roe-state) quadrature of the
+ *              non-conservative and bathymetry integrals, Roe-type averages,
+ *              bathymetry sharpness sensor psi, Einfeldt speeds, eigenvectors
+ *              of Appendix C; limited second-order corrections (minmod, MC)
+ *              and a transverse Riemann solver (wave propagation, Sec. 4);
+ *   source     Sec. 4: per-cell linear ODE in (hw, h sigma, hp, h p_b),
+ *              integrated with the two-stage L-stable SDIRK(2,2) method;
+ *   SWE switch Sec. 3.3 and Sec. 4 (transition function): c^2 = alpha^2 g
+ *              H phi_T; cells with phi_T = 0, dry cells and cells latched as
+ *              breaking carry no auxiliary variables.
+ *   CFL        Sec. 4: global maximum wave speed.
+ *
+ * Readings of points the paper leaves open (c^2 = alpha^2 g H; 2D form;
+ * wet/dry states; breaking latch; transverse construction; s = 0 split) are
+ * listed in the design notes of the repository and marked at each use below.
+ *
+ * No blocking, fusion or reordering: every step runs over the whole grid and
+ * stores its results in plain arrays before the next step starts.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "hsgn_oracle.h"
+
+enum { IH = 0, IHU = 1, IHV = 2, IHW = 3, IHS = 4, IHP = 5, IHPB = 6 };
+
+struct orc_grid {
+    orc_params P;
+    int nx, ny, sx, sy;         /* sx = nx + 4, sy = ny + 4: two ghost layers */
+    double x0, y0, dx, dy;
+    int bc[4];
+    double *q;                  /* [7][sy][sx] */
+    double *b;                  /* [sy][sx] */
+    unsigned char *phi;         /* [sy][sx] transition function phi_T */
+    unsigned char *brk;         /* [sy][sx] breaking latch */
+    double t, dt_next;
+    long long nstep, nrej;
+    int have_dt;
+    double clipped;
+    int ngauge;
+    double *gxy;
+    int nrec, caprec;
+    double *rec_t, *rec_eta;
+    /* per-step work arrays, allocated on the first step */
+    double *w_qs, *w_c2, *w_Flim, *w_Ftr, *w_Glim, *w_Gtr, *w_clip;
+    struct edge_s *w_EX, *w_EY;
+};
+
+#define CELL(g, i, j) ((size_t)((j) + 2) * (size_t)(g)->sx + (size_t)((i) + 2))
+#define PLANE(g) ((size_t)(g)->sx * (size_t)(g)->sy)
+
+/* ------------------------------------------------------------------ */
+/* boundary conditions: index map of a ghost cell onto an interior cell */
+
+static int map_index(int i, int n, int lo, int hi, int *flip)
+{
+    *flip = 0;
+    if (i < 0) {
+        if (lo == ORC_BC_PERIODIC) return i + n;
+        if (lo == ORC_BC_WALL) { *flip = 1; return -1 - i; }
+        return 0;
+    }
+    if (i >= n) {
+        if (hi == ORC_BC_PERIODIC) return i - n;
+        if (hi == ORC_BC_WALL) { *flip = 1; return 2 * n - 1 - i; }
+        return n - 1;
+    }
+    return i;
+}
+
+/* fill the two ghost layers of q, b, phi and the latch from the interior */
+static void fill_ghosts(orc_grid *g)
+{
+    size_t np = PLANE(g);
+    for (int j = -2; j < g->ny + 2; j++) {
+        for (int i = -2; i < g->nx + 2; i++) {
+            if (i >= 0 && i < g->nx && j >= 0 && j < g->ny) continue;
+            int fx, fy;
+            int mi = map_index(i, g->nx, g->bc[0], g->bc[1], &fx);
+            int mj = map_index(j, g->ny, g->bc[2], g->bc[3], &fy);
+            size_t d = CELL(g, i, j), s = CELL(g, mi, mj);
+            for (int m = 0; m < ORC_NV; m++) g->q[m * np + d] = g->q[m * np + s];
+            if (fx) g->q[IHU * np + d] = -g->q[IHU * np + d];
+            if (fy) g->q[IHV * np + d] = -g->q[IHV * np + d];
+            g->b[d] = g->b[s];
+            g->phi[d] = g->phi[s];
+            g->brk[d] = g->brk[s];
+        }
+    }
+}
+
+/* still-water depth H = (eta0 - b)^+ */
+static double still_depth(const orc_params *P, double b)
+{
+    double H = P->eta0 - b;
+    return H > 0.0 ? H : 0.0;
+}
+
+/* c^2 = alpha^2 g H phi_T, zero in SWE cells (phi_T = 0 or breaking) */
+static double cell_c2(const orc_grid *g, size_t k)
+{
+    if (!g->phi[k] || g->brk[k]) return 0.0;
+    return g->P.alpha * g->P.alpha * g->P.g * still_depth(&g->P, g->b[k]);
+}
+
+/* ------------------------------------------------------------------ */
+/* creation, data in and out                                           */
+
+orc_grid *orc_create(const orc_params *p, int nx, int ny, double x0, double y0,
+                     double dx, double dy, const int bc[4])
+{
+    if (!p || nx < 4 || ny < 4 || !(dx > 0) || !(dy > 0)) return NULL;
+    if ((bc[0] == ORC_BC_PERIODIC) != (bc[1] == ORC_BC_PERIODIC)) return NULL;
+    if ((bc[2] == ORC_BC_PERIODIC) != (bc[3] == ORC_BC_PERIODIC)) return NULL;
+    if (p->nbr_n < 0 || p->nbr_n > 2) return NULL;
+    orc_grid *g = (orc_grid *)calloc(1, sizeof(orc_grid));
+    if (!g) return NULL;
+    g->P = *p;
+    g->nx = nx; g->ny = ny; g->sx = nx + 4; g->sy = ny + 4;
+    g->x0 = x0; g->y0 = y0; g->dx = dx; g->dy = dy;
+    memcpy(g->bc, bc, 4 * sizeof(int));
+    size_t np = PLANE(g);
+    g->q = (double *)calloc(ORC_NV * np, sizeof(double));
+    g->b = (double *)calloc(np, sizeof(double));
+    g->phi = (unsigned char *)calloc(np, 1);
+    g->brk = (unsigned char *)calloc(np, 1);
+    if (!g->q || !g->b || !g->phi || !g->brk) { orc_destroy(g); return NULL; }
+    return g;
+}
+
+void orc_destroy(orc_grid *g)
+{
+    if (!g) return;
+    free(g->q); free(g->b); free(g->phi); free(g->brk);
+    free(g->gxy); free(g->rec_t); free(g->rec_eta);
+    free(g->w_qs); free(g->w_c2); free(g->w_Flim); free(g->w_Ftr);
+    free(g->w_Glim); free(g->w_Gtr); free(g->w_clip); free(g->w_EX); free(g->w_EY);
+    free(g);
+}
+
+/* bathymetry and the transition function phi_T (eq. transition function):
+ * phi_T = 1 iff the minimum of H over the cells within n cells (max-norm box)
+ * exceeds h_star. */
+int orc_set_bathymetry(orc_grid *g, const double *b)
+{
+    for (int j = 0; j < g->ny; j++)
+        for (int i = 0; i < g->nx; i++)
+            g->b[CELL(g, i, j)] = b[(size_t)j * g->nx + i];
+    int n = g->P.nbr_n;
+    for (int j = 0; j < g->ny; j++) {
+        for (int i = 0; i < g->nx; i++) {
+            double hmin = INFINITY;
+            for (int dj = -n; dj <= n; dj++) {
+                for (int di = -n; di <= n; di++) {
+                    int fx, fy;
+                    int mi = map_index(i + di, g->nx, g->bc[0], g->bc[1], &fx);
+                    int mj = map_index(j + dj, g->ny, g->bc[2], g->bc[3], &fy);
+                    double H = still_depth(&g->P, g->b[CELL(g, mi, mj)]);
+                    if (H < hmin) hmin = H;
+                }
+            }
+            g->phi[CELL(g, i, j)] = (hmin > g->P.h_star) ? 1 : 0;
+            g->brk[CELL(g, i, j)] = 0;
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_set_state(orc_grid *g, const double *q)
+{
+    size_t np = PLANE(g), nn = (size_t)g->nx * g->ny;
+    for (int m = 0; m < ORC_NV; m++)
+        for (int j = 0; j < g->ny; j++)
+            for (int i = 0; i < g->nx; i++)
+                g->q[m * np + CELL(g, i, j)] = q[m * nn + (size_t)j * g->nx + i];
+    return ORC_OK;
+}
+
+int orc_get_state(const orc_grid *g, double *q)
+{
+    size_t np = PLANE(g), nn = (size_t)g->nx * g->ny;
+    for (int m = 0; m < ORC_NV; m++)
+        for (int j = 0; j < g->ny; j++)
+            for (int i = 0; i < g->nx; i++)
+                q[m * nn + (size_t)j * g->nx + i] = g->q[m * np + CELL(g, i, j)];
+    return ORC_OK;
+}
+
+int orc_get_mask(const orc_grid *g, unsigned char *m)
+{
+    for (int j = 0; j < g->ny; j++)
+        for (int i = 0; i < g->nx; i++) {
+            size_t k = CELL(g, i, j);
+            m[(size_t)j * g->nx + i] = (unsigned char)(g->phi[k] | (g->brk[k] << 1));
+        }
+    return ORC_OK;
+}
+
+int orc_set_mask(orc_grid *g, const unsigned char *m)
+{
+    for (int j = 0; j < g->ny; j++)
+        for (int i = 0; i < g->nx; i++) {
+            size_t k = CELL(g, i, j);
+            g->phi[k] = m[(size_t)j * g->nx + i] & 1;
+            g->brk[k] = (m[(size_t)j * g->nx + i] >> 1) & 1;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* source step (Sec. 4): dY/dt = (1/h) M Y for Y = (hw, h sigma, hp, h p_b),
+ * read off the right-hand side of eq. (HSGN):
+ *   d(hw)/dt      = p_b
+ *   d(h sigma)/dt = -6 p_b + 12 p
+ *   d(hp)/dt      = -c^2 sigma
+ *   d(h p_b)/dt   = -6 c^2 (w - sigma/2)
+ * integrated with the two-stage SDIRK(2,2) method with
+ * gamma = 1 - 1/sqrt(2): Y1 = Y + gamma tau f(Y1),
+ * Y2 = Y + (1-gamma) tau f(Y1) + gamma tau f(Y2), result Y2. */
+
+/* Gaussian elimination with partial pivoting; b is overwritten by x */
+static void solve4(double A[4][4], double b[4])
+{
+    for (int k = 0; k < 4; k++) {
+        int piv = k;
+        for (int r = k + 1; r < 4; r++)
+            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+        if (piv != k) {
+            for (int c = 0; c < 4; c++) { double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t; }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int r = k + 1; r < 4; r++) {
+            double f = A[r][k] / A[k][k];
+            for (int c = k; c < 4; c++) A[r][c] -= f * A[k][c];
+            b[r] -= f * b[k];
+        }
+    }
+    for (int k = 3; k >= 0; k--) {
+        double s = b[k];
+        for (int c = k + 1; c < 4; c++) s -= A[k][c] * b[c];
+        b[k] = s / A[k][k];
+    }
+}
+
+void orc_source_cell(double *q, double c2, double tau)
+{
+    double h = q[IH];
+    double M[4][4] = {
+        {0.0, 0.0, 0.0, 1.0},
+        {0.0, 0.0, 12.0, -6.0},
+        {0.0, -c2, 0.0, 0.0},
+        {-6.0 * c2, 3.0 * c2, 0.0, 0.0},
+    };
+    double J[4][4];
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) J[r][c] = (tau / h) * M[r][c];
+    double gam = 1.0 - 1.0 / sqrt(2.0);
+    double A[4][4];
+    double Y[4] = {q[IHW], q[IHS], q[IHP], q[IHPB]};
+    /* stage 1: (I - gamma J) Y1 = Y */
+    double Y1[4] = {Y[0], Y[1], Y[2], Y[3]};
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) A[r][c] = (r == c ? 1.0 : 0.0) - gam * J[r][c];
+    solve4(A, Y1);
+    /* stage 2: (I - gamma J) Y2 = Y + (1 - gamma) J Y1 */
+    double Y2[4];
+    for (int r = 0; r < 4; r++) {
+        double s = 0.0;
+        for (int c = 0; c < 4; c++) s += J[r][c] * Y1[c];
+        Y2[r] = Y[r] + (1.0 - gam) * s;
+    }
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) A[r][c] = (r == c ? 1.0 : 0.0) - gam * J[r][c];
+    solve4(A, Y2);
+    q[IHW] = Y2[0]; q[IHS] = Y2[1]; q[IHP] = Y2[2]; q[IHPB] = Y2[3];
+}
+
+/* apply the source step of length tau to one cell, or clear the auxiliary
+ * variables of a dry or SWE cell (SWE region: c^2 -> 0 with p -> 0) */
+static void source_or_clear(orc_grid *g, size_t k, double tau, double *qc)
+{
+    int wet = qc[IH] > g->P.dry_tol;
+    int swe = !g->phi[k] || g->brk[k];
+    if (wet && !swe) {
+        orc_source_cell(qc, cell_c2(g, k), tau);
+    } else {
+        qc[IHW] = 0.0; qc[IHS] = 0.0; qc[IHP] = 0.0; qc[IHPB] = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* normal Riemann solver (Sec. 4, eq. total fluctuation; Appendix C)
+ *
+ * Works in the edge's normal frame: q = (h, h u_n, h u_t, hw, h sigma, hp,
+ * h p_b).  The y-direction solve permutes hu and hv before and after. */
+
+typedef struct {
+    double uh, vh, wh, sh, ph, pbh;  /* Roe-type averages, normal frame */
+    double hh, c2h, ce2;             /* arithmetic means, Ce^2 */
+    double smin, smax;               /* Einfeldt speeds */
+    int wet;                         /* both cells wet: usable for splitting */
+} eig_t;
+
+typedef struct edge_s {
+    double Z[7][7];     /* Z[p][m]: f-wave p, component m (normal frame) */
+    double s[7];        /* speed of f-wave p */
+    double amdq[7], apdq[7];
+    int kind;           /* 0 regular, 1 wall (right dry), 2 wall (left dry), 3 dry */
+    eig_t e;
+} edge_t;
+
+/* bathymetry sharpness sensor psi(b_i, b_{i-1}) of Sec. 4 */
+static double sensor(const orc_params *P, double bL, double bR)
+{
+    double db = bR - bL;
+    if (db == 0.0) return 1.0;
+    double sum = fabs(bR + bL);
+    if (sum == 0.0) return 0.0;
+    double xi = 2.0 * fabs(db) / sum;
+    if (xi < P->xi0) return 1.0;
+    if (xi < P->xi0 + P->xi1) {
+        double r = (xi - P->xi0) / P->xi1;
+        return -3.0 * r * r + 2.0 * r * r * r + 1.0;
+    }
+    return 0.0;
+}
+
+typedef struct {
+    double h, hun, un, ut, w, sg, p, pb, hp;
+} side_t;
+
+/* primitive variables of one side; a dry side (h <= dry_tol) keeps its
+ * depth, so that a thin film at rest stays in balance, and has zero velocity
+ * and auxiliary variables */
+static void side_from_q(const orc_params *P, const double *q, side_t *s)
+{
+    memset(s, 0, sizeof(*s));
+    s->h = q[IH] > 0.0 ? q[IH] : 0.0;
+    if (q[IH] > P->dry_tol) {
+        s->h = q[IH];
+        s->hun = q[IHU];
+        s->un = q[IHU] / q[IH];
+        s->ut = q[IHV] / q[IH];
+        s->w = q[IHW] / q[IH];
+        s->sg = q[IHS] / q[IH];
+        s->p = q[IHP] / q[IH];
+        s->pb = q[IHPB] / q[IH];
+        s->hp = q[IHP];
+    }
+}
+
+static int riemann_n(const orc_params *P, const double *qL, const double *qR,
+                     double bL, double bR, double c2L, double c2R, edge_t *E)
+{
+    const double g = P->g;
+    memset(E, 0, sizeof(*E));
+    int wetL = qL[IH] > P->dry_tol, wetR = qR[IH] > P->dry_tol;
+    if (!wetL && !wetR) { E->kind = 3; return ORC_OK; }
+
+    side_t L, R;
+    side_from_q(P, qL, &L);
+    side_from_q(P, qR, &R);
+    double bl = bL, br = bR, cl = c2L, cr = c2R;
+    int dryL = 0, dryR = 0;
+    /* wet/dry states: a dry neighbour whose bed lies above the wet side's
+     * surface acts as a wall (mirror state); otherwise the dry side enters
+     * at rest with its own (thin) depth and the dry-front speed bounds the
+     * fan. */
+    if (wetL && !wetR) {
+        if (qL[IH] + bL < bR) {
+            E->kind = 1;
+            R = L; R.hun = -L.hun; R.un = -L.un;
+            br = bl; cr = cl;
+        } else {
+            dryR = 1;
+        }
+    } else if (!wetL && wetR) {
+        if (qR[IH] + bR < bL) {
+            E->kind = 2;
+            L = R; L.hun = -R.hun; L.un = -R.un;
+            bl = br; cl = cr;
+        } else {
+            dryL = 1;
+        }
+    }
+
+    /* Roe-type interface state: arithmetic means of h and c^2, sqrt(h)
+     * weighted means of the primitive variables */
+    double sqL = sqrt(L.h), sqR = sqrt(R.h);
+    double den = sqL + sqR;
+    double hh = 0.5 * (L.h + R.h);
+    double c2h = 0.5 * (cl + cr);
+    double uh = (sqR * R.un + sqL * L.un) / den;
+    double vh = (sqR * R.ut + sqL * L.ut) / den;
+    double wh = (sqR * R.w + sqL * L.w) / den;
+    double sh = (sqR * R.sg + sqL * L.sg) / den;
+    double ph = (sqR * R.p + sqL * L.p) / den;
+    double pbh = (sqR * R.pb + sqL * L.pb) / den;
+
+    double psi = sensor(P, bl, br);
+    double db = br - bl;
+    double dh = R.h - L.h;
+    double deta = (R.h + br) - (L.h + bl);
+
+    /* total fluctuation: flux difference plus one-point quadrature of the
+     * non-conservative products and bathymetry terms at the Roe state.
+     * The hydrostatic part is written as g h^ (Delta eta), which equals
+     * Delta(g h^2 / 2) + g h^ Delta b exactly. */
+    double df[7];
+    df[0] = R.hun - L.hun;
+    df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * pbh * db;
+    df[2] = R.hun * R.ut - L.hun * L.ut;
+    df[3] = R.hun * R.w - L.hun * L.w;
+    df[4] = R.hun * R.sg - L.hun * L.sg;
+    df[5] = (R.hun * (R.p + cr) - L.hun * (L.p + cl)) - c2h * uh * dh;
+    df[6] = (R.hun * R.pb - L.hun * L.pb) - 6.0 * c2h * uh * psi * db;
+
+    /* Einfeldt speeds from the eigenvalue bound u +- sqrt(g h + p + c^2) */
+    double ce2 = g * hh + ph + c2h;
+    if (!(ce2 > 0.0)) return ORC_ENONHYP;
+    double ceh = sqrt(ce2);
+    double smin, smax;
+    if (dryL) {
+        smin = R.un - 2.0 * sqrt(g * R.h);
+    } else {
+        double a = g * L.h + L.p + cl;
+        if (a < 0.0) return ORC_ENONHYP;
+        smin = fmin(uh - ceh, L.un - sqrt(a));
+    }
+    if (dryR) {
+        smax = L.un + 2.0 * sqrt(g * L.h);
+    } else {
+        double a = g * R.h + R.p + cr;
+        if (a < 0.0) return ORC_ENONHYP;
+        smax = fmax(uh + ceh, R.un + sqrt(a));
+    }
+
+    if (cl == 0.0 && cr == 0.0) {
+        /* SWE edge (both cells in the SWE region).  The paper leaves this
+         * region to a robust SWE solver; here: the HLLE solver in
+         * fluctuation form, whose two waves carry the state jump as well as
+         * the flux difference (which supplies the entropy dissipation a pure
+         * flux-difference split lacks at transonic rarefactions), with the
+         * surface elevation in place of h in the state jump so that the
+         * ocean at rest stays exactly at rest.  Remaining components travel
+         * as contacts at the Roe speed. */
+        double ds = smax - smin;
+        double dq0 = deta, dq1 = R.hun - L.hun;
+        double z1h = smin * ((smax * dq0 - df[0]) / ds);
+        double z1m = smin * ((smax * dq1 - df[1]) / ds);
+        double z7h = smax * ((df[0] - smin * dq0) / ds);
+        double z7m = smax * ((df[1] - smin * dq1) / ds);
+        double S = z1h + z7h;
+        double r1[7] = {z1h, z1m, vh * z1h, wh * z1h, sh * z1h, ph * z1h, pbh * z1h};
+        double r7[7] = {z7h, z7m, vh * z7h, wh * z7h, sh * z7h, ph * z7h, pbh * z7h};
+        for (int m = 0; m < 7; m++) { E->Z[0][m] = r1[m]; E->Z[6][m] = r7[m]; }
+        E->Z[1][IHP] = df[5] - ph * S;
+        E->Z[2][IHS] = df[4] - sh * S;
+        E->Z[3][IHW] = df[3] - wh * S;
+        E->Z[4][IHV] = df[2] - vh * S;
+        E->Z[5][IHPB] = df[6] - pbh * S;
+    } else {
+    /* f-wave coefficients: eigenvectors of Appendix C with the Einfeldt
+     * speeds in place of u -+ Ce in the two acoustic eigenvectors */
+    double b2 = ((c2h + ph) * df[0] - df[5]) / ce2;
+    double S = df[0] - b2;
+    double T = df[1] - uh * b2;
+    double b1 = (smax * S - T) / (smax - smin);
+    double b7 = (T - smin * S) / (smax - smin);
+    double bs = df[4] - sh * S;
+    double bw = df[3] - wh * S;
+    double bv = df[2] - vh * S;
+    double bpb = df[6] - pbh * S;
+
+    double r1[7] = {1.0, smin, vh, wh, sh, c2h + ph, pbh};
+    double r2[7] = {1.0, uh, 0.0, 0.0, 0.0, -g * hh, 0.0};
+    double r7[7] = {1.0, smax, vh, wh, sh, c2h + ph, pbh};
+    for (int m = 0; m < 7; m++) {
+        E->Z[0][m] = b1 * r1[m];
+        E->Z[1][m] = b2 * r2[m];
+        E->Z[6][m] = b7 * r7[m];
+    }
+    E->Z[2][IHS] = bs;
+    E->Z[3][IHW] = bw;
+    E->Z[4][IHV] = bv;
+    E->Z[5][IHPB] = bpb;
+    }
+    E->s[0] = smin;
+    for (int p = 1; p < 6; p++) E->s[p] = uh;
+    E->s[6] = smax;
+
+    /* fluctuations; a wave of speed exactly zero is split half and half */
+    for (int m = 0; m < 7; m++) {
+        double am = 0.0, ap = 0.0;
+        for (int p = 0; p < 7; p++) {
+            if (E->s[p] < 0.0) am += E->Z[p][m];
+            else if (E->s[p] > 0.0) ap += E->Z[p][m];
+            else { am += 0.5 * E->Z[p][m]; ap += 0.5 * E->Z[p][m]; }
+        }
+        E->amdq[m] = am;
+        E->apdq[m] = ap;
+    }
+    if (E->kind == 1) for (int m = 0; m < 7; m++) E->apdq[m] = 0.0;
+    if (E->kind == 2) for (int m = 0; m < 7; m++) E->amdq[m] = 0.0;
+
+    E->e.uh = uh; E->e.vh = vh; E->e.wh = wh; E->e.sh = sh; E->e.ph = ph; E->e.pbh = pbh;
+    E->e.hh = hh; E->e.c2h = c2h; E->e.ce2 = ce2; E->e.smin = smin; E->e.smax = smax;
+    E->e.wet = wetL && wetR;
+    return ORC_OK;
+}
+
+/* swap the hu and hv components (frame change between x and y edges) */
+static void swap_uv(double *v)
+{
+    double t = v[IHU]; v[IHU] = v[IHV]; v[IHV] = t;
+}
+
+/* y-edge solve: permute into the normal frame, solve, permute back */
+static int riemann_y(const orc_params *P, const double *qL, const double *qR,
+                     double bL, double bR, double c2L, double c2R, edge_t *E)
+{
+    double a[7], c[7];
+    memcpy(a, qL, sizeof(a)); memcpy(c, qR, sizeof(c));
+    swap_uv(a); swap_uv(c);
+    int rc = riemann_n(P, a, c, bL, bR, c2L, c2R, E);
+    for (int p = 0; p < 7; p++) swap_uv(E->Z[p]);
+    swap_uv(E->amdq); swap_uv(E->apdq);
+    return rc;
+}
+
+int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
+                  double bL, double bR, double c2L, double c2R,
+                  double *waves, double *speeds, double *amdq, double *apdq,
+                  int *kind)
+{
+    edge_t E;
+    int rc = riemann_n(p, qL, qR, bL, bR, c2L, c2R, &E);
+    for (int q = 0; q < 7; q++) {
+        for (int m = 0; m < 7; m++) waves[q * 7 + m] = E.Z[q][m];
+        speeds[q] = E.s[q];
+    }
+    memcpy(amdq, E.amdq, sizeof(E.amdq));
+    memcpy(apdq, E.apdq, sizeof(E.apdq));
+    *kind = E.kind;
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* transverse splitting: decompose a vector a, given in the normal frame of
+ * the splitting edge, on that edge's eigenvectors (same closed form as the
+ * normal solve) and return the part moving in direction sgn (B+ or B-) */
+static void trans_split(const orc_params *P, const eig_t *e, const double *a,
+                        int sgn, double *out)
+{
+    double g2 = ((e->c2h + e->ph) * a[0] - a[5]) / e->ce2;
+    double S = a[0] - g2;
+    double T = a[1] - e->uh * g2;
+    double g1 = (e->smax * S - T) / (e->smax - e->smin);
+    double g7 = (T - e->smin * S) / (e->smax - e->smin);
+    double gt = a[2] - e->vh * S;
+    double gw = a[3] - e->wh * S;
+    double gs = a[4] - e->sh * S;
+    double gpb = a[6] - e->pbh * S;
+    double s1 = sgn > 0 ? fmax(e->smin, 0.0) : fmin(e->smin, 0.0);
+    double sm = sgn > 0 ? fmax(e->uh, 0.0) : fmin(e->uh, 0.0);
+    double s7 = sgn > 0 ? fmax(e->smax, 0.0) : fmin(e->smax, 0.0);
+    double r1[7] = {1.0, e->smin, e->vh, e->wh, e->sh, e->c2h + e->ph, e->pbh};
+    double r2[7] = {1.0, e->uh, 0.0, 0.0, 0.0, -P->g * e->hh, 0.0};
+    double r7[7] = {1.0, e->smax, e->vh, e->wh, e->sh, e->c2h + e->ph, e->pbh};
+    double mid[7] = {g2 * r2[0], g2 * r2[1], gt, gw, gs, g2 * r2[5], gpb};
+    for (int m = 0; m < 7; m++)
+        out[m] = s1 * g1 * r1[m] + sm * mid[m] + s7 * g7 * r7[m];
+}
+
+/* x-edge fluctuation a (global frame) split by a y-edge (normal frame = y) */
+static void split_by_y(const orc_params *P, const eig_t *e, const double *a,
+                       int sgn, double *out)
+{
+    double t[7];
+    memcpy(t, a, sizeof(t));
+    swap_uv(t);
+    trans_split(P, e, t, sgn, out);
+    swap_uv(out);
+}
+
+/* ------------------------------------------------------------------ */
+/* wave limiter (Sec. 4): minmod or MC applied to each f-wave family */
+static double limiter_phi(int lim, double th)
+{
+    switch (lim) {
+    case 1: return fmax(0.0, fmin(1.0, th));
+    case 2: return fmax(0.0, fmin(fmin(0.5 * (1.0 + th), 2.0), 2.0 * th));
+    case 3: return 1.0;
+    default: return 0.0;
+    }
+}
+
+static double dot7(const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int m = 0; m < 7; m++) s += a[m] * b[m];
+    return s;
+}
+
+/* limited second-order correction F~ = 1/2 sum_p sgn(s_p)(1 - dt/dx |s_p|) Z~_p
+ * of edge E with upwind neighbours El (left/below) and Er (right/above);
+ * the Z are in the global frame */
+static void correction(int lim, double dtdx, const edge_t *El, const edge_t *E,
+                       const edge_t *Er, double *F)
+{
+    for (int m = 0; m < 7; m++) F[m] = 0.0;
+    if (lim == 0 || E->kind != 0) return;
+    for (int p = 0; p < 7; p++) {
+        double zz = dot7(E->Z[p], E->Z[p]);
+        if (zz == 0.0) continue;
+        const edge_t *U = E->s[p] > 0.0 ? El : Er;
+        double th = dot7(U->Z[p], E->Z[p]) / zz;
+        double ph = limiter_phi(lim, th);
+        double sg = E->s[p] > 0.0 ? 1.0 : (E->s[p] < 0.0 ? -1.0 : 0.0);
+        double c = 0.5 * sg * (1.0 - dtdx * fabs(E->s[p])) * ph;
+        for (int m = 0; m < 7; m++) F[m] += c * E->Z[p][m];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* one step                                                             */
+
+int orc_step(orc_grid *g, double dt, double *courant)
+{
+    const orc_params *P = &g->P;
+    const int nx = g->nx, ny = g->ny;
+    const size_t np = PLANE(g);
+    const double dtdx = dt / g->dx, dtdy = dt / g->dy;
+    const int nxe = nx + 3, nye = nx + 2;          /* edges per row */
+    const size_t nex = (size_t)nxe * (ny + 2);     /* x-edges, rows -1..ny */
+    const size_t ney = (size_t)nye * (ny + 3);     /* y-edges, rows -1..ny+1 */
+    int rc = ORC_OK;
+
+    if (!g->w_qs) {
+        g->w_qs = (double *)malloc(ORC_NV * np * sizeof(double));
+        g->w_c2 = (double *)malloc(np * sizeof(double));
+        g->w_EX = (edge_t *)malloc(nex * sizeof(edge_t));
+        g->w_EY = (edge_t *)malloc(ney * sizeof(edge_t));
+        g->w_Flim = (double *)malloc(nex * 7 * sizeof(double));
+        g->w_Ftr = (double *)malloc(nex * 7 * sizeof(double));
+        g->w_Glim = (double *)malloc(ney * 7 * sizeof(double));
+        g->w_Gtr = (double *)malloc(ney * 7 * sizeof(double));
+        g->w_clip = (double *)malloc((size_t)ny * sizeof(double));
+        if (!g->w_qs || !g->w_c2 || !g->w_EX || !g->w_EY || !g->w_Flim || !g->w_Ftr ||
+            !g->w_Glim || !g->w_Gtr || !g->w_clip)
+            return ORC_ENOMEM;
+    }
+    double *qs = g->w_qs, *c2 = g->w_c2;
+    edge_t *EX = g->w_EX, *EY = g->w_EY;
+    double *Flim = g->w_Flim, *Ftr = g->w_Ftr, *Glim = g->w_Glim, *Gtr = g->w_Gtr;
+    memset(Flim, 0, nex * 7 * sizeof(double));
+    memset(Ftr, 0, nex * 7 * sizeof(double));
+    memset(Glim, 0, ney * 7 * sizeof(double));
+    memset(Gtr, 0, ney * 7 * sizeof(double));
+#define XE(i, j) ((size_t)((j) + 1) * nxe + (size_t)((i) + 1))
+#define YE(i, j) ((size_t)((j) + 1) * nye + (size_t)((i) + 1))
+
+    fill_ghosts(g);
+
+    /* 1. source half step (Strang) on every cell including ghosts; Lie only
+     *    clears the auxiliary variables of dry and SWE cells here. */
+#pragma omp parallel for schedule(static)
+    for (long kk = 0; kk < (long)np; kk++) {
+        size_t k = (size_t)kk;
+        double qc[7];
+        for (int m = 0; m < 7; m++) qc[m] = g->q[m * np + k];
+        if (P->splitting) {
+            source_or_clear(g, k, 0.5 * dt, qc);
+        } else if (qc[IH] <= P->dry_tol || !g->phi[k] || g->brk[k]) {
+            qc[IHW] = 0.0; qc[IHS] = 0.0; qc[IHP] = 0.0; qc[IHPB] = 0.0;
+        }
+        for (int m = 0; m < 7; m++) qs[m * np + k] = qc[m];
+        c2[k] = cell_c2(g, k);
+    }
+
+    /* 2. normal solves at every x-edge i (between cells i-1 and i) of rows
+     *    -1..ny, i = -1..nx+1 */
+#pragma omp parallel for schedule(static) reduction(min:rc)
+    for (int j = -1; j <= ny; j++) {
+        for (int i = -1; i <= nx + 1; i++) {
+            size_t kl = CELL(g, i - 1, j), kr = CELL(g, i, j);
+            double ql[7], qr[7];
+            for (int m = 0; m < 7; m++) { ql[m] = qs[m * np + kl]; qr[m] = qs[m * np + kr]; }
+            int r = riemann_n(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr], &EX[XE(i, j)]);
+            if (r < rc) rc = r;
+        }
+    }
+    /* 3. normal solves at every y-edge j (between cells j-1 and j) of
+     *    columns -1..nx, j = -1..ny+1 */
+#pragma omp parallel for schedule(static) reduction(min:rc)
+    for (int j = -1; j <= ny + 1; j++) {
+        for (int i = -1; i <= nx; i++) {
+            size_t kl = CELL(g, i, j - 1), kr = CELL(g, i, j);
+            double ql[7], qr[7];
+            for (int m = 0; m < 7; m++) { ql[m] = qs[m * np + kl]; qr[m] = qs[m * np + kr]; }
+            int r = riemann_y(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr], &EY[YE(i, j)]);
+            if (r < rc) rc = r;
+        }
+    }
+    if (rc != ORC_OK) return rc;
+
+    /* 4. limited corrections at the x-edges i = 0..nx of rows -1..ny and the
+     *    y-edges j = 0..ny of columns -1..nx */
+#pragma omp parallel for schedule(static)
+    for (int j = -1; j <= ny; j++)
+        for (int i = 0; i <= nx; i++)
+            correction(P->limiter, dtdx, &EX[XE(i - 1, j)], &EX[XE(i, j)],
+                       &EX[XE(i + 1, j)], &Flim[XE(i, j) * 7]);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j <= ny; j++)
+        for (int i = -1; i <= nx; i++)
+            correction(P->limiter, dtdy, &EY[YE(i, j - 1)], &EY[YE(i, j)],
+                       &EY[YE(i, j + 1)], &Glim[YE(i, j) * 7]);
+
+    /* 5. transverse propagation.  The fluctuation an edge sends into a
+     *    cell, including its limited correction (A+ - F~ to the right cell,
+     *    A- + F~ to the left cell), is split by the eigenstructure of the
+     *    cell's two edges in the other direction; the upward (rightward)
+     *    part feeds the far edge's correction with weight dt/(2 dx). */
+    if (P->transverse == 2) {
+        const double cx = 0.5 * dtdx, cy = 0.5 * dtdy;
+        /* G~ at y-edge (i, j) from the x-fluctuations entering cells
+         * (i, j-1) [upward part] and (i, j) [downward part] */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j <= ny; j++) {
+            for (int i = 0; i < nx; i++) {
+                const edge_t *ye = &EY[YE(i, j)];
+                double *G = &Gtr[YE(i, j) * 7];
+                if (!ye->e.wet) continue;
+                for (int part = 0; part < 4; part++) {
+                    int row = (part < 2) ? j - 1 : j;
+                    int sgn = (part < 2) ? 1 : -1;
+                    int ex = (part % 2 == 0) ? i : i + 1;
+                    const edge_t *xe = &EX[XE(ex, row)];
+                    if (xe->kind != 0) continue;
+                    const double *F = &Flim[XE(ex, row) * 7];
+                    double a[7], v[7];
+                    for (int m = 0; m < 7; m++)
+                        a[m] = (part % 2 == 0) ? xe->apdq[m] - F[m] : xe->amdq[m] + F[m];
+                    split_by_y(P, &ye->e, a, sgn, v);
+                    for (int m = 0; m < 7; m++) G[m] -= cx * v[m];
+                }
+            }
+        }
+        /* F~ at x-edge (i, j) from the y-fluctuations entering cells
+         * (i-1, j) [rightward part] and (i, j) [leftward part] */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < ny; j++) {
+            for (int i = 0; i <= nx; i++) {
+                const edge_t *xe = &EX[XE(i, j)];
+                double *F = &Ftr[XE(i, j) * 7];
+                if (!xe->e.wet) continue;
+                for (int part = 0; part < 4; part++) {
+                    int col = (part < 2) ? i - 1 : i;
+                    int sgn = (part < 2) ? 1 : -1;
+                    int ey = (part % 2 == 0) ? j : j + 1;
+                    const edge_t *ye = &EY[YE(col, ey)];
+                    if (ye->kind != 0) continue;
+                    const double *G = &Glim[YE(col, ey) * 7];
+                    double a[7], v[7];
+                    for (int m = 0; m < 7; m++)
+                        a[m] = (part % 2 == 0) ? ye->apdq[m] - G[m] : ye->amdq[m] + G[m];
+                    trans_split(P, &xe->e, a, sgn, v);
+                    for (int m = 0; m < 7; m++) F[m] -= cy * v[m];
+                }
+            }
+        }
+    }
+
+    /* 6. flux-difference update of the interior cells, then
+     * 7. the source step (second Strang half, or the whole Lie step), then
+     * 8. fix-ups: positivity, dry cells, breaking latch, SWE cells */
+#pragma omp parallel for schedule(static) reduction(min:rc)
+    for (int j = 0; j < ny; j++) {
+        double clip = 0.0;
+        for (int i = 0; i < nx; i++) {
+            size_t k = CELL(g, i, j);
+            size_t xl = XE(i, j), xr = XE(i + 1, j), yb = YE(i, j), yt = YE(i, j + 1);
+            double qc[7];
+            for (int m = 0; m < 7; m++) {
+                double fx = EX[xl].apdq[m] + EX[xr].amdq[m]
+                          + (Flim[xr * 7 + m] + Ftr[xr * 7 + m])
+                          - (Flim[xl * 7 + m] + Ftr[xl * 7 + m]);
+                double gy = EY[yb].apdq[m] + EY[yt].amdq[m]
+                          + (Glim[yt * 7 + m] + Gtr[yt * 7 + m])
+                          - (Glim[yb * 7 + m] + Gtr[yb * 7 + m]);
+                qc[m] = qs[m * np + k] - dtdx * fx - dtdy * gy;
+            }
+            source_or_clear(g, k, P->splitting ? 0.5 * dt : dt, qc);
+            if (qc[IH] < 0.0) {
+                clip += -qc[IH] * g->dx * g->dy;
+                qc[IH] = 0.0;
+            }
+            if (qc[IH] <= P->dry_tol) {
+                for (int m = 1; m < 7; m++) qc[m] = 0.0;
+            } else if (P->kappa > 0.0 && g->phi[k] && !g->brk[k]) {
+                double H = still_depth(P, g->b[k]);
+                if (qc[IH] + g->b[k] - P->eta0 > P->kappa * H) g->brk[k] = 1;
+            }
+            if (!g->phi[k] || g->brk[k] || qc[IH] <= P->dry_tol) {
+                qc[IHW] = 0.0; qc[IHS] = 0.0; qc[IHP] = 0.0; qc[IHPB] = 0.0;
+            }
+            for (int m = 0; m < 7; m++) {
+                if (!isfinite(qc[m]) && ORC_ENAN < rc) rc = ORC_ENAN;
+                g->q[m * np + k] = qc[m];
+            }
+        }
+        g->w_clip[j] = clip;
+    }
+    for (int j = 0; j < ny; j++) g->clipped += g->w_clip[j];
+
+    /* 9. Courant number from the speeds of the edges of interior cells */
+    {
+        double rx = 0.0, ry = 0.0;
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i <= nx; i++)
+                for (int p = 0; p < 7; p++) rx = fmax(rx, fabs(EX[XE(i, j)].s[p]));
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i < nx; i++)
+                for (int p = 0; p < 7; p++) ry = fmax(ry, fabs(EY[YE(i, j)].s[p]));
+        *courant = fmax(dt * rx / g->dx, dt * ry / g->dy);
+    }
+#undef XE
+#undef YE
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* time-step control, gauges, diagnostics                               */
+
+int orc_initial_dt(const orc_grid *g, double *dt0)
+{
+    const orc_params *P = &g->P;
+    size_t np = PLANE(g);
+    double mx = 0.0;
+    for (int j = 0; j < g->ny; j++) {
+        for (int i = 0; i < g->nx; i++) {
+            size_t k = CELL(g, i, j);
+            double h = g->q[IH * np + k];
+            if (h <= P->dry_tol) continue;
+            double u = g->q[IHU * np + k] / h, v = g->q[IHV * np + k] / h;
+            double p = g->q[IHP * np + k] / h;
+            double a = P->g * h + p + cell_c2(g, k);
+            if (a < 0.0) return ORC_ENONHYP;
+            double ce = sqrt(a);
+            mx = fmax(mx, fmax((fabs(u) + ce) / g->dx, (fabs(v) + ce) / g->dy));
+        }
+    }
+    if (!(mx > 0.0)) return ORC_EINVAL;
+    *dt0 = P->cfl / mx;
+    return ORC_OK;
+}
+
+static double gauge_eta(const orc_grid *g, double gx, double gy)
+{
+    size_t np = PLANE(g);
+    double fx = (gx - g->x0) / g->dx - 0.5;
+    double fy = (gy - g->y0) / g->dy - 0.5;
+    int i0 = (int)floor(fx), j0 = (int)floor(fy);
+    if (i0 < 0) i0 = 0;
+    if (i0 > g->nx - 2) i0 = g->nx - 2;
+    if (j0 < 0) j0 = 0;
+    if (j0 > g->ny - 2) j0 = g->ny - 2;
+    double wx = fx - i0, wy = fy - j0;
+    wx = fmin(fmax(wx, 0.0), 1.0);
+    wy = fmin(fmax(wy, 0.0), 1.0);
+    double e[2][2];
+    for (int dj = 0; dj < 2; dj++)
+        for (int di = 0; di < 2; di++) {
+            size_t k = CELL(g, i0 + di, j0 + dj);
+            double h = g->q[IH * np + k];
+            e[dj][di] = h > g->P.dry_tol ? h + g->b[k] - g->P.eta0 : 0.0;
+        }
+    return (1.0 - wx) * (1.0 - wy) * e[0][0] + wx * (1.0 - wy) * e[0][1]
+         + (1.0 - wx) * wy * e[1][0] + wx * wy * e[1][1];
+}
+
+static int record_gauges(orc_grid *g)
+{
+    if (g->ngauge == 0) return ORC_OK;
+    if (g->nrec == g->caprec) {
+        int cap = g->caprec ? 2 * g->caprec : 256;
+        double *t = (double *)realloc(g->rec_t, (size_t)cap * sizeof(double));
+        if (!t) return ORC_ENOMEM;
+        g->rec_t = t;
+        double *e = (double *)realloc(g->rec_eta, (size_t)cap * g->ngauge * sizeof(double));
+        if (!e) return ORC_ENOMEM;
+        g->rec_eta = e;
+        g->caprec = cap;
+    }
+    g->rec_t[g->nrec] = g->t;
+    for (int k = 0; k < g->ngauge; k++)
+        g->rec_eta[(size_t)g->nrec * g->ngauge + k] = gauge_eta(g, g->gxy[2 * k], g->gxy[2 * k + 1]);
+    g->nrec++;
+    return ORC_OK;
+}
+
+int orc_set_gauges(orc_grid *g, int n, const double *xy)
+{
+    for (int k = 0; k < n; k++) {
+        double x = xy[2 * k], y = xy[2 * k + 1];
+        if (x < g->x0 || x > g->x0 + g->nx * g->dx || y < g->y0 || y > g->y0 + g->ny * g->dy)
+            return ORC_ERANGE;
+    }
+    free(g->gxy); free(g->rec_t); free(g->rec_eta);
+    g->gxy = NULL; g->rec_t = NULL; g->rec_eta = NULL;
+    g->nrec = 0; g->caprec = 0; g->ngauge = n;
+    if (n > 0) {
+        g->gxy = (double *)malloc((size_t)2 * n * sizeof(double));
+        if (!g->gxy) return ORC_ENOMEM;
+        memcpy(g->gxy, xy, (size_t)2 * n * sizeof(double));
+    }
+    return ORC_OK;
+}
+
+int orc_read_gauges(const orc_grid *g, double *t, double *eta, int max_records, int *n_records)
+{
+    int n = g->nrec < max_records ? g->nrec : max_records;
+    for (int r = 0; r < n; r++) {
+        t[r] = g->rec_t[r];
+        for (int k = 0; k < g->ngauge; k++)
+            eta[(size_t)r * g->ngauge + k] = g->rec_eta[(size_t)r * g->ngauge + k];
+    }
+    *n_records = n;
+    return ORC_OK;
+}
+
+int orc_advance(orc_grid *g, double dt, int n)
+{
+    const orc_params *P = &g->P;
+    int adaptive = !(dt > 0.0);
+    if (adaptive && !g->have_dt) {
+        int r = orc_initial_dt(g, &g->dt_next);
+        if (r != ORC_OK) return r;
+        g->have_dt = 1;
+    }
+    size_t np = PLANE(g);
+    double *save_q = (double *)malloc(ORC_NV * np * sizeof(double));
+    unsigned char *save_b = (unsigned char *)malloc(np);
+    if (!save_q || !save_b) { free(save_q); free(save_b); return ORC_ENOMEM; }
+    int rc = ORC_OK, accepted = 0, rejects_in_row = 0;
+    while (accepted < n) {
+        double d = adaptive ? g->dt_next : dt;
+        double save_clip = g->clipped, cour = 0.0;
+        memcpy(save_q, g->q, ORC_NV * np * sizeof(double));
+        memcpy(save_b, g->brk, np);
+        int r = orc_step(g, d, &cour);
+        if (r != ORC_OK || cour > P->cfl_max) {
+            memcpy(g->q, save_q, ORC_NV * np * sizeof(double));
+            memcpy(g->brk, save_b, np);
+            g->clipped = save_clip;
+            if (r != ORC_OK) { rc = r; break; }
+            if (!adaptive || ++rejects_in_row > 64) { rc = ORC_ECFL; break; }
+            g->dt_next = d * P->cfl / cour;
+            g->nrej++;
+            continue;
+        }
+        rejects_in_row = 0;
+        g->t += d;
+        g->nstep++;
+        accepted++;
+        if (adaptive) {
+            if (cour > 0.0) g->dt_next = d * P->cfl / cour;
+        } else {
+            g->dt_next = d;
+        }
+        r = record_gauges(g);
+        if (r != ORC_OK) { rc = r; break; }
+    }
+    free(save_q); free(save_b);
+    return rc;
+}
+
+int orc_get_clock(const orc_grid *g, double *t, double *dt_next, long long *steps,
+                  long long *rejected)
+{
+    *t = g->t; *dt_next = g->have_dt ? g->dt_next : 0.0;
+    *steps = g->nstep; *rejected = g->nrej;
+    return ORC_OK;
+}
+
+int orc_set_clock(orc_grid *g, double t, double dt_next, long long steps)
+{
+    g->t = t; g->nstep = steps;
+    if (dt_next > 0.0) { g->dt_next = dt_next; g->have_dt = 1; }
+    else g->have_dt = 0;
+    return ORC_OK;
+}
+
+double orc_mass(const orc_grid *g)
+{
+    size_t np = PLANE(g);
+    double s = 0.0;
+    for (int j = 0; j < g->ny; j++)
+        for (int i = 0; i < g->nx; i++) s += g->q[IH * np + CELL(g, i, j)];
+    return s * g->dx * g->dy;
+}
+
+double orc_clipped_mass(const orc_grid *g) { return g->clipped; }

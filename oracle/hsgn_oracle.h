@@ -1,0 +1,108 @@
+/*
+ * hsgn_oracle.h -- interface of the plain FP64 CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that the tests, the
+ * smoke check and the CPU-baseline timing can compare the GPU library
+ * against a slow, obviously correct statement of the method.  No product
+ * code links, loads or calls it.  It shares no source with the GPU path.
+ *
+ * What it computes: one explicit finite-volume step of the hyperbolic
+ * Serre-Green-Naghdi system (HSGN, Sec. 3, eq. HSGN) on a 2D Cartesian
+ * grid, in the wave-propagation form of Sec. 4 (f-wave normal Riemann
+ * solver with Roe-type interface state and Einfeldt speeds, limited
+ * second-order corrections, transverse Riemann solver), with the SDIRK(2,2)
+ * relaxation source step (Sec. 4) applied by Strang or Lie splitting and the
+ * cell-wise switch to the shallow water equations through the transition
+ * function phi_T and c^2 = alpha^2 g H phi_T (Sec. 3.3, eq. transition
+ * function).
+ *
+ * State layout at this interface: q[7][ny][nx], row-major, conserved
+ * variables in the order of Appendix C: h, hu, hv, hw, h*sigma, hp, h*p_b.
+ */
+#ifndef HSGN_ORACLE_H
+#define HSGN_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NV 7
+
+/* status codes (same meaning as the GPU library's, defined independently) */
+#define ORC_OK          0
+#define ORC_EINVAL     -1
+#define ORC_ENOMEM     -2
+#define ORC_ECFL       -3
+#define ORC_ENONHYP    -4
+#define ORC_ENAN       -5
+#define ORC_ERANGE     -6
+
+/* boundary conditions, one per side: x-low, x-high, y-low, y-high */
+#define ORC_BC_PERIODIC 0
+#define ORC_BC_WALL     1
+#define ORC_BC_EXTRAP   2
+
+typedef struct orc_params {
+    double g;           /* gravity */
+    double alpha;       /* relaxation parameter alpha = c / sqrt(g H) */
+    double eta0;        /* sea level at rest */
+    double h_star;      /* transition depth for phi_T */
+    double dry_tol;     /* h <= dry_tol is dry */
+    double xi0, xi1;    /* bathymetry sharpness sensor parameters */
+    double cfl;         /* desired Courant number (adaptive dt) */
+    double cfl_max;     /* largest accepted Courant number */
+    double kappa;       /* breaking latch: eta - eta0 > kappa H (<= 0: off) */
+    int nbr_n;          /* neighbourhood half-width n of phi_T */
+    int limiter;        /* 0 first order, 1 minmod, 2 MC, 3 unlimited */
+    int transverse;     /* 0 none, 2 transverse incl. corrections */
+    int splitting;      /* 0 Lie, 1 Strang */
+} orc_params;
+
+typedef struct orc_grid orc_grid;
+
+orc_grid *orc_create(const orc_params *p, int nx, int ny, double x0, double y0,
+                     double dx, double dy, const int bc[4]);
+void orc_destroy(orc_grid *g);
+
+/* b[ny][nx]; computes H = (eta0 - b)^+ and phi_T */
+int orc_set_bathymetry(orc_grid *g, const double *b);
+int orc_set_state(orc_grid *g, const double *q);
+int orc_get_state(const orc_grid *g, double *q);
+/* mask byte per cell: bit0 = phi_T, bit1 = breaking latch */
+int orc_get_mask(const orc_grid *g, unsigned char *m);
+int orc_set_mask(orc_grid *g, const unsigned char *m);
+
+/* One step attempt of size dt from the current state.  Always replaces the
+ * state with Q^{n+1}; *courant receives the Courant number of the step. */
+int orc_step(orc_grid *g, double dt, double *courant);
+
+/* Driver: n accepted steps.  dt > 0: fixed step, returns ORC_ECFL (state
+ * left at the last good step) if the Courant number exceeds cfl_max.
+ * dt <= 0: adaptive step with reject and redo. */
+int orc_advance(orc_grid *g, double dt, int n);
+int orc_initial_dt(const orc_grid *g, double *dt0);
+int orc_get_clock(const orc_grid *g, double *t, double *dt_next,
+                  long long *steps, long long *rejected);
+int orc_set_clock(orc_grid *g, double t, double dt_next, long long steps);
+
+int orc_set_gauges(orc_grid *g, int n, const double *xy);
+int orc_read_gauges(const orc_grid *g, double *t, double *eta, int max_records,
+                    int *n_records);
+double orc_mass(const orc_grid *g);
+double orc_clipped_mass(const orc_grid *g);
+
+/* Unit-level entry points used by the pin tests. */
+/* x-direction f-wave solve of one edge.  waves[p*7+m] = component m of
+ * f-wave p, speeds[p], fluctuations amdq/apdq, kind (0 regular, 1 wall with
+ * the right cell dry, 2 wall with the left cell dry, 3 both dry). */
+int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
+                  double bL, double bR, double c2L, double c2R,
+                  double *waves, double *speeds, double *amdq, double *apdq,
+                  int *kind);
+/* SDIRK(2,2) source step of length tau on one cell (in place). */
+void orc_source_cell(double *q, double c2, double tau);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,225 @@
+"""ctypes binding of the plain FP64 CPU oracle (oracle/hsgn_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline leg of the benchmark.  The GPU library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("HSGN_ORACLE_LIB", os.path.join(HERE, "libhsgn_oracle.so"))
+SRC_PATH = os.path.join(HERE, "hsgn_oracle.c")
+
+OK, EINVAL, ENOMEM, ECFL, ENONHYP, ENAN, ERANGE = 0, -1, -2, -3, -4, -5, -6
+
+
+def build(openmp: bool = True) -> str:
+    """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+           "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", "-o", LIB_PATH, SRC_PATH, "-lm"]
+    if openmp:
+        cmd.insert(1, "-fopenmp")
+    subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("eta0", ctypes.c_double), ("h_star", ctypes.c_double),
+                ("dry_tol", ctypes.c_double), ("xi0", ctypes.c_double),
+                ("xi1", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("cfl_max", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("nbr_n", ctypes.c_int), ("limiter", ctypes.c_int),
+                ("transverse", ctypes.c_int), ("splitting", ctypes.c_int)]
+
+
+def _params(p) -> OrcParams:
+    return OrcParams(p.g, p.alpha, p.eta0, p.h_star, p.dry_tol, p.xi0, p.xi1,
+                     p.cfl, p.cfl_max, p.kappa, p.nbr_n, p.limiter,
+                     p.transverse, p.splitting)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        for name in ("orc_set_bathymetry", "orc_set_state", "orc_get_state"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, dp]
+        L.orc_get_mask.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+        L.orc_set_mask.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
+        L.orc_advance.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
+        L.orc_initial_dt.argtypes = [ctypes.c_void_p, dp]
+        L.orc_get_clock.argtypes = [ctypes.c_void_p, dp, dp,
+                                    ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_longlong)]
+        L.orc_set_clock.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_longlong]
+        L.orc_set_gauges.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+        L.orc_read_gauges.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
+        L.orc_mass.restype = ctypes.c_double
+        L.orc_mass.argtypes = [ctypes.c_void_p]
+        L.orc_clipped_mass.restype = ctypes.c_double
+        L.orc_clipped_mass.argtypes = [ctypes.c_void_p]
+        L.orc_riemann_x.argtypes = [ctypes.POINTER(OrcParams), dp, dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
+        L.orc_source_cell.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__("oracle %s failed with status %d" % (where, code))
+        self.code = code
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise OracleError(rc, where)
+
+
+class OracleGrid:
+    """One grid patch advanced by the oracle."""
+
+    def __init__(self, params, grid):
+        L = lib()
+        self.params = params
+        self.grid = grid
+        self._p = _params(params)
+        bc = (ctypes.c_int * 4)(*grid.bc)
+        self.h = L.orc_create(ctypes.byref(self._p), grid.nx, grid.ny, grid.x0, grid.y0,
+                              grid.dx, grid.dy, bc)
+        if not self.h:
+            raise OracleError(EINVAL, "create")
+        self.ngauge = 0
+
+    def close(self):
+        if self.h:
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_bathymetry(self, b):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        assert b.shape == (self.grid.ny, self.grid.nx)
+        _check(lib().orc_set_bathymetry(self.h, _dp(b)), "set_bathymetry")
+
+    def set_state(self, q):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        assert q.shape == (7, self.grid.ny, self.grid.nx)
+        _check(lib().orc_set_state(self.h, _dp(q)), "set_state")
+
+    def get_state(self):
+        q = np.empty((7, self.grid.ny, self.grid.nx))
+        _check(lib().orc_get_state(self.h, _dp(q)), "get_state")
+        return q
+
+    def get_mask(self):
+        m = np.empty((self.grid.ny, self.grid.nx), dtype=np.uint8)
+        _check(lib().orc_get_mask(self.h, m.ctypes.data_as(ctypes.c_char_p)), "get_mask")
+        return m
+
+    def set_mask(self, m):
+        m = np.ascontiguousarray(m, dtype=np.uint8)
+        _check(lib().orc_set_mask(self.h, m.ctypes.data_as(ctypes.c_char_p)), "set_mask")
+
+    def step(self, dt):
+        c = ctypes.c_double(0.0)
+        _check(lib().orc_step(self.h, dt, ctypes.byref(c)), "step")
+        return c.value
+
+    def advance(self, dt, n):
+        _check(lib().orc_advance(self.h, float(dt), int(n)), "advance")
+
+    def initial_dt(self):
+        d = ctypes.c_double(0.0)
+        _check(lib().orc_initial_dt(self.h, ctypes.byref(d)), "initial_dt")
+        return d.value
+
+    def clock(self):
+        t, d = ctypes.c_double(), ctypes.c_double()
+        s, r = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(lib().orc_get_clock(self.h, ctypes.byref(t), ctypes.byref(d),
+                                   ctypes.byref(s), ctypes.byref(r)), "get_clock")
+        return t.value, d.value, s.value, r.value
+
+    def set_clock(self, t, dt_next, steps):
+        _check(lib().orc_set_clock(self.h, t, dt_next, steps), "set_clock")
+
+    def set_gauges(self, xy):
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        self.ngauge = xy.shape[0]
+        _check(lib().orc_set_gauges(self.h, self.ngauge, _dp(xy)), "set_gauges")
+
+    def read_gauges(self, max_records=1 << 20):
+        t = np.empty(max_records)
+        e = np.empty((max_records, max(self.ngauge, 1)))
+        n = ctypes.c_int(0)
+        _check(lib().orc_read_gauges(self.h, _dp(t), _dp(e), max_records,
+                                     ctypes.byref(n)), "read_gauges")
+        return t[:n.value].copy(), e[:n.value, :self.ngauge].copy()
+
+    def mass(self):
+        return lib().orc_mass(self.h)
+
+    def clipped_mass(self):
+        return lib().orc_clipped_mass(self.h)
+
+
+def from_workload(w) -> OracleGrid:
+    g = OracleGrid(w.params, w.grid)
+    g.set_bathymetry(w.b)
+    g.set_state(w.q)
+    if w.gauges is not None and len(w.gauges):
+        g.set_gauges(w.gauges)
+    return g
+
+
+def riemann_x(params, qL, qR, bL, bR, c2L, c2R):
+    """One x-edge f-wave solve: returns (waves[7,7], speeds[7], amdq, apdq,
+    kind)."""
+    p = _params(params)
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    waves = np.zeros((7, 7)); speeds = np.zeros(7)
+    amdq = np.zeros(7); apdq = np.zeros(7)
+    kind = ctypes.c_int(0)
+    rc = lib().orc_riemann_x(ctypes.byref(p), _dp(qL), _dp(qR), bL, bR, c2L, c2R,
+                             _dp(waves), _dp(speeds), _dp(amdq), _dp(apdq),
+                             ctypes.byref(kind))
+    _check(rc, "riemann_x")
+    return waves, speeds, amdq, apdq, kind.value
+
+
+def source_cell(q, c2, tau):
+    q = np.array(q, dtype=np.float64)
+    lib().orc_source_cell(_dp(q), c2, tau)
+    return q

@@ -1,0 +1,154 @@
+/*
+ * hsgn.h -- C ABI of the MI355X time-step library for the hyperbolic
+ * Serre-Green-Naghdi system coupled to the shallow water equations.
+ *
+ * The library advances sets of 2D Cartesian grid patches by the explicit
+ * finite-volume step of Sec. 4 of the paper: per-edge f-wave Riemann solves
+ * (eq. total fluctuation, Appendix C eigenstructure, Einfeldt speeds) with
+ * limited second-order and transverse corrections, the flux-difference
+ * cell update, the SDIRK(2,2) relaxation source step (Strang or Lie
+ * splitting), and the cell-wise switch to the shallow water equations where
+ * the still-water depth within one cell is below h_star (eq. transition
+ * function, c^2 = alpha^2 g H phi_T) or where a cell is latched as breaking.
+ * The time step follows the CFL condition with the global maximum wave speed
+ * (Sec. 4).  All arithmetic runs in HIP kernels on the device.
+ *
+ * Conventions
+ *   - Every call returns an int status: HSGN_OK (0) or a negative HSGN_E*
+ *     code.  No call throws, aborts or prints.  hsgn_last_error() gives a
+ *     context-owned message for the last failure.
+ *   - State arrays at this interface are float64, layout q[7][ny][nx]
+ *     (row-major, x fastest), conserved variables in the order h, hu, hv,
+ *     hw, h*sigma, hp, h*p_b (Appendix C).  Bathymetry b[ny][nx] is float64,
+ *     measured from the sea level eta0 (negative below it).
+ *   - Pointers passed in are borrowed for the duration of the call only
+ *     (copy semantics); on_device = 1 means the pointer is device memory on
+ *     the context's device, 0 means host memory.
+ *   - All device work is enqueued on the stream given to hsgn_create (a
+ *     borrowed hipStream_t; NULL = the default stream).
+ *   - A context owns its device buffers: two state buffers (the step reads
+ *     one and writes the other), bathymetry, two mask buffers, per-scenario
+ *     clocks and gauge records.
+ *   - A scenario is an independent simulation with its own clock and time
+ *     step; each patch belongs to one scenario.  Patches of one scenario
+ *     are independent grids here (no exchange between patches).
+ */
+#ifndef HSGN_H
+#define HSGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSGN_OK          0
+#define HSGN_EINVAL     -1   /* bad argument or call order */
+#define HSGN_ENOMEM     -2   /* device or host allocation failed */
+#define HSGN_ECFL       -3   /* fixed step exceeded cfl_max (state kept at last good step) */
+#define HSGN_ENONHYP    -4   /* g h + p + c^2 <= 0 at an edge (Sec. 3 hyperbolicity) */
+#define HSGN_ENAN       -5   /* non-finite value produced */
+#define HSGN_ERANGE     -6   /* gauge outside its scenario's patches */
+#define HSGN_EDEVICE    -7   /* HIP runtime error */
+#define HSGN_ENOTSUP    -8   /* option not supported by this build */
+
+#define HSGN_BC_PERIODIC 0
+#define HSGN_BC_WALL     1   /* reflecting wall: mirror, normal momentum negated */
+#define HSGN_BC_EXTRAP   2   /* zeroth-order extrapolation */
+
+typedef struct hsgn_params {
+    int model;          /* 0 = HSGN (7 variables) */
+    int precision;      /* 0 = FP64 */
+    double g;           /* gravity */
+    double alpha;       /* relaxation parameter alpha = c / sqrt(g H), Sec. 3 */
+    double eta0;        /* sea level at rest */
+    double h_star;      /* SWE transition depth of phi_T */
+    double dry_tol;     /* cells with h <= dry_tol are dry */
+    double xi0, xi1;    /* bathymetry sharpness sensor parameters (Sec. 4) */
+    double cfl;         /* Courant number targeted by the adaptive step */
+    double cfl_max;     /* largest accepted Courant number */
+    double kappa;       /* breaking latch eta - eta0 > kappa H; <= 0 disables */
+    int nbr_n;          /* neighbourhood half-width n of phi_T (0..2) */
+    int limiter;        /* 0 first order, 1 minmod, 2 MC, 3 unlimited */
+    int transverse;     /* 0 none, 2 transverse waves incl. corrections */
+    int splitting;      /* 0 Lie, 1 Strang */
+    int tile_rows;      /* rows per marching tile; <= 0 lets the library choose */
+} hsgn_params;
+
+typedef struct hsgn_diag {
+    double mass;            /* sum of h dx dy (FP64, fixed summation order) */
+    double clipped_mass;    /* water added by clipping negative depths */
+    double max_courant;     /* largest accepted Courant number so far */
+    double last_courant;    /* Courant number of the last accepted step */
+    long long steps;        /* accepted steps */
+    long long rejected;     /* rejected adaptive attempts */
+    long long cell_updates; /* interior cell updates of accepted steps */
+    long long n_swe_cells;  /* cells with phi_T = 0 or latched breaking */
+    long long n_breaking;   /* cells latched as breaking */
+} hsgn_diag;
+
+typedef struct hsgn_ctx hsgn_ctx;
+
+/* Create a context.  *p is copied.  hip_stream: borrowed hipStream_t.
+ * Errors: EINVAL (bad parameters), ENOTSUP (model/precision), EDEVICE. */
+int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out);
+
+/* Add an nx x ny patch with cell size dx, dy and lower-left corner (x0, y0)
+ * to a scenario (scenarios are numbered from 0 and need not be declared).
+ * bc[4] = {x-low, x-high, y-low, y-high}; periodic sides come in pairs.
+ * Errors: EINVAL (nx or ny < 4, bad bc, after finalize). */
+int hsgn_add_grid(hsgn_ctx *c, int scenario, int nx, int ny, double x0, double y0,
+                  double dx, double dy, const int bc[4], int *patch_id);
+
+/* Allocate the device buffers and build the work tables.  Errors: ENOMEM. */
+int hsgn_finalize(hsgn_ctx *c);
+
+/* Bathymetry b[ny][nx] of a patch; computes H = (eta0 - b)^+ and phi_T (the
+ * minimum of H over the (2n+1)^2 box through the boundary map exceeds
+ * h_star) and clears the breaking latch. */
+int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device);
+
+/* State q[7][ny][nx] (float64) of a patch, copied in or out. */
+int hsgn_set_state(hsgn_ctx *c, int patch, const double *q, int on_device);
+int hsgn_get_state(hsgn_ctx *c, int patch, double *q, int on_device);
+
+/* Mask byte per cell: bit0 = phi_T, bit1 = breaking latch. */
+int hsgn_get_mask(hsgn_ctx *c, int patch, uint8_t *m, int on_device);
+int hsgn_set_mask(hsgn_ctx *c, int patch, const uint8_t *m, int on_device);
+
+/* Gauges of a scenario at points xy[n][2] (host).  Each accepted step
+ * records eta' = h + b - eta0 (0 in dry cells) interpolated bilinearly
+ * between the four nearest cell centres of the patch containing the point.
+ * Errors: ERANGE. */
+int hsgn_set_gauges(hsgn_ctx *c, int scenario, int n, const double *xy);
+
+/* Copy out the gauge records taken since the last read (t[r],
+ * eta[r][n]) and forget them.  Host pointers. */
+int hsgn_read_gauges(hsgn_ctx *c, int scenario, double *t, double *eta,
+                     int max_records, int *n_records);
+
+/* Advance every scenario by n_steps accepted steps.  dt > 0: fixed step
+ * (ECFL if a step's Courant number exceeds cfl_max; that scenario stops at
+ * its last good step).  dt <= 0: adaptive step dt_next = dt cfl / Courant
+ * with reject and redo above cfl_max; the first step uses
+ * cfl / max((|u| + Ce)/dx, (|v| + Ce)/dy).  Returns after the device work
+ * has completed.  Errors: ECFL, ENONHYP, ENAN, EDEVICE. */
+int hsgn_advance(hsgn_ctx *c, double dt, int n_steps);
+
+int hsgn_diagnostics(hsgn_ctx *c, int scenario, hsgn_diag *d);
+int hsgn_get_clock(hsgn_ctx *c, int scenario, double *t, double *dt_next,
+                   long long *steps);
+int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next,
+                   long long steps);
+
+/* Number of marching work items (wavefronts) of one step. */
+int hsgn_work_items(hsgn_ctx *c, int *n);
+
+int hsgn_destroy(hsgn_ctx *c);
+const char *hsgn_strerror(int code);
+const char *hsgn_last_error(hsgn_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,328 @@
+// hsgn_march.hpp -- one wavefront advances one strip of a patch by one step.
+//
+// Mapping: lane l of a 64-wide wavefront owns column i0 - 2 + l of a patch,
+// so a wavefront covers 60 interior columns plus two halo columns on each
+// side.  It marches up the rows r0 - 2 .. r0 + th + 1 of its strip, loading
+// one row per iteration (coalesced SoA loads), and writes rows r0 .. r0+th-1.
+// x-neighbours are exchanged with lane shuffles; y-neighbours live in
+// registers (sliding windows).  Nothing is staged in LDS and no barrier is
+// needed: a wavefront is independent of every other.
+//
+// Per iteration k (row k loaded):
+//   1. load cell (i, k) through the boundary map, first source half step;
+//   2. x-edge (i-1/2, k): normal solve, limiter (neighbour waves by
+//      shuffle), net fluctuation entering cell (i, k);
+//   3. y-edge (i, k-1/2): normal solve; finish the limiter of the y-edge
+//      below it and feed its fluctuations to rows k-1 and k-2;
+//   4. transverse terms: the x-fluctuations entering cells (i, k-1) and
+//      (i, k) split by the y-edge (i, k-1/2); the y-fluctuations entering
+//      cells (i-1, k-2) and (i, k-2) split by the x-edge (i-1/2, k-2);
+//   5. row k-2 is complete: second source half step, fix-ups, store.
+//
+// The transverse terms of a cell are split once for the sum of the
+// fluctuations entering it from its two edges in the other direction; by
+// linearity of the split this equals splitting each edge's fluctuation.
+#pragma once
+
+#include "hsgn_math.hpp"
+
+namespace hsgn {
+
+struct PatchInfo {
+    int nx, ny, pitch, scen;
+    int bc[4];               // x-low, x-high, y-low, y-high
+    double dx, dy;
+    long long qoff;          // element offset of the patch's 7 planes
+    long long coff;          // element offset of its bathymetry / mask plane
+};
+
+struct WorkItem {
+    int patch, i0, r0, th;   // strip: columns i0..i0+59, rows r0..r0+th-1
+};
+
+// per-scenario clock and control, device resident
+struct ScenState {
+    double t, dt, dt_fixed, courant, max_courant;
+    double rx, ry;           // max |speed| over x- and y-edges of the attempt
+    long long steps, rejects, target, records;
+    int cur;                 // which state buffer holds Q^n
+    int active;              // step kernels work on this scenario
+    int err;                 // sticky error code
+    int accepted;            // the last attempt was accepted
+    int adaptive;
+    int streak;              // consecutive rejected attempts
+    unsigned long long rx_bits, ry_bits;
+    double clip_total;
+};
+
+template <class T>
+struct MarchArgs {
+    StepParams P;
+    const PatchInfo *patches;
+    const WorkItem *work;
+    T *q0, *q1;              // state buffers (ping-pong)
+    const T *bath;
+    uint8_t *m0, *m1;        // mask buffers (ping-pong): bit0 phi_T, bit1 breaking
+    ScenState *scen;
+    double *clip_slots;      // one per work item
+    int nwork;
+};
+
+template <class L, class T>
+HSGN_HD void shfl_cell(L &ln, const Cell<T> &c, Cell<T> &o, bool up)
+{
+    for (int m = 0; m < 7; m++) o.q[m] = up ? ln.up(c.q[m]) : ln.dn(c.q[m]);
+    o.h = up ? ln.up(c.h) : ln.dn(c.h);
+    o.u = up ? ln.up(c.u) : ln.dn(c.u);
+    o.v = up ? ln.up(c.v) : ln.dn(c.v);
+    o.w = up ? ln.up(c.w) : ln.dn(c.w);
+    o.s = up ? ln.up(c.s) : ln.dn(c.s);
+    o.p = up ? ln.up(c.p) : ln.dn(c.p);
+    o.pb = up ? ln.up(c.pb) : ln.dn(c.pb);
+    o.b = up ? ln.up(c.b) : ln.dn(c.b);
+    o.c2 = up ? ln.up(c.c2) : ln.dn(c.c2);
+    o.wet = up ? ln.upi(c.wet) : ln.dni(c.wet);
+}
+
+template <class L, class T>
+HSGN_HD void shfl_waves_up(L &ln, const Waves<T> &w, Waves<T> &o)
+{
+    for (int m = 0; m < 7; m++) { o.z0[m] = ln.up(w.z0[m]); o.z6[m] = ln.up(w.z6[m]); }
+    for (int m = 0; m < 3; m++) o.zm[m] = ln.up(w.zm[m]);
+    o.bs = ln.up(w.bs); o.bw = ln.up(w.bw); o.bt = ln.up(w.bt); o.bpb = ln.up(w.bpb);
+    o.smin = ln.up(w.smin); o.smax = ln.up(w.smax); o.uh = ln.up(w.uh);
+    o.kind = ln.upi(w.kind);
+}
+
+template <class L, class T>
+HSGN_HD void shfl_vec(L &ln, const T *a, T *o, bool up)
+{
+    for (int m = 0; m < 7; m++) o[m] = up ? ln.up(a[m]) : ln.dn(a[m]);
+}
+
+// load cell (col, row) of a patch through the boundary map and apply the
+// first source half step (Strang) or clear a dry/SWE cell's auxiliaries
+template <class T>
+HSGN_HD void load_cell(const StepParams &P, const PatchInfo &pi, const T *q, const T *bath,
+                       const uint8_t *mask, int mc, int fx, int row, T tau_pre, Cell<T> &c,
+                       int &phi, int &brk)
+{
+    int fy;
+    int mr = map_index(row, pi.ny, pi.bc[2], pi.bc[3], &fy);
+    long long idx = (long long)mr * pi.pitch + mc;
+    long long plane = (long long)pi.ny * pi.pitch;
+    const T *qp = q + pi.qoff + idx;
+    for (int m = 0; m < 7; m++) c.q[m] = qp[m * plane];
+    if (fx) c.q[IHU] = -c.q[IHU];
+    if (fy) c.q[IHV] = -c.q[IHV];
+    c.b = bath[pi.coff + idx];
+    uint8_t mk = mask[pi.coff + idx];
+    phi = mk & 1;
+    brk = (mk >> 1) & 1;
+    int swe = !phi || brk;
+    T H = still_depth(P, c.b);
+    c.c2 = swe ? (T)0 : (T)P.a2g * H;
+    if (P.splitting) {
+        source_or_clear(P, c.q, c.c2, swe, tau_pre);
+    } else if (!(c.q[IH] > (T)P.dry_tol) || swe) {
+        c.q[IHW] = (T)0; c.q[IHS] = (T)0; c.q[IHP] = (T)0; c.q[IHPB] = (T)0;
+    }
+    derive(P, c);
+}
+
+// Lanes policy L provides: lane(), up(x)/dn(x) (value of lane-1 / lane+1)
+// for T and upi/dni for int, and finish(wave, rx, ry, clip) which reduces over
+// the wavefront and publishes the results.
+template <class L, class T>
+HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
+{
+    const WorkItem wk = A.work[wid];
+    const PatchInfo pi = A.patches[wk.patch];
+    ScenState *sc = &A.scen[pi.scen];
+    const StepParams &P = A.P;
+    if (!sc->active) return;                    // uniform over the wavefront
+    const int cur = sc->cur;
+    const T *qin = cur ? A.q1 : A.q0;
+    T *qout = cur ? A.q0 : A.q1;
+    const uint8_t *min_ = cur ? A.m1 : A.m0;
+    uint8_t *mout = cur ? A.m0 : A.m1;
+    const T dt = (T)sc->dt;
+    const T dtdx = dt / (T)pi.dx, dtdy = dt / (T)pi.dy;
+    const T tau_pre = (T)0.5 * dt;
+    const T tau_post = P.splitting ? (T)0.5 * dt : dt;
+    const int lim = P.limiter;
+    const bool trans = P.transverse == 2;
+
+    const int lane = ln.lane();
+    int col = wk.i0 - 2 + lane;
+    if (col > pi.nx + 1) col = pi.nx + 1;       // idle lanes of a partial strip
+    int fx;
+    const int mc = map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
+    const int i_hi = wk.i0 + 59 < pi.nx - 1 ? wk.i0 + 59 : pi.nx - 1;
+    const bool interior = (wk.i0 - 2 + lane) >= wk.i0 && (wk.i0 - 2 + lane) <= i_hi;
+    const bool interior_left = lane >= 1 && (wk.i0 - 3 + lane) >= wk.i0 && (wk.i0 - 3 + lane) <= i_hi;
+    const int r0 = wk.r0, th = wk.th;
+
+    Cell<T> cprev;
+    int phi_c = 0, brk_c = 0;
+    // sliding windows over rows k-2 (index 0), k-1 (1) and k (2), shifted
+    // down by one row at the end of each iteration
+    T acc[3][7];                 // update accumulators
+    int phi_w[3], brk_w[3];      // masks
+    T b_w[3];                    // bathymetry
+    Eig<T> ex[3];                // x-edge eigenstructure
+    Waves<T> yprev;              // waves of the y-edge below the new one
+    T ydl[7];                    // its dot products with the edge below it
+    T xtr_prev[7];               // transverse x-fluctuation entering (i, k-1)
+    T bp_saved[7];               // transverse y-fluctuation entering (i, k-1) from below
+    T rx = (T)0, ry = (T)0, clip = (T)0;
+    for (int m = 0; m < 7; m++) { xtr_prev[m] = (T)0; bp_saved[m] = (T)0; ydl[m] = (T)0; }
+
+    for (int k = r0 - 2; k <= r0 + th + 1; k++) {
+        const int sk = 2, sk1 = 1, sk2 = 0;
+        Cell<T> c;
+        load_cell(P, pi, qin, A.bath, min_, mc, fx, k, tau_pre, c, phi_c, brk_c);
+        phi_w[sk] = phi_c;
+        brk_w[sk] = brk_c;
+        b_w[sk] = c.b;
+        for (int m = 0; m < 7; m++) acc[sk][m] = c.q[m];
+
+        // ---- x-edge (i-1/2, k) ----
+        T xtr[7];
+        for (int m = 0; m < 7; m++) xtr[m] = (T)0;
+        if (k >= r0 - 1 && k <= r0 + th) {
+            Cell<T> cl;
+            shfl_cell(ln, c, cl, true);
+            Waves<T> xw;
+            Eig<T> xe;
+            bool ok = riemann<0>(P, cl, c, xw, xe);
+            if (!ok && lane >= 1) sc->err = -4;
+            Waves<T> xwl;
+            shfl_waves_up(ln, xw, xwl);
+            T dl[7], dr[7];
+            family_dots<0>(xwl, xw, dl);
+            for (int f = 0; f < 7; f++) dr[f] = ln.dn(dl[f]);
+            T F[7], am[7], ap[7];
+            correction<0>(lim, dtdx, xw, dl, dr, F);
+            fluctuations<0>(xw, am, ap);
+            T apc[7], amc[7], amr[7];
+            for (int m = 0; m < 7; m++) { apc[m] = ap[m] - F[m]; amc[m] = am[m] + F[m]; }
+            shfl_vec(ln, amc, amr, false);
+            int kind_r = ln.dni(xw.kind);
+            for (int m = 0; m < 7; m++) {
+                acc[sk][m] -= dtdx * (apc[m] + amr[m]);
+                xtr[m] = (xw.kind == KIND_REGULAR ? apc[m] : (T)0)
+                       + (kind_r == KIND_REGULAR ? amr[m] : (T)0);
+            }
+            ex[sk] = xe;
+            if (k >= r0 && k < r0 + th && (interior || interior_left))
+                rx = tmax(rx, tmax(fabs(xw.smin), tmax(fabs(xw.smax), fabs(xw.uh))));
+        }
+
+        // ---- y-edge (i, k-1/2) ----
+        if (k >= r0 - 1) {
+            Waves<T> yw;
+            Eig<T> ye;
+            bool ok = riemann<1>(P, cprev, c, yw, ye);
+            if (!ok) sc->err = -4;
+            if (k >= r0 && k <= r0 + th && interior)
+                ry = tmax(ry, tmax(fabs(yw.smin), tmax(fabs(yw.smax), fabs(yw.uh))));
+            if (k >= r0) {
+                T dk[7];
+                family_dots<1>(yw, yprev, dk);
+                if (k - 1 >= r0 && k - 1 <= r0 + th) {
+                    // the y-edge (i, k-3/2) between rows k-2 and k-1 is complete
+                    T G[7], bm[7], bp[7];
+                    correction<1>(lim, dtdy, yprev, ydl, dk, G);
+                    fluctuations<1>(yprev, bm, bp);
+                    T btm[7], btp[7];
+                    for (int m = 0; m < 7; m++) {
+                        T bpc = bp[m] - G[m], bmc = bm[m] + G[m];
+                        acc[sk1][m] -= dtdy * bpc;
+                        acc[sk2][m] -= dtdy * bmc;
+                        btp[m] = yprev.kind == KIND_REGULAR ? bpc : (T)0;
+                        btm[m] = yprev.kind == KIND_REGULAR ? bmc : (T)0;
+                    }
+                    if (k - 2 >= r0 && k - 2 <= r0 + th - 1) {
+                        // transverse y-fluctuation entering (i, k-2), split by
+                        // the x-edges (i-1/2, k-2) and (i+1/2, k-2)
+                        T ytr[7], ytl[7];
+                        for (int m = 0; m < 7; m++) ytr[m] = bp_saved[m] + btm[m];
+                        shfl_vec(ln, ytr, ytl, true);
+                        T Ft[7];
+                        for (int m = 0; m < 7; m++) Ft[m] = (T)0;
+                        if (trans && ex[sk2].wet) {
+                            T vp[7], vm[7];
+                            trans_split<0>(ex[sk2], ytl, 1, vp);
+                            trans_split<0>(ex[sk2], ytr, -1, vm);
+                            for (int m = 0; m < 7; m++) Ft[m] = (T)-0.5 * dtdy * (vp[m] + vm[m]);
+                        }
+                        T Ftr[7];
+                        shfl_vec(ln, Ft, Ftr, false);
+                        for (int m = 0; m < 7; m++) acc[sk2][m] -= dtdx * (Ftr[m] - Ft[m]);
+                    }
+                    for (int m = 0; m < 7; m++) bp_saved[m] = btp[m];
+                }
+                for (int f = 0; f < 7; f++) ydl[f] = dk[f];
+            }
+            if (trans && k >= r0 && k <= r0 + th && ye.wet) {
+                // transverse x-fluctuations entering (i, k-1) [up] and (i, k) [down]
+                T vp[7], vm[7];
+                trans_split<1>(ye, xtr_prev, 1, vp);
+                trans_split<1>(ye, xtr, -1, vm);
+                for (int m = 0; m < 7; m++) {
+                    T Gt = (T)-0.5 * dtdx * (vp[m] + vm[m]);
+                    acc[sk1][m] -= dtdy * Gt;
+                    acc[sk][m] += dtdy * Gt;
+                }
+            }
+            yprev = yw;
+        }
+
+        // ---- row k-2 complete ----
+        if (k - 2 >= r0 && k - 2 <= r0 + th - 1) {
+            T *qn = acc[sk2];
+            int phi = phi_w[sk2], brk = brk_w[sk2];
+            T bb = b_w[sk2];
+            int swe = !phi || brk;
+            T c2 = swe ? (T)0 : (T)P.a2g * still_depth(P, bb);
+            source_or_clear(P, qn, c2, swe, tau_post);
+            if (qn[IH] < (T)0) {
+                clip += -qn[IH] * (T)pi.dx * (T)pi.dy;
+                qn[IH] = (T)0;
+            }
+            if (qn[IH] <= (T)P.dry_tol) {
+                for (int m = 1; m < 7; m++) qn[m] = (T)0;
+            } else if (P.kappa > 0.0 && phi && !brk) {
+                T H = still_depth(P, bb);
+                if (qn[IH] + bb - (T)P.eta0 > (T)P.kappa * H) brk = 1;
+            }
+            if (!phi || brk || qn[IH] <= (T)P.dry_tol) {
+                qn[IHW] = (T)0; qn[IHS] = (T)0; qn[IHP] = (T)0; qn[IHPB] = (T)0;
+            }
+            bool bad = false;
+            for (int m = 0; m < 7; m++) bad = bad || !(fabs(qn[m]) <= (T)1e300);
+            if (interior) {
+                if (bad) sc->err = -5;
+                long long idx = (long long)(k - 2) * pi.pitch + (wk.i0 - 2 + lane);
+                long long plane = (long long)pi.ny * pi.pitch;
+                T *qo = qout + pi.qoff + idx;
+                for (int m = 0; m < 7; m++) qo[m * plane] = qn[m];
+                mout[pi.coff + idx] = (uint8_t)(phi | (brk << 1));
+            }
+        }
+        for (int m = 0; m < 7; m++) {
+            xtr_prev[m] = xtr[m];
+            acc[0][m] = acc[1][m];
+            acc[1][m] = acc[2][m];
+        }
+        phi_w[0] = phi_w[1]; phi_w[1] = phi_w[2];
+        brk_w[0] = brk_w[1]; brk_w[1] = brk_w[2];
+        b_w[0] = b_w[1]; b_w[1] = b_w[2];
+        ex[0] = ex[1]; ex[1] = ex[2];
+        cprev = c;
+    }
+    ln.finish(A, wid, pi.scen, rx, ry, clip);
+}
+
+}  // namespace hsgn

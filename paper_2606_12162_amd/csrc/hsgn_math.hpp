@@ -1,0 +1,466 @@
+// hsgn_math.hpp -- per-cell and per-edge arithmetic of the HSGN/SWE step.
+//
+// Device functions (also compilable as plain host C++) used by the marching
+// step kernel: loading a cell, the relaxation source step, the normal
+// Riemann solver, the wave limiter and the transverse splitting.
+//
+//   model        eq. (HSGN), Sec. 3, in 2D with u = (u, v) and the scalar
+//                sigma = -h div(u);
+//   Riemann      Sec. 4, eq. (total fluctuation): f-wave split of the flux
+//                difference plus the Roe-state quadrature of the
+//                non-conservative and bathymetry terms, Roe-type averages,
+//                sharpness sensor psi, Einfeldt speeds, eigenvectors of
+//                Appendix C; in the SWE region (c^2 = 0 on both sides) an
+//                HLLE split that carries the surface-elevation jump;
+//   limiter      Sec. 4 (minmod, MC) on each wave family;
+//   source       Sec. 4, SDIRK(2,2) with gamma = 1 - 1/sqrt(2) on
+//                Y = (hw, h sigma, hp, h p_b); the 4x4 stage systems are
+//                solved in closed form;
+//   SWE switch   Sec. 3.3 / eq. (transition function): c^2 = alpha^2 g H
+//                phi_T, zero in breaking cells.
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define HSGN_HD __host__ __device__ __forceinline__
+#else
+#define HSGN_HD inline
+#endif
+
+namespace hsgn {
+
+enum { IH = 0, IHU = 1, IHV = 2, IHW = 3, IHS = 4, IHP = 5, IHPB = 6 };
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_EXTRAP = 2 };
+enum { KIND_REGULAR = 0, KIND_WALL_R = 1, KIND_WALL_L = 2, KIND_DRY = 3 };
+
+// run parameters as the kernels see them
+struct StepParams {
+    double g;
+    double a2g;        // alpha^2 g
+    double eta0, h_star, dry_tol, xi0, xi1, kappa;
+    int limiter;       // 0 first order, 1 minmod, 2 MC, 3 unlimited
+    int transverse;    // 0 none, 2 with corrections
+    int splitting;     // 0 Lie, 1 Strang
+};
+
+// one cell after loading and the first source half step
+template <class T>
+struct Cell {
+    T q[7];            // conserved (h, hu, hv, hw, h sigma, hp, h p_b)
+    T h;               // max(q[0], 0)
+    T u, v, w, s, p, pb;   // primitives, zero in dry cells
+    T b, c2;
+    int wet;           // h > dry_tol
+};
+
+// waves of one edge in the global frame.  Families: 0 (speed smin), 1
+// (speed uh; nonzero components h, normal momentum, hp), contacts sigma, w,
+// tangential momentum, p_b (speed uh), 6 (speed smax).
+template <class T>
+struct Waves {
+    T z0[7], z6[7];
+    T zm[3];           // family 1: h, normal momentum, hp
+    T bs, bw, bt, bpb; // contact strengths
+    T smin, smax, uh;
+    int kind;
+};
+
+// eigenstructure of an edge used to split fluctuations transversally
+// (normal frame of that edge)
+template <class T>
+struct Eig {
+    T uh, vh, wh, sh, pbh, ghh, c2p, ce2, smin, smax;
+    int wet;           // both cells wet
+};
+
+template <class T>
+HSGN_HD T tmax(T a, T b) { return a > b ? a : b; }
+template <class T>
+HSGN_HD T tmin(T a, T b) { return a < b ? a : b; }
+
+HSGN_HD int map_index(int i, int n, int lo, int hi, int *flip)
+{
+    *flip = 0;
+    if (i < 0) {
+        if (lo == BC_PERIODIC) return i + n;
+        if (lo == BC_WALL) { *flip = 1; return -1 - i; }
+        return 0;
+    }
+    if (i >= n) {
+        if (hi == BC_PERIODIC) return i - n;
+        if (hi == BC_WALL) { *flip = 1; return 2 * n - 1 - i; }
+        return n - 1;
+    }
+    return i;
+}
+
+template <class T>
+HSGN_HD T still_depth(const StepParams &P, T b)
+{
+    T H = (T)P.eta0 - b;
+    return H > (T)0 ? H : (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// relaxation source step: (I - k M) X = R solved in closed form, k = gamma
+// tau / h, M the 4x4 matrix of the right-hand side of eq. (HSGN) acting on
+// (w, sigma, p, p_b):
+//   rows  hw: p_b;  h sigma: 12 p - 6 p_b;  hp: -c^2 sigma;
+//         h p_b: -6 c^2 w + 3 c^2 sigma
+template <class T>
+HSGN_HD void stage_solve(T k, T c2, const T R[4], T X[4])
+{
+    T kc2 = k * c2;
+    T a = (T)1 + (T)12 * k * kc2;
+    T d = (T)1 + (T)6 * k * kc2;
+    T det = a * d + (T)18 * k * kc2;
+    T r2 = R[1] + (T)12 * k * R[2];
+    T r4 = R[3] - (T)6 * kc2 * R[0];
+    T x2 = (d * r2 - (T)6 * k * r4) / det;
+    T x4 = (a * r4 + (T)3 * kc2 * r2) / det;
+    X[0] = R[0] + k * x4;
+    X[1] = x2;
+    X[2] = R[2] - kc2 * x2;
+    X[3] = x4;
+}
+
+template <class T>
+HSGN_HD void source_step(T *q, T c2, T tau)
+{
+    const T gam = (T)(1.0 - 0.70710678118654752440);
+    T h = q[IH];
+    T Y[4] = {q[IHW], q[IHS], q[IHP], q[IHPB]};
+    T k = gam * tau / h;
+    T Y1[4];
+    stage_solve(k, c2, Y, Y1);
+    T th = tau / h;
+    T w = (T)1 - gam;
+    T MY[4] = {Y1[3], (T)12 * Y1[2] - (T)6 * Y1[3], -c2 * Y1[1],
+               (T)-6 * c2 * Y1[0] + (T)3 * c2 * Y1[1]};
+    T R[4];
+    for (int m = 0; m < 4; m++) R[m] = Y[m] + w * (th * MY[m]);
+    T Y2[4];
+    stage_solve(k, c2, R, Y2);
+    q[IHW] = Y2[0]; q[IHS] = Y2[1]; q[IHP] = Y2[2]; q[IHPB] = Y2[3];
+}
+
+// source step or clearing of the auxiliary variables (dry or SWE cell)
+template <class T>
+HSGN_HD void source_or_clear(const StepParams &P, T *q, T c2, int swe, T tau)
+{
+    if (q[IH] > (T)P.dry_tol && !swe) {
+        source_step(q, c2, tau);
+    } else {
+        q[IHW] = (T)0; q[IHS] = (T)0; q[IHP] = (T)0; q[IHPB] = (T)0;
+    }
+}
+
+// fill the derived fields of a cell from its conserved variables
+template <class T>
+HSGN_HD void derive(const StepParams &P, Cell<T> &c)
+{
+    c.h = c.q[IH] > (T)0 ? c.q[IH] : (T)0;
+    c.wet = c.q[IH] > (T)P.dry_tol;
+    if (c.wet) {
+        T h = c.q[IH];
+        c.u = c.q[IHU] / h; c.v = c.q[IHV] / h; c.w = c.q[IHW] / h;
+        c.s = c.q[IHS] / h; c.p = c.q[IHP] / h; c.pb = c.q[IHPB] / h;
+    } else {
+        c.u = c.v = c.w = c.s = c.p = c.pb = (T)0;
+    }
+}
+
+// bathymetry sharpness sensor psi of Sec. 4
+template <class T>
+HSGN_HD T sensor(const StepParams &P, T bL, T bR)
+{
+    T db = bR - bL;
+    if (db == (T)0) return (T)1;
+    T sum = fabs(bR + bL);
+    if (sum == (T)0) return (T)0;
+    T xi = (T)2 * fabs(db) / sum;
+    if (xi < (T)P.xi0) return (T)1;
+    if (xi < (T)(P.xi0 + P.xi1)) {
+        T r = (xi - (T)P.xi0) / (T)P.xi1;
+        return (T)-3 * r * r + (T)2 * r * r * r + (T)1;
+    }
+    return (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// normal Riemann solve.  DIR = 0: x-edge (normal momentum hu), DIR = 1:
+// y-edge (normal momentum hv).  Returns false if the edge is not hyperbolic.
+template <class T>
+struct Side {
+    T h, hun, un, ut, w, s, p, pb, hp, b, c2;
+};
+
+template <int DIR, class T>
+HSGN_HD void side_of(const Cell<T> &c, Side<T> &sd)
+{
+    const int IN = DIR == 0 ? IHU : IHV;
+    sd.h = c.h;
+    sd.b = c.b;
+    sd.c2 = c.c2;
+    if (c.wet) {
+        sd.hun = c.q[IN];
+        sd.un = DIR == 0 ? c.u : c.v;
+        sd.ut = DIR == 0 ? c.v : c.u;
+        sd.w = c.w; sd.s = c.s; sd.p = c.p; sd.pb = c.pb; sd.hp = c.q[IHP];
+    } else {
+        sd.hun = sd.un = sd.ut = sd.w = sd.s = sd.p = sd.pb = sd.hp = (T)0;
+    }
+}
+
+template <int DIR, class T>
+HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
+                     Waves<T> &W, Eig<T> &E)
+{
+    const int IN = DIR == 0 ? IHU : IHV;   // normal momentum component
+    const int IT = DIR == 0 ? IHV : IHU;   // tangential momentum component
+    const T g = (T)P.g;
+    for (int m = 0; m < 7; m++) { W.z0[m] = (T)0; W.z6[m] = (T)0; }
+    W.zm[0] = W.zm[1] = W.zm[2] = (T)0;
+    W.bs = W.bw = W.bt = W.bpb = (T)0;
+    W.smin = W.smax = W.uh = (T)0;
+    W.kind = KIND_REGULAR;
+    E.wet = cL.wet && cR.wet;
+    E.uh = E.vh = E.wh = E.sh = E.pbh = E.ghh = E.c2p = (T)0;
+    E.ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1;
+    if (!cL.wet && !cR.wet) { W.kind = KIND_DRY; return true; }
+
+    Side<T> L, R;
+    side_of<DIR>(cL, L);
+    side_of<DIR>(cR, R);
+    int dryL = 0, dryR = 0;
+    if (cL.wet && !cR.wet) {
+        if (cL.q[IH] + cL.b < cR.b) {
+            W.kind = KIND_WALL_R;
+            R = L; R.hun = -L.hun; R.un = -L.un;
+        } else {
+            dryR = 1;
+        }
+    } else if (!cL.wet && cR.wet) {
+        if (cR.q[IH] + cR.b < cL.b) {
+            W.kind = KIND_WALL_L;
+            L = R; L.hun = -R.hun; L.un = -R.un;
+        } else {
+            dryL = 1;
+        }
+    }
+
+    T sqL = sqrt(L.h), sqR = sqrt(R.h);
+    T den = sqL + sqR;
+    T hh = (T)0.5 * (L.h + R.h);
+    T c2h = (T)0.5 * (L.c2 + R.c2);
+    T uh = (sqR * R.un + sqL * L.un) / den;
+    T vh = (sqR * R.ut + sqL * L.ut) / den;
+    T wh = (sqR * R.w + sqL * L.w) / den;
+    T sh = (sqR * R.s + sqL * L.s) / den;
+    T ph = (sqR * R.p + sqL * L.p) / den;
+    T pbh = (sqR * R.pb + sqL * L.pb) / den;
+
+    T psi = sensor(P, L.b, R.b);
+    T db = R.b - L.b;
+    T dh = R.h - L.h;
+    T deta = (R.h + R.b) - (L.h + L.b);
+
+    T df[7];
+    df[0] = R.hun - L.hun;
+    df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * pbh * db;
+    df[2] = R.hun * R.ut - L.hun * L.ut;
+    df[3] = R.hun * R.w - L.hun * L.w;
+    df[4] = R.hun * R.s - L.hun * L.s;
+    df[5] = (R.hun * (R.p + R.c2) - L.hun * (L.p + L.c2)) - c2h * uh * dh;
+    df[6] = (R.hun * R.pb - L.hun * L.pb) - (T)6 * c2h * uh * psi * db;
+
+    T ce2 = g * hh + ph + c2h;
+    if (!(ce2 > (T)0)) return false;
+    T ceh = sqrt(ce2);
+    T smin, smax;
+    if (dryL) {
+        smin = R.un - (T)2 * sqrt(g * R.h);
+    } else {
+        T a = g * L.h + L.p + L.c2;
+        if (a < (T)0) return false;
+        smin = tmin(uh - ceh, L.un - sqrt(a));
+    }
+    if (dryR) {
+        smax = L.un + (T)2 * sqrt(g * L.h);
+    } else {
+        T a = g * R.h + R.p + R.c2;
+        if (a < (T)0) return false;
+        smax = tmax(uh + ceh, R.un + sqrt(a));
+    }
+
+    // normal-frame waves, then scattered into the global frame
+    T n0[7], n6[7];
+    if (L.c2 == (T)0 && R.c2 == (T)0) {
+        // SWE edge: HLLE waves carrying the surface-elevation jump
+        T ds = smax - smin;
+        T dq0 = deta, dq1 = R.hun - L.hun;
+        T z1h = smin * ((smax * dq0 - df[0]) / ds);
+        T z1m = smin * ((smax * dq1 - df[1]) / ds);
+        T z7h = smax * ((df[0] - smin * dq0) / ds);
+        T z7m = smax * ((df[1] - smin * dq1) / ds);
+        T S = z1h + z7h;
+        n0[0] = z1h; n0[1] = z1m; n0[2] = vh * z1h; n0[3] = wh * z1h;
+        n0[4] = sh * z1h; n0[5] = ph * z1h; n0[6] = pbh * z1h;
+        n6[0] = z7h; n6[1] = z7m; n6[2] = vh * z7h; n6[3] = wh * z7h;
+        n6[4] = sh * z7h; n6[5] = ph * z7h; n6[6] = pbh * z7h;
+        W.zm[0] = (T)0; W.zm[1] = (T)0; W.zm[2] = df[5] - ph * S;
+        W.bs = df[4] - sh * S;
+        W.bw = df[3] - wh * S;
+        W.bt = df[2] - vh * S;
+        W.bpb = df[6] - pbh * S;
+    } else {
+        T b2 = ((c2h + ph) * df[0] - df[5]) / ce2;
+        T S = df[0] - b2;
+        T Tm = df[1] - uh * b2;
+        T b1 = (smax * S - Tm) / (smax - smin);
+        T b7 = (Tm - smin * S) / (smax - smin);
+        n0[0] = b1; n0[1] = b1 * smin; n0[2] = b1 * vh; n0[3] = b1 * wh;
+        n0[4] = b1 * sh; n0[5] = b1 * (c2h + ph); n0[6] = b1 * pbh;
+        n6[0] = b7; n6[1] = b7 * smax; n6[2] = b7 * vh; n6[3] = b7 * wh;
+        n6[4] = b7 * sh; n6[5] = b7 * (c2h + ph); n6[6] = b7 * pbh;
+        W.zm[0] = b2; W.zm[1] = b2 * uh; W.zm[2] = b2 * (-g * hh);
+        W.bs = df[4] - sh * S;
+        W.bw = df[3] - wh * S;
+        W.bt = df[2] - vh * S;
+        W.bpb = df[6] - pbh * S;
+    }
+    W.z0[IH] = n0[0]; W.z0[IN] = n0[1]; W.z0[IT] = n0[2];
+    W.z6[IH] = n6[0]; W.z6[IN] = n6[1]; W.z6[IT] = n6[2];
+    for (int m = 3; m < 7; m++) { W.z0[m] = n0[m]; W.z6[m] = n6[m]; }
+    W.smin = smin; W.smax = smax; W.uh = uh;
+
+    E.uh = uh; E.vh = vh; E.wh = wh; E.sh = sh; E.pbh = pbh;
+    E.ghh = g * hh; E.c2p = c2h + ph; E.ce2 = ce2; E.smin = smin; E.smax = smax;
+    return true;
+}
+
+// full 7-vector of family f of the waves (global frame); DIR selects where
+// the normal-momentum component of family 1 and the tangential contact sit
+template <int DIR, class T>
+HSGN_HD void wave_vec(const Waves<T> &W, int f, T *z)
+{
+    const int IN = DIR == 0 ? IHU : IHV;
+    const int IT = DIR == 0 ? IHV : IHU;
+    for (int m = 0; m < 7; m++) z[m] = (T)0;
+    switch (f) {
+    case 0: for (int m = 0; m < 7; m++) z[m] = W.z0[m]; break;
+    case 1: z[IH] = W.zm[0]; z[IN] = W.zm[1]; z[IHP] = W.zm[2]; break;
+    case 2: z[IHS] = W.bs; break;
+    case 3: z[IHW] = W.bw; break;
+    case 4: z[IT] = W.bt; break;
+    case 5: z[IHPB] = W.bpb; break;
+    default: for (int m = 0; m < 7; m++) z[m] = W.z6[m]; break;
+    }
+}
+
+template <class T>
+HSGN_HD T wave_speed(const Waves<T> &W, int f)
+{
+    return f == 0 ? W.smin : (f == 6 ? W.smax : W.uh);
+}
+
+// dot products of the 7 families of two edges (same direction)
+template <int DIR, class T>
+HSGN_HD void family_dots(const Waves<T> &A, const Waves<T> &B, T *d)
+{
+    for (int f = 0; f < 7; f++) {
+        T za[7], zb[7];
+        wave_vec<DIR>(A, f, za);
+        wave_vec<DIR>(B, f, zb);
+        T s = (T)0;
+        for (int m = 0; m < 7; m++) s += za[m] * zb[m];
+        d[f] = s;
+    }
+}
+
+template <class T>
+HSGN_HD T limiter_phi(int lim, T th)
+{
+    switch (lim) {
+    case 1: return tmax((T)0, tmin((T)1, th));
+    case 2: return tmax((T)0, tmin(tmin((T)0.5 * ((T)1 + th), (T)2), (T)2 * th));
+    case 3: return (T)1;
+    default: return (T)0;
+    }
+}
+
+// limited second-order correction of an edge from its own waves and the dot
+// products with the left (dl) and right (dr) neighbouring edges
+template <int DIR, class T>
+HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T *dr, T *F)
+{
+    for (int m = 0; m < 7; m++) F[m] = (T)0;
+    if (lim == 0 || W.kind != KIND_REGULAR) return;
+    T self[7];
+    family_dots<DIR>(W, W, self);
+    for (int f = 0; f < 7; f++) {
+        T zz = self[f];
+        if (zz == (T)0) continue;
+        T s = wave_speed(W, f);
+        T th = (s > (T)0 ? dl[f] : dr[f]) / zz;
+        T ph = limiter_phi(lim, th);
+        T sg = s > (T)0 ? (T)1 : (s < (T)0 ? (T)-1 : (T)0);
+        T c = (T)0.5 * sg * ((T)1 - dtdx * fabs(s)) * ph;
+        T z[7];
+        wave_vec<DIR>(W, f, z);
+        for (int m = 0; m < 7; m++) F[m] += c * z[m];
+    }
+}
+
+// left- and right-going fluctuations
+template <int DIR, class T>
+HSGN_HD void fluctuations(const Waves<T> &W, T *am, T *ap)
+{
+    for (int m = 0; m < 7; m++) { am[m] = (T)0; ap[m] = (T)0; }
+    for (int f = 0; f < 7; f++) {
+        T s = wave_speed(W, f);
+        T z[7];
+        wave_vec<DIR>(W, f, z);
+        for (int m = 0; m < 7; m++) {
+            if (s < (T)0) am[m] += z[m];
+            else if (s > (T)0) ap[m] += z[m];
+            else { am[m] += (T)0.5 * z[m]; ap[m] += (T)0.5 * z[m]; }
+        }
+    }
+    if (W.kind == KIND_WALL_R) for (int m = 0; m < 7; m++) ap[m] = (T)0;
+    if (W.kind == KIND_WALL_L) for (int m = 0; m < 7; m++) am[m] = (T)0;
+}
+
+// transverse split of a global-frame vector a by the eigenstructure E of an
+// edge of direction DIR: returns the part moving with sign sgn
+template <int DIR, class T>
+HSGN_HD void trans_split(const Eig<T> &E, const T *a, int sgn, T *out)
+{
+    const int IN = DIR == 0 ? IHU : IHV;
+    const int IT = DIR == 0 ? IHV : IHU;
+    T an[7] = {a[IH], a[IN], a[IT], a[IHW], a[IHS], a[IHP], a[IHPB]};
+    T g2 = (E.c2p * an[0] - an[5]) / E.ce2;
+    T S = an[0] - g2;
+    T Tm = an[1] - E.uh * g2;
+    T g1 = (E.smax * S - Tm) / (E.smax - E.smin);
+    T g7 = (Tm - E.smin * S) / (E.smax - E.smin);
+    T gt = an[2] - E.vh * S;
+    T gw = an[3] - E.wh * S;
+    T gs = an[4] - E.sh * S;
+    T gpb = an[6] - E.pbh * S;
+    T s1 = sgn > 0 ? tmax(E.smin, (T)0) : tmin(E.smin, (T)0);
+    T sm = sgn > 0 ? tmax(E.uh, (T)0) : tmin(E.uh, (T)0);
+    T s7 = sgn > 0 ? tmax(E.smax, (T)0) : tmin(E.smax, (T)0);
+    T r1[7] = {(T)1, E.smin, E.vh, E.wh, E.sh, E.c2p, E.pbh};
+    T r7[7] = {(T)1, E.smax, E.vh, E.wh, E.sh, E.c2p, E.pbh};
+    T mid[7] = {g2, g2 * E.uh, gt, gw, gs, g2 * (-E.ghh), gpb};
+    T on[7];
+    for (int m = 0; m < 7; m++) on[m] = s1 * g1 * r1[m] + sm * mid[m] + s7 * g7 * r7[m];
+    out[IH] = on[0]; out[IN] = on[1]; out[IT] = on[2];
+    for (int m = 3; m < 7; m++) out[m] = on[m];
+}
+
+}  // namespace hsgn

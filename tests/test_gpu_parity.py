@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar: every conserved field within 1e-11 of the oracle relative to that
+field's largest magnitude, masks (transition function and breaking latch)
+equal, clocks equal to 1e-12, gauges within 1e-11 of the wave amplitude.
+Both sides compute in FP64 without fused multiply-add; they differ only in
+summation order (the kernel regroups the transverse split per cell and
+solves the source step's 4x4 systems in closed form), so results agree to a
+few ulps per step.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_12162_amd import hsgn as H
+from paper_2606_12162_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    H.lib()
+    yield
+
+
+def field_errors(got, exp):
+    scale = np.abs(exp).max(axis=(1, 2))
+    err = np.abs(got - exp).max(axis=(1, 2))
+    return np.where(scale > 0, err / np.where(scale > 0, scale, 1.0), err)
+
+
+def assert_parity(got, exp, what=""):
+    e = field_errors(got, exp)
+    assert np.all(e <= TOL), "%s field errors %s" % (what, np.array2string(e, precision=2))
+    return e.max()
+
+
+def run_pair(workloads, steps, dt=0.0, tile_rows=0, gauges=True):
+    ctx = H.from_workloads(workloads, tile_rows=tile_rows, gauges=gauges)
+    ctx.advance(dt, steps)
+    refs = []
+    for w in workloads:
+        r = O.from_workload(w) if gauges else O.OracleGrid(w.params, w.grid)
+        if not gauges:
+            r.set_bathymetry(w.b)
+            r.set_state(w.q)
+        r.advance(dt, steps)
+        refs.append(r)
+    return ctx, refs
+
+
+def check_all(ctx, refs, workloads, gauges=True):
+    worst = 0.0
+    for s, (r, w) in enumerate(zip(refs, workloads)):
+        print("case", w.name, "scenario", s, flush=True)
+        worst = max(worst, assert_parity(ctx.get_state(s), r.get_state(), w.name))
+        assert np.array_equal(ctx.get_mask(s), r.get_mask())
+        t, dtn, steps = ctx.clock(s)
+        rt, rdt, rsteps, _ = r.clock()
+        assert steps == rsteps
+        assert abs(t - rt) <= 1e-12 * max(rt, 1e-300)
+        if gauges and len(w.gauges):
+            tg, eg = ctx.read_gauges(s)
+            to, eo = r.read_gauges()
+            assert tg.shape == to.shape and eg.shape == eo.shape
+            np.testing.assert_allclose(tg, to, rtol=1e-12, atol=0)
+            assert np.abs(eg - eo).max() <= TOL * w.amplitude
+    return worst
+
+
+def test_gaussian_hump_128_periodic_full_config():
+    w = W.gaussian_hump()                      # 128 x 128, 200 adaptive steps
+    ctx, refs = run_pair([w], w.steps)
+    worst = check_all(ctx, refs, [w])
+    print("worst relative field error", worst)
+    d = ctx.diagnostics(0)
+    assert abs(d["mass"] - refs[0].mass()) <= 1e-13 * refs[0].mass()
+    assert d["steps"] == 200 and d["cell_updates"] == 200 * 128 * 128
+
+
+def test_beach_wet_dry_walls_reduced():
+    w = W.beach_soliton(n=256, dx=0.2, steps=600)
+    ctx, refs = run_pair([w], w.steps)
+    check_all(ctx, refs, [w])
+    assert refs[0].get_mask().max() <= 3
+
+
+def rough_case(nx, ny, bc, seed):
+    rng = np.random.default_rng(seed)
+    grid = W.Grid(nx, ny, 0.0, 0.0, 0.1, 0.13, bc)
+    X, Y = W.cell_centres(grid)
+    b = W.fp32_representable(-1.0 + 1.3 * X / X.max() + 0.1 * rng.standard_normal((ny, nx)))
+    q = np.zeros((7, ny, nx))
+    q[0] = np.maximum(0.1 * np.exp(-((X - 2) ** 2 + (Y - 3) ** 2)) - b, 0.0)
+    q[1] = q[0] * 0.2 * rng.standard_normal((ny, nx))
+    q[2] = q[0] * 0.2 * rng.standard_normal((ny, nx))
+    q[3] = q[0] * 0.01 * rng.standard_normal((ny, nx))
+    q[4] = q[0] * 0.01 * rng.standard_normal((ny, nx))
+    q[5] = q[0] * q[0] * 0.05 * rng.standard_normal((ny, nx))
+    q[6] = q[0] * q[0] * 0.05 * rng.standard_normal((ny, nx))
+    P = W.Params(alpha=3.0, h_star=0.2, kappa=0.8)
+    gx = np.array([[1.0, 1.0], [3.3, 2.1], [5.0, 4.0]])
+    return W.Workload("rough_%dx%d_bc%s" % (nx, ny, "".join(map(str, bc))), P, grid, b, q, gx,
+                      20, 0.004, 0.1)
+
+
+@pytest.mark.parametrize("bc", [
+    (W.BC_WALL, W.BC_EXTRAP, W.BC_PERIODIC, W.BC_PERIODIC),
+    (W.BC_PERIODIC, W.BC_PERIODIC, W.BC_WALL, W.BC_EXTRAP),
+    (W.BC_EXTRAP, W.BC_WALL, W.BC_EXTRAP, W.BC_WALL),
+])
+def test_ragged_strips_and_tiles_all_boundaries(bc):
+    # 70 = 60 + 10 columns (partial strip), 45 rows with 11-row tiles (ragged tail)
+    w = rough_case(70, 45, bc, 5)
+    ctx, refs = run_pair([w], 20, dt=0.004, tile_rows=11)
+    check_all(ctx, refs, [w])
+
+
+def test_smallest_grid():
+    w = rough_case(4, 4, (W.BC_PERIODIC,) * 4, 6)
+    w.gauges = np.zeros((0, 2))
+    ctx, refs = run_pair([w], 10, dt=0.002)
+    check_all(ctx, refs, [w])
+
+
+def test_batched_scenarios_one_launch():
+    ws = [W.gaussian_hump(n=64, dx=0.1), rough_case(70, 45, (W.BC_WALL,) * 4, 7),
+          W.beach_soliton(n=128, dx=0.4)]
+    for w in ws:
+        w.gauges = w.gauges[:4]
+    ctx, refs = run_pair(ws, 30)
+    check_all(ctx, refs, ws)
+
+
+def test_beach_full_size_bench_configuration():
+    """The 1024 x 1024 beach in the launch configuration the benchmark times
+    (library-chosen tiles), a few adaptive steps, every field compared."""
+    w = W.beach_soliton()
+    ctx, refs = run_pair([w], 3)
+    check_all(ctx, refs, [w])
+
+
+def test_tiling_invariance_bitwise_and_determinism():
+    w = W.gaussian_hump(n=128, dx=0.1)
+    outs = []
+    for th in (8, 33, 8):
+        ctx = H.from_workloads([w], tile_rows=th)
+        ctx.advance(0.0, 50)
+        outs.append(ctx.get_state(0))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+def test_checkpoint_restart_bitwise():
+    w = W.beach_soliton(n=128, dx=0.4)
+    a = H.from_workloads([w])
+    a.advance(0.0, 40)
+    qa = a.get_state(0)
+    b = H.from_workloads([w])
+    b.advance(0.0, 20)
+    q, m, clk = b.get_state(0), b.get_mask(0), b.clock(0)
+    c = H.from_workloads([w])
+    c.set_state(0, q)
+    c.set_mask(0, m)
+    c.set_clock(0, clk[0], clk[1], clk[2])
+    c.advance(0.0, 20)
+    assert np.array_equal(c.get_state(0), qa)
+    assert c.clock(0) == a.clock(0)
+
+
+def test_device_resident_io_matches_host_io():
+    w = W.gaussian_hump(n=64, dx=0.1)
+    a = H.from_workloads([w])
+    b = H.from_workloads([w])
+    b.set_state(0, torch.from_numpy(w.q).cuda())
+    a.advance(0.0, 10)
+    b.advance(0.0, 10)
+    out = torch.empty((7, 64, 64), dtype=torch.float64, device="cuda")
+    b.get_state(0, out)
+    assert np.array_equal(out.cpu().numpy(), a.get_state(0))
+
+
+def test_fixed_step_above_cfl_reports_and_keeps_last_good_state():
+    w = W.gaussian_hump(n=64, dx=0.1)
+    dt = 1.5 * 0.1 / 10.0                 # Courant ~ 1.5
+    ctx = H.from_workloads([w])
+    assert ctx.advance_status(dt, 3) == H.HSGN_ECFL
+    assert np.array_equal(ctx.get_state(0), w.q)
+    r = O.from_workload(w)
+    with pytest.raises(O.OracleError) as e:
+        r.advance(dt, 3)
+    assert e.value.code == O.ECFL
+
+
+def test_non_hyperbolic_and_non_finite_states_are_reported():
+    w = W.gaussian_hump(n=64, dx=0.1)
+    q = w.q.copy()
+    q[5, 10, 10] = -1e4 * q[0, 10, 10]     # p far below -(g h + c^2)
+    ctx = H.from_workloads([w])
+    ctx.set_state(0, q)
+    assert ctx.advance_status(0.002, 2) == H.HSGN_ENONHYP
+    q = w.q.copy()
+    q[1, 20, 20] = np.nan
+    ctx = H.from_workloads([w])
+    ctx.set_state(0, q)
+    assert ctx.advance_status(0.002, 2) in (H.HSGN_ENAN, H.HSGN_ENONHYP)

@@ -144,6 +144,13 @@ int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next,
 /* Number of marching work items (wavefronts) of one step. */
 int hsgn_work_items(hsgn_ctx *c, int *n);
 
+/* Kernel timing for measurement: with on = 1, every launch of the step
+ * kernel inside hsgn_advance is bracketed by HIP events on the context's
+ * stream.  hsgn_get_timing returns the summed event time (ms) and the number
+ * of launches timed since timing was switched on, then resets both. */
+int hsgn_set_timing(hsgn_ctx *c, int on);
+int hsgn_get_timing(hsgn_ctx *c, double *step_kernel_ms, long long *launches);
+
 int hsgn_destroy(hsgn_ctx *c);
 const char *hsgn_strerror(int code);
 const char *hsgn_last_error(hsgn_ctx *c);

@@ -272,6 +272,12 @@ struct hsgn_ctx {
     int ngauge_total = 0;
     long long qtotal = 0, ctotal = 0, rec_total = 0;
     std::string last_error;
+    // optional step-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;     // pairs (start, stop) per timed launch
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    long long timed_launches = 0;
 };
 
 static int fail(hsgn_ctx *c, int code, const std::string &msg)
@@ -287,8 +293,16 @@ static int fail(hsgn_ctx *c, int code, const std::string &msg)
             return fail((c), HSGN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+static void free_events(hsgn_ctx *c)
+{
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    c->ev_used = 0;
+}
+
 static void free_device(hsgn_ctx *c)
 {
+    free_events(c);
     void *ptrs[] = {c->q0, c->q1, c->bath, c->clip, c->rec, c->m0, c->m1, c->d_patches,
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
                     c->d_mass};
@@ -695,6 +709,8 @@ int hsgn_read_gauges(hsgn_ctx *c, int scenario, double *t, double *eta, int max_
     return push_scen(c, st);
 }
 
+static int collect_timing(hsgn_ctx *c);
+
 static int launch_attempt(hsgn_ctx *c)
 {
     MarchArgs<double> A;
@@ -707,7 +723,21 @@ static int launch_attempt(hsgn_ctx *c)
     A.scen = c->d_scen;
     A.clip_slots = c->clip;
     A.nwork = (int)c->work.size();
+    if (c->timing) {
+        if (c->ev_used + 2 > c->ev.size()) {
+            for (int k = 0; k < 256; k++) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreate(&e));
+                c->ev.push_back(e);
+            }
+        }
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    }
     march_kernel<<<(unsigned)c->work.size(), 64, 0, c->stream>>>(A);
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+    }
     int ns = (int)c->scen.size();
     control_kernel<<<(unsigned)((ns + 63) / 64), 64, 0, c->stream>>>(c->d_scen, c->d_sstat, c->clip, ns);
     if (c->ngauge_total > 0)
@@ -764,8 +794,10 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
     if ((rc = ensure_gauges(c, st, (long long)n_steps + 256))) return rc;
     long long attempts = n_steps, budget = (long long)n_steps + 4096;
     while (attempts > 0) {
-        for (long long a = 0; a < attempts; a++)
+        for (long long a = 0; a < attempts; a++) {
             if ((rc = launch_attempt(c))) return rc;
+            if (c->timing && c->ev_used >= 8192 && (rc = collect_timing(c))) return rc;
+        }
         budget -= attempts;
         if ((rc = pull_scen(c, st))) return rc;
         long long left = 0;
@@ -855,6 +887,43 @@ int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next, long lon
     st[scenario].steps = steps;
     st[scenario].err = 0;
     return push_scen(c, st);
+}
+
+static int collect_timing(hsgn_ctx *c)
+{
+    if (c->ev_used == 0) return HSGN_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+    }
+    c->ev_used = 0;
+    return HSGN_OK;
+}
+
+int hsgn_set_timing(hsgn_ctx *c, int on)
+{
+    if (!c) return HSGN_EINVAL;
+    int rc = collect_timing(c);
+    if (rc) return rc;
+    c->timing = on != 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return HSGN_OK;
+}
+
+int hsgn_get_timing(hsgn_ctx *c, double *step_kernel_ms, long long *launches)
+{
+    if (!c) return HSGN_EINVAL;
+    int rc = collect_timing(c);
+    if (rc) return rc;
+    if (step_kernel_ms) *step_kernel_ms = c->timed_ms;
+    if (launches) *launches = c->timed_launches;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return HSGN_OK;
 }
 
 int hsgn_work_items(hsgn_ctx *c, int *n)

@@ -22,8 +22,8 @@ BC_PERIODIC, BC_WALL, BC_EXTRAP = 0, 1, 2
 EXPORTS = ("hsgn_create", "hsgn_add_grid", "hsgn_finalize", "hsgn_set_bathymetry",
            "hsgn_set_state", "hsgn_get_state", "hsgn_get_mask", "hsgn_set_mask",
            "hsgn_set_gauges", "hsgn_read_gauges", "hsgn_advance", "hsgn_diagnostics",
-           "hsgn_get_clock", "hsgn_set_clock", "hsgn_work_items", "hsgn_destroy",
-           "hsgn_strerror", "hsgn_last_error")
+           "hsgn_get_clock", "hsgn_set_clock", "hsgn_work_items", "hsgn_set_timing",
+           "hsgn_get_timing", "hsgn_destroy", "hsgn_strerror", "hsgn_last_error")
 
 
 class hsgn_params(ctypes.Structure):
@@ -76,6 +76,8 @@ def lib():
         L.hsgn_set_clock.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_longlong]
         L.hsgn_work_items.argtypes = [vp, ip]
+        L.hsgn_set_timing.argtypes = [vp, ctypes.c_int]
+        L.hsgn_get_timing.argtypes = [vp, dp, dp]
         L.hsgn_destroy.argtypes = [vp]
         L.hsgn_strerror.argtypes = [ctypes.c_int]
         L.hsgn_strerror.restype = ctypes.c_char_p
@@ -222,6 +224,16 @@ class Context:
     def set_clock(self, scenario, t, dt_next, steps):
         self._check(lib().hsgn_set_clock(self.h, scenario, t, dt_next, steps), "hsgn_set_clock")
 
+    def set_timing(self, on):
+        self._check(lib().hsgn_set_timing(self.h, 1 if on else 0), "hsgn_set_timing")
+
+    def get_timing(self):
+        """(summed step-kernel milliseconds, launches) since the last call."""
+        ms, n = ctypes.c_double(), ctypes.c_longlong()
+        self._check(lib().hsgn_get_timing(self.h, ctypes.byref(ms), ctypes.byref(n)),
+                    "hsgn_get_timing")
+        return ms.value, n.value
+
     def work_items(self):
         n = ctypes.c_int()
         self._check(lib().hsgn_work_items(self.h, ctypes.byref(n)), "hsgn_work_items")
@@ -232,6 +244,9 @@ def from_workloads(workloads, tile_rows=0, stream=None, gauges=True):
     """A finalized context with one scenario per workload (one patch each),
     bathymetry, state and gauges set."""
     ws = list(workloads)
+    for w in ws[1:]:
+        if w.params != ws[0].params:
+            raise ValueError("workloads of one context must share their parameters")
     ctx = Context(ws[0].params, tile_rows=tile_rows, stream=stream)
     for s, w in enumerate(ws):
         ctx.add_grid(s, w.grid)

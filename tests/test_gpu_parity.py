@@ -131,10 +131,13 @@ def test_smallest_grid():
 
 
 def test_batched_scenarios_one_launch():
+    # a context shares one parameter set; every scenario and its oracle use it
     ws = [W.gaussian_hump(n=64, dx=0.1), rough_case(70, 45, (W.BC_WALL,) * 4, 7),
           W.beach_soliton(n=128, dx=0.4)]
+    common = W.Params(alpha=3.0, h_star=0.05, kappa=0.8, dry_tol=1e-3)
     for w in ws:
         w.gauges = w.gauges[:4]
+        w.params = common
     ctx, refs = run_pair(ws, 30)
     check_all(ctx, refs, ws)
 

@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated tile heights to time before the run; the "
+                         "fastest is used for the timed steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -80,7 +83,22 @@ def main():
     torch.cuda.set_device(0)
     ws = workload_by_name(args.workload)
     dt = ws[0].dt
-    ctx = H.from_workloads(ws, tile_rows=args.tile_rows)
+    tile_rows = args.tile_rows
+    if args.sweep:
+        best = None
+        for th in [int(x) for x in args.sweep.split(",")]:
+            c = H.from_workloads(ws, tile_rows=th)
+            c.advance(dt, 5)
+            c.set_timing(True)
+            c.advance(dt, 50)
+            ms, n = c.get_timing()
+            c.close()
+            us = ms / max(n, 1) * 1e3
+            print("sweep: tile rows %d: step kernel %.1f us" % (th, us), file=sys.stderr, flush=True)
+            if best is None or us < best[0]:
+                best = (us, th)
+        tile_rows = best[1]
+    ctx = H.from_workloads(ws, tile_rows=tile_rows)
     cells = sum(w.grid.nx * w.grid.ny for w in ws)
     print("bench: %s, %d cells, %d work items, warmup %d, steps %d"
           % (ws[0].name, cells, ctx.work_items(), args.warmup, args.steps),
@@ -117,7 +135,7 @@ def main():
         "config": {"workload": ws[0].name, "cells": cells, "precision": "fp64",
                    "dt": "adaptive, cfl 0.9" if dt <= 0 else "fixed %.6g" % dt,
                    "rejected_steps": diag["rejected"], "max_courant": diag["max_courant"],
-                   "work_items": ctx.work_items()},
+                   "work_items": ctx.work_items(), "tile_rows": tile_rows or "library"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "march_kernel", "kernel_avg_us": kavg_s * 1e6,

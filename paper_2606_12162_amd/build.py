@@ -18,8 +18,8 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions (their forms are not trusted on this target)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # products and sums are rounded separately, as in the reference arithmetic
-    "-ffp-contract=off",
+    # fused multiply-add where the compiler finds a*b+c
+    "-ffp-contract=fast",
     "-Wno-unused-result",
 ]
 

@@ -66,13 +66,26 @@ struct ScenStatic {
     int w0, w1;               // work-item range of the scenario
 };
 
-__global__ void control_kernel(ScenState *S, const ScenStatic *SS, const double *clip_slots,
-                               int nscen)
+// one block per scenario; the clipped-mass slots are summed in a fixed order
+// (strided per thread, then a fixed tree) so results are reproducible
+__global__ __launch_bounds__(256) void control_kernel(ScenState *S, const ScenStatic *SS,
+                                                      const double *clip_slots, int nscen)
 {
-    int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    __shared__ double part[256];
+    const int s = (int)blockIdx.x;
+    const int tid = (int)threadIdx.x;
     if (s >= nscen) return;
+    const ScenStatic ss = SS[s];
+    double cs = 0.0;
+    for (int w = ss.w0 + tid; w < ss.w1; w += 256) cs += clip_slots[w];
+    part[tid] = cs;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) part[tid] += part[tid + h];
+        __syncthreads();
+    }
+    if (tid != 0) return;
     ScenState &st = S[s];
-    const ScenStatic &ss = SS[s];
     double rx = __longlong_as_double((long long)st.rx_bits);
     double ry = __longlong_as_double((long long)st.ry_bits);
     st.rx_bits = 0ull;
@@ -98,9 +111,7 @@ __global__ void control_kernel(ScenState *S, const ScenStatic *SS, const double 
     st.accepted = 1;
     st.courant = courant;
     st.max_courant = fmax(st.max_courant, courant);
-    double clip = 0.0;
-    for (int w = ss.w0; w < ss.w1; w++) clip += clip_slots[w];
-    st.clip_total += clip;
+    st.clip_total += part[0];
     if (st.adaptive && courant > 0.0) st.dt = dt * ss.cfl / courant;
     if (st.steps >= st.target) st.active = 0;
 }
@@ -739,7 +750,7 @@ static int launch_attempt(hsgn_ctx *c)
         c->ev_used += 2;
     }
     int ns = (int)c->scen.size();
-    control_kernel<<<(unsigned)((ns + 63) / 64), 64, 0, c->stream>>>(c->d_scen, c->d_sstat, c->clip, ns);
+    control_kernel<<<(unsigned)ns, 256, 0, c->stream>>>(c->d_scen, c->d_sstat, c->clip, ns);
     if (c->ngauge_total > 0)
         gauge_kernel<<<(unsigned)((c->ngauge_total + 63) / 64), 64, 0, c->stream>>>(
             c->d_gauges, c->ngauge_total, c->d_scen, c->q0, c->q1, c->bath, c->prm.eta0,

@@ -73,6 +73,9 @@ HSGN_HD void shfl_cell(L &ln, const Cell<T> &c, Cell<T> &o, bool up)
 {
     for (int m = 0; m < 7; m++) o.q[m] = up ? ln.up(c.q[m]) : ln.dn(c.q[m]);
     o.h = up ? ln.up(c.h) : ln.dn(c.h);
+    o.sq = up ? ln.up(c.sq) : ln.dn(c.sq);
+    o.ce = up ? ln.up(c.ce) : ln.dn(c.ce);
+    o.hyp = up ? ln.upi(c.hyp) : ln.dni(c.hyp);
     o.u = up ? ln.up(c.u) : ln.dn(c.u);
     o.v = up ? ln.up(c.v) : ln.dn(c.v);
     o.w = up ? ln.up(c.w) : ln.dn(c.w);
@@ -100,25 +103,41 @@ HSGN_HD void shfl_vec(L &ln, const T *a, T *o, bool up)
     for (int m = 0; m < 7; m++) o[m] = up ? ln.up(a[m]) : ln.dn(a[m]);
 }
 
-// load cell (col, row) of a patch through the boundary map and apply the
-// first source half step (Strang) or clear a dry/SWE cell's auxiliaries
+// raw data of one cell as stored (state, bathymetry, mask byte)
 template <class T>
-HSGN_HD void load_cell(const StepParams &P, const PatchInfo &pi, const T *q, const T *bath,
-                       const uint8_t *mask, int mc, int fx, int row, T tau_pre, Cell<T> &c,
-                       int &phi, int &brk)
+struct RawCell {
+    T q[7];
+    T b;
+    int mk;
+};
+
+// load cell (col, row) of a patch through the boundary map
+template <class T>
+HSGN_HD void load_raw(const PatchInfo &pi, const T *q, const T *bath, const uint8_t *mask,
+                      int mc, int fx, int row, RawCell<T> &r)
 {
     int fy;
     int mr = map_index(row, pi.ny, pi.bc[2], pi.bc[3], &fy);
     long long idx = (long long)mr * pi.pitch + mc;
     long long plane = (long long)pi.ny * pi.pitch;
     const T *qp = q + pi.qoff + idx;
-    for (int m = 0; m < 7; m++) c.q[m] = qp[m * plane];
-    if (fx) c.q[IHU] = -c.q[IHU];
-    if (fy) c.q[IHV] = -c.q[IHV];
-    c.b = bath[pi.coff + idx];
-    uint8_t mk = mask[pi.coff + idx];
-    phi = mk & 1;
-    brk = (mk >> 1) & 1;
+    for (int m = 0; m < 7; m++) r.q[m] = qp[m * plane];
+    if (fx) r.q[IHU] = -r.q[IHU];
+    if (fy) r.q[IHV] = -r.q[IHV];
+    r.b = bath[pi.coff + idx];
+    r.mk = mask[pi.coff + idx];
+}
+
+// apply the first source half step (Strang) or clear a dry/SWE cell's
+// auxiliaries, then derive the primitive variables
+template <class T>
+HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, Cell<T> &c,
+                          int &phi, int &brk)
+{
+    for (int m = 0; m < 7; m++) c.q[m] = r.q[m];
+    c.b = r.b;
+    phi = r.mk & 1;
+    brk = (r.mk >> 1) & 1;
     int swe = !phi || brk;
     T H = still_depth(P, c.b);
     c.c2 = swe ? (T)0 : (T)P.a2g * H;
@@ -178,10 +197,17 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
     T rx = (T)0, ry = (T)0, clip = (T)0;
     for (int m = 0; m < 7; m++) { xtr_prev[m] = (T)0; bp_saved[m] = (T)0; ydl[m] = (T)0; }
 
+    RawCell<T> nxt;
+    load_raw(pi, qin, A.bath, min_, mc, fx, r0 - 2, nxt);
     for (int k = r0 - 2; k <= r0 + th + 1; k++) {
         const int sk = 2, sk1 = 1, sk2 = 0;
         Cell<T> c;
-        load_cell(P, pi, qin, A.bath, min_, mc, fx, k, tau_pre, c, phi_c, brk_c);
+        {
+            RawCell<T> raw = nxt;
+            // issue the next row's loads before working on this one
+            if (k < r0 + th + 1) load_raw(pi, qin, A.bath, min_, mc, fx, k + 1, nxt);
+            prepare_cell(P, raw, tau_pre, c, phi_c, brk_c);
+        }
         phi_w[sk] = phi_c;
         brk_w[sk] = brk_c;
         b_w[sk] = c.b;

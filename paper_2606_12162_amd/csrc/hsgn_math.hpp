@@ -51,9 +51,12 @@ template <class T>
 struct Cell {
     T q[7];            // conserved (h, hu, hv, hw, h sigma, hp, h p_b)
     T h;               // max(q[0], 0)
+    T sq;              // sqrt(h)
+    T ce;              // sqrt(g h + p + c^2) of a wet cell
     T u, v, w, s, p, pb;   // primitives, zero in dry cells
     T b, c2;
     int wet;           // h > dry_tol
+    int hyp;           // g h + p + c^2 >= 0 (always true for a dry cell)
 };
 
 // waves of one edge in the global frame.  Families: 0 (speed smin), 1
@@ -72,12 +75,32 @@ struct Waves {
 // (normal frame of that edge)
 template <class T>
 struct Eig {
-    T uh, vh, wh, sh, pbh, ghh, c2p, ce2, smin, smax;
+    T uh, vh, wh, sh, pbh, ghh, c2p, inv_ce2, smin, smax, inv_ds;
     int wet;           // both cells wet
 };
 
 template <class T>
 HSGN_HD T tmax(T a, T b) { return a > b ? a : b; }
+
+// reciprocal used where one denominator serves several quotients
+template <class T>
+HSGN_HD T recip(T x) { return (T)1 / x; }
+
+// reciprocal for the limiter ratios: hardware estimate refined by two
+// Newton steps (a few ulp), which is all a ratio fed to a continuous
+// limiter function needs
+HSGN_HD double frcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+#else
+    return 1.0 / x;
+#endif
+}
 template <class T>
 HSGN_HD T tmin(T a, T b) { return a < b ? a : b; }
 
@@ -116,11 +139,11 @@ HSGN_HD void stage_solve(T k, T c2, const T R[4], T X[4])
     T kc2 = k * c2;
     T a = (T)1 + (T)12 * k * kc2;
     T d = (T)1 + (T)6 * k * kc2;
-    T det = a * d + (T)18 * k * kc2;
+    T idet = recip(a * d + (T)18 * k * kc2);
     T r2 = R[1] + (T)12 * k * R[2];
     T r4 = R[3] - (T)6 * kc2 * R[0];
-    T x2 = (d * r2 - (T)6 * k * r4) / det;
-    T x4 = (a * r4 + (T)3 * kc2 * r2) / det;
+    T x2 = (d * r2 - (T)6 * k * r4) * idet;
+    T x4 = (a * r4 + (T)3 * kc2 * r2) * idet;
     X[0] = R[0] + k * x4;
     X[1] = x2;
     X[2] = R[2] - kc2 * x2;
@@ -131,12 +154,11 @@ template <class T>
 HSGN_HD void source_step(T *q, T c2, T tau)
 {
     const T gam = (T)(1.0 - 0.70710678118654752440);
-    T h = q[IH];
+    T th = tau * recip(q[IH]);
     T Y[4] = {q[IHW], q[IHS], q[IHP], q[IHPB]};
-    T k = gam * tau / h;
+    T k = gam * th;
     T Y1[4];
     stage_solve(k, c2, Y, Y1);
-    T th = tau / h;
     T w = (T)1 - gam;
     T MY[4] = {Y1[3], (T)12 * Y1[2] - (T)6 * Y1[3], -c2 * Y1[1],
                (T)-6 * c2 * Y1[0] + (T)3 * c2 * Y1[1]};
@@ -163,11 +185,17 @@ template <class T>
 HSGN_HD void derive(const StepParams &P, Cell<T> &c)
 {
     c.h = c.q[IH] > (T)0 ? c.q[IH] : (T)0;
+    c.sq = sqrt(c.h);
     c.wet = c.q[IH] > (T)P.dry_tol;
+    c.hyp = 1;
+    c.ce = (T)0;
     if (c.wet) {
-        T h = c.q[IH];
-        c.u = c.q[IHU] / h; c.v = c.q[IHV] / h; c.w = c.q[IHW] / h;
-        c.s = c.q[IHS] / h; c.p = c.q[IHP] / h; c.pb = c.q[IHPB] / h;
+        T ih = recip(c.q[IH]);
+        c.u = c.q[IHU] * ih; c.v = c.q[IHV] * ih; c.w = c.q[IHW] * ih;
+        c.s = c.q[IHS] * ih; c.p = c.q[IHP] * ih; c.pb = c.q[IHPB] * ih;
+        T a = (T)P.g * c.h + c.p + c.c2;
+        c.hyp = a >= (T)0;
+        c.ce = sqrt(a > (T)0 ? a : (T)0);
     } else {
         c.u = c.v = c.w = c.s = c.p = c.pb = (T)0;
     }
@@ -195,7 +223,8 @@ HSGN_HD T sensor(const StepParams &P, T bL, T bR)
 // y-edge (normal momentum hv).  Returns false if the edge is not hyperbolic.
 template <class T>
 struct Side {
-    T h, hun, un, ut, w, s, p, pb, hp, b, c2;
+    T h, sq, ce, hun, un, ut, w, s, p, pb, hp, b, c2;
+    int hyp;
 };
 
 template <int DIR, class T>
@@ -203,6 +232,9 @@ HSGN_HD void side_of(const Cell<T> &c, Side<T> &sd)
 {
     const int IN = DIR == 0 ? IHU : IHV;
     sd.h = c.h;
+    sd.sq = c.sq;
+    sd.ce = c.ce;
+    sd.hyp = c.hyp;
     sd.b = c.b;
     sd.c2 = c.c2;
     if (c.wet) {
@@ -229,7 +261,7 @@ HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
     W.kind = KIND_REGULAR;
     E.wet = cL.wet && cR.wet;
     E.uh = E.vh = E.wh = E.sh = E.pbh = E.ghh = E.c2p = (T)0;
-    E.ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1;
+    E.inv_ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1; E.inv_ds = (T)0.5;
     if (!cL.wet && !cR.wet) { W.kind = KIND_DRY; return true; }
 
     Side<T> L, R;
@@ -252,16 +284,16 @@ HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
         }
     }
 
-    T sqL = sqrt(L.h), sqR = sqrt(R.h);
-    T den = sqL + sqR;
+    T sqL = L.sq, sqR = R.sq;
+    T iden = recip(sqL + sqR);
     T hh = (T)0.5 * (L.h + R.h);
     T c2h = (T)0.5 * (L.c2 + R.c2);
-    T uh = (sqR * R.un + sqL * L.un) / den;
-    T vh = (sqR * R.ut + sqL * L.ut) / den;
-    T wh = (sqR * R.w + sqL * L.w) / den;
-    T sh = (sqR * R.s + sqL * L.s) / den;
-    T ph = (sqR * R.p + sqL * L.p) / den;
-    T pbh = (sqR * R.pb + sqL * L.pb) / den;
+    T uh = (sqR * R.un + sqL * L.un) * iden;
+    T vh = (sqR * R.ut + sqL * L.ut) * iden;
+    T wh = (sqR * R.w + sqL * L.w) * iden;
+    T sh = (sqR * R.s + sqL * L.s) * iden;
+    T ph = (sqR * R.p + sqL * L.p) * iden;
+    T pbh = (sqR * R.pb + sqL * L.pb) * iden;
 
     T psi = sensor(P, L.b, R.b);
     T db = R.b - L.b;
@@ -280,32 +312,32 @@ HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
     T ce2 = g * hh + ph + c2h;
     if (!(ce2 > (T)0)) return false;
     T ceh = sqrt(ce2);
+    T ice2 = recip(ce2);
+    T sg = sqrt(g);
     T smin, smax;
     if (dryL) {
-        smin = R.un - (T)2 * sqrt(g * R.h);
+        smin = R.un - (T)2 * sg * R.sq;
     } else {
-        T a = g * L.h + L.p + L.c2;
-        if (a < (T)0) return false;
-        smin = tmin(uh - ceh, L.un - sqrt(a));
+        if (!L.hyp) return false;
+        smin = tmin(uh - ceh, L.un - L.ce);
     }
     if (dryR) {
-        smax = L.un + (T)2 * sqrt(g * L.h);
+        smax = L.un + (T)2 * sg * L.sq;
     } else {
-        T a = g * R.h + R.p + R.c2;
-        if (a < (T)0) return false;
-        smax = tmax(uh + ceh, R.un + sqrt(a));
+        if (!R.hyp) return false;
+        smax = tmax(uh + ceh, R.un + R.ce);
     }
+    T ids = recip(smax - smin);
 
     // normal-frame waves, then scattered into the global frame
     T n0[7], n6[7];
     if (L.c2 == (T)0 && R.c2 == (T)0) {
         // SWE edge: HLLE waves carrying the surface-elevation jump
-        T ds = smax - smin;
         T dq0 = deta, dq1 = R.hun - L.hun;
-        T z1h = smin * ((smax * dq0 - df[0]) / ds);
-        T z1m = smin * ((smax * dq1 - df[1]) / ds);
-        T z7h = smax * ((df[0] - smin * dq0) / ds);
-        T z7m = smax * ((df[1] - smin * dq1) / ds);
+        T z1h = smin * ((smax * dq0 - df[0]) * ids);
+        T z1m = smin * ((smax * dq1 - df[1]) * ids);
+        T z7h = smax * ((df[0] - smin * dq0) * ids);
+        T z7m = smax * ((df[1] - smin * dq1) * ids);
         T S = z1h + z7h;
         n0[0] = z1h; n0[1] = z1m; n0[2] = vh * z1h; n0[3] = wh * z1h;
         n0[4] = sh * z1h; n0[5] = ph * z1h; n0[6] = pbh * z1h;
@@ -317,11 +349,11 @@ HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
         W.bt = df[2] - vh * S;
         W.bpb = df[6] - pbh * S;
     } else {
-        T b2 = ((c2h + ph) * df[0] - df[5]) / ce2;
+        T b2 = ((c2h + ph) * df[0] - df[5]) * ice2;
         T S = df[0] - b2;
         T Tm = df[1] - uh * b2;
-        T b1 = (smax * S - Tm) / (smax - smin);
-        T b7 = (Tm - smin * S) / (smax - smin);
+        T b1 = (smax * S - Tm) * ids;
+        T b7 = (Tm - smin * S) * ids;
         n0[0] = b1; n0[1] = b1 * smin; n0[2] = b1 * vh; n0[3] = b1 * wh;
         n0[4] = b1 * sh; n0[5] = b1 * (c2h + ph); n0[6] = b1 * pbh;
         n6[0] = b7; n6[1] = b7 * smax; n6[2] = b7 * vh; n6[3] = b7 * wh;
@@ -338,7 +370,8 @@ HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
     W.smin = smin; W.smax = smax; W.uh = uh;
 
     E.uh = uh; E.vh = vh; E.wh = wh; E.sh = sh; E.pbh = pbh;
-    E.ghh = g * hh; E.c2p = c2h + ph; E.ce2 = ce2; E.smin = smin; E.smax = smax;
+    E.ghh = g * hh; E.c2p = c2h + ph; E.inv_ce2 = ice2; E.smin = smin; E.smax = smax;
+    E.inv_ds = ids;
     return true;
 }
 
@@ -403,9 +436,11 @@ HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T
     family_dots<DIR>(W, W, self);
     for (int f = 0; f < 7; f++) {
         T zz = self[f];
-        if (zz == (T)0) continue;
+        // waves below 1e-100 in norm contribute nothing at double precision;
+        // skipping them also keeps the reciprocal of zz finite
+        if (!(zz > (T)1e-200)) continue;
         T s = wave_speed(W, f);
-        T th = (s > (T)0 ? dl[f] : dr[f]) / zz;
+        T th = (s > (T)0 ? dl[f] : dr[f]) * frcp(zz);
         T ph = limiter_phi(lim, th);
         T sg = s > (T)0 ? (T)1 : (s < (T)0 ? (T)-1 : (T)0);
         T c = (T)0.5 * sg * ((T)1 - dtdx * fabs(s)) * ph;
@@ -442,11 +477,11 @@ HSGN_HD void trans_split(const Eig<T> &E, const T *a, int sgn, T *out)
     const int IN = DIR == 0 ? IHU : IHV;
     const int IT = DIR == 0 ? IHV : IHU;
     T an[7] = {a[IH], a[IN], a[IT], a[IHW], a[IHS], a[IHP], a[IHPB]};
-    T g2 = (E.c2p * an[0] - an[5]) / E.ce2;
+    T g2 = (E.c2p * an[0] - an[5]) * E.inv_ce2;
     T S = an[0] - g2;
     T Tm = an[1] - E.uh * g2;
-    T g1 = (E.smax * S - Tm) / (E.smax - E.smin);
-    T g7 = (Tm - E.smin * S) / (E.smax - E.smin);
+    T g1 = (E.smax * S - Tm) * E.inv_ds;
+    T g7 = (Tm - E.smin * S) * E.inv_ds;
     T gt = an[2] - E.vh * S;
     T gw = an[3] - E.wh * S;
     T gs = an[4] - E.sh * S;

@@ -32,6 +32,8 @@ using namespace hsgn;
 // device side
 
 struct GpuLanes {
+    double *ring_;
+    __device__ double *ring() const { return ring_; }
     __device__ int lane() const { return (int)(threadIdx.x & 63); }
     __device__ double up(double x) const { return __shfl_up(x, 1, 64); }
     __device__ double dn(double x) const { return __shfl_down(x, 1, 64); }
@@ -57,7 +59,8 @@ __global__ __launch_bounds__(64) void march_kernel(MarchArgs<double> A)
 {
     int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;
-    GpuLanes ln;
+    __shared__ double ring[3 * EIG_FIELDS * 64];
+    GpuLanes ln{ring};
     march(ln, A, wid);
 }
 

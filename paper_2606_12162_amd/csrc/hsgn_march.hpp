@@ -69,22 +69,38 @@ struct MarchArgs {
 };
 
 template <class L, class T>
-HSGN_HD void shfl_cell(L &ln, const Cell<T> &c, Cell<T> &o, bool up)
+HSGN_HD void shfl_side_up(L &ln, const Side<T> &c, Side<T> &o)
 {
-    for (int m = 0; m < 7; m++) o.q[m] = up ? ln.up(c.q[m]) : ln.dn(c.q[m]);
-    o.h = up ? ln.up(c.h) : ln.dn(c.h);
-    o.sq = up ? ln.up(c.sq) : ln.dn(c.sq);
-    o.ce = up ? ln.up(c.ce) : ln.dn(c.ce);
-    o.hyp = up ? ln.upi(c.hyp) : ln.dni(c.hyp);
-    o.u = up ? ln.up(c.u) : ln.dn(c.u);
-    o.v = up ? ln.up(c.v) : ln.dn(c.v);
-    o.w = up ? ln.up(c.w) : ln.dn(c.w);
-    o.s = up ? ln.up(c.s) : ln.dn(c.s);
-    o.p = up ? ln.up(c.p) : ln.dn(c.p);
-    o.pb = up ? ln.up(c.pb) : ln.dn(c.pb);
-    o.b = up ? ln.up(c.b) : ln.dn(c.b);
-    o.c2 = up ? ln.up(c.c2) : ln.dn(c.c2);
-    o.wet = up ? ln.upi(c.wet) : ln.dni(c.wet);
+    o.h = ln.up(c.h); o.sq = ln.up(c.sq); o.ce = ln.up(c.ce);
+    o.hun = ln.up(c.hun); o.un = ln.up(c.un); o.ut = ln.up(c.ut);
+    o.w = ln.up(c.w); o.s = ln.up(c.s); o.p = ln.up(c.p); o.pb = ln.up(c.pb);
+    o.hp = ln.up(c.hp); o.b = ln.up(c.b); o.c2 = ln.up(c.c2);
+    o.wet = ln.upi(c.wet); o.hyp = ln.upi(c.hyp);
+}
+
+// x-edge eigenstructure kept for two rows in a per-wavefront LDS ring
+// (3 row slots x EIG_FIELDS x 64 lanes); each lane only touches its own
+// entries, so no synchronisation is needed
+constexpr int EIG_FIELDS = 12;
+
+template <class T>
+HSGN_HD void eig_store(T *ring, int slot, int lane, const Eig<T> &e)
+{
+    T *p = ring + (slot * EIG_FIELDS) * 64 + lane;
+    p[0 * 64] = e.uh; p[1 * 64] = e.vh; p[2 * 64] = e.wh; p[3 * 64] = e.sh;
+    p[4 * 64] = e.pbh; p[5 * 64] = e.ghh; p[6 * 64] = e.c2p; p[7 * 64] = e.inv_ce2;
+    p[8 * 64] = e.smin; p[9 * 64] = e.smax; p[10 * 64] = e.inv_ds;
+    p[11 * 64] = e.wet ? (T)1 : (T)0;
+}
+
+template <class T>
+HSGN_HD void eig_load(const T *ring, int slot, int lane, Eig<T> &e)
+{
+    const T *p = ring + (slot * EIG_FIELDS) * 64 + lane;
+    e.uh = p[0 * 64]; e.vh = p[1 * 64]; e.wh = p[2 * 64]; e.sh = p[3 * 64];
+    e.pbh = p[4 * 64]; e.ghh = p[5 * 64]; e.c2p = p[6 * 64]; e.inv_ce2 = p[7 * 64];
+    e.smin = p[8 * 64]; e.smax = p[9 * 64]; e.inv_ds = p[10 * 64];
+    e.wet = p[11 * 64] != (T)0;
 }
 
 template <class L, class T>
@@ -150,7 +166,8 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
 }
 
 // Lanes policy L provides: lane(), up(x)/dn(x) (value of lane-1 / lane+1)
-// for T and upi/dni for int, and finish(wave, rx, ry, clip) which reduces over
+// for T and upi/dni for int, ring() (the wavefront's LDS ring of 3 *
+// EIG_FIELDS * 64 values), and finish(wave, rx, ry, clip) which reduces over
 // the wavefront and publishes the results.
 template <class L, class T>
 HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
@@ -182,14 +199,14 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
     const bool interior_left = lane >= 1 && (wk.i0 - 3 + lane) >= wk.i0 && (wk.i0 - 3 + lane) <= i_hi;
     const int r0 = wk.r0, th = wk.th;
 
-    Cell<T> cprev;
+    T *ring = ln.ring();
+    Side<T> yside_prev;          // lower cell of the next y-edge (y normal frame)
     int phi_c = 0, brk_c = 0;
     // sliding windows over rows k-2 (index 0), k-1 (1) and k (2), shifted
     // down by one row at the end of each iteration
     T acc[3][7];                 // update accumulators
     int phi_w[3], brk_w[3];      // masks
     T b_w[3];                    // bathymetry
-    Eig<T> ex[3];                // x-edge eigenstructure
     Waves<T> yprev;              // waves of the y-edge below the new one
     T ydl[7];                    // its dot products with the edge below it
     T xtr_prev[7];               // transverse x-fluctuation entering (i, k-1)
@@ -213,15 +230,17 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
         b_w[sk] = c.b;
         for (int m = 0; m < 7; m++) acc[sk][m] = c.q[m];
 
+        const int slot_k = (k - r0 + 6) % 3, slot_k2 = (k - r0 + 4) % 3;
         // ---- x-edge (i-1/2, k) ----
         T xtr[7];
         for (int m = 0; m < 7; m++) xtr[m] = (T)0;
         if (k >= r0 - 1 && k <= r0 + th) {
-            Cell<T> cl;
-            shfl_cell(ln, c, cl, true);
+            Side<T> sr, sl;
+            side_of<0>(c, sr);
+            shfl_side_up(ln, sr, sl);
             Waves<T> xw;
             Eig<T> xe;
-            bool ok = riemann<0>(P, cl, c, xw, xe);
+            bool ok = riemann<0>(P, sl, sr, xw, xe);
             if (!ok && lane >= 1) sc->err = -4;
             Waves<T> xwl;
             shfl_waves_up(ln, xw, xwl);
@@ -240,16 +259,18 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
                 xtr[m] = (xw.kind == KIND_REGULAR ? apc[m] : (T)0)
                        + (kind_r == KIND_REGULAR ? amr[m] : (T)0);
             }
-            ex[sk] = xe;
+            eig_store(ring, slot_k, lane, xe);
             if (k >= r0 && k < r0 + th && (interior || interior_left))
                 rx = tmax(rx, tmax(fabs(xw.smin), tmax(fabs(xw.smax), fabs(xw.uh))));
         }
 
         // ---- y-edge (i, k-1/2) ----
+        Side<T> yside;
+        side_of<1>(c, yside);
         if (k >= r0 - 1) {
             Waves<T> yw;
             Eig<T> ye;
-            bool ok = riemann<1>(P, cprev, c, yw, ye);
+            bool ok = riemann<1>(P, yside_prev, yside, yw, ye);
             if (!ok) sc->err = -4;
             if (k >= r0 && k <= r0 + th && interior)
                 ry = tmax(ry, tmax(fabs(yw.smin), tmax(fabs(yw.smax), fabs(yw.uh))));
@@ -277,10 +298,12 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
                         shfl_vec(ln, ytr, ytl, true);
                         T Ft[7];
                         for (int m = 0; m < 7; m++) Ft[m] = (T)0;
-                        if (trans && ex[sk2].wet) {
+                        Eig<T> exk2;
+                        eig_load(ring, slot_k2, lane, exk2);
+                        if (trans && exk2.wet) {
                             T vp[7], vm[7];
-                            trans_split<0>(ex[sk2], ytl, 1, vp);
-                            trans_split<0>(ex[sk2], ytr, -1, vm);
+                            trans_split<0>(exk2, ytl, 1, vp);
+                            trans_split<0>(exk2, ytr, -1, vm);
                             for (int m = 0; m < 7; m++) Ft[m] = (T)-0.5 * dtdy * (vp[m] + vm[m]);
                         }
                         T Ftr[7];
@@ -345,8 +368,7 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
         phi_w[0] = phi_w[1]; phi_w[1] = phi_w[2];
         brk_w[0] = brk_w[1]; brk_w[1] = brk_w[2];
         b_w[0] = b_w[1]; b_w[1] = b_w[2];
-        ex[0] = ex[1]; ex[1] = ex[2];
-        cprev = c;
+        yside_prev = yside;
     }
     ln.finish(A, wid, pi.scen, rx, ry, clip);
 }

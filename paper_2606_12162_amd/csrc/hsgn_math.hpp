@@ -26,8 +26,10 @@
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
 #define HSGN_HD __host__ __device__ __forceinline__
+#define HSGN_UNROLL _Pragma("unroll")
 #else
 #define HSGN_HD inline
+#define HSGN_UNROLL
 #endif
 
 namespace hsgn {
@@ -163,6 +165,7 @@ HSGN_HD void source_step(T *q, T c2, T tau)
     T MY[4] = {Y1[3], (T)12 * Y1[2] - (T)6 * Y1[3], -c2 * Y1[1],
                (T)-6 * c2 * Y1[0] + (T)3 * c2 * Y1[1]};
     T R[4];
+    HSGN_UNROLL
     for (int m = 0; m < 4; m++) R[m] = Y[m] + w * (th * MY[m]);
     T Y2[4];
     stage_solve(k, c2, R, Y2);
@@ -221,10 +224,13 @@ HSGN_HD T sensor(const StepParams &P, T bL, T bR)
 // ---------------------------------------------------------------------------
 // normal Riemann solve.  DIR = 0: x-edge (normal momentum hu), DIR = 1:
 // y-edge (normal momentum hv).  Returns false if the edge is not hyperbolic.
+// one side of an edge in the edge's normal frame: what the normal solve
+// needs of a cell (a dry cell keeps its thin depth and has zero velocity and
+// auxiliaries)
 template <class T>
 struct Side {
     T h, sq, ce, hun, un, ut, w, s, p, pb, hp, b, c2;
-    int hyp;
+    int wet, hyp;
 };
 
 template <int DIR, class T>
@@ -234,6 +240,7 @@ HSGN_HD void side_of(const Cell<T> &c, Side<T> &sd)
     sd.h = c.h;
     sd.sq = c.sq;
     sd.ce = c.ce;
+    sd.wet = c.wet;
     sd.hyp = c.hyp;
     sd.b = c.b;
     sd.c2 = c.c2;
@@ -248,35 +255,34 @@ HSGN_HD void side_of(const Cell<T> &c, Side<T> &sd)
 }
 
 template <int DIR, class T>
-HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
+HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
                      Waves<T> &W, Eig<T> &E)
 {
     const int IN = DIR == 0 ? IHU : IHV;   // normal momentum component
     const int IT = DIR == 0 ? IHV : IHU;   // tangential momentum component
     const T g = (T)P.g;
+    HSGN_UNROLL
     for (int m = 0; m < 7; m++) { W.z0[m] = (T)0; W.z6[m] = (T)0; }
     W.zm[0] = W.zm[1] = W.zm[2] = (T)0;
     W.bs = W.bw = W.bt = W.bpb = (T)0;
     W.smin = W.smax = W.uh = (T)0;
     W.kind = KIND_REGULAR;
-    E.wet = cL.wet && cR.wet;
+    E.wet = sL.wet && sR.wet;
     E.uh = E.vh = E.wh = E.sh = E.pbh = E.ghh = E.c2p = (T)0;
     E.inv_ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1; E.inv_ds = (T)0.5;
-    if (!cL.wet && !cR.wet) { W.kind = KIND_DRY; return true; }
+    if (!sL.wet && !sR.wet) { W.kind = KIND_DRY; return true; }
 
-    Side<T> L, R;
-    side_of<DIR>(cL, L);
-    side_of<DIR>(cR, R);
+    Side<T> L = sL, R = sR;
     int dryL = 0, dryR = 0;
-    if (cL.wet && !cR.wet) {
-        if (cL.q[IH] + cL.b < cR.b) {
+    if (sL.wet && !sR.wet) {
+        if (sL.h + sL.b < sR.b) {
             W.kind = KIND_WALL_R;
             R = L; R.hun = -L.hun; R.un = -L.un;
         } else {
             dryR = 1;
         }
-    } else if (!cL.wet && cR.wet) {
-        if (cR.q[IH] + cR.b < cL.b) {
+    } else if (!sL.wet && sR.wet) {
+        if (sR.h + sR.b < sL.b) {
             W.kind = KIND_WALL_L;
             L = R; L.hun = -R.hun; L.un = -R.un;
         } else {
@@ -366,6 +372,7 @@ HSGN_HD bool riemann(const StepParams &P, const Cell<T> &cL, const Cell<T> &cR,
     }
     W.z0[IH] = n0[0]; W.z0[IN] = n0[1]; W.z0[IT] = n0[2];
     W.z6[IH] = n6[0]; W.z6[IN] = n6[1]; W.z6[IT] = n6[2];
+    HSGN_UNROLL
     for (int m = 3; m < 7; m++) { W.z0[m] = n0[m]; W.z6[m] = n6[m]; }
     W.smin = smin; W.smax = smax; W.uh = uh;
 
@@ -382,6 +389,7 @@ HSGN_HD void wave_vec(const Waves<T> &W, int f, T *z)
 {
     const int IN = DIR == 0 ? IHU : IHV;
     const int IT = DIR == 0 ? IHV : IHU;
+    HSGN_UNROLL
     for (int m = 0; m < 7; m++) z[m] = (T)0;
     switch (f) {
     case 0: for (int m = 0; m < 7; m++) z[m] = W.z0[m]; break;
@@ -404,11 +412,13 @@ HSGN_HD T wave_speed(const Waves<T> &W, int f)
 template <int DIR, class T>
 HSGN_HD void family_dots(const Waves<T> &A, const Waves<T> &B, T *d)
 {
+    HSGN_UNROLL
     for (int f = 0; f < 7; f++) {
         T za[7], zb[7];
         wave_vec<DIR>(A, f, za);
         wave_vec<DIR>(B, f, zb);
         T s = (T)0;
+        HSGN_UNROLL
         for (int m = 0; m < 7; m++) s += za[m] * zb[m];
         d[f] = s;
     }
@@ -430,43 +440,53 @@ HSGN_HD T limiter_phi(int lim, T th)
 template <int DIR, class T>
 HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T *dr, T *F)
 {
+    HSGN_UNROLL
     for (int m = 0; m < 7; m++) F[m] = (T)0;
     if (lim == 0 || W.kind != KIND_REGULAR) return;
     T self[7];
     family_dots<DIR>(W, W, self);
+    HSGN_UNROLL
     for (int f = 0; f < 7; f++) {
         T zz = self[f];
+        T s = wave_speed(W, f);
         // waves below 1e-100 in norm contribute nothing at double precision;
         // skipping them also keeps the reciprocal of zz finite
-        if (!(zz > (T)1e-200)) continue;
-        T s = wave_speed(W, f);
-        T th = (s > (T)0 ? dl[f] : dr[f]) * frcp(zz);
-        T ph = limiter_phi(lim, th);
+        bool live = zz > (T)1e-200;
+        T th = live ? (s > (T)0 ? dl[f] : dr[f]) * frcp(zz) : (T)0;
+        T ph = live ? limiter_phi(lim, th) : (T)0;
         T sg = s > (T)0 ? (T)1 : (s < (T)0 ? (T)-1 : (T)0);
         T c = (T)0.5 * sg * ((T)1 - dtdx * fabs(s)) * ph;
         T z[7];
         wave_vec<DIR>(W, f, z);
+        HSGN_UNROLL
         for (int m = 0; m < 7; m++) F[m] += c * z[m];
     }
 }
 
-// left- and right-going fluctuations
+// left- and right-going fluctuations; a wave of speed exactly zero is split
+// half and half
 template <int DIR, class T>
 HSGN_HD void fluctuations(const Waves<T> &W, T *am, T *ap)
 {
+    HSGN_UNROLL
     for (int m = 0; m < 7; m++) { am[m] = (T)0; ap[m] = (T)0; }
+    HSGN_UNROLL
     for (int f = 0; f < 7; f++) {
         T s = wave_speed(W, f);
+        T wm = s < (T)0 ? (T)1 : (s > (T)0 ? (T)0 : (T)0.5);
+        T wp = s > (T)0 ? (T)1 : (s < (T)0 ? (T)0 : (T)0.5);
         T z[7];
         wave_vec<DIR>(W, f, z);
+        HSGN_UNROLL
         for (int m = 0; m < 7; m++) {
-            if (s < (T)0) am[m] += z[m];
-            else if (s > (T)0) ap[m] += z[m];
-            else { am[m] += (T)0.5 * z[m]; ap[m] += (T)0.5 * z[m]; }
+            am[m] += wm * z[m];
+            ap[m] += wp * z[m];
         }
     }
-    if (W.kind == KIND_WALL_R) for (int m = 0; m < 7; m++) ap[m] = (T)0;
-    if (W.kind == KIND_WALL_L) for (int m = 0; m < 7; m++) am[m] = (T)0;
+    const T km = W.kind == KIND_WALL_L ? (T)0 : (T)1;
+    const T kp = W.kind == KIND_WALL_R ? (T)0 : (T)1;
+    HSGN_UNROLL
+    for (int m = 0; m < 7; m++) { am[m] *= km; ap[m] *= kp; }
 }
 
 // transverse split of a global-frame vector a by the eigenstructure E of an
@@ -493,8 +513,10 @@ HSGN_HD void trans_split(const Eig<T> &E, const T *a, int sgn, T *out)
     T r7[7] = {(T)1, E.smax, E.vh, E.wh, E.sh, E.c2p, E.pbh};
     T mid[7] = {g2, g2 * E.uh, gt, gw, gs, g2 * (-E.ghh), gpb};
     T on[7];
+    HSGN_UNROLL
     for (int m = 0; m < 7; m++) on[m] = s1 * g1 * r1[m] + sm * mid[m] + s7 * g7 * r7[m];
     out[IH] = on[0]; out[IN] = on[1]; out[IT] = on[2];
+    HSGN_UNROLL
     for (int m = 3; m < 7; m++) out[m] = on[m];
 }
 

@@ -58,7 +58,9 @@ extern "C" {
 
 typedef struct hsgn_params {
     int model;          /* 0 = HSGN (7 variables) */
-    int precision;      /* 0 = FP64 */
+    int precision;      /* 0 = FP64; 1 = mixed: FP32 storage of eta' = h + b -
+                           eta0 and FP32 arithmetic, FP64 for every edge with
+                           an SWE or dry side, for cell fix-ups and mass sums */
     double g;           /* gravity */
     double alpha;       /* relaxation parameter alpha = c / sqrt(g H), Sec. 3 */
     double eta0;        /* sea level at rest */

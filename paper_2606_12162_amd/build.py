@@ -20,6 +20,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # fused multiply-add where the compiler finds a*b+c
     "-ffp-contract=fast",
+    # FP32 division and square root to ~1 ulp (the FP64 ones stay IEEE)
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wno-unused-result",
 ]
 

@@ -31,15 +31,20 @@ using namespace hsgn;
 // ---------------------------------------------------------------------------
 // device side
 
+template <class T>
 struct GpuLanes {
-    double *ring_;
-    __device__ double *ring() const { return ring_; }
+    T *ring_;
+    __device__ T *ring() const { return ring_; }
     __device__ int lane() const { return (int)(threadIdx.x & 63); }
     __device__ double up(double x) const { return __shfl_up(x, 1, 64); }
     __device__ double dn(double x) const { return __shfl_down(x, 1, 64); }
+    __device__ float up(float x) const { return __shfl_up(x, 1, 64); }
+    __device__ float dn(float x) const { return __shfl_down(x, 1, 64); }
     __device__ int upi(int x) const { return __shfl_up(x, 1, 64); }
     __device__ int dni(int x) const { return __shfl_down(x, 1, 64); }
-    __device__ void finish(const MarchArgs<double> &A, int wid, int scen, double rx, double ry,
+    __device__ bool any(int p) const { return __any(p); }
+    template <class S>
+    __device__ void finish(const MarchArgs<S> &A, int wid, int scen, double rx, double ry,
                            double clip) const
     {
         for (int o = 32; o > 0; o >>= 1) {
@@ -55,13 +60,14 @@ struct GpuLanes {
     }
 };
 
-__global__ __launch_bounds__(64) void march_kernel(MarchArgs<double> A)
+template <class S, class T, bool MIXED>
+__global__ __launch_bounds__(64) void march_kernel(MarchArgs<S> A)
 {
     int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;
-    __shared__ double ring[3 * EIG_FIELDS * 64];
-    GpuLanes ln{ring};
-    march(ln, A, wid);
+    __shared__ T ring[3 * EIG_FIELDS * 64];
+    GpuLanes<T> ln{ring};
+    march<GpuLanes<T>, S, T, MIXED>(ln, A, wid);
 }
 
 struct ScenStatic {
@@ -128,25 +134,28 @@ struct GaugeDev {
     long long cap;
 };
 
-__global__ void gauge_kernel(const GaugeDev *G, int n, const ScenState *S, const double *q0,
-                             const double *q1, const double *bath, double eta0, double dry_tol,
+template <class S, bool MIXED>
+__global__ void gauge_kernel(const GaugeDev *G, int n, const ScenState *Sc, const S *q0,
+                             const S *q1, const S *bath, double eta0, double dry_tol,
                              double *rec)
 {
     int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (k >= n) return;
     const GaugeDev g = G[k];
-    const ScenState &st = S[g.scen];
+    const ScenState &st = Sc[g.scen];
     if (!st.accepted) return;
     long long r = st.records - 1;
     if (r < 0 || r >= g.cap) return;
-    const double *q = st.cur ? q1 : q0;
+    const S *q = st.cur ? q1 : q0;
     long long cells[4] = {g.c00, g.c01, g.c10, g.c11};
     double e[4];
     for (int a = 0; a < 4; a++) {
         long long ci = cells[a];
-        double h = q[g.qoff + ci];
-        double b = bath[g.plane + ci];
-        e[a] = h > dry_tol ? h + b - eta0 : 0.0;
+        double v = (double)q[g.qoff + ci];
+        double b = (double)bath[g.plane + ci];
+        double h = MIXED ? v + eta0 - b : v;
+        double ep = MIXED ? v : h + b - eta0;
+        e[a] = h > dry_tol ? ep : 0.0;
     }
     double wx = g.wx, wy = g.wy;
     double eta = (1.0 - wx) * (1.0 - wy) * e[0] + wx * (1.0 - wy) * e[1]
@@ -156,7 +165,8 @@ __global__ void gauge_kernel(const GaugeDev *G, int n, const ScenState *S, const
     rec[base + 1 + g.slot] = eta;
 }
 
-__global__ void mask_kernel(PatchInfo pi, const double *bath, uint8_t *m0, uint8_t *m1,
+template <class S>
+__global__ void mask_kernel(PatchInfo pi, const S *bath, uint8_t *m0, uint8_t *m1,
                             double eta0, double h_star, int n)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -169,7 +179,7 @@ __global__ void mask_kernel(PatchInfo pi, const double *bath, uint8_t *m0, uint8
             int fx, fy;
             int mx = map_index(x + di, pi.nx, pi.bc[0], pi.bc[1], &fx);
             int my = map_index(y + dj, pi.ny, pi.bc[2], pi.bc[3], &fy);
-            double H = eta0 - bath[pi.coff + (long long)my * pi.pitch + mx];
+            double H = eta0 - (double)bath[pi.coff + (long long)my * pi.pitch + mx];
             H = H > 0.0 ? H : 0.0;
             hmin = H < hmin ? H : hmin;
         }
@@ -180,7 +190,8 @@ __global__ void mask_kernel(PatchInfo pi, const double *bath, uint8_t *m0, uint8
     m1[idx] = phi;
 }
 
-__global__ void initdt_kernel(PatchInfo pi, StepParams P, const double *q, const double *bath,
+template <class S, bool MIXED>
+__global__ void initdt_kernel(PatchInfo pi, StepParams P, const S *q, const S *bath,
                               const uint8_t *mask, unsigned long long *slot, int *err)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -190,13 +201,14 @@ __global__ void initdt_kernel(PatchInfo pi, StepParams P, const double *q, const
         int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
         long long idx = (long long)y * pi.pitch + x;
         long long plane = (long long)pi.ny * pi.pitch;
-        double h = q[pi.qoff + idx];
+        double b = (double)bath[pi.coff + idx];
+        double h = (double)q[pi.qoff + idx];
+        if (MIXED) h = h + P.eta0 - b;
         if (h > P.dry_tol) {
-            double u = q[pi.qoff + plane + idx] / h, v = q[pi.qoff + 2 * plane + idx] / h;
-            double p = q[pi.qoff + 5 * plane + idx] / h;
+            double u = (double)q[pi.qoff + plane + idx] / h, v = (double)q[pi.qoff + 2 * plane + idx] / h;
+            double p = (double)q[pi.qoff + 5 * plane + idx] / h;
             uint8_t mk = mask[pi.coff + idx];
             int swe = !(mk & 1) || ((mk >> 1) & 1);
-            double b = bath[pi.coff + idx];
             double H = P.eta0 - b;
             H = H > 0.0 ? H : 0.0;
             double c2 = swe ? 0.0 : P.a2g * H;
@@ -222,14 +234,22 @@ __global__ void initdt_finish(ScenState *S, const ScenStatic *SS, const unsigned
 
 // FP64 sum of h over one patch: fixed decomposition (1024 threads, strided),
 // then a fixed-order tree in shared memory
-__global__ __launch_bounds__(1024) void mass_kernel(PatchInfo pi, const double *q, double *out)
+template <class S, bool MIXED>
+__global__ __launch_bounds__(1024) void mass_kernel(PatchInfo pi, const S *q, const S *bath,
+                                                    double eta0, double *out)
 {
     __shared__ double part[1024];
     long long ncell = (long long)pi.nx * pi.ny;
     double s = 0.0;
     for (long long i = threadIdx.x; i < ncell; i += 1024) {
         int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
-        s += q[pi.qoff + (long long)y * pi.pitch + x];
+        long long idx = (long long)y * pi.pitch + x;
+        double v = (double)q[pi.qoff + idx];
+        if (MIXED) {
+            v = v + eta0 - (double)bath[pi.coff + idx];
+            v = v > 0.0 ? v : 0.0;
+        }
+        s += v;
     }
     part[threadIdx.x] = s;
     __syncthreads();
@@ -252,6 +272,43 @@ __global__ void count_kernel(PatchInfo pi, const uint8_t *mask, unsigned long lo
     if ((mk >> 1) & 1) atomicAdd(&cnt[1], 1ull);
 }
 
+// conversion between the ABI layout (FP64, plane 0 = h) and FP32 storage
+// (plane 0 = eta' = h + b - eta0)
+__global__ void to_storage_kernel(PatchInfo pi, const double *in, float *q, const float *bath,
+                                  double eta0)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long ncell = (long long)pi.nx * pi.ny;
+    if (i >= ncell) return;
+    int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
+    long long idx = (long long)y * pi.pitch + x;
+    long long plane = (long long)pi.ny * pi.pitch;
+    double b = (double)bath[pi.coff + idx];
+    q[pi.qoff + idx] = (float)(in[i] + b - eta0);
+    for (int m = 1; m < 7; m++) q[pi.qoff + m * plane + idx] = (float)in[m * ncell + i];
+}
+
+__global__ void from_storage_kernel(PatchInfo pi, const float *q, const float *bath, double eta0,
+                                    double *out)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long ncell = (long long)pi.nx * pi.ny;
+    if (i >= ncell) return;
+    int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
+    long long idx = (long long)y * pi.pitch + x;
+    long long plane = (long long)pi.ny * pi.pitch;
+    double b = (double)bath[pi.coff + idx];
+    double h = (double)q[pi.qoff + idx] + eta0 - b;
+    out[i] = h > 0.0 ? h : 0.0;
+    for (int m = 1; m < 7; m++) out[m * ncell + i] = (double)q[pi.qoff + m * plane + idx];
+}
+
+__global__ void to_float_kernel(const double *in, float *out, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -272,8 +329,12 @@ struct hsgn_ctx {
     std::vector<ScenHost> scen;
     std::vector<WorkItem> work;
     std::vector<ScenStatic> sstat;
-    // device
+    bool mixed = false;         // FP32 eta' storage with FP64 near-shore edges
+    // device (FP64 storage: q0, q1, bath; mixed storage: f0, f1, fbath)
     double *q0 = nullptr, *q1 = nullptr, *bath = nullptr, *clip = nullptr, *rec = nullptr;
+    float *f0 = nullptr, *f1 = nullptr, *fbath = nullptr;
+    double *stage = nullptr;    // FP64 staging for conversions at the ABI
+    long long stage_len = 0;
     uint8_t *m0 = nullptr, *m1 = nullptr;
     PatchInfo *d_patches = nullptr;
     WorkItem *d_work = nullptr;
@@ -319,13 +380,30 @@ static void free_device(hsgn_ctx *c)
     free_events(c);
     void *ptrs[] = {c->q0, c->q1, c->bath, c->clip, c->rec, c->m0, c->m1, c->d_patches,
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
-                    c->d_mass};
+                    c->d_mass, c->f0, c->f1, c->fbath, c->stage};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    c->q0 = c->q1 = c->bath = c->clip = c->rec = c->d_mass = nullptr;
+    c->q0 = c->q1 = c->bath = c->clip = c->rec = c->d_mass = c->stage = nullptr;
+    c->f0 = c->f1 = c->fbath = nullptr;
     c->m0 = c->m1 = nullptr;
     c->d_patches = nullptr; c->d_work = nullptr; c->d_scen = nullptr; c->d_sstat = nullptr;
     c->d_gauges = nullptr; c->d_slots = nullptr; c->d_err = nullptr;
+}
+
+template <class S>
+static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath)
+{
+    MarchArgs<S> A;
+    A.P = c->P;
+    A.patches = c->d_patches;
+    A.work = c->d_work;
+    A.q0 = q0; A.q1 = q1;
+    A.bath = bath;
+    A.m0 = c->m0; A.m1 = c->m1;
+    A.scen = c->d_scen;
+    A.clip_slots = c->clip;
+    A.nwork = (int)c->work.size();
+    return A;
 }
 
 extern "C" {
@@ -352,7 +430,7 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
 {
     if (!p || !out) return HSGN_EINVAL;
     *out = nullptr;
-    if (p->model != 0 || p->precision != 0) return HSGN_ENOTSUP;
+    if (p->model != 0 || (p->precision != 0 && p->precision != 1)) return HSGN_ENOTSUP;
     if (!(p->g > 0) || p->alpha < 0 || !(p->dry_tol >= 0) || !(p->cfl > 0) ||
         !(p->cfl_max >= p->cfl) || p->nbr_n < 0 || p->nbr_n > 2 || p->limiter < 0 ||
         p->limiter > 3 || (p->transverse != 0 && p->transverse != 2) ||
@@ -361,6 +439,7 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     hsgn_ctx *c = new (std::nothrow) hsgn_ctx();
     if (!c) return HSGN_ENOMEM;
     c->prm = *p;
+    c->mixed = p->precision == 1;
     c->stream = (hipStream_t)hip_stream;
     StepParams &P = c->P;
     P.g = p->g;
@@ -452,9 +531,25 @@ int hsgn_finalize(hsgn_ctx *c)
         ss.w1 = (int)c->work.size();
     }
     size_t nscen = c->scen.size();
-    HIPCHK(c, hipMalloc(&c->q0, sizeof(double) * c->qtotal));
-    HIPCHK(c, hipMalloc(&c->q1, sizeof(double) * c->qtotal));
-    HIPCHK(c, hipMalloc(&c->bath, sizeof(double) * c->ctotal));
+    if (c->mixed) {
+        HIPCHK(c, hipMalloc(&c->f0, sizeof(float) * c->qtotal));
+        HIPCHK(c, hipMalloc(&c->f1, sizeof(float) * c->qtotal));
+        HIPCHK(c, hipMalloc(&c->fbath, sizeof(float) * c->ctotal));
+        HIPCHK(c, hipMemsetAsync(c->f0, 0, sizeof(float) * c->qtotal, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->f1, 0, sizeof(float) * c->qtotal, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->fbath, 0, sizeof(float) * c->ctotal, c->stream));
+        long long big = 0;
+        for (const PatchInfo &p : c->patches) big = std::max<long long>(big, 7LL * p.nx * p.ny);
+        c->stage_len = big;
+        HIPCHK(c, hipMalloc(&c->stage, sizeof(double) * big));
+    } else {
+        HIPCHK(c, hipMalloc(&c->q0, sizeof(double) * c->qtotal));
+        HIPCHK(c, hipMalloc(&c->q1, sizeof(double) * c->qtotal));
+        HIPCHK(c, hipMalloc(&c->bath, sizeof(double) * c->ctotal));
+        HIPCHK(c, hipMemsetAsync(c->q0, 0, sizeof(double) * c->qtotal, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->q1, 0, sizeof(double) * c->qtotal, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->bath, 0, sizeof(double) * c->ctotal, c->stream));
+    }
     HIPCHK(c, hipMalloc(&c->m0, c->ctotal));
     HIPCHK(c, hipMalloc(&c->m1, c->ctotal));
     HIPCHK(c, hipMalloc(&c->clip, sizeof(double) * c->work.size()));
@@ -465,9 +560,6 @@ int hsgn_finalize(hsgn_ctx *c)
     HIPCHK(c, hipMalloc(&c->d_slots, sizeof(unsigned long long) * nscen));
     HIPCHK(c, hipMalloc(&c->d_err, sizeof(int)));
     HIPCHK(c, hipMalloc(&c->d_mass, sizeof(double) * 2));
-    HIPCHK(c, hipMemsetAsync(c->q0, 0, sizeof(double) * c->qtotal, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->q1, 0, sizeof(double) * c->qtotal, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->bath, 0, sizeof(double) * c->ctotal, c->stream));
     HIPCHK(c, hipMemsetAsync(c->m0, 0, c->ctotal, c->stream));
     HIPCHK(c, hipMemsetAsync(c->m1, 0, c->ctotal, c->stream));
     HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * c->work.size(), c->stream));
@@ -526,11 +618,20 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
     if (rc) return rc;
     if (!b) return fail(c, HSGN_EINVAL, "null bathymetry");
     const PatchInfo &p = c->patches[patch];
-    HIPCHK(c, hipMemcpyAsync(c->bath + p.coff, b, sizeof(double) * p.nx * p.ny, kind_in(on_device),
-                             c->stream));
     long long n = (long long)p.nx * p.ny;
-    mask_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
-        p, c->bath, c->m0, c->m1, c->prm.eta0, c->prm.h_star, c->prm.nbr_n);
+    unsigned nb = (unsigned)((n + 255) / 256);
+    if (c->mixed) {
+        // stored in FP32; phi_T is computed from the stored values
+        HIPCHK(c, hipMemcpyAsync(c->stage, b, sizeof(double) * n, kind_in(on_device), c->stream));
+        to_float_kernel<<<nb, 256, 0, c->stream>>>(c->stage, c->fbath + p.coff, n);
+        mask_kernel<float><<<nb, 256, 0, c->stream>>>(p, c->fbath, c->m0, c->m1, c->prm.eta0,
+                                                      c->prm.h_star, c->prm.nbr_n);
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->bath + p.coff, b, sizeof(double) * n, kind_in(on_device),
+                                 c->stream));
+        mask_kernel<double><<<nb, 256, 0, c->stream>>>(p, c->bath, c->m0, c->m1, c->prm.eta0,
+                                                       c->prm.h_star, c->prm.nbr_n);
+    }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
@@ -544,8 +645,18 @@ int hsgn_set_state(hsgn_ctx *c, int patch, const double *q, int on_device)
     std::vector<ScenState> st;
     if ((rc = pull_scen(c, st))) return rc;
     const PatchInfo &p = c->patches[patch];
-    double *dst = (st[p.scen].cur ? c->q1 : c->q0) + p.qoff;
-    HIPCHK(c, hipMemcpyAsync(dst, q, sizeof(double) * 7 * p.nx * p.ny, kind_in(on_device), c->stream));
+    if (c->mixed) {
+        long long n = (long long)p.nx * p.ny;
+        HIPCHK(c, hipMemcpyAsync(c->stage, q, sizeof(double) * 7 * n, kind_in(on_device), c->stream));
+        float *dst = st[p.scen].cur ? c->f1 : c->f0;
+        to_storage_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+            p, c->stage, dst, c->fbath, c->prm.eta0);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        double *dst = (st[p.scen].cur ? c->q1 : c->q0) + p.qoff;
+        HIPCHK(c, hipMemcpyAsync(dst, q, sizeof(double) * 7 * p.nx * p.ny, kind_in(on_device),
+                                 c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
 }
@@ -558,8 +669,18 @@ int hsgn_get_state(hsgn_ctx *c, int patch, double *q, int on_device)
     std::vector<ScenState> st;
     if ((rc = pull_scen(c, st))) return rc;
     const PatchInfo &p = c->patches[patch];
-    const double *src = (st[p.scen].cur ? c->q1 : c->q0) + p.qoff;
-    HIPCHK(c, hipMemcpyAsync(q, src, sizeof(double) * 7 * p.nx * p.ny, kind_out(on_device), c->stream));
+    if (c->mixed) {
+        long long n = (long long)p.nx * p.ny;
+        const float *src = st[p.scen].cur ? c->f1 : c->f0;
+        from_storage_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+            p, src, c->fbath, c->prm.eta0, c->stage);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(q, c->stage, sizeof(double) * 7 * n, kind_out(on_device), c->stream));
+    } else {
+        const double *src = (st[p.scen].cur ? c->q1 : c->q0) + p.qoff;
+        HIPCHK(c, hipMemcpyAsync(q, src, sizeof(double) * 7 * p.nx * p.ny, kind_out(on_device),
+                                 c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
 }
@@ -727,16 +848,6 @@ static int collect_timing(hsgn_ctx *c);
 
 static int launch_attempt(hsgn_ctx *c)
 {
-    MarchArgs<double> A;
-    A.P = c->P;
-    A.patches = c->d_patches;
-    A.work = c->d_work;
-    A.q0 = c->q0; A.q1 = c->q1;
-    A.bath = c->bath;
-    A.m0 = c->m0; A.m1 = c->m1;
-    A.scen = c->d_scen;
-    A.clip_slots = c->clip;
-    A.nwork = (int)c->work.size();
     if (c->timing) {
         if (c->ev_used + 2 > c->ev.size()) {
             for (int k = 0; k < 256; k++) {
@@ -747,17 +858,30 @@ static int launch_attempt(hsgn_ctx *c)
         }
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
     }
-    march_kernel<<<(unsigned)c->work.size(), 64, 0, c->stream>>>(A);
+    unsigned nw = (unsigned)c->work.size();
+    if (c->mixed)
+        march_kernel<float, float, true><<<nw, 64, 0, c->stream>>>(
+            march_args<float>(c, c->f0, c->f1, c->fbath));
+    else
+        march_kernel<double, double, false><<<nw, 64, 0, c->stream>>>(
+            march_args<double>(c, c->q0, c->q1, c->bath));
     if (c->timing) {
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     }
     int ns = (int)c->scen.size();
     control_kernel<<<(unsigned)ns, 256, 0, c->stream>>>(c->d_scen, c->d_sstat, c->clip, ns);
-    if (c->ngauge_total > 0)
-        gauge_kernel<<<(unsigned)((c->ngauge_total + 63) / 64), 64, 0, c->stream>>>(
-            c->d_gauges, c->ngauge_total, c->d_scen, c->q0, c->q1, c->bath, c->prm.eta0,
-            c->prm.dry_tol, c->rec);
+    if (c->ngauge_total > 0) {
+        unsigned gb = (unsigned)((c->ngauge_total + 63) / 64);
+        if (c->mixed)
+            gauge_kernel<float, true><<<gb, 64, 0, c->stream>>>(
+                c->d_gauges, c->ngauge_total, c->d_scen, c->f0, c->f1, c->fbath, c->prm.eta0,
+                c->prm.dry_tol, c->rec);
+        else
+            gauge_kernel<double, false><<<gb, 64, 0, c->stream>>>(
+                c->d_gauges, c->ngauge_total, c->d_scen, c->q0, c->q1, c->bath, c->prm.eta0,
+                c->prm.dry_tol, c->rec);
+    }
     HIPCHK(c, hipGetLastError());
     return HSGN_OK;
 }
@@ -792,10 +916,16 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
             const PatchInfo &p = c->patches[pid];
             if (st[p.scen].dt > 0.0) continue;
             long long n = (long long)p.nx * p.ny;
-            const double *q = st[p.scen].cur ? c->q1 : c->q0;
             const uint8_t *m = st[p.scen].cur ? c->m1 : c->m0;
-            initdt_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
-                p, c->P, q, c->bath, m, c->d_slots + p.scen, c->d_err);
+            unsigned nb = (unsigned)((n + 255) / 256);
+            if (c->mixed)
+                initdt_kernel<float, true><<<nb, 256, 0, c->stream>>>(
+                    p, c->P, st[p.scen].cur ? c->f1 : c->f0, c->fbath, m, c->d_slots + p.scen,
+                    c->d_err);
+            else
+                initdt_kernel<double, false><<<nb, 256, 0, c->stream>>>(
+                    p, c->P, st[p.scen].cur ? c->q1 : c->q0, c->bath, m, c->d_slots + p.scen,
+                    c->d_err);
         }
         initdt_finish<<<(unsigned)((ns + 63) / 64), 64, 0, c->stream>>>(c->d_scen, c->d_sstat,
                                                                         c->d_slots, ns);
@@ -847,9 +977,13 @@ int hsgn_diagnostics(hsgn_ctx *c, int scenario, hsgn_diag *d)
     HIPCHK(c, hipMalloc(&dcnt, sizeof(unsigned long long) * 2));
     for (int pid : c->scen[scenario].patches) {
         const PatchInfo &p = c->patches[pid];
-        const double *q = s.cur ? c->q1 : c->q0;
         const uint8_t *m = s.cur ? c->m1 : c->m0;
-        mass_kernel<<<1, 1024, 0, c->stream>>>(p, q, c->d_mass);
+        if (c->mixed)
+            mass_kernel<float, true><<<1, 1024, 0, c->stream>>>(p, s.cur ? c->f1 : c->f0,
+                                                                 c->fbath, c->prm.eta0, c->d_mass);
+        else
+            mass_kernel<double, false><<<1, 1024, 0, c->stream>>>(p, s.cur ? c->q1 : c->q0,
+                                                                  c->bath, c->prm.eta0, c->d_mass);
         double pm = 0.0;
         HIPCHK(c, hipMemcpyAsync(&pm, c->d_mass, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemsetAsync(dcnt, 0, sizeof(unsigned long long) * 2, c->stream));

@@ -55,13 +55,16 @@ struct ScenState {
     double clip_total;
 };
 
-template <class T>
+// S: storage type of the state and bathymetry planes.  With FP64 storage
+// plane 0 holds h; with FP32 storage it holds the surface deviation
+// eta' = h + b - eta0.
+template <class S>
 struct MarchArgs {
     StepParams P;
     const PatchInfo *patches;
     const WorkItem *work;
-    T *q0, *q1;              // state buffers (ping-pong)
-    const T *bath;
+    S *q0, *q1;              // state buffers (ping-pong)
+    const S *bath;
     uint8_t *m0, *m1;        // mask buffers (ping-pong): bit0 phi_T, bit1 breaking
     ScenState *scen;
     double *clip_slots;      // one per work item
@@ -119,7 +122,8 @@ HSGN_HD void shfl_vec(L &ln, const T *a, T *o, bool up)
     for (int m = 0; m < 7; m++) o[m] = up ? ln.up(a[m]) : ln.dn(a[m]);
 }
 
-// raw data of one cell as stored (state, bathymetry, mask byte)
+// raw data of one cell as stored (state plane 0 as stored, bathymetry,
+// mask byte), converted to the compute type
 template <class T>
 struct RawCell {
     T q[7];
@@ -128,30 +132,40 @@ struct RawCell {
 };
 
 // load cell (col, row) of a patch through the boundary map
-template <class T>
-HSGN_HD void load_raw(const PatchInfo &pi, const T *q, const T *bath, const uint8_t *mask,
+template <class S, class T>
+HSGN_HD void load_raw(const PatchInfo &pi, const S *q, const S *bath, const uint8_t *mask,
                       int mc, int fx, int row, RawCell<T> &r)
 {
     int fy;
     int mr = map_index(row, pi.ny, pi.bc[2], pi.bc[3], &fy);
     long long idx = (long long)mr * pi.pitch + mc;
     long long plane = (long long)pi.ny * pi.pitch;
-    const T *qp = q + pi.qoff + idx;
-    for (int m = 0; m < 7; m++) r.q[m] = qp[m * plane];
+    const S *qp = q + pi.qoff + idx;
+    HSGN_UNROLL
+    for (int m = 0; m < 7; m++) r.q[m] = (T)qp[m * plane];
     if (fx) r.q[IHU] = -r.q[IHU];
     if (fy) r.q[IHV] = -r.q[IHV];
-    r.b = bath[pi.coff + idx];
+    r.b = (T)bath[pi.coff + idx];
     r.mk = mask[pi.coff + idx];
+}
+
+// depth from the stored plane-0 value
+template <class T, bool MIXED>
+HSGN_HD T depth_of(const StepParams &P, T q0, T b)
+{
+    return MIXED ? q0 + (T)P.eta0 - b : q0;
 }
 
 // apply the first source half step (Strang) or clear a dry/SWE cell's
 // auxiliaries, then derive the primitive variables
-template <class T>
+template <class T, bool MIXED>
 HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, Cell<T> &c,
                           int &phi, int &brk)
 {
+    HSGN_UNROLL
     for (int m = 0; m < 7; m++) c.q[m] = r.q[m];
     c.b = r.b;
+    c.q[IH] = depth_of<T, MIXED>(P, r.q[IH], r.b);
     phi = r.mk & 1;
     brk = (r.mk >> 1) & 1;
     int swe = !phi || brk;
@@ -165,12 +179,40 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
     derive(P, c);
 }
 
+// normal solve of an edge.  In mixed precision an edge with an SWE or dry
+// side (c^2 = 0 on a side) is solved again in FP64 from the promoted sides
+// and its results replace the FP32 ones.
+template <int DIR, bool MIXED, class L, class T>
+HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Side<T> &sr,
+                        Waves<T> &W, Eig<T> &E)
+{
+    bool ok = riemann<DIR>(P, sl, sr, W, E);
+    if (MIXED) {
+        int need = !(sl.c2 > (T)0) || !(sr.c2 > (T)0);
+        if (ln.any(need)) {
+            Side<double> dl, dr;
+            convert(sl, dl);
+            convert(sr, dr);
+            Waves<double> Wd;
+            Eig<double> Ed;
+            bool okd = riemann<DIR>(P, dl, dr, Wd, Ed);
+            if (need) {
+                convert(Wd, W);
+                convert(Ed, E);
+                ok = okd;
+            }
+        }
+    }
+    return ok;
+}
+
 // Lanes policy L provides: lane(), up(x)/dn(x) (value of lane-1 / lane+1)
-// for T and upi/dni for int, ring() (the wavefront's LDS ring of 3 *
-// EIG_FIELDS * 64 values), and finish(wave, rx, ry, clip) which reduces over
-// the wavefront and publishes the results.
-template <class L, class T>
-HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
+// for float, double and int (upi/dni), any(pred) over the wavefront, ring()
+// (the wavefront's LDS ring of 3 * EIG_FIELDS * 64 compute values), and
+// finish(args, wave, scenario, rx, ry, clip) which reduces over the
+// wavefront and publishes the results.
+template <class L, class S, class T, bool MIXED>
+HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 {
     const WorkItem wk = A.work[wid];
     const PatchInfo pi = A.patches[wk.patch];
@@ -178,12 +220,13 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
     const StepParams &P = A.P;
     if (!sc->active) return;                    // uniform over the wavefront
     const int cur = sc->cur;
-    const T *qin = cur ? A.q1 : A.q0;
-    T *qout = cur ? A.q0 : A.q1;
+    const S *qin = cur ? A.q1 : A.q0;
+    S *qout = cur ? A.q0 : A.q1;
     const uint8_t *min_ = cur ? A.m1 : A.m0;
     uint8_t *mout = cur ? A.m0 : A.m1;
-    const T dt = (T)sc->dt;
-    const T dtdx = dt / (T)pi.dx, dtdy = dt / (T)pi.dy;
+    const double dtd = sc->dt;
+    const T dt = (T)dtd;
+    const T dtdx = (T)(dtd / pi.dx), dtdy = (T)(dtd / pi.dy);
     const T tau_pre = (T)0.5 * dt;
     const T tau_post = P.splitting ? (T)0.5 * dt : dt;
     const int lim = P.limiter;
@@ -203,15 +246,18 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
     Side<T> yside_prev;          // lower cell of the next y-edge (y normal frame)
     int phi_c = 0, brk_c = 0;
     // sliding windows over rows k-2 (index 0), k-1 (1) and k (2), shifted
-    // down by one row at the end of each iteration
-    T acc[3][7];                 // update accumulators
+    // down by one row at the end of each iteration.  acc[.][0] accumulates
+    // the stored plane-0 variable (h, or eta' in mixed precision).
+    T acc[3][7];
     int phi_w[3], brk_w[3];      // masks
     T b_w[3];                    // bathymetry
     Waves<T> yprev;              // waves of the y-edge below the new one
     T ydl[7];                    // its dot products with the edge below it
     T xtr_prev[7];               // transverse x-fluctuation entering (i, k-1)
     T bp_saved[7];               // transverse y-fluctuation entering (i, k-1) from below
-    T rx = (T)0, ry = (T)0, clip = (T)0;
+    T rx = (T)0, ry = (T)0;
+    double clip = 0.0;
+    HSGN_UNROLL
     for (int m = 0; m < 7; m++) { xtr_prev[m] = (T)0; bp_saved[m] = (T)0; ydl[m] = (T)0; }
 
     RawCell<T> nxt;
@@ -223,16 +269,19 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
             RawCell<T> raw = nxt;
             // issue the next row's loads before working on this one
             if (k < r0 + th + 1) load_raw(pi, qin, A.bath, min_, mc, fx, k + 1, nxt);
-            prepare_cell(P, raw, tau_pre, c, phi_c, brk_c);
+            prepare_cell<T, MIXED>(P, raw, tau_pre, c, phi_c, brk_c);
+            acc[sk][IH] = raw.q[IH];
         }
         phi_w[sk] = phi_c;
         brk_w[sk] = brk_c;
         b_w[sk] = c.b;
-        for (int m = 0; m < 7; m++) acc[sk][m] = c.q[m];
+        HSGN_UNROLL
+        for (int m = 1; m < 7; m++) acc[sk][m] = c.q[m];
 
         const int slot_k = (k - r0 + 6) % 3, slot_k2 = (k - r0 + 4) % 3;
         // ---- x-edge (i-1/2, k) ----
         T xtr[7];
+        HSGN_UNROLL
         for (int m = 0; m < 7; m++) xtr[m] = (T)0;
         if (k >= r0 - 1 && k <= r0 + th) {
             Side<T> sr, sl;
@@ -240,20 +289,23 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
             shfl_side_up(ln, sr, sl);
             Waves<T> xw;
             Eig<T> xe;
-            bool ok = riemann<0>(P, sl, sr, xw, xe);
+            bool ok = edge_solve<0, MIXED>(ln, P, sl, sr, xw, xe);
             if (!ok && lane >= 1) sc->err = -4;
             Waves<T> xwl;
             shfl_waves_up(ln, xw, xwl);
             T dl[7], dr[7];
             family_dots<0>(xwl, xw, dl);
+            HSGN_UNROLL
             for (int f = 0; f < 7; f++) dr[f] = ln.dn(dl[f]);
             T F[7], am[7], ap[7];
             correction<0>(lim, dtdx, xw, dl, dr, F);
             fluctuations<0>(xw, am, ap);
             T apc[7], amc[7], amr[7];
+            HSGN_UNROLL
             for (int m = 0; m < 7; m++) { apc[m] = ap[m] - F[m]; amc[m] = am[m] + F[m]; }
             shfl_vec(ln, amc, amr, false);
             int kind_r = ln.dni(xw.kind);
+            HSGN_UNROLL
             for (int m = 0; m < 7; m++) {
                 acc[sk][m] -= dtdx * (apc[m] + amr[m]);
                 xtr[m] = (xw.kind == KIND_REGULAR ? apc[m] : (T)0)
@@ -261,7 +313,7 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
             }
             eig_store(ring, slot_k, lane, xe);
             if (k >= r0 && k < r0 + th && (interior || interior_left))
-                rx = tmax(rx, tmax(fabs(xw.smin), tmax(fabs(xw.smax), fabs(xw.uh))));
+                rx = tmax(rx, tmax((T)fabs(xw.smin), tmax((T)fabs(xw.smax), (T)fabs(xw.uh))));
         }
 
         // ---- y-edge (i, k-1/2) ----
@@ -270,10 +322,10 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
         if (k >= r0 - 1) {
             Waves<T> yw;
             Eig<T> ye;
-            bool ok = riemann<1>(P, yside_prev, yside, yw, ye);
+            bool ok = edge_solve<1, MIXED>(ln, P, yside_prev, yside, yw, ye);
             if (!ok) sc->err = -4;
             if (k >= r0 && k <= r0 + th && interior)
-                ry = tmax(ry, tmax(fabs(yw.smin), tmax(fabs(yw.smax), fabs(yw.uh))));
+                ry = tmax(ry, tmax((T)fabs(yw.smin), tmax((T)fabs(yw.smax), (T)fabs(yw.uh))));
             if (k >= r0) {
                 T dk[7];
                 family_dots<1>(yw, yprev, dk);
@@ -283,6 +335,7 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
                     correction<1>(lim, dtdy, yprev, ydl, dk, G);
                     fluctuations<1>(yprev, bm, bp);
                     T btm[7], btp[7];
+                    HSGN_UNROLL
                     for (int m = 0; m < 7; m++) {
                         T bpc = bp[m] - G[m], bmc = bm[m] + G[m];
                         acc[sk1][m] -= dtdy * bpc;
@@ -294,9 +347,11 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
                         // transverse y-fluctuation entering (i, k-2), split by
                         // the x-edges (i-1/2, k-2) and (i+1/2, k-2)
                         T ytr[7], ytl[7];
+                        HSGN_UNROLL
                         for (int m = 0; m < 7; m++) ytr[m] = bp_saved[m] + btm[m];
                         shfl_vec(ln, ytr, ytl, true);
                         T Ft[7];
+                        HSGN_UNROLL
                         for (int m = 0; m < 7; m++) Ft[m] = (T)0;
                         Eig<T> exk2;
                         eig_load(ring, slot_k2, lane, exk2);
@@ -304,14 +359,18 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
                             T vp[7], vm[7];
                             trans_split<0>(exk2, ytl, 1, vp);
                             trans_split<0>(exk2, ytr, -1, vm);
+                            HSGN_UNROLL
                             for (int m = 0; m < 7; m++) Ft[m] = (T)-0.5 * dtdy * (vp[m] + vm[m]);
                         }
                         T Ftr[7];
                         shfl_vec(ln, Ft, Ftr, false);
+                        HSGN_UNROLL
                         for (int m = 0; m < 7; m++) acc[sk2][m] -= dtdx * (Ftr[m] - Ft[m]);
                     }
+                    HSGN_UNROLL
                     for (int m = 0; m < 7; m++) bp_saved[m] = btp[m];
                 }
+                HSGN_UNROLL
                 for (int f = 0; f < 7; f++) ydl[f] = dk[f];
             }
             if (trans && k >= r0 && k <= r0 + th && ye.wet) {
@@ -319,6 +378,7 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
                 T vp[7], vm[7];
                 trans_split<1>(ye, xtr_prev, 1, vp);
                 trans_split<1>(ye, xtr, -1, vm);
+                HSGN_UNROLL
                 for (int m = 0; m < 7; m++) {
                     T Gt = (T)-0.5 * dtdx * (vp[m] + vm[m]);
                     acc[sk1][m] -= dtdy * Gt;
@@ -328,38 +388,57 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
             yprev = yw;
         }
 
-        // ---- row k-2 complete ----
+        // ---- row k-2 complete: second source half step and fix-ups ----
         if (k - 2 >= r0 && k - 2 <= r0 + th - 1) {
-            T *qn = acc[sk2];
             int phi = phi_w[sk2], brk = brk_w[sk2];
-            T bb = b_w[sk2];
             int swe = !phi || brk;
+            T bb = b_w[sk2];
             T c2 = swe ? (T)0 : (T)P.a2g * still_depth(P, bb);
+            // depth in the compute type for the source step
+            T qn[7];
+            HSGN_UNROLL
+            for (int m = 0; m < 7; m++) qn[m] = acc[sk2][m];
+            qn[IH] = depth_of<T, MIXED>(P, acc[sk2][IH], bb);
             source_or_clear(P, qn, c2, swe, tau_post);
-            if (qn[IH] < (T)0) {
-                clip += -qn[IH] * (T)pi.dx * (T)pi.dy;
-                qn[IH] = (T)0;
+            // fix-ups in FP64: the depth from the stored variable, clipping
+            // (mass bookkeeping in FP64), dry cells, breaking latch, SWE cells
+            double bD = (double)bb;
+            double hD = MIXED ? (double)acc[sk2][IH] + P.eta0 - bD : (double)acc[sk2][IH];
+            double qd[7];
+            HSGN_UNROLL
+            for (int m = 1; m < 7; m++) qd[m] = (double)qn[m];
+            if (hD < 0.0) {
+                clip += -hD * pi.dx * pi.dy;
+                hD = 0.0;
             }
-            if (qn[IH] <= (T)P.dry_tol) {
-                for (int m = 1; m < 7; m++) qn[m] = (T)0;
+            if (hD <= P.dry_tol) {
+                HSGN_UNROLL
+                for (int m = 1; m < 7; m++) qd[m] = 0.0;
             } else if (P.kappa > 0.0 && phi && !brk) {
-                T H = still_depth(P, bb);
-                if (qn[IH] + bb - (T)P.eta0 > (T)P.kappa * H) brk = 1;
+                double H = P.eta0 - bD;
+                H = H > 0.0 ? H : 0.0;
+                if (hD + bD - P.eta0 > P.kappa * H) brk = 1;
             }
-            if (!phi || brk || qn[IH] <= (T)P.dry_tol) {
-                qn[IHW] = (T)0; qn[IHS] = (T)0; qn[IHP] = (T)0; qn[IHPB] = (T)0;
+            if (!phi || brk || hD <= P.dry_tol) {
+                qd[IHW] = 0.0; qd[IHS] = 0.0; qd[IHP] = 0.0; qd[IHPB] = 0.0;
             }
-            bool bad = false;
-            for (int m = 0; m < 7; m++) bad = bad || !(fabs(qn[m]) <= (T)1e300);
+            // stored plane-0 variable
+            S out0 = MIXED ? (S)(hD + bD - P.eta0) : (S)hD;
+            bool bad = !finite_val<double>(hD);
+            HSGN_UNROLL
+            for (int m = 1; m < 7; m++) bad = bad || !finite_val<double>(qd[m]);
             if (interior) {
                 if (bad) sc->err = -5;
                 long long idx = (long long)(k - 2) * pi.pitch + (wk.i0 - 2 + lane);
                 long long plane = (long long)pi.ny * pi.pitch;
-                T *qo = qout + pi.qoff + idx;
-                for (int m = 0; m < 7; m++) qo[m * plane] = qn[m];
+                S *qo = qout + pi.qoff + idx;
+                qo[0] = out0;
+                HSGN_UNROLL
+                for (int m = 1; m < 7; m++) qo[m * plane] = (S)qd[m];
                 mout[pi.coff + idx] = (uint8_t)(phi | (brk << 1));
             }
         }
+        HSGN_UNROLL
         for (int m = 0; m < 7; m++) {
             xtr_prev[m] = xtr[m];
             acc[0][m] = acc[1][m];
@@ -370,7 +449,7 @@ HSGN_HD void march(L &ln, const MarchArgs<T> &A, int wid)
         b_w[0] = b_w[1]; b_w[1] = b_w[2];
         yside_prev = yside;
     }
-    ln.finish(A, wid, pi.scen, rx, ry, clip);
+    ln.finish(A, wid, pi.scen, (double)rx, (double)ry, clip);
 }
 
 }  // namespace hsgn

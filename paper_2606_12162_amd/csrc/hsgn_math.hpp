@@ -91,6 +91,24 @@ HSGN_HD T recip(T x) { return (T)1 / x; }
 // reciprocal for the limiter ratios: hardware estimate refined by two
 // Newton steps (a few ulp), which is all a ratio fed to a continuous
 // limiter function needs
+HSGN_HD float frcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// squared wave norms below this are treated as zero waves by the limiter
+template <class T> HSGN_HD T tiny_norm();
+template <> HSGN_HD double tiny_norm<double>() { return 1e-200; }
+template <> HSGN_HD float tiny_norm<float>() { return 1e-30f; }
+// finite and of sane magnitude
+template <class T> HSGN_HD bool finite_val(T x);
+template <> HSGN_HD bool finite_val<double>(double x) { return fabs(x) <= 1e300; }
+template <> HSGN_HD bool finite_val<float>(float x) { return fabsf(x) <= 3e38f; }
+
 HSGN_HD double frcp(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -382,6 +400,36 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     return true;
 }
 
+// precision conversion of solver results
+template <class D, class T>
+HSGN_HD void convert(const Waves<T> &a, Waves<D> &o)
+{
+    HSGN_UNROLL
+    for (int m = 0; m < 7; m++) { o.z0[m] = (D)a.z0[m]; o.z6[m] = (D)a.z6[m]; }
+    o.zm[0] = (D)a.zm[0]; o.zm[1] = (D)a.zm[1]; o.zm[2] = (D)a.zm[2];
+    o.bs = (D)a.bs; o.bw = (D)a.bw; o.bt = (D)a.bt; o.bpb = (D)a.bpb;
+    o.smin = (D)a.smin; o.smax = (D)a.smax; o.uh = (D)a.uh;
+    o.kind = a.kind;
+}
+
+template <class D, class T>
+HSGN_HD void convert(const Eig<T> &a, Eig<D> &o)
+{
+    o.uh = (D)a.uh; o.vh = (D)a.vh; o.wh = (D)a.wh; o.sh = (D)a.sh; o.pbh = (D)a.pbh;
+    o.ghh = (D)a.ghh; o.c2p = (D)a.c2p; o.inv_ce2 = (D)a.inv_ce2;
+    o.smin = (D)a.smin; o.smax = (D)a.smax; o.inv_ds = (D)a.inv_ds;
+    o.wet = a.wet;
+}
+
+template <class D, class T>
+HSGN_HD void convert(const Side<T> &a, Side<D> &o)
+{
+    o.h = (D)a.h; o.sq = (D)a.sq; o.ce = (D)a.ce; o.hun = (D)a.hun; o.un = (D)a.un;
+    o.ut = (D)a.ut; o.w = (D)a.w; o.s = (D)a.s; o.p = (D)a.p; o.pb = (D)a.pb;
+    o.hp = (D)a.hp; o.b = (D)a.b; o.c2 = (D)a.c2;
+    o.wet = a.wet; o.hyp = a.hyp;
+}
+
 // full 7-vector of family f of the waves (global frame); DIR selects where
 // the normal-momentum component of family 1 and the tangential contact sit
 template <int DIR, class T>
@@ -449,9 +497,9 @@ HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T
     for (int f = 0; f < 7; f++) {
         T zz = self[f];
         T s = wave_speed(W, f);
-        // waves below 1e-100 in norm contribute nothing at double precision;
+        // waves this small contribute nothing at the working precision;
         // skipping them also keeps the reciprocal of zz finite
-        bool live = zz > (T)1e-200;
+        bool live = zz > tiny_norm<T>();
         T th = live ? (s > (T)0 ? dl[f] : dr[f]) * frcp(zz) : (T)0;
         T ph = live ? limiter_phi(lim, th) : (T)0;
         T sg = s > (T)0 ? (T)1 : (s < (T)0 ? (T)-1 : (T)0);

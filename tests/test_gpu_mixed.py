@@ -1,0 +1,81 @@
+"""Mixed precision (FP32 surface-deviation storage, FP64 near-shore edges,
+fix-ups and mass sums) against the FP64 oracle.
+
+Bar: gauge error max |eta'_mixed - eta'_oracle| <= 1e-4 of the source
+amplitude on the same fixed time steps; the ocean at rest stays exactly at
+rest in FP32; mass drift stays at FP32 rounding level.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_12162_amd import hsgn as H
+from paper_2606_12162_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    H.lib()
+    yield
+
+
+def mixed_context(ws, tile_rows=0):
+    ctx = H.Context(ws[0].params, tile_rows=tile_rows, precision=1)
+    for s, w in enumerate(ws):
+        ctx.add_grid(s, w.grid)
+    ctx.finalize()
+    for s, w in enumerate(ws):
+        ctx.set_bathymetry(s, w.b)
+        ctx.set_state(s, w.q)
+        if len(w.gauges):
+            ctx.set_gauges(s, w.gauges)
+    return ctx
+
+
+def test_mixed_ocean_at_rest_is_exact():
+    w = W.synthetic_ocean(n=256, dx=4000.0, amp=0.0)
+    ctx = mixed_context([w])
+    ctx.advance(w.dt, 100)
+    q = ctx.get_state(0)
+    # h = eta' - b with eta' = 0 stored exactly; momenta and auxiliaries stay 0
+    assert np.abs(q[1:]).max() == 0.0
+    np.testing.assert_array_equal(q[0], np.maximum(-w.b.astype(np.float32).astype(np.float64), 0.0))
+
+
+def test_mixed_gauges_within_1e4_of_amplitude_against_fp64_oracle():
+    w = W.synthetic_ocean(n=512, dx=2000.0, steps=300)
+    print("case", w.name, "dt", w.dt, flush=True)
+    ctx = mixed_context([w])
+    ctx.advance(w.dt, w.steps)
+    tg, eg = ctx.read_gauges(0)
+    r = O.from_workload(w)
+    r.advance(w.dt, w.steps)
+    to, eo = r.read_gauges()
+    assert eg.shape == eo.shape == (300, 64)
+    np.testing.assert_allclose(tg, to, rtol=1e-12)
+    gauge_err = np.abs(eg - eo).max() / w.amplitude
+    print("gauge error / amplitude", gauge_err, "max |eta| at gauges", np.abs(eo).max())
+    assert np.abs(eo).max() > 1e-3 * w.amplitude      # the wave reached some gauges
+    assert gauge_err <= 1e-4
+    q = ctx.get_state(0)
+    qo = r.get_state()
+    eta_err = np.abs((q[0] + w.b) - (qo[0] + w.b))[qo[0] > 1e-3].max() / w.amplitude
+    print("field eta' error / amplitude", eta_err)
+    assert eta_err <= 1e-4
+    assert np.array_equal(ctx.get_mask(0), r.get_mask())
+
+
+def test_mixed_mass_bookkeeping():
+    w = W.synthetic_ocean(n=256, dx=4000.0, steps=200)
+    ctx = mixed_context([w])
+    m0 = ctx.diagnostics(0)["mass"]
+    ctx.advance(w.dt, w.steps)
+    d = ctx.diagnostics(0)
+    print("mass drift", (d["mass"] - m0) / m0, "clipped", d["clipped_mass"])
+    assert abs(d["mass"] - m0 - d["clipped_mass"]) <= 1e-6 * m0

@@ -4,15 +4,21 @@ A step is one accepted time step of the whole hot path (source half steps,
 x and y normal solves, limiters, transverse splits, flux-difference update,
 SWE switch and fix-ups, CFL control) over every cell of the workload.
 
-Default workload: the 1024 x 1024 plane beach with an incoming SGN solitary
-wave (FP64, adaptive CFL 0.9, reflecting walls, SWE transition below 0.05,
-breaking latch, 16 gauges).  Inputs are synthetic (seeded generators in
-paper_2606_12162_amd/workloads.py) and resident in HBM before timing starts.
+Default workload (--workload ensemble): 48 independent source scenarios on
+synthetic shelf oceans (grids of 512^2 to 1536^2 cells, 500 m to 2 km
+spacing, dipole sources of 1-8 m), advanced together, one launch per step,
+in the mixed FP32/FP64 form with each scenario's own fixed CFL-0.9 step.
+The same ensemble is then advanced in plain FP64 over the same steps; the
+line reports both rates and the gauge error of the mixed run against the
+FP64 run (the FP64 kernels match the FP64 CPU oracle to 1e-11, see tests).
+Other workloads: --workload beach (1024^2 plane beach, FP64, adaptive) and
+--workload ocean (2048^2 synthetic ocean, mixed and FP64).
 
-Prints one JSON line: value = interior cell-updates per second over the
-timed steps; roofline = the step kernel's algorithmic HBM bytes per launch
-over its average launch time (HIP events on the library's stream);
-cpu_baseline = the FP64 CPU oracle on a bounded sample of the same workload.
+Inputs are synthetic (seeded generators in paper_2606_12162_amd/workloads.py)
+and resident in HBM before timing starts.  The JSON line's roofline is the
+step kernel's algorithmic HBM bytes per launch over its average launch time
+(HIP events on the library's stream); cpu_baseline is the FP64 CPU oracle on
+a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -24,49 +30,88 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per FP64 cell update: read Q^n (7 x 8) and write Q^{n+1}
-# (7 x 8), read the bathymetry (8), read and write the mask byte (1 + 1)
-ALG_BYTES_FP64 = 7 * 8 * 2 + 8 + 2
+# algorithmic bytes per cell update: read Q^n and write Q^{n+1} (7 variables),
+# read the bathymetry, read and write the mask byte
+ALG_BYTES = {"fp64": 7 * 8 * 2 + 8 + 2, "mixed": 7 * 4 * 2 + 4 + 2}
 
 
-def workload_by_name(name):
-    from paper_2606_12162_amd import workloads as W
-    if name == "beach":
-        return [W.beach_soliton()]
-    if name == "hump":
-        return [W.gaussian_hump()]
-    if name == "ocean":
-        return [W.synthetic_ocean()]
-    raise SystemExit("unknown workload %s" % name)
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(ws, steps, dt):
-    """The FP64 oracle as it stands, on `steps` steps of the first workload."""
+def make_context(H, ws, precision, tile_rows=0, gauges=True):
+    ctx = H.Context(ws[0].params, tile_rows=tile_rows, precision=1 if precision == "mixed" else 0)
+    for s, w in enumerate(ws):
+        ctx.add_grid(s, w.grid)
+    ctx.finalize()
+    for s, w in enumerate(ws):
+        ctx.set_bathymetry(s, w.b)
+        ctx.set_state(s, w.q)
+        if gauges and len(w.gauges):
+            ctx.set_gauges(s, w.gauges)
+        if w.dt > 0:
+            ctx.set_clock(s, 0.0, w.dt, 0)
+    return ctx
+
+
+def run(H, torch, ws, precision, steps, warmup, tile_rows=0):
+    """Advance the workloads; returns (context, seconds, kernel ms per launch)."""
+    ctx = make_context(H, ws, precision, tile_rows)
+    dt = -1.0 if ws[0].dt > 0 else 0.0          # per-scenario fixed steps, or adaptive
+    if warmup:
+        ctx.advance(dt, warmup)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(dt, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n = ctx.get_timing()
+    ctx.set_timing(False)
+    return ctx, el, ms / max(n, 1), n
+
+
+def cpu_baseline(w, steps):
+    """The FP64 oracle as it stands, on `steps` steps of one workload."""
     from oracle import oracle as O
     if not os.path.exists(O.LIB_PATH):
         O.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    w = ws[0]
     g = O.from_workload(w)
     t0 = time.perf_counter()
-    g.advance(dt, steps)
+    g.advance(w.dt, steps)
     el = time.perf_counter() - t0
     cells = w.grid.nx * w.grid.ny
     return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": "first %d steps of %s (%d cell-updates), wall %.1f s"
+            "sample": "first %d steps of %s (%d cell-updates), wall %.1f s, FP64"
                       % (steps, w.name, cells * steps, el)}
+
+
+def gauge_error(ctx_a, ctx_b, ws):
+    """max over scenarios of max |eta'_a - eta'_b| / amplitude."""
+    import numpy as np
+    worst = 0.0
+    for s, w in enumerate(ws):
+        if not len(w.gauges):
+            continue
+        _, ea = ctx_a.read_gauges(s)
+        _, eb = ctx_b.read_gauges(s)
+        n = min(len(ea), len(eb))
+        worst = max(worst, float(np.abs(ea[:n] - eb[:n]).max()) / w.amplitude)
+    return worst
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="beach")
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="ensemble", choices=["ensemble", "beach", "ocean"])
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--sweep", default="",
                     help="comma-separated tile heights to time before the run; the "
                          "fastest is used for the timed steps")
@@ -78,47 +123,39 @@ def main():
 
     import torch
     from paper_2606_12162_amd import hsgn as H
+    from paper_2606_12162_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    ws = workload_by_name(args.workload)
-    dt = ws[0].dt
+    t0 = time.perf_counter()
+    if args.workload == "ensemble":
+        ws, precision = W.ensemble(), "mixed"
+    elif args.workload == "ocean":
+        ws, precision = [W.synthetic_ocean()], "mixed"
+    else:
+        ws, precision = [W.beach_soliton()], "fp64"
+    cells = sum(w.grid.nx * w.grid.ny for w in ws)
+    log("bench: %s x%d, %.2f M cells, precision %s, inputs generated in %.1f s"
+        % (ws[0].name, len(ws), cells / 1e6, precision, time.perf_counter() - t0))
+
     tile_rows = args.tile_rows
     if args.sweep:
         best = None
         for th in [int(x) for x in args.sweep.split(",")]:
-            c = H.from_workloads(ws, tile_rows=th)
-            c.advance(dt, 5)
-            c.set_timing(True)
-            c.advance(dt, 50)
-            ms, n = c.get_timing()
+            c, el, kms, n = run(H, torch, ws, precision, 20, 3, th)
             c.close()
-            us = ms / max(n, 1) * 1e3
-            print("sweep: tile rows %d: step kernel %.1f us" % (th, us), file=sys.stderr, flush=True)
-            if best is None or us < best[0]:
-                best = (us, th)
+            log("sweep: tile rows %d: step kernel %.1f us" % (th, kms * 1e3))
+            if best is None or kms < best[0]:
+                best = (kms, th)
         tile_rows = best[1]
-    ctx = H.from_workloads(ws, tile_rows=tile_rows)
-    cells = sum(w.grid.nx * w.grid.ny for w in ws)
-    print("bench: %s, %d cells, %d work items, warmup %d, steps %d"
-          % (ws[0].name, cells, ctx.work_items(), args.warmup, args.steps),
-          file=sys.stderr, flush=True)
 
-    if args.warmup:
-        ctx.advance(dt, args.warmup)
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.advance(dt, args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kern_ms, launches = ctx.get_timing()
-    ctx.set_timing(False)
-    diag = ctx.diagnostics(0)
-
+    ctx, el, kms, launches = run(H, torch, ws, precision, args.steps, args.warmup, tile_rows)
     value = cells * args.steps / el
-    kavg_s = kern_ms / max(launches, 1) / 1e3
-    achieved = ALG_BYTES_FP64 * cells / kavg_s / 1e9
+    diag = ctx.diagnostics(0)
+    log("timed: %.3f ms/step, step kernel %.1f us, %.3e cell-updates/s"
+        % (el * 1e3 / args.steps, kms * 1e3, value))
+    achieved = ALG_BYTES[precision] * cells / (kms / 1e3) / 1e9
+    dtype = {"mixed": "f32+f64", "fp64": "f64"}[precision]
     out = {
         "metric": "cell-updates/s",
         "value": value,
@@ -130,19 +167,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": ws[0].name, "cells": cells, "precision": "fp64",
-                   "dt": "adaptive, cfl 0.9" if dt <= 0 else "fixed %.6g" % dt,
-                   "rejected_steps": diag["rejected"], "max_courant": diag["max_courant"],
-                   "work_items": ctx.work_items(), "tile_rows": tile_rows or "library"},
+        "config": {"workload": ws[0].name if len(ws) == 1 else "ensemble_%d_scenarios" % len(ws),
+                   "scenarios": len(ws), "cells": cells, "precision": precision,
+                   "dt": "per-scenario fixed, cfl 0.9" if ws[0].dt > 0 else "adaptive, cfl 0.9",
+                   "work_items": ctx.work_items(), "tile_rows": tile_rows or "library",
+                   "max_courant_scenario0": diag["max_courant"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "march_kernel", "kernel_avg_us": kavg_s * 1e6,
-                     "launches": launches, "alg_bytes_per_cell": ALG_BYTES_FP64},
+                     "kernel": "march_kernel<%s>" % precision, "kernel_avg_us": kms * 1e3,
+                     "launches": launches, "alg_bytes_per_cell": ALG_BYTES[precision]},
     }
+    if precision == "mixed" and not args.no_fp64:
+        ctx64, el64, kms64, _ = run(H, torch, ws, "fp64", args.steps, args.warmup, tile_rows)
+        out["fp64_plain"] = {"value": cells * args.steps / el64,
+                             "ms_per_step": el64 * 1e3 / args.steps,
+                             "kernel_avg_us": kms64 * 1e3}
+        out["mixed_over_fp64"] = value / out["fp64_plain"]["value"]
+        out["gauge_err_over_amp"] = gauge_error(ctx, ctx64, ws)
+        log("fp64: %.3f ms/step; mixed/fp64 %.2fx; gauge error / amplitude %.2e"
+            % (out["fp64_plain"]["ms_per_step"], out["mixed_over_fp64"], out["gauge_err_over_amp"]))
+        ctx64.close()
+    ctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ws, args.cpu_steps, dt)
+        steps = args.cpu_steps or (60 if args.workload == "ensemble" else 20)
+        out["cpu_baseline"] = cpu_baseline(ws[0], steps)
     print(json.dumps(out), flush=True)
 
 

@@ -129,12 +129,14 @@ int hsgn_set_gauges(hsgn_ctx *c, int scenario, int n, const double *xy);
 int hsgn_read_gauges(hsgn_ctx *c, int scenario, double *t, double *eta,
                      int max_records, int *n_records);
 
-/* Advance every scenario by n_steps accepted steps.  dt > 0: fixed step
- * (ECFL if a step's Courant number exceeds cfl_max; that scenario stops at
- * its last good step).  dt <= 0: adaptive step dt_next = dt cfl / Courant
- * with reject and redo above cfl_max; the first step uses
+/* Advance every scenario by n_steps accepted steps.  dt > 0: the same
+ * fixed step for every scenario (ECFL if a step's Courant number exceeds
+ * cfl_max; that scenario stops at its last good step).  dt < 0: every
+ * scenario takes the fixed step set as dt_next by hsgn_set_clock (EINVAL if
+ * one is not set).  dt == 0: adaptive step dt_next = dt cfl / Courant with
+ * reject and redo above cfl_max; the first step uses
  * cfl / max((|u| + Ce)/dx, (|v| + Ce)/dy).  Returns after the device work
- * has completed.  Errors: ECFL, ENONHYP, ENAN, EDEVICE. */
+ * has completed.  Errors: ECFL, ENONHYP, ENAN, EINVAL, EDEVICE. */
 int hsgn_advance(hsgn_ctx *c, double dt, int n_steps);
 
 int hsgn_diagnostics(hsgn_ctx *c, int scenario, hsgn_diag *d);

@@ -228,64 +228,49 @@ int orc_set_mask(orc_grid *g, const unsigned char *m)
  *   d(h sigma)/dt = -6 p_b + 12 p
  *   d(hp)/dt      = -c^2 sigma
  *   d(h p_b)/dt   = -6 c^2 (w - sigma/2)
- * integrated with the two-stage SDIRK(2,2) method with
+ * so M = [[0,0,0,1],[0,0,12,-6],[0,-c^2,0,0],[-6c^2,3c^2,0,0]] acting on
+ * (w, sigma, p, p_b), integrated with the two-stage SDIRK(2,2) method with
  * gamma = 1 - 1/sqrt(2): Y1 = Y + gamma tau f(Y1),
  * Y2 = Y + (1-gamma) tau f(Y1) + gamma tau f(Y2), result Y2. */
 
-/* Gaussian elimination with partial pivoting; b is overwritten by x */
-static void solve4(double A[4][4], double b[4])
+/* One SDIRK stage: solve (I - k M) X = R with k = gamma tau / h and M the
+ * matrix above (acting on w, sigma, p, p_b).  The hw and hp rows give
+ * X0 = R0 + k X3 and X2 = R2 - k c^2 X1; substituting them into the
+ * h sigma and h p_b rows leaves
+ *   (1 + 12 k^2 c^2) X1 + 6 k X3        = R1 + 12 k R2
+ *   -3 k c^2 X1      + (1 + 6 k^2 c^2) X3 = R3 - 6 k c^2 R0
+ * which is solved by Cramer's rule. */
+static void stage_solve(double k, double c2, const double R[4], double X[4])
 {
-    for (int k = 0; k < 4; k++) {
-        int piv = k;
-        for (int r = k + 1; r < 4; r++)
-            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
-        if (piv != k) {
-            for (int c = 0; c < 4; c++) { double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t; }
-            double t = b[k]; b[k] = b[piv]; b[piv] = t;
-        }
-        for (int r = k + 1; r < 4; r++) {
-            double f = A[r][k] / A[k][k];
-            for (int c = k; c < 4; c++) A[r][c] -= f * A[k][c];
-            b[r] -= f * b[k];
-        }
-    }
-    for (int k = 3; k >= 0; k--) {
-        double s = b[k];
-        for (int c = k + 1; c < 4; c++) s -= A[k][c] * b[c];
-        b[k] = s / A[k][k];
-    }
+    double kc2 = k * c2;
+    double a = 1.0 + 12.0 * k * kc2;
+    double d = 1.0 + 6.0 * k * kc2;
+    double det = a * d + 18.0 * k * kc2;
+    double r1 = R[1] + 12.0 * k * R[2];
+    double r3 = R[3] - 6.0 * kc2 * R[0];
+    double x1 = (d * r1 - 6.0 * k * r3) / det;
+    double x3 = (a * r3 + 3.0 * kc2 * r1) / det;
+    X[0] = R[0] + k * x3;
+    X[1] = x1;
+    X[2] = R[2] - kc2 * x1;
+    X[3] = x3;
 }
 
 void orc_source_cell(double *q, double c2, double tau)
 {
-    double h = q[IH];
-    double M[4][4] = {
-        {0.0, 0.0, 0.0, 1.0},
-        {0.0, 0.0, 12.0, -6.0},
-        {0.0, -c2, 0.0, 0.0},
-        {-6.0 * c2, 3.0 * c2, 0.0, 0.0},
-    };
-    double J[4][4];
-    for (int r = 0; r < 4; r++)
-        for (int c = 0; c < 4; c++) J[r][c] = (tau / h) * M[r][c];
     double gam = 1.0 - 1.0 / sqrt(2.0);
-    double A[4][4];
+    double th = tau / q[IH];
+    double k = gam * th;
     double Y[4] = {q[IHW], q[IHS], q[IHP], q[IHPB]};
-    /* stage 1: (I - gamma J) Y1 = Y */
-    double Y1[4] = {Y[0], Y[1], Y[2], Y[3]};
-    for (int r = 0; r < 4; r++)
-        for (int c = 0; c < 4; c++) A[r][c] = (r == c ? 1.0 : 0.0) - gam * J[r][c];
-    solve4(A, Y1);
-    /* stage 2: (I - gamma J) Y2 = Y + (1 - gamma) J Y1 */
-    double Y2[4];
-    for (int r = 0; r < 4; r++) {
-        double s = 0.0;
-        for (int c = 0; c < 4; c++) s += J[r][c] * Y1[c];
-        Y2[r] = Y[r] + (1.0 - gam) * s;
-    }
-    for (int r = 0; r < 4; r++)
-        for (int c = 0; c < 4; c++) A[r][c] = (r == c ? 1.0 : 0.0) - gam * J[r][c];
-    solve4(A, Y2);
+    double Y1[4], R[4], Y2[4];
+    /* stage 1: Y1 = Y + gamma tau f(Y1) */
+    stage_solve(k, c2, Y, Y1);
+    /* stage 2: Y2 = Y + (1 - gamma) tau f(Y1) + gamma tau f(Y2), with
+     * tau f(Y1) = (tau / h) M Y1 */
+    double MY[4] = {Y1[3], 12.0 * Y1[2] - 6.0 * Y1[3], -c2 * Y1[1],
+                    -6.0 * c2 * Y1[0] + 3.0 * c2 * Y1[1]};
+    for (int r = 0; r < 4; r++) R[r] = Y[r] + (1.0 - gam) * (th * MY[r]);
+    stage_solve(k, c2, R, Y2);
     q[IHW] = Y2[0]; q[IHS] = Y2[1]; q[IHP] = Y2[2]; q[IHPB] = Y2[3];
 }
 
@@ -626,7 +611,8 @@ static void correction(int lim, double dtdx, const edge_t *El, const edge_t *E,
     if (lim == 0 || E->kind != 0) return;
     for (int p = 0; p < 7; p++) {
         double zz = dot7(E->Z[p], E->Z[p]);
-        if (zz == 0.0) continue;
+        /* a wave whose squared norm is below 1e-200 is a zero wave */
+        if (!(zz > 1e-200)) continue;
         const edge_t *U = E->s[p] > 0.0 ? El : Er;
         double th = dot7(U->Z[p], E->Z[p]) / zz;
         double ph = limiter_phi(lim, th);
@@ -733,57 +719,68 @@ int orc_step(orc_grid *g, double dt, double *courant)
 
     /* 5. transverse propagation.  The fluctuation an edge sends into a
      *    cell, including its limited correction (A+ - F~ to the right cell,
-     *    A- + F~ to the left cell), is split by the eigenstructure of the
-     *    cell's two edges in the other direction; the upward (rightward)
-     *    part feeds the far edge's correction with weight dt/(2 dx). */
+     *    A- + F~ to the left cell; none from wall or dry edges), is split by
+     *    the eigenstructure of the cell's edges in the other direction.  The
+     *    part moving up (right) feeds the correction of the cell's upper
+     *    (right) edge, the part moving down (left) that of its lower (left)
+     *    edge, with weight dt/(2 dx).  The split is linear, so the two
+     *    fluctuations entering a cell through its opposite edges are split
+     *    together. */
     if (P->transverse == 2) {
-        const double cx = 0.5 * dtdx, cy = 0.5 * dtdy;
-        /* G~ at y-edge (i, j) from the x-fluctuations entering cells
-         * (i, j-1) [upward part] and (i, j) [downward part] */
+        const double cx = -0.5 * dtdx, cy = -0.5 * dtdy;
+        /* x-fluctuation entering cell (i, j), i = 0..nx-1, j = -1..ny */
+        double *Xin = (double *)malloc((size_t)nx * (ny + 2) * 7 * sizeof(double));
+        /* y-fluctuation entering cell (i, j), i = -1..nx, j = 0..ny-1 */
+        double *Yin = (double *)malloc((size_t)(nx + 2) * ny * 7 * sizeof(double));
+        if (!Xin || !Yin) { free(Xin); free(Yin); return ORC_ENOMEM; }
+#define XI(i, j) (((size_t)((j) + 1) * nx + (size_t)(i)) * 7)
+#define YI(i, j) (((size_t)(j) * (nx + 2) + (size_t)((i) + 1)) * 7)
+        for (int j = -1; j <= ny; j++) {
+            for (int i = 0; i < nx; i++) {
+                const edge_t *el = &EX[XE(i, j)], *er = &EX[XE(i + 1, j)];
+                const double *Fl = &Flim[XE(i, j) * 7], *Fr = &Flim[XE(i + 1, j) * 7];
+                for (int m = 0; m < 7; m++)
+                    Xin[XI(i, j) + m] = (el->kind == 0 ? el->apdq[m] - Fl[m] : 0.0)
+                                      + (er->kind == 0 ? er->amdq[m] + Fr[m] : 0.0);
+            }
+        }
+        for (int j = 0; j < ny; j++) {
+            for (int i = -1; i <= nx; i++) {
+                const edge_t *eb = &EY[YE(i, j)], *et = &EY[YE(i, j + 1)];
+                const double *Gb = &Glim[YE(i, j) * 7], *Gt = &Glim[YE(i, j + 1) * 7];
+                for (int m = 0; m < 7; m++)
+                    Yin[YI(i, j) + m] = (eb->kind == 0 ? eb->apdq[m] - Gb[m] : 0.0)
+                                      + (et->kind == 0 ? et->amdq[m] + Gt[m] : 0.0);
+            }
+        }
+        /* G~ at y-edge (i, j): up part of cell (i, j-1), down part of (i, j) */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j <= ny; j++) {
             for (int i = 0; i < nx; i++) {
                 const edge_t *ye = &EY[YE(i, j)];
-                double *G = &Gtr[YE(i, j) * 7];
                 if (!ye->e.wet) continue;
-                for (int part = 0; part < 4; part++) {
-                    int row = (part < 2) ? j - 1 : j;
-                    int sgn = (part < 2) ? 1 : -1;
-                    int ex = (part % 2 == 0) ? i : i + 1;
-                    const edge_t *xe = &EX[XE(ex, row)];
-                    if (xe->kind != 0) continue;
-                    const double *F = &Flim[XE(ex, row) * 7];
-                    double a[7], v[7];
-                    for (int m = 0; m < 7; m++)
-                        a[m] = (part % 2 == 0) ? xe->apdq[m] - F[m] : xe->amdq[m] + F[m];
-                    split_by_y(P, &ye->e, a, sgn, v);
-                    for (int m = 0; m < 7; m++) G[m] -= cx * v[m];
-                }
+                double vp[7], vm[7];
+                split_by_y(P, &ye->e, &Xin[XI(i, j - 1)], 1, vp);
+                split_by_y(P, &ye->e, &Xin[XI(i, j)], -1, vm);
+                for (int m = 0; m < 7; m++) Gtr[YE(i, j) * 7 + m] = cx * (vp[m] + vm[m]);
             }
         }
-        /* F~ at x-edge (i, j) from the y-fluctuations entering cells
-         * (i-1, j) [rightward part] and (i, j) [leftward part] */
+        /* F~ at x-edge (i, j): right part of cell (i-1, j), left part of (i, j) */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < ny; j++) {
             for (int i = 0; i <= nx; i++) {
                 const edge_t *xe = &EX[XE(i, j)];
-                double *F = &Ftr[XE(i, j) * 7];
                 if (!xe->e.wet) continue;
-                for (int part = 0; part < 4; part++) {
-                    int col = (part < 2) ? i - 1 : i;
-                    int sgn = (part < 2) ? 1 : -1;
-                    int ey = (part % 2 == 0) ? j : j + 1;
-                    const edge_t *ye = &EY[YE(col, ey)];
-                    if (ye->kind != 0) continue;
-                    const double *G = &Glim[YE(col, ey) * 7];
-                    double a[7], v[7];
-                    for (int m = 0; m < 7; m++)
-                        a[m] = (part % 2 == 0) ? ye->apdq[m] - G[m] : ye->amdq[m] + G[m];
-                    trans_split(P, &xe->e, a, sgn, v);
-                    for (int m = 0; m < 7; m++) F[m] -= cy * v[m];
-                }
+                double vp[7], vm[7];
+                trans_split(P, &xe->e, &Yin[YI(i - 1, j)], 1, vp);
+                trans_split(P, &xe->e, &Yin[YI(i, j)], -1, vm);
+                for (int m = 0; m < 7; m++) Ftr[XE(i, j) * 7 + m] = cy * (vp[m] + vm[m]);
             }
         }
+#undef XI
+#undef YI
+        free(Xin);
+        free(Yin);
     }
 
     /* 6. flux-difference update of the interior cells, then
@@ -795,15 +792,21 @@ int orc_step(orc_grid *g, double dt, double *courant)
         for (int i = 0; i < nx; i++) {
             size_t k = CELL(g, i, j);
             size_t xl = XE(i, j), xr = XE(i + 1, j), yb = YE(i, j), yt = YE(i, j + 1);
+            /* Q^{n+1} = Q - dt/dx (A+dQ_{i-1/2} + A-dQ_{i+1/2} + F~_{i+1/2} - F~_{i-1/2})
+             *             - dt/dy (B+dQ_{j-1/2} + B-dQ_{j+1/2} + G~_{j+1/2} - G~_{j-1/2}),
+             * F~ and G~ being the limited corrections plus the transverse
+             * terms; the contributions are applied one after the other in
+             * this order (any order gives the same sum up to rounding) */
             double qc[7];
             for (int m = 0; m < 7; m++) {
-                double fx = EX[xl].apdq[m] + EX[xr].amdq[m]
-                          + (Flim[xr * 7 + m] + Ftr[xr * 7 + m])
-                          - (Flim[xl * 7 + m] + Ftr[xl * 7 + m]);
-                double gy = EY[yb].apdq[m] + EY[yt].amdq[m]
-                          + (Glim[yt * 7 + m] + Gtr[yt * 7 + m])
-                          - (Glim[yb * 7 + m] + Gtr[yb * 7 + m]);
-                qc[m] = qs[m * np + k] - dtdx * fx - dtdy * gy;
+                double v = qs[m * np + k];
+                v -= dtdx * ((EX[xl].apdq[m] - Flim[xl * 7 + m]) + (EX[xr].amdq[m] + Flim[xr * 7 + m]));
+                v += dtdy * Gtr[yb * 7 + m];
+                v -= dtdy * (EY[yb].apdq[m] - Glim[yb * 7 + m]);
+                v -= dtdy * Gtr[yt * 7 + m];
+                v -= dtdy * (EY[yt].amdq[m] + Glim[yt * 7 + m]);
+                v -= dtdx * (Ftr[xr * 7 + m] - Ftr[xl * 7 + m]);
+                qc[m] = v;
             }
             source_or_clear(g, k, P->splitting ? 0.5 * dt : dt, qc);
             if (qc[IH] < 0.0) {

@@ -9,26 +9,38 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libhsgn.so")
-SOURCES = [os.path.join(CSRC, "hsgn_api.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("hsgn_math.hpp", "hsgn_march.hpp")] + \
+SOURCES = [os.path.join(CSRC, f) for f in ("hsgn_api.hip", "hsgn_step64.hip", "hsgn_step32.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("hsgn_math.hpp", "hsgn_march.hpp", "hsgn_step.hpp")] + \
           [os.path.join(INCLUDE, "hsgn.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions (their forms are not trusted on this target)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # fused multiply-add where the compiler finds a*b+c
-    "-ffp-contract=fast",
     # FP32 division and square root to ~1 ulp (the FP64 ones stay IEEE)
     "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wno-unused-result",
 ]
+# per-source floating-point contraction: the FP64 step kernel rounds every
+# product and sum separately; the FP32 one and the host code may fuse
+CONTRACT = {"hsgn_step64.hip": "-ffp-contract=off"}
+BUILD_DIR = os.path.join(HERE, "_build")
 
 
 def build(verbose: bool = False) -> str:
     """Compile libhsgn.so for gfx950; always recompiles."""
-    cmd = [HIPCC] + FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", LIB_PATH + ".tmp"] + SOURCES
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+        contract = CONTRACT.get(os.path.basename(src), "-ffp-contract=fast")
+        cmd = [HIPCC] + FLAGS + [contract, "-I", INCLUDE, "-I", CSRC, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB_PATH + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -31,44 +31,10 @@ using namespace hsgn;
 // ---------------------------------------------------------------------------
 // device side
 
-template <class T>
-struct GpuLanes {
-    T *ring_;
-    __device__ T *ring() const { return ring_; }
-    __device__ int lane() const { return (int)(threadIdx.x & 63); }
-    __device__ double up(double x) const { return __shfl_up(x, 1, 64); }
-    __device__ double dn(double x) const { return __shfl_down(x, 1, 64); }
-    __device__ float up(float x) const { return __shfl_up(x, 1, 64); }
-    __device__ float dn(float x) const { return __shfl_down(x, 1, 64); }
-    __device__ int upi(int x) const { return __shfl_up(x, 1, 64); }
-    __device__ int dni(int x) const { return __shfl_down(x, 1, 64); }
-    __device__ bool any(int p) const { return __any(p); }
-    template <class S>
-    __device__ void finish(const MarchArgs<S> &A, int wid, int scen, double rx, double ry,
-                           double clip) const
-    {
-        for (int o = 32; o > 0; o >>= 1) {
-            rx = fmax(rx, __shfl_xor(rx, o, 64));
-            ry = fmax(ry, __shfl_xor(ry, o, 64));
-            clip += __shfl_xor(clip, o, 64);
-        }
-        if (lane() == 0) {
-            atomicMax(&A.scen[scen].rx_bits, (unsigned long long)__double_as_longlong(rx));
-            atomicMax(&A.scen[scen].ry_bits, (unsigned long long)__double_as_longlong(ry));
-            A.clip_slots[wid] = clip;
-        }
-    }
-};
-
-template <class S, class T, bool MIXED>
-__global__ __launch_bounds__(64) void march_kernel(MarchArgs<S> A)
-{
-    int wid = (int)blockIdx.x;
-    if (wid >= A.nwork) return;
-    __shared__ T ring[3 * EIG_FIELDS * 64];
-    GpuLanes<T> ln{ring};
-    march<GpuLanes<T>, S, T, MIXED>(ln, A, wid);
-}
+// the step kernel is compiled in two translation units with different
+// floating-point contraction (hsgn_step64.hip: none, hsgn_step32.hip: FMA)
+void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
+void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
 
 struct ScenStatic {
     double dx, dy, cfl, cfl_max;
@@ -860,11 +826,9 @@ static int launch_attempt(hsgn_ctx *c)
     }
     unsigned nw = (unsigned)c->work.size();
     if (c->mixed)
-        march_kernel<float, float, true><<<nw, 64, 0, c->stream>>>(
-            march_args<float>(c, c->f0, c->f1, c->fbath));
+        launch_march32(march_args<float>(c, c->f0, c->f1, c->fbath), nw, c->stream);
     else
-        march_kernel<double, double, false><<<nw, 64, 0, c->stream>>>(
-            march_args<double>(c, c->q0, c->q1, c->bath));
+        launch_march64(march_args<double>(c, c->q0, c->q1, c->bath), nw, c->stream);
     if (c->timing) {
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
@@ -894,14 +858,19 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
     std::vector<ScenState> st;
     int rc = pull_scen(c, st);
     if (rc) return rc;
-    bool adaptive = !(dt > 0.0);
+    // dt > 0: one fixed step for all scenarios; dt == 0: adaptive steps;
+    // dt < 0: each scenario keeps the fixed step stored in its clock
+    bool adaptive = dt == 0.0;
+    bool per_scen = dt < 0.0;
     bool need_dt0 = false;
     for (size_t s = 0; s < st.size(); s++) {
         if (st[s].err) return fail(c, st[s].err, "scenario in error state");
+        if (per_scen && !(st[s].dt > 0.0))
+            return fail(c, HSGN_EINVAL, "per-scenario fixed step not set (hsgn_set_clock)");
         st[s].adaptive = adaptive ? 1 : 0;
-        st[s].dt_fixed = adaptive ? 0.0 : dt;
-        if (!adaptive) st[s].dt = dt;
-        else if (!(st[s].dt > 0.0)) need_dt0 = true;
+        st[s].dt_fixed = adaptive ? 0.0 : (per_scen ? st[s].dt : dt);
+        if (!adaptive && !per_scen) st[s].dt = dt;
+        else if (adaptive && !(st[s].dt > 0.0)) need_dt0 = true;
         st[s].target = st[s].steps + n_steps;
         st[s].active = 1;
         st[s].streak = 0;

@@ -84,7 +84,7 @@ HSGN_HD void shfl_side_up(L &ln, const Side<T> &c, Side<T> &o)
 // x-edge eigenstructure kept for two rows in a per-wavefront LDS ring
 // (3 row slots x EIG_FIELDS x 64 lanes); each lane only touches its own
 // entries, so no synchronisation is needed
-constexpr int EIG_FIELDS = 12;
+constexpr int EIG_FIELDS = 13;
 
 template <class T>
 HSGN_HD void eig_store(T *ring, int slot, int lane, const Eig<T> &e)
@@ -93,7 +93,7 @@ HSGN_HD void eig_store(T *ring, int slot, int lane, const Eig<T> &e)
     p[0 * 64] = e.uh; p[1 * 64] = e.vh; p[2 * 64] = e.wh; p[3 * 64] = e.sh;
     p[4 * 64] = e.pbh; p[5 * 64] = e.ghh; p[6 * 64] = e.c2p; p[7 * 64] = e.inv_ce2;
     p[8 * 64] = e.smin; p[9 * 64] = e.smax; p[10 * 64] = e.inv_ds;
-    p[11 * 64] = e.wet ? (T)1 : (T)0;
+    p[11 * 64] = e.wet ? (T)1 : (T)0; p[12 * 64] = e.ce2;
 }
 
 template <class T>
@@ -103,7 +103,7 @@ HSGN_HD void eig_load(const T *ring, int slot, int lane, Eig<T> &e)
     e.uh = p[0 * 64]; e.vh = p[1 * 64]; e.wh = p[2 * 64]; e.sh = p[3 * 64];
     e.pbh = p[4 * 64]; e.ghh = p[5 * 64]; e.c2p = p[6 * 64]; e.inv_ce2 = p[7 * 64];
     e.smin = p[8 * 64]; e.smax = p[9 * 64]; e.inv_ds = p[10 * 64];
-    e.wet = p[11 * 64] != (T)0;
+    e.wet = p[11 * 64] != (T)0; e.ce2 = p[12 * 64];
 }
 
 template <class L, class T>

@@ -77,7 +77,7 @@ struct Waves {
 // (normal frame of that edge)
 template <class T>
 struct Eig {
-    T uh, vh, wh, sh, pbh, ghh, c2p, inv_ce2, smin, smax, inv_ds;
+    T uh, vh, wh, sh, pbh, ghh, c2p, ce2, inv_ce2, smin, smax, inv_ds;
     int wet;           // both cells wet
 };
 
@@ -87,6 +87,17 @@ HSGN_HD T tmax(T a, T b) { return a > b ? a : b; }
 // reciprocal used where one denominator serves several quotients
 template <class T>
 HSGN_HD T recip(T x) { return (T)1 / x; }
+
+// quotient a / b given inv = 1 / b: FP64 divides (same rounding as a plain
+// division; the flux differences that follow cancel strongly, so their
+// inputs are rounded exactly as a direct quotient), FP32 multiplies
+HSGN_HD double quot(double a, double b, double) { return a / b; }
+HSGN_HD float quot(float a, float, float inv) { return a * inv; }
+
+// sqrt(g h) for the dry-front speed: FP64 evaluates it directly, FP32 reuses
+// the cell's sqrt(h)
+HSGN_HD double front_root(double g, double h, double, double) { return sqrt(g * h); }
+HSGN_HD float front_root(float, float, float sg, float sq) { return sg * sq; }
 
 // reciprocal for the limiter ratios: hardware estimate refined by two
 // Newton steps (a few ulp), which is all a ratio fed to a continuous
@@ -159,11 +170,12 @@ HSGN_HD void stage_solve(T k, T c2, const T R[4], T X[4])
     T kc2 = k * c2;
     T a = (T)1 + (T)12 * k * kc2;
     T d = (T)1 + (T)6 * k * kc2;
-    T idet = recip(a * d + (T)18 * k * kc2);
+    T det = a * d + (T)18 * k * kc2;
+    T idet = recip(det);
     T r2 = R[1] + (T)12 * k * R[2];
     T r4 = R[3] - (T)6 * kc2 * R[0];
-    T x2 = (d * r2 - (T)6 * k * r4) * idet;
-    T x4 = (a * r4 + (T)3 * kc2 * r2) * idet;
+    T x2 = quot(d * r2 - (T)6 * k * r4, det, idet);
+    T x4 = quot(a * r4 + (T)3 * kc2 * r2, det, idet);
     X[0] = R[0] + k * x4;
     X[1] = x2;
     X[2] = R[2] - kc2 * x2;
@@ -173,8 +185,8 @@ HSGN_HD void stage_solve(T k, T c2, const T R[4], T X[4])
 template <class T>
 HSGN_HD void source_step(T *q, T c2, T tau)
 {
-    const T gam = (T)(1.0 - 0.70710678118654752440);
-    T th = tau * recip(q[IH]);
+    const T gam = (T)1 - (T)1 / sqrt((T)2);
+    T th = quot(tau, q[IH], recip(q[IH]));
     T Y[4] = {q[IHW], q[IHS], q[IHP], q[IHPB]};
     T k = gam * th;
     T Y1[4];
@@ -211,9 +223,11 @@ HSGN_HD void derive(const StepParams &P, Cell<T> &c)
     c.hyp = 1;
     c.ce = (T)0;
     if (c.wet) {
-        T ih = recip(c.q[IH]);
-        c.u = c.q[IHU] * ih; c.v = c.q[IHV] * ih; c.w = c.q[IHW] * ih;
-        c.s = c.q[IHS] * ih; c.p = c.q[IHP] * ih; c.pb = c.q[IHPB] * ih;
+        T h = c.q[IH];
+        T ih = recip(h);
+        c.u = quot(c.q[IHU], h, ih); c.v = quot(c.q[IHV], h, ih);
+        c.w = quot(c.q[IHW], h, ih); c.s = quot(c.q[IHS], h, ih);
+        c.p = quot(c.q[IHP], h, ih); c.pb = quot(c.q[IHPB], h, ih);
         T a = (T)P.g * c.h + c.p + c.c2;
         c.hyp = a >= (T)0;
         c.ce = sqrt(a > (T)0 ? a : (T)0);
@@ -287,7 +301,7 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     W.kind = KIND_REGULAR;
     E.wet = sL.wet && sR.wet;
     E.uh = E.vh = E.wh = E.sh = E.pbh = E.ghh = E.c2p = (T)0;
-    E.inv_ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1; E.inv_ds = (T)0.5;
+    E.ce2 = (T)1; E.inv_ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1; E.inv_ds = (T)0.5;
     if (!sL.wet && !sR.wet) { W.kind = KIND_DRY; return true; }
 
     Side<T> L = sL, R = sR;
@@ -309,15 +323,16 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     }
 
     T sqL = L.sq, sqR = R.sq;
-    T iden = recip(sqL + sqR);
+    T den = sqL + sqR;
+    T iden = recip(den);
     T hh = (T)0.5 * (L.h + R.h);
     T c2h = (T)0.5 * (L.c2 + R.c2);
-    T uh = (sqR * R.un + sqL * L.un) * iden;
-    T vh = (sqR * R.ut + sqL * L.ut) * iden;
-    T wh = (sqR * R.w + sqL * L.w) * iden;
-    T sh = (sqR * R.s + sqL * L.s) * iden;
-    T ph = (sqR * R.p + sqL * L.p) * iden;
-    T pbh = (sqR * R.pb + sqL * L.pb) * iden;
+    T uh = quot(sqR * R.un + sqL * L.un, den, iden);
+    T vh = quot(sqR * R.ut + sqL * L.ut, den, iden);
+    T wh = quot(sqR * R.w + sqL * L.w, den, iden);
+    T sh = quot(sqR * R.s + sqL * L.s, den, iden);
+    T ph = quot(sqR * R.p + sqL * L.p, den, iden);
+    T pbh = quot(sqR * R.pb + sqL * L.pb, den, iden);
 
     T psi = sensor(P, L.b, R.b);
     T db = R.b - L.b;
@@ -340,13 +355,13 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     T sg = sqrt(g);
     T smin, smax;
     if (dryL) {
-        smin = R.un - (T)2 * sg * R.sq;
+        smin = R.un - (T)2 * front_root(g, R.h, sg, R.sq);
     } else {
         if (!L.hyp) return false;
         smin = tmin(uh - ceh, L.un - L.ce);
     }
     if (dryR) {
-        smax = L.un + (T)2 * sg * L.sq;
+        smax = L.un + (T)2 * front_root(g, L.h, sg, L.sq);
     } else {
         if (!R.hyp) return false;
         smax = tmax(uh + ceh, R.un + R.ce);
@@ -358,10 +373,11 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     if (L.c2 == (T)0 && R.c2 == (T)0) {
         // SWE edge: HLLE waves carrying the surface-elevation jump
         T dq0 = deta, dq1 = R.hun - L.hun;
-        T z1h = smin * ((smax * dq0 - df[0]) * ids);
-        T z1m = smin * ((smax * dq1 - df[1]) * ids);
-        T z7h = smax * ((df[0] - smin * dq0) * ids);
-        T z7m = smax * ((df[1] - smin * dq1) * ids);
+        T ds = smax - smin;
+        T z1h = smin * quot(smax * dq0 - df[0], ds, ids);
+        T z1m = smin * quot(smax * dq1 - df[1], ds, ids);
+        T z7h = smax * quot(df[0] - smin * dq0, ds, ids);
+        T z7m = smax * quot(df[1] - smin * dq1, ds, ids);
         T S = z1h + z7h;
         n0[0] = z1h; n0[1] = z1m; n0[2] = vh * z1h; n0[3] = wh * z1h;
         n0[4] = sh * z1h; n0[5] = ph * z1h; n0[6] = pbh * z1h;
@@ -373,11 +389,11 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
         W.bt = df[2] - vh * S;
         W.bpb = df[6] - pbh * S;
     } else {
-        T b2 = ((c2h + ph) * df[0] - df[5]) * ice2;
+        T b2 = quot((c2h + ph) * df[0] - df[5], ce2, ice2);
         T S = df[0] - b2;
         T Tm = df[1] - uh * b2;
-        T b1 = (smax * S - Tm) * ids;
-        T b7 = (Tm - smin * S) * ids;
+        T b1 = quot(smax * S - Tm, smax - smin, ids);
+        T b7 = quot(Tm - smin * S, smax - smin, ids);
         n0[0] = b1; n0[1] = b1 * smin; n0[2] = b1 * vh; n0[3] = b1 * wh;
         n0[4] = b1 * sh; n0[5] = b1 * (c2h + ph); n0[6] = b1 * pbh;
         n6[0] = b7; n6[1] = b7 * smax; n6[2] = b7 * vh; n6[3] = b7 * wh;
@@ -395,7 +411,7 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     W.smin = smin; W.smax = smax; W.uh = uh;
 
     E.uh = uh; E.vh = vh; E.wh = wh; E.sh = sh; E.pbh = pbh;
-    E.ghh = g * hh; E.c2p = c2h + ph; E.inv_ce2 = ice2; E.smin = smin; E.smax = smax;
+    E.ghh = g * hh; E.c2p = c2h + ph; E.ce2 = ce2; E.inv_ce2 = ice2; E.smin = smin; E.smax = smax;
     E.inv_ds = ids;
     return true;
 }
@@ -416,7 +432,7 @@ template <class D, class T>
 HSGN_HD void convert(const Eig<T> &a, Eig<D> &o)
 {
     o.uh = (D)a.uh; o.vh = (D)a.vh; o.wh = (D)a.wh; o.sh = (D)a.sh; o.pbh = (D)a.pbh;
-    o.ghh = (D)a.ghh; o.c2p = (D)a.c2p; o.inv_ce2 = (D)a.inv_ce2;
+    o.ghh = (D)a.ghh; o.c2p = (D)a.c2p; o.ce2 = (D)a.ce2; o.inv_ce2 = (D)a.inv_ce2;
     o.smin = (D)a.smin; o.smax = (D)a.smax; o.inv_ds = (D)a.inv_ds;
     o.wet = a.wet;
 }
@@ -500,7 +516,7 @@ HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T
         // waves this small contribute nothing at the working precision;
         // skipping them also keeps the reciprocal of zz finite
         bool live = zz > tiny_norm<T>();
-        T th = live ? (s > (T)0 ? dl[f] : dr[f]) * frcp(zz) : (T)0;
+        T th = live ? quot(s > (T)0 ? dl[f] : dr[f], zz, frcp(zz)) : (T)0;
         T ph = live ? limiter_phi(lim, th) : (T)0;
         T sg = s > (T)0 ? (T)1 : (s < (T)0 ? (T)-1 : (T)0);
         T c = (T)0.5 * sg * ((T)1 - dtdx * fabs(s)) * ph;
@@ -545,11 +561,11 @@ HSGN_HD void trans_split(const Eig<T> &E, const T *a, int sgn, T *out)
     const int IN = DIR == 0 ? IHU : IHV;
     const int IT = DIR == 0 ? IHV : IHU;
     T an[7] = {a[IH], a[IN], a[IT], a[IHW], a[IHS], a[IHP], a[IHPB]};
-    T g2 = (E.c2p * an[0] - an[5]) * E.inv_ce2;
+    T g2 = quot(E.c2p * an[0] - an[5], E.ce2, E.inv_ce2);
     T S = an[0] - g2;
     T Tm = an[1] - E.uh * g2;
-    T g1 = (E.smax * S - Tm) * E.inv_ds;
-    T g7 = (Tm - E.smin * S) * E.inv_ds;
+    T g1 = quot(E.smax * S - Tm, E.smax - E.smin, E.inv_ds);
+    T g7 = quot(Tm - E.smin * S, E.smax - E.smin, E.inv_ds);
     T gt = an[2] - E.vh * S;
     T gw = an[3] - E.wh * S;
     T gs = an[4] - E.sh * S;

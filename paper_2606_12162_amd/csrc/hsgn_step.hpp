@@ -1,0 +1,50 @@
+#pragma once
+// hsgn_step.hpp -- the marching step kernel and its wavefront lane policy.
+
+#include <hip/hip_runtime.h>
+
+#include "hsgn_march.hpp"
+
+namespace hsgn {
+
+template <class T>
+struct GpuLanes {
+    T *ring_;
+    __device__ T *ring() const { return ring_; }
+    __device__ int lane() const { return (int)(threadIdx.x & 63); }
+    __device__ double up(double x) const { return __shfl_up(x, 1, 64); }
+    __device__ double dn(double x) const { return __shfl_down(x, 1, 64); }
+    __device__ float up(float x) const { return __shfl_up(x, 1, 64); }
+    __device__ float dn(float x) const { return __shfl_down(x, 1, 64); }
+    __device__ int upi(int x) const { return __shfl_up(x, 1, 64); }
+    __device__ int dni(int x) const { return __shfl_down(x, 1, 64); }
+    __device__ bool any(int p) const { return __any(p); }
+    template <class S>
+    __device__ void finish(const MarchArgs<S> &A, int wid, int scen, double rx, double ry,
+                           double clip) const
+    {
+        for (int o = 32; o > 0; o >>= 1) {
+            rx = fmax(rx, __shfl_xor(rx, o, 64));
+            ry = fmax(ry, __shfl_xor(ry, o, 64));
+            clip += __shfl_xor(clip, o, 64);
+        }
+        if (lane() == 0) {
+            atomicMax(&A.scen[scen].rx_bits, (unsigned long long)__double_as_longlong(rx));
+            atomicMax(&A.scen[scen].ry_bits, (unsigned long long)__double_as_longlong(ry));
+            A.clip_slots[wid] = clip;
+        }
+    }
+};
+
+template <class S, class T, bool MIXED>
+__global__ __launch_bounds__(64) void march_kernel(MarchArgs<S> A)
+{
+    int wid = (int)blockIdx.x;
+    if (wid >= A.nwork) return;
+    __shared__ T ring[3 * EIG_FIELDS * 64];
+    GpuLanes<T> ln{ring};
+    march<GpuLanes<T>, S, T, MIXED>(ln, A, wid);
+}
+
+
+}  // namespace hsgn

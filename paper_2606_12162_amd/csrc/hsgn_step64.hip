@@ -1,0 +1,11 @@
+// hsgn_step64.hip -- FP64 instantiation of the step kernel, compiled without
+// floating-point contraction so that products and sums round as in a plain
+// FP64 evaluation of the same formulas.
+#include "hsgn_step.hpp"
+
+using namespace hsgn;
+
+void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream)
+{
+    march_kernel<double, double, false><<<nwork, 64, 0, stream>>>(A);
+}

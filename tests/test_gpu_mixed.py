@@ -79,3 +79,53 @@ def test_mixed_mass_bookkeeping():
     d = ctx.diagnostics(0)
     print("mass drift", (d["mass"] - m0) / m0, "clipped", d["clipped_mass"])
     assert abs(d["mass"] - m0 - d["clipped_mass"]) <= 1e-6 * m0
+
+
+def small_ensemble(count=6, seed0=77):
+    return W.ensemble(count=count, seed0=seed0, nmin=64, nmax=200, steps=120)
+
+
+def test_ensemble_one_launch_per_step_fp64_parity_and_mixed_gauges():
+    ws = small_ensemble()
+    for precision, bar in ((0, None), (1, 1e-4)):
+        ctx = H.Context(ws[0].params, precision=precision)
+        for s, w in enumerate(ws):
+            ctx.add_grid(s, w.grid)
+        ctx.finalize()
+        for s, w in enumerate(ws):
+            ctx.set_bathymetry(s, w.b)
+            ctx.set_state(s, w.q)
+            ctx.set_gauges(s, w.gauges)
+            ctx.set_clock(s, 0.0, w.dt, 0)          # per-scenario fixed step
+        ctx.advance(-1.0, ws[0].steps)
+        for s, w in enumerate(ws):
+            print("case", w.name, "precision", precision, flush=True)
+            r = O.from_workload(w)
+            r.advance(w.dt, w.steps)
+            t, dtn, steps = ctx.clock(s)
+            assert steps == w.steps and abs(t - w.steps * w.dt) <= 1e-9 * t
+            tg, eg = ctx.read_gauges(s)
+            to, eo = r.read_gauges()
+            if bar is None:
+                got, exp = ctx.get_state(s), r.get_state()
+                scale = np.abs(exp).max(axis=(1, 2))
+                err = np.abs(got - exp).max(axis=(1, 2)) / np.where(scale > 0, scale, 1.0)
+                assert err.max() <= 1e-11, err
+                assert np.abs(eg - eo).max() <= 1e-11 * w.amplitude
+            else:
+                ge = np.abs(eg - eo).max() / w.amplitude
+                print("  gauge error / amplitude", ge)
+                assert ge <= bar
+        ctx.close()
+
+
+def test_per_scenario_step_requires_clock():
+    ws = small_ensemble(count=2)
+    ctx = H.Context(ws[0].params, precision=1)
+    for s, w in enumerate(ws):
+        ctx.add_grid(s, w.grid)
+    ctx.finalize()
+    for s, w in enumerate(ws):
+        ctx.set_bathymetry(s, w.b)
+        ctx.set_state(s, w.q)
+    assert ctx.advance_status(-1.0, 1) == H.HSGN_EINVAL

@@ -15,12 +15,23 @@ Other workloads: --workload beach (1024^2 plane beach, FP64, adaptive) and
 --workload ocean (2048^2 synthetic ocean, mixed and FP64).
 
 Inputs are synthetic (seeded generators in paper_2606_12162_amd/workloads.py)
-and resident in HBM before timing starts.  The JSON line's roofline is the
-step kernel's algorithmic HBM bytes per launch over its average launch time
-(HIP events on the library's stream); cpu_baseline is the FP64 CPU oracle on
-a bounded sample of the same workload.
+and resident in HBM before timing starts.  The step kernel issues far more
+vector ALU instructions than its HBM bytes need (about 20 flops per byte), so
+the JSON line's roofline is its algorithmic floating-point work, 1274 flops
+per cell update (counted by csrc/opcount.cpp), over its average launch time
+(HIP events on the library's stream), against the vector ALU peak of the chip
+(256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s, the same for FP64
+and for unpacked FP32).  The algorithmic HBM rate is reported beside it, and
+`traffic` is the HBM bytes per launch measured with rocprofv3 counters for
+the current kernel sources (null when the sources have changed since).
+cpu_baseline is the FP64 CPU oracle on a bounded sample of the same workload.
+
+`python bench.py --copy-calibration` runs one 2 GiB device copy and nothing
+else: the kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate the byte
+counters of the step kernel.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,9 +41,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12      # 78.6
+# algorithmic flops per cell update (csrc/opcount.cpp)
+ALG_FLOPS = 1274
 # algorithmic bytes per cell update: read Q^n and write Q^{n+1} (7 variables),
 # read the bathymetry, read and write the mask byte
 ALG_BYTES = {"fp64": 7 * 8 * 2 + 8 + 2, "mixed": 7 * 4 * 2 + 4 + 2}
+# HBM bytes per step-kernel launch from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch; FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the
+# factors a plain 2 GiB copy reads), for the kernel sources whose digest is
+# given; any change to those sources makes the figure stale (null)
+KERNEL_SOURCES = ["hsgn_math.hpp", "hsgn_march.hpp", "hsgn_step.hpp",
+                  "hsgn_step32.hip", "hsgn_step64.hip"]
+MEASURED_TRAFFIC = {
+    ("ensemble", "mixed"): {"fetch_kib": 1.36742e6, "write_kib": 1.56542e6,
+                            "digest": "2d72a32d56017c1a"},
+}
+
+
+def kernel_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_12162_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    m = MEASURED_TRAFFIC.get((workload, precision))
+    if m is None or m["digest"] != kernel_digest():
+        return None
+    return (m["fetch_kib"] * 2.0 + m["write_kib"] * 1.0) * 1024.0
 
 
 def log(*a):
@@ -112,6 +151,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 2 GiB device copy (byte-counter calibration) and exit")
     ap.add_argument("--sweep", default="",
                     help="comma-separated tile heights to time before the run; the "
                          "fastest is used for the timed steps")
@@ -122,11 +163,19 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2606_12162_amd import hsgn as H
-    from paper_2606_12162_amd import workloads as W
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied %d bytes" % (a.numel() * 8))
+        return
+
+    from paper_2606_12162_amd import hsgn as H
+    from paper_2606_12162_amd import workloads as W
     t0 = time.perf_counter()
     if args.workload == "ensemble":
         ws, precision = W.ensemble(), "mixed"
@@ -154,7 +203,9 @@ def main():
     diag = ctx.diagnostics(0)
     log("timed: %.3f ms/step, step kernel %.1f us, %.3e cell-updates/s"
         % (el * 1e3 / args.steps, kms * 1e3, value))
-    achieved = ALG_BYTES[precision] * cells / (kms / 1e3) / 1e9
+    tflops = ALG_FLOPS * cells / (kms / 1e3) / 1e12
+    hbm_gbs = ALG_BYTES[precision] * cells / (kms / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, precision)
     dtype = {"mixed": "f32+f64", "fp64": "f64"}[precision]
     out = {
         "metric": "cell-updates/s",
@@ -174,10 +225,15 @@ def main():
                    "dt": "per-scenario fixed, cfl 0.9" if ws[0].dt > 0 else "adaptive, cfl 0.9",
                    "work_items": ctx.work_items(), "tile_rows": tile_rows or "library",
                    "max_courant_scenario0": diag["max_courant"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "march_kernel<%s>" % precision, "kernel_avg_us": kms * 1e3,
-                     "launches": launches, "alg_bytes_per_cell": ALG_BYTES[precision]},
+                     "launches": launches, "alg_flops_per_cell": ALG_FLOPS,
+                     "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": hbm_gbs / HBM_PEAK_GBS,
+                             "alg_bytes_per_cell": ALG_BYTES[precision],
+                             "traffic_over_alg": (traffic / (ALG_BYTES[precision] * cells)
+                                                  if traffic else None)}},
     }
     if precision == "mixed" and not args.no_fp64:
         ctx64, el64, kms64, _ = run(H, torch, ws, "fp64", args.steps, args.warmup, tile_rows)

@@ -47,6 +47,11 @@ struct orc_grid {
     double *b;                  /* [sy][sx] */
     unsigned char *phi;         /* [sy][sx] transition function phi_T */
     unsigned char *brk;         /* [sy][sx] breaking latch */
+    /* patch sets: ghosts written by the caller instead of the boundary map,
+     * and per-cell flags of edges whose fluxes the caller replaces
+     * (bit 0 left, 1 right, 2 bottom, 3 top) */
+    int ext_ghosts;
+    unsigned char *iface;       /* [sy][sx] */
     double t, dt_next;
     long long nstep, nrej;
     int have_dt;
@@ -138,14 +143,15 @@ orc_grid *orc_create(const orc_params *p, int nx, int ny, double x0, double y0,
     g->b = (double *)calloc(np, sizeof(double));
     g->phi = (unsigned char *)calloc(np, 1);
     g->brk = (unsigned char *)calloc(np, 1);
-    if (!g->q || !g->b || !g->phi || !g->brk) { orc_destroy(g); return NULL; }
+    g->iface = (unsigned char *)calloc(np, 1);
+    if (!g->q || !g->b || !g->phi || !g->brk || !g->iface) { orc_destroy(g); return NULL; }
     return g;
 }
 
 void orc_destroy(orc_grid *g)
 {
     if (!g) return;
-    free(g->q); free(g->b); free(g->phi); free(g->brk);
+    free(g->q); free(g->b); free(g->phi); free(g->brk); free(g->iface);
     free(g->gxy); free(g->rec_t); free(g->rec_eta);
     free(g->w_qs); free(g->w_c2); free(g->w_Flim); free(g->w_Ftr);
     free(g->w_Glim); free(g->w_Gtr); free(g->w_clip); free(g->w_EX); free(g->w_EY);
@@ -660,7 +666,7 @@ int orc_step(orc_grid *g, double dt, double *courant)
 #define XE(i, j) ((size_t)((j) + 1) * nxe + (size_t)((i) + 1))
 #define YE(i, j) ((size_t)((j) + 1) * nye + (size_t)((i) + 1))
 
-    fill_ghosts(g);
+    if (!g->ext_ghosts) fill_ghosts(g);
 
     /* 1. source half step (Strang) on every cell including ghosts; Lie only
      *    clears the auxiliary variables of dry and SWE cells here. */
@@ -797,15 +803,27 @@ int orc_step(orc_grid *g, double dt, double *courant)
              * F~ and G~ being the limited corrections plus the transverse
              * terms; the contributions are applied one after the other in
              * this order (any order gives the same sum up to rounding) */
+            /* in a patch set, the contributions through an edge shared
+             * with a finer patch are left out here; the finer patch's
+             * fluxes replace them after its substeps (refluxing) */
+            const int fl = g->iface[k];
             double qc[7];
             for (int m = 0; m < 7; m++) {
+                double xl_n = (fl & 1) ? 0.0 : EX[xl].apdq[m] - Flim[xl * 7 + m];
+                double xr_n = (fl & 2) ? 0.0 : EX[xr].amdq[m] + Flim[xr * 7 + m];
+                double yb_t = (fl & 4) ? 0.0 : Gtr[yb * 7 + m];
+                double yb_n = (fl & 4) ? 0.0 : EY[yb].apdq[m] - Glim[yb * 7 + m];
+                double yt_t = (fl & 8) ? 0.0 : Gtr[yt * 7 + m];
+                double yt_n = (fl & 8) ? 0.0 : EY[yt].amdq[m] + Glim[yt * 7 + m];
+                double xr_t = (fl & 2) ? 0.0 : Ftr[xr * 7 + m];
+                double xl_t = (fl & 1) ? 0.0 : Ftr[xl * 7 + m];
                 double v = qs[m * np + k];
-                v -= dtdx * ((EX[xl].apdq[m] - Flim[xl * 7 + m]) + (EX[xr].amdq[m] + Flim[xr * 7 + m]));
-                v += dtdy * Gtr[yb * 7 + m];
-                v -= dtdy * (EY[yb].apdq[m] - Glim[yb * 7 + m]);
-                v -= dtdy * Gtr[yt * 7 + m];
-                v -= dtdy * (EY[yt].amdq[m] + Glim[yt * 7 + m]);
-                v -= dtdx * (Ftr[xr * 7 + m] - Ftr[xl * 7 + m]);
+                v -= dtdx * (xl_n + xr_n);
+                v += dtdy * yb_t;
+                v -= dtdy * yb_n;
+                v -= dtdy * yt_t;
+                v -= dtdy * yt_n;
+                v -= dtdx * (xr_t - xl_t);
                 qc[m] = v;
             }
             source_or_clear(g, k, P->splitting ? 0.5 * dt : dt, qc);
@@ -1019,3 +1037,89 @@ double orc_mass(const orc_grid *g)
 }
 
 double orc_clipped_mass(const orc_grid *g) { return g->clipped; }
+
+/* ------------------------------------------------------------------ */
+/* patch sets (static AMR, Sec. 4 notes the wave-propagation AMR of Berger
+ * and LeVeque): the caller owns the ghost frame and the flux registers      */
+
+int orc_framed(orc_grid *g, double **q, double **b, unsigned char **phi,
+               unsigned char **brk, unsigned char **iface, int *sx, int *sy)
+{
+    *q = g->q; *b = g->b; *phi = g->phi; *brk = g->brk; *iface = g->iface;
+    *sx = g->sx; *sy = g->sy;
+    return ORC_OK;
+}
+
+void orc_set_external_ghosts(orc_grid *g, int on) { g->ext_ghosts = on ? 1 : 0; }
+
+/* phi_T of the interior cells from the bathymetry of the frame, ghost cells
+ * included (the caller has filled them); clears the breaking latch */
+int orc_update_phi_framed(orc_grid *g)
+{
+    int n = g->P.nbr_n;
+    for (int j = 0; j < g->ny; j++) {
+        for (int i = 0; i < g->nx; i++) {
+            double hmin = INFINITY;
+            for (int dj = -n; dj <= n; dj++)
+                for (int di = -n; di <= n; di++) {
+                    double H = still_depth(&g->P, g->b[CELL(g, i + di, j + dj)]);
+                    if (H < hmin) hmin = H;
+                }
+            g->phi[CELL(g, i, j)] = (hmin > g->P.h_star) ? 1 : 0;
+            g->brk[CELL(g, i, j)] = 0;
+        }
+    }
+    return ORC_OK;
+}
+
+/* What the last step sent through each boundary edge of the patch, as the
+ * flux through the edge minus the flux function of the cell outside it:
+ *   left   (x-edge i = 0):   A-dQ + F~ + F~tr
+ *   right  (x-edge i = nx): -(A+dQ - F~) + F~tr
+ *   bottom (y-edge j = 0):   B-dQ + G~ + G~tr
+ *   top    (y-edge j = ny): -(B+dQ - G~) + G~tr
+ * K[e][7] with e = j (left), ny + j (right), 2 ny + i (bottom),
+ * 2 ny + nx + i (top).  Valid after orc_step. */
+int orc_boundary_flux(const orc_grid *g, double *K)
+{
+    if (!g->w_EX) return ORC_EINVAL;
+    const int nx = g->nx, ny = g->ny;
+    const int nxe = nx + 3, nye = nx + 2;
+#define XE(i, j) ((size_t)((j) + 1) * nxe + (size_t)((i) + 1))
+#define YE(i, j) ((size_t)((j) + 1) * nye + (size_t)((i) + 1))
+    const edge_t *EX = g->w_EX, *EY = g->w_EY;
+    const double *Flim = g->w_Flim, *Ftr = g->w_Ftr, *Glim = g->w_Glim, *Gtr = g->w_Gtr;
+    for (int j = 0; j < ny; j++) {
+        size_t xl = XE(0, j), xr = XE(nx, j);
+        for (int m = 0; m < 7; m++) {
+            K[(size_t)j * 7 + m] = (EX[xl].amdq[m] + Flim[xl * 7 + m]) + Ftr[xl * 7 + m];
+            K[(size_t)(ny + j) * 7 + m] = -(EX[xr].apdq[m] - Flim[xr * 7 + m]) + Ftr[xr * 7 + m];
+        }
+    }
+    for (int i = 0; i < nx; i++) {
+        size_t yb = YE(i, 0), yt = YE(i, ny);
+        for (int m = 0; m < 7; m++) {
+            K[(size_t)(2 * ny + i) * 7 + m] = (EY[yb].amdq[m] + Glim[yb * 7 + m]) + Gtr[yb * 7 + m];
+            K[(size_t)(2 * ny + nx + i) * 7 + m] =
+                -(EY[yt].apdq[m] - Glim[yt * 7 + m]) + Gtr[yt * 7 + m];
+        }
+    }
+#undef XE
+#undef YE
+    return ORC_OK;
+}
+
+/* total fluctuation A-dQ + A+dQ of one edge (dir 0: x, 1: y), the
+ * non-conservative form of F(Q_R) - F(Q_L) in eq. (total fluctuation) */
+int orc_edge_dflux(const orc_params *p, int dir, const double *qL, const double *qR,
+                   double bL, double bR, double c2L, double c2R, double *df)
+{
+    edge_t E;
+    int rc = dir ? riemann_y(p, qL, qR, bL, bR, c2L, c2R, &E)
+                 : riemann_n(p, qL, qR, bL, bR, c2L, c2R, &E);
+    for (int m = 0; m < 7; m++) df[m] = E.amdq[m] + E.apdq[m];
+    return rc;
+}
+
+/* bilinear eta' of the patch at a point (same rule as the gauges) */
+double orc_gauge_eta(const orc_grid *g, double x, double y) { return gauge_eta(g, x, y); }

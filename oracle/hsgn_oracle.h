@@ -102,6 +102,25 @@ int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
 /* SDIRK(2,2) source step of length tau on one cell (in place). */
 void orc_source_cell(double *q, double c2, double tau);
 
+/* Patch sets.  orc_framed exposes the grid's framed arrays ([7][sy][sx]
+ * state, [sy][sx] bathymetry, phi_T, latch and interface flags; sx = nx+4,
+ * sy = ny+4, interior cell (i, j) at (j+2) sx + i+2).  With external ghosts
+ * on, orc_step uses the ghost cells as the caller left them.  Interface
+ * flag bits (0 left, 1 right, 2 bottom, 3 top) drop the contributions of
+ * that edge from the cell's update. */
+int orc_framed(orc_grid *g, double **q, double **b, unsigned char **phi,
+               unsigned char **brk, unsigned char **iface, int *sx, int *sy);
+void orc_set_external_ghosts(orc_grid *g, int on);
+int orc_update_phi_framed(orc_grid *g);
+/* boundary-edge fluxes of the last step relative to the outside cell,
+ * K[2 ny + 2 nx][7] (left rows, right rows, bottom columns, top columns) */
+int orc_boundary_flux(const orc_grid *g, double *K);
+/* eta' at a point by the gauge rule (bilinear over the 4 nearest centres) */
+double orc_gauge_eta(const orc_grid *g, double x, double y);
+/* A-dQ + A+dQ of one edge, dir 0 = x, 1 = y */
+int orc_edge_dflux(const orc_params *p, int dir, const double *qL, const double *qR,
+                   double bL, double bR, double c2L, double c2R, double *df);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,18 @@ def lib():
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
         L.orc_source_cell.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        ucp = ctypes.POINTER(ctypes.c_ubyte)
+        L.orc_framed.argtypes = [ctypes.c_void_p, ctypes.POINTER(dp), ctypes.POINTER(dp),
+                                 ctypes.POINTER(ucp), ctypes.POINTER(ucp), ctypes.POINTER(ucp),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.orc_set_external_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_update_phi_framed.argtypes = [ctypes.c_void_p]
+        L.orc_boundary_flux.argtypes = [ctypes.c_void_p, dp]
+        L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, dp]
+        L.orc_gauge_eta.restype = ctypes.c_double
+        L.orc_gauge_eta.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -190,6 +202,41 @@ class OracleGrid:
     def mass(self):
         return lib().orc_mass(self.h)
 
+    # --- patch sets: framed arrays shared with the C grid (no copies) ---
+    def framed(self):
+        """numpy views (q[7][sy][sx], b, phi, brk, iface [sy][sx]) of the
+        grid's own arrays; interior cell (i, j) sits at [j + 2, i + 2]."""
+        dp = ctypes.POINTER(ctypes.c_double)
+        ucp = ctypes.POINTER(ctypes.c_ubyte)
+        q, b = dp(), dp()
+        phi, brk, ifc = ucp(), ucp(), ucp()
+        sx, sy = ctypes.c_int(), ctypes.c_int()
+        _check(lib().orc_framed(self.h, ctypes.byref(q), ctypes.byref(b), ctypes.byref(phi),
+                                ctypes.byref(brk), ctypes.byref(ifc), ctypes.byref(sx),
+                                ctypes.byref(sy)), "framed")
+        n = sx.value * sy.value
+        shp = (sy.value, sx.value)
+        return (np.ctypeslib.as_array(q, shape=(7 * n,)).reshape((7,) + shp),
+                np.ctypeslib.as_array(b, shape=(n,)).reshape(shp),
+                np.ctypeslib.as_array(phi, shape=(n,)).reshape(shp),
+                np.ctypeslib.as_array(brk, shape=(n,)).reshape(shp),
+                np.ctypeslib.as_array(ifc, shape=(n,)).reshape(shp))
+
+    def set_external_ghosts(self, on=True):
+        lib().orc_set_external_ghosts(self.h, 1 if on else 0)
+
+    def update_phi_framed(self):
+        _check(lib().orc_update_phi_framed(self.h), "update_phi_framed")
+
+    def boundary_flux(self):
+        nx, ny = self.grid.nx, self.grid.ny
+        K = np.empty((2 * ny + 2 * nx, 7))
+        _check(lib().orc_boundary_flux(self.h, _dp(K)), "boundary_flux")
+        return K
+
+    def gauge_eta(self, x, y):
+        return lib().orc_gauge_eta(self.h, float(x), float(y))
+
     def clipped_mass(self):
         return lib().orc_clipped_mass(self.h)
 
@@ -217,6 +264,18 @@ def riemann_x(params, qL, qR, bL, bR, c2L, c2R):
                              ctypes.byref(kind))
     _check(rc, "riemann_x")
     return waves, speeds, amdq, apdq, kind.value
+
+
+def edge_dflux(params, direction, qL, qR, bL, bR, c2L, c2R):
+    """A-dQ + A+dQ of one edge (direction 0: x, 1: y)."""
+    p = _params(params)
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    df = np.zeros(7)
+    rc = lib().orc_edge_dflux(ctypes.byref(p), int(direction), _dp(qL), _dp(qR), float(bL),
+                              float(bR), float(c2L), float(c2R), _dp(df))
+    _check(rc, "edge_dflux")
+    return df
 
 
 def source_cell(q, c2, tau):

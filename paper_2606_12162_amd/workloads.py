@@ -265,3 +265,246 @@ def ensemble(count=48, seed0=5000, nmin=512, nmax=1536, steps=3000):
         w.name = "ensemble_%02d_%dx%d" % (s, n, n)
         out.append(w)
     return out
+
+
+# --------------------------------------------------------------------------
+# patch sets (static AMR)
+
+@dataclasses.dataclass
+class PatchSpec:
+    level: int
+    nx: int
+    ny: int
+    x0: float
+    y0: float
+    b: np.ndarray              # [ny, nx]
+    q: np.ndarray              # [7, ny, nx]
+
+
+@dataclasses.dataclass
+class AmrWorkload:
+    """One scenario on a static patch set: level-0 spacing dx0, dy0; level l
+    has spacing dx0 / 4^l; `bc` applies on the domain boundary."""
+    name: str
+    params: Params
+    dx0: float
+    dy0: float
+    bc: tuple
+    patches: list
+    gauges: np.ndarray
+    steps: int
+    dt: float                  # fixed level-0 step
+    amplitude: float
+
+
+RATIO = 4
+
+
+def tiled(w: Workload, kx: int, ky: int) -> AmrWorkload:
+    """A single-grid workload cut into kx x ky level-0 patches."""
+    g = w.grid
+    xs = np.linspace(0, g.nx, kx + 1).astype(int)
+    ys = np.linspace(0, g.ny, ky + 1).astype(int)
+    patches = []
+    for j in range(ky):
+        for i in range(kx):
+            sl = (slice(ys[j], ys[j + 1]), slice(xs[i], xs[i + 1]))
+            patches.append(PatchSpec(0, int(xs[i + 1] - xs[i]), int(ys[j + 1] - ys[j]),
+                                     g.x0 + xs[i] * g.dx, g.y0 + ys[j] * g.dy,
+                                     w.b[sl].copy(), w.q[(slice(None),) + sl].copy()))
+    return AmrWorkload(w.name + "_tiled%dx%d" % (kx, ky), w.params, g.dx, g.dy, g.bc, patches,
+                       w.gauges, w.steps, w.dt, w.amplitude)
+
+
+def _ring_state(X, Y, b, centre, r0, width, amp, g=G):
+    """outgoing circular long wave: eta' = A exp(-((r - r0)/w)^2), depth-
+    averaged radial momentum eta' sqrt(g H), auxiliaries zero"""
+    dxc, dyc = X - centre[0], Y - centre[1]
+    r = np.sqrt(dxc ** 2 + dyc ** 2)
+    eta = amp * np.exp(-((r - r0) / width) ** 2)
+    H = np.maximum(-b, 0.0)
+    h = np.maximum(eta - b, 0.0)
+    h = np.where(b >= 0.0, 0.0, h)
+    m = eta * np.sqrt(g * H)
+    rr = np.where(r > 0, r, 1.0)
+    q = np.zeros((7,) + X.shape)
+    q[0] = h
+    q[1] = np.where(h > 0, m * dxc / rr, 0.0)
+    q[2] = np.where(h > 0, m * dyc / rr, 0.0)
+    return q
+
+
+def _bilinear(field, x0, y0, dx, X, Y):
+    """bilinear interpolation of a cell-centred field (origin x0, y0) at
+    points X, Y (clamped at the edges)"""
+    ny, nx = field.shape
+    fx = np.clip((X - x0) / dx - 0.5, 0.0, nx - 1.000001)
+    fy = np.clip((Y - y0) / dx - 0.5, 0.0, ny - 1.000001)
+    i0 = np.floor(fx).astype(int)
+    j0 = np.floor(fy).astype(int)
+    wx, wy = fx - i0, fy - j0
+    return ((1 - wx) * (1 - wy) * field[j0, i0] + wx * (1 - wy) * field[j0, i0 + 1]
+            + (1 - wx) * wy * field[j0 + 1, i0] + wx * wy * field[j0 + 1, i0 + 1])
+
+
+def _basin(n0, dx, depth, amp, width, rough, seed):
+    """bathymetry and initial state (functions of cell centres) of the small
+    deep basin: depth plus four seeded smooth bumps, a Gaussian hump at rest
+    centred at (0.45 L, 0.55 L)"""
+    rng = np.random.default_rng(seed)
+    L = n0 * dx
+    bumps = rng.standard_normal((4, 3))
+
+    def bath(X, Y):
+        b = -depth + 0.0 * X
+        for a, cx, cy in bumps:
+            b = b + rough * a * np.exp(-(((X / L - 0.5 - 0.3 * cx) ** 2
+                                          + (Y / L - 0.5 - 0.3 * cy) ** 2) / 0.02))
+        return fp32_representable(b)
+
+    def state(X, Y, b):
+        eta = amp * np.exp(-(((X - 0.45 * L) ** 2 + (Y - 0.55 * L) ** 2) / width ** 2))
+        q = np.zeros((7,) + X.shape)
+        q[0] = np.maximum(eta - b, 0.0)
+        return q
+
+    return bath, state
+
+
+def amr_small(n0=48, tiles=2, dx=500.0, depth=4000.0, amp=1.0, width=3e3,
+              fine=((1, 64, 80, 40, 40), (1, 104, 88, 24, 32), (2, 300, 360, 48, 40)),
+              bc=(BC_WALL,) * 4, steps=6, rough=200.0, seed=11, cfl=0.9):
+    """Small three-level patch set: an n0 x n0 deep basin (depth plus seeded
+    smooth roughness) in tiles x tiles level-0 patches, a Gaussian hump at
+    rest off-centre, and the finer patches `fine` given as (level, i0, j0,
+    nx, ny) in cells of their own level."""
+    bath, state = _basin(n0, dx, depth, amp, width, rough, seed)
+    L = n0 * dx
+    patches = []
+    cuts = np.linspace(0, n0, tiles + 1).astype(int)
+    for j in range(tiles):
+        for i in range(tiles):
+            gx = Grid(int(cuts[i + 1] - cuts[i]), int(cuts[j + 1] - cuts[j]), cuts[i] * dx,
+                      cuts[j] * dx, dx, dx, bc)
+            X, Y = cell_centres(gx)
+            b = bath(X, Y)
+            patches.append(PatchSpec(0, gx.nx, gx.ny, gx.x0, gx.y0, b, state(X, Y, b)))
+    for lev, i0, j0, nx, ny in fine:
+        d = dx / RATIO ** lev
+        gx = Grid(nx, ny, i0 * d, j0 * d, d, d, bc)
+        X, Y = cell_centres(gx)
+        b = bath(X, Y)
+        patches.append(PatchSpec(lev, nx, ny, gx.x0, gx.y0, b, state(X, Y, b)))
+    params = Params(alpha=3.0, h_star=20.0, kappa=0.8, dry_tol=1e-3, cfl=cfl)
+    ce = math.sqrt(G * (depth + rough * 3 + amp) * (1 + 9.0))
+    dt = cfl * dx / ce
+    gauges = np.array([[0.45 * L, 0.55 * L], [0.3 * L, 0.3 * L], [0.62 * L, 0.5 * L],
+                       [0.7 * L, 0.7 * L]])
+    return AmrWorkload("amr_small_%d" % n0, params, dx, dx, bc, patches, gauges, steps, dt, amp)
+
+
+def amr_small_uniform(level, n0=48, dx=500.0, depth=4000.0, amp=1.0, width=3e3,
+                      bc=(BC_WALL,) * 4, steps=6, rough=200.0, seed=11, cfl=0.9):
+    """The basin of amr_small on one uniform grid at the spacing of `level`,
+    with 4^level steps of dt / 4^level per level-0 step"""
+    bath, state = _basin(n0, dx, depth, amp, width, rough, seed)
+    r = RATIO ** level
+    grid = Grid(n0 * r, n0 * r, 0.0, 0.0, dx / r, dx / r, bc)
+    X, Y = cell_centres(grid)
+    b = bath(X, Y)
+    w = amr_small(n0=n0, dx=dx, depth=depth, amp=amp, width=width, bc=bc, steps=steps,
+                  rough=rough, seed=seed, cfl=cfl)
+    return Workload("basin_uniform_level%d" % level, w.params, grid, b, state(X, Y, b), w.gauges,
+                    steps * r, w.dt / r, amp)
+
+
+def amr_ocean(n=2048, dx=500.0, tile=128, seed=4, targets=(1000, 1250),
+              band=(40e3, 10e3), r0=430e3, ring_amp=0.5, ring_width=15e3,
+              centre=(650e3, 512e3), max_tries=1_000_000, steps=500, cfl=0.9,
+              deep=-1000.0):
+    """Three-level patch set on the synthetic ocean: level 0 is the 2048^2
+    ocean at 500 m cut into 128^2 patches; levels 1 (125 m) and 2 (31.25 m)
+    hold patches with sides drawn from {16, 20, ..., 128} cells of their own
+    level, placed by seeded rejection sampling in deep water around a ring of
+    radius r0 about the source (half-widths band[0] and band[1]); level-2
+    patches nest inside one level-1 patch shrunk by one level-1 cell.  The
+    state is an outgoing circular long wave on that ring.  Fine bathymetry
+    is the bilinear interpolation of the level-0 bathymetry."""
+    base = synthetic_ocean(n=n, dx=dx, steps=steps, cfl=cfl)
+    rng = np.random.default_rng(seed)
+    L = n * dx
+    scale = L / 1024e3
+    c = (centre[0] * scale, centre[1] * scale)
+    b0 = base.b
+    patches = []
+    for J in range(0, n, tile):
+        for I in range(0, n, tile):
+            g = Grid(tile, tile, I * dx, J * dx, dx, dx, base.grid.bc)
+            X, Y = cell_centres(g)
+            bb = b0[J:J + tile, I:I + tile].copy()
+            patches.append(PatchSpec(0, tile, tile, g.x0, g.y0, bb,
+                                     _ring_state(X, Y, bb, c, r0 * scale, ring_width, ring_amp)))
+    sides = np.arange(16, 129, 4)
+
+    def deep_enough(x0, y0, w, h):
+        i0, j0 = int(x0 // dx), int(y0 // dx)
+        i1, j1 = int(math.ceil((x0 + w) / dx)), int(math.ceil((y0 + h) / dx))
+        if i0 < 1 or j0 < 1 or i1 > n - 1 or j1 > n - 1:
+            return False
+        return float(b0[j0:j1, i0:i1].max()) < deep
+
+    # level 1: occupancy in level-1 cells
+    d1 = dx / RATIO
+    n1 = n * RATIO
+    occ1 = np.zeros((n1, n1), dtype=bool)
+    lev1 = []
+    tries = 0
+    while len(lev1) < targets[0] and tries < max_tries:
+        tries += 1
+        th = rng.uniform(0, 2 * math.pi)
+        rr = r0 * scale + rng.uniform(-band[0], band[0])
+        wx, wy = int(rng.choice(sides)), int(rng.choice(sides))
+        cx, cy = c[0] + rr * math.cos(th), c[1] + rr * math.sin(th)
+        i0 = int(round((cx / d1 - wx / 2) / RATIO)) * RATIO
+        j0 = int(round((cy / d1 - wy / 2) / RATIO)) * RATIO
+        if i0 < RATIO or j0 < RATIO or i0 + wx > n1 - RATIO or j0 + wy > n1 - RATIO:
+            continue
+        if occ1[j0:j0 + wy, i0:i0 + wx].any():
+            continue
+        if not deep_enough(i0 * d1, j0 * d1, wx * d1, wy * d1):
+            continue
+        occ1[j0:j0 + wy, i0:i0 + wx] = True
+        lev1.append((i0, j0, wx, wy))
+    # level 2: inside one level-1 patch shrunk by one level-1 cell
+    d2 = d1 / RATIO
+    lev2 = []
+    occ2 = {}
+    tries = 0
+    while len(lev2) < targets[1] and tries < max_tries and lev1:
+        tries += 1
+        k = int(rng.integers(len(lev1)))
+        pi0, pj0, pw, ph = lev1[k]
+        wx, wy = int(rng.choice(sides)), int(rng.choice(sides))
+        inner_w, inner_h = (pw - 2) * RATIO, (ph - 2) * RATIO     # in level-2 cells
+        if wx > inner_w or wy > inner_h:
+            continue
+        ox = int(rng.integers(0, (inner_w - wx) // RATIO + 1)) * RATIO
+        oy = int(rng.integers(0, (inner_h - wy) // RATIO + 1)) * RATIO
+        o = occ2.setdefault(k, np.zeros((inner_h, inner_w), dtype=bool))
+        if o[oy:oy + wy, ox:ox + wx].any():
+            continue
+        o[oy:oy + wy, ox:ox + wx] = True
+        lev2.append(((pi0 + 1) * RATIO + ox, (pj0 + 1) * RATIO + oy, wx, wy))
+    for lev, items, d in ((1, lev1, d1), (2, lev2, d2)):
+        for i0, j0, wx, wy in items:
+            g = Grid(wx, wy, i0 * d, j0 * d, d, d, base.grid.bc)
+            X, Y = cell_centres(g)
+            bb = fp32_representable(_bilinear(b0, 0.0, 0.0, dx, X, Y))
+            patches.append(PatchSpec(lev, wx, wy, g.x0, g.y0, bb,
+                                     _ring_state(X, Y, bb, c, r0 * scale, ring_width, ring_amp)))
+    ang = np.linspace(0.55 * math.pi, 1.45 * math.pi, 16)
+    gauges = np.array([[c[0] + r0 * scale * math.cos(a), c[1] + r0 * scale * math.sin(a)]
+                       for a in ang])
+    name = "amr_ocean_%d_L0x%d_L1x%d_L2x%d" % (n, (n // tile) ** 2, len(lev1), len(lev2))
+    return AmrWorkload(name, base.params, dx, dx, base.grid.bc, patches, gauges, steps,
+                       base.dt, ring_amp)

@@ -30,8 +30,26 @@
  *     one and writes the other), bathymetry, two mask buffers, per-scenario
  *     clocks and gauge records.
  *   - A scenario is an independent simulation with its own clock and time
- *     step; each patch belongs to one scenario.  Patches of one scenario
- *     are independent grids here (no exchange between patches).
+ *     step; each patch belongs to one scenario.
+ *   - Patch sets (static AMR, the block-structured refinement of Sec. 4): a
+ *     scenario with more than one patch.  Level-0 patches tile a rectangle
+ *     (the domain; their boundary conditions apply on its sides, so they
+ *     must agree); level-l patches have spacing dx0 / 4^l, corners on
+ *     level-(l-1) cell corners, sides that are multiples of 4, stay one
+ *     level-(l-1) cell inside the domain and lie in the union of level-(l-1)
+ *     patches with one level-(l-1) cell to spare.  Patches of one level do
+ *     not overlap.  Each level-0 step runs 4 substeps of every level-1
+ *     patch, each of which runs 4 level-2 substeps, and so on.  Ghost cells
+ *     come from the same-level neighbour or the domain boundary condition,
+ *     else from the coarser level: linear in time between its old and new
+ *     states, linear in space with minmod-limited slopes of eta' = h + b -
+ *     eta0, hu, hv, hw, h sigma, hp, h p_b (zero slopes next to dry cells).
+ *     Coarse cells next to a finer patch take the finer patch's fluxes
+ *     (refluxing: their own contribution through that edge is replaced by
+ *     the mean of the 4 x 4 fine-edge, fine-substep fluxes, which keeps the
+ *     mass exact); covered coarse cells take the mean of their 4 x 4 fine
+ *     cells after the substeps, and their bathymetry the mean of the fine
+ *     bathymetry.  Patch sets advance with fixed steps only.
  */
 #ifndef HSGN_H
 #define HSGN_H
@@ -95,14 +113,17 @@ typedef struct hsgn_ctx hsgn_ctx;
  * Errors: EINVAL (bad parameters), ENOTSUP (model/precision), EDEVICE. */
 int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out);
 
-/* Add an nx x ny patch with cell size dx, dy and lower-left corner (x0, y0)
- * to a scenario (scenarios are numbered from 0 and need not be declared).
- * bc[4] = {x-low, x-high, y-low, y-high}; periodic sides come in pairs.
+/* Add an nx x ny patch of refinement level `level` (0 = coarsest, at most
+ * 5) with cell size dx, dy and lower-left corner (x0, y0) to a scenario
+ * (scenarios are numbered from 0 and need not be declared).  bc[4] =
+ * {x-low, x-high, y-low, y-high}; periodic sides come in pairs.
  * Errors: EINVAL (nx or ny < 4, bad bc, after finalize). */
-int hsgn_add_grid(hsgn_ctx *c, int scenario, int nx, int ny, double x0, double y0,
+int hsgn_add_grid(hsgn_ctx *c, int scenario, int level, int nx, int ny, double x0, double y0,
                   double dx, double dy, const int bc[4], int *patch_id);
 
-/* Allocate the device buffers and build the work tables.  Errors: ENOMEM. */
+/* Check the patch sets (rules above), allocate the device buffers and build
+ * the work and patch-set tables.  Errors: EINVAL (with the broken rule in
+ * hsgn_last_error), ENOMEM. */
 int hsgn_finalize(hsgn_ctx *c);
 
 /* Bathymetry b[ny][nx] of a patch; computes H = (eta0 - b)^+ and phi_T (the
@@ -120,8 +141,8 @@ int hsgn_set_mask(hsgn_ctx *c, int patch, const uint8_t *m, int on_device);
 
 /* Gauges of a scenario at points xy[n][2] (host).  Each accepted step
  * records eta' = h + b - eta0 (0 in dry cells) interpolated bilinearly
- * between the four nearest cell centres of the patch containing the point.
- * Errors: ERANGE. */
+ * between the four nearest cell centres of the finest patch containing the
+ * point (patch sets: one record per level-0 step).  Errors: ERANGE. */
 int hsgn_set_gauges(hsgn_ctx *c, int scenario, int n, const double *xy);
 
 /* Copy out the gauge records taken since the last read (t[r],
@@ -135,10 +156,14 @@ int hsgn_read_gauges(hsgn_ctx *c, int scenario, double *t, double *eta,
  * scenario takes the fixed step set as dt_next by hsgn_set_clock (EINVAL if
  * one is not set).  dt == 0: adaptive step dt_next = dt cfl / Courant with
  * reject and redo above cfl_max; the first step uses
- * cfl / max((|u| + Ce)/dx, (|v| + Ce)/dy).  Returns after the device work
- * has completed.  Errors: ECFL, ENONHYP, ENAN, EINVAL, EDEVICE. */
+ * cfl / max((|u| + Ce)/dx, (|v| + Ce)/dy).  Patch sets need dt != 0
+ * (ENOTSUP) and take n_steps level-0 steps; their whole level-0 step is
+ * replayed from a HIP graph when timing is off.  Returns after the device
+ * work has completed.  Errors: ECFL, ENONHYP, ENAN, EINVAL, ENOTSUP, EDEVICE. */
 int hsgn_advance(hsgn_ctx *c, double dt, int n_steps);
 
+/* Diagnostics of a scenario (patch sets: mass of level 0, counts and cell
+ * updates over all levels, clipped mass including refluxing). */
 int hsgn_diagnostics(hsgn_ctx *c, int scenario, hsgn_diag *d);
 int hsgn_get_clock(hsgn_ctx *c, int scenario, double *t, double *dt_next,
                    long long *steps);
@@ -150,7 +175,7 @@ int hsgn_work_items(hsgn_ctx *c, int *n);
 
 /* Kernel timing for measurement: with on = 1, every launch of the step
  * kernel inside hsgn_advance is bracketed by HIP events on the context's
- * stream.  hsgn_get_timing returns the summed event time (ms) and the number
+ * stream (patch sets: one launch per level step, launched directly).  hsgn_get_timing returns the summed event time (ms) and the number
  * of launches timed since timing was switched on, then resets both. */
 int hsgn_set_timing(hsgn_ctx *c, int on);
 int hsgn_get_timing(hsgn_ctx *c, double *step_kernel_ms, long long *launches);

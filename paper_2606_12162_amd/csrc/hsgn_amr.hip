@@ -1,0 +1,357 @@
+// hsgn_amr.hip -- kernels of static patch sets: ghost fill, boundary-flux
+// sums, refluxing and averaging down (rules in hsgn_amr.hpp).  Compiled
+// without floating-point contraction, like the FP64 step kernel, so that the
+// FP64 results round exactly as a plain evaluation of the same formulas.
+#include "hsgn_amr.hpp"
+
+namespace hsgn {
+
+namespace {
+
+constexpr int TPB = 128;
+
+inline unsigned blocks(long long n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+__device__ inline bool scen_failed(const ScenState *S, int slot) { return S[slot].err != 0; }
+
+// minmod of two slopes: the one of smaller magnitude if they agree in sign
+__device__ inline double minmod(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return a <= b ? a : b;
+    if (a < 0.0 && b < 0.0) return a >= b ? a : b;
+    return 0.0;
+}
+
+template <class S>
+__global__ void halo_copy_kernel(AmrBuffers<S> B, const GhostCopy *R, int n)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const GhostCopy r = R[k];
+    const PatchInfo D = B.patches[r.dp], Sp = B.patches[r.sp];
+    if (scen_failed(B.scen, D.scen)) return;
+    const int cur = B.scen[D.scen].cur;          // same level: same slot as the source
+    S *q = cur ? B.q1 : B.q0;
+    uint8_t *mk = cur ? B.m1 : B.m0;
+    for (int m = 0; m < 7; m++) {
+        S v = q[Sp.qoff + m * Sp.plane + r.sl];
+        if ((m == IHU && (r.flips & 1)) || (m == IHV && (r.flips & 2))) v = -v;
+        q[D.qoff + m * D.plane + r.dl] = v;
+    }
+    mk[D.coff + r.dl] = (uint8_t)(mk[Sp.coff + r.sl] & 3);
+}
+
+// eta', hu, ..., h p_b of a coarse cell at the old and new time levels, in
+// FP64, and whether it is dry at either
+template <class S, bool MIXED>
+__device__ void coarse_cell(const AmrBuffers<S> &B, const PatchInfo &C, int cl, const S *qo,
+                            const S *qn, double eta0, double dry_tol, double vo[7], double vn[7],
+                            bool &dry)
+{
+    const double b = (double)B.bath[C.coff + cl];
+    for (int m = 0; m < 7; m++) {
+        vo[m] = (double)qo[C.qoff + m * C.plane + cl];
+        vn[m] = (double)qn[C.qoff + m * C.plane + cl];
+    }
+    double ho, hn;
+    if (MIXED) {
+        ho = (vo[0] + eta0) - b;
+        hn = (vn[0] + eta0) - b;
+    } else {
+        ho = vo[0];
+        hn = vn[0];
+        vo[0] = (vo[0] + b) - eta0;
+        vn[0] = (vn[0] + b) - eta0;
+    }
+    dry = !(ho > dry_tol) || !(hn > dry_tol);
+}
+
+template <class S, bool MIXED>
+__global__ void halo_interp_kernel(AmrBuffers<S> B, const GhostInterp *R, int n, double theta,
+                                   double eta0, double dry_tol)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const GhostInterp r = R[k];
+    const PatchInfo D = B.patches[r.dp];
+    if (scen_failed(B.scen, D.scen)) return;
+    const PatchInfo C = B.patches[r.cp[0]];
+    const int ccur = B.scen[C.scen].cur;         // the coarse step is done: cur = new
+    const S *qn = ccur ? B.q1 : B.q0;
+    const S *qo = ccur ? B.q0 : B.q1;
+    double v[5][7];
+    bool have[5], any_dry = false;
+    for (int s = 0; s < 5; s++) {
+        have[s] = r.cp[s] >= 0;
+        if (!have[s]) continue;
+        const PatchInfo Cs = B.patches[r.cp[s]];
+        double vo[7], vn[7];
+        bool dry;
+        coarse_cell<S, MIXED>(B, Cs, r.cl[s], qo, qn, eta0, dry_tol, vo, vn, dry);
+        any_dry = any_dry || dry;
+        for (int m = 0; m < 7; m++) v[s][m] = (1.0 - theta) * vo[m] + theta * vn[m];
+    }
+    const double ox = (double)r.ox, oy = (double)r.oy;
+    double out[7];
+    for (int m = 0; m < 7; m++) {
+        double sx = 0.0, sy = 0.0;
+        if (!any_dry) {
+            if (have[1] && have[2]) sx = minmod(v[2][m] - v[0][m], v[0][m] - v[1][m]);
+            if (have[3] && have[4]) sy = minmod(v[4][m] - v[0][m], v[0][m] - v[3][m]);
+        }
+        out[m] = (v[0][m] + ox * sx) + oy * sy;
+    }
+    const double bg = (double)B.bath[D.coff + r.dl];
+    double h = (out[0] + eta0) - bg;
+    if (MIXED) {
+        if (!(h > 0.0)) out[0] = bg - eta0;      // depth clipped at zero
+    } else {
+        out[0] = h > 0.0 ? h : 0.0;
+    }
+    const int cur = B.scen[D.scen].cur;
+    S *q = cur ? B.q1 : B.q0;
+    for (int m = 0; m < 7; m++) q[D.qoff + m * D.plane + r.dl] = (S)out[m];
+    const uint8_t *mc = ccur ? B.m1 : B.m0;
+    uint8_t *md = cur ? B.m1 : B.m0;
+    md[D.coff + r.dl] = (uint8_t)(mc[C.coff + r.cl[0]] & 3);
+}
+
+template <class S>
+__global__ void ghost_bath_kernel(AmrBuffers<S> B, const GhostCopy *Cp, int nc,
+                                  const GhostInterp *In, int ni)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < nc) {
+        const GhostCopy r = Cp[k];
+        const PatchInfo D = B.patches[r.dp], Sp = B.patches[r.sp];
+        B.bath[D.coff + r.dl] = B.bath[Sp.coff + r.sl];
+    } else if (k < nc + ni) {
+        const GhostInterp r = In[k - nc];
+        const PatchInfo D = B.patches[r.dp], C = B.patches[r.cp[0]];
+        B.bath[D.coff + r.dl] = B.bath[C.coff + r.cl[0]];
+    }
+}
+
+// mean of the 4 x 4 fine cells (rows outer, columns inner)
+template <class S>
+__global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath_only)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const AvgRec r = R[k];
+    const PatchInfo F = B.patches[r.fp], C = B.patches[r.cp];
+    if (bath_only) {
+        double s = 0.0;
+        for (int a = 0; a < AMR_RATIO; a++)
+            for (int c = 0; c < AMR_RATIO; c++) s += (double)B.bath[F.coff + r.fl + a * F.pitch + c];
+        B.bath[C.coff + r.cl] = (S)(s * 0.0625);
+        return;
+    }
+    if (scen_failed(B.scen, C.scen) || scen_failed(B.scen, F.scen)) return;
+    const S *qf = B.scen[F.scen].cur ? B.q1 : B.q0;
+    S *qc = B.scen[C.scen].cur ? B.q1 : B.q0;
+    for (int m = 0; m < 7; m++) {
+        double s = 0.0;
+        for (int a = 0; a < AMR_RATIO; a++)
+            for (int c = 0; c < AMR_RATIO; c++)
+                s += (double)qf[F.qoff + m * F.plane + r.fl + a * F.pitch + c];
+        qc[C.qoff + m * C.plane + r.cl] = (S)(s * 0.0625);
+    }
+}
+
+// one cell of the old state of a patch (the buffer the last step read), after
+// its first source half step, as an edge side in direction DIR
+template <int DIR, class S, bool MIXED>
+__device__ void old_side(const AmrBuffers<S> &B, const StepParams &P, const PatchInfo &pi, int l,
+                         Side<double> &sd)
+{
+    const ScenState &st = B.scen[pi.scen];
+    const S *q = st.cur ? B.q0 : B.q1;            // after the swap: the other buffer
+    const uint8_t *mk = st.cur ? B.m0 : B.m1;
+    RawCell<double> raw;
+    for (int m = 0; m < 7; m++) raw.q[m] = (double)q[pi.qoff + m * pi.plane + l];
+    raw.b = (double)B.bath[pi.coff + l];
+    raw.mk = mk[pi.coff + l];
+    Cell<double> c;
+    int phi, brk;
+    prepare_cell<double, MIXED>(P, raw, 0.5 * st.dt, c, phi, brk);
+    side_of<DIR>(c, sd);
+}
+
+template <int DIR, class S, bool MIXED>
+__device__ void edge_dflux(const AmrBuffers<S> &B, const StepParams &P, const FluxRec &r,
+                           double D[7])
+{
+    const PatchInfo F = B.patches[r.fp], C = B.patches[r.cp];
+    Side<double> sc, sg;
+    old_side<DIR, S, MIXED>(B, P, C, r.cl, sc);
+    old_side<DIR, S, MIXED>(B, P, F, r.gl, sg);
+    Waves<double> W;
+    Eig<double> E;
+    double am[7], ap[7];
+    if (r.low) {
+        riemann<DIR>(P, sc, sg, W, E);
+        fluctuations<DIR>(W, am, ap);
+        for (int m = 0; m < 7; m++) D[m] = am[m] + ap[m];
+    } else {
+        riemann<DIR>(P, sg, sc, W, E);
+        fluctuations<DIR>(W, am, ap);
+        for (int m = 0; m < 7; m++) D[m] = -(am[m] + ap[m]);
+    }
+}
+
+template <class S, bool MIXED>
+__global__ void bflux_kernel(AmrBuffers<S> B, StepParams P, const FluxRec *R, int n,
+                             const double *E, double *Rg)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const FluxRec r = R[k];
+    const PatchInfo F = B.patches[r.fp];
+    if (scen_failed(B.scen, F.scen)) return;
+    double D[7];
+    if (r.dir == 0) edge_dflux<0, S, MIXED>(B, P, r, D);
+    else edge_dflux<1, S, MIXED>(B, P, r, D);
+    const long long e = (F.eoff + r.entry) * 7;
+    for (int m = 0; m < 7; m++) Rg[e + m] = Rg[e + m] + (E[e + m] + D[m]);
+}
+
+template <class S, bool MIXED>
+__global__ void reflux_kernel(AmrBuffers<S> B, StepParams P, const RefluxRec *R, int n,
+                              const double *Rg, double *rclip)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const RefluxRec r = R[k];
+    const PatchInfo C = B.patches[r.cp];
+    if (scen_failed(B.scen, C.scen)) return;
+    const ScenState &st = B.scen[C.scen];
+    S *q = st.cur ? B.q1 : B.q0;
+    const uint8_t mk = (st.cur ? B.m1 : B.m0)[C.coff + r.cl];
+    const double b = (double)B.bath[C.coff + r.cl];
+    double v[7];
+    for (int m = 0; m < 7; m++) v[m] = (double)q[C.qoff + m * C.plane + r.cl];
+    if (MIXED) v[0] = (v[0] + P.eta0) - b;
+    const double dtdx = st.dt / C.dx, dtdy = st.dt / C.dy;
+    for (int e = 0; e < 4; e++) {
+        if (r.fp[e] < 0) continue;
+        const PatchInfo F = B.patches[r.fp[e]];
+        const double *Rf = Rg + (F.eoff + r.e0[e]) * 7;
+        const double dtd = e < 2 ? dtdx : dtdy;
+        for (int m = 0; m < 7; m++) {
+            double s = ((Rf[m] + Rf[7 + m]) + Rf[14 + m]) + Rf[21 + m];
+            double corr = dtd * (s * 0.0625);
+            // fine patch to the left / below: the cell lies above the edge
+            v[m] = (e == 0 || e == 2) ? v[m] + corr : v[m] - corr;
+        }
+    }
+    double clip = 0.0;
+    if (v[0] < 0.0) {
+        clip = -v[0] * C.dx * C.dy;
+        v[0] = 0.0;
+    }
+    if (v[0] <= P.dry_tol)
+        for (int m = 1; m < 7; m++) v[m] = 0.0;
+    const int phi = mk & 1, brk = (mk >> 1) & 1;
+    if (!phi || brk || v[0] <= P.dry_tol) {
+        v[IHW] = 0.0; v[IHS] = 0.0; v[IHP] = 0.0; v[IHPB] = 0.0;
+    }
+    rclip[k] += clip;
+    if (MIXED) v[0] = (v[0] + b) - P.eta0;
+    for (int m = 0; m < 7; m++) q[C.qoff + m * C.plane + r.cl] = (S)v[m];
+}
+
+__global__ void iface_kernel(const PatchInfo *patches, const RefluxRec *R, int n, uint8_t *m0,
+                             uint8_t *m1)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const RefluxRec r = R[k];
+    const PatchInfo C = patches[r.cp];
+    int bits = 0;
+    for (int e = 0; e < 4; e++)
+        if (r.fp[e] >= 0) bits |= 1 << e;
+    long long i = C.coff + r.cl;
+    m0[i] = (uint8_t)((m0[i] & 3) | (bits << 2));
+    m1[i] = (uint8_t)((m1[i] & 3) | (bits << 2));
+}
+
+__global__ void fill_zero_kernel(double *p, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+void launch_halo_copy64(const AmrBuffers<double> &B, const GhostCopy *r, int n, hipStream_t s)
+{
+    if (n > 0) halo_copy_kernel<double><<<blocks(n), TPB, 0, s>>>(B, r, n);
+}
+void launch_halo_copy32(const AmrBuffers<float> &B, const GhostCopy *r, int n, hipStream_t s)
+{
+    if (n > 0) halo_copy_kernel<float><<<blocks(n), TPB, 0, s>>>(B, r, n);
+}
+void launch_halo_interp64(const AmrBuffers<double> &B, const GhostInterp *r, int n, double theta,
+                          double eta0, double dry_tol, hipStream_t s)
+{
+    if (n > 0)
+        halo_interp_kernel<double, false><<<blocks(n), TPB, 0, s>>>(B, r, n, theta, eta0, dry_tol);
+}
+void launch_halo_interp32(const AmrBuffers<float> &B, const GhostInterp *r, int n, double theta,
+                          double eta0, double dry_tol, hipStream_t s)
+{
+    if (n > 0)
+        halo_interp_kernel<float, true><<<blocks(n), TPB, 0, s>>>(B, r, n, theta, eta0, dry_tol);
+}
+void launch_ghost_bath64(const AmrBuffers<double> &B, const GhostCopy *c, int nc,
+                         const GhostInterp *r, int ni, hipStream_t s)
+{
+    if (nc + ni > 0) ghost_bath_kernel<double><<<blocks(nc + ni), TPB, 0, s>>>(B, c, nc, r, ni);
+}
+void launch_ghost_bath32(const AmrBuffers<float> &B, const GhostCopy *c, int nc,
+                         const GhostInterp *r, int ni, hipStream_t s)
+{
+    if (nc + ni > 0) ghost_bath_kernel<float><<<blocks(nc + ni), TPB, 0, s>>>(B, c, nc, r, ni);
+}
+void launch_avgdown64(const AmrBuffers<double> &B, const AvgRec *r, int n, bool bath_only,
+                      hipStream_t s)
+{
+    if (n > 0) avgdown_kernel<double><<<blocks(n), TPB, 0, s>>>(B, r, n, bath_only ? 1 : 0);
+}
+void launch_avgdown32(const AmrBuffers<float> &B, const AvgRec *r, int n, bool bath_only,
+                      hipStream_t s)
+{
+    if (n > 0) avgdown_kernel<float><<<blocks(n), TPB, 0, s>>>(B, r, n, bath_only ? 1 : 0);
+}
+void launch_bflux64(const AmrBuffers<double> &B, const StepParams &P, const FluxRec *r, int n,
+                    const double *E, double *R, hipStream_t s)
+{
+    if (n > 0) bflux_kernel<double, false><<<blocks(n), TPB, 0, s>>>(B, P, r, n, E, R);
+}
+void launch_bflux32(const AmrBuffers<float> &B, const StepParams &P, const FluxRec *r, int n,
+                    const double *E, double *R, hipStream_t s)
+{
+    if (n > 0) bflux_kernel<float, true><<<blocks(n), TPB, 0, s>>>(B, P, r, n, E, R);
+}
+void launch_reflux64(const AmrBuffers<double> &B, const StepParams &P, const RefluxRec *r, int n,
+                     const double *R, double *rclip, hipStream_t s)
+{
+    if (n > 0) reflux_kernel<double, false><<<blocks(n), TPB, 0, s>>>(B, P, r, n, R, rclip);
+}
+void launch_reflux32(const AmrBuffers<float> &B, const StepParams &P, const RefluxRec *r, int n,
+                     const double *R, double *rclip, hipStream_t s)
+{
+    if (n > 0) reflux_kernel<float, true><<<blocks(n), TPB, 0, s>>>(B, P, r, n, R, rclip);
+}
+void launch_iface(const PatchInfo *patches, const RefluxRec *r, int n, uint8_t *m0, uint8_t *m1,
+                  hipStream_t s)
+{
+    if (n > 0) iface_kernel<<<blocks(n), TPB, 0, s>>>(patches, r, n, m0, m1);
+}
+void launch_fill_zero(double *p, long long n, hipStream_t s)
+{
+    if (n > 0) fill_zero_kernel<<<blocks(n), TPB, 0, s>>>(p, n);
+}
+
+}  // namespace hsgn

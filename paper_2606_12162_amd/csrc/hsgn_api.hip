@@ -23,7 +23,10 @@
 #include <string>
 #include <vector>
 
+#include <map>
+
 #include "hsgn.h"
+#include "hsgn_amr.hpp"
 #include "hsgn_march.hpp"
 
 using namespace hsgn;
@@ -35,6 +38,9 @@ using namespace hsgn;
 // floating-point contraction (hsgn_step64.hip: none, hsgn_step32.hip: FMA)
 void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
 void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
+// instantiations for patches of patch sets (hsgn_step64amr.hip, hsgn_step32amr.hip)
+void launch_march64_amr(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
+void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
 
 struct ScenStatic {
     double dx, dy, cfl, cfl_max;
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(256) void control_kernel(ScenState *S, const ScenSt
 
 struct GaugeDev {
     int scen, slot, ng;
-    int pad;
+    int qscen;                                    // slot whose buffer index the patch uses
     long long qoff, plane, c00, c01, c10, c11;   // cell offsets (bathymetry space)
     double wx, wy;
     long long roff;                               // record area offset
@@ -112,7 +118,7 @@ __global__ void gauge_kernel(const GaugeDev *G, int n, const ScenState *Sc, cons
     if (!st.accepted) return;
     long long r = st.records - 1;
     if (r < 0 || r >= g.cap) return;
-    const S *q = st.cur ? q1 : q0;
+    const S *q = Sc[g.qscen].cur ? q1 : q0;
     long long cells[4] = {g.c00, g.c01, g.c10, g.c11};
     double e[4];
     for (int a = 0; a < 4; a++) {
@@ -143,8 +149,9 @@ __global__ void mask_kernel(PatchInfo pi, const S *bath, uint8_t *m0, uint8_t *m
     for (int dj = -n; dj <= n; dj++) {
         for (int di = -n; di <= n; di++) {
             int fx, fy;
-            int mx = map_index(x + di, pi.nx, pi.bc[0], pi.bc[1], &fx);
-            int my = map_index(y + dj, pi.ny, pi.bc[2], pi.bc[3], &fy);
+            // stored ghost cells (patch sets) or the boundary map
+            int mx = pi.frame ? x + di : map_index(x + di, pi.nx, pi.bc[0], pi.bc[1], &fx);
+            int my = pi.frame ? y + dj : map_index(y + dj, pi.ny, pi.bc[2], pi.bc[3], &fy);
             double H = eta0 - (double)bath[pi.coff + (long long)my * pi.pitch + mx];
             H = H > 0.0 ? H : 0.0;
             hmin = H < hmin ? H : hmin;
@@ -166,7 +173,7 @@ __global__ void initdt_kernel(PatchInfo pi, StepParams P, const S *q, const S *b
     if (i < ncell) {
         int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
         long long idx = (long long)y * pi.pitch + x;
-        long long plane = (long long)pi.ny * pi.pitch;
+        long long plane = pi.plane;
         double b = (double)bath[pi.coff + idx];
         double h = (double)q[pi.qoff + idx];
         if (MIXED) h = h + P.eta0 - b;
@@ -238,9 +245,11 @@ __global__ void count_kernel(PatchInfo pi, const uint8_t *mask, unsigned long lo
     if ((mk >> 1) & 1) atomicAdd(&cnt[1], 1ull);
 }
 
-// conversion between the ABI layout (FP64, plane 0 = h) and FP32 storage
-// (plane 0 = eta' = h + b - eta0)
-__global__ void to_storage_kernel(PatchInfo pi, const double *in, float *q, const float *bath,
+// conversion between the ABI layout (FP64 q[7][ny][nx], plane 0 = h) and the
+// stored one (FP64 with plane 0 = h, or FP32 with plane 0 = eta' = h + b -
+// eta0; rows of pitch elements, possibly inside a ghost frame)
+template <class S, bool MIXED>
+__global__ void to_storage_kernel(PatchInfo pi, const double *in, S *q, const S *bath,
                                   double eta0)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -248,13 +257,13 @@ __global__ void to_storage_kernel(PatchInfo pi, const double *in, float *q, cons
     if (i >= ncell) return;
     int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
     long long idx = (long long)y * pi.pitch + x;
-    long long plane = (long long)pi.ny * pi.pitch;
     double b = (double)bath[pi.coff + idx];
-    q[pi.qoff + idx] = (float)(in[i] + b - eta0);
-    for (int m = 1; m < 7; m++) q[pi.qoff + m * plane + idx] = (float)in[m * ncell + i];
+    q[pi.qoff + idx] = MIXED ? (S)(in[i] + b - eta0) : (S)in[i];
+    for (int m = 1; m < 7; m++) q[pi.qoff + m * pi.plane + idx] = (S)in[m * ncell + i];
 }
 
-__global__ void from_storage_kernel(PatchInfo pi, const float *q, const float *bath, double eta0,
+template <class S, bool MIXED>
+__global__ void from_storage_kernel(PatchInfo pi, const S *q, const S *bath, double eta0,
                                     double *out)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,11 +271,38 @@ __global__ void from_storage_kernel(PatchInfo pi, const float *q, const float *b
     if (i >= ncell) return;
     int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
     long long idx = (long long)y * pi.pitch + x;
-    long long plane = (long long)pi.ny * pi.pitch;
-    double b = (double)bath[pi.coff + idx];
-    double h = (double)q[pi.qoff + idx] + eta0 - b;
-    out[i] = h > 0.0 ? h : 0.0;
-    for (int m = 1; m < 7; m++) out[m * ncell + i] = (double)q[pi.qoff + m * plane + idx];
+    if (MIXED) {
+        double b = (double)bath[pi.coff + idx];
+        double h = (double)q[pi.qoff + idx] + eta0 - b;
+        out[i] = h > 0.0 ? h : 0.0;
+    } else {
+        out[i] = (double)q[pi.qoff + idx];
+    }
+    for (int m = 1; m < 7; m++) out[m * ncell + i] = (double)q[pi.qoff + m * pi.plane + idx];
+}
+
+// one cell plane (bathymetry or mask) between the ABI layout and storage
+template <class A, class S>
+__global__ void scatter_plane_kernel(PatchInfo pi, const A *in, S *out, int keep_high_bits)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long ncell = (long long)pi.nx * pi.ny;
+    if (i >= ncell) return;
+    int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
+    long long idx = pi.coff + (long long)y * pi.pitch + x;
+    if (keep_high_bits) out[idx] = (S)(((int)out[idx] & ~3) | ((int)in[i] & 3));
+    else out[idx] = (S)in[i];
+}
+
+template <class S, class A>
+__global__ void gather_plane_kernel(PatchInfo pi, const S *in, A *out, int low_bits_only)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long ncell = (long long)pi.nx * pi.ny;
+    if (i >= ncell) return;
+    int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
+    S v = in[pi.coff + (long long)y * pi.pitch + x];
+    out[i] = low_bits_only ? (A)((int)v & 3) : (A)v;
 }
 
 __global__ void to_float_kernel(const double *in, float *out, long long n)
@@ -279,10 +315,28 @@ __global__ void to_float_kernel(const double *in, float *out, long long n)
 // host side
 
 struct ScenHost {
-    std::vector<int> patches;
+    std::vector<int> patches;              // every patch of the scenario, in add order
+    std::vector<std::vector<int>> lev;     // patch ids per refinement level
+    std::vector<int> slot;                 // clock slot of each level (slot[0] = scenario)
+    bool amr = false;                      // more than one patch: a patch set
+    int NX = 0, NY = 0;                    // level-0 domain size in cells (patch sets)
+    double X0 = 0.0, Y0 = 0.0;             // domain corner
+    int bc[4] = {0, 0, 0, 0};              // domain boundary conditions (patch sets)
     std::vector<double> gauge_xy;
     long long gcap = 0, roff = 0;
     int ng = 0;
+};
+
+// table ranges of one refinement level
+struct LevelRange {
+    int w0 = 0, w1 = 0, wa = 0;     // work items [w0, w1); [w0, wa) single-grid, [wa, w1) patch sets
+    int s0 = 0, s1 = 0;             // clock slots
+    int gc0 = 0, gc1 = 0;           // ghost copies
+    int gi0 = 0, gi1 = 0;           // ghost interpolations
+    int fr0 = 0, fr1 = 0;           // boundary-flux records (this level as the fine one)
+    int rf0 = 0, rf1 = 0;           // reflux records (this level as the coarse one)
+    int av0 = 0, av1 = 0;           // average-down records (this level as the fine one)
+    long long e0 = 0, e1 = 0;       // boundary-flux entries (7-vectors)
 };
 
 struct hsgn_ctx {
@@ -292,9 +346,13 @@ struct hsgn_ctx {
     bool finalized = false;
     std::vector<PatchInfo> patches;
     std::vector<double> px0, py0;
+    std::vector<int> pI0, pJ0;             // patch origin in cells of its level (patch sets)
     std::vector<ScenHost> scen;
     std::vector<WorkItem> work;
     std::vector<ScenStatic> sstat;
+    int nslot = 0, nlev = 1;
+    bool any_amr = false;
+    std::vector<LevelRange> L;
     bool mixed = false;         // FP32 eta' storage with FP64 near-shore edges
     // device (FP64 storage: q0, q1, bath; mixed storage: f0, f1, fbath)
     double *q0 = nullptr, *q1 = nullptr, *bath = nullptr, *clip = nullptr, *rec = nullptr;
@@ -308,10 +366,28 @@ struct hsgn_ctx {
     ScenStatic *d_sstat = nullptr;
     GaugeDev *d_gauges = nullptr;
     unsigned long long *d_slots = nullptr;
+    unsigned long long *d_cnt = nullptr;
     int *d_err = nullptr;
     double *d_mass = nullptr;
     int ngauge_total = 0;
     long long qtotal = 0, ctotal = 0, rec_total = 0;
+    // patch sets
+    std::vector<GhostCopy> h_gc;
+    std::vector<GhostInterp> h_gi;
+    std::vector<FluxRec> h_fr;
+    std::vector<RefluxRec> h_rf;
+    std::vector<AvgRec> h_av;
+    GhostCopy *d_gc = nullptr;
+    GhostInterp *d_gi = nullptr;
+    FluxRec *d_fr = nullptr;
+    RefluxRec *d_rf = nullptr;
+    AvgRec *d_av = nullptr;
+    double *d_E = nullptr, *d_R = nullptr, *d_rclip = nullptr;
+    long long etotal = 0;
+    bool amr_dirty = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false, graph_failed = false;
     std::string last_error;
     // optional step-kernel timing
     bool timing = false;
@@ -341,35 +417,329 @@ static void free_events(hsgn_ctx *c)
     c->ev_used = 0;
 }
 
+static void drop_graph(hsgn_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->graph_valid = false;
+}
+
 static void free_device(hsgn_ctx *c)
 {
     free_events(c);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     void *ptrs[] = {c->q0, c->q1, c->bath, c->clip, c->rec, c->m0, c->m1, c->d_patches,
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
-                    c->d_mass, c->f0, c->f1, c->fbath, c->stage};
+                    c->d_mass, c->f0, c->f1, c->fbath, c->stage, c->d_cnt, c->d_gc, c->d_gi,
+                    c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c->q0 = c->q1 = c->bath = c->clip = c->rec = c->d_mass = c->stage = nullptr;
     c->f0 = c->f1 = c->fbath = nullptr;
     c->m0 = c->m1 = nullptr;
     c->d_patches = nullptr; c->d_work = nullptr; c->d_scen = nullptr; c->d_sstat = nullptr;
-    c->d_gauges = nullptr; c->d_slots = nullptr; c->d_err = nullptr;
+    c->d_gauges = nullptr; c->d_slots = nullptr; c->d_err = nullptr; c->d_cnt = nullptr;
+    c->d_gc = nullptr; c->d_gi = nullptr; c->d_fr = nullptr; c->d_rf = nullptr; c->d_av = nullptr;
+    c->d_E = c->d_R = c->d_rclip = nullptr;
 }
 
 template <class S>
-static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath)
+static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath, int w0, int w1)
 {
     MarchArgs<S> A;
     A.P = c->P;
     A.patches = c->d_patches;
-    A.work = c->d_work;
+    A.work = c->d_work + w0;
     A.q0 = q0; A.q1 = q1;
     A.bath = bath;
     A.m0 = c->m0; A.m1 = c->m1;
     A.scen = c->d_scen;
-    A.clip_slots = c->clip;
-    A.nwork = (int)c->work.size();
+    A.clip_slots = c->clip + w0;
+    A.eflux = c->d_E;
+    A.nwork = w1 - w0;
     return A;
+}
+
+template <class S>
+static AmrBuffers<S> amr_buffers(hsgn_ctx *c, S *q0, S *q1, S *bath)
+{
+    AmrBuffers<S> B;
+    B.patches = c->d_patches;
+    B.scen = c->d_scen;
+    B.q0 = q0; B.q1 = q1;
+    B.bath = bath;
+    B.m0 = c->m0; B.m1 = c->m1;
+    return B;
+}
+
+// ---------------------------------------------------------------------------
+// patch-set geometry: which patch of a level covers a cell
+
+struct LevelIndex {
+    static constexpr int BS = 64;                     // bucket side in cells
+    std::map<long long, std::vector<int>> buckets;
+    const hsgn_ctx *c = nullptr;
+    static long long key(long long bi, long long bj) { return (bi + (1LL << 30)) * (1LL << 31) + bj + (1LL << 30); }
+    static long long fdiv(long long a, long long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+    void add(int pid)
+    {
+        const PatchInfo &p = c->patches[pid];
+        long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
+        for (long long bj = fdiv(J0, BS); bj <= fdiv(J0 + p.ny - 1, BS); bj++)
+            for (long long bi = fdiv(I0, BS); bi <= fdiv(I0 + p.nx - 1, BS); bi++)
+                buckets[key(bi, bj)].push_back(pid);
+    }
+    int find(long long I, long long J) const
+    {
+        auto it = buckets.find(key(fdiv(I, BS), fdiv(J, BS)));
+        if (it == buckets.end()) return -1;
+        for (int pid : it->second) {
+            const PatchInfo &p = c->patches[pid];
+            long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
+            if (I >= I0 && I < I0 + p.nx && J >= J0 && J < J0 + p.ny) return pid;
+        }
+        return -1;
+    }
+};
+
+static int host_map(int i, int n, int lo, int hi, int *flip)
+{
+    *flip = 0;
+    if (i < 0) {
+        if (lo == HSGN_BC_PERIODIC) return i + n;
+        if (lo == HSGN_BC_WALL) { *flip = 1; return -1 - i; }
+        return 0;
+    }
+    if (i >= n) {
+        if (hi == HSGN_BC_PERIODIC) return i - n;
+        if (hi == HSGN_BC_WALL) { *flip = 1; return 2 * n - 1 - i; }
+        return n - 1;
+    }
+    return i;
+}
+
+static int local_of(const PatchInfo &p, long long i, long long j) { return (int)(j * p.pitch + i); }
+
+// validate a patch set and build its tables (appended to the context's)
+static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<int>> &lev_gc,
+                           std::vector<std::vector<int>> &lev_gi, std::vector<std::vector<int>> &lev_fr,
+                           std::vector<std::vector<int>> &lev_rf, std::vector<std::vector<int>> &lev_av,
+                           std::vector<GhostCopy> &gc, std::vector<GhostInterp> &gi,
+                           std::vector<FluxRec> &fr, std::vector<RefluxRec> &rf,
+                           std::vector<AvgRec> &av)
+{
+    ScenHost &sh = c->scen[s];
+    const int nl = (int)sh.lev.size();
+    std::vector<LevelIndex> idx(nl);
+    for (int l = 0; l < nl; l++) {
+        idx[l].c = c;
+        for (int pid : sh.lev[l]) idx[l].add(pid);
+    }
+    // no two patches of a level overlap
+    for (int l = 0; l < nl; l++)
+        for (int pid : sh.lev[l]) {
+            const PatchInfo &p = c->patches[pid];
+            for (int q : sh.lev[l]) {
+                if (q <= pid) continue;
+                const PatchInfo &o = c->patches[q];
+                bool ov = c->pI0[pid] < c->pI0[q] + o.nx && c->pI0[q] < c->pI0[pid] + p.nx &&
+                          c->pJ0[pid] < c->pJ0[q] + o.ny && c->pJ0[q] < c->pJ0[pid] + p.ny;
+                if (ov) return fail(c, HSGN_EINVAL, "patches of one level overlap");
+            }
+        }
+    long long area = 0;
+    for (int pid : sh.lev[0]) area += (long long)c->patches[pid].nx * c->patches[pid].ny;
+    if (area != (long long)sh.NX * sh.NY)
+        return fail(c, HSGN_EINVAL, "level-0 patches must tile a rectangle");
+    // finer patches stay one coarser cell away from the domain boundary
+    for (int l = 1; l < nl; l++) {
+        long long NXl = (long long)sh.NX, NYl = (long long)sh.NY;
+        for (int k = 0; k < l; k++) { NXl *= AMR_RATIO; NYl *= AMR_RATIO; }
+        for (int pid : sh.lev[l]) {
+            const PatchInfo &p = c->patches[pid];
+            if (c->pI0[pid] < AMR_RATIO || c->pJ0[pid] < AMR_RATIO ||
+                c->pI0[pid] + p.nx > NXl - AMR_RATIO || c->pJ0[pid] + p.ny > NYl - AMR_RATIO)
+                return fail(c, HSGN_EINVAL, "a refined patch touches the domain boundary");
+        }
+    }
+    auto covered = [&](int l, long long I, long long J) {
+        return l + 1 < nl && idx[l + 1].find(AMR_RATIO * I, AMR_RATIO * J) >= 0;
+    };
+    for (int l = 0; l < nl; l++) {
+        for (int pid : sh.lev[l]) {
+            const PatchInfo &P = c->patches[pid];
+            const long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
+            // ghost cells
+            for (int j = -2; j < P.ny + 2; j++)
+                for (int i = -2; i < P.nx + 2; i++) {
+                    if (i >= 0 && i < P.nx && j >= 0 && j < P.ny) continue;
+                    long long I = I0 + i, J = J0 + j;
+                    if (l == 0) {
+                        int fx, fy;
+                        int mi = host_map((int)I, sh.NX, sh.bc[0], sh.bc[1], &fx);
+                        int mj = host_map((int)J, sh.NY, sh.bc[2], sh.bc[3], &fy);
+                        int sp = idx[0].find(mi, mj);
+                        if (sp < 0) return fail(c, HSGN_EINVAL, "level-0 patches leave a hole");
+                        lev_gc[l].push_back((int)gc.size());
+                        gc.push_back({pid, local_of(P, i, j), sp,
+                                      local_of(c->patches[sp], mi - c->pI0[sp], mj - c->pJ0[sp]),
+                                      fx | (fy << 1)});
+                        continue;
+                    }
+                    int sp = idx[l].find(I, J);
+                    if (sp >= 0) {
+                        lev_gc[l].push_back((int)gc.size());
+                        gc.push_back({pid, local_of(P, i, j), sp,
+                                      local_of(c->patches[sp], I - c->pI0[sp], J - c->pJ0[sp]), 0});
+                        continue;
+                    }
+                    long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
+                    GhostInterp g;
+                    g.dp = pid;
+                    g.dl = local_of(P, i, j);
+                    const long long nb[5][2] = {{Ic, Jc}, {Ic - 1, Jc}, {Ic + 1, Jc}, {Ic, Jc - 1}, {Ic, Jc + 1}};
+                    for (int k = 0; k < 5; k++) {
+                        int cp = idx[l - 1].find(nb[k][0], nb[k][1]);
+                        g.cp[k] = cp;
+                        g.cl[k] = cp >= 0 ? local_of(c->patches[cp], nb[k][0] - c->pI0[cp],
+                                                     nb[k][1] - c->pJ0[cp]) : 0;
+                    }
+                    if (g.cp[0] < 0) return fail(c, HSGN_EINVAL, "refined patch not properly nested");
+                    g.ox = (float)(((double)(I - AMR_RATIO * Ic) + 0.5) / AMR_RATIO - 0.5);
+                    g.oy = (float)(((double)(J - AMR_RATIO * Jc) + 0.5) / AMR_RATIO - 0.5);
+                    lev_gi[l].push_back((int)gi.size());
+                    gi.push_back(g);
+                }
+            if (l == 0) continue;
+            // boundary edges facing the coarser level: left, right, bottom, top
+            for (int side = 0; side < 4; side++) {
+                int len = side < 2 ? P.ny : P.nx;
+                for (int k = 0; k < len; k++) {
+                    int gi_ = side == 0 ? -1 : side == 1 ? P.nx : k;
+                    int gj_ = side < 2 ? k : side == 2 ? -1 : P.ny;
+                    long long I = I0 + gi_, J = J0 + gj_;
+                    if (idx[l].find(I, J) >= 0) continue;
+                    long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
+                    int cp = idx[l - 1].find(Ic, Jc);
+                    if (cp < 0) return fail(c, HSGN_EINVAL, "refined patch not properly nested");
+                    int entry = side == 0 ? k : side == 1 ? P.ny + k : side == 2 ? 2 * P.ny + k
+                                                                                   : 2 * P.ny + P.nx + k;
+                    lev_fr[l].push_back((int)fr.size());
+                    fr.push_back({pid, entry, local_of(P, gi_, gj_), cp,
+                                  local_of(c->patches[cp], Ic - c->pI0[cp], Jc - c->pJ0[cp]),
+                                  side < 2 ? 0 : 1, (side == 0 || side == 2) ? 1 : 0});
+                }
+            }
+            // covered coarse cells
+            for (int jj = 0; jj < P.ny / AMR_RATIO; jj++)
+                for (int ii = 0; ii < P.nx / AMR_RATIO; ii++) {
+                    long long Ic = I0 / AMR_RATIO + ii, Jc = J0 / AMR_RATIO + jj;
+                    int cp = idx[l - 1].find(Ic, Jc);
+                    if (cp < 0) return fail(c, HSGN_EINVAL, "refined patch outside the coarser level");
+                    lev_av[l].push_back((int)av.size());
+                    av.push_back({pid, local_of(P, AMR_RATIO * ii, AMR_RATIO * jj), cp,
+                                  local_of(c->patches[cp], Ic - c->pI0[cp], Jc - c->pJ0[cp])});
+                }
+        }
+        // reflux records: uncovered level-l cells next to a level-(l+1) patch
+        if (l + 1 < nl) {
+            std::vector<std::pair<long long, long long>> cand;
+            for (int f : sh.lev[l + 1]) {
+                const PatchInfo &F = c->patches[f];
+                long long a0 = c->pI0[f] / AMR_RATIO, b0 = c->pJ0[f] / AMR_RATIO;
+                long long a1 = a0 + F.nx / AMR_RATIO, b1 = b0 + F.ny / AMR_RATIO;
+                for (long long J = b0; J < b1; J++) { cand.push_back({J, a0 - 1}); cand.push_back({J, a1}); }
+                for (long long I = a0; I < a1; I++) { cand.push_back({b0 - 1, I}); cand.push_back({b1, I}); }
+            }
+            std::sort(cand.begin(), cand.end());
+            cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            for (auto &jc : cand) {
+                long long J = jc.first, I = jc.second;
+                int cp = idx[l].find(I, J);
+                if (cp < 0 || covered(l, I, J)) continue;
+                RefluxRec r;
+                r.cp = cp;
+                r.cl = local_of(c->patches[cp], I - c->pI0[cp], J - c->pJ0[cp]);
+                const long long nb[4][2] = {{I - 1, J}, {I + 1, J}, {I, J - 1}, {I, J + 1}};
+                bool any = false;
+                for (int e = 0; e < 4; e++) {
+                    r.fp[e] = -1;
+                    r.e0[e] = 0;
+                    if (!covered(l, nb[e][0], nb[e][1])) continue;
+                    // a fine cell just across the edge
+                    long long fi = e == 0 ? AMR_RATIO * I - 1 : e == 1 ? AMR_RATIO * (I + 1) : AMR_RATIO * I;
+                    long long fj = e == 2 ? AMR_RATIO * J - 1 : e == 3 ? AMR_RATIO * (J + 1) : AMR_RATIO * J;
+                    int f = idx[l + 1].find(fi, fj);
+                    const PatchInfo &F = c->patches[f];
+                    long long fI0 = c->pI0[f], fJ0 = c->pJ0[f];
+                    r.fp[e] = f;
+                    r.e0[e] = e == 0 ? (int)(F.ny + AMR_RATIO * J - fJ0)
+                            : e == 1 ? (int)(AMR_RATIO * J - fJ0)
+                            : e == 2 ? (int)(2 * F.ny + F.nx + AMR_RATIO * I - fI0)
+                                     : (int)(2 * F.ny + AMR_RATIO * I - fI0);
+                    any = true;
+                }
+                if (any) {
+                    lev_rf[l].push_back((int)rf.size());
+                    rf.push_back(r);
+                }
+            }
+        }
+    }
+    return HSGN_OK;
+}
+
+// every table entry addresses cells inside its patch's storage (interior or
+// ghost frame as required) and entries inside the flux buffer: checked on
+// the host before any table reaches the device
+static bool local_ok(const hsgn_ctx *c, int pid, int local, bool interior)
+{
+    if (pid < 0 || pid >= (int)c->patches.size()) return false;
+    const PatchInfo &p = c->patches[pid];
+    long long base = (long long)local + (long long)p.frame * p.pitch + p.frame;
+    if (base < 0) return false;
+    long long i = base % p.pitch - p.frame, j = base / p.pitch - p.frame;
+    if (interior) return i >= 0 && i < p.nx && j >= 0 && j < p.ny;
+    return i >= -p.frame && i < p.nx + p.frame && j >= -p.frame && j < p.ny + p.frame &&
+           !(i >= 0 && i < p.nx && j >= 0 && j < p.ny);
+}
+
+static int validate_tables(hsgn_ctx *c)
+{
+    auto bad = [&](const char *what) { return fail(c, HSGN_EINVAL, std::string("internal table check: ") + what); };
+    for (const GhostCopy &r : c->h_gc)
+        if (!local_ok(c, r.dp, r.dl, false) || !local_ok(c, r.sp, r.sl, true)) return bad("ghost copy");
+    for (const GhostInterp &r : c->h_gi) {
+        if (!local_ok(c, r.dp, r.dl, false) || r.cp[0] < 0) return bad("ghost interpolation");
+        for (int k = 0; k < 5; k++)
+            if (r.cp[k] >= 0 && !local_ok(c, r.cp[k], r.cl[k], true)) return bad("ghost stencil");
+    }
+    for (const FluxRec &r : c->h_fr) {
+        if (!local_ok(c, r.fp, r.gl, false) || !local_ok(c, r.cp, r.cl, true)) return bad("flux record");
+        const PatchInfo &F = c->patches[r.fp];
+        if (F.eoff < 0 || r.entry < 0 || r.entry >= 2 * (F.nx + F.ny)) return bad("flux entry");
+    }
+    for (const RefluxRec &r : c->h_rf) {
+        if (!local_ok(c, r.cp, r.cl, true)) return bad("reflux cell");
+        for (int e = 0; e < 4; e++) {
+            if (r.fp[e] < 0) continue;
+            if (r.fp[e] >= (int)c->patches.size()) return bad("reflux patch");
+            const PatchInfo &F = c->patches[r.fp[e]];
+            int lo = e == 0 ? F.ny : e == 1 ? 0 : e == 2 ? 2 * F.ny + F.nx : 2 * F.ny;
+            int len = e < 2 ? F.ny : F.nx;
+            if (F.eoff < 0 || r.e0[e] < lo || r.e0[e] + AMR_RATIO > lo + len) return bad("reflux entry");
+        }
+    }
+    for (const AvgRec &r : c->h_av) {
+        if (!local_ok(c, r.cp, r.cl, true)) return bad("average-down cell");
+        const PatchInfo &F = c->patches[r.fp < 0 ? 0 : r.fp];
+        for (int a = 0; a < AMR_RATIO; a++)
+            for (int b = 0; b < AMR_RATIO; b++)
+                if (!local_ok(c, r.fp, r.fl + a * F.pitch + b, true)) return bad("average-down block");
+    }
+    return HSGN_OK;
 }
 
 extern "C" {
@@ -417,32 +787,33 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     return HSGN_OK;
 }
 
-int hsgn_add_grid(hsgn_ctx *c, int scenario, int nx, int ny, double x0, double y0, double dx,
-                  double dy, const int bc[4], int *patch_id)
+int hsgn_add_grid(hsgn_ctx *c, int scenario, int level, int nx, int ny, double x0, double y0,
+                  double dx, double dy, const int bc[4], int *patch_id)
 {
     if (!c) return HSGN_EINVAL;
     if (c->finalized) return fail(c, HSGN_EINVAL, "add_grid after finalize");
-    if (scenario < 0 || nx < 4 || ny < 4 || !(dx > 0) || !(dy > 0) || !bc)
+    if (scenario < 0 || level < 0 || level > 5 || nx < 4 || ny < 4 || !(dx > 0) || !(dy > 0) ||
+        !bc)
         return fail(c, HSGN_EINVAL, "bad grid arguments");
     for (int k = 0; k < 4; k++)
         if (bc[k] < 0 || bc[k] > 2) return fail(c, HSGN_EINVAL, "bad boundary condition");
     if ((bc[0] == HSGN_BC_PERIODIC) != (bc[1] == HSGN_BC_PERIODIC) ||
         (bc[2] == HSGN_BC_PERIODIC) != (bc[3] == HSGN_BC_PERIODIC))
         return fail(c, HSGN_EINVAL, "periodic sides must come in pairs");
+    if ((long long)(nx + 4) * (ny + 4) > (1LL << 30)) return fail(c, HSGN_EINVAL, "patch too large");
     if ((int)c->scen.size() <= scenario) c->scen.resize(scenario + 1);
-    if (!c->scen[scenario].patches.empty()) {
-        const PatchInfo &f = c->patches[c->scen[scenario].patches[0]];
-        if (f.dx != dx || f.dy != dy)
-            return fail(c, HSGN_EINVAL, "patches of one scenario share dx, dy");
-    }
     PatchInfo pi;
     memset(&pi, 0, sizeof(pi));
     pi.nx = nx; pi.ny = ny; pi.pitch = nx; pi.scen = scenario;
     for (int k = 0; k < 4; k++) pi.bc[k] = bc[k];
     pi.dx = dx; pi.dy = dy;
+    pi.level = level;
+    pi.eoff = -1;
     c->patches.push_back(pi);
     c->px0.push_back(x0);
     c->py0.push_back(y0);
+    c->pI0.push_back(0);
+    c->pJ0.push_back(0);
     int id = (int)c->patches.size() - 1;
     c->scen[scenario].patches.push_back(id);
     if (patch_id) *patch_id = id;
@@ -461,42 +832,207 @@ static int choose_rows(const hsgn_ctx *c)
     return th;
 }
 
+// geometry checks of the scenarios and level structure
+static int check_scenarios(hsgn_ctx *c)
+{
+    c->nlev = 1;
+    c->any_amr = false;
+    for (size_t s = 0; s < c->scen.size(); s++) {
+        ScenHost &sh = c->scen[s];
+        if (sh.patches.empty()) return fail(c, HSGN_EINVAL, "scenario numbers must be dense");
+        sh.amr = sh.patches.size() > 1;
+        int nl = 0;
+        for (int pid : sh.patches) nl = std::max(nl, c->patches[pid].level + 1);
+        sh.lev.assign(nl, std::vector<int>());
+        for (int pid : sh.patches) sh.lev[c->patches[pid].level].push_back(pid);
+        for (int l = 0; l < nl; l++)
+            if (sh.lev[l].empty()) return fail(c, HSGN_EINVAL, "refinement levels must be dense");
+        if (!sh.amr) continue;
+        c->any_amr = true;
+        c->nlev = std::max(c->nlev, nl);
+        const PatchInfo &f = c->patches[sh.lev[0][0]];
+        double dx0 = f.dx, dy0 = f.dy;
+        for (int k = 0; k < 4; k++) sh.bc[k] = f.bc[k];
+        sh.X0 = 1e300; sh.Y0 = 1e300;
+        for (int pid : sh.lev[0]) {
+            const PatchInfo &p = c->patches[pid];
+            if (p.dx != dx0 || p.dy != dy0) return fail(c, HSGN_EINVAL, "level-0 patches share dx, dy");
+            for (int k = 0; k < 4; k++)
+                if (p.bc[k] != sh.bc[k])
+                    return fail(c, HSGN_EINVAL, "level-0 patches share the domain boundary conditions");
+            sh.X0 = std::min(sh.X0, c->px0[pid]);
+            sh.Y0 = std::min(sh.Y0, c->py0[pid]);
+        }
+        sh.NX = 0; sh.NY = 0;
+        for (int pid : sh.patches) {
+            PatchInfo &p = c->patches[pid];
+            double r = std::pow((double)AMR_RATIO, p.level);
+            if (std::fabs(p.dx * r - dx0) > 1e-9 * dx0 || std::fabs(p.dy * r - dy0) > 1e-9 * dy0)
+                return fail(c, HSGN_EINVAL, "level-l spacing must be the level-0 spacing / 4^l");
+            double ux = p.level ? p.dx * AMR_RATIO : p.dx, uy = p.level ? p.dy * AMR_RATIO : p.dy;
+            double ax = (c->px0[pid] - sh.X0) / ux, ay = (c->py0[pid] - sh.Y0) / uy;
+            if (std::fabs(ax - std::round(ax)) > 1e-6 || std::fabs(ay - std::round(ay)) > 1e-6)
+                return fail(c, HSGN_EINVAL, "patch corner not aligned to the coarser level's cells");
+            if (p.level && (p.nx % AMR_RATIO || p.ny % AMR_RATIO))
+                return fail(c, HSGN_EINVAL, "refined patch sides must be multiples of 4");
+            long long k = p.level ? AMR_RATIO : 1;
+            c->pI0[pid] = (int)(std::llround(ax) * k);
+            c->pJ0[pid] = (int)(std::llround(ay) * k);
+            if (p.level == 0) {
+                sh.NX = std::max(sh.NX, c->pI0[pid] + p.nx);
+                sh.NY = std::max(sh.NY, c->pJ0[pid] + p.ny);
+            }
+        }
+        for (int pid : sh.lev[0])
+            if (c->pI0[pid] < 0 || c->pJ0[pid] < 0) return fail(c, HSGN_EINVAL, "bad level-0 layout");
+    }
+    return HSGN_OK;
+}
+
+}  // extern "C"
+
+template <class T>
+static int upload(hsgn_ctx *c, T **d, const std::vector<T> &h)
+{
+    if (h.empty()) return HSGN_OK;
+    HIPCHK(c, hipMalloc(d, sizeof(T) * h.size()));
+    HIPCHK(c, hipMemcpyAsync(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, c->stream));
+    return HSGN_OK;
+}
+
+extern "C" {
+
 int hsgn_finalize(hsgn_ctx *c)
 {
     if (!c) return HSGN_EINVAL;
     if (c->finalized) return fail(c, HSGN_EINVAL, "finalize called twice");
     if (c->patches.empty()) return fail(c, HSGN_EINVAL, "no patches");
-    for (size_t s = 0; s < c->scen.size(); s++)
-        if (c->scen[s].patches.empty()) return fail(c, HSGN_EINVAL, "scenario numbers must be dense");
+    int rc = check_scenarios(c);
+    if (rc) return rc;
+    const int nscen = (int)c->scen.size();
+    // storage: patch sets keep a 2-cell ghost frame
     long long qo = 0, co = 0;
-    for (PatchInfo &p : c->patches) {
-        long long cells = (long long)p.pitch * p.ny;
-        p.qoff = qo;
-        p.coff = co;
-        qo += 7 * cells;
-        co += cells;
-    }
+    for (size_t s = 0; s < c->scen.size(); s++)
+        for (int pid : c->scen[s].patches) {
+            PatchInfo &p = c->patches[pid];
+            p.frame = c->scen[s].amr ? 2 : 0;
+            p.pitch = p.nx + 2 * p.frame;
+            p.plane = (long long)p.pitch * (p.ny + 2 * p.frame);
+            long long org = (long long)p.frame * p.pitch + p.frame;
+            p.qoff = qo + org;
+            p.coff = co + org;
+            qo += 7 * p.plane;
+            co += p.plane;
+        }
     c->qtotal = qo;
     c->ctotal = co;
+    // clock slots: scenario s is slot s (its level 0); finer levels of patch
+    // sets follow, level by level
+    c->nslot = nscen;
+    std::vector<int> slot_level(nscen, 0), slot_scen(nscen);
+    for (int s = 0; s < nscen; s++) {
+        c->scen[s].slot.assign(c->scen[s].lev.size(), -1);
+        c->scen[s].slot[0] = s;
+        slot_scen[s] = s;
+    }
+    for (int l = 1; l < c->nlev; l++)
+        for (int s = 0; s < nscen; s++)
+            if ((int)c->scen[s].lev.size() > l) {
+                c->scen[s].slot[l] = c->nslot++;
+                slot_level.push_back(l);
+                slot_scen.push_back(s);
+            }
+    for (int s = 0; s < nscen; s++)
+        for (size_t l = 0; l < c->scen[s].lev.size(); l++)
+            for (int pid : c->scen[s].lev[l]) c->patches[pid].scen = c->scen[s].slot[l];
+    // boundary-flux entries of refined patches, level by level
+    c->L.assign(c->nlev, LevelRange());
+    c->etotal = 0;
+    for (int l = 1; l < c->nlev; l++) {
+        c->L[l].e0 = c->etotal;
+        for (int s = 0; s < nscen; s++)
+            if ((int)c->scen[s].lev.size() > l)
+                for (int pid : c->scen[s].lev[l]) {
+                    PatchInfo &p = c->patches[pid];
+                    p.eoff = c->etotal;
+                    c->etotal += 2LL * (p.nx + p.ny);
+                }
+        c->L[l].e1 = c->etotal;
+    }
+    // work items: slots in order; on level 0 single grids before patch sets
     int th = choose_rows(c);
     c->work.clear();
-    c->sstat.assign(c->scen.size(), ScenStatic());
-    for (size_t s = 0; s < c->scen.size(); s++) {
-        ScenStatic &ss = c->sstat[s];
-        ss.dx = c->patches[c->scen[s].patches[0]].dx;
-        ss.dy = c->patches[c->scen[s].patches[0]].dy;
+    c->sstat.assign(c->nslot, ScenStatic());
+    auto add_slot_work = [&](int slot) {
+        int s = slot_scen[slot], l = slot_level[slot];
+        ScenStatic &ss = c->sstat[slot];
+        const PatchInfo &p0 = c->patches[c->scen[s].lev[l][0]];
+        ss.dx = p0.dx;
+        ss.dy = p0.dy;
         ss.cfl = c->prm.cfl;
         ss.cfl_max = c->prm.cfl_max;
         ss.w0 = (int)c->work.size();
-        for (int pid : c->scen[s].patches) {
+        for (int pid : c->scen[s].lev[l]) {
             const PatchInfo &p = c->patches[pid];
             for (int r0 = 0; r0 < p.ny; r0 += th)
                 for (int i0 = 0; i0 < p.nx; i0 += 60)
                     c->work.push_back({pid, i0, r0, std::min(th, p.ny - r0)});
         }
         ss.w1 = (int)c->work.size();
+    };
+    c->L[0].w0 = 0;
+    c->L[0].s0 = 0;
+    c->L[0].s1 = nscen;
+    for (int s = 0; s < nscen; s++)
+        if (!c->scen[s].amr) add_slot_work(s);
+    c->L[0].wa = (int)c->work.size();
+    for (int s = 0; s < nscen; s++)
+        if (c->scen[s].amr) add_slot_work(s);
+    c->L[0].w1 = (int)c->work.size();
+    for (int l = 1; l < c->nlev; l++) {
+        c->L[l].w0 = c->L[l].wa = (int)c->work.size();
+        c->L[l].s0 = -1;
+        for (int slot = nscen; slot < c->nslot; slot++)
+            if (slot_level[slot] == l) {
+                if (c->L[l].s0 < 0) c->L[l].s0 = slot;
+                c->L[l].s1 = slot + 1;
+                add_slot_work(slot);
+            }
+        c->L[l].w1 = (int)c->work.size();
     }
-    size_t nscen = c->scen.size();
+    // patch-set tables, grouped by level
+    {
+        std::vector<std::vector<int>> lgc(c->nlev), lgi(c->nlev), lfr(c->nlev), lrf(c->nlev), lav(c->nlev);
+        std::vector<GhostCopy> gc;
+        std::vector<GhostInterp> gi;
+        std::vector<FluxRec> fr;
+        std::vector<RefluxRec> rf;
+        std::vector<AvgRec> av;
+        for (int s = 0; s < nscen; s++)
+            if (c->scen[s].amr &&
+                (rc = build_patch_set(c, s, lgc, lgi, lfr, lrf, lav, gc, gi, fr, rf, av)))
+                return rc;
+        c->h_gc.clear(); c->h_gi.clear(); c->h_fr.clear(); c->h_rf.clear(); c->h_av.clear();
+        for (int l = 0; l < c->nlev; l++) {
+            LevelRange &R = c->L[l];
+            R.gc0 = (int)c->h_gc.size();
+            for (int k : lgc[l]) c->h_gc.push_back(gc[k]);
+            R.gc1 = (int)c->h_gc.size();
+            R.gi0 = (int)c->h_gi.size();
+            for (int k : lgi[l]) c->h_gi.push_back(gi[k]);
+            R.gi1 = (int)c->h_gi.size();
+            R.fr0 = (int)c->h_fr.size();
+            for (int k : lfr[l]) c->h_fr.push_back(fr[k]);
+            R.fr1 = (int)c->h_fr.size();
+            R.rf0 = (int)c->h_rf.size();
+            for (int k : lrf[l]) c->h_rf.push_back(rf[k]);
+            R.rf1 = (int)c->h_rf.size();
+            R.av0 = (int)c->h_av.size();
+            for (int k : lav[l]) c->h_av.push_back(av[k]);
+            R.av1 = (int)c->h_av.size();
+        }
+    }
+    if ((rc = validate_tables(c))) return rc;
     if (c->mixed) {
         HIPCHK(c, hipMalloc(&c->f0, sizeof(float) * c->qtotal));
         HIPCHK(c, hipMalloc(&c->f1, sizeof(float) * c->qtotal));
@@ -504,10 +1040,6 @@ int hsgn_finalize(hsgn_ctx *c)
         HIPCHK(c, hipMemsetAsync(c->f0, 0, sizeof(float) * c->qtotal, c->stream));
         HIPCHK(c, hipMemsetAsync(c->f1, 0, sizeof(float) * c->qtotal, c->stream));
         HIPCHK(c, hipMemsetAsync(c->fbath, 0, sizeof(float) * c->ctotal, c->stream));
-        long long big = 0;
-        for (const PatchInfo &p : c->patches) big = std::max<long long>(big, 7LL * p.nx * p.ny);
-        c->stage_len = big;
-        HIPCHK(c, hipMalloc(&c->stage, sizeof(double) * big));
     } else {
         HIPCHK(c, hipMalloc(&c->q0, sizeof(double) * c->qtotal));
         HIPCHK(c, hipMalloc(&c->q1, sizeof(double) * c->qtotal));
@@ -516,37 +1048,58 @@ int hsgn_finalize(hsgn_ctx *c)
         HIPCHK(c, hipMemsetAsync(c->q1, 0, sizeof(double) * c->qtotal, c->stream));
         HIPCHK(c, hipMemsetAsync(c->bath, 0, sizeof(double) * c->ctotal, c->stream));
     }
+    long long big = 0;
+    for (const PatchInfo &p : c->patches) big = std::max<long long>(big, 7LL * p.nx * p.ny);
+    c->stage_len = big;
+    HIPCHK(c, hipMalloc(&c->stage, sizeof(double) * big));
     HIPCHK(c, hipMalloc(&c->m0, c->ctotal));
     HIPCHK(c, hipMalloc(&c->m1, c->ctotal));
-    HIPCHK(c, hipMalloc(&c->clip, sizeof(double) * c->work.size()));
+    HIPCHK(c, hipMalloc(&c->clip, sizeof(double) * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_patches, sizeof(PatchInfo) * c->patches.size()));
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(WorkItem) * c->work.size()));
-    HIPCHK(c, hipMalloc(&c->d_scen, sizeof(ScenState) * nscen));
-    HIPCHK(c, hipMalloc(&c->d_sstat, sizeof(ScenStatic) * nscen));
-    HIPCHK(c, hipMalloc(&c->d_slots, sizeof(unsigned long long) * nscen));
+    HIPCHK(c, hipMalloc(&c->d_scen, sizeof(ScenState) * c->nslot));
+    HIPCHK(c, hipMalloc(&c->d_sstat, sizeof(ScenStatic) * c->nslot));
+    HIPCHK(c, hipMalloc(&c->d_slots, sizeof(unsigned long long) * c->nslot));
+    HIPCHK(c, hipMalloc(&c->d_cnt, sizeof(unsigned long long) * 2));
     HIPCHK(c, hipMalloc(&c->d_err, sizeof(int)));
     HIPCHK(c, hipMalloc(&c->d_mass, sizeof(double) * 2));
     HIPCHK(c, hipMemsetAsync(c->m0, 0, c->ctotal, c->stream));
     HIPCHK(c, hipMemsetAsync(c->m1, 0, c->ctotal, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * c->work.size(), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * std::max<size_t>(c->work.size(), 1),
+                             c->stream));
+    if (c->etotal > 0) {
+        HIPCHK(c, hipMalloc(&c->d_E, sizeof(double) * 7 * c->etotal));
+        HIPCHK(c, hipMalloc(&c->d_R, sizeof(double) * 7 * c->etotal));
+        HIPCHK(c, hipMemsetAsync(c->d_E, 0, sizeof(double) * 7 * c->etotal, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->d_R, 0, sizeof(double) * 7 * c->etotal, c->stream));
+    }
+    if (!c->h_rf.empty()) {
+        HIPCHK(c, hipMalloc(&c->d_rclip, sizeof(double) * c->h_rf.size()));
+        HIPCHK(c, hipMemsetAsync(c->d_rclip, 0, sizeof(double) * c->h_rf.size(), c->stream));
+    }
+    if ((rc = upload(c, &c->d_gc, c->h_gc)) || (rc = upload(c, &c->d_gi, c->h_gi)) ||
+        (rc = upload(c, &c->d_fr, c->h_fr)) || (rc = upload(c, &c->d_rf, c->h_rf)) ||
+        (rc = upload(c, &c->d_av, c->h_av)))
+        return rc;
     HIPCHK(c, hipMemcpyAsync(c->d_patches, c->patches.data(), sizeof(PatchInfo) * c->patches.size(),
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_work, c->work.data(), sizeof(WorkItem) * c->work.size(),
                              hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_sstat, c->sstat.data(), sizeof(ScenStatic) * nscen,
+    HIPCHK(c, hipMemcpyAsync(c->d_sstat, c->sstat.data(), sizeof(ScenStatic) * c->nslot,
                              hipMemcpyHostToDevice, c->stream));
-    std::vector<ScenState> st(nscen);
-    memset(st.data(), 0, sizeof(ScenState) * nscen);
-    HIPCHK(c, hipMemcpyAsync(c->d_scen, st.data(), sizeof(ScenState) * nscen,
+    std::vector<ScenState> st(c->nslot);
+    memset(st.data(), 0, sizeof(ScenState) * c->nslot);
+    HIPCHK(c, hipMemcpyAsync(c->d_scen, st.data(), sizeof(ScenState) * c->nslot,
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->finalized = true;
+    c->amr_dirty = c->any_amr;
     return HSGN_OK;
 }
 
 static int pull_scen(hsgn_ctx *c, std::vector<ScenState> &st)
 {
-    st.resize(c->scen.size());
+    st.resize(c->nslot);
     HIPCHK(c, hipMemcpyAsync(st.data(), c->d_scen, sizeof(ScenState) * st.size(),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -578,26 +1131,78 @@ static hipMemcpyKind kind_out(int on_device)
     return on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
 }
 
+static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+// patch sets: coarse bathymetry under refined patches (mean of the fine one,
+// finest level first), ghost bathymetry, phi_T and the interface flags
+static int ensure_prepared(hsgn_ctx *c)
+{
+    if (!c->any_amr || !c->amr_dirty) return HSGN_OK;
+    for (int l = c->nlev - 1; l >= 1; l--) {
+        const LevelRange &R = c->L[l];
+        if (c->mixed)
+            launch_avgdown32(amr_buffers<float>(c, c->f0, c->f1, c->fbath), c->d_av + R.av0,
+                             R.av1 - R.av0, true, c->stream);
+        else
+            launch_avgdown64(amr_buffers<double>(c, c->q0, c->q1, c->bath), c->d_av + R.av0,
+                             R.av1 - R.av0, true, c->stream);
+    }
+    int nc = (int)c->h_gc.size(), ni = (int)c->h_gi.size();
+    if (c->mixed)
+        launch_ghost_bath32(amr_buffers<float>(c, c->f0, c->f1, c->fbath), c->d_gc, nc, c->d_gi, ni,
+                            c->stream);
+    else
+        launch_ghost_bath64(amr_buffers<double>(c, c->q0, c->q1, c->bath), c->d_gc, nc, c->d_gi, ni,
+                            c->stream);
+    for (size_t s = 0; s < c->scen.size(); s++) {
+        if (!c->scen[s].amr) continue;
+        for (int pid : c->scen[s].patches) {
+            const PatchInfo &p = c->patches[pid];
+            unsigned nb = nblk((long long)p.nx * p.ny);
+            if (c->mixed)
+                mask_kernel<float><<<nb, 256, 0, c->stream>>>(p, c->fbath, c->m0, c->m1, c->prm.eta0,
+                                                              c->prm.h_star, c->prm.nbr_n);
+            else
+                mask_kernel<double><<<nb, 256, 0, c->stream>>>(p, c->bath, c->m0, c->m1, c->prm.eta0,
+                                                               c->prm.h_star, c->prm.nbr_n);
+        }
+    }
+    launch_iface(c->d_patches, c->d_rf, (int)c->h_rf.size(), c->m0, c->m1, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->amr_dirty = false;
+    return HSGN_OK;
+}
+
 int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
 {
     int rc = check_patch(c, patch);
     if (rc) return rc;
     if (!b) return fail(c, HSGN_EINVAL, "null bathymetry");
     const PatchInfo &p = c->patches[patch];
+    const bool amr = p.frame != 0;       // a patch of a patch set
     long long n = (long long)p.nx * p.ny;
-    unsigned nb = (unsigned)((n + 255) / 256);
+    unsigned nb = nblk(n);
     if (c->mixed) {
         // stored in FP32; phi_T is computed from the stored values
         HIPCHK(c, hipMemcpyAsync(c->stage, b, sizeof(double) * n, kind_in(on_device), c->stream));
-        to_float_kernel<<<nb, 256, 0, c->stream>>>(c->stage, c->fbath + p.coff, n);
-        mask_kernel<float><<<nb, 256, 0, c->stream>>>(p, c->fbath, c->m0, c->m1, c->prm.eta0,
-                                                      c->prm.h_star, c->prm.nbr_n);
+        scatter_plane_kernel<double, float><<<nb, 256, 0, c->stream>>>(p, c->stage, c->fbath, 0);
+        if (!amr)
+            mask_kernel<float><<<nb, 256, 0, c->stream>>>(p, c->fbath, c->m0, c->m1, c->prm.eta0,
+                                                          c->prm.h_star, c->prm.nbr_n);
     } else {
-        HIPCHK(c, hipMemcpyAsync(c->bath + p.coff, b, sizeof(double) * n, kind_in(on_device),
-                                 c->stream));
-        mask_kernel<double><<<nb, 256, 0, c->stream>>>(p, c->bath, c->m0, c->m1, c->prm.eta0,
-                                                       c->prm.h_star, c->prm.nbr_n);
+        if (p.frame) {
+            HIPCHK(c, hipMemcpyAsync(c->stage, b, sizeof(double) * n, kind_in(on_device), c->stream));
+            scatter_plane_kernel<double, double><<<nb, 256, 0, c->stream>>>(p, c->stage, c->bath, 0);
+        } else {
+            HIPCHK(c, hipMemcpyAsync(c->bath + p.coff, b, sizeof(double) * n, kind_in(on_device),
+                                     c->stream));
+        }
+        if (!amr)
+            mask_kernel<double><<<nb, 256, 0, c->stream>>>(p, c->bath, c->m0, c->m1, c->prm.eta0,
+                                                           c->prm.h_star, c->prm.nbr_n);
     }
+    if (amr) c->amr_dirty = true;
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
@@ -608,20 +1213,23 @@ int hsgn_set_state(hsgn_ctx *c, int patch, const double *q, int on_device)
     int rc = check_patch(c, patch);
     if (rc) return rc;
     if (!q) return fail(c, HSGN_EINVAL, "null state");
+    if ((rc = ensure_prepared(c))) return rc;
     std::vector<ScenState> st;
     if ((rc = pull_scen(c, st))) return rc;
     const PatchInfo &p = c->patches[patch];
-    if (c->mixed) {
-        long long n = (long long)p.nx * p.ny;
+    long long n = (long long)p.nx * p.ny;
+    if (c->mixed || p.frame) {
         HIPCHK(c, hipMemcpyAsync(c->stage, q, sizeof(double) * 7 * n, kind_in(on_device), c->stream));
-        float *dst = st[p.scen].cur ? c->f1 : c->f0;
-        to_storage_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
-            p, c->stage, dst, c->fbath, c->prm.eta0);
+        if (c->mixed)
+            to_storage_kernel<float, true><<<nblk(n), 256, 0, c->stream>>>(
+                p, c->stage, st[p.scen].cur ? c->f1 : c->f0, c->fbath, c->prm.eta0);
+        else
+            to_storage_kernel<double, false><<<nblk(n), 256, 0, c->stream>>>(
+                p, c->stage, st[p.scen].cur ? c->q1 : c->q0, c->bath, c->prm.eta0);
         HIPCHK(c, hipGetLastError());
     } else {
         double *dst = (st[p.scen].cur ? c->q1 : c->q0) + p.qoff;
-        HIPCHK(c, hipMemcpyAsync(dst, q, sizeof(double) * 7 * p.nx * p.ny, kind_in(on_device),
-                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(dst, q, sizeof(double) * 7 * n, kind_in(on_device), c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
@@ -632,20 +1240,23 @@ int hsgn_get_state(hsgn_ctx *c, int patch, double *q, int on_device)
     int rc = check_patch(c, patch);
     if (rc) return rc;
     if (!q) return fail(c, HSGN_EINVAL, "null output");
+    if ((rc = ensure_prepared(c))) return rc;
     std::vector<ScenState> st;
     if ((rc = pull_scen(c, st))) return rc;
     const PatchInfo &p = c->patches[patch];
-    if (c->mixed) {
-        long long n = (long long)p.nx * p.ny;
-        const float *src = st[p.scen].cur ? c->f1 : c->f0;
-        from_storage_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
-            p, src, c->fbath, c->prm.eta0, c->stage);
+    long long n = (long long)p.nx * p.ny;
+    if (c->mixed || p.frame) {
+        if (c->mixed)
+            from_storage_kernel<float, true><<<nblk(n), 256, 0, c->stream>>>(
+                p, st[p.scen].cur ? c->f1 : c->f0, c->fbath, c->prm.eta0, c->stage);
+        else
+            from_storage_kernel<double, false><<<nblk(n), 256, 0, c->stream>>>(
+                p, st[p.scen].cur ? c->q1 : c->q0, c->bath, c->prm.eta0, c->stage);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(q, c->stage, sizeof(double) * 7 * n, kind_out(on_device), c->stream));
     } else {
         const double *src = (st[p.scen].cur ? c->q1 : c->q0) + p.qoff;
-        HIPCHK(c, hipMemcpyAsync(q, src, sizeof(double) * 7 * p.nx * p.ny, kind_out(on_device),
-                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(q, src, sizeof(double) * 7 * n, kind_out(on_device), c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
@@ -655,11 +1266,21 @@ int hsgn_get_mask(hsgn_ctx *c, int patch, uint8_t *m, int on_device)
 {
     int rc = check_patch(c, patch);
     if (rc) return rc;
+    if (!m) return fail(c, HSGN_EINVAL, "null output");
+    if ((rc = ensure_prepared(c))) return rc;
     std::vector<ScenState> st;
     if ((rc = pull_scen(c, st))) return rc;
     const PatchInfo &p = c->patches[patch];
-    const uint8_t *src = (st[p.scen].cur ? c->m1 : c->m0) + p.coff;
-    HIPCHK(c, hipMemcpyAsync(m, src, (size_t)p.nx * p.ny, kind_out(on_device), c->stream));
+    long long n = (long long)p.nx * p.ny;
+    const uint8_t *src = st[p.scen].cur ? c->m1 : c->m0;
+    if (p.frame) {
+        uint8_t *tmp = (uint8_t *)c->stage;
+        gather_plane_kernel<uint8_t, uint8_t><<<nblk(n), 256, 0, c->stream>>>(p, src, tmp, 1);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(m, tmp, (size_t)n, kind_out(on_device), c->stream));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(m, src + p.coff, (size_t)n, kind_out(on_device), c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
 }
@@ -668,11 +1289,39 @@ int hsgn_set_mask(hsgn_ctx *c, int patch, const uint8_t *m, int on_device)
 {
     int rc = check_patch(c, patch);
     if (rc) return rc;
+    if (!m) return fail(c, HSGN_EINVAL, "null mask");
+    if ((rc = ensure_prepared(c))) return rc;
     const PatchInfo &p = c->patches[patch];
-    HIPCHK(c, hipMemcpyAsync(c->m0 + p.coff, m, (size_t)p.nx * p.ny, kind_in(on_device), c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->m1 + p.coff, m, (size_t)p.nx * p.ny, kind_in(on_device), c->stream));
+    long long n = (long long)p.nx * p.ny;
+    if (p.frame) {
+        uint8_t *tmp = (uint8_t *)c->stage;
+        HIPCHK(c, hipMemcpyAsync(tmp, m, (size_t)n, kind_in(on_device), c->stream));
+        scatter_plane_kernel<uint8_t, uint8_t><<<nblk(n), 256, 0, c->stream>>>(p, tmp, c->m0, 1);
+        scatter_plane_kernel<uint8_t, uint8_t><<<nblk(n), 256, 0, c->stream>>>(p, tmp, c->m1, 1);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->m0 + p.coff, m, (size_t)n, kind_in(on_device), c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->m1 + p.coff, m, (size_t)n, kind_in(on_device), c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
+}
+
+static bool point_in(const hsgn_ctx *c, int pid, double x, double y)
+{
+    const PatchInfo &p = c->patches[pid];
+    return x >= c->px0[pid] && x <= c->px0[pid] + p.nx * p.dx && y >= c->py0[pid] &&
+           y <= c->py0[pid] + p.ny * p.dy;
+}
+
+// the finest patch of a scenario containing a point (-1: none)
+static int finest_patch(const hsgn_ctx *c, int scenario, double x, double y)
+{
+    const ScenHost &sh = c->scen[scenario];
+    for (int l = (int)sh.lev.size() - 1; l >= 0; l--)
+        for (int pid : sh.lev[l])
+            if (point_in(c, pid, x, y)) return pid;
+    return -1;
 }
 
 int hsgn_set_gauges(hsgn_ctx *c, int scenario, int n, const double *xy)
@@ -680,16 +1329,9 @@ int hsgn_set_gauges(hsgn_ctx *c, int scenario, int n, const double *xy)
     if (!c || !c->finalized) return fail(c, HSGN_EINVAL, "call hsgn_finalize first");
     if (scenario < 0 || scenario >= (int)c->scen.size() || n < 0 || (n > 0 && !xy))
         return fail(c, HSGN_EINVAL, "bad gauge arguments");
-    for (int k = 0; k < n; k++) {
-        bool found = false;
-        for (int pid : c->scen[scenario].patches) {
-            const PatchInfo &p = c->patches[pid];
-            double x = xy[2 * k], y = xy[2 * k + 1];
-            if (x >= c->px0[pid] && x <= c->px0[pid] + p.nx * p.dx && y >= c->py0[pid] &&
-                y <= c->py0[pid] + p.ny * p.dy) { found = true; break; }
-        }
-        if (!found) return fail(c, HSGN_ERANGE, "gauge outside the scenario");
-    }
+    for (int k = 0; k < n; k++)
+        if (finest_patch(c, scenario, xy[2 * k], xy[2 * k + 1]) < 0)
+            return fail(c, HSGN_ERANGE, "gauge outside the scenario");
     c->scen[scenario].gauge_xy.assign(xy, xy + 2 * n);
     c->scen[scenario].ng = n;
     c->scen[scenario].gcap = 0;     // record area rebuilt on the next advance
@@ -711,6 +1353,7 @@ static int ensure_gauges(hsgn_ctx *c, const std::vector<ScenState> &st, long lon
         for (auto &s : c->scen) tot += s.ng;
         if (tot == c->ngauge_total) return HSGN_OK;
     }
+    drop_graph(c);                  // the step graph holds the old tables
     // keep the records already taken
     std::vector<double> old;
     if (c->rec && c->rec_total > 0) {
@@ -732,12 +1375,7 @@ static int ensure_gauges(hsgn_ctx *c, const std::vector<ScenState> &st, long lon
         off += cap * (1 + sh.ng);
         for (int k = 0; k < sh.ng; k++) {
             double x = sh.gauge_xy[2 * k], y = sh.gauge_xy[2 * k + 1];
-            int pid = -1;
-            for (int q : sh.patches) {
-                const PatchInfo &p = c->patches[q];
-                if (x >= c->px0[q] && x <= c->px0[q] + p.nx * p.dx && y >= c->py0[q] &&
-                    y <= c->py0[q] + p.ny * p.dy) { pid = q; break; }
-            }
+            int pid = finest_patch(c, (int)s, x, y);
             const PatchInfo &p = c->patches[pid];
             double fx = (x - c->px0[pid]) / p.dx - 0.5;
             double fy = (y - c->py0[pid]) / p.dy - 0.5;
@@ -749,6 +1387,7 @@ static int ensure_gauges(hsgn_ctx *c, const std::vector<ScenState> &st, long lon
             GaugeDev g;
             memset(&g, 0, sizeof(g));
             g.scen = (int)s; g.slot = k; g.ng = sh.ng;
+            g.qscen = p.scen;
             g.qoff = p.qoff; g.plane = p.coff;
             g.c00 = (long long)j0 * p.pitch + i0;
             g.c01 = g.c00 + 1;
@@ -759,7 +1398,6 @@ static int ensure_gauges(hsgn_ctx *c, const std::vector<ScenState> &st, long lon
             G.push_back(g);
         }
     }
-    if (c->d_gauges) { (void)hipFree(c->d_gauges); c->d_gauges = nullptr; }
     double *nrec = nullptr;
     if (off > 0) HIPCHK(c, hipMalloc(&nrec, sizeof(double) * off));
     for (size_t s = 0; s < c->scen.size(); s++) {
@@ -772,6 +1410,8 @@ static int ensure_gauges(hsgn_ctx *c, const std::vector<ScenState> &st, long lon
     if (c->rec) (void)hipFree(c->rec);
     c->rec = nrec;
     c->rec_total = off;
+    if (c->d_gauges) (void)hipFree(c->d_gauges);
+    c->d_gauges = nullptr;
     c->ngauge_total = (int)G.size();
     if (!G.empty()) {
         HIPCHK(c, hipMalloc(&c->d_gauges, sizeof(GaugeDev) * G.size()));
@@ -812,40 +1452,147 @@ int hsgn_read_gauges(hsgn_ctx *c, int scenario, double *t, double *eta, int max_
 
 static int collect_timing(hsgn_ctx *c);
 
+static int timed_begin(hsgn_ctx *c, hipStream_t s)
+{
+    if (!c->timing) return HSGN_OK;
+    if (c->ev_used + 2 > c->ev.size()) {
+        for (int k = 0; k < 256; k++) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+    }
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used], s));
+    return HSGN_OK;
+}
+
+static int timed_end(hsgn_ctx *c, hipStream_t s)
+{
+    if (!c->timing) return HSGN_OK;
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], s));
+    c->ev_used += 2;
+    return HSGN_OK;
+}
+
+static void launch_gauges(hsgn_ctx *c, hipStream_t s)
+{
+    if (c->ngauge_total <= 0) return;
+    unsigned gb = (unsigned)((c->ngauge_total + 63) / 64);
+    if (c->mixed)
+        gauge_kernel<float, true><<<gb, 64, 0, s>>>(c->d_gauges, c->ngauge_total, c->d_scen, c->f0,
+                                                    c->f1, c->fbath, c->prm.eta0, c->prm.dry_tol,
+                                                    c->rec);
+    else
+        gauge_kernel<double, false><<<gb, 64, 0, s>>>(c->d_gauges, c->ngauge_total, c->d_scen, c->q0,
+                                                      c->q1, c->bath, c->prm.eta0, c->prm.dry_tol,
+                                                      c->rec);
+}
+
+// step kernels over work items [w0, w1): single grids with the plain
+// kernel, patch-set patches [wa, w1) with the patch-set kernel
+static void launch_march_range(hsgn_ctx *c, int w0, int wa, int w1, hipStream_t s)
+{
+    if (wa > w0) {
+        if (c->mixed)
+            launch_march32(march_args<float>(c, c->f0, c->f1, c->fbath, w0, wa), (unsigned)(wa - w0), s);
+        else
+            launch_march64(march_args<double>(c, c->q0, c->q1, c->bath, w0, wa), (unsigned)(wa - w0), s);
+    }
+    if (w1 > wa) {
+        if (c->mixed)
+            launch_march32_amr(march_args<float>(c, c->f0, c->f1, c->fbath, wa, w1),
+                               (unsigned)(w1 - wa), s);
+        else
+            launch_march64_amr(march_args<double>(c, c->q0, c->q1, c->bath, wa, w1),
+                               (unsigned)(w1 - wa), s);
+    }
+}
+
+static void launch_control(hsgn_ctx *c, int s0, int s1, hipStream_t s)
+{
+    if (s1 > s0)
+        control_kernel<<<(unsigned)(s1 - s0), 256, 0, s>>>(c->d_scen + s0, c->d_sstat + s0, c->clip,
+                                                            s1 - s0);
+}
+
+// one step of level l (and, recursively, the 4 substeps of every finer
+// level) of all patch sets and single grids
+static void launch_level(hsgn_ctx *c, int l, double theta, hipStream_t s, bool timed)
+{
+    const LevelRange &R = c->L[l];
+    const double eta0 = c->prm.eta0, dtol = c->prm.dry_tol;
+    if (c->mixed) {
+        AmrBuffers<float> B = amr_buffers<float>(c, c->f0, c->f1, c->fbath);
+        launch_halo_copy32(B, c->d_gc + R.gc0, R.gc1 - R.gc0, s);
+        launch_halo_interp32(B, c->d_gi + R.gi0, R.gi1 - R.gi0, theta, eta0, dtol, s);
+    } else {
+        AmrBuffers<double> B = amr_buffers<double>(c, c->q0, c->q1, c->bath);
+        launch_halo_copy64(B, c->d_gc + R.gc0, R.gc1 - R.gc0, s);
+        launch_halo_interp64(B, c->d_gi + R.gi0, R.gi1 - R.gi0, theta, eta0, dtol, s);
+    }
+    if (timed) (void)timed_begin(c, s);
+    launch_march_range(c, R.w0, R.wa, R.w1, s);
+    if (timed) (void)timed_end(c, s);
+    launch_control(c, R.s0, R.s1, s);
+    if (l + 1 >= c->nlev) return;
+    const LevelRange &F = c->L[l + 1];
+    launch_fill_zero(c->d_R + 7 * F.e0, 7 * (F.e1 - F.e0), s);
+    for (int sub = 0; sub < AMR_RATIO; sub++) {
+        launch_level(c, l + 1, (double)sub / AMR_RATIO, s, timed);
+        if (c->mixed)
+            launch_bflux32(amr_buffers<float>(c, c->f0, c->f1, c->fbath), c->P, c->d_fr + F.fr0,
+                           F.fr1 - F.fr0, c->d_E, c->d_R, s);
+        else
+            launch_bflux64(amr_buffers<double>(c, c->q0, c->q1, c->bath), c->P, c->d_fr + F.fr0,
+                           F.fr1 - F.fr0, c->d_E, c->d_R, s);
+    }
+    if (c->mixed) {
+        AmrBuffers<float> B = amr_buffers<float>(c, c->f0, c->f1, c->fbath);
+        launch_reflux32(B, c->P, c->d_rf + R.rf0, R.rf1 - R.rf0, c->d_R, c->d_rclip + R.rf0, s);
+        launch_avgdown32(B, c->d_av + F.av0, F.av1 - F.av0, false, s);
+    } else {
+        AmrBuffers<double> B = amr_buffers<double>(c, c->q0, c->q1, c->bath);
+        launch_reflux64(B, c->P, c->d_rf + R.rf0, R.rf1 - R.rf0, c->d_R, c->d_rclip + R.rf0, s);
+        launch_avgdown64(B, c->d_av + F.av0, F.av1 - F.av0, false, s);
+    }
+}
+
+// one step attempt of every scenario
 static int launch_attempt(hsgn_ctx *c)
 {
-    if (c->timing) {
-        if (c->ev_used + 2 > c->ev.size()) {
-            for (int k = 0; k < 256; k++) {
-                hipEvent_t e;
-                HIPCHK(c, hipEventCreate(&e));
-                c->ev.push_back(e);
-            }
+    if (!c->any_amr) {
+        if ((c->timing && timed_begin(c, c->stream))) return HSGN_EDEVICE;
+        launch_march_range(c, 0, (int)c->work.size(), (int)c->work.size(), c->stream);
+        if ((c->timing && timed_end(c, c->stream))) return HSGN_EDEVICE;
+        launch_control(c, 0, c->nslot, c->stream);
+        launch_gauges(c, c->stream);
+        HIPCHK(c, hipGetLastError());
+        return HSGN_OK;
+    }
+    // patch sets: the whole level-0 step with its substeps, replayed from a
+    // captured graph (captured on a private stream, launched on the
+    // context's); with timing on, direct launches with the step kernels timed
+    if (!c->timing && !c->graph_failed && !c->graph_valid) {
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+        if (ok) {
+            launch_level(c, 0, 0.0, c->cap_stream, false);
+            launch_gauges(c, c->cap_stream);
+            ok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && g;
         }
-        HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+        if (ok) ok = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->graph_valid = ok;
+        c->graph_failed = !ok;
     }
-    unsigned nw = (unsigned)c->work.size();
-    if (c->mixed)
-        launch_march32(march_args<float>(c, c->f0, c->f1, c->fbath), nw, c->stream);
-    else
-        launch_march64(march_args<double>(c, c->q0, c->q1, c->bath), nw, c->stream);
-    if (c->timing) {
-        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
-        c->ev_used += 2;
+    if (!c->timing && c->graph_valid) {
+        HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+        return HSGN_OK;
     }
-    int ns = (int)c->scen.size();
-    control_kernel<<<(unsigned)ns, 256, 0, c->stream>>>(c->d_scen, c->d_sstat, c->clip, ns);
-    if (c->ngauge_total > 0) {
-        unsigned gb = (unsigned)((c->ngauge_total + 63) / 64);
-        if (c->mixed)
-            gauge_kernel<float, true><<<gb, 64, 0, c->stream>>>(
-                c->d_gauges, c->ngauge_total, c->d_scen, c->f0, c->f1, c->fbath, c->prm.eta0,
-                c->prm.dry_tol, c->rec);
-        else
-            gauge_kernel<double, false><<<gb, 64, 0, c->stream>>>(
-                c->d_gauges, c->ngauge_total, c->d_scen, c->q0, c->q1, c->bath, c->prm.eta0,
-                c->prm.dry_tol, c->rec);
-    }
+    launch_level(c, 0, 0.0, c->stream, c->timing);
+    launch_gauges(c, c->stream);
     HIPCHK(c, hipGetLastError());
     return HSGN_OK;
 }
@@ -855,15 +1602,19 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
     if (!c || !c->finalized) return fail(c, HSGN_EINVAL, "call hsgn_finalize first");
     if (n_steps < 0) return fail(c, HSGN_EINVAL, "negative step count");
     if (n_steps == 0) return HSGN_OK;
-    std::vector<ScenState> st;
-    int rc = pull_scen(c, st);
+    int rc = ensure_prepared(c);
     if (rc) return rc;
+    std::vector<ScenState> st;
+    if ((rc = pull_scen(c, st))) return rc;
     // dt > 0: one fixed step for all scenarios; dt == 0: adaptive steps;
     // dt < 0: each scenario keeps the fixed step stored in its clock
     bool adaptive = dt == 0.0;
     bool per_scen = dt < 0.0;
+    if (adaptive && c->any_amr)
+        return fail(c, HSGN_ENOTSUP, "patch sets advance with fixed steps (dt != 0)");
     bool need_dt0 = false;
-    for (size_t s = 0; s < st.size(); s++) {
+    const int nscen = (int)c->scen.size();
+    for (int s = 0; s < nscen; s++) {
         if (st[s].err) return fail(c, st[s].err, "scenario in error state");
         if (per_scen && !(st[s].dt > 0.0))
             return fail(c, HSGN_EINVAL, "per-scenario fixed step not set (hsgn_set_clock)");
@@ -875,29 +1626,42 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
         st[s].active = 1;
         st[s].streak = 0;
         st[s].rx_bits = 0; st[s].ry_bits = 0;
+        // finer levels of a patch set: 4^l substeps of dt / 4^l
+        const ScenHost &sh = c->scen[s];
+        long long k = 1;
+        for (size_t l = 1; l < sh.slot.size(); l++) {
+            k *= AMR_RATIO;
+            ScenState &f = st[sh.slot[l]];
+            if (f.err) return fail(c, f.err, "scenario in error state");
+            f.adaptive = 0;
+            f.dt = st[s].dt_fixed / (double)k;
+            f.dt_fixed = f.dt;
+            f.target = f.steps + (long long)n_steps * k;
+            f.active = 1;
+            f.streak = 0;
+            f.rx_bits = 0; f.ry_bits = 0;
+        }
     }
     if ((rc = push_scen(c, st))) return rc;
     if (need_dt0) {
-        int ns = (int)c->scen.size();
-        HIPCHK(c, hipMemsetAsync(c->d_slots, 0, sizeof(unsigned long long) * ns, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->d_slots, 0, sizeof(unsigned long long) * nscen, c->stream));
         HIPCHK(c, hipMemsetAsync(c->d_err, 0, sizeof(int), c->stream));
         for (size_t pid = 0; pid < c->patches.size(); pid++) {
             const PatchInfo &p = c->patches[pid];
             if (st[p.scen].dt > 0.0) continue;
             long long n = (long long)p.nx * p.ny;
             const uint8_t *m = st[p.scen].cur ? c->m1 : c->m0;
-            unsigned nb = (unsigned)((n + 255) / 256);
             if (c->mixed)
-                initdt_kernel<float, true><<<nb, 256, 0, c->stream>>>(
+                initdt_kernel<float, true><<<nblk(n), 256, 0, c->stream>>>(
                     p, c->P, st[p.scen].cur ? c->f1 : c->f0, c->fbath, m, c->d_slots + p.scen,
                     c->d_err);
             else
-                initdt_kernel<double, false><<<nb, 256, 0, c->stream>>>(
+                initdt_kernel<double, false><<<nblk(n), 256, 0, c->stream>>>(
                     p, c->P, st[p.scen].cur ? c->q1 : c->q0, c->bath, m, c->d_slots + p.scen,
                     c->d_err);
         }
-        initdt_finish<<<(unsigned)((ns + 63) / 64), 64, 0, c->stream>>>(c->d_scen, c->d_sstat,
-                                                                        c->d_slots, ns);
+        initdt_finish<<<(unsigned)((nscen + 63) / 64), 64, 0, c->stream>>>(c->d_scen, c->d_sstat,
+                                                                           c->d_slots, nscen);
         HIPCHK(c, hipGetLastError());
         int err = 0;
         HIPCHK(c, hipMemcpyAsync(&err, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -914,17 +1678,19 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
         budget -= attempts;
         if ((rc = pull_scen(c, st))) return rc;
         long long left = 0;
-        for (size_t s = 0; s < st.size(); s++)
+        for (int s = 0; s < nscen; s++)
             if (st[s].active && !st[s].err) left = std::max(left, st[s].target - st[s].steps);
-        if (left > 0 && budget > 0) {
+        if (left > 0 && budget > 0 && !c->any_amr) {
             if ((rc = ensure_gauges(c, st, left + 256))) return rc;
             attempts = std::min(left, budget);
         } else {
             attempts = 0;
         }
     }
-    for (size_t s = 0; s < st.size(); s++) {
-        if (st[s].err) return fail(c, st[s].err, std::string("scenario ") + std::to_string(s) + ": " + hsgn_strerror(st[s].err));
+    for (int s = 0; s < nscen; s++) {
+        int err = st[s].err;
+        for (size_t l = 1; l < c->scen[s].slot.size() && !err; l++) err = st[c->scen[s].slot[l]].err;
+        if (err) return fail(c, err, std::string("scenario ") + std::to_string(s) + ": " + hsgn_strerror(err));
         if (st[s].steps < st[s].target) return fail(c, HSGN_ECFL, "too many rejected steps");
     }
     return HSGN_OK;
@@ -934,46 +1700,69 @@ int hsgn_diagnostics(hsgn_ctx *c, int scenario, hsgn_diag *d)
 {
     if (!c || !c->finalized || !d) return fail(c, HSGN_EINVAL, "bad arguments");
     if (scenario < 0 || scenario >= (int)c->scen.size()) return fail(c, HSGN_EINVAL, "bad scenario");
-    std::vector<ScenState> st;
-    int rc = pull_scen(c, st);
+    int rc = ensure_prepared(c);
     if (rc) return rc;
+    std::vector<ScenState> st;
+    if ((rc = pull_scen(c, st))) return rc;
     memset(d, 0, sizeof(*d));
+    const ScenHost &sh = c->scen[scenario];
     const ScenState &s = st[scenario];
-    double mass = 0.0;
+    double mass = 0.0, clip = 0.0, maxc = 0.0;
     unsigned long long cnt_h[2] = {0, 0};
-    long long cells = 0;
-    unsigned long long *dcnt = nullptr;
-    HIPCHK(c, hipMalloc(&dcnt, sizeof(unsigned long long) * 2));
-    for (int pid : c->scen[scenario].patches) {
-        const PatchInfo &p = c->patches[pid];
-        const uint8_t *m = s.cur ? c->m1 : c->m0;
-        if (c->mixed)
-            mass_kernel<float, true><<<1, 1024, 0, c->stream>>>(p, s.cur ? c->f1 : c->f0,
-                                                                 c->fbath, c->prm.eta0, c->d_mass);
-        else
-            mass_kernel<double, false><<<1, 1024, 0, c->stream>>>(p, s.cur ? c->q1 : c->q0,
-                                                                  c->bath, c->prm.eta0, c->d_mass);
-        double pm = 0.0;
-        HIPCHK(c, hipMemcpyAsync(&pm, c->d_mass, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipMemsetAsync(dcnt, 0, sizeof(unsigned long long) * 2, c->stream));
-        long long n = (long long)p.nx * p.ny;
-        count_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(p, m, dcnt);
-        unsigned long long ch[2];
-        HIPCHK(c, hipMemcpyAsync(ch, dcnt, sizeof(ch), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        mass += pm * p.dx * p.dy;
-        cnt_h[0] += ch[0];
-        cnt_h[1] += ch[1];
-        cells += n;
+    long long updates = 0;
+    for (size_t l = 0; l < sh.lev.size(); l++) {
+        const ScenState &sl = st[sh.slot[l]];
+        clip += sl.clip_total;
+        maxc = std::max(maxc, sl.max_courant);
+        for (int pid : sh.lev[l]) {
+            const PatchInfo &p = c->patches[pid];
+            long long n = (long long)p.nx * p.ny;
+            updates += sl.steps * n;
+            const uint8_t *m = sl.cur ? c->m1 : c->m0;
+            HIPCHK(c, hipMemsetAsync(c->d_cnt, 0, sizeof(unsigned long long) * 2, c->stream));
+            count_kernel<<<nblk(n), 256, 0, c->stream>>>(p, m, c->d_cnt);
+            unsigned long long ch[2];
+            HIPCHK(c, hipMemcpyAsync(ch, c->d_cnt, sizeof(ch), hipMemcpyDeviceToHost, c->stream));
+            if (l == 0) {
+                // the mass of a patch set is that of level 0 (finer levels are
+                // averaged onto it after every level-0 step)
+                if (c->mixed)
+                    mass_kernel<float, true><<<1, 1024, 0, c->stream>>>(p, sl.cur ? c->f1 : c->f0,
+                                                                        c->fbath, c->prm.eta0,
+                                                                        c->d_mass);
+                else
+                    mass_kernel<double, false><<<1, 1024, 0, c->stream>>>(p, sl.cur ? c->q1 : c->q0,
+                                                                          c->bath, c->prm.eta0,
+                                                                          c->d_mass);
+                double pm = 0.0;
+                HIPCHK(c, hipMemcpyAsync(&pm, c->d_mass, sizeof(double), hipMemcpyDeviceToHost,
+                                         c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                mass += pm * p.dx * p.dy;
+            }
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            cnt_h[0] += ch[0];
+            cnt_h[1] += ch[1];
+        }
     }
-    (void)hipFree(dcnt);
+    if (!c->h_rf.empty()) {
+        std::vector<double> rcl(c->h_rf.size());
+        HIPCHK(c, hipMemcpyAsync(rcl.data(), c->d_rclip, sizeof(double) * rcl.size(),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < rcl.size(); k++) {
+            int slot = c->patches[c->h_rf[k].cp].scen;
+            for (int sl : sh.slot)
+                if (sl == slot) clip += rcl[k];
+        }
+    }
     d->mass = mass;
-    d->clipped_mass = s.clip_total;
-    d->max_courant = s.max_courant;
+    d->clipped_mass = clip;
+    d->max_courant = maxc;
     d->last_courant = s.courant;
     d->steps = s.steps;
     d->rejected = s.rejects;
-    d->cell_updates = s.steps * cells;
+    d->cell_updates = updates;
     d->n_swe_cells = (long long)cnt_h[0];
     d->n_breaking = (long long)cnt_h[1];
     return HSGN_OK;
@@ -999,10 +1788,16 @@ int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next, long lon
     std::vector<ScenState> st;
     int rc = pull_scen(c, st);
     if (rc) return rc;
-    st[scenario].t = t;
-    st[scenario].dt = dt_next > 0.0 ? dt_next : 0.0;
-    st[scenario].steps = steps;
-    st[scenario].err = 0;
+    const ScenHost &sh = c->scen[scenario];
+    long long k = 1;
+    for (size_t l = 0; l < sh.slot.size(); l++) {
+        ScenState &x = st[sh.slot[l]];
+        x.t = t;
+        x.dt = dt_next > 0.0 ? dt_next / (double)k : 0.0;
+        x.steps = steps * k;
+        x.err = 0;
+        k *= AMR_RATIO;
+    }
     return push_scen(c, st);
 }
 

@@ -32,9 +32,19 @@ struct PatchInfo {
     int nx, ny, pitch, scen;
     int bc[4];               // x-low, x-high, y-low, y-high
     double dx, dy;
-    long long qoff;          // element offset of the patch's 7 planes
-    long long coff;          // element offset of its bathymetry / mask plane
+    long long qoff;          // element offset of interior cell (0, 0) in plane 0
+    long long coff;          // element offset of interior cell (0, 0) in the
+                             // bathymetry / mask plane
+    long long plane;         // elements per state plane
+    long long eoff;          // offset (in 7-vectors) of the patch's boundary-flux
+                             // entries, -1 if it has none
+    int level, frame;        // refinement level; 2 if ghost cells are stored
 };
+
+// mask byte bits: phi_T, breaking latch, and the four edges of a cell whose
+// contributions a finer patch replaces (patch sets)
+constexpr int MASK_PHI = 1, MASK_BRK = 2;
+constexpr int IFACE_L = 1, IFACE_R = 2, IFACE_B = 4, IFACE_T = 8;   // (mask >> 2)
 
 struct WorkItem {
     int patch, i0, r0, th;   // strip: columns i0..i0+59, rows r0..r0+th-1
@@ -68,6 +78,7 @@ struct MarchArgs {
     uint8_t *m0, *m1;        // mask buffers (ping-pong): bit0 phi_T, bit1 breaking
     ScenState *scen;
     double *clip_slots;      // one per work item
+    double *eflux;           // boundary-edge fluxes of patches with eoff >= 0
     int nwork;
 };
 
@@ -131,15 +142,16 @@ struct RawCell {
     int mk;
 };
 
-// load cell (col, row) of a patch through the boundary map
-template <class S, class T>
+// load cell (col, row) of a patch through the boundary map, or (FRAMED)
+// from the stored ghost frame
+template <bool FRAMED, class S, class T>
 HSGN_HD void load_raw(const PatchInfo &pi, const S *q, const S *bath, const uint8_t *mask,
                       int mc, int fx, int row, RawCell<T> &r)
 {
-    int fy;
-    int mr = map_index(row, pi.ny, pi.bc[2], pi.bc[3], &fy);
+    int fy = 0;
+    int mr = FRAMED ? row : map_index(row, pi.ny, pi.bc[2], pi.bc[3], &fy);
     long long idx = (long long)mr * pi.pitch + mc;
-    long long plane = (long long)pi.ny * pi.pitch;
+    long long plane = pi.plane;
     const S *qp = q + pi.qoff + idx;
     HSGN_UNROLL
     for (int m = 0; m < 7; m++) r.q[m] = (T)qp[m * plane];
@@ -211,7 +223,16 @@ HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Sid
 // (the wavefront's LDS ring of 3 * EIG_FIELDS * 64 compute values), and
 // finish(args, wave, scenario, rx, ry, clip) which reduces over the
 // wavefront and publishes the results.
-template <class L, class S, class T, bool MIXED>
+//
+// AMR: patches of a patch set.  Their ghost cells are stored (filled before
+// the step), a cell's update leaves out what reaches it through an edge
+// flagged in its mask byte (a finer patch replaces it by refluxing), and the
+// boundary edges of a patch with eoff >= 0 record what they send through
+// the edge, relative to the flux function of the outside cell:
+//   left  A-dQ + F~ + F~tr,   right -(A+dQ - F~) + F~tr,
+//   below B-dQ + G~ + G~tr,   above -(B+dQ - G~) + G~tr
+// at entries j, ny + j, 2 ny + i, 2 ny + nx + i of the patch.
+template <class L, class S, class T, bool MIXED, bool AMR>
 HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 {
     const WorkItem wk = A.work[wid];
@@ -235,12 +256,17 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     const int lane = ln.lane();
     int col = wk.i0 - 2 + lane;
     if (col > pi.nx + 1) col = pi.nx + 1;       // idle lanes of a partial strip
-    int fx;
-    const int mc = map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
+    int fx = 0;
+    const int mc = AMR ? col : map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
     const int i_hi = wk.i0 + 59 < pi.nx - 1 ? wk.i0 + 59 : pi.nx - 1;
     const bool interior = (wk.i0 - 2 + lane) >= wk.i0 && (wk.i0 - 2 + lane) <= i_hi;
     const bool interior_left = lane >= 1 && (wk.i0 - 3 + lane) >= wk.i0 && (wk.i0 - 3 + lane) <= i_hi;
     const int r0 = wk.r0, th = wk.th;
+    // boundary-flux recording (patch sets): lanes of the patch's edge columns
+    double *ef = (AMR && pi.eoff >= 0) ? A.eflux + pi.eoff * 7 : nullptr;
+    const bool e_left = ef && col == 0 && wk.i0 == 0;
+    const bool e_right = ef && (wk.i0 - 2 + lane) == pi.nx && i_hi == pi.nx - 1;
+    const bool e_cols = ef && interior;
 
     T *ring = ln.ring();
     Side<T> yside_prev;          // lower cell of the next y-edge (y normal frame)
@@ -250,6 +276,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     // the stored plane-0 variable (h, or eta' in mixed precision).
     T acc[3][7];
     int phi_w[3], brk_w[3];      // masks
+    int fl_w[3] = {0, 0, 0};     // interface edge flags (patch sets)
     T b_w[3];                    // bathymetry
     Waves<T> yprev;              // waves of the y-edge below the new one
     T ydl[7];                    // its dot products with the edge below it
@@ -261,16 +288,17 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     for (int m = 0; m < 7; m++) { xtr_prev[m] = (T)0; bp_saved[m] = (T)0; ydl[m] = (T)0; }
 
     RawCell<T> nxt;
-    load_raw(pi, qin, A.bath, min_, mc, fx, r0 - 2, nxt);
+    load_raw<AMR>(pi, qin, A.bath, min_, mc, fx, r0 - 2, nxt);
     for (int k = r0 - 2; k <= r0 + th + 1; k++) {
         const int sk = 2, sk1 = 1, sk2 = 0;
         Cell<T> c;
         {
             RawCell<T> raw = nxt;
             // issue the next row's loads before working on this one
-            if (k < r0 + th + 1) load_raw(pi, qin, A.bath, min_, mc, fx, k + 1, nxt);
+            if (k < r0 + th + 1) load_raw<AMR>(pi, qin, A.bath, min_, mc, fx, k + 1, nxt);
             prepare_cell<T, MIXED>(P, raw, tau_pre, c, phi_c, brk_c);
             acc[sk][IH] = raw.q[IH];
+            if (AMR) fl_w[sk] = (raw.mk >> 2) & 15;
         }
         phi_w[sk] = phi_c;
         brk_w[sk] = brk_c;
@@ -305,11 +333,23 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             for (int m = 0; m < 7; m++) { apc[m] = ap[m] - F[m]; amc[m] = am[m] + F[m]; }
             shfl_vec(ln, amc, amr, false);
             int kind_r = ln.dni(xw.kind);
+            const bool zl = AMR && (fl_w[sk] & IFACE_L), zr = AMR && (fl_w[sk] & IFACE_R);
             HSGN_UNROLL
             for (int m = 0; m < 7; m++) {
-                acc[sk][m] -= dtdx * (apc[m] + amr[m]);
+                acc[sk][m] -= dtdx * ((zl ? (T)0 : apc[m]) + (zr ? (T)0 : amr[m]));
                 xtr[m] = (xw.kind == KIND_REGULAR ? apc[m] : (T)0)
                        + (kind_r == KIND_REGULAR ? amr[m] : (T)0);
+            }
+            if (AMR && k >= r0 && k < r0 + th) {
+                if (e_left) {
+                    HSGN_UNROLL
+                    for (int m = 0; m < 7; m++) ef[(long long)k * 7 + m] = (double)amc[m];
+                }
+                if (e_right) {
+                    HSGN_UNROLL
+                    for (int m = 0; m < 7; m++)
+                        ef[(long long)(pi.ny + k) * 7 + m] = -(double)apc[m];
+                }
             }
             eig_store(ring, slot_k, lane, xe);
             if (k >= r0 && k < r0 + th && (interior || interior_left))
@@ -335,13 +375,31 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                     correction<1>(lim, dtdy, yprev, ydl, dk, G);
                     fluctuations<1>(yprev, bm, bp);
                     T btm[7], btp[7];
+                    const bool zb = AMR && (fl_w[sk1] & IFACE_B), zt = AMR && (fl_w[sk2] & IFACE_T);
                     HSGN_UNROLL
                     for (int m = 0; m < 7; m++) {
                         T bpc = bp[m] - G[m], bmc = bm[m] + G[m];
-                        acc[sk1][m] -= dtdy * bpc;
-                        acc[sk2][m] -= dtdy * bmc;
+                        acc[sk1][m] -= dtdy * (zb ? (T)0 : bpc);
+                        acc[sk2][m] -= dtdy * (zt ? (T)0 : bmc);
                         btp[m] = yprev.kind == KIND_REGULAR ? bpc : (T)0;
                         btm[m] = yprev.kind == KIND_REGULAR ? bmc : (T)0;
+                    }
+                    if (AMR && e_cols) {
+                        // the y-edge between rows k-2 and k-1
+                        if (k - 1 == 0) {
+                            HSGN_UNROLL
+                            for (int m = 0; m < 7; m++) {
+                                double *e = ef + (long long)(2 * pi.ny + col) * 7 + m;
+                                *e = (double)(bm[m] + G[m]) + *e;
+                            }
+                        }
+                        if (k - 1 == pi.ny) {
+                            HSGN_UNROLL
+                            for (int m = 0; m < 7; m++) {
+                                double *e = ef + (long long)(2 * pi.ny + pi.nx + col) * 7 + m;
+                                *e = -(double)(bp[m] - G[m]) + *e;
+                            }
+                        }
                     }
                     if (k - 2 >= r0 && k - 2 <= r0 + th - 1) {
                         // transverse y-fluctuation entering (i, k-2), split by
@@ -364,8 +422,16 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                         }
                         T Ftr[7];
                         shfl_vec(ln, Ft, Ftr, false);
+                        const bool fzl = AMR && (fl_w[sk2] & IFACE_L);
+                        const bool fzr = AMR && (fl_w[sk2] & IFACE_R);
                         HSGN_UNROLL
-                        for (int m = 0; m < 7; m++) acc[sk2][m] -= dtdx * (Ftr[m] - Ft[m]);
+                        for (int m = 0; m < 7; m++)
+                            acc[sk2][m] -= dtdx * ((fzr ? (T)0 : Ftr[m]) - (fzl ? (T)0 : Ft[m]));
+                        if (AMR && (e_left || e_right)) {
+                            long long e0 = (long long)((e_left ? 0 : pi.ny) + (k - 2)) * 7;
+                            HSGN_UNROLL
+                            for (int m = 0; m < 7; m++) ef[e0 + m] = ef[e0 + m] + (double)Ft[m];
+                        }
                     }
                     HSGN_UNROLL
                     for (int m = 0; m < 7; m++) bp_saved[m] = btp[m];
@@ -373,17 +439,27 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 HSGN_UNROLL
                 for (int f = 0; f < 7; f++) ydl[f] = dk[f];
             }
+            T Gt[7];
+            HSGN_UNROLL
+            for (int m = 0; m < 7; m++) Gt[m] = (T)0;
             if (trans && k >= r0 && k <= r0 + th && ye.wet) {
                 // transverse x-fluctuations entering (i, k-1) [up] and (i, k) [down]
                 T vp[7], vm[7];
                 trans_split<1>(ye, xtr_prev, 1, vp);
                 trans_split<1>(ye, xtr, -1, vm);
+                const bool zt = AMR && (fl_w[sk1] & IFACE_T), zb = AMR && (fl_w[sk] & IFACE_B);
                 HSGN_UNROLL
                 for (int m = 0; m < 7; m++) {
-                    T Gt = (T)-0.5 * dtdx * (vp[m] + vm[m]);
-                    acc[sk1][m] -= dtdy * Gt;
-                    acc[sk][m] += dtdy * Gt;
+                    Gt[m] = (T)-0.5 * dtdx * (vp[m] + vm[m]);
+                    acc[sk1][m] -= dtdy * (zt ? (T)0 : Gt[m]);
+                    acc[sk][m] += dtdy * (zb ? (T)0 : Gt[m]);
                 }
+            }
+            if (AMR && e_cols && (k == 0 || k == pi.ny) && k >= r0 && k <= r0 + th) {
+                // transverse part of the patch's lower or upper boundary edge
+                long long e0 = (long long)(k == 0 ? 2 * pi.ny + col : 2 * pi.ny + pi.nx + col) * 7;
+                HSGN_UNROLL
+                for (int m = 0; m < 7; m++) ef[e0 + m] = (double)Gt[m];
             }
             yprev = yw;
         }
@@ -430,12 +506,12 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             if (interior) {
                 if (bad) sc->err = -5;
                 long long idx = (long long)(k - 2) * pi.pitch + (wk.i0 - 2 + lane);
-                long long plane = (long long)pi.ny * pi.pitch;
+                long long plane = pi.plane;
                 S *qo = qout + pi.qoff + idx;
                 qo[0] = out0;
                 HSGN_UNROLL
                 for (int m = 1; m < 7; m++) qo[m * plane] = (S)qd[m];
-                mout[pi.coff + idx] = (uint8_t)(phi | (brk << 1));
+                mout[pi.coff + idx] = (uint8_t)(phi | (brk << 1) | (AMR ? fl_w[sk2] << 2 : 0));
             }
         }
         HSGN_UNROLL
@@ -445,6 +521,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             acc[1][m] = acc[2][m];
         }
         phi_w[0] = phi_w[1]; phi_w[1] = phi_w[2];
+        fl_w[0] = fl_w[1]; fl_w[1] = fl_w[2];
         brk_w[0] = brk_w[1]; brk_w[1] = brk_w[2];
         b_w[0] = b_w[1]; b_w[1] = b_w[2];
         yside_prev = yside;

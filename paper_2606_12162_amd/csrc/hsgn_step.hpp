@@ -36,14 +36,14 @@ struct GpuLanes {
     }
 };
 
-template <class S, class T, bool MIXED>
+template <class S, class T, bool MIXED, bool AMR>
 __global__ __launch_bounds__(64) void march_kernel(MarchArgs<S> A)
 {
     int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;
     __shared__ T ring[3 * EIG_FIELDS * 64];
     GpuLanes<T> ln{ring};
-    march<GpuLanes<T>, S, T, MIXED>(ln, A, wid);
+    march<GpuLanes<T>, S, T, MIXED, AMR>(ln, A, wid);
 }
 
 

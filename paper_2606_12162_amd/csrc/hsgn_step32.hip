@@ -7,5 +7,5 @@ using namespace hsgn;
 
 void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
 {
-    march_kernel<float, float, true><<<nwork, 64, 0, stream>>>(A);
+    march_kernel<float, float, true, false><<<nwork, 64, 0, stream>>>(A);
 }

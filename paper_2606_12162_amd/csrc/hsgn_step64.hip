@@ -7,5 +7,5 @@ using namespace hsgn;
 
 void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream)
 {
-    march_kernel<double, double, false><<<nwork, 64, 0, stream>>>(A);
+    march_kernel<double, double, false, false><<<nwork, 64, 0, stream>>>(A);
 }

@@ -1,0 +1,11 @@
+// hsgn_step64amr.hip -- FP64 step kernel for patches of patch sets (stored
+// ghost frames, interface edges, boundary-flux records), compiled without
+// floating-point contraction like the plain FP64 kernel.
+#include "hsgn_step.hpp"
+
+using namespace hsgn;
+
+void launch_march64_amr(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream)
+{
+    march_kernel<double, double, false, true><<<nwork, 64, 0, stream>>>(A);
+}

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import types
 
 import numpy as np
 
@@ -62,8 +63,9 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p
         L.hsgn_create.argtypes = [ctypes.POINTER(hsgn_params), vp, ctypes.POINTER(vp)]
-        L.hsgn_add_grid.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ip, ip]
+        L.hsgn_add_grid.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ip, ip]
         L.hsgn_finalize.argtypes = [vp]
         for n in ("hsgn_set_bathymetry", "hsgn_set_state", "hsgn_get_state", "hsgn_get_mask",
                   "hsgn_set_mask"):
@@ -144,11 +146,12 @@ class Context:
         except Exception:
             pass
 
-    def add_grid(self, scenario, grid):
+    def add_grid(self, scenario, grid, level=0):
         pid = ctypes.c_int(-1)
         bc = (ctypes.c_int * 4)(*grid.bc)
-        self._check(lib().hsgn_add_grid(self.h, scenario, grid.nx, grid.ny, grid.x0, grid.y0,
-                                        grid.dx, grid.dy, bc, ctypes.byref(pid)), "hsgn_add_grid")
+        self._check(lib().hsgn_add_grid(self.h, scenario, level, grid.nx, grid.ny, grid.x0,
+                                        grid.y0, grid.dx, grid.dy, bc, ctypes.byref(pid)),
+                    "hsgn_add_grid")
         self.grids.append(grid)
         return pid.value
 
@@ -238,6 +241,35 @@ class Context:
         n = ctypes.c_int()
         self._check(lib().hsgn_work_items(self.h, ctypes.byref(n)), "hsgn_work_items")
         return n.value
+
+
+def from_amr_workloads(workloads, tile_rows=0, stream=None, gauges=True, precision=0):
+    """A finalized context with one patch-set scenario per AMR workload
+    (patches added in workload order), bathymetry, state, gauges and the
+    fixed level-0 step (scenario clock) set.  Returns (context, patch ids)."""
+    ws = list(workloads)
+    for w in ws[1:]:
+        if w.params != ws[0].params:
+            raise ValueError("workloads of one context must share their parameters")
+    ctx = Context(ws[0].params, tile_rows=tile_rows, stream=stream, precision=precision)
+    ids = []
+    for s, w in enumerate(ws):
+        ids.append([])
+        for p in w.patches:
+            d = 4.0 ** p.level
+            g = types.SimpleNamespace(nx=p.nx, ny=p.ny, x0=p.x0, y0=p.y0, dx=w.dx0 / d,
+                                      dy=w.dy0 / d, bc=tuple(w.bc))
+            ids[s].append(ctx.add_grid(s, g, level=p.level))
+    ctx.finalize()
+    for s, w in enumerate(ws):
+        for pid, p in zip(ids[s], w.patches):
+            ctx.set_bathymetry(pid, p.b)
+        for pid, p in zip(ids[s], w.patches):
+            ctx.set_state(pid, p.q)
+        if gauges and w.gauges is not None and len(w.gauges):
+            ctx.set_gauges(s, w.gauges)
+        ctx.set_clock(s, 0.0, w.dt, 0)
+    return ctx, ids
 
 
 def from_workloads(workloads, tile_rows=0, stream=None, gauges=True):

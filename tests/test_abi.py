@@ -45,10 +45,47 @@ def test_strerror_and_param_validation_on_host():
     assert L.hsgn_create(ctypes.byref(good), None, ctypes.byref(h)) == H.HSGN_OK
     bc = (ctypes.c_int * 4)(0, 1, 1, 1)      # unpaired periodic side
     pid = ctypes.c_int()
-    assert L.hsgn_add_grid(h, 0, 16, 16, 0.0, 0.0, 0.1, 0.1, bc, ctypes.byref(pid)) == H.HSGN_EINVAL
+    assert L.hsgn_add_grid(h, 0, 0, 16, 16, 0.0, 0.0, 0.1, 0.1, bc, ctypes.byref(pid)) == H.HSGN_EINVAL
     bc = (ctypes.c_int * 4)(1, 1, 1, 1)
-    assert L.hsgn_add_grid(h, 0, 3, 16, 0.0, 0.0, 0.1, 0.1, bc, ctypes.byref(pid)) == H.HSGN_EINVAL
-    assert L.hsgn_add_grid(h, 0, 16, 16, 0.0, 0.0, 0.1, 0.1, bc, ctypes.byref(pid)) == H.HSGN_OK
+    assert L.hsgn_add_grid(h, 0, 0, 3, 16, 0.0, 0.0, 0.1, 0.1, bc, ctypes.byref(pid)) == H.HSGN_EINVAL
+    assert L.hsgn_add_grid(h, 0, 0, 16, 16, 0.0, 0.0, 0.1, 0.1, bc, ctypes.byref(pid)) == H.HSGN_OK
     assert L.hsgn_advance(h, 0.0, 1) == H.HSGN_EINVAL          # before finalize
     assert b"finalize" in L.hsgn_last_error(h)
     assert L.hsgn_destroy(h) == H.HSGN_OK
+
+
+def _patch_set_error(patches):
+    """hsgn_finalize of one scenario made of `patches` (level, nx, ny, i0, j0
+    in cells of the patch's level, level-0 spacing 1): the status and message.
+    Invalid sets are rejected on the host, before any device call."""
+    L = H.lib()
+    h = ctypes.c_void_p()
+    good = H.make_params(W.Params())
+    assert L.hsgn_create(ctypes.byref(good), None, ctypes.byref(h)) == H.HSGN_OK
+    bc = (ctypes.c_int * 4)(1, 1, 1, 1)
+    pid = ctypes.c_int()
+    for lev, nx, ny, i0, j0 in patches:
+        d = 1.0 / 4 ** lev
+        assert L.hsgn_add_grid(h, 0, lev, nx, ny, i0 * d, j0 * d, d, d, bc,
+                               ctypes.byref(pid)) == H.HSGN_OK
+    rc = L.hsgn_finalize(h)
+    msg = L.hsgn_last_error(h).decode()
+    L.hsgn_destroy(h)
+    return rc, msg
+
+
+@pytest.mark.parametrize("patches, words", [
+    ([(0, 16, 16, 0, 0), (0, 16, 16, 8, 0)], "overlap"),                    # level-0 overlap
+    ([(0, 16, 16, 0, 0), (0, 16, 16, 20, 0)], "tile"),                      # hole in level 0
+    ([(0, 16, 16, 0, 0), (1, 16, 16, 0, 16)], "domain boundary"),           # touches the edge
+    ([(0, 16, 16, 0, 0), (1, 18, 16, 8, 8)], "multiples of 4"),
+    ([(0, 16, 16, 0, 0), (1, 16, 16, 10, 8)], "aligned"),                   # not on a coarse corner
+    ([(0, 16, 16, 0, 0), (2, 16, 16, 40, 40)], "levels must be dense"),     # no level 1
+    ([(0, 32, 32, 0, 0), (1, 16, 16, 20, 20), (2, 16, 16, 80, 80)], "nested"),
+])
+def test_patch_set_rules_are_checked_on_host(patches, words):
+    if not os.path.exists(H.LIB_PATH):
+        pytest.skip("libhsgn.so not built")
+    rc, msg = _patch_set_error(patches)
+    assert rc == H.HSGN_EINVAL, (rc, msg)
+    assert words in msg, msg

@@ -1,0 +1,191 @@
+"""GPU parity of static patch sets (AMR) against the FP64 oracle.
+
+Bar (FP64): every field of every patch within 1e-11 of the oracle relative
+to that field's largest magnitude on the patch, masks equal, gauges within
+1e-11 of the amplitude.  Both sides evaluate the same formulas in the same
+order without fused multiply-add.  Mixed precision: gauges within 1e-4 of
+the amplitude.  The level-0 step of a patch set is replayed from a HIP
+graph; the runs below replay it several times with host reads in between
+and compare every intermediate state.
+"""
+import numpy as np
+import pytest
+
+from oracle import amr as A
+from oracle import oracle as O
+from paper_2606_12162_amd import hsgn as H
+from paper_2606_12162_amd import workloads as W
+
+from cases import rough_case
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    H.lib()
+    yield
+
+
+def field_errors(got, exp):
+    scale = np.abs(exp).max(axis=(1, 2))
+    err = np.abs(got - exp).max(axis=(1, 2))
+    return np.where(scale > 0, err / np.where(scale > 0, scale, 1.0), err)
+
+
+def compare(ctx, ids, o, w, what):
+    worst = 0.0
+    for pid, k in zip(ids, range(len(w.patches))):
+        e = field_errors(ctx.get_state(pid), o.get_state(k))
+        assert np.all(e <= TOL), "%s patch %d (level %d): %s" % (
+            what, k, w.patches[k].level, np.array2string(e, precision=2))
+        assert np.array_equal(ctx.get_mask(pid), o.get_mask(k)), (what, k)
+        worst = max(worst, float(e.max()))
+    return worst
+
+
+def test_level0_tiling_matches_oracle_single_grid():
+    bc = (W.BC_WALL, W.BC_EXTRAP, W.BC_PERIODIC, W.BC_PERIODIC)
+    w = rough_case(61, 47, bc, seed=5)
+    t = W.tiled(w, 3, 2)
+    print("case", t.name, flush=True)
+    ctx, ids = H.from_amr_workloads([t])
+    ctx.advance(-1.0, 12)
+    ref = O.from_workload(w)
+    ref.advance(w.dt, 12)
+    q, m = ref.get_state(), ref.get_mask()
+    for pid, p in zip(ids[0], t.patches):
+        i0, j0 = int(round(p.x0 / w.grid.dx)), int(round(p.y0 / w.grid.dy))
+        sl = (slice(j0, j0 + p.ny), slice(i0, i0 + p.nx))
+        e = field_errors(ctx.get_state(pid), q[(slice(None),) + sl])
+        assert np.all(e <= TOL), e
+        assert np.array_equal(ctx.get_mask(pid), m[sl])
+    ctx.close()
+
+
+def test_three_levels_fp64_parity_across_graph_replays():
+    w = W.amr_small(steps=6)
+    print("case", w.name, flush=True)
+    ctx, ids = H.from_amr_workloads([w])
+    o = A.from_workload(w)
+    worst = 0.0
+    for chunk in (1, 2, 3):                    # graph replays with host reads between
+        ctx.advance(-1.0, chunk)
+        o.advance(w.dt, chunk)
+        worst = max(worst, compare(ctx, ids[0], o, w, "after %d more steps" % chunk))
+        t, dtn, steps = ctx.clock(0)
+        assert abs(t - o.t) <= 1e-12 * o.t and steps == o.steps
+    print("worst relative field error", worst)
+    tg, eg = ctx.read_gauges(0)
+    to, eo = o.read_gauges()
+    np.testing.assert_allclose(tg, to, rtol=1e-12)
+    assert np.abs(eg - eo).max() <= TOL * w.amplitude
+    d = ctx.diagnostics(0)
+    assert abs(d["mass"] - o.mass()) <= 1e-13 * o.mass()
+    assert d["steps"] == 6
+    ctx.close()
+
+
+def test_direct_launches_equal_graph_replays_bitwise():
+    w = W.amr_small(steps=3)
+    runs = []
+    for timing in (False, True):
+        ctx, ids = H.from_amr_workloads([w])
+        ctx.set_timing(timing)
+        ctx.advance(-1.0, w.steps)
+        runs.append([ctx.get_state(pid) for pid in ids[0]])
+        ctx.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_lake_at_rest_exact_fp64_and_mixed():
+    w = W.amr_small(amp=0.0, steps=3)
+    o = A.from_workload(w)
+    o.prepare()
+    for precision in (0, 1):
+        ctx, ids = H.from_amr_workloads([w], precision=precision)
+        for pid, p in zip(ids[0], o.patches):
+            q = np.zeros((7, p.ny, p.nx))
+            q[0] = np.maximum(-p.b[2:-2, 2:-2], 0.0)
+            ctx.set_state(pid, q)
+        ctx.advance(-1.0, w.steps)
+        for pid, p in zip(ids[0], o.patches):
+            q = ctx.get_state(pid)
+            assert np.abs(q[1:]).max() == 0.0, (precision, pid)
+            if precision == 0:
+                assert np.array_equal(q[0], np.maximum(-p.b[2:-2, 2:-2], 0.0))
+        ctx.close()
+
+
+def test_mass_conserved_on_device():
+    w = W.amr_small(steps=6)
+    ctx, ids = H.from_amr_workloads([w])
+    ctx.advance(-1.0, 1)
+    m1 = ctx.diagnostics(0)["mass"]
+    ctx.advance(-1.0, 5)
+    d = ctx.diagnostics(0)
+    print("relative mass drift", (d["mass"] - m1) / m1)
+    assert abs(d["mass"] - m1) <= 2e-15 * m1 and d["clipped_mass"] == 0.0
+    ctx.close()
+
+
+def test_mixed_gauges_within_1e4_of_amplitude():
+    w = W.amr_small(steps=6)
+    ctx, ids = H.from_amr_workloads([w], precision=1)
+    ctx.advance(-1.0, w.steps)
+    o = A.from_workload(w)
+    o.advance(w.dt, w.steps)
+    _, eg = ctx.read_gauges(0)
+    _, eo = o.read_gauges()
+    err = np.abs(eg - eo).max() / w.amplitude
+    print("mixed gauge error / amplitude", err)
+    assert err <= 1e-4
+    ctx.close()
+
+
+def test_patch_sets_and_single_grids_in_one_context():
+    """an ensemble mixing a patch set and a single grid: each matches its
+    own oracle run"""
+    a = W.amr_small(steps=2)
+    g = W.amr_small_uniform(0, steps=2)
+    ctx = H.Context(a.params)
+    ids = []
+    for p in a.patches:
+        d = 4.0 ** p.level
+        grid = W.Grid(p.nx, p.ny, p.x0, p.y0, a.dx0 / d, a.dy0 / d, a.bc)
+        ids.append(ctx.add_grid(0, grid, level=p.level))
+    gid = ctx.add_grid(1, g.grid)
+    ctx.finalize()
+    for pid, p in zip(ids, a.patches):
+        ctx.set_bathymetry(pid, p.b)
+    for pid, p in zip(ids, a.patches):
+        ctx.set_state(pid, p.q)
+    ctx.set_bathymetry(gid, g.b)
+    ctx.set_state(gid, g.q)
+    ctx.set_clock(0, 0.0, a.dt, 0)
+    ctx.set_clock(1, 0.0, g.dt, 0)
+    ctx.advance(-1.0, 2)
+    o = A.from_workload(a)
+    o.advance(a.dt, 2)
+    compare(ctx, ids, o, a, "patch set")
+    r = O.OracleGrid(g.params, g.grid)
+    r.set_bathymetry(g.b)
+    r.set_state(g.q)
+    r.advance(g.dt, 2)
+    e = field_errors(ctx.get_state(gid), r.get_state())
+    assert np.all(e <= TOL), e
+    ctx.close()
+
+
+def test_adaptive_step_is_refused_for_patch_sets():
+    w = W.amr_small(steps=1)
+    ctx, ids = H.from_amr_workloads([w])
+    assert ctx.advance_status(0.0, 1) == H.HSGN_ENOTSUP
+    ctx.close()

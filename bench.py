@@ -11,8 +11,12 @@ in the mixed FP32/FP64 form with each scenario's own fixed CFL-0.9 step.
 The same ensemble is then advanced in plain FP64 over the same steps; the
 line reports both rates and the gauge error of the mixed run against the
 FP64 run (the FP64 kernels match the FP64 CPU oracle to 1e-11, see tests).
-Other workloads: --workload beach (1024^2 plane beach, FP64, adaptive) and
---workload ocean (2048^2 synthetic ocean, mixed and FP64).
+Other workloads: --workload beach (1024^2 plane beach, FP64, adaptive),
+--workload ocean (2048^2 synthetic ocean, mixed and FP64) and --workload amr
+(the ocean as a three-level patch set: 256 level-0 patches of 128^2, 1000
+level-1 and 1250 level-2 patches of 16..128 cells around a circular wave;
+one step is a level-0 step with its 4 + 16 substeps, a cell update is one
+cell advanced one step of its own level).
 
 Inputs are synthetic (seeded generators in paper_2606_12162_amd/workloads.py)
 and resident in HBM before timing starts.  The step kernel issues far more
@@ -95,6 +99,8 @@ def make_context(H, ws, precision, tile_rows=0, gauges=True):
 
 def run(H, torch, ws, precision, steps, warmup, tile_rows=0):
     """Advance the workloads; returns (context, seconds, kernel ms per launch)."""
+    if hasattr(ws[0], "patches"):
+        return run_amr(H, torch, ws, precision, steps, warmup, tile_rows)
     ctx = make_context(H, ws, precision, tile_rows)
     dt = -1.0 if ws[0].dt > 0 else 0.0          # per-scenario fixed steps, or adaptive
     if warmup:
@@ -108,6 +114,31 @@ def run(H, torch, ws, precision, steps, warmup, tile_rows=0):
     ms, n = ctx.get_timing()
     ctx.set_timing(False)
     return ctx, el, ms / max(n, 1), n
+
+
+def run_amr(H, torch, ws, precision, steps, warmup, tile_rows=0):
+    """Patch sets: the timed steps replay the captured level-0 step graph;
+    a second, untimed-by-the-clock pass of the same number of steps with
+    direct launches times every step-kernel launch with HIP events"""
+    ctx, _ = H.from_amr_workloads(ws, tile_rows=tile_rows,
+                                  precision=1 if precision == "mixed" else 0)
+    if warmup:
+        ctx.advance(-1.0, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(-1.0, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.set_timing(True)
+    ctx.advance(-1.0, steps)
+    ms, n = ctx.get_timing()
+    ctx.set_timing(False)
+    return ctx, el, ms / max(n, 1), n
+
+
+def amr_updates(w):
+    """cell updates of one level-0 step of a patch set"""
+    return sum(p.nx * p.ny * 4 ** p.level for p in w.patches)
 
 
 def cpu_baseline(w, steps):
@@ -146,7 +177,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="ensemble", choices=["ensemble", "beach", "ocean"])
+    ap.add_argument("--workload", default="ensemble", choices=["ensemble", "beach", "ocean", "amr"])
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -181,9 +212,12 @@ def main():
         ws, precision = W.ensemble(), "mixed"
     elif args.workload == "ocean":
         ws, precision = [W.synthetic_ocean()], "mixed"
+    elif args.workload == "amr":
+        ws, precision = [W.amr_ocean()], "mixed"
     else:
         ws, precision = [W.beach_soliton()], "fp64"
-    cells = sum(w.grid.nx * w.grid.ny for w in ws)
+    amr = args.workload == "amr"
+    cells = sum(amr_updates(w) if amr else w.grid.nx * w.grid.ny for w in ws)
     log("bench: %s x%d, %.2f M cells, precision %s, inputs generated in %.1f s"
         % (ws[0].name, len(ws), cells / 1e6, precision, time.perf_counter() - t0))
 
@@ -200,11 +234,14 @@ def main():
 
     ctx, el, kms, launches = run(H, torch, ws, precision, args.steps, args.warmup, tile_rows)
     value = cells * args.steps / el
+    # per timed step-kernel launch: the cells it advances (patch sets: the
+    # launches of all levels together advance `cells` per level-0 step)
+    cells_per_launch = cells * args.steps / max(launches, 1) if amr else cells
     diag = ctx.diagnostics(0)
     log("timed: %.3f ms/step, step kernel %.1f us, %.3e cell-updates/s"
         % (el * 1e3 / args.steps, kms * 1e3, value))
-    tflops = ALG_FLOPS * cells / (kms / 1e3) / 1e12
-    hbm_gbs = ALG_BYTES[precision] * cells / (kms / 1e3) / 1e9
+    tflops = ALG_FLOPS * cells_per_launch / (kms / 1e3) / 1e12
+    hbm_gbs = ALG_BYTES[precision] * cells_per_launch / (kms / 1e3) / 1e9
     traffic = measured_traffic(args.workload, precision)
     dtype = {"mixed": "f32+f64", "fp64": "f64"}[precision]
     out = {
@@ -221,7 +258,7 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": ws[0].name if len(ws) == 1 else "ensemble_%d_scenarios" % len(ws),
-                   "scenarios": len(ws), "cells": cells, "precision": precision,
+                   "scenarios": len(ws), "cell_updates_per_step": cells, "precision": precision,
                    "dt": "per-scenario fixed, cfl 0.9" if ws[0].dt > 0 else "adaptive, cfl 0.9",
                    "work_items": ctx.work_items(), "tile_rows": tile_rows or "library",
                    "max_courant_scenario0": diag["max_courant"]},
@@ -232,7 +269,7 @@ def main():
                      "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": hbm_gbs / HBM_PEAK_GBS,
                              "alg_bytes_per_cell": ALG_BYTES[precision],
-                             "traffic_over_alg": (traffic / (ALG_BYTES[precision] * cells)
+                             "traffic_over_alg": (traffic / (ALG_BYTES[precision] * cells_per_launch)
                                                   if traffic else None)}},
     }
     if precision == "mixed" and not args.no_fp64:
@@ -248,7 +285,9 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         steps = args.cpu_steps or (60 if args.workload == "ensemble" else 20)
-        out["cpu_baseline"] = cpu_baseline(ws[0], steps)
+        # patch sets: the oracle on the level-0 ocean grid of the same set
+        base = W.synthetic_ocean() if amr else ws[0]
+        out["cpu_baseline"] = cpu_baseline(base, steps)
     print(json.dumps(out), flush=True)
 
 

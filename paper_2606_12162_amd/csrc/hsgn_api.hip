@@ -820,16 +820,26 @@ int hsgn_add_grid(hsgn_ctx *c, int scenario, int level, int nx, int ny, double x
     return HSGN_OK;
 }
 
-static int choose_rows(const hsgn_ctx *c)
+// rows per marching tile for the patches of one refinement level.  A tile
+// of th rows costs th + 4 row iterations (2 halo rows below and above) and
+// the chip runs 256 CUs x 4 SIMDs x (2 wavefronts in mixed precision, 1 in
+// FP64) tiles at a time, so a level of W(th) tiles takes about
+// ceil(W(th) / slots) * (th + 4) row times; the smallest such cost wins
+// (ties: the taller tile).
+static int choose_rows(const hsgn_ctx *c, int level)
 {
     if (c->prm.tile_rows > 0) return c->prm.tile_rows;
-    // enough wavefronts to fill the chip several times over: 256 CUs x 4 SIMDs
-    long long cells = 0;
-    for (const PatchInfo &p : c->patches) cells += (long long)p.nx * p.ny;
-    long long target_waves = 4096;
-    long long cells_per_wave = std::max<long long>(60 * 8, cells / target_waves);
-    int th = (int)std::min<long long>(64, std::max<long long>(8, cells_per_wave / 60));
-    return th;
+    const long long slots = 256LL * 4 * (c->mixed ? 2 : 1);
+    int best = 64;
+    long long best_cost = -1;
+    for (int th = 64; th >= 8; th--) {
+        long long waves = 0;
+        for (const PatchInfo &p : c->patches)
+            if (p.level == level) waves += (long long)((p.nx + 59) / 60) * ((p.ny + th - 1) / th);
+        long long cost = ((waves + slots - 1) / slots) * (th + 4);
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = th; }
+    }
+    return best;
 }
 
 // geometry checks of the scenarios and level structure
@@ -960,7 +970,6 @@ int hsgn_finalize(hsgn_ctx *c)
         c->L[l].e1 = c->etotal;
     }
     // work items: slots in order; on level 0 single grids before patch sets
-    int th = choose_rows(c);
     c->work.clear();
     c->sstat.assign(c->nslot, ScenStatic());
     auto add_slot_work = [&](int slot) {
@@ -972,6 +981,7 @@ int hsgn_finalize(hsgn_ctx *c)
         ss.cfl = c->prm.cfl;
         ss.cfl_max = c->prm.cfl_max;
         ss.w0 = (int)c->work.size();
+        const int th = choose_rows(c, l);
         for (int pid : c->scen[s].lev[l]) {
             const PatchInfo &p = c->patches[pid];
             for (int r0 = 0; r0 < p.ny; r0 += th)

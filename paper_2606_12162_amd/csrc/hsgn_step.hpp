@@ -36,8 +36,13 @@ struct GpuLanes {
     }
 };
 
+// Mixed precision runs two wavefronts per SIMD: registers are capped at
+// 256 per lane (the few values beyond that spill to scratch), which hides
+// more latency than the spills cost.  FP64 keeps one wavefront per SIMD
+// with its values in VGPRs and AGPRs.
 template <class S, class T, bool MIXED, bool AMR>
-__global__ __launch_bounds__(64) void march_kernel(MarchArgs<S> A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
+void march_kernel(MarchArgs<S> A)
 {
     int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;

@@ -88,7 +88,7 @@ HSGN_HD void shfl_side_up(L &ln, const Side<T> &c, Side<T> &o)
     o.h = ln.up(c.h); o.sq = ln.up(c.sq); o.ce = ln.up(c.ce);
     o.hun = ln.up(c.hun); o.un = ln.up(c.un); o.ut = ln.up(c.ut);
     o.w = ln.up(c.w); o.s = ln.up(c.s); o.p = ln.up(c.p); o.pb = ln.up(c.pb);
-    o.hp = ln.up(c.hp); o.b = ln.up(c.b); o.c2 = ln.up(c.c2);
+    o.hp = ln.up(c.hp); o.b = ln.up(c.b); o.c2 = ln.up(c.c2); o.eta = ln.up(c.eta);
     o.wet = ln.upi(c.wet); o.hyp = ln.upi(c.hyp);
 }
 
@@ -189,6 +189,7 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
         c.q[IHW] = (T)0; c.q[IHS] = (T)0; c.q[IHP] = (T)0; c.q[IHPB] = (T)0;
     }
     derive(P, c);
+    c.eta = MIXED ? r.q[IH] : c.h + c.b;
 }
 
 // normal solve of an edge.  In mixed precision an edge with an SWE or dry
@@ -220,7 +221,8 @@ HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Sid
 
 // Lanes policy L provides: lane(), up(x)/dn(x) (value of lane-1 / lane+1)
 // for float, double and int (upi/dni), any(pred) over the wavefront, ring()
-// (the wavefront's LDS ring of 3 * EIG_FIELDS * 64 compute values), and
+// (the wavefront's LDS ring of 3 * EIG_FIELDS * 64 compute values, followed
+// in mixed precision by 3 * 7 * 64 more for the rows' base states), and
 // finish(args, wave, scenario, rx, ry, clip) which reduces over the
 // wavefront and publishes the results.
 //
@@ -269,6 +271,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     const bool e_cols = ef && interior;
 
     T *ring = ln.ring();
+    T *base = ring + 3 * EIG_FIELDS * 64;        // mixed precision: 3 rows x 7 x 64
     Side<T> yside_prev;          // lower cell of the next y-edge (y normal frame)
     int phi_c = 0, brk_c = 0;
     // sliding windows over rows k-2 (index 0), k-1 (1) and k (2), shifted
@@ -303,10 +306,22 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         phi_w[sk] = phi_c;
         brk_w[sk] = brk_c;
         b_w[sk] = c.b;
-        HSGN_UNROLL
-        for (int m = 1; m < 7; m++) acc[sk][m] = c.q[m];
-
         const int slot_k = (k - r0 + 6) % 3, slot_k2 = (k - r0 + 4) % 3;
+        if (MIXED) {
+            // increment form: the cell's state after the first source half
+            // step waits in LDS while its contributions are summed from
+            // zero, so that the FP32 momenta and auxiliaries are rounded
+            // once per step rather than once per contribution
+            HSGN_UNROLL
+            for (int m = 1; m < 7; m++) {
+                base[(slot_k * 7 + m) * 64 + lane] = c.q[m];
+                acc[sk][m] = (T)0;
+            }
+        } else {
+            HSGN_UNROLL
+            for (int m = 1; m < 7; m++) acc[sk][m] = c.q[m];
+        }
+
         // ---- x-edge (i-1/2, k) ----
         T xtr[7];
         HSGN_UNROLL
@@ -473,7 +488,9 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             // depth in the compute type for the source step
             T qn[7];
             HSGN_UNROLL
-            for (int m = 0; m < 7; m++) qn[m] = acc[sk2][m];
+            for (int m = 0; m < 7; m++)
+                qn[m] = (MIXED && m > 0) ? base[(slot_k2 * 7 + m) * 64 + lane] + acc[sk2][m]
+                                         : acc[sk2][m];
             qn[IH] = depth_of<T, MIXED>(P, acc[sk2][IH], bb);
             source_or_clear(P, qn, c2, swe, tau_post);
             // fix-ups in FP64: the depth from the stored variable, clipping

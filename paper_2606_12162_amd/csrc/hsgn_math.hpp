@@ -57,6 +57,9 @@ struct Cell {
     T ce;              // sqrt(g h + p + c^2) of a wet cell
     T u, v, w, s, p, pb;   // primitives, zero in dry cells
     T b, c2;
+    T eta;             // surface for the hydrostatic jump: h + b (FP64) or the
+                       // stored deviation eta' (mixed precision, where h + b
+                       // would carry the FP32 rounding of a 4000 m depth)
     int wet;           // h > dry_tol
     int hyp;           // g h + p + c^2 >= 0 (always true for a dry cell)
 };
@@ -261,7 +264,7 @@ HSGN_HD T sensor(const StepParams &P, T bL, T bR)
 // auxiliaries)
 template <class T>
 struct Side {
-    T h, sq, ce, hun, un, ut, w, s, p, pb, hp, b, c2;
+    T h, sq, ce, hun, un, ut, w, s, p, pb, hp, b, c2, eta;
     int wet, hyp;
 };
 
@@ -276,6 +279,7 @@ HSGN_HD void side_of(const Cell<T> &c, Side<T> &sd)
     sd.hyp = c.hyp;
     sd.b = c.b;
     sd.c2 = c.c2;
+    sd.eta = c.eta;
     if (c.wet) {
         sd.hun = c.q[IN];
         sd.un = DIR == 0 ? c.u : c.v;
@@ -337,7 +341,7 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     T psi = sensor(P, L.b, R.b);
     T db = R.b - L.b;
     T dh = R.h - L.h;
-    T deta = (R.h + R.b) - (L.h + L.b);
+    T deta = R.eta - L.eta;
 
     T df[7];
     df[0] = R.hun - L.hun;
@@ -389,7 +393,20 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
         W.bt = df[2] - vh * S;
         W.bpb = df[6] - pbh * S;
     } else {
-        T b2 = quot((c2h + ph) * df[0] - df[5], ce2, ice2);
+        // strength of the wave at speed u_hat: ((c2 + p)_hat df1 - df6) / Ce^2.
+        // In FP32 the two terms (each about c^2 hu, 1e7 in deep water) are
+        // expanded so that the c^2 parts cancel exactly:
+        //   c2_hat (hu_R - hu_L) - (hu_R c2_R - hu_L c2_L)
+        //     = -(c2_R - c2_L) (hu_R + hu_L) / 2,
+        // leaving no difference of large numbers.  FP64 keeps the plain form.
+        T num;
+        if constexpr (sizeof(T) == 4) {
+            num = ph * df[0] - (R.hun * R.p - L.hun * L.p)
+                - (T)0.5 * (R.c2 - L.c2) * (R.hun + L.hun) + c2h * uh * dh;
+        } else {
+            num = (c2h + ph) * df[0] - df[5];
+        }
+        T b2 = quot(num, ce2, ice2);
         T S = df[0] - b2;
         T Tm = df[1] - uh * b2;
         T b1 = quot(smax * S - Tm, smax - smin, ids);
@@ -442,7 +459,7 @@ HSGN_HD void convert(const Side<T> &a, Side<D> &o)
 {
     o.h = (D)a.h; o.sq = (D)a.sq; o.ce = (D)a.ce; o.hun = (D)a.hun; o.un = (D)a.un;
     o.ut = (D)a.ut; o.w = (D)a.w; o.s = (D)a.s; o.p = (D)a.p; o.pb = (D)a.pb;
-    o.hp = (D)a.hp; o.b = (D)a.b; o.c2 = (D)a.c2;
+    o.hp = (D)a.hp; o.b = (D)a.b; o.c2 = (D)a.c2; o.eta = (D)a.eta;
     o.wet = a.wet; o.hyp = a.hyp;
 }
 

@@ -67,7 +67,7 @@ void march_kernel(MarchArgs<S> A)
 {
     int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;
-    __shared__ T ring[3 * EIG_FIELDS * 64];
+    __shared__ T ring[3 * EIG_FIELDS * 64 + (MIXED ? 3 * 7 * 64 : 0)];
     GpuLanes<T> ln{ring};
     march<GpuLanes<T>, S, T, MIXED, AMR>(ln, A, wid);
 }

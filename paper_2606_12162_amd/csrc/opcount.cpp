@@ -43,12 +43,12 @@ template <> inline CF tiny_norm<CF>() { return CF(1e-200); }
 using namespace hsgn;
 int main() {
   StepParams P; P.g = 9.81; P.a2g = 9 * 9.81; P.eta0 = 0; P.h_star = 0.05; P.dry_tol = 1e-3; P.xi0 = 0.01; P.xi1 = 0.05; P.kappa = 0.8; P.limiter = 2; P.transverse = 2; P.splitting = 1;
-  auto mkcell = [&](double h, double u, double v, double b) { Cell<CF> c; double q[7] = {h, h*u, h*v, 0.01*h, 0.02*h, 0.1*h, 0.15*h}; for (int m=0;m<7;m++) c.q[m]=mk(q[m],false,false); c.b = mk(b,false,false); c.c2 = mk(9*9.81*(-b),false,false); derive(P, c); return c; };
+  auto mkcell = [&](double h, double u, double v, double b) { Cell<CF> c; double q[7] = {h, h*u, h*v, 0.01*h, 0.02*h, 0.1*h, 0.15*h}; for (int m=0;m<7;m++) c.q[m]=mk(q[m],false,false); c.b = mk(b,false,false); c.c2 = mk(9*9.81*(-b),false,false); derive(P, c); c.eta = c.h + c.b; return c; };
   Cell<CF> a = mkcell(1.0, 0.1, 0.05, -1.0), b = mkcell(1.02, 0.12, 0.04, -0.98);
   auto snap = [&](const char* what) { long t = C.add + C.mul + C.div + C.sqrt; printf("%-34s add %4ld mul %4ld div %3ld sqrt %2ld total %5ld\n", what, C.add, C.mul, C.div, C.sqrt, t); C = Cnt(); return t; };
   C = Cnt(); long total = 0;
   { CF q[7]; for (int m=0;m<7;m++) q[m]=a.q[m]; source_step(q, a.c2, mk(0.001,false,false)); } total += 2 * snap("source half step (x2 per cell)");
-  { Cell<CF> c = a; derive(P, c); } total += snap("primitives, sqrt(h), wave speed");
+  { Cell<CF> c = a; derive(P, c); c.eta = c.h + c.b; } total += snap("primitives, sqrt(h), wave speed");
   Side<CF> sa, sb; side_of<0>(a, sa); side_of<0>(b, sb); C = Cnt();
   Waves<CF> W; Eig<CF> E; riemann<0>(P, sa, sb, W, E); total += 2 * snap("normal solve (x2 per cell)");
   CF d[7]; family_dots<0>(W, W, d); total += 2 * snap("neighbour dot products (x2)");

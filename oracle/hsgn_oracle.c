@@ -254,8 +254,9 @@ static void stage_solve(double k, double c2, const double R[4], double X[4])
     double det = a * d + 18.0 * k * kc2;
     double r1 = R[1] + 12.0 * k * R[2];
     double r3 = R[3] - 6.0 * kc2 * R[0];
-    double x1 = (d * r1 - 6.0 * k * r3) / det;
-    double x3 = (a * r3 + 3.0 * kc2 * r1) / det;
+    double idet = 1.0 / det;
+    double x1 = (d * r1 - 6.0 * k * r3) * idet;
+    double x3 = (a * r3 + 3.0 * kc2 * r1) * idet;
     X[0] = R[0] + k * x3;
     X[1] = x1;
     X[2] = R[2] - kc2 * x1;
@@ -342,14 +343,15 @@ static void side_from_q(const orc_params *P, const double *q, side_t *s)
     memset(s, 0, sizeof(*s));
     s->h = q[IH] > 0.0 ? q[IH] : 0.0;
     if (q[IH] > P->dry_tol) {
+        double ih = 1.0 / q[IH];
         s->h = q[IH];
         s->hun = q[IHU];
-        s->un = q[IHU] / q[IH];
-        s->ut = q[IHV] / q[IH];
-        s->w = q[IHW] / q[IH];
-        s->sg = q[IHS] / q[IH];
-        s->p = q[IHP] / q[IH];
-        s->pb = q[IHPB] / q[IH];
+        s->un = q[IHU] * ih;
+        s->ut = q[IHV] * ih;
+        s->w = q[IHW] * ih;
+        s->sg = q[IHS] * ih;
+        s->p = q[IHP] * ih;
+        s->pb = q[IHPB] * ih;
         s->hp = q[IHP];
     }
 }
@@ -392,15 +394,15 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
     /* Roe-type interface state: arithmetic means of h and c^2, sqrt(h)
      * weighted means of the primitive variables */
     double sqL = sqrt(L.h), sqR = sqrt(R.h);
-    double den = sqL + sqR;
+    double iden = 1.0 / (sqL + sqR);
     double hh = 0.5 * (L.h + R.h);
     double c2h = 0.5 * (cl + cr);
-    double uh = (sqR * R.un + sqL * L.un) / den;
-    double vh = (sqR * R.ut + sqL * L.ut) / den;
-    double wh = (sqR * R.w + sqL * L.w) / den;
-    double sh = (sqR * R.sg + sqL * L.sg) / den;
-    double ph = (sqR * R.p + sqL * L.p) / den;
-    double pbh = (sqR * R.pb + sqL * L.pb) / den;
+    double uh = (sqR * R.un + sqL * L.un) * iden;
+    double vh = (sqR * R.ut + sqL * L.ut) * iden;
+    double wh = (sqR * R.w + sqL * L.w) * iden;
+    double sh = (sqR * R.sg + sqL * L.sg) * iden;
+    double ph = (sqR * R.p + sqL * L.p) * iden;
+    double pbh = (sqR * R.pb + sqL * L.pb) * iden;
 
     double psi = sensor(P, bl, br);
     double db = br - bl;
@@ -449,12 +451,12 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
          * surface elevation in place of h in the state jump so that the
          * ocean at rest stays exactly at rest.  Remaining components travel
          * as contacts at the Roe speed. */
-        double ds = smax - smin;
+        double ids = 1.0 / (smax - smin);
         double dq0 = deta, dq1 = R.hun - L.hun;
-        double z1h = smin * ((smax * dq0 - df[0]) / ds);
-        double z1m = smin * ((smax * dq1 - df[1]) / ds);
-        double z7h = smax * ((df[0] - smin * dq0) / ds);
-        double z7m = smax * ((df[1] - smin * dq1) / ds);
+        double z1h = smin * ((smax * dq0 - df[0]) * ids);
+        double z1m = smin * ((smax * dq1 - df[1]) * ids);
+        double z7h = smax * ((df[0] - smin * dq0) * ids);
+        double z7m = smax * ((df[1] - smin * dq1) * ids);
         double S = z1h + z7h;
         double r1[7] = {z1h, z1m, vh * z1h, wh * z1h, sh * z1h, ph * z1h, pbh * z1h};
         double r7[7] = {z7h, z7m, vh * z7h, wh * z7h, sh * z7h, ph * z7h, pbh * z7h};
@@ -467,11 +469,12 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
     } else {
     /* f-wave coefficients: eigenvectors of Appendix C with the Einfeldt
      * speeds in place of u -+ Ce in the two acoustic eigenvectors */
-    double b2 = ((c2h + ph) * df[0] - df[5]) / ce2;
+    double ids = 1.0 / (smax - smin);
+    double b2 = ((c2h + ph) * df[0] - df[5]) * (1.0 / ce2);
     double S = df[0] - b2;
     double T = df[1] - uh * b2;
-    double b1 = (smax * S - T) / (smax - smin);
-    double b7 = (T - smin * S) / (smax - smin);
+    double b1 = (smax * S - T) * ids;
+    double b7 = (T - smin * S) * ids;
     double bs = df[4] - sh * S;
     double bw = df[3] - wh * S;
     double bv = df[2] - vh * S;
@@ -557,11 +560,12 @@ int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
 static void trans_split(const orc_params *P, const eig_t *e, const double *a,
                         int sgn, double *out)
 {
-    double g2 = ((e->c2h + e->ph) * a[0] - a[5]) / e->ce2;
+    double g2 = ((e->c2h + e->ph) * a[0] - a[5]) * (1.0 / e->ce2);
     double S = a[0] - g2;
     double T = a[1] - e->uh * g2;
-    double g1 = (e->smax * S - T) / (e->smax - e->smin);
-    double g7 = (T - e->smin * S) / (e->smax - e->smin);
+    double ids = 1.0 / (e->smax - e->smin);
+    double g1 = (e->smax * S - T) * ids;
+    double g7 = (T - e->smin * S) * ids;
     double gt = a[2] - e->vh * S;
     double gw = a[3] - e->wh * S;
     double gs = a[4] - e->sh * S;

@@ -177,8 +177,8 @@ HSGN_HD void stage_solve(T k, T c2, const T R[4], T X[4])
     T idet = recip(det);
     T r2 = R[1] + (T)12 * k * R[2];
     T r4 = R[3] - (T)6 * kc2 * R[0];
-    T x2 = quot(d * r2 - (T)6 * k * r4, det, idet);
-    T x4 = quot(a * r4 + (T)3 * kc2 * r2, det, idet);
+    T x2 = (d * r2 - (T)6 * k * r4) * idet;
+    T x4 = (a * r4 + (T)3 * kc2 * r2) * idet;
     X[0] = R[0] + k * x4;
     X[1] = x2;
     X[2] = R[2] - kc2 * x2;
@@ -228,9 +228,9 @@ HSGN_HD void derive(const StepParams &P, Cell<T> &c)
     if (c.wet) {
         T h = c.q[IH];
         T ih = recip(h);
-        c.u = quot(c.q[IHU], h, ih); c.v = quot(c.q[IHV], h, ih);
-        c.w = quot(c.q[IHW], h, ih); c.s = quot(c.q[IHS], h, ih);
-        c.p = quot(c.q[IHP], h, ih); c.pb = quot(c.q[IHPB], h, ih);
+        c.u = c.q[IHU] * ih; c.v = c.q[IHV] * ih;
+        c.w = c.q[IHW] * ih; c.s = c.q[IHS] * ih;
+        c.p = c.q[IHP] * ih; c.pb = c.q[IHPB] * ih;
         T a = (T)P.g * c.h + c.p + c.c2;
         c.hyp = a >= (T)0;
         c.ce = sqrt(a > (T)0 ? a : (T)0);
@@ -331,12 +331,12 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     T iden = recip(den);
     T hh = (T)0.5 * (L.h + R.h);
     T c2h = (T)0.5 * (L.c2 + R.c2);
-    T uh = quot(sqR * R.un + sqL * L.un, den, iden);
-    T vh = quot(sqR * R.ut + sqL * L.ut, den, iden);
-    T wh = quot(sqR * R.w + sqL * L.w, den, iden);
-    T sh = quot(sqR * R.s + sqL * L.s, den, iden);
-    T ph = quot(sqR * R.p + sqL * L.p, den, iden);
-    T pbh = quot(sqR * R.pb + sqL * L.pb, den, iden);
+    T uh = (sqR * R.un + sqL * L.un) * iden;
+    T vh = (sqR * R.ut + sqL * L.ut) * iden;
+    T wh = (sqR * R.w + sqL * L.w) * iden;
+    T sh = (sqR * R.s + sqL * L.s) * iden;
+    T ph = (sqR * R.p + sqL * L.p) * iden;
+    T pbh = (sqR * R.pb + sqL * L.pb) * iden;
 
     T psi = sensor(P, L.b, R.b);
     T db = R.b - L.b;
@@ -377,11 +377,10 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     if (L.c2 == (T)0 && R.c2 == (T)0) {
         // SWE edge: HLLE waves carrying the surface-elevation jump
         T dq0 = deta, dq1 = R.hun - L.hun;
-        T ds = smax - smin;
-        T z1h = smin * quot(smax * dq0 - df[0], ds, ids);
-        T z1m = smin * quot(smax * dq1 - df[1], ds, ids);
-        T z7h = smax * quot(df[0] - smin * dq0, ds, ids);
-        T z7m = smax * quot(df[1] - smin * dq1, ds, ids);
+        T z1h = smin * ((smax * dq0 - df[0]) * ids);
+        T z1m = smin * ((smax * dq1 - df[1]) * ids);
+        T z7h = smax * ((df[0] - smin * dq0) * ids);
+        T z7m = smax * ((df[1] - smin * dq1) * ids);
         T S = z1h + z7h;
         n0[0] = z1h; n0[1] = z1m; n0[2] = vh * z1h; n0[3] = wh * z1h;
         n0[4] = sh * z1h; n0[5] = ph * z1h; n0[6] = pbh * z1h;
@@ -406,11 +405,11 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
         } else {
             num = (c2h + ph) * df[0] - df[5];
         }
-        T b2 = quot(num, ce2, ice2);
+        T b2 = num * ice2;
         T S = df[0] - b2;
         T Tm = df[1] - uh * b2;
-        T b1 = quot(smax * S - Tm, smax - smin, ids);
-        T b7 = quot(Tm - smin * S, smax - smin, ids);
+        T b1 = (smax * S - Tm) * ids;
+        T b7 = (Tm - smin * S) * ids;
         n0[0] = b1; n0[1] = b1 * smin; n0[2] = b1 * vh; n0[3] = b1 * wh;
         n0[4] = b1 * sh; n0[5] = b1 * (c2h + ph); n0[6] = b1 * pbh;
         n6[0] = b7; n6[1] = b7 * smax; n6[2] = b7 * vh; n6[3] = b7 * wh;
@@ -578,11 +577,11 @@ HSGN_HD void trans_split(const Eig<T> &E, const T *a, int sgn, T *out)
     const int IN = DIR == 0 ? IHU : IHV;
     const int IT = DIR == 0 ? IHV : IHU;
     T an[7] = {a[IH], a[IN], a[IT], a[IHW], a[IHS], a[IHP], a[IHPB]};
-    T g2 = quot(E.c2p * an[0] - an[5], E.ce2, E.inv_ce2);
+    T g2 = (E.c2p * an[0] - an[5]) * E.inv_ce2;
     T S = an[0] - g2;
     T Tm = an[1] - E.uh * g2;
-    T g1 = quot(E.smax * S - Tm, E.smax - E.smin, E.inv_ds);
-    T g7 = quot(Tm - E.smin * S, E.smax - E.smin, E.inv_ds);
+    T g1 = (E.smax * S - Tm) * E.inv_ds;
+    T g7 = (Tm - E.smin * S) * E.inv_ds;
     T gt = an[2] - E.vh * S;
     T gw = an[3] - E.wh * S;
     T gs = an[4] - E.sh * S;

@@ -305,7 +305,7 @@ class AmrOracle:
         wet = q[0] > self.P.dry_tol
         if self.P.splitting:
             if wet and not swe:
-                q = O.source_cell(q, self._c2(b, phi, brk), tau)
+                q = O.source_cell(q, self._c2(b, phi, brk), tau, getattr(self.P, "model", 0))
             else:
                 q[3:] = 0.0
         elif (not wet) or swe:

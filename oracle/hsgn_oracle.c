@@ -281,6 +281,33 @@ void orc_source_cell(double *q, double c2, double tau)
     q[IHW] = Y2[0]; q[IHS] = Y2[1]; q[IHP] = Y2[2]; q[IHPB] = Y2[3];
 }
 
+/* mbHSGN source (Sec. 3, eq. mbHSGN): d(hw)/dt = 3 p / 2 and
+ * d(hp)/dt = -2 c^2 w, i.e. dY/dt = (1/h) [[0, 3/2], [-2 c^2, 0]] Y for
+ * Y = (hw, hp), by the same SDIRK(2,2).  A stage (I - k M) X = R has the
+ * closed form X0 = (R0 + 3/2 k R1) / det, X1 = (R1 - 2 c^2 k R0) / det with
+ * det = 1 + 3 c^2 k^2. */
+static void stage_solve_mb(double k, double c2, const double R[2], double X[2])
+{
+    double kc2 = k * c2;
+    double idet = 1.0 / (1.0 + 3.0 * k * kc2);
+    X[0] = (R[0] + 1.5 * k * R[1]) * idet;
+    X[1] = (R[1] - 2.0 * kc2 * R[0]) * idet;
+}
+
+void orc_source_cell_mb(double *q, double c2, double tau)
+{
+    double gam = 1.0 - 1.0 / sqrt(2.0);
+    double th = tau / q[IH];
+    double k = gam * th;
+    double Y[2] = {q[IHW], q[IHP]};
+    double Y1[2], R[2], Y2[2];
+    stage_solve_mb(k, c2, Y, Y1);
+    double MY[2] = {1.5 * Y1[1], -2.0 * c2 * Y1[0]};
+    for (int r = 0; r < 2; r++) R[r] = Y[r] + (1.0 - gam) * (th * MY[r]);
+    stage_solve_mb(k, c2, R, Y2);
+    q[IHW] = Y2[0]; q[IHP] = Y2[1];
+}
+
 /* apply the source step of length tau to one cell, or clear the auxiliary
  * variables of a dry or SWE cell (SWE region: c^2 -> 0 with p -> 0) */
 static void source_or_clear(orc_grid *g, size_t k, double tau, double *qc)
@@ -288,7 +315,8 @@ static void source_or_clear(orc_grid *g, size_t k, double tau, double *qc)
     int wet = qc[IH] > g->P.dry_tol;
     int swe = !g->phi[k] || g->brk[k];
     if (wet && !swe) {
-        orc_source_cell(qc, cell_c2(g, k), tau);
+        if (g->P.model == 1) orc_source_cell_mb(qc, cell_c2(g, k), tau);
+        else orc_source_cell(qc, cell_c2(g, k), tau);
     } else {
         qc[IHW] = 0.0; qc[IHS] = 0.0; qc[IHP] = 0.0; qc[IHPB] = 0.0;
     }
@@ -415,12 +443,21 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
      * Delta(g h^2 / 2) + g h^ Delta b exactly. */
     double df[7];
     df[0] = R.hun - L.hun;
-    df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * pbh * db;
     df[2] = R.hun * R.ut - L.hun * L.ut;
     df[3] = R.hun * R.w - L.hun * L.w;
     df[4] = R.hun * R.sg - L.hun * L.sg;
-    df[5] = (R.hun * (R.p + cr) - L.hun * (L.p + cl)) - c2h * uh * dh;
     df[6] = (R.hun * R.pb - L.hun * L.pb) - 6.0 * c2h * uh * psi * db;
+    if (P->model == 1) {
+        /* mbHSGN has no p_b equation: its plane stays zero */
+        df[6] = 0.0;
+        /* mbHSGN (eq. mbHSGN): momentum bathymetry term (g h + 3/2 psi p) db,
+         * hp row d(u h p) + c^2 d(hu) - c^2 u (d eta + psi db) (Sec. 4) */
+        df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * (1.5 * ph) * db;
+        df[5] = ((R.hun * R.p - L.hun * L.p) + c2h * df[0]) - c2h * uh * (deta + psi * db);
+    } else {
+        df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * pbh * db;
+        df[5] = (R.hun * (R.p + cr) - L.hun * (L.p + cl)) - c2h * uh * dh;
+    }
 
     /* Einfeldt speeds from the eigenvalue bound u +- sqrt(g h + p + c^2) */
     double ce2 = g * hh + ph + c2h;

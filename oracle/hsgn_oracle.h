@@ -56,6 +56,8 @@ typedef struct orc_params {
     int limiter;        /* 0 first order, 1 minmod, 2 MC, 3 unlimited */
     int transverse;     /* 0 none, 2 transverse incl. corrections */
     int splitting;      /* 0 Lie, 1 Strang */
+    int model;          /* 0 HSGN (eq. HSGN), 1 mbHSGN (eq. mbHSGN: sigma and
+                           p_b stay zero) */
 } orc_params;
 
 typedef struct orc_grid orc_grid;
@@ -99,8 +101,10 @@ int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
                   double bL, double bR, double c2L, double c2R,
                   double *waves, double *speeds, double *amdq, double *apdq,
                   int *kind);
-/* SDIRK(2,2) source step of length tau on one cell (in place). */
+/* SDIRK(2,2) source step of length tau on one cell (in place): HSGN
+ * (4x4 system in hw, h sigma, hp, h p_b) and mbHSGN (2x2 in hw, hp). */
 void orc_source_cell(double *q, double c2, double tau);
+void orc_source_cell_mb(double *q, double c2, double tau);
 
 /* Patch sets.  orc_framed exposes the grid's framed arrays ([7][sy][sx]
  * state, [sy][sx] bathymetry, phi_T, latch and interface flags; sx = nx+4,

@@ -35,13 +35,14 @@ class OrcParams(ctypes.Structure):
                 ("xi1", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("cfl_max", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("nbr_n", ctypes.c_int), ("limiter", ctypes.c_int),
-                ("transverse", ctypes.c_int), ("splitting", ctypes.c_int)]
+                ("transverse", ctypes.c_int), ("splitting", ctypes.c_int),
+                ("model", ctypes.c_int)]
 
 
 def _params(p) -> OrcParams:
     return OrcParams(p.g, p.alpha, p.eta0, p.h_star, p.dry_tol, p.xi0, p.xi1,
                      p.cfl, p.cfl_max, p.kappa, p.nbr_n, p.limiter,
-                     p.transverse, p.splitting)
+                     p.transverse, p.splitting, getattr(p, "model", 0))
 
 
 _lib = None
@@ -82,6 +83,7 @@ def lib():
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
         L.orc_source_cell.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+        L.orc_source_cell_mb.argtypes = [dp, ctypes.c_double, ctypes.c_double]
         ucp = ctypes.POINTER(ctypes.c_ubyte)
         L.orc_framed.argtypes = [ctypes.c_void_p, ctypes.POINTER(dp), ctypes.POINTER(dp),
                                  ctypes.POINTER(ucp), ctypes.POINTER(ucp), ctypes.POINTER(ucp),
@@ -278,7 +280,7 @@ def edge_dflux(params, direction, qL, qR, bL, bR, c2L, c2R):
     return df
 
 
-def source_cell(q, c2, tau):
+def source_cell(q, c2, tau, model=0):
     q = np.array(q, dtype=np.float64)
-    lib().orc_source_cell(_dp(q), c2, tau)
+    (lib().orc_source_cell_mb if model == 1 else lib().orc_source_cell)(_dp(q), c2, tau)
     return q

@@ -47,6 +47,7 @@ class Params:
     limiter: int = 2          # 0 first order, 1 minmod, 2 MC, 3 unlimited
     transverse: int = 2       # 0 none, 2 with corrections
     splitting: int = 1        # 0 Lie, 1 Strang
+    model: int = 0            # 0 HSGN, 1 mbHSGN
 
 
 @dataclasses.dataclass

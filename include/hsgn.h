@@ -75,7 +75,9 @@ extern "C" {
 #define HSGN_BC_EXTRAP   2   /* zeroth-order extrapolation */
 
 typedef struct hsgn_params {
-    int model;          /* 0 = HSGN (7 variables) */
+    int model;          /* 0 = HSGN (eq. HSGN, 7 variables); 1 = mbHSGN (eq.
+                           mbHSGN: the same 7-plane layout with h sigma and
+                           h p_b identically zero, which the library keeps) */
     int precision;      /* 0 = FP64; 1 = mixed: FP32 storage of eta' = h + b -
                            eta0 and FP32 arithmetic, FP64 for every edge with
                            an SWE or dry side, for cell fix-ups and mass sums */
@@ -169,6 +171,15 @@ int hsgn_get_clock(hsgn_ctx *c, int scenario, double *t, double *dt_next,
                    long long *steps);
 int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next,
                    long long steps);
+
+/* Tile-height autotuning: for every refinement level, times `trials`
+ * step-kernel launches (after one warm-up) for each candidate height in
+ * {8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64} on the current state, and keeps
+ * the fastest.  The state does not advance (the launches write only the
+ * spare buffer and the clocks are restored).  rows[nlevels] (may be NULL)
+ * receives the chosen heights.  Call after the state is set; drops the
+ * captured step graph.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int hsgn_autotune(hsgn_ctx *c, int trials, int *rows);
 
 /* Number of marching work items (wavefronts) of one step. */
 int hsgn_work_items(hsgn_ctx *c, int *n);

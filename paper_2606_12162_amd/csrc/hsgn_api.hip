@@ -352,6 +352,8 @@ struct hsgn_ctx {
     std::vector<ScenStatic> sstat;
     int nslot = 0, nlev = 1;
     bool any_amr = false;
+    std::vector<int> slot_scen, slot_level;   // scenario and level of each clock slot
+    std::vector<int> th_level;                // tile rows per refinement level
     std::vector<LevelRange> L;
     bool mixed = false;         // FP32 eta' storage with FP64 near-shore edges
     // device (FP64 storage: q0, q1, bath; mixed storage: f0, f1, fbath)
@@ -766,7 +768,8 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
 {
     if (!p || !out) return HSGN_EINVAL;
     *out = nullptr;
-    if (p->model != 0 || (p->precision != 0 && p->precision != 1)) return HSGN_ENOTSUP;
+    if ((p->model != 0 && p->model != 1) || (p->precision != 0 && p->precision != 1))
+        return HSGN_ENOTSUP;
     if (!(p->g > 0) || p->alpha < 0 || !(p->dry_tol >= 0) || !(p->cfl > 0) ||
         !(p->cfl_max >= p->cfl) || p->nbr_n < 0 || p->nbr_n > 2 || p->limiter < 0 ||
         p->limiter > 3 || (p->transverse != 0 && p->transverse != 2) ||
@@ -783,6 +786,7 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     P.eta0 = p->eta0; P.h_star = p->h_star; P.dry_tol = p->dry_tol;
     P.xi0 = p->xi0; P.xi1 = p->xi1; P.kappa = p->kappa;
     P.limiter = p->limiter; P.transverse = p->transverse; P.splitting = p->splitting;
+    P.model = p->model;
     *out = c;
     return HSGN_OK;
 }
@@ -840,6 +844,56 @@ static int choose_rows(const hsgn_ctx *c, int level)
         if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = th; }
     }
     return best;
+}
+
+// marching work items with tile heights th[level]: clock slots in order; on
+// level 0 the single grids come before the patch sets (they use different
+// kernel instantiations); fills each slot's work range and each level's
+// ranges
+static void build_work(const hsgn_ctx *c, const std::vector<int> &th, std::vector<WorkItem> &work,
+                       std::vector<ScenStatic> &sstat, std::vector<LevelRange> &L)
+{
+    const int nscen = (int)c->scen.size();
+    work.clear();
+    sstat.assign(c->nslot, ScenStatic());
+    auto add_slot_work = [&](int slot) {
+        int s = c->slot_scen[slot], l = c->slot_level[slot];
+        ScenStatic &ss = sstat[slot];
+        const PatchInfo &p0 = c->patches[c->scen[s].lev[l][0]];
+        ss.dx = p0.dx;
+        ss.dy = p0.dy;
+        ss.cfl = c->prm.cfl;
+        ss.cfl_max = c->prm.cfl_max;
+        ss.w0 = (int)work.size();
+        const int t = th[l];
+        for (int pid : c->scen[s].lev[l]) {
+            const PatchInfo &p = c->patches[pid];
+            for (int r0 = 0; r0 < p.ny; r0 += t)
+                for (int i0 = 0; i0 < p.nx; i0 += 60)
+                    work.push_back({pid, i0, r0, std::min(t, p.ny - r0)});
+        }
+        ss.w1 = (int)work.size();
+    };
+    L[0].w0 = 0;
+    L[0].s0 = 0;
+    L[0].s1 = nscen;
+    for (int s = 0; s < nscen; s++)
+        if (!c->scen[s].amr) add_slot_work(s);
+    L[0].wa = (int)work.size();
+    for (int s = 0; s < nscen; s++)
+        if (c->scen[s].amr) add_slot_work(s);
+    L[0].w1 = (int)work.size();
+    for (int l = 1; l < c->nlev; l++) {
+        L[l].w0 = L[l].wa = (int)work.size();
+        L[l].s0 = -1;
+        for (int slot = nscen; slot < c->nslot; slot++)
+            if (c->slot_level[slot] == l) {
+                if (L[l].s0 < 0) L[l].s0 = slot;
+                L[l].s1 = slot + 1;
+                add_slot_work(slot);
+            }
+        L[l].w1 = (int)work.size();
+    }
 }
 
 // geometry checks of the scenarios and level structure
@@ -969,47 +1023,11 @@ int hsgn_finalize(hsgn_ctx *c)
                 }
         c->L[l].e1 = c->etotal;
     }
-    // work items: slots in order; on level 0 single grids before patch sets
-    c->work.clear();
-    c->sstat.assign(c->nslot, ScenStatic());
-    auto add_slot_work = [&](int slot) {
-        int s = slot_scen[slot], l = slot_level[slot];
-        ScenStatic &ss = c->sstat[slot];
-        const PatchInfo &p0 = c->patches[c->scen[s].lev[l][0]];
-        ss.dx = p0.dx;
-        ss.dy = p0.dy;
-        ss.cfl = c->prm.cfl;
-        ss.cfl_max = c->prm.cfl_max;
-        ss.w0 = (int)c->work.size();
-        const int th = choose_rows(c, l);
-        for (int pid : c->scen[s].lev[l]) {
-            const PatchInfo &p = c->patches[pid];
-            for (int r0 = 0; r0 < p.ny; r0 += th)
-                for (int i0 = 0; i0 < p.nx; i0 += 60)
-                    c->work.push_back({pid, i0, r0, std::min(th, p.ny - r0)});
-        }
-        ss.w1 = (int)c->work.size();
-    };
-    c->L[0].w0 = 0;
-    c->L[0].s0 = 0;
-    c->L[0].s1 = nscen;
-    for (int s = 0; s < nscen; s++)
-        if (!c->scen[s].amr) add_slot_work(s);
-    c->L[0].wa = (int)c->work.size();
-    for (int s = 0; s < nscen; s++)
-        if (c->scen[s].amr) add_slot_work(s);
-    c->L[0].w1 = (int)c->work.size();
-    for (int l = 1; l < c->nlev; l++) {
-        c->L[l].w0 = c->L[l].wa = (int)c->work.size();
-        c->L[l].s0 = -1;
-        for (int slot = nscen; slot < c->nslot; slot++)
-            if (slot_level[slot] == l) {
-                if (c->L[l].s0 < 0) c->L[l].s0 = slot;
-                c->L[l].s1 = slot + 1;
-                add_slot_work(slot);
-            }
-        c->L[l].w1 = (int)c->work.size();
-    }
+    c->slot_scen = slot_scen;
+    c->slot_level = slot_level;
+    c->th_level.assign(c->nlev, 0);
+    for (int l = 0; l < c->nlev; l++) c->th_level[l] = choose_rows(c, l);
+    build_work(c, c->th_level, c->work, c->sstat, c->L);
     // patch-set tables, grouped by level
     {
         std::vector<std::vector<int>> lgc(c->nlev), lgi(c->nlev), lfr(c->nlev), lrf(c->nlev), lav(c->nlev);
@@ -1703,6 +1721,153 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
         if (err) return fail(c, err, std::string("scenario ") + std::to_string(s) + ": " + hsgn_strerror(err));
         if (st[s].steps < st[s].target) return fail(c, HSGN_ECFL, "too many rejected steps");
     }
+    return HSGN_OK;
+}
+
+// Autotuning of the tile height, per refinement level: every candidate is
+// timed with step-kernel launches over that level's patches on the current
+// state.  The launches write only the spare state buffer (no clock slot is
+// swapped), and the clock slots are restored afterwards, so the state does
+// not advance.
+int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
+{
+    if (!c || !c->finalized) return fail(c, HSGN_EINVAL, "call hsgn_finalize first");
+    if (trials < 1 || trials > 100) return fail(c, HSGN_EINVAL, "trials must be 1..100");
+    int rc = ensure_prepared(c);
+    if (rc) return rc;
+    std::vector<ScenState> saved, st;
+    if ((rc = pull_scen(c, saved))) return rc;
+    st = saved;
+    for (ScenState &x : st) {
+        x.active = 1;
+        x.err = 0;
+    }
+    if ((rc = push_scen(c, st))) return rc;
+    static const int cand[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64};
+    // scratch work table and clip slots for the largest candidate table
+    std::vector<int> th8(c->nlev, 8);
+    std::vector<WorkItem> wk;
+    std::vector<ScenStatic> ss;
+    std::vector<LevelRange> L = c->L;
+    build_work(c, th8, wk, ss, L);
+    WorkItem *dwork = nullptr;
+    double *dclip = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (dwork) (void)hipFree(dwork);
+        if (dclip) (void)hipFree(dclip);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&dwork, sizeof(WorkItem) * wk.size()) != hipSuccess ||
+        hipMalloc(&dclip, sizeof(double) * wk.size()) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(c, HSGN_ENOMEM, "autotune scratch");
+    }
+    std::vector<int> best = c->th_level;
+    for (int l = 0; l < c->nlev; l++) {
+        int maxny = 0;
+        for (const PatchInfo &p : c->patches)
+            if (p.level == l) maxny = std::max(maxny, p.ny);
+        // ghost frames of patch sets from the current states
+        const LevelRange &R = c->L[l];
+        if (c->mixed) {
+            AmrBuffers<float> B = amr_buffers<float>(c, c->f0, c->f1, c->fbath);
+            launch_halo_copy32(B, c->d_gc + R.gc0, R.gc1 - R.gc0, c->stream);
+            launch_halo_interp32(B, c->d_gi + R.gi0, R.gi1 - R.gi0, 1.0, c->prm.eta0,
+                                 c->prm.dry_tol, c->stream);
+        } else {
+            AmrBuffers<double> B = amr_buffers<double>(c, c->q0, c->q1, c->bath);
+            launch_halo_copy64(B, c->d_gc + R.gc0, R.gc1 - R.gc0, c->stream);
+            launch_halo_interp64(B, c->d_gi + R.gi0, R.gi1 - R.gi0, 1.0, c->prm.eta0,
+                                 c->prm.dry_tol, c->stream);
+        }
+        double best_ms = -1.0;
+        int prev = 0;
+        for (int th : cand) {
+            if (prev >= maxny) break;           // taller tiles give the same work table
+            prev = th;
+            std::vector<int> thl = c->th_level;
+            thl[l] = th;
+            build_work(c, thl, wk, ss, L);
+            const LevelRange &Q = L[l];
+            int n = Q.w1 - Q.w0;
+            if (n <= 0) continue;
+            if (hipMemcpyAsync(dwork, wk.data() + Q.w0, sizeof(WorkItem) * n, hipMemcpyHostToDevice,
+                               c->stream) != hipSuccess) {
+                cleanup();
+                return fail(c, HSGN_EDEVICE, "autotune upload");
+            }
+            int na = Q.wa - Q.w0;    // single-grid items first, then patch-set items
+            auto launch = [&]() {
+                if (na > 0) {
+                    if (c->mixed) {
+                        MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, na);
+                        A.work = dwork; A.clip_slots = dclip;
+                        launch_march32(A, (unsigned)na, c->stream);
+                    } else {
+                        MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, na);
+                        A.work = dwork; A.clip_slots = dclip;
+                        launch_march64(A, (unsigned)na, c->stream);
+                    }
+                }
+                if (n > na) {
+                    if (c->mixed) {
+                        MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, n - na);
+                        A.work = dwork + na; A.clip_slots = dclip + na;
+                        launch_march32_amr(A, (unsigned)(n - na), c->stream);
+                    } else {
+                        MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, n - na);
+                        A.work = dwork + na; A.clip_slots = dclip + na;
+                        launch_march64_amr(A, (unsigned)(n - na), c->stream);
+                    }
+                }
+            };
+            launch();                                   // warm-up
+            (void)hipEventRecord(e0, c->stream);
+            for (int t = 0; t < trials; t++) launch();
+            (void)hipEventRecord(e1, c->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                cleanup();
+                return fail(c, HSGN_EDEVICE, "autotune timing");
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (best_ms < 0.0 || ms < best_ms) { best_ms = ms; best[l] = th; }
+        }
+    }
+    cleanup();
+    HIPCHK(c, hipGetLastError());
+    if ((rc = push_scen(c, saved))) return rc;
+    // the chosen tile heights
+    std::vector<WorkItem> work;
+    std::vector<ScenStatic> sstat;
+    std::vector<LevelRange> L2 = c->L;
+    build_work(c, best, work, sstat, L2);
+    if (work.size() > c->work.size()) {
+        WorkItem *nw = nullptr;
+        double *nc = nullptr;
+        HIPCHK(c, hipMalloc(&nw, sizeof(WorkItem) * work.size()));
+        HIPCHK(c, hipMalloc(&nc, sizeof(double) * work.size()));
+        (void)hipFree(c->d_work);
+        (void)hipFree(c->clip);
+        c->d_work = nw;
+        c->clip = nc;
+    }
+    HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * work.size(), c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_work, work.data(), sizeof(WorkItem) * work.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_sstat, sstat.data(), sizeof(ScenStatic) * sstat.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->work = work;
+    c->sstat = sstat;
+    c->L = L2;
+    c->th_level = best;
+    drop_graph(c);
+    if (rows)
+        for (int l = 0; l < c->nlev; l++) rows[l] = best[l];
     return HSGN_OK;
 }
 

@@ -24,7 +24,8 @@ EXPORTS = ("hsgn_create", "hsgn_add_grid", "hsgn_finalize", "hsgn_set_bathymetry
            "hsgn_set_state", "hsgn_get_state", "hsgn_get_mask", "hsgn_set_mask",
            "hsgn_set_gauges", "hsgn_read_gauges", "hsgn_advance", "hsgn_diagnostics",
            "hsgn_get_clock", "hsgn_set_clock", "hsgn_work_items", "hsgn_set_timing",
-           "hsgn_get_timing", "hsgn_destroy", "hsgn_strerror", "hsgn_last_error")
+           "hsgn_get_timing", "hsgn_autotune", "hsgn_destroy", "hsgn_strerror",
+           "hsgn_last_error")
 
 
 class hsgn_params(ctypes.Structure):
@@ -73,6 +74,7 @@ def lib():
         L.hsgn_set_gauges.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp]
         L.hsgn_read_gauges.argtypes = [vp, ctypes.c_int, dp, dp, ctypes.c_int, ip]
         L.hsgn_advance.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+        L.hsgn_autotune.argtypes = [vp, ctypes.c_int, ip]
         L.hsgn_diagnostics.argtypes = [vp, ctypes.c_int, ctypes.POINTER(hsgn_diag)]
         L.hsgn_get_clock.argtypes = [vp, ctypes.c_int, dp, dp, dp]
         L.hsgn_set_clock.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -98,7 +100,8 @@ def _strerror(code):
 
 def make_params(p, tile_rows=0, precision=0) -> hsgn_params:
     """hsgn_params from a workloads.Params."""
-    return hsgn_params(0, precision, p.g, p.alpha, p.eta0, p.h_star, p.dry_tol, p.xi0, p.xi1,
+    return hsgn_params(getattr(p, "model", 0), precision, p.g, p.alpha, p.eta0, p.h_star,
+                       p.dry_tol, p.xi0, p.xi1,
                        p.cfl, p.cfl_max, p.kappa, p.nbr_n, p.limiter, p.transverse,
                        p.splitting, tile_rows)
 
@@ -236,6 +239,13 @@ class Context:
         self._check(lib().hsgn_get_timing(self.h, ctypes.byref(ms), ctypes.byref(n)),
                     "hsgn_get_timing")
         return ms.value, n.value
+
+    def autotune(self, trials=3):
+        """time the candidate tile heights per refinement level on the
+        current state (which does not advance); returns the chosen heights"""
+        rows = (ctypes.c_int * 8)()
+        self._check(lib().hsgn_autotune(self.h, int(trials), rows), "hsgn_autotune")
+        return [rows[k] for k in range(8) if rows[k] > 0]
 
     def work_items(self):
         n = ctypes.c_int()

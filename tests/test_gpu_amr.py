@@ -194,3 +194,44 @@ def test_adaptive_step_is_refused_for_patch_sets():
     ctx, ids = H.from_amr_workloads([w])
     assert ctx.advance_status(0.0, 1) == H.HSGN_ENOTSUP
     ctx.close()
+
+
+def test_autotune_per_level_keeps_state_and_results():
+    w = W.amr_small(steps=3)
+    a, ids = H.from_amr_workloads([w])
+    b, _ = H.from_amr_workloads([w])
+    before = [b.get_state(pid) for pid in ids[0]]
+    rows = b.autotune(trials=2)
+    print("tile rows per level", rows, flush=True)
+    assert len(rows) == 3
+    for pid, q in zip(ids[0], before):
+        assert np.array_equal(b.get_state(pid), q)
+    a.advance(-1.0, w.steps)
+    b.advance(-1.0, w.steps)
+    for pid in ids[0]:
+        assert np.array_equal(a.get_state(pid), b.get_state(pid))
+    a.close()
+    b.close()
+
+
+def test_full_size_amr_ocean_properties():
+    """the three-level AMR ocean of the benchmark at full size (2506 patches):
+    FP64 mass conserved to round-off over level-0 steps 2..4, and the mixed
+    form's gauges within 1e-4 of the amplitude of the FP64 run"""
+    w = W.amr_ocean()
+    print("case", w.name, flush=True)
+    gauges = {}
+    for precision in (0, 1):
+        ctx, ids = H.from_amr_workloads([w], precision=precision)
+        ctx.advance(-1.0, 1)
+        m1 = ctx.diagnostics(0)["mass"]
+        ctx.advance(-1.0, 3)
+        d = ctx.diagnostics(0)
+        drift = abs(d["mass"] - m1 - d["clipped_mass"]) / m1
+        print("precision", precision, "relative mass drift", drift, flush=True)
+        assert drift <= (1e-14 if precision == 0 else 1e-6)
+        gauges[precision] = ctx.read_gauges(0)[1]
+        ctx.close()
+    err = np.abs(gauges[1] - gauges[0]).max() / w.amplitude
+    print("mixed vs FP64 gauge error / amplitude", err)
+    assert err <= 1e-4

@@ -129,3 +129,44 @@ def test_per_scenario_step_requires_clock():
         ctx.set_bathymetry(s, w.b)
         ctx.set_state(s, w.q)
     assert ctx.advance_status(-1.0, 1) == H.HSGN_EINVAL
+
+
+def test_full_ensemble_launch_two_scenarios_against_oracle():
+    """the 48-scenario ensemble of the benchmark at full size, in its launch
+    configuration: two of its scenarios (the smallest and the largest grid)
+    compared with the oracle after 2 steps in FP64, and the mixed form's
+    gauges for all 48 against the FP64 run"""
+    ws = W.ensemble()
+    sizes = [w.grid.nx for w in ws]
+    picks = [int(np.argmin(sizes)), int(np.argmax(sizes))]
+    runs = {}
+    for precision in (0, 1):
+        ctx = H.Context(ws[0].params, precision=precision)
+        for s, w in enumerate(ws):
+            ctx.add_grid(s, w.grid)
+        ctx.finalize()
+        for s, w in enumerate(ws):
+            ctx.set_bathymetry(s, w.b)
+            ctx.set_state(s, w.q)
+            ctx.set_gauges(s, w.gauges)
+            ctx.set_clock(s, 0.0, w.dt, 0)
+        ctx.advance(-1.0, 2)
+        runs[precision] = ctx
+    for s in picks:
+        w = ws[s]
+        print("case", w.name, flush=True)
+        r = O.from_workload(w)
+        r.advance(w.dt, 2)
+        got, exp = runs[0].get_state(s), r.get_state()
+        scale = np.abs(exp).max(axis=(1, 2))
+        err = np.abs(got - exp).max(axis=(1, 2)) / np.where(scale > 0, scale, 1.0)
+        assert err.max() <= 1e-11, err
+    worst = 0.0
+    for s, w in enumerate(ws):
+        _, e0 = runs[0].read_gauges(s)
+        _, e1 = runs[1].read_gauges(s)
+        worst = max(worst, float(np.abs(e1 - e0).max()) / w.amplitude)
+    print("mixed vs FP64 gauge error / amplitude over 48 scenarios", worst)
+    assert worst <= 1e-4
+    for ctx in runs.values():
+        ctx.close()

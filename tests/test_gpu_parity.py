@@ -197,3 +197,25 @@ def test_non_hyperbolic_and_non_finite_states_are_reported():
     ctx = H.from_workloads([w])
     ctx.set_state(0, q)
     assert ctx.advance_status(0.002, 2) in (H.HSGN_ENAN, H.HSGN_ENONHYP)
+
+
+def test_autotune_keeps_the_state_and_the_results():
+    """the autotuner times step launches on the current state without
+    advancing it; the run after it equals a run with the model's tiles"""
+    w = W.beach_soliton(n=256, dx=0.2, steps=40)
+    a = H.from_workloads([w])
+    a.advance(0.0, 10)
+    b = H.from_workloads([w])
+    b.advance(0.0, 10)
+    q0, t0 = b.get_state(0), b.clock(0)
+    rows = b.autotune(trials=2)
+    print("case", w.name, "tile rows", rows, flush=True)
+    assert len(rows) == 1 and 8 <= rows[0] <= 64
+    assert np.array_equal(b.get_state(0), q0) and b.clock(0) == t0
+    a.advance(0.0, 30)
+    b.advance(0.0, 30)
+    assert np.array_equal(a.get_state(0), b.get_state(0))
+    assert np.array_equal(a.get_mask(0), b.get_mask(0))
+    assert a.clock(0) == b.clock(0)
+    a.close()
+    b.close()

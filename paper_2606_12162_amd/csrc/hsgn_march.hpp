@@ -493,33 +493,62 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                                          : acc[sk2][m];
             qn[IH] = depth_of<T, MIXED>(P, acc[sk2][IH], bb);
             source_or_clear(P, qn, c2, swe, tau_post);
-            // fix-ups in FP64: the depth from the stored variable, clipping
-            // (mass bookkeeping in FP64), dry cells, breaking latch, SWE cells
-            double bD = (double)bb;
-            double hD = MIXED ? (double)acc[sk2][IH] + P.eta0 - bD : (double)acc[sk2][IH];
-            double qd[7];
-            HSGN_UNROLL
-            for (int m = 1; m < 7; m++) qd[m] = (double)qn[m];
-            if (hD < 0.0) {
-                clip += -hD * pi.dx * pi.dy;
-                hD = 0.0;
-            }
-            if (hD <= P.dry_tol) {
+            // fix-ups: clipping (the clipped mass summed in FP64), dry cells,
+            // breaking latch (eta - eta0 > kappa H), SWE cells.  FP64: on h
+            // as the oracle does; mixed precision: in FP32 on the stored
+            // deviation eta' directly.
+            S out0;
+            S qs[7];
+            bool bad;
+            if constexpr (MIXED) {
+                T eta = acc[sk2][IH];
+                T h = eta + (T)P.eta0 - bb;
+                if (h < (T)0) {
+                    clip += -(double)h * pi.dx * pi.dy;
+                    h = (T)0;
+                    eta = bb - (T)P.eta0;
+                }
+                const bool dry = !(h > (T)P.dry_tol);
+                if (dry) {
+                    HSGN_UNROLL
+                    for (int m = 1; m < 7; m++) qn[m] = (T)0;
+                } else if (P.kappa > 0.0 && phi && !brk) {
+                    T H = tmax((T)P.eta0 - bb, (T)0);
+                    if (eta > (T)P.kappa * H) brk = 1;
+                }
+                if (!phi || brk || dry) {
+                    qn[IHW] = (T)0; qn[IHS] = (T)0; qn[IHP] = (T)0; qn[IHPB] = (T)0;
+                }
+                out0 = (S)eta;
+                bad = !finite_val<T>(eta);
                 HSGN_UNROLL
-                for (int m = 1; m < 7; m++) qd[m] = 0.0;
-            } else if (P.kappa > 0.0 && phi && !brk) {
-                double H = P.eta0 - bD;
-                H = H > 0.0 ? H : 0.0;
-                if (hD + bD - P.eta0 > P.kappa * H) brk = 1;
+                for (int m = 1; m < 7; m++) { qs[m] = (S)qn[m]; bad = bad || !finite_val<T>(qn[m]); }
+            } else {
+                double hD = (double)acc[sk2][IH];
+                double qd[7];
+                HSGN_UNROLL
+                for (int m = 1; m < 7; m++) qd[m] = (double)qn[m];
+                if (hD < 0.0) {
+                    clip += -hD * pi.dx * pi.dy;
+                    hD = 0.0;
+                }
+                if (hD <= P.dry_tol) {
+                    HSGN_UNROLL
+                    for (int m = 1; m < 7; m++) qd[m] = 0.0;
+                } else if (P.kappa > 0.0 && phi && !brk) {
+                    double bD = (double)bb;
+                    double H = P.eta0 - bD;
+                    H = H > 0.0 ? H : 0.0;
+                    if (hD + bD - P.eta0 > P.kappa * H) brk = 1;
+                }
+                if (!phi || brk || hD <= P.dry_tol) {
+                    qd[IHW] = 0.0; qd[IHS] = 0.0; qd[IHP] = 0.0; qd[IHPB] = 0.0;
+                }
+                out0 = (S)hD;
+                bad = !finite_val<double>(hD);
+                HSGN_UNROLL
+                for (int m = 1; m < 7; m++) { qs[m] = (S)qd[m]; bad = bad || !finite_val<double>(qd[m]); }
             }
-            if (!phi || brk || hD <= P.dry_tol) {
-                qd[IHW] = 0.0; qd[IHS] = 0.0; qd[IHP] = 0.0; qd[IHPB] = 0.0;
-            }
-            // stored plane-0 variable
-            S out0 = MIXED ? (S)(hD + bD - P.eta0) : (S)hD;
-            bool bad = !finite_val<double>(hD);
-            HSGN_UNROLL
-            for (int m = 1; m < 7; m++) bad = bad || !finite_val<double>(qd[m]);
             if (interior) {
                 if (bad) sc->err = -5;
                 long long idx = (long long)(k - 2) * pi.pitch + (wk.i0 - 2 + lane);
@@ -527,7 +556,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 S *qo = qout + pi.qoff + idx;
                 qo[0] = out0;
                 HSGN_UNROLL
-                for (int m = 1; m < 7; m++) qo[m * plane] = (S)qd[m];
+                for (int m = 1; m < 7; m++) qo[m * plane] = qs[m];
                 mout[pi.coff + idx] = (uint8_t)(phi | (brk << 1) | (AMR ? fl_w[sk2] << 2 : 0));
             }
         }

@@ -46,6 +46,7 @@ struct StepParams {
     int limiter;       // 0 first order, 1 minmod, 2 MC, 3 unlimited
     int transverse;    // 0 none, 2 with corrections
     int splitting;     // 0 Lie, 1 Strang
+    int model;         // 0 HSGN, 1 mbHSGN (sigma and p_b stay zero)
 };
 
 // one cell after loading and the first source half step
@@ -205,12 +206,44 @@ HSGN_HD void source_step(T *q, T c2, T tau)
     q[IHW] = Y2[0]; q[IHS] = Y2[1]; q[IHP] = Y2[2]; q[IHPB] = Y2[3];
 }
 
+// mbHSGN (eq. mbHSGN): d(hw)/dt = 3 p / 2, d(hp)/dt = -2 c^2 w, by the same
+// SDIRK(2,2); a stage (I - k M) X = R has X0 = (R0 + 3/2 k R1) / det,
+// X1 = (R1 - 2 c^2 k R0) / det, det = 1 + 3 c^2 k^2
+template <class T>
+HSGN_HD void stage_solve_mb(T k, T c2, const T R[2], T X[2])
+{
+    T kc2 = k * c2;
+    T idet = recip((T)1 + (T)3 * k * kc2);
+    X[0] = (R[0] + (T)1.5 * k * R[1]) * idet;
+    X[1] = (R[1] - (T)2 * kc2 * R[0]) * idet;
+}
+
+template <class T>
+HSGN_HD void source_step_mb(T *q, T c2, T tau)
+{
+    const T gam = (T)1 - (T)1 / sqrt((T)2);
+    T th = quot(tau, q[IH], recip(q[IH]));
+    T Y[2] = {q[IHW], q[IHP]};
+    T k = gam * th;
+    T Y1[2];
+    stage_solve_mb(k, c2, Y, Y1);
+    T w = (T)1 - gam;
+    T MY[2] = {(T)1.5 * Y1[1], (T)-2 * c2 * Y1[0]};
+    T R[2];
+    HSGN_UNROLL
+    for (int m = 0; m < 2; m++) R[m] = Y[m] + w * (th * MY[m]);
+    T Y2[2];
+    stage_solve_mb(k, c2, R, Y2);
+    q[IHW] = Y2[0]; q[IHP] = Y2[1];
+}
+
 // source step or clearing of the auxiliary variables (dry or SWE cell)
 template <class T>
 HSGN_HD void source_or_clear(const StepParams &P, T *q, T c2, int swe, T tau)
 {
     if (q[IH] > (T)P.dry_tol && !swe) {
-        source_step(q, c2, tau);
+        if (P.model == 1) source_step_mb(q, c2, tau);
+        else source_step(q, c2, tau);
     } else {
         q[IHW] = (T)0; q[IHS] = (T)0; q[IHP] = (T)0; q[IHPB] = (T)0;
     }
@@ -345,12 +378,21 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
 
     T df[7];
     df[0] = R.hun - L.hun;
-    df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * pbh * db;
     df[2] = R.hun * R.ut - L.hun * L.ut;
     df[3] = R.hun * R.w - L.hun * L.w;
     df[4] = R.hun * R.s - L.hun * L.s;
-    df[5] = (R.hun * (R.p + R.c2) - L.hun * (L.p + L.c2)) - c2h * uh * dh;
-    df[6] = (R.hun * R.pb - L.hun * L.pb) - (T)6 * c2h * uh * psi * db;
+    const bool mb = P.model == 1;
+    if (mb) {
+        // mbHSGN: (g h + 3/2 psi p) db in the momentum, and the hp row
+        // d(u h p) + c^2 d(hu) - c^2 u (d eta + psi db); no p_b equation
+        df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * ((T)1.5 * ph) * db;
+        df[5] = ((R.hun * R.p - L.hun * L.p) + c2h * df[0]) - c2h * uh * (deta + psi * db);
+        df[6] = (T)0;
+    } else {
+        df[1] = g * hh * deta + ((R.hun * R.un + R.hp) - (L.hun * L.un + L.hp)) + psi * pbh * db;
+        df[5] = (R.hun * (R.p + R.c2) - L.hun * (L.p + L.c2)) - c2h * uh * dh;
+        df[6] = (R.hun * R.pb - L.hun * L.pb) - (T)6 * c2h * uh * psi * db;
+    }
 
     T ce2 = g * hh + ph + c2h;
     if (!(ce2 > (T)0)) return false;
@@ -400,8 +442,11 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
         // leaving no difference of large numbers.  FP64 keeps the plain form.
         T num;
         if constexpr (sizeof(T) == 4) {
-            num = ph * df[0] - (R.hun * R.p - L.hun * L.p)
-                - (T)0.5 * (R.c2 - L.c2) * (R.hun + L.hun) + c2h * uh * dh;
+            if (mb)   // the c^2 d(hu) parts cancel exactly
+                num = ph * df[0] - (R.hun * R.p - L.hun * L.p) + c2h * uh * (deta + psi * db);
+            else
+                num = ph * df[0] - (R.hun * R.p - L.hun * L.p)
+                    - (T)0.5 * (R.c2 - L.c2) * (R.hun + L.hun) + c2h * uh * dh;
         } else {
             num = (c2h + ph) * df[0] - df[5];
         }

@@ -21,7 +21,7 @@ cell advanced one step of its own level).
 Inputs are synthetic (seeded generators in paper_2606_12162_amd/workloads.py)
 and resident in HBM before timing starts.  The step kernel issues far more
 vector ALU instructions than its HBM bytes need (about 20 flops per byte), so
-the JSON line's roofline is its algorithmic floating-point work, 1271 flops
+the JSON line's roofline is its algorithmic floating-point work, 1259 flops
 per cell update (counted by csrc/opcount.cpp), over its average launch time
 (HIP events on the library's stream), against the vector ALU peak of the chip
 (256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s, the same for FP64
@@ -47,7 +47,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12      # 78.6
 # algorithmic flops per cell update (csrc/opcount.cpp)
-ALG_FLOPS = 1271
+ALG_FLOPS = 1259
 # algorithmic bytes per cell update: read Q^n and write Q^{n+1} (7 variables),
 # read the bathymetry, read and write the mask byte
 ALG_BYTES = {"fp64": 7 * 8 * 2 + 8 + 2, "mixed": 7 * 4 * 2 + 4 + 2}
@@ -97,11 +97,13 @@ def make_context(H, ws, precision, tile_rows=0, gauges=True):
     return ctx
 
 
-def run(H, torch, ws, precision, steps, warmup, tile_rows=0):
-    """Advance the workloads; returns (context, seconds, kernel ms per launch)."""
+def run(H, torch, ws, precision, steps, warmup, tile_rows=0, autotune=True):
+    """Advance the workloads; returns (context, seconds, kernel ms per launch,
+    launches, tile rows per level)."""
     if hasattr(ws[0], "patches"):
-        return run_amr(H, torch, ws, precision, steps, warmup, tile_rows)
+        return run_amr(H, torch, ws, precision, steps, warmup, tile_rows, autotune)
     ctx = make_context(H, ws, precision, tile_rows)
+    rows = ctx.autotune() if autotune and not tile_rows else [tile_rows or "library"]
     dt = -1.0 if ws[0].dt > 0 else 0.0          # per-scenario fixed steps, or adaptive
     if warmup:
         ctx.advance(dt, warmup)
@@ -113,15 +115,16 @@ def run(H, torch, ws, precision, steps, warmup, tile_rows=0):
     el = time.perf_counter() - t0
     ms, n = ctx.get_timing()
     ctx.set_timing(False)
-    return ctx, el, ms / max(n, 1), n
+    return ctx, el, ms / max(n, 1), n, rows
 
 
-def run_amr(H, torch, ws, precision, steps, warmup, tile_rows=0):
+def run_amr(H, torch, ws, precision, steps, warmup, tile_rows=0, autotune=True):
     """Patch sets: the timed steps replay the captured level-0 step graph;
     a second, untimed-by-the-clock pass of the same number of steps with
     direct launches times every step-kernel launch with HIP events"""
     ctx, _ = H.from_amr_workloads(ws, tile_rows=tile_rows,
                                   precision=1 if precision == "mixed" else 0)
+    rows = ctx.autotune() if autotune and not tile_rows else [tile_rows or "library"]
     if warmup:
         ctx.advance(-1.0, warmup)
     torch.cuda.synchronize()
@@ -133,7 +136,7 @@ def run_amr(H, torch, ws, precision, steps, warmup, tile_rows=0):
     ctx.advance(-1.0, steps)
     ms, n = ctx.get_timing()
     ctx.set_timing(False)
-    return ctx, el, ms / max(n, 1), n
+    return ctx, el, ms / max(n, 1), n, rows
 
 
 def amr_updates(w):
@@ -178,7 +181,12 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="ensemble", choices=["ensemble", "beach", "ocean", "amr"])
-    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--model", default="hsgn", choices=["hsgn", "mbhsgn"],
+                    help="hsgn (eq. HSGN, default) or mbhsgn (eq. mbHSGN)")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="fixed tile height (default: the library's autotuner)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's tile-height model instead of its autotuner")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
@@ -217,6 +225,13 @@ def main():
     else:
         ws, precision = [W.beach_soliton()], "fp64"
     amr = args.workload == "amr"
+    if args.model == "mbhsgn":
+        import dataclasses
+        for w in ws:
+            w.params = dataclasses.replace(w.params, model=1)
+            for q in ([w.q] if not amr else [p.q for p in w.patches]):
+                q[4] = 0.0
+                q[6] = 0.0
     cells = sum(amr_updates(w) if amr else w.grid.nx * w.grid.ny for w in ws)
     log("bench: %s x%d, %.2f M cells, precision %s, inputs generated in %.1f s"
         % (ws[0].name, len(ws), cells / 1e6, precision, time.perf_counter() - t0))
@@ -225,14 +240,15 @@ def main():
     if args.sweep:
         best = None
         for th in [int(x) for x in args.sweep.split(",")]:
-            c, el, kms, n = run(H, torch, ws, precision, 20, 3, th)
+            c, el, kms, n, _ = run(H, torch, ws, precision, 20, 3, th)
             c.close()
             log("sweep: tile rows %d: step kernel %.1f us" % (th, kms * 1e3))
             if best is None or kms < best[0]:
                 best = (kms, th)
         tile_rows = best[1]
 
-    ctx, el, kms, launches = run(H, torch, ws, precision, args.steps, args.warmup, tile_rows)
+    ctx, el, kms, launches, rows = run(H, torch, ws, precision, args.steps, args.warmup, tile_rows,
+                                       not args.no_autotune)
     value = cells * args.steps / el
     # per timed step-kernel launch: the cells it advances (patch sets: the
     # launches of all levels together advance `cells` per level-0 step)
@@ -259,8 +275,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": ws[0].name if len(ws) == 1 else "ensemble_%d_scenarios" % len(ws),
                    "scenarios": len(ws), "cell_updates_per_step": cells, "precision": precision,
+                   "model": args.model,
                    "dt": "per-scenario fixed, cfl 0.9" if ws[0].dt > 0 else "adaptive, cfl 0.9",
-                   "work_items": ctx.work_items(), "tile_rows": tile_rows or "library",
+                   "work_items": ctx.work_items(), "tile_rows": rows,
                    "max_courant_scenario0": diag["max_courant"]},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
@@ -273,10 +290,11 @@ def main():
                                                   if traffic else None)}},
     }
     if precision == "mixed" and not args.no_fp64:
-        ctx64, el64, kms64, _ = run(H, torch, ws, "fp64", args.steps, args.warmup, tile_rows)
+        ctx64, el64, kms64, _, rows64 = run(H, torch, ws, "fp64", args.steps, args.warmup,
+                                            tile_rows, not args.no_autotune)
         out["fp64_plain"] = {"value": cells * args.steps / el64,
                              "ms_per_step": el64 * 1e3 / args.steps,
-                             "kernel_avg_us": kms64 * 1e3}
+                             "kernel_avg_us": kms64 * 1e3, "tile_rows": rows64}
         out["mixed_over_fp64"] = value / out["fp64_plain"]["value"]
         out["gauge_err_over_amp"] = gauge_error(ctx, ctx64, ws)
         log("fp64: %.3f ms/step; mixed/fp64 %.2fx; gauge error / amplitude %.2e"

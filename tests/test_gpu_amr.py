@@ -8,6 +8,8 @@ the amplitude.  The level-0 step of a patch set is replayed from a HIP
 graph; the runs below replay it several times with host reads in between
 and compare every intermediate state.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -215,21 +217,31 @@ def test_autotune_per_level_keeps_state_and_results():
 
 
 def test_full_size_amr_ocean_properties():
-    """the three-level AMR ocean of the benchmark at full size (2506 patches):
-    FP64 mass conserved to round-off over level-0 steps 2..4, and the mixed
-    form's gauges within 1e-4 of the amplitude of the FP64 run"""
-    w = W.amr_ocean()
-    print("case", w.name, flush=True)
+    """the three-level AMR ocean of the benchmark at full size (2506 patches),
+    with walls on the domain boundary so that no water leaves (the ring wave
+    crosses the open boundary of the benchmark case, where the level-0 mass
+    falls by 1.65e-10 of itself over these steps, as the oracle on level 0
+    alone shows too): FP64 mass conserved over level-0 steps 2..4 to the
+    rounding of the diagnostic itself, and the mixed form's gauges within
+    1e-4 of the amplitude of the FP64 run.
+
+    The diagnostic sums 256 patches of 128^2 cells: 16 cells per thread, a
+    10-level tree, then the 256 patch sums in order on the host, so each
+    evaluation carries at most about 280 ulps of relative rounding (3.1e-14);
+    the bar on the difference of two evaluations is 1e-13."""
+    w = dataclasses.replace(W.amr_ocean(), bc=(W.BC_WALL,) * 4)
+    print("case", w.name, "walls", flush=True)
     gauges = {}
     for precision in (0, 1):
         ctx, ids = H.from_amr_workloads([w], precision=precision)
         ctx.advance(-1.0, 1)
         m1 = ctx.diagnostics(0)["mass"]
+        c1 = ctx.diagnostics(0)["clipped_mass"]
         ctx.advance(-1.0, 3)
         d = ctx.diagnostics(0)
-        drift = abs(d["mass"] - m1 - d["clipped_mass"]) / m1
+        drift = abs(d["mass"] - m1 - (d["clipped_mass"] - c1)) / m1
         print("precision", precision, "relative mass drift", drift, flush=True)
-        assert drift <= (1e-14 if precision == 0 else 1e-6)
+        assert drift <= (1e-13 if precision == 0 else 1e-6)
         gauges[precision] = ctx.read_gauges(0)[1]
         ctx.close()
     err = np.abs(gauges[1] - gauges[0]).max() / w.amplitude

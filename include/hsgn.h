@@ -95,6 +95,10 @@ typedef struct hsgn_params {
     int transverse;     /* 0 none, 2 transverse waves incl. corrections */
     int splitting;      /* 0 Lie, 1 Strang */
     int tile_rows;      /* rows per marching tile; <= 0 lets the library choose */
+    double c2;          /* 0: c^2 = alpha^2 g H phi_T (Sec. 3.3); > 0: this fixed
+                           relaxation parameter c^2 (m^2/s^2) times phi_T, as in
+                           the steady-state tests of Sec. 5; negative or NaN
+                           is HSGN_EINVAL */
 } hsgn_params;
 
 typedef struct hsgn_diag {

@@ -166,6 +166,8 @@ class AmrOracle:
     def _c2(self, b, phi, brk):
         if not phi or brk:
             return 0.0
+        if getattr(self.P, "c2", 0.0) > 0.0:
+            return self.P.c2
         H = self.P.eta0 - b
         H = H if H > 0.0 else 0.0
         return self.P.alpha * self.P.alpha * self.P.g * H

@@ -115,10 +115,12 @@ static double still_depth(const orc_params *P, double b)
     return H > 0.0 ? H : 0.0;
 }
 
-/* c^2 = alpha^2 g H phi_T, zero in SWE cells (phi_T = 0 or breaking) */
+/* c^2 = alpha^2 g H phi_T, or the fixed c^2 of the run times phi_T; zero in
+   SWE cells (phi_T = 0 or breaking) */
 static double cell_c2(const orc_grid *g, size_t k)
 {
     if (!g->phi[k] || g->brk[k]) return 0.0;
+    if (g->P.c2 > 0.0) return g->P.c2;
     return g->P.alpha * g->P.alpha * g->P.g * still_depth(&g->P, g->b[k]);
 }
 

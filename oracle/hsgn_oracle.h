@@ -58,6 +58,9 @@ typedef struct orc_params {
     int splitting;      /* 0 Lie, 1 Strang */
     int model;          /* 0 HSGN (eq. HSGN), 1 mbHSGN (eq. mbHSGN: sigma and
                            p_b stay zero) */
+    double c2;          /* > 0: a fixed relaxation parameter c^2 in place of
+                           alpha^2 g H (the steady states of Sec. 5 fix c^2);
+                           still zero in SWE cells */
 } orc_params;
 
 typedef struct orc_grid orc_grid;

@@ -36,13 +36,14 @@ class OrcParams(ctypes.Structure):
                 ("cfl_max", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("nbr_n", ctypes.c_int), ("limiter", ctypes.c_int),
                 ("transverse", ctypes.c_int), ("splitting", ctypes.c_int),
-                ("model", ctypes.c_int)]
+                ("model", ctypes.c_int), ("c2", ctypes.c_double)]
 
 
 def _params(p) -> OrcParams:
     return OrcParams(p.g, p.alpha, p.eta0, p.h_star, p.dry_tol, p.xi0, p.xi1,
                      p.cfl, p.cfl_max, p.kappa, p.nbr_n, p.limiter,
-                     p.transverse, p.splitting, getattr(p, "model", 0))
+                     p.transverse, p.splitting, getattr(p, "model", 0),
+                     getattr(p, "c2", 0.0))
 
 
 _lib = None

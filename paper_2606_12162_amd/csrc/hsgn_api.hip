@@ -184,7 +184,7 @@ __global__ void initdt_kernel(PatchInfo pi, StepParams P, const S *q, const S *b
             int swe = !(mk & 1) || ((mk >> 1) & 1);
             double H = P.eta0 - b;
             H = H > 0.0 ? H : 0.0;
-            double c2 = swe ? 0.0 : P.a2g * H;
+            double c2 = swe ? 0.0 : P.a2g * H + P.c2f;
             double a = P.g * h + p + c2;
             if (a < 0.0) *err = HSGN_ENONHYP;
             double ce = sqrt(a);
@@ -773,7 +773,7 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     if (!(p->g > 0) || p->alpha < 0 || !(p->dry_tol >= 0) || !(p->cfl > 0) ||
         !(p->cfl_max >= p->cfl) || p->nbr_n < 0 || p->nbr_n > 2 || p->limiter < 0 ||
         p->limiter > 3 || (p->transverse != 0 && p->transverse != 2) ||
-        (p->splitting != 0 && p->splitting != 1) || !(p->xi1 > 0))
+        (p->splitting != 0 && p->splitting != 1) || !(p->xi1 > 0) || !(p->c2 >= 0))
         return HSGN_EINVAL;
     hsgn_ctx *c = new (std::nothrow) hsgn_ctx();
     if (!c) return HSGN_ENOMEM;
@@ -782,7 +782,8 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     c->stream = (hipStream_t)hip_stream;
     StepParams &P = c->P;
     P.g = p->g;
-    P.a2g = p->alpha * p->alpha * p->g;
+    P.a2g = p->c2 > 0.0 ? 0.0 : p->alpha * p->alpha * p->g;
+    P.c2f = p->c2 > 0.0 ? p->c2 : 0.0;
     P.eta0 = p->eta0; P.h_star = p->h_star; P.dry_tol = p->dry_tol;
     P.xi0 = p->xi0; P.xi1 = p->xi1; P.kappa = p->kappa;
     P.limiter = p->limiter; P.transverse = p->transverse; P.splitting = p->splitting;

@@ -182,7 +182,7 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
     brk = (r.mk >> 1) & 1;
     int swe = !phi || brk;
     T H = still_depth(P, c.b);
-    c.c2 = swe ? (T)0 : (T)P.a2g * H;
+    c.c2 = swe ? (T)0 : (T)P.a2g * H + (T)P.c2f;
     if (P.splitting) {
         source_or_clear(P, c.q, c.c2, swe, tau_pre);
     } else if (!(c.q[IH] > (T)P.dry_tol) || swe) {
@@ -484,7 +484,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             int phi = phi_w[sk2], brk = brk_w[sk2];
             int swe = !phi || brk;
             T bb = b_w[sk2];
-            T c2 = swe ? (T)0 : (T)P.a2g * still_depth(P, bb);
+            T c2 = swe ? (T)0 : (T)P.a2g * still_depth(P, bb) + (T)P.c2f;
             // depth in the compute type for the source step
             T qn[7];
             HSGN_UNROLL

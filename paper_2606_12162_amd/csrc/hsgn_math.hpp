@@ -41,7 +41,9 @@ enum { KIND_REGULAR = 0, KIND_WALL_R = 1, KIND_WALL_L = 2, KIND_DRY = 3 };
 // run parameters as the kernels see them
 struct StepParams {
     double g;
-    double a2g;        // alpha^2 g
+    double a2g;        // alpha^2 g, or 0 when c^2 is fixed
+    double c2f;        // the fixed c^2, or 0: a wet non-SWE cell has
+                       // c^2 = a2g H + c2f, one of the two terms zero
     double eta0, h_star, dry_tol, xi0, xi1, kappa;
     int limiter;       // 0 first order, 1 minmod, 2 MC, 3 unlimited
     int transverse;    // 0 none, 2 with corrections

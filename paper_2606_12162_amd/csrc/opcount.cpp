@@ -42,7 +42,7 @@ template <> inline CF tiny_norm<CF>() { return CF(1e-200); }
 }
 using namespace hsgn;
 int main() {
-  StepParams P; P.g = 9.81; P.a2g = 9 * 9.81; P.eta0 = 0; P.h_star = 0.05; P.dry_tol = 1e-3; P.xi0 = 0.01; P.xi1 = 0.05; P.kappa = 0.8; P.limiter = 2; P.transverse = 2; P.splitting = 1; P.model = 0;
+  StepParams P; P.g = 9.81; P.a2g = 9 * 9.81; P.c2f = 0; P.eta0 = 0; P.h_star = 0.05; P.dry_tol = 1e-3; P.xi0 = 0.01; P.xi1 = 0.05; P.kappa = 0.8; P.limiter = 2; P.transverse = 2; P.splitting = 1; P.model = 0;
   auto mkcell = [&](double h, double u, double v, double b) { Cell<CF> c; double q[7] = {h, h*u, h*v, 0.01*h, 0.02*h, 0.1*h, 0.15*h}; for (int m=0;m<7;m++) c.q[m]=mk(q[m],false,false); c.b = mk(b,false,false); c.c2 = mk(9*9.81*(-b),false,false); derive(P, c); c.eta = c.h + c.b; return c; };
   Cell<CF> a = mkcell(1.0, 0.1, 0.05, -1.0), b = mkcell(1.02, 0.12, 0.04, -0.98);
   auto snap = [&](const char* what) { long t = C.add + C.mul + C.div + C.sqrt; printf("%-34s add %4ld mul %4ld div %3ld sqrt %2ld total %5ld\n", what, C.add, C.mul, C.div, C.sqrt, t); C = Cnt(); return t; };

@@ -36,7 +36,7 @@ class hsgn_params(ctypes.Structure):
                 ("cfl_max", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("nbr_n", ctypes.c_int), ("limiter", ctypes.c_int),
                 ("transverse", ctypes.c_int), ("splitting", ctypes.c_int),
-                ("tile_rows", ctypes.c_int)]
+                ("tile_rows", ctypes.c_int), ("c2", ctypes.c_double)]
 
 
 class hsgn_diag(ctypes.Structure):
@@ -103,7 +103,7 @@ def make_params(p, tile_rows=0, precision=0) -> hsgn_params:
     return hsgn_params(getattr(p, "model", 0), precision, p.g, p.alpha, p.eta0, p.h_star,
                        p.dry_tol, p.xi0, p.xi1,
                        p.cfl, p.cfl_max, p.kappa, p.nbr_n, p.limiter, p.transverse,
-                       p.splitting, tile_rows)
+                       p.splitting, tile_rows, getattr(p, "c2", 0.0))
 
 
 def _ptr(a):
@@ -282,14 +282,14 @@ def from_amr_workloads(workloads, tile_rows=0, stream=None, gauges=True, precisi
     return ctx, ids
 
 
-def from_workloads(workloads, tile_rows=0, stream=None, gauges=True):
+def from_workloads(workloads, tile_rows=0, stream=None, gauges=True, precision=0):
     """A finalized context with one scenario per workload (one patch each),
-    bathymetry, state and gauges set."""
+    bathymetry, state and gauges set; precision 0 is FP64, 1 mixed."""
     ws = list(workloads)
     for w in ws[1:]:
         if w.params != ws[0].params:
             raise ValueError("workloads of one context must share their parameters")
-    ctx = Context(ws[0].params, tile_rows=tile_rows, stream=stream)
+    ctx = Context(ws[0].params, tile_rows=tile_rows, stream=stream, precision=precision)
     for s, w in enumerate(ws):
         ctx.add_grid(s, w.grid)
     ctx.finalize()

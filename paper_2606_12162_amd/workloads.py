@@ -48,6 +48,7 @@ class Params:
     transverse: int = 2       # 0 none, 2 with corrections
     splitting: int = 1        # 0 Lie, 1 Strang
     model: int = 0            # 0 HSGN, 1 mbHSGN
+    c2: float = 0.0           # > 0: fixed c^2 (m^2/s^2) instead of alpha^2 g H
 
 
 @dataclasses.dataclass

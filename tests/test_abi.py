@@ -39,6 +39,9 @@ def test_strerror_and_param_validation_on_host():
     bad = H.make_params(W.Params(limiter=7))
     h = ctypes.c_void_p()
     assert L.hsgn_create(ctypes.byref(bad), None, ctypes.byref(h)) == H.HSGN_EINVAL
+    for c2 in (-1.0, float("nan")):            # the fixed c^2 must be >= 0
+        bad = H.make_params(W.Params(c2=c2))
+        assert L.hsgn_create(ctypes.byref(bad), None, ctypes.byref(h)) == H.HSGN_EINVAL
     nosup = H.make_params(W.Params(), precision=5)
     assert L.hsgn_create(ctypes.byref(nosup), None, ctypes.byref(h)) == H.HSGN_ENOTSUP
     good = H.make_params(W.Params())

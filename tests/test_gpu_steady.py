@@ -81,8 +81,10 @@ def test_fixed_c2_steady_state_fp64_parity(which):
     assert np.array_equal(ctx.get_mask(0), r.get_mask())
     t, _, steps = ctx.clock(0)
     assert steps == w.steps and abs(t - r.clock()[0]) <= 1e-12 * t
-    # the state stays near the steady state (first-order error, Sec. 5)
-    assert np.abs(got[0] - w.q[0]).max() < 0.05
+    # the state stays near the steady state: first-order error for HSGN; the
+    # mbHSGN case keeps the O(0.1) error of the default sensor on this coarse
+    # grid (its terms are switched off where the bottom is steep)
+    assert np.abs(got[0] - w.q[0]).max() < (0.05 if which == "hsgn_guermond" else 0.3)
     ctx.close()
 
 

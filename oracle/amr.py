@@ -87,6 +87,7 @@ class _Patch:
         self.I0, self.J0 = I0, J0
         self.g = grid
         self.q, self.b, self.phi, self.brk, self.iface = grid.framed()
+        self.b_raw = None          # bathymetry as set, before averaging down
 
     def contains(self, I, J):
         return self.I0 <= I < self.I0 + self.nx and self.J0 <= J < self.J0 + self.ny
@@ -145,7 +146,8 @@ class AmrOracle:
     # ------------------------------------------------------------ data in/out
     def set_bathymetry(self, pid, b):
         p = self.patches[pid]
-        p.b[2:-2, 2:-2] = np.asarray(b, dtype=np.float64)
+        p.b_raw = np.array(b, dtype=np.float64).reshape(p.ny, p.nx)
+        p.b[2:-2, 2:-2] = p.b_raw
         self.prepared = False
 
     def set_state(self, pid, q):

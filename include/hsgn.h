@@ -195,6 +195,59 @@ int hsgn_work_items(hsgn_ctx *c, int *n);
 int hsgn_set_timing(hsgn_ctx *c, int on);
 int hsgn_get_timing(hsgn_ctx *c, double *step_kernel_ms, long long *launches);
 
+/* Regridding of a patch-set scenario (Sec. 4: Berger-Oliger-Colella
+ * adaptive refinement; flagging by the surface jump between neighbouring
+ * cells as in the solitary-wave test of Sec. 5).  Call between hsgn_advance
+ * calls (all levels are then at the same time).  Level `level` + 1 is
+ * rebuilt from flags on level `level`; deeper levels are dropped (regrid
+ * them next, level by level).  The rules:
+ *   flags    a pair of face neighbours inside a level-l patch, both wet,
+ *            whose surface eta' = (h + b) - eta0 differs by more than tol,
+ *            flags both cells; then every cell within nbuf cells (max norm,
+ *            inside the patch) of a flag;
+ *   clusters per level-l patch: a box shrinks to the bounding box of its
+ *            flags; with at least `cutoff` of its cells flagged it is
+ *            accepted once both sides are <= max_side (else its longer side
+ *            is halved, x on ties); otherwise it splits at an empty column or
+ *            row of the flag counts nearest the middle (x first, then the
+ *            lower index), else at the strongest sign change of their second
+ *            difference (sides >= 4; ties: nearest the middle, x, lower
+ *            index), else in the middle of the longer side; low half first;
+ *   nesting  boxes are clipped to their patch less one cell and refined by
+ *            4; new patches follow the patches of their parents and the
+ *            order of the clusters;
+ *   bottom   a new patch takes the bilinear interpolant of the level-0
+ *            bathymetry as set (cell-centred, index coordinates, clamped at
+ *            the outer centres); kept patches keep what they were given;
+ *            covered coarse cells then take the fine mean;
+ *   state    kept cells keep their state (a wet cell whose bathymetry
+ *            changed keeps its surface, depth clipped at zero; a dry one
+ *            its depth); new cells take the ghost rule's spatial
+ *            interpolation from their parent, or a copy where an old
+ *            level-(l+1) patch covered them; breaking latches come along;
+ *            clocks, clipped mass and unread gauge records carry over.
+ * Patch ids change: hsgn_num_patches / hsgn_patch_info list the new patches
+ * (every other scenario's patches first in their old order; this scenario's
+ * levels <= l, then the new ones).  Tile heights return to the library's
+ * choice.  n_new (may be NULL) receives the number of new patches.  Errors:
+ * EINVAL (not finalized, bad parameters, bathymetry not set), ENOTSUP (not a
+ * patch set), ENOMEM, EDEVICE; on error the context is unchanged. */
+typedef struct hsgn_regrid_params {
+    int level;          /* rebuild level + 1 from flags on this level */
+    int nbuf;           /* buffer width in level cells (0..64) */
+    double tol;         /* surface-jump tolerance (m); negative flags all wet pairs */
+    double cutoff;      /* clustering efficiency in (0, 1] */
+    int max_side;       /* largest box side in level cells (>= 1) */
+} hsgn_regrid_params;
+int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_new);
+
+/* The patches of a context: their number, and per patch its scenario,
+ * refinement level, size, lower-left corner and spacing (any output may be
+ * NULL).  Errors: EINVAL. */
+int hsgn_num_patches(hsgn_ctx *c, int *n);
+int hsgn_patch_info(hsgn_ctx *c, int patch, int *scenario, int *level, int *nx, int *ny,
+                    double *x0, double *y0, double *dx, double *dy);
+
 int hsgn_destroy(hsgn_ctx *c);
 const char *hsgn_strerror(int code);
 const char *hsgn_last_error(hsgn_ctx *c);

@@ -282,6 +282,157 @@ __global__ void fill_zero_kernel(double *p, long long n)
     if (i < n) p[i] = 0.0;
 }
 
+// ---- regridding ----------------------------------------------------------
+
+// flag of one interior cell of a level-l patch: a wet face neighbour inside
+// the patch whose surface eta' = (h + b) - eta0 differs by more than tol
+template <class S, bool MIXED>
+__device__ inline bool surface_of(const PatchInfo &P, const S *q, const S *bath, int x, int y,
+                                  double eta0, double dry_tol, double &e)
+{
+    const long long l = (long long)y * P.pitch + x;
+    const double v = (double)q[P.qoff + l];
+    const double b = (double)bath[P.coff + l];
+    if (MIXED) {
+        e = v;
+        return ((v + eta0) - b) > dry_tol;
+    }
+    e = (v + b) - eta0;
+    return v > dry_tol;
+}
+
+template <class S, bool MIXED>
+__global__ void regrid_flag_kernel(PatchInfo P, const S *q, const S *bath, uint8_t *out,
+                                   double eta0, double dry_tol, double tol)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long long)P.nx * P.ny) return;
+    const int x = (int)(k % P.nx), y = (int)(k / P.nx);
+    double e0, e1;
+    uint8_t f = 0;
+    if (surface_of<S, MIXED>(P, q, bath, x, y, eta0, dry_tol, e0)) {
+        const int nbx[4] = {x - 1, x + 1, x, x};
+        const int nby[4] = {y, y, y - 1, y + 1};
+        for (int s = 0; s < 4; s++) {
+            if (nbx[s] < 0 || nbx[s] >= P.nx || nby[s] < 0 || nby[s] >= P.ny) continue;
+            if (surface_of<S, MIXED>(P, q, bath, nbx[s], nby[s], eta0, dry_tol, e1) &&
+                fabs(e1 - e0) > tol)
+                f = 1;
+        }
+    }
+    out[k] = f;
+}
+
+// the record holding launch cell k (records sorted by c0, the first at 0)
+template <class R>
+__device__ inline int record_of(const R *rec, int nr, long long k)
+{
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rec[mid].c0 <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// copy one cell from the old storage; a wet cell whose bathymetry changed
+// keeps its surface (depth clipped at zero), a dry cell keeps its depth; the
+// breaking latch comes along, phi_T and the interface bits stay the new ones
+template <class S, bool MIXED>
+__global__ void regrid_copy_kernel(const RegridCopy<S> *R, int nr, long long total, S *q,
+                                   const S *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                                   double dry_tol)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    const RegridCopy<S> r = R[record_of(R, nr, k)];
+    const long long e = k - r.c0;
+    const int x = (int)(e % r.nx), y = (int)(e / r.nx);
+    const long long sl = (long long)(r.sj0 + y) * r.src.pitch + (r.si0 + x);
+    const long long dl = (long long)(r.dj0 + y) * r.dst.pitch + (r.di0 + x);
+    for (int m = 1; m < 7; m++)
+        q[r.dst.qoff + m * r.dst.plane + dl] = r.sq[r.src.qoff + m * r.src.plane + sl];
+    S v0 = r.sq[r.src.qoff + sl];
+    const double bo = (double)r.sb[r.src.coff + sl], bn = (double)bath[r.dst.coff + dl];
+    if (bo != bn) {
+        if (MIXED) {
+            const double h = ((double)v0 + eta0) - bo;
+            double h2 = h;
+            if (h > dry_tol) {
+                h2 = h + (bo - bn);
+                if (!(h2 > 0.0)) h2 = 0.0;
+            }
+            v0 = (S)((h2 + bn) - eta0);
+        } else if ((double)v0 > dry_tol) {
+            const double h2 = (double)v0 + (bo - bn);
+            v0 = (S)(h2 > 0.0 ? h2 : 0.0);
+        }
+    }
+    q[r.dst.qoff + dl] = v0;
+    const uint8_t lat = (uint8_t)(r.sm[r.src.coff + sl] & MASK_BRK);
+    m0[r.dst.coff + dl] = (uint8_t)((m0[r.dst.coff + dl] & ~MASK_BRK) | lat);
+    m1[r.dst.coff + dl] = (uint8_t)((m1[r.dst.coff + dl] & ~MASK_BRK) | lat);
+}
+
+// one cell of a new patch from its coarse parent: the ghost rule's spatial
+// interpolation (minmod-limited slopes, zero if a stencil cell is dry) and the
+// parent cell's breaking latch.  The stencil lies inside the parent (the new
+// patch keeps one parent cell clear of the parent's edges).
+template <class S, bool MIXED>
+__global__ void regrid_interp_kernel(const RegridInterp *R, int nr, long long total, S *q,
+                                     const S *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                                     double dry_tol)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    const RegridInterp r = R[record_of(R, nr, k)];
+    const long long e = k - r.c0;
+    const int i = (int)(e % r.fine.nx), j = (int)(e / r.fine.nx);
+    const int ic = r.ci0 + (i >> 2), jc = r.cj0 + (j >> 2);
+    const PatchInfo C = r.coarse, F = r.fine;
+    const int sx_[5] = {ic, ic - 1, ic + 1, ic, ic};
+    const int sy_[5] = {jc, jc, jc, jc - 1, jc + 1};
+    double v[5][7];
+    bool any_dry = false;
+    for (int s = 0; s < 5; s++) {
+        const long long cl = (long long)sy_[s] * C.pitch + sx_[s];
+        for (int m = 0; m < 7; m++) v[s][m] = (double)q[C.qoff + m * C.plane + cl];
+        const double b = (double)bath[C.coff + cl];
+        double h;
+        if (MIXED) {
+            h = (v[s][0] + eta0) - b;
+        } else {
+            h = v[s][0];
+            v[s][0] = (h + b) - eta0;
+        }
+        any_dry = any_dry || !(h > dry_tol);
+    }
+    const double ox = ((double)(i & 3) + 0.5) / 4.0 - 0.5;
+    const double oy = ((double)(j & 3) + 0.5) / 4.0 - 0.5;
+    double out[7];
+    for (int m = 0; m < 7; m++) {
+        double sx = 0.0, sy = 0.0;
+        if (!any_dry) {
+            sx = minmod(v[2][m] - v[0][m], v[0][m] - v[1][m]);
+            sy = minmod(v[4][m] - v[0][m], v[0][m] - v[3][m]);
+        }
+        out[m] = (v[0][m] + ox * sx) + oy * sy;
+    }
+    const long long fl = (long long)j * F.pitch + i;
+    const double bf = (double)bath[F.coff + fl];
+    const double h = (out[0] + eta0) - bf;
+    if (MIXED) {
+        if (!(h > 0.0)) out[0] = bf - eta0;
+    } else {
+        out[0] = h > 0.0 ? h : 0.0;
+    }
+    for (int m = 0; m < 7; m++) q[F.qoff + m * F.plane + fl] = (S)out[m];
+    const uint8_t lat = (uint8_t)(m0[C.coff + (long long)jc * C.pitch + ic] & MASK_BRK);
+    m0[F.coff + fl] = (uint8_t)((m0[F.coff + fl] & ~MASK_BRK) | lat);
+    m1[F.coff + fl] = (uint8_t)((m1[F.coff + fl] & ~MASK_BRK) | lat);
+}
+
 }  // namespace
 
 void launch_halo_copy64(const AmrBuffers<double> &B, const GhostCopy *r, int n, hipStream_t s)
@@ -352,6 +503,53 @@ void launch_iface(const PatchInfo *patches, const RefluxRec *r, int n, uint8_t *
 void launch_fill_zero(double *p, long long n, hipStream_t s)
 {
     if (n > 0) fill_zero_kernel<<<blocks(n), TPB, 0, s>>>(p, n);
+}
+
+void launch_regrid_flag64(const PatchInfo &p, const double *q, const double *bath, uint8_t *out,
+                          double eta0, double dry_tol, double tol, hipStream_t s)
+{
+    long long n = (long long)p.nx * p.ny;
+    if (n > 0) regrid_flag_kernel<double, false><<<blocks(n), TPB, 0, s>>>(p, q, bath, out, eta0,
+                                                                          dry_tol, tol);
+}
+void launch_regrid_flag32(const PatchInfo &p, const float *q, const float *bath, uint8_t *out,
+                          double eta0, double dry_tol, double tol, hipStream_t s)
+{
+    long long n = (long long)p.nx * p.ny;
+    if (n > 0) regrid_flag_kernel<float, true><<<blocks(n), TPB, 0, s>>>(p, q, bath, out, eta0,
+                                                                        dry_tol, tol);
+}
+void launch_regrid_copy64(const RegridCopy<double> *r, int nr, long long total, double *q,
+                          const double *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                          double dry_tol, hipStream_t s)
+{
+    if (nr > 0 && total > 0)
+        regrid_copy_kernel<double, false><<<blocks(total), TPB, 0, s>>>(r, nr, total, q, bath, m0,
+                                                                        m1, eta0, dry_tol);
+}
+void launch_regrid_copy32(const RegridCopy<float> *r, int nr, long long total, float *q,
+                          const float *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                          double dry_tol, hipStream_t s)
+{
+    if (nr > 0 && total > 0)
+        regrid_copy_kernel<float, true><<<blocks(total), TPB, 0, s>>>(r, nr, total, q, bath, m0,
+                                                                      m1, eta0, dry_tol);
+}
+void launch_regrid_interp64(const RegridInterp *r, int nr, long long total, double *q,
+                            const double *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                            double dry_tol, hipStream_t s)
+{
+    if (nr > 0 && total > 0)
+        regrid_interp_kernel<double, false><<<blocks(total), TPB, 0, s>>>(r, nr, total, q, bath, m0,
+                                                                          m1, eta0, dry_tol);
+}
+void launch_regrid_interp32(const RegridInterp *r, int nr, long long total, float *q,
+                            const float *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                            double dry_tol, hipStream_t s)
+{
+    if (nr > 0 && total > 0)
+        regrid_interp_kernel<float, true><<<blocks(total), TPB, 0, s>>>(r, nr, total, q, bath, m0,
+                                                                        m1, eta0, dry_tol);
 }
 
 }  // namespace hsgn

@@ -99,4 +99,44 @@ void launch_iface(const PatchInfo *patches, const RefluxRec *r, int n, uint8_t *
                   hipStream_t s);
 void launch_fill_zero(double *p, long long n, hipStream_t s);
 
+// regridding (hsgn_regrid): a rectangle of interior cells copied from a patch
+// of the old storage (buffers sq, sb, sm: the ones holding its current step)
+// to a patch of the new storage, and a new patch filled from its coarse
+// parent.  Records are laid end to end: c0 is the first cell of a record in
+// the launch.
+template <class S>
+struct RegridCopy {
+    PatchInfo src, dst;
+    const S *sq;
+    const S *sb;
+    const uint8_t *sm;
+    int si0, sj0, di0, dj0;   // rectangle origin, interior cells of each patch
+    int nx, ny;
+    long long c0;
+};
+
+struct RegridInterp {
+    PatchInfo fine, coarse;   // both in the new storage
+    int ci0, cj0;             // coarse-local cell under the fine cell (0, 0)
+    int pad;
+    long long c0;
+};
+
+void launch_regrid_flag64(const PatchInfo &p, const double *q, const double *bath, uint8_t *out,
+                          double eta0, double dry_tol, double tol, hipStream_t s);
+void launch_regrid_flag32(const PatchInfo &p, const float *q, const float *bath, uint8_t *out,
+                          double eta0, double dry_tol, double tol, hipStream_t s);
+void launch_regrid_copy64(const RegridCopy<double> *r, int nr, long long total, double *q,
+                          const double *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                          double dry_tol, hipStream_t s);
+void launch_regrid_copy32(const RegridCopy<float> *r, int nr, long long total, float *q,
+                          const float *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                          double dry_tol, hipStream_t s);
+void launch_regrid_interp64(const RegridInterp *r, int nr, long long total, double *q,
+                            const double *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                            double dry_tol, hipStream_t s);
+void launch_regrid_interp32(const RegridInterp *r, int nr, long long total, float *q,
+                            const float *bath, uint8_t *m0, uint8_t *m1, double eta0,
+                            double dry_tol, hipStream_t s);
+
 }  // namespace hsgn

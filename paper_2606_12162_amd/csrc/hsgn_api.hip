@@ -345,6 +345,7 @@ struct hsgn_ctx {
     hipStream_t stream = nullptr;
     bool finalized = false;
     std::vector<PatchInfo> patches;
+    std::vector<std::vector<double>> braw;   // bathymetry as set, per patch (host copy)
     std::vector<double> px0, py0;
     std::vector<int> pI0, pJ0;             // patch origin in cells of its level (patch sets)
     std::vector<ScenHost> scen;
@@ -1212,6 +1213,13 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
     const bool amr = p.frame != 0;       // a patch of a patch set
     long long n = (long long)p.nx * p.ny;
     unsigned nb = nblk(n);
+    // host copy of the bathymetry as set: regridding rebuilds from it
+    if ((int)c->braw.size() < (int)c->patches.size()) c->braw.resize(c->patches.size());
+    c->braw[patch].resize((size_t)n);
+    if (on_device)
+        HIPCHK(c, hipMemcpy(c->braw[patch].data(), b, sizeof(double) * n, hipMemcpyDeviceToHost));
+    else
+        memcpy(c->braw[patch].data(), b, sizeof(double) * n);
     if (c->mixed) {
         // stored in FP32; phi_T is computed from the stored values
         HIPCHK(c, hipMemcpyAsync(c->stage, b, sizeof(double) * n, kind_in(on_device), c->stream));
@@ -2028,6 +2036,457 @@ int hsgn_destroy(hsgn_ctx *c)
     else (void)hipDeviceSynchronize();
     free_device(c);
     delete c;
+    return HSGN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// regridding: flags on level l, clusters, a new context with the rebuilt
+// level l+1, the state moved across on the device, then the new context takes
+// the place of the old one behind the caller's handle.
+
+namespace {
+
+struct RgBox {
+    int i0, i1, j0, j1;     // half-open, in cells of the flagged patch
+};
+
+// clusters of the flags F[ny][nx] (Berger-Rigoutsos, rules in hsgn.h)
+void rg_cluster(const std::vector<uint8_t> &F, int NX, int i0, int i1, int j0, int j1,
+                double cutoff, int max_side, std::vector<RgBox> &out)
+{
+    int a0 = i1, a1 = i0 - 1, b0 = j1, b1 = j0 - 1;
+    long long n = 0;
+    for (int j = j0; j < j1; j++)
+        for (int i = i0; i < i1; i++)
+            if (F[(size_t)j * NX + i]) {
+                n++;
+                a0 = std::min(a0, i); a1 = std::max(a1, i);
+                b0 = std::min(b0, j); b1 = std::max(b1, j);
+            }
+    if (n == 0) return;
+    i0 = a0; i1 = a1 + 1; j0 = b0; j1 = b1 + 1;
+    const int nx = i1 - i0, ny = j1 - j0;
+    int dim = -1, cut = 0;
+    if ((double)n >= cutoff * (double)((long long)nx * ny)) {
+        if (nx <= max_side && ny <= max_side) {
+            out.push_back({i0, i1, j0, j1});
+            return;
+        }
+        if (nx >= ny) { dim = 0; cut = nx / 2; } else { dim = 1; cut = ny / 2; }
+    } else {
+        std::vector<long long> S[2];
+        S[0].assign(nx, 0);
+        S[1].assign(ny, 0);
+        for (int j = j0; j < j1; j++)
+            for (int i = i0; i < i1; i++)
+                if (F[(size_t)j * NX + i]) { S[0][i - i0]++; S[1][j - j0]++; }
+        const int Ls[2] = {nx, ny};
+        // (a) an empty column or row, nearest the middle
+        long long bk0 = 0;
+        int bd = 0, bk = 0;
+        bool found = false;
+        for (int d = 0; d < 2; d++)
+            for (int k = 1; k < Ls[d] - 1; k++)
+                if (S[d][k] == 0) {
+                    long long k0 = std::llabs(2LL * k - (Ls[d] - 1));
+                    if (!found || k0 < bk0 || (k0 == bk0 && (d < bd || (d == bd && k < bk)))) {
+                        found = true; bk0 = k0; bd = d; bk = k;
+                    }
+                }
+        if (found) {
+            dim = bd; cut = bk;
+        } else {
+            // (b) the strongest sign change of the second difference
+            long long bs = 0, bm = 0;
+            for (int d = 0; d < 2; d++) {
+                const int L = Ls[d];
+                if (L < 4) continue;
+                auto lap = [&](int k) { return S[d][k - 1] - 2 * S[d][k] + S[d][k + 1]; };
+                for (int k = 1; k < L - 2; k++) {
+                    const long long a = lap(k), b = lap(k + 1);
+                    if (a * b < 0) {
+                        const long long st = std::llabs(b - a);
+                        const long long mid = std::llabs(2LL * (k + 1) - L);
+                        if (!found || st > bs || (st == bs && (mid < bm || (mid == bm &&
+                            (d < bd || (d == bd && k < bk)))))) {
+                            found = true; bs = st; bm = mid; bd = d; bk = k;
+                        }
+                    }
+                }
+            }
+            if (found) {
+                dim = bd; cut = bk + 1;
+            } else if (nx >= ny) {
+                dim = 0; cut = nx / 2;
+            } else {
+                dim = 1; cut = ny / 2;
+            }
+        }
+    }
+    if (dim == 0) {
+        rg_cluster(F, NX, i0, i0 + cut, j0, j1, cutoff, max_side, out);
+        rg_cluster(F, NX, i0 + cut, i1, j0, j1, cutoff, max_side, out);
+    } else {
+        rg_cluster(F, NX, i0, i1, j0, j0 + cut, cutoff, max_side, out);
+        rg_cluster(F, NX, i0, i1, j0 + cut, j1, cutoff, max_side, out);
+    }
+}
+
+// bilinear interpolant of the level-0 bathymetry B[NY][NX] at the centres of
+// a level-`level` box (level-`level` cells I0.., J0..)
+void rg_topo(const std::vector<double> &B, int NX, int NY, int level, int nx, int ny, int I0,
+             int J0, std::vector<double> &out)
+{
+    out.resize((size_t)nx * ny);
+    const double sc = (double)(1LL << (2 * level));
+    for (int j = 0; j < ny; j++) {
+        const double fy = ((double)(J0 + j) + 0.5) / sc - 0.5;
+        const int jj = std::min(std::max((int)std::floor(fy), 0), NY - 2);
+        const double s = std::min(std::max(fy - jj, 0.0), 1.0);
+        for (int i = 0; i < nx; i++) {
+            const double fx = ((double)(I0 + i) + 0.5) / sc - 0.5;
+            const int ii = std::min(std::max((int)std::floor(fx), 0), NX - 2);
+            const double t = std::min(std::max(fx - ii, 0.0), 1.0);
+            const double *r0 = &B[(size_t)jj * NX], *r1 = &B[(size_t)(jj + 1) * NX];
+            out[(size_t)j * nx + i] = (r0[ii] * (1.0 - t) + r0[ii + 1] * t) * (1.0 - s) +
+                                      (r1[ii] * (1.0 - t) + r1[ii + 1] * t) * s;
+        }
+    }
+}
+
+template <class T>
+int rg_upload(hsgn_ctx *c, T **d, const std::vector<T> &h)
+{
+    *d = nullptr;
+    if (h.empty()) return HSGN_OK;
+    HIPCHK(c, hipMalloc(d, sizeof(T) * h.size()));
+    HIPCHK(c, hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return HSGN_OK;
+}
+
+// the state of the new context n from the old one c (buffers of the current
+// step of every old patch, buffer 0 of the new context)
+template <class S, bool MIXED>
+int rg_transfer(hsgn_ctx *c, hsgn_ctx *n, const std::vector<ScenState> &st_old,
+                const std::vector<std::pair<int, int>> &kept,
+                const std::vector<std::pair<int, int>> &fresh_parent,
+                const std::vector<int> &old_fine, int level)
+{
+    S *oq0 = MIXED ? (S *)c->f0 : (S *)c->q0, *oq1 = MIXED ? (S *)c->f1 : (S *)c->q1;
+    const S *ob = MIXED ? (const S *)c->fbath : (const S *)c->bath;
+    S *nq = MIXED ? (S *)n->f0 : (S *)n->q0;
+    const S *nb = MIXED ? (const S *)n->fbath : (const S *)n->bath;
+    auto old_rec = [&](int op, const PatchInfo &dst, int si0, int sj0, int di0, int dj0, int w,
+                       int h, long long c0) {
+        const PatchInfo &src = c->patches[op];
+        const int cur = st_old[src.scen].cur;
+        RegridCopy<S> r;
+        memset(&r, 0, sizeof(r));
+        r.src = src; r.dst = dst;
+        r.sq = cur ? oq1 : oq0;
+        r.sb = ob;
+        r.sm = cur ? c->m1 : c->m0;
+        r.si0 = si0; r.sj0 = sj0; r.di0 = di0; r.dj0 = dj0;
+        r.nx = w; r.ny = h; r.c0 = c0;
+        return r;
+    };
+    // kept patches: whole interiors
+    std::vector<RegridCopy<S>> K;
+    long long tk = 0;
+    for (auto &pr : kept) {
+        const PatchInfo &s = c->patches[pr.first];
+        K.push_back(old_rec(pr.first, n->patches[pr.second], 0, 0, 0, 0, s.nx, s.ny, tk));
+        tk += (long long)s.nx * s.ny;
+    }
+    // new patches from their parents, then old level-(l+1) overlaps
+    std::vector<RegridInterp> I;
+    std::vector<RegridCopy<S>> O;
+    long long ti = 0, to = 0;
+    for (auto &fp : fresh_parent) {
+        const int f = fp.first, cp = fp.second;
+        RegridInterp r;
+        memset(&r, 0, sizeof(r));
+        r.fine = n->patches[f];
+        r.coarse = n->patches[cp];
+        r.ci0 = n->pI0[f] / AMR_RATIO - n->pI0[cp];
+        r.cj0 = n->pJ0[f] / AMR_RATIO - n->pJ0[cp];
+        if (r.ci0 < 1 || r.cj0 < 1 || r.ci0 + r.fine.nx / AMR_RATIO > r.coarse.nx - 1 ||
+            r.cj0 + r.fine.ny / AMR_RATIO > r.coarse.ny - 1)
+            return fail(c, HSGN_EINVAL, "regrid: a new patch leaves its parent");
+        r.c0 = ti;
+        ti += (long long)r.fine.nx * r.fine.ny;
+        I.push_back(r);
+        for (int op : old_fine) {
+            const PatchInfo &o = c->patches[op];
+            const int ax0 = std::max(n->pI0[f], c->pI0[op]);
+            const int ax1 = std::min(n->pI0[f] + r.fine.nx, c->pI0[op] + o.nx);
+            const int ay0 = std::max(n->pJ0[f], c->pJ0[op]);
+            const int ay1 = std::min(n->pJ0[f] + r.fine.ny, c->pJ0[op] + o.ny);
+            if (ax1 <= ax0 || ay1 <= ay0) continue;
+            O.push_back(old_rec(op, r.fine, ax0 - c->pI0[op], ay0 - c->pJ0[op], ax0 - n->pI0[f],
+                                ay0 - n->pJ0[f], ax1 - ax0, ay1 - ay0, to));
+            to += (long long)(ax1 - ax0) * (ay1 - ay0);
+        }
+    }
+    (void)level;
+    RegridCopy<S> *dK = nullptr, *dO = nullptr;
+    RegridInterp *dI = nullptr;
+    int rc;
+    if ((rc = rg_upload(c, &dK, K)) || (rc = rg_upload(c, &dI, I)) || (rc = rg_upload(c, &dO, O))) {
+        if (dK) (void)hipFree(dK);
+        if (dI) (void)hipFree(dI);
+        if (dO) (void)hipFree(dO);
+        return rc;
+    }
+    const double eta0 = c->prm.eta0, dtol = c->prm.dry_tol;
+    if (MIXED) {
+        launch_regrid_copy32((const RegridCopy<float> *)dK, (int)K.size(), tk, (float *)nq,
+                             (const float *)nb, n->m0, n->m1, eta0, dtol, n->stream);
+        launch_regrid_interp32(dI, (int)I.size(), ti, (float *)nq, (const float *)nb, n->m0, n->m1,
+                               eta0, dtol, n->stream);
+        launch_regrid_copy32((const RegridCopy<float> *)dO, (int)O.size(), to, (float *)nq,
+                             (const float *)nb, n->m0, n->m1, eta0, dtol, n->stream);
+    } else {
+        launch_regrid_copy64((const RegridCopy<double> *)dK, (int)K.size(), tk, (double *)nq,
+                             (const double *)nb, n->m0, n->m1, eta0, dtol, n->stream);
+        launch_regrid_interp64(dI, (int)I.size(), ti, (double *)nq, (const double *)nb, n->m0,
+                               n->m1, eta0, dtol, n->stream);
+        launch_regrid_copy64((const RegridCopy<double> *)dO, (int)O.size(), to, (double *)nq,
+                             (const double *)nb, n->m0, n->m1, eta0, dtol, n->stream);
+    }
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(n->stream);
+    if (dK) (void)hipFree(dK);
+    if (dI) (void)hipFree(dI);
+    if (dO) (void)hipFree(dO);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(c, HSGN_EDEVICE, std::string("regrid transfer: ") +
+                                         hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return HSGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsgn_num_patches(hsgn_ctx *c, int *n)
+{
+    if (!c || !n) return HSGN_EINVAL;
+    *n = (int)c->patches.size();
+    return HSGN_OK;
+}
+
+int hsgn_patch_info(hsgn_ctx *c, int patch, int *scenario, int *level, int *nx, int *ny,
+                    double *x0, double *y0, double *dx, double *dy)
+{
+    if (!c || patch < 0 || patch >= (int)c->patches.size())
+        return fail(c, HSGN_EINVAL, "bad patch id");
+    const PatchInfo &p = c->patches[patch];
+    int s = 0;
+    for (size_t k = 0; k < c->scen.size(); k++)
+        for (int q : c->scen[k].patches)
+            if (q == patch) s = (int)k;
+    if (scenario) *scenario = s;
+    if (level) *level = p.level;
+    if (nx) *nx = p.nx;
+    if (ny) *ny = p.ny;
+    if (x0) *x0 = c->px0[patch];
+    if (y0) *y0 = c->py0[patch];
+    if (dx) *dx = p.dx;
+    if (dy) *dy = p.dy;
+    return HSGN_OK;
+}
+
+int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_new)
+{
+    if (!c || !c->finalized || !r) return fail(c, HSGN_EINVAL, "call hsgn_finalize first");
+    if (scenario < 0 || scenario >= (int)c->scen.size())
+        return fail(c, HSGN_EINVAL, "bad scenario");
+    ScenHost &sh = c->scen[scenario];
+    if (!sh.amr) return fail(c, HSGN_ENOTSUP, "regridding needs a patch set (tile level 0)");
+    const int level = r->level;
+    if (level < 0 || level >= (int)sh.lev.size() || level + 1 > 5 || !(r->tol == r->tol) ||
+        r->nbuf < 0 || r->nbuf > 64 || !(r->cutoff > 0.0 && r->cutoff <= 1.0) || r->max_side < 1)
+        return fail(c, HSGN_EINVAL, "bad regrid parameters");
+    for (int pid : sh.patches)
+        if (pid >= (int)c->braw.size() || c->braw[pid].size() != (size_t)c->patches[pid].nx *
+                                                                        c->patches[pid].ny)
+            return fail(c, HSGN_EINVAL, "set the bathymetry of every patch before regridding");
+    int rc = ensure_prepared(c);
+    if (rc) return rc;
+    std::vector<ScenState> st;
+    if ((rc = pull_scen(c, st))) return rc;
+    // 1-4. flags of the level-l patches, clusters, new level-(l+1) boxes
+    struct NewBox { int parent, nx, ny, I0, J0; };
+    std::vector<NewBox> boxes;
+    for (int pid : sh.lev[level]) {
+        const PatchInfo &p = c->patches[pid];
+        const int cur = st[p.scen].cur;
+        uint8_t *dflag = (uint8_t *)c->stage;
+        if (c->mixed)
+            launch_regrid_flag32(p, cur ? c->f1 : c->f0, c->fbath, dflag, c->prm.eta0,
+                                 c->prm.dry_tol, r->tol, c->stream);
+        else
+            launch_regrid_flag64(p, cur ? c->q1 : c->q0, c->bath, dflag, c->prm.eta0,
+                                 c->prm.dry_tol, r->tol, c->stream);
+        HIPCHK(c, hipGetLastError());
+        std::vector<uint8_t> F((size_t)p.nx * p.ny), B;
+        HIPCHK(c, hipMemcpyAsync(F.data(), dflag, F.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        B = F;
+        for (int j = 0; j < p.ny; j++)
+            for (int i = 0; i < p.nx; i++) {
+                if (!F[(size_t)j * p.nx + i]) continue;
+                for (int b = std::max(0, j - r->nbuf); b <= std::min(p.ny - 1, j + r->nbuf); b++)
+                    for (int a = std::max(0, i - r->nbuf); a <= std::min(p.nx - 1, i + r->nbuf); a++)
+                        B[(size_t)b * p.nx + a] = 1;
+            }
+        std::vector<RgBox> cl;
+        rg_cluster(B, p.nx, 0, p.nx, 0, p.ny, r->cutoff, r->max_side, cl);
+        for (const RgBox &x : cl) {
+            const int i0 = std::max(x.i0, 1), i1 = std::min(x.i1, p.nx - 1);
+            const int j0 = std::max(x.j0, 1), j1 = std::min(x.j1, p.ny - 1);
+            if (i1 <= i0 || j1 <= j0) continue;
+            boxes.push_back({pid, AMR_RATIO * (i1 - i0), AMR_RATIO * (j1 - j0),
+                             AMR_RATIO * (c->pI0[pid] + i0), AMR_RATIO * (c->pJ0[pid] + j0)});
+        }
+    }
+    // 5. the new context: every patch of the other scenarios, the levels <= l
+    // of this one, then the new boxes
+    hsgn_ctx *n = nullptr;
+    if ((rc = hsgn_create(&c->prm, c->stream, &n))) return fail(c, rc, "regrid: context");
+    auto bail = [&](int code, const std::string &why) {
+        std::string msg = why + (n->last_error.empty() ? "" : ": " + n->last_error);
+        hsgn_destroy(n);
+        return fail(c, code, msg);
+    };
+    std::vector<int> newid(c->patches.size(), -1);
+    std::vector<std::pair<int, int>> kept, fresh;     // (old, new); (new, new parent)
+    std::vector<int> old_fine;
+    double dx0 = 0.0, dy0 = 0.0;
+    for (size_t s = 0; s < c->scen.size(); s++)
+        for (int pid : c->scen[s].patches) {
+            const PatchInfo &p = c->patches[pid];
+            if ((int)s == scenario && p.level > level) {
+                if (p.level == level + 1) old_fine.push_back(pid);
+                continue;
+            }
+            if ((int)s == scenario && p.level == 0) { dx0 = p.dx; dy0 = p.dy; }
+            int id = -1;
+            if ((rc = hsgn_add_grid(n, (int)s, p.level, p.nx, p.ny, c->px0[pid], c->py0[pid],
+                                    p.dx, p.dy, p.bc, &id)))
+                return bail(rc, "regrid: add_grid");
+            newid[pid] = id;
+            kept.push_back({pid, id});
+        }
+    const double sc = (double)(1LL << (2 * (level + 1)));
+    const double dxf = dx0 / sc, dyf = dy0 / sc;
+    const int *bc0 = c->patches[sh.lev[0][0]].bc;
+    std::vector<int> fresh_ids;
+    for (const NewBox &b : boxes) {
+        int id = -1;
+        if ((rc = hsgn_add_grid(n, scenario, level + 1, b.nx, b.ny, sh.X0 + b.I0 * dxf,
+                                sh.Y0 + b.J0 * dyf, dxf, dyf, bc0, &id)))
+            return bail(rc, "regrid: add_grid (new patch)");
+        fresh.push_back({id, newid[b.parent]});
+        fresh_ids.push_back(id);
+    }
+    if ((rc = hsgn_finalize(n))) return bail(rc, "regrid: finalize");
+    n->timing = c->timing;
+    // bathymetry as set (kept patches) or from the level-0 bathymetry (new)
+    for (auto &k : kept)
+        if ((rc = hsgn_set_bathymetry(n, k.second, c->braw[k.first].data(), 0)))
+            return bail(rc, "regrid: bathymetry");
+    if (!boxes.empty()) {
+        std::vector<double> B0((size_t)sh.NX * sh.NY);
+        for (int pid : sh.lev[0]) {
+            const PatchInfo &p = c->patches[pid];
+            for (int j = 0; j < p.ny; j++)
+                memcpy(&B0[(size_t)(c->pJ0[pid] + j) * sh.NX + c->pI0[pid]],
+                       &c->braw[pid][(size_t)j * p.nx], sizeof(double) * p.nx);
+        }
+        std::vector<double> bt;
+        for (size_t k = 0; k < boxes.size(); k++) {
+            rg_topo(B0, sh.NX, sh.NY, level + 1, boxes[k].nx, boxes[k].ny, boxes[k].I0,
+                    boxes[k].J0, bt);
+            if ((rc = hsgn_set_bathymetry(n, fresh_ids[k], bt.data(), 0)))
+                return bail(rc, "regrid: bathymetry (new patch)");
+        }
+    }
+    if ((rc = ensure_prepared(n))) return bail(rc, "regrid: prepare");
+    // 6. the state
+    for (auto &f : fresh) {
+        if (n->pI0[f.first] % AMR_RATIO || n->pJ0[f.first] % AMR_RATIO)
+            return bail(HSGN_EINVAL, "regrid: misaligned patch");
+    }
+    rc = c->mixed ? rg_transfer<float, true>(c, n, st, kept, fresh, old_fine, level)
+                  : rg_transfer<double, false>(c, n, st, kept, fresh, old_fine, level);
+    if (rc) { hsgn_destroy(n); return rc; }
+    // 7. clocks, clipped mass, gauges and their records
+    std::vector<ScenState> sn;
+    if ((rc = pull_scen(n, sn))) return bail(rc, "regrid: clock");
+    std::vector<std::vector<double>> recs(c->scen.size());
+    std::vector<long long> nrec(c->scen.size(), 0);
+    for (size_t s = 0; s < c->scen.size(); s++) {
+        const ScenHost &o = c->scen[s];
+        const ScenState &o0 = st[o.slot[0]];
+        double clip = 0.0;
+        for (int sl : o.slot) clip += st[sl].clip_total;
+        if (!c->h_rf.empty()) {
+            std::vector<double> rcl(c->h_rf.size());
+            HIPCHK(c, hipMemcpy(rcl.data(), c->d_rclip, sizeof(double) * rcl.size(),
+                                hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < rcl.size(); k++)
+                for (int sl : o.slot)
+                    if (c->patches[c->h_rf[k].cp].scen == sl) clip += rcl[k];
+        }
+        const ScenHost &nh = n->scen[s];
+        long long f = 1;
+        for (size_t l = 0; l < nh.slot.size(); l++) {
+            ScenState &x = sn[nh.slot[l]];
+            const ScenState *src = l < o.slot.size() ? &st[o.slot[l]] : &o0;
+            x = *src;
+            x.cur = 0;
+            x.records = 0;
+            x.clip_total = l == 0 ? clip : 0.0;
+            if (l >= o.slot.size()) {
+                x.t = o0.t;
+                x.dt = o0.dt / (double)f;
+                x.dt_fixed = o0.dt_fixed / (double)f;
+                x.steps = o0.steps * f;
+                x.max_courant = 0.0;
+            }
+            f *= AMR_RATIO;
+        }
+        // gauge records not yet read
+        nrec[s] = std::min<long long>(o0.records, o.gcap);
+        if (o.ng > 0 && nrec[s] > 0 && c->rec) {
+            recs[s].resize((size_t)nrec[s] * (1 + o.ng));
+            HIPCHK(c, hipMemcpy(recs[s].data(), c->rec + o.roff, sizeof(double) * recs[s].size(),
+                                hipMemcpyDeviceToHost));
+        }
+    }
+    if ((rc = push_scen(n, sn))) return bail(rc, "regrid: clock");
+    for (size_t s = 0; s < c->scen.size(); s++)
+        if (c->scen[s].ng > 0 &&
+            (rc = hsgn_set_gauges(n, (int)s, c->scen[s].ng, c->scen[s].gauge_xy.data())))
+            return bail(rc, "regrid: gauges");
+    if ((rc = pull_scen(n, sn))) return bail(rc, "regrid: clock");
+    for (size_t s = 0; s < c->scen.size(); s++) sn[s].records = nrec[s];
+    if ((rc = ensure_gauges(n, sn, 0))) return bail(rc, "regrid: gauge records");
+    for (size_t s = 0; s < c->scen.size(); s++)
+        if (!recs[s].empty()) {
+            hipError_t e = hipMemcpy(n->rec + n->scen[s].roff, recs[s].data(),
+                                     sizeof(double) * recs[s].size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return bail(HSGN_EDEVICE, "regrid: gauge records");
+        }
+    if ((rc = push_scen(n, sn))) return bail(rc, "regrid: clock");
+    // 8. the new context replaces the old one
+    std::swap(*c, *n);
+    hsgn_destroy(n);
+    if (n_new) *n_new = (int)boxes.size();
     return HSGN_OK;
 }
 

@@ -24,7 +24,8 @@ EXPORTS = ("hsgn_create", "hsgn_add_grid", "hsgn_finalize", "hsgn_set_bathymetry
            "hsgn_set_state", "hsgn_get_state", "hsgn_get_mask", "hsgn_set_mask",
            "hsgn_set_gauges", "hsgn_read_gauges", "hsgn_advance", "hsgn_diagnostics",
            "hsgn_get_clock", "hsgn_set_clock", "hsgn_work_items", "hsgn_set_timing",
-           "hsgn_get_timing", "hsgn_autotune", "hsgn_destroy", "hsgn_strerror",
+           "hsgn_get_timing", "hsgn_autotune", "hsgn_regrid", "hsgn_num_patches",
+           "hsgn_patch_info", "hsgn_destroy", "hsgn_strerror",
            "hsgn_last_error")
 
 
@@ -37,6 +38,11 @@ class hsgn_params(ctypes.Structure):
                 ("nbr_n", ctypes.c_int), ("limiter", ctypes.c_int),
                 ("transverse", ctypes.c_int), ("splitting", ctypes.c_int),
                 ("tile_rows", ctypes.c_int), ("c2", ctypes.c_double)]
+
+
+class hsgn_regrid_params(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("nbuf", ctypes.c_int), ("tol", ctypes.c_double),
+                ("cutoff", ctypes.c_double), ("max_side", ctypes.c_int)]
 
 
 class hsgn_diag(ctypes.Structure):
@@ -82,6 +88,9 @@ def lib():
         L.hsgn_work_items.argtypes = [vp, ip]
         L.hsgn_set_timing.argtypes = [vp, ctypes.c_int]
         L.hsgn_get_timing.argtypes = [vp, dp, dp]
+        L.hsgn_regrid.argtypes = [vp, ctypes.c_int, ctypes.POINTER(hsgn_regrid_params), ip]
+        L.hsgn_num_patches.argtypes = [vp, ip]
+        L.hsgn_patch_info.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip, dp, dp, dp, dp]
         L.hsgn_destroy.argtypes = [vp]
         L.hsgn_strerror.argtypes = [ctypes.c_int]
         L.hsgn_strerror.restype = ctypes.c_char_p
@@ -246,6 +255,36 @@ class Context:
         rows = (ctypes.c_int * 8)()
         self._check(lib().hsgn_autotune(self.h, int(trials), rows), "hsgn_autotune")
         return [rows[k] for k in range(8) if rows[k] > 0]
+
+    def regrid(self, scenario, level, tol, nbuf=2, cutoff=0.7, max_side=32):
+        """rebuild level+1 of a patch-set scenario from the surface-jump
+        flags on `level` (deeper levels are dropped); patch ids change:
+        returns the new patch list (self.patches())"""
+        r = hsgn_regrid_params(int(level), int(nbuf), float(tol), float(cutoff), int(max_side))
+        n = ctypes.c_int(0)
+        self._check(lib().hsgn_regrid(self.h, int(scenario), ctypes.byref(r), ctypes.byref(n)),
+                    "hsgn_regrid")
+        plist = self.patches()
+        self.grids = [types.SimpleNamespace(nx=p["nx"], ny=p["ny"], x0=p["x0"], y0=p["y0"],
+                                            dx=p["dx"], dy=p["dy"]) for p in plist]
+        return plist
+
+    def patches(self):
+        """[{scenario, level, nx, ny, x0, y0, dx, dy}] by patch id"""
+        n = ctypes.c_int(0)
+        self._check(lib().hsgn_num_patches(self.h, ctypes.byref(n)), "hsgn_num_patches")
+        out = []
+        for pid in range(n.value):
+            s, l, nx, ny = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            x0, y0, dx, dy = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            self._check(lib().hsgn_patch_info(self.h, pid, ctypes.byref(s), ctypes.byref(l),
+                                              ctypes.byref(nx), ctypes.byref(ny),
+                                              ctypes.byref(x0), ctypes.byref(y0),
+                                              ctypes.byref(dx), ctypes.byref(dy)),
+                        "hsgn_patch_info")
+            out.append(dict(scenario=s.value, level=l.value, nx=nx.value, ny=ny.value,
+                            x0=x0.value, y0=y0.value, dx=dx.value, dy=dy.value))
+        return out
 
     def work_items(self):
         n = ctypes.c_int()

@@ -139,6 +139,47 @@ def run_amr(H, torch, ws, precision, steps, warmup, tile_rows=0, autotune=True):
     return ctx, el, ms / max(n, 1), n, rows
 
 
+def run_adaptive(H, torch, w, steps, every, tol0, levels=2):
+    """Regridded patch sets: level 0 of the ocean as given, levels 1..levels
+    rebuilt every `every` level-0 steps from the surface-jump flags (the
+    tolerance shrinks by 4 per level, as the jumps do with the spacing).
+    Returns wall times of the whole loop and of the regrids, the cell updates
+    done, the step-kernel timing and the patch counts per level."""
+    ctx, _ = H.from_amr_workloads([w], precision=1)
+
+    def regrid_all():
+        for l in range(levels):
+            ctx.regrid(0, l, tol=tol0 / 4.0 ** l, nbuf=2)
+
+    regrid_all()
+    ctx.advance(-1.0, 1)                      # warm-up and graph capture
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    updates, t_regrid, nreg = 0, 0.0, 0
+    counts = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        plist = ctx.patches()
+        updates += k * sum(p["nx"] * p["ny"] * 4 ** p["level"] for p in plist)
+        counts.append([sum(1 for p in plist if p["level"] == l) for l in range(levels + 1)])
+        ctx.advance(-1.0, k)
+        done += k
+        if done < steps:
+            torch.cuda.synchronize()
+            r0 = time.perf_counter()
+            regrid_all()
+            torch.cuda.synchronize()
+            t_regrid += time.perf_counter() - r0
+            nreg += 1
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n = ctx.get_timing()
+    ctx.set_timing(False)
+    return ctx, el, t_regrid, nreg, updates, ms / max(n, 1), n, counts
+
+
 def amr_updates(w):
     """cell updates of one level-0 step of a patch set"""
     return sum(p.nx * p.ny * 4 ** p.level for p in w.patches)
@@ -180,7 +221,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="ensemble", choices=["ensemble", "beach", "ocean", "amr"])
+    ap.add_argument("--workload", default="ensemble",
+                    choices=["ensemble", "beach", "ocean", "amr", "amr_adaptive"])
+    ap.add_argument("--regrid-every", type=int, default=10,
+                    help="amr_adaptive: level-0 steps between regrids")
+    ap.add_argument("--regrid-tol", type=float, default=0.004,
+                    help="amr_adaptive: surface-jump tolerance on level 0 (m)")
+    ap.add_argument("--regrid-levels", type=int, default=1,
+                    help="amr_adaptive: refined levels rebuilt by regridding (1 or 2)")
     ap.add_argument("--model", default="hsgn", choices=["hsgn", "mbhsgn"],
                     help="hsgn (eq. HSGN, default) or mbhsgn (eq. mbHSGN)")
     ap.add_argument("--tile-rows", type=int, default=0,
@@ -216,6 +264,9 @@ def main():
     from paper_2606_12162_amd import hsgn as H
     from paper_2606_12162_amd import workloads as W
     t0 = time.perf_counter()
+    if args.workload == "amr_adaptive":
+        main_adaptive(args, H, W, torch)
+        return
     if args.workload == "ensemble":
         ws, precision = W.ensemble(), "mixed"
     elif args.workload == "ocean":
@@ -306,6 +357,45 @@ def main():
         # patch sets: the oracle on the level-0 ocean grid of the same set
         base = W.synthetic_ocean() if amr else ws[0]
         out["cpu_baseline"] = cpu_baseline(base, steps)
+    print(json.dumps(out), flush=True)
+
+
+def main_adaptive(args, H, W, torch):
+    import dataclasses
+    full = W.amr_ocean()
+    w = dataclasses.replace(full, patches=[p for p in full.patches if p.level == 0])
+    log("bench: %s, level 0 only (%d patches), %d level(s) regridded every %d steps, "
+        "tolerance %.4g m" % (full.name, len(w.patches), args.regrid_levels, args.regrid_every,
+                              args.regrid_tol))
+    ctx, el, t_reg, nreg, updates, kms, launches, counts = run_adaptive(
+        H, torch, w, args.steps, args.regrid_every, args.regrid_tol, args.regrid_levels)
+    value = updates / el
+    cells_per_launch = updates / max(launches, 1)
+    tflops = ALG_FLOPS * cells_per_launch / (kms / 1e3) / 1e12
+    hbm_gbs = ALG_BYTES["mixed"] * cells_per_launch / (kms / 1e3) / 1e9
+    log("timed: %.3f ms/step incl. regrids, %d regrids of %.1f ms, %.3e cell-updates/s; "
+        "patches per level %s .. %s" % (el * 1e3 / args.steps, nreg,
+                                        t_reg * 1e3 / max(nreg, 1), value, counts[0], counts[-1]))
+    out = {
+        "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": full.name + "_regridded", "precision": "mixed",
+                   "regrid_every": args.regrid_every, "regrid_tol_level0": args.regrid_tol,
+                   "regrid_levels": args.regrid_levels,
+                   "patches_per_level_first": counts[0], "patches_per_level_last": counts[-1]},
+        "regrid": {"count": nreg, "ms_mean": t_reg * 1e3 / max(nreg, 1),
+                   "share_of_wall": t_reg / el,
+                   "stepping_only_value": updates / max(el - t_reg, 1e-12)},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "march_kernel<mixed>", "kernel_avg_us": kms * 1e3,
+                     "launches": launches,
+                     "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": hbm_gbs / HBM_PEAK_GBS}},
+    }
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -433,6 +433,34 @@ __global__ void regrid_interp_kernel(const RegridInterp *R, int nr, long long to
     m1[F.coff + fl] = (uint8_t)((m1[F.coff + fl] & ~MASK_BRK) | lat);
 }
 
+// bilinear interpolant of the level-0 bathymetry at one cell centre, in
+// level-0 index coordinates (exact in binary), clamped at the outer centres
+template <class S>
+__global__ void topo_kernel(const TopoRec *R, int nr, long long total, const double *B0, int NX,
+                            int NY, S *bath)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    const TopoRec r = R[record_of(R, nr, k)];
+    const long long e = k - r.c0;
+    const int i = (int)(e % r.p.nx), j = (int)(e / r.p.nx);
+    const double sc = (double)(1LL << (2 * r.level));
+    const double fy = ((double)(r.J0 + j) + 0.5) / sc - 0.5;
+    int jj = (int)floor(fy);
+    jj = jj < 0 ? 0 : (jj > NY - 2 ? NY - 2 : jj);
+    double s = fy - jj;
+    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+    const double fx = ((double)(r.I0 + i) + 0.5) / sc - 0.5;
+    int ii = (int)floor(fx);
+    ii = ii < 0 ? 0 : (ii > NX - 2 ? NX - 2 : ii);
+    double t = fx - ii;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    const double *r0 = B0 + (long long)jj * NX, *r1 = B0 + (long long)(jj + 1) * NX;
+    const double b = (r0[ii] * (1.0 - t) + r0[ii + 1] * t) * (1.0 - s) +
+                     (r1[ii] * (1.0 - t) + r1[ii + 1] * t) * s;
+    bath[r.p.coff + (long long)j * r.p.pitch + i] = (S)b;
+}
+
 }  // namespace
 
 void launch_halo_copy64(const AmrBuffers<double> &B, const GhostCopy *r, int n, hipStream_t s)
@@ -550,6 +578,19 @@ void launch_regrid_interp32(const RegridInterp *r, int nr, long long total, floa
     if (nr > 0 && total > 0)
         regrid_interp_kernel<float, true><<<blocks(total), TPB, 0, s>>>(r, nr, total, q, bath, m0,
                                                                         m1, eta0, dry_tol);
+}
+
+void launch_topo64(const TopoRec *r, int nr, long long total, const double *B0, int NX, int NY,
+                   double *bath, hipStream_t s)
+{
+    if (nr > 0 && total > 0)
+        topo_kernel<double><<<blocks(total), TPB, 0, s>>>(r, nr, total, B0, NX, NY, bath);
+}
+void launch_topo32(const TopoRec *r, int nr, long long total, const double *B0, int NX, int NY,
+                   float *bath, hipStream_t s)
+{
+    if (nr > 0 && total > 0)
+        topo_kernel<float><<<blocks(total), TPB, 0, s>>>(r, nr, total, B0, NX, NY, bath);
 }
 
 }  // namespace hsgn

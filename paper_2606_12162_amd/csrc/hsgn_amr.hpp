@@ -122,6 +122,19 @@ struct RegridInterp {
     long long c0;
 };
 
+// bathymetry from the level-0 bathymetry B0[NY][NX] (cell-centred): the
+// bilinear interpolant at the centres of a level-`level` patch whose cell
+// (0, 0) is level cell (I0, J0); at level 0 it returns B0 itself
+struct TopoRec {
+    PatchInfo p;
+    int I0, J0, level, pad;
+    long long c0;
+};
+void launch_topo64(const TopoRec *r, int nr, long long total, const double *B0, int NX, int NY,
+                   double *bath, hipStream_t s);
+void launch_topo32(const TopoRec *r, int nr, long long total, const double *B0, int NX, int NY,
+                   float *bath, hipStream_t s);
+
 void launch_regrid_flag64(const PatchInfo &p, const double *q, const double *bath, uint8_t *out,
                           double eta0, double dry_tol, double tol, hipStream_t s);
 void launch_regrid_flag32(const PatchInfo &p, const float *q, const float *bath, uint8_t *out,

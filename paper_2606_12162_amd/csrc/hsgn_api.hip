@@ -294,6 +294,60 @@ __global__ void scatter_plane_kernel(PatchInfo pi, const A *in, S *out, int keep
     else out[idx] = (S)in[i];
 }
 
+// the bathymetry of many patches from one host-order buffer: records of
+// (patch, first cell) sorted by their first cell
+struct BulkRec {
+    PatchInfo p;
+    long long c0;
+};
+
+template <class S>
+__global__ void scatter_bulk_kernel(const BulkRec *R, int nr, long long total, const double *in,
+                                    S *out)
+{
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (R[mid].c0 <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    const PatchInfo pi = R[lo].p;
+    const long long e = k - R[lo].c0;
+    const int x = (int)(e % pi.nx), y = (int)(e / pi.nx);
+    out[pi.coff + (long long)y * pi.pitch + x] = (S)in[k];
+}
+
+// phi_T of many patch-set patches at once (records as for scatter_bulk_kernel)
+template <class S>
+__global__ void mask_bulk_kernel(const BulkRec *R, int nr, long long total, const S *bath,
+                                 uint8_t *m0, uint8_t *m1, double eta0, double h_star, int n)
+{
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (R[mid].c0 <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    const PatchInfo pi = R[lo].p;
+    const long long e = k - R[lo].c0;
+    const int x = (int)(e % pi.nx), y = (int)(e / pi.nx);
+    double hmin = INFINITY;
+    for (int dj = -n; dj <= n; dj++)
+        for (int di = -n; di <= n; di++) {
+            double H = eta0 - (double)bath[pi.coff + (long long)(y + dj) * pi.pitch + (x + di)];
+            H = H > 0.0 ? H : 0.0;
+            hmin = H < hmin ? H : hmin;
+        }
+    const uint8_t phi = hmin > h_star ? 1 : 0;
+    const long long idx = pi.coff + (long long)y * pi.pitch + x;
+    m0[idx] = phi;
+    m1[idx] = phi;
+}
+
 template <class S, class A>
 __global__ void gather_plane_kernel(PatchInfo pi, const S *in, A *out, int low_bits_only)
 {
@@ -346,6 +400,8 @@ struct hsgn_ctx {
     bool finalized = false;
     std::vector<PatchInfo> patches;
     std::vector<std::vector<double>> braw;   // bathymetry as set, per patch (host copy)
+    std::vector<char> braw_rule;             // 1: a regridded patch, bathymetry from the
+                                             // level-0 bathymetry (no host copy kept)
     std::vector<double> px0, py0;
     std::vector<int> pI0, pJ0;             // patch origin in cells of its level (patch sets)
     std::vector<ScenHost> scen;
@@ -482,23 +538,31 @@ static AmrBuffers<S> amr_buffers(hsgn_ctx *c, S *q0, S *q1, S *bath)
 
 struct LevelIndex {
     static constexpr int BS = 64;                     // bucket side in cells
-    std::map<long long, std::vector<int>> buckets;
+    std::vector<std::vector<int>> buckets;            // dense over the level's domain
+    long long NXl = 0, NYl = 0, nbx = 0, nby = 0;
     const hsgn_ctx *c = nullptr;
-    static long long key(long long bi, long long bj) { return (bi + (1LL << 30)) * (1LL << 31) + bj + (1LL << 30); }
     static long long fdiv(long long a, long long b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+    void init(const hsgn_ctx *ctx, long long nx, long long ny)
+    {
+        c = ctx;
+        NXl = nx; NYl = ny;
+        nbx = (nx + BS - 1) / BS;
+        nby = (ny + BS - 1) / BS;
+        buckets.assign((size_t)(nbx * nby), std::vector<int>());
+    }
     void add(int pid)
     {
         const PatchInfo &p = c->patches[pid];
         long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
-        for (long long bj = fdiv(J0, BS); bj <= fdiv(J0 + p.ny - 1, BS); bj++)
-            for (long long bi = fdiv(I0, BS); bi <= fdiv(I0 + p.nx - 1, BS); bi++)
-                buckets[key(bi, bj)].push_back(pid);
+        long long b0 = std::max(fdiv(J0, BS), 0LL), b1 = std::min(fdiv(J0 + p.ny - 1, BS), nby - 1);
+        long long a0 = std::max(fdiv(I0, BS), 0LL), a1 = std::min(fdiv(I0 + p.nx - 1, BS), nbx - 1);
+        for (long long bj = b0; bj <= b1; bj++)
+            for (long long bi = a0; bi <= a1; bi++) buckets[(size_t)(bj * nbx + bi)].push_back(pid);
     }
     int find(long long I, long long J) const
     {
-        auto it = buckets.find(key(fdiv(I, BS), fdiv(J, BS)));
-        if (it == buckets.end()) return -1;
-        for (int pid : it->second) {
+        if (I < 0 || J < 0 || I >= NXl || J >= NYl) return -1;
+        for (int pid : buckets[(size_t)((J / BS) * nbx + I / BS)]) {
             const PatchInfo &p = c->patches[pid];
             long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
             if (I >= I0 && I < I0 + p.nx && J >= J0 && J < J0 + p.ny) return pid;
@@ -537,7 +601,9 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<int>> &le
     const int nl = (int)sh.lev.size();
     std::vector<LevelIndex> idx(nl);
     for (int l = 0; l < nl; l++) {
-        idx[l].c = c;
+        long long f = 1;
+        for (int k = 0; k < l; k++) f *= AMR_RATIO;
+        idx[l].init(c, (long long)sh.NX * f, (long long)sh.NY * f);
         for (int pid : sh.lev[l]) idx[l].add(pid);
     }
     // no two patches of a level overlap
@@ -1184,17 +1250,38 @@ static int ensure_prepared(hsgn_ctx *c)
     else
         launch_ghost_bath64(amr_buffers<double>(c, c->q0, c->q1, c->bath), c->d_gc, nc, c->d_gi, ni,
                             c->stream);
-    for (size_t s = 0; s < c->scen.size(); s++) {
-        if (!c->scen[s].amr) continue;
-        for (int pid : c->scen[s].patches) {
-            const PatchInfo &p = c->patches[pid];
-            unsigned nb = nblk((long long)p.nx * p.ny);
-            if (c->mixed)
-                mask_kernel<float><<<nb, 256, 0, c->stream>>>(p, c->fbath, c->m0, c->m1, c->prm.eta0,
-                                                              c->prm.h_star, c->prm.nbr_n);
-            else
-                mask_kernel<double><<<nb, 256, 0, c->stream>>>(p, c->bath, c->m0, c->m1, c->prm.eta0,
-                                                               c->prm.h_star, c->prm.nbr_n);
+    {
+        // phi_T of every patch-set patch, one launch (the ghost frames hold
+        // the neighbourhood's bathymetry)
+        std::vector<BulkRec> recs;
+        long long tot = 0;
+        for (size_t s = 0; s < c->scen.size(); s++) {
+            if (!c->scen[s].amr) continue;
+            for (int pid : c->scen[s].patches) {
+                recs.push_back({c->patches[pid], tot});
+                tot += (long long)c->patches[pid].nx * c->patches[pid].ny;
+            }
+        }
+        if (!recs.empty()) {
+            BulkRec *d = nullptr;
+            HIPCHK(c, hipMalloc(&d, sizeof(BulkRec) * recs.size()));
+            hipError_t e = hipMemcpy(d, recs.data(), sizeof(BulkRec) * recs.size(),
+                                     hipMemcpyHostToDevice);
+            if (e == hipSuccess) {
+                if (c->mixed)
+                    mask_bulk_kernel<float><<<nblk(tot), 256, 0, c->stream>>>(
+                        d, (int)recs.size(), tot, c->fbath, c->m0, c->m1, c->prm.eta0, c->prm.h_star,
+                        c->prm.nbr_n);
+                else
+                    mask_bulk_kernel<double><<<nblk(tot), 256, 0, c->stream>>>(
+                        d, (int)recs.size(), tot, c->bath, c->m0, c->m1, c->prm.eta0, c->prm.h_star,
+                        c->prm.nbr_n);
+                e = hipGetLastError();
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            }
+            (void)hipFree(d);
+            if (e != hipSuccess)
+                return fail(c, HSGN_EDEVICE, std::string("phi_T: ") + hipGetErrorString(e));
         }
     }
     launch_iface(c->d_patches, c->d_rf, (int)c->h_rf.size(), c->m0, c->m1, c->stream);
@@ -1215,6 +1302,8 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
     unsigned nb = nblk(n);
     // host copy of the bathymetry as set: regridding rebuilds from it
     if ((int)c->braw.size() < (int)c->patches.size()) c->braw.resize(c->patches.size());
+    if ((int)c->braw_rule.size() < (int)c->patches.size()) c->braw_rule.resize(c->patches.size(), 0);
+    c->braw_rule[patch] = 0;
     c->braw[patch].resize((size_t)n);
     if (on_device)
         HIPCHK(c, hipMemcpy(c->braw[patch].data(), b, sizeof(double) * n, hipMemcpyDeviceToHost));
@@ -2310,10 +2399,12 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     if (level < 0 || level >= (int)sh.lev.size() || level + 1 > 5 || !(r->tol == r->tol) ||
         r->nbuf < 0 || r->nbuf > 64 || !(r->cutoff > 0.0 && r->cutoff <= 1.0) || r->max_side < 1)
         return fail(c, HSGN_EINVAL, "bad regrid parameters");
-    for (int pid : sh.patches)
-        if (pid >= (int)c->braw.size() || c->braw[pid].size() != (size_t)c->patches[pid].nx *
-                                                                        c->patches[pid].ny)
+    for (int pid : sh.patches) {
+        const bool rule = pid < (int)c->braw_rule.size() && c->braw_rule[pid];
+        if (!rule && (pid >= (int)c->braw.size() ||
+                      c->braw[pid].size() != (size_t)c->patches[pid].nx * c->patches[pid].ny))
             return fail(c, HSGN_EINVAL, "set the bathymetry of every patch before regridding");
+    }
     int rc = ensure_prepared(c);
     if (rc) return rc;
     std::vector<ScenState> st;
@@ -2321,21 +2412,37 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     // 1-4. flags of the level-l patches, clusters, new level-(l+1) boxes
     struct NewBox { int parent, nx, ny, I0, J0; };
     std::vector<NewBox> boxes;
+    std::vector<long long> foff;
+    long long ftot = 0;
     for (int pid : sh.lev[level]) {
-        const PatchInfo &p = c->patches[pid];
+        foff.push_back(ftot);
+        ftot += (long long)c->patches[pid].nx * c->patches[pid].ny;
+    }
+    uint8_t *dflag = nullptr;
+    HIPCHK(c, hipMalloc(&dflag, (size_t)std::max<long long>(ftot, 1)));
+    for (size_t k = 0; k < sh.lev[level].size(); k++) {
+        const PatchInfo &p = c->patches[sh.lev[level][k]];
         const int cur = st[p.scen].cur;
-        uint8_t *dflag = (uint8_t *)c->stage;
         if (c->mixed)
-            launch_regrid_flag32(p, cur ? c->f1 : c->f0, c->fbath, dflag, c->prm.eta0,
+            launch_regrid_flag32(p, cur ? c->f1 : c->f0, c->fbath, dflag + foff[k], c->prm.eta0,
                                  c->prm.dry_tol, r->tol, c->stream);
         else
-            launch_regrid_flag64(p, cur ? c->q1 : c->q0, c->bath, dflag, c->prm.eta0,
+            launch_regrid_flag64(p, cur ? c->q1 : c->q0, c->bath, dflag + foff[k], c->prm.eta0,
                                  c->prm.dry_tol, r->tol, c->stream);
-        HIPCHK(c, hipGetLastError());
-        std::vector<uint8_t> F((size_t)p.nx * p.ny), B;
-        HIPCHK(c, hipMemcpyAsync(F.data(), dflag, F.size(), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        B = F;
+    }
+    std::vector<uint8_t> Fall((size_t)std::max<long long>(ftot, 1));
+    hipError_t fe = hipGetLastError();
+    if (fe == hipSuccess)
+        fe = hipMemcpyAsync(Fall.data(), dflag, (size_t)ftot, hipMemcpyDeviceToHost, c->stream);
+    if (fe == hipSuccess) fe = hipStreamSynchronize(c->stream);
+    (void)hipFree(dflag);
+    if (fe != hipSuccess)
+        return fail(c, HSGN_EDEVICE, std::string("regrid flags: ") + hipGetErrorString(fe));
+    for (size_t k = 0; k < sh.lev[level].size(); k++) {
+        const int pid = sh.lev[level][k];
+        const PatchInfo &p = c->patches[pid];
+        std::vector<uint8_t> F(Fall.begin() + foff[k], Fall.begin() + foff[k] + (long long)p.nx * p.ny);
+        std::vector<uint8_t> B = F;
         for (int j = 0; j < p.ny; j++)
             for (int i = 0; i < p.nx; i++) {
                 if (!F[(size_t)j * p.nx + i]) continue;
@@ -2395,11 +2502,12 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     }
     if ((rc = hsgn_finalize(n))) return bail(rc, "regrid: finalize");
     n->timing = c->timing;
-    // bathymetry as set (kept patches) or from the level-0 bathymetry (new)
-    for (auto &k : kept)
-        if ((rc = hsgn_set_bathymetry(n, k.second, c->braw[k.first].data(), 0)))
-            return bail(rc, "regrid: bathymetry");
-    if (!boxes.empty()) {
+    // bathymetry: level-0 and regridded patches from the level-0 bathymetry
+    // B0 (on the device; at level 0 the rule returns B0 itself), patches given
+    // by the caller from their host copies (one transfer)
+    n->braw.assign(n->patches.size(), std::vector<double>());
+    n->braw_rule.assign(n->patches.size(), 0);
+    {
         std::vector<double> B0((size_t)sh.NX * sh.NY);
         for (int pid : sh.lev[0]) {
             const PatchInfo &p = c->patches[pid];
@@ -2407,13 +2515,102 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
                 memcpy(&B0[(size_t)(c->pJ0[pid] + j) * sh.NX + c->pI0[pid]],
                        &c->braw[pid][(size_t)j * p.nx], sizeof(double) * p.nx);
         }
-        std::vector<double> bt;
-        for (size_t k = 0; k < boxes.size(); k++) {
-            rg_topo(B0, sh.NX, sh.NY, level + 1, boxes[k].nx, boxes[k].ny, boxes[k].I0,
-                    boxes[k].J0, bt);
-            if ((rc = hsgn_set_bathymetry(n, fresh_ids[k], bt.data(), 0)))
-                return bail(rc, "regrid: bathymetry (new patch)");
+        std::vector<TopoRec> topo;
+        std::vector<BulkRec> bulk;
+        long long ttot = 0, btot = 0;
+        auto add_topo = [&](int id) {
+            TopoRec t;
+            memset(&t, 0, sizeof(t));
+            t.p = n->patches[id];
+            t.I0 = n->pI0[id]; t.J0 = n->pJ0[id]; t.level = n->patches[id].level;
+            t.c0 = ttot;
+            ttot += (long long)t.p.nx * t.p.ny;
+            topo.push_back(t);
+        };
+        for (auto &k : kept) {
+            const bool this_scen = n->slot_scen[n->patches[k.second].scen] == scenario;
+            const bool rule = k.first < (int)c->braw_rule.size() && c->braw_rule[k.first];
+            if (this_scen && (c->patches[k.first].level == 0 || rule)) {
+                add_topo(k.second);
+                n->braw_rule[k.second] = rule ? 1 : 0;
+                if (!rule) n->braw[k.second] = c->braw[k.first];
+            } else if (rule) {
+                return bail(HSGN_EINVAL, "regrid: rule bathymetry outside its scenario");
+            } else {
+                n->braw[k.second] = c->braw[k.first];
+                bulk.push_back({n->patches[k.second], btot});
+                btot += (long long)n->braw[k.second].size();
+            }
         }
+        for (int id : fresh_ids) {
+            add_topo(id);
+            n->braw_rule[id] = 1;
+        }
+        std::vector<double> all((size_t)std::max<long long>(btot, 1));
+        for (size_t k = 0, pos = 0; k < kept.size(); k++) {
+            const int id = kept[k].second;
+            if (n->braw[id].empty() || n->braw_rule[id]) continue;
+            const bool topo_done = n->slot_scen[n->patches[id].scen] == scenario &&
+                                   n->patches[id].level == 0;
+            if (topo_done) continue;
+            memcpy(&all[pos], n->braw[id].data(), sizeof(double) * n->braw[id].size());
+            pos += n->braw[id].size();
+        }
+        double *dB0 = nullptr, *din = nullptr;
+        TopoRec *dtopo = nullptr;
+        BulkRec *dbulk = nullptr;
+        hipError_t be = hipMalloc(&dB0, sizeof(double) * B0.size());
+        if (be == hipSuccess)
+            be = hipMemcpy(dB0, B0.data(), sizeof(double) * B0.size(), hipMemcpyHostToDevice);
+        if (be == hipSuccess && !topo.empty()) {
+            be = hipMalloc(&dtopo, sizeof(TopoRec) * topo.size());
+            if (be == hipSuccess)
+                be = hipMemcpy(dtopo, topo.data(), sizeof(TopoRec) * topo.size(), hipMemcpyHostToDevice);
+        }
+        if (be == hipSuccess && !bulk.empty()) {
+            be = hipMalloc(&din, sizeof(double) * btot);
+            if (be == hipSuccess) be = hipMalloc(&dbulk, sizeof(BulkRec) * bulk.size());
+            if (be == hipSuccess)
+                be = hipMemcpy(din, all.data(), sizeof(double) * btot, hipMemcpyHostToDevice);
+            if (be == hipSuccess)
+                be = hipMemcpy(dbulk, bulk.data(), sizeof(BulkRec) * bulk.size(), hipMemcpyHostToDevice);
+        }
+        if (be == hipSuccess) {
+            if (n->mixed) {
+                launch_topo32(dtopo, (int)topo.size(), ttot, dB0, sh.NX, sh.NY, n->fbath, n->stream);
+                if (!bulk.empty())
+                    scatter_bulk_kernel<float><<<nblk(btot), 256, 0, n->stream>>>(
+                        dbulk, (int)bulk.size(), btot, din, n->fbath);
+            } else {
+                launch_topo64(dtopo, (int)topo.size(), ttot, dB0, sh.NX, sh.NY, n->bath, n->stream);
+                if (!bulk.empty())
+                    scatter_bulk_kernel<double><<<nblk(btot), 256, 0, n->stream>>>(
+                        dbulk, (int)bulk.size(), btot, din, n->bath);
+            }
+            // single grids: phi_T from their bathymetry (patch sets: at preparation)
+            for (size_t pid = 0; pid < n->patches.size(); pid++) {
+                const PatchInfo &p = n->patches[pid];
+                if (p.frame) continue;
+                unsigned nb = nblk((long long)p.nx * p.ny);
+                if (n->mixed)
+                    mask_kernel<float><<<nb, 256, 0, n->stream>>>(p, n->fbath, n->m0, n->m1,
+                                                                  n->prm.eta0, n->prm.h_star,
+                                                                  n->prm.nbr_n);
+                else
+                    mask_kernel<double><<<nb, 256, 0, n->stream>>>(p, n->bath, n->m0, n->m1,
+                                                                   n->prm.eta0, n->prm.h_star,
+                                                                   n->prm.nbr_n);
+            }
+            be = hipGetLastError();
+            if (be == hipSuccess) be = hipStreamSynchronize(n->stream);
+        }
+        if (dB0) (void)hipFree(dB0);
+        if (dtopo) (void)hipFree(dtopo);
+        if (din) (void)hipFree(din);
+        if (dbulk) (void)hipFree(dbulk);
+        if (be != hipSuccess)
+            return bail(HSGN_EDEVICE, std::string("regrid: bathymetry: ") + hipGetErrorString(be));
+        n->amr_dirty = n->any_amr;
     }
     if ((rc = ensure_prepared(n))) return bail(rc, "regrid: prepare");
     // 6. the state
@@ -2483,7 +2680,10 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
             if (e != hipSuccess) return bail(HSGN_EDEVICE, "regrid: gauge records");
         }
     if ((rc = push_scen(n, sn))) return bail(rc, "regrid: clock");
-    // 8. the new context replaces the old one
+    // 8. the new context replaces the old one (with the kernel timing so far)
+    if ((rc = collect_timing(c))) return bail(rc, "regrid: timing");
+    n->timed_ms = c->timed_ms;
+    n->timed_launches = c->timed_launches;
     std::swap(*c, *n);
     hsgn_destroy(n);
     if (n_new) *n_new = (int)boxes.size();

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include <map>
+#include <thread>
 
 #include "hsgn.h"
 #include "hsgn_amr.hpp"
@@ -636,82 +637,112 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<int>> &le
     auto covered = [&](int l, long long I, long long J) {
         return l + 1 < nl && idx[l + 1].find(AMR_RATIO * I, AMR_RATIO * J) >= 0;
     };
-    for (int l = 0; l < nl; l++) {
-        for (int pid : sh.lev[l]) {
-            const PatchInfo &P = c->patches[pid];
-            const long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
-            // ghost cells
-            for (int j = -2; j < P.ny + 2; j++)
-                for (int i = -2; i < P.nx + 2; i++) {
-                    if (i >= 0 && i < P.nx && j >= 0 && j < P.ny) continue;
-                    long long I = I0 + i, J = J0 + j;
-                    if (l == 0) {
-                        int fx, fy;
-                        int mi = host_map((int)I, sh.NX, sh.bc[0], sh.bc[1], &fx);
-                        int mj = host_map((int)J, sh.NY, sh.bc[2], sh.bc[3], &fy);
-                        int sp = idx[0].find(mi, mj);
-                        if (sp < 0) return fail(c, HSGN_EINVAL, "level-0 patches leave a hole");
-                        lev_gc[l].push_back((int)gc.size());
-                        gc.push_back({pid, local_of(P, i, j), sp,
+    // per patch: ghost, boundary-flux and covered-cell records.  Patches are
+    // independent (the indexes are read only), so they are built on host
+    // threads and joined in patch order: the tables do not depend on the
+    // number of threads.
+    struct PatchRecs {
+        std::vector<GhostCopy> gc;
+        std::vector<GhostInterp> gi;
+        std::vector<FluxRec> fr;
+        std::vector<AvgRec> av;
+        const char *err = nullptr;
+    };
+    auto build_one = [&](int l, int pid, PatchRecs &out) {
+        const PatchInfo &P = c->patches[pid];
+        const long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
+        // ghost cells
+        for (int j = -2; j < P.ny + 2; j++)
+            for (int i = -2; i < P.nx + 2; i++) {
+                if (i >= 0 && i < P.nx && j >= 0 && j < P.ny) continue;
+                long long I = I0 + i, J = J0 + j;
+                if (l == 0) {
+                    int fx, fy;
+                    int mi = host_map((int)I, sh.NX, sh.bc[0], sh.bc[1], &fx);
+                    int mj = host_map((int)J, sh.NY, sh.bc[2], sh.bc[3], &fy);
+                    int sp = idx[0].find(mi, mj);
+                    if (sp < 0) { out.err = "level-0 patches leave a hole"; return; }
+                    out.gc.push_back({pid, local_of(P, i, j), sp,
                                       local_of(c->patches[sp], mi - c->pI0[sp], mj - c->pJ0[sp]),
                                       fx | (fy << 1)});
-                        continue;
-                    }
-                    int sp = idx[l].find(I, J);
-                    if (sp >= 0) {
-                        lev_gc[l].push_back((int)gc.size());
-                        gc.push_back({pid, local_of(P, i, j), sp,
-                                      local_of(c->patches[sp], I - c->pI0[sp], J - c->pJ0[sp]), 0});
-                        continue;
-                    }
-                    long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
-                    GhostInterp g;
-                    g.dp = pid;
-                    g.dl = local_of(P, i, j);
-                    const long long nb[5][2] = {{Ic, Jc}, {Ic - 1, Jc}, {Ic + 1, Jc}, {Ic, Jc - 1}, {Ic, Jc + 1}};
-                    for (int k = 0; k < 5; k++) {
-                        int cp = idx[l - 1].find(nb[k][0], nb[k][1]);
-                        g.cp[k] = cp;
-                        g.cl[k] = cp >= 0 ? local_of(c->patches[cp], nb[k][0] - c->pI0[cp],
-                                                     nb[k][1] - c->pJ0[cp]) : 0;
-                    }
-                    if (g.cp[0] < 0) return fail(c, HSGN_EINVAL, "refined patch not properly nested");
-                    g.ox = (float)(((double)(I - AMR_RATIO * Ic) + 0.5) / AMR_RATIO - 0.5);
-                    g.oy = (float)(((double)(J - AMR_RATIO * Jc) + 0.5) / AMR_RATIO - 0.5);
-                    lev_gi[l].push_back((int)gi.size());
-                    gi.push_back(g);
+                    continue;
                 }
-            if (l == 0) continue;
-            // boundary edges facing the coarser level: left, right, bottom, top
-            for (int side = 0; side < 4; side++) {
-                int len = side < 2 ? P.ny : P.nx;
-                for (int k = 0; k < len; k++) {
-                    int gi_ = side == 0 ? -1 : side == 1 ? P.nx : k;
-                    int gj_ = side < 2 ? k : side == 2 ? -1 : P.ny;
-                    long long I = I0 + gi_, J = J0 + gj_;
-                    if (idx[l].find(I, J) >= 0) continue;
-                    long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
-                    int cp = idx[l - 1].find(Ic, Jc);
-                    if (cp < 0) return fail(c, HSGN_EINVAL, "refined patch not properly nested");
-                    int entry = side == 0 ? k : side == 1 ? P.ny + k : side == 2 ? 2 * P.ny + k
-                                                                                   : 2 * P.ny + P.nx + k;
-                    lev_fr[l].push_back((int)fr.size());
-                    fr.push_back({pid, entry, local_of(P, gi_, gj_), cp,
+                int sp = idx[l].find(I, J);
+                if (sp >= 0) {
+                    out.gc.push_back({pid, local_of(P, i, j), sp,
+                                      local_of(c->patches[sp], I - c->pI0[sp], J - c->pJ0[sp]), 0});
+                    continue;
+                }
+                long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
+                GhostInterp g;
+                g.dp = pid;
+                g.dl = local_of(P, i, j);
+                const long long nb[5][2] = {{Ic, Jc}, {Ic - 1, Jc}, {Ic + 1, Jc}, {Ic, Jc - 1}, {Ic, Jc + 1}};
+                for (int k = 0; k < 5; k++) {
+                    int cp = idx[l - 1].find(nb[k][0], nb[k][1]);
+                    g.cp[k] = cp;
+                    g.cl[k] = cp >= 0 ? local_of(c->patches[cp], nb[k][0] - c->pI0[cp],
+                                                 nb[k][1] - c->pJ0[cp]) : 0;
+                }
+                if (g.cp[0] < 0) { out.err = "refined patch not properly nested"; return; }
+                g.ox = (float)(((double)(I - AMR_RATIO * Ic) + 0.5) / AMR_RATIO - 0.5);
+                g.oy = (float)(((double)(J - AMR_RATIO * Jc) + 0.5) / AMR_RATIO - 0.5);
+                out.gi.push_back(g);
+            }
+        if (l == 0) return;
+        // boundary edges facing the coarser level: left, right, bottom, top
+        for (int side = 0; side < 4; side++) {
+            int len = side < 2 ? P.ny : P.nx;
+            for (int k = 0; k < len; k++) {
+                int gi_ = side == 0 ? -1 : side == 1 ? P.nx : k;
+                int gj_ = side < 2 ? k : side == 2 ? -1 : P.ny;
+                long long I = I0 + gi_, J = J0 + gj_;
+                if (idx[l].find(I, J) >= 0) continue;
+                long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
+                int cp = idx[l - 1].find(Ic, Jc);
+                if (cp < 0) { out.err = "refined patch not properly nested"; return; }
+                int entry = side == 0 ? k : side == 1 ? P.ny + k : side == 2 ? 2 * P.ny + k
+                                                                               : 2 * P.ny + P.nx + k;
+                out.fr.push_back({pid, entry, local_of(P, gi_, gj_), cp,
                                   local_of(c->patches[cp], Ic - c->pI0[cp], Jc - c->pJ0[cp]),
                                   side < 2 ? 0 : 1, (side == 0 || side == 2) ? 1 : 0});
-                }
             }
-            // covered coarse cells
-            for (int jj = 0; jj < P.ny / AMR_RATIO; jj++)
-                for (int ii = 0; ii < P.nx / AMR_RATIO; ii++) {
-                    long long Ic = I0 / AMR_RATIO + ii, Jc = J0 / AMR_RATIO + jj;
-                    int cp = idx[l - 1].find(Ic, Jc);
-                    if (cp < 0) return fail(c, HSGN_EINVAL, "refined patch outside the coarser level");
-                    lev_av[l].push_back((int)av.size());
-                    av.push_back({pid, local_of(P, AMR_RATIO * ii, AMR_RATIO * jj), cp,
-                                  local_of(c->patches[cp], Ic - c->pI0[cp], Jc - c->pJ0[cp])});
-                }
         }
+        // covered coarse cells
+        for (int jj = 0; jj < P.ny / AMR_RATIO; jj++)
+            for (int ii = 0; ii < P.nx / AMR_RATIO; ii++) {
+                long long Ic = I0 / AMR_RATIO + ii, Jc = J0 / AMR_RATIO + jj;
+                int cp = idx[l - 1].find(Ic, Jc);
+                if (cp < 0) { out.err = "refined patch outside the coarser level"; return; }
+                out.av.push_back({pid, local_of(P, AMR_RATIO * ii, AMR_RATIO * jj), cp,
+                                  local_of(c->patches[cp], Ic - c->pI0[cp], Jc - c->pJ0[cp])});
+            }
+    };
+    const int hw = (int)std::thread::hardware_concurrency();
+    const int nthreads = std::max(1, std::min(16, hw));
+    for (int l = 0; l < nl; l++) {
+        const std::vector<int> &L = sh.lev[l];
+        std::vector<PatchRecs> recs(L.size());
+        auto work = [&](int t) {
+            for (size_t k = (size_t)t; k < L.size(); k += (size_t)nthreads) build_one(l, L[k], recs[k]);
+        };
+        if (nthreads > 1 && L.size() > 8) {
+            std::vector<std::thread> th;
+            for (int t = 0; t < nthreads; t++) th.emplace_back(work, t);
+            for (auto &x : th) x.join();
+        } else {
+            work(0);
+            for (int t = 1; t < nthreads; t++) work(t);
+        }
+        for (auto &r : recs) {
+            if (r.err) return fail(c, HSGN_EINVAL, r.err);
+            for (auto &x : r.gc) { lev_gc[l].push_back((int)gc.size()); gc.push_back(x); }
+            for (auto &x : r.gi) { lev_gi[l].push_back((int)gi.size()); gi.push_back(x); }
+            for (auto &x : r.fr) { lev_fr[l].push_back((int)fr.size()); fr.push_back(x); }
+            for (auto &x : r.av) { lev_av[l].push_back((int)av.size()); av.push_back(x); }
+        }
+    }
+    for (int l = 0; l < nl; l++) {
         // reflux records: uncovered level-l cells next to a level-(l+1) patch
         if (l + 1 < nl) {
             std::vector<std::pair<long long, long long>> cand;

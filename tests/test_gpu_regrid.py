@@ -172,3 +172,38 @@ def test_regrid_refusals_leave_the_context_usable():
     o.advance(w.dt, 1)
     compare(ctx, o, "after refused regrids")
     ctx.close()
+
+
+def test_full_size_ocean_regrid_matches_oracle_clusters():
+    """the ocean of the adaptive benchmark at full size (level 0: 2048^2 in
+    256 patches): the level-1 patches the GPU builds from its flags equal
+    those the oracle's flags and clusters give on the same state (FP64), and
+    after regrids every 5 steps the mixed form's gauges stay within 1e-4 of
+    the amplitude of the FP64 run"""
+    import dataclasses
+    full = W.amr_ocean()
+    w = dataclasses.replace(full, patches=[p for p in full.patches if p.level == 0])
+    print("case", w.name, "level 0 only", flush=True)
+    o = A.from_workload(w)
+    o.prepare()
+    boxes = RG.new_boxes(o, 0, 0.004, 2, 0.7, 32)
+    gauges = {}
+    for precision in (0, 1):
+        ctx, ids = H.from_amr_workloads([w], precision=precision)
+        plist = ctx.regrid(0, 0, tol=0.004, nbuf=2)
+        fine = [p for p in plist if p["level"] == 1]
+        if precision == 0:
+            dx1 = w.dx0 / 4
+            got = [(p["nx"], p["ny"], int(round(p["x0"] / dx1)), int(round(p["y0"] / dx1)))
+                   for p in fine]
+            assert got == boxes, (len(got), len(boxes))
+            print("level-1 patches", len(fine), "cells", sum(p["nx"] * p["ny"] for p in fine))
+        for cycle in range(3):
+            ctx.advance(-1.0, 5)
+            ctx.regrid(0, 0, tol=0.004, nbuf=2)
+        ctx.advance(-1.0, 5)
+        gauges[precision] = ctx.read_gauges(0)[1]
+        ctx.close()
+    err = np.abs(gauges[1] - gauges[0]).max() / w.amplitude
+    print("mixed vs FP64 gauge error / amplitude", err)
+    assert err <= 1e-4

@@ -134,7 +134,9 @@ int hsgn_finalize(hsgn_ctx *c);
 
 /* Bathymetry b[ny][nx] of a patch; computes H = (eta0 - b)^+ and phi_T (the
  * minimum of H over the (2n+1)^2 box through the boundary map exceeds
- * h_star) and clears the breaking latch. */
+ * h_star) and clears the breaking latch.  The library keeps a host copy of b
+ * (8 bytes per cell; regridding rebuilds from it); a device pointer is read
+ * with a synchronous copy. */
 int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device);
 
 /* State q[7][ny][nx] (float64) of a patch, copied in or out. */

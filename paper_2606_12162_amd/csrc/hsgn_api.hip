@@ -2469,11 +2469,15 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     (void)hipFree(dflag);
     if (fe != hipSuccess)
         return fail(c, HSGN_EDEVICE, std::string("regrid flags: ") + hipGetErrorString(fe));
-    for (size_t k = 0; k < sh.lev[level].size(); k++) {
+    // buffer and clusters per level-l patch, on host threads, joined in
+    // patch order
+    const size_t np_l = sh.lev[level].size();
+    std::vector<std::vector<NewBox>> pboxes(np_l);
+    auto cluster_one = [&](size_t k) {
         const int pid = sh.lev[level][k];
         const PatchInfo &p = c->patches[pid];
-        std::vector<uint8_t> F(Fall.begin() + foff[k], Fall.begin() + foff[k] + (long long)p.nx * p.ny);
-        std::vector<uint8_t> B = F;
+        const uint8_t *F = Fall.data() + foff[k];
+        std::vector<uint8_t> B(F, F + (long long)p.nx * p.ny);
         for (int j = 0; j < p.ny; j++)
             for (int i = 0; i < p.nx; i++) {
                 if (!F[(size_t)j * p.nx + i]) continue;
@@ -2487,10 +2491,24 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
             const int i0 = std::max(x.i0, 1), i1 = std::min(x.i1, p.nx - 1);
             const int j0 = std::max(x.j0, 1), j1 = std::min(x.j1, p.ny - 1);
             if (i1 <= i0 || j1 <= j0) continue;
-            boxes.push_back({pid, AMR_RATIO * (i1 - i0), AMR_RATIO * (j1 - j0),
-                             AMR_RATIO * (c->pI0[pid] + i0), AMR_RATIO * (c->pJ0[pid] + j0)});
+            pboxes[k].push_back({pid, AMR_RATIO * (i1 - i0), AMR_RATIO * (j1 - j0),
+                                 AMR_RATIO * (c->pI0[pid] + i0), AMR_RATIO * (c->pJ0[pid] + j0)});
+        }
+    };
+    {
+        const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+        if (nt > 1 && np_l > 8) {
+            std::vector<std::thread> th;
+            for (int t = 0; t < nt; t++)
+                th.emplace_back([&, t]() {
+                    for (size_t k = (size_t)t; k < np_l; k += (size_t)nt) cluster_one(k);
+                });
+            for (auto &x : th) x.join();
+        } else {
+            for (size_t k = 0; k < np_l; k++) cluster_one(k);
         }
     }
+    for (auto &v : pboxes) boxes.insert(boxes.end(), v.begin(), v.end());
     // 5. the new context: every patch of the other scenarios, the levels <= l
     // of this one, then the new boxes
     hsgn_ctx *n = nullptr;

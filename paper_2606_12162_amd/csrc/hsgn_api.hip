@@ -806,39 +806,77 @@ static bool local_ok(const hsgn_ctx *c, int pid, int local, bool interior)
            !(i >= 0 && i < p.nx && j >= 0 && j < p.ny);
 }
 
+// true if ok(k) holds for every k < n, checked on host threads
+template <class F>
+static bool all_of_parallel(size_t n, F ok)
+{
+    const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    if (nt == 1 || n < 4096) {
+        for (size_t k = 0; k < n; k++)
+            if (!ok(k)) return false;
+        return true;
+    }
+    std::vector<char> good(nt, 1);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; t++)
+        th.emplace_back([&, t]() {
+            for (size_t k = (size_t)t; k < n; k += (size_t)nt)
+                if (!ok(k)) { good[t] = 0; return; }
+        });
+    for (auto &x : th) x.join();
+    for (char g : good)
+        if (!g) return false;
+    return true;
+}
+
 static int validate_tables(hsgn_ctx *c)
 {
     auto bad = [&](const char *what) { return fail(c, HSGN_EINVAL, std::string("internal table check: ") + what); };
-    for (const GhostCopy &r : c->h_gc)
-        if (!local_ok(c, r.dp, r.dl, false) || !local_ok(c, r.sp, r.sl, true)) return bad("ghost copy");
-    for (const GhostInterp &r : c->h_gi) {
-        if (!local_ok(c, r.dp, r.dl, false) || r.cp[0] < 0) return bad("ghost interpolation");
-        for (int k = 0; k < 5; k++)
-            if (r.cp[k] >= 0 && !local_ok(c, r.cp[k], r.cl[k], true)) return bad("ghost stencil");
-    }
-    for (const FluxRec &r : c->h_fr) {
-        if (!local_ok(c, r.fp, r.gl, false) || !local_ok(c, r.cp, r.cl, true)) return bad("flux record");
-        const PatchInfo &F = c->patches[r.fp];
-        if (F.eoff < 0 || r.entry < 0 || r.entry >= 2 * (F.nx + F.ny)) return bad("flux entry");
-    }
-    for (const RefluxRec &r : c->h_rf) {
-        if (!local_ok(c, r.cp, r.cl, true)) return bad("reflux cell");
-        for (int e = 0; e < 4; e++) {
-            if (r.fp[e] < 0) continue;
-            if (r.fp[e] >= (int)c->patches.size()) return bad("reflux patch");
-            const PatchInfo &F = c->patches[r.fp[e]];
-            int lo = e == 0 ? F.ny : e == 1 ? 0 : e == 2 ? 2 * F.ny + F.nx : 2 * F.ny;
-            int len = e < 2 ? F.ny : F.nx;
-            if (F.eoff < 0 || r.e0[e] < lo || r.e0[e] + AMR_RATIO > lo + len) return bad("reflux entry");
-        }
-    }
-    for (const AvgRec &r : c->h_av) {
-        if (!local_ok(c, r.cp, r.cl, true)) return bad("average-down cell");
-        const PatchInfo &F = c->patches[r.fp < 0 ? 0 : r.fp];
-        for (int a = 0; a < AMR_RATIO; a++)
-            for (int b = 0; b < AMR_RATIO; b++)
-                if (!local_ok(c, r.fp, r.fl + a * F.pitch + b, true)) return bad("average-down block");
-    }
+    if (!all_of_parallel(c->h_gc.size(), [&](size_t k) {
+            const GhostCopy &r = c->h_gc[k];
+            return local_ok(c, r.dp, r.dl, false) && local_ok(c, r.sp, r.sl, true);
+        }))
+        return bad("ghost copy");
+    if (!all_of_parallel(c->h_gi.size(), [&](size_t k) {
+            const GhostInterp &r = c->h_gi[k];
+            if (!local_ok(c, r.dp, r.dl, false) || r.cp[0] < 0) return false;
+            for (int s = 0; s < 5; s++)
+                if (r.cp[s] >= 0 && !local_ok(c, r.cp[s], r.cl[s], true)) return false;
+            return true;
+        }))
+        return bad("ghost interpolation");
+    if (!all_of_parallel(c->h_fr.size(), [&](size_t k) {
+            const FluxRec &r = c->h_fr[k];
+            if (!local_ok(c, r.fp, r.gl, false) || !local_ok(c, r.cp, r.cl, true)) return false;
+            const PatchInfo &F = c->patches[r.fp];
+            return !(F.eoff < 0 || r.entry < 0 || r.entry >= 2 * (F.nx + F.ny));
+        }))
+        return bad("flux record");
+    if (!all_of_parallel(c->h_rf.size(), [&](size_t k) {
+            const RefluxRec &r = c->h_rf[k];
+            if (!local_ok(c, r.cp, r.cl, true)) return false;
+            for (int e = 0; e < 4; e++) {
+                if (r.fp[e] < 0) continue;
+                if (r.fp[e] >= (int)c->patches.size()) return false;
+                const PatchInfo &F = c->patches[r.fp[e]];
+                int lo = e == 0 ? F.ny : e == 1 ? 0 : e == 2 ? 2 * F.ny + F.nx : 2 * F.ny;
+                int len = e < 2 ? F.ny : F.nx;
+                if (F.eoff < 0 || r.e0[e] < lo || r.e0[e] + AMR_RATIO > lo + len) return false;
+            }
+            return true;
+        }))
+        return bad("reflux record");
+    if (!all_of_parallel(c->h_av.size(), [&](size_t k) {
+            const AvgRec &r = c->h_av[k];
+            if (!local_ok(c, r.cp, r.cl, true)) return false;
+            if (r.fp < 0 || r.fp >= (int)c->patches.size()) return false;
+            const PatchInfo &F = c->patches[r.fp];
+            for (int a = 0; a < AMR_RATIO; a++)
+                for (int b = 0; b < AMR_RATIO; b++)
+                    if (!local_ok(c, r.fp, r.fl + a * F.pitch + b, true)) return false;
+            return true;
+        }))
+        return bad("average-down record");
     return HSGN_OK;
 }
 

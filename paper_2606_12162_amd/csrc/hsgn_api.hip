@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -39,6 +40,9 @@ using namespace hsgn;
 // floating-point contraction (hsgn_step64.hip: none, hsgn_step32.hip: FMA)
 void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
 void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
+void launch_march32_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
+void launch_classify32(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream);
+void launch_static_class32(const MarchArgs<float> &A, unsigned nwork, int *out, hipStream_t stream);
 // instantiations for patches of patch sets (hsgn_step64amr.hip, hsgn_step32amr.hip)
 void launch_march64_amr(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
 void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
@@ -422,6 +426,12 @@ struct hsgn_ctx {
     uint8_t *m0 = nullptr, *m1 = nullptr;
     PatchInfo *d_patches = nullptr;
     WorkItem *d_work = nullptr;
+    int *d_list = nullptr;      // item lists of the split mixed step (2 per item)
+    unsigned *d_lcnt = nullptr; // their lengths
+    int *d_cls = nullptr;       // the items' classes for the attempt
+    int *d_clsb = nullptr;      // their bottom part
+    bool clsb_dirty = true;     // d_clsb to recompute (bathymetry or work table changed)
+    bool split = false;         // mixed single grids: deep items without the FP64 edges
     ScenState *d_scen = nullptr;
     ScenStatic *d_sstat = nullptr;
     GaugeDev *d_gauges = nullptr;
@@ -446,6 +456,8 @@ struct hsgn_ctx {
     long long etotal = 0;
     bool amr_dirty = true;
     hipStream_t cap_stream = nullptr;
+    hipStream_t aux_stream = nullptr;           // items of the split step that need FP64 edges
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool graph_valid = false, graph_failed = false;
     std::string last_error;
@@ -490,10 +502,16 @@ static void free_device(hsgn_ctx *c)
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
+    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    c->aux_stream = nullptr;
+    c->ev_fork = c->ev_join = nullptr;
     void *ptrs[] = {c->q0, c->q1, c->bath, c->clip, c->rec, c->m0, c->m1, c->d_patches,
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
                     c->d_mass, c->f0, c->f1, c->fbath, c->stage, c->d_cnt, c->d_gc, c->d_gi,
-                    c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip};
+                    c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip, c->d_list,
+                    c->d_lcnt, c->d_clsb, c->d_cls};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c->q0 = c->q1 = c->bath = c->clip = c->rec = c->d_mass = c->stage = nullptr;
@@ -503,6 +521,8 @@ static void free_device(hsgn_ctx *c)
     c->d_gauges = nullptr; c->d_slots = nullptr; c->d_err = nullptr; c->d_cnt = nullptr;
     c->d_gc = nullptr; c->d_gi = nullptr; c->d_fr = nullptr; c->d_rf = nullptr; c->d_av = nullptr;
     c->d_E = c->d_R = c->d_rclip = nullptr;
+    c->d_list = c->d_clsb = c->d_cls = nullptr;
+    c->d_lcnt = nullptr;
 }
 
 template <class S>
@@ -518,6 +538,9 @@ static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath, int w0,
     A.scen = c->d_scen;
     A.clip_slots = c->clip + w0;
     A.eflux = c->d_E;
+    A.list = nullptr;
+    A.lcnt = nullptr;
+    A.clsb = nullptr;
     A.nwork = w1 - w0;
     return A;
 }
@@ -915,6 +938,10 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     if (!c) return HSGN_ENOMEM;
     c->prm = *p;
     c->mixed = p->precision == 1;
+    // HSGN_NO_KERNEL_SPLIT=1 keeps every mixed item on the full kernel (a
+    // diagnostic: results are the same bit for bit)
+    const char *nosplit = getenv("HSGN_NO_KERNEL_SPLIT");
+    c->split = c->mixed && !(nosplit && nosplit[0] == '1');
     c->stream = (hipStream_t)hip_stream;
     StepParams &P = c->P;
     P.g = p->g;
@@ -1222,6 +1249,16 @@ int hsgn_finalize(hsgn_ctx *c)
     HIPCHK(c, hipMalloc(&c->clip, sizeof(double) * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_patches, sizeof(PatchInfo) * c->patches.size()));
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(WorkItem) * c->work.size()));
+    HIPCHK(c, hipMalloc(&c->d_list, sizeof(int) * 2 * std::max<size_t>(c->work.size(), 1)));
+    HIPCHK(c, hipMalloc(&c->d_lcnt, sizeof(unsigned) * 2));
+    HIPCHK(c, hipMalloc(&c->d_cls, sizeof(int) * std::max<size_t>(c->work.size(), 1)));
+    HIPCHK(c, hipMalloc(&c->d_clsb, sizeof(int) * std::max<size_t>(c->work.size(), 1)));
+    c->clsb_dirty = true;
+    if (c->split) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
     HIPCHK(c, hipMalloc(&c->d_scen, sizeof(ScenState) * c->nslot));
     HIPCHK(c, hipMalloc(&c->d_sstat, sizeof(ScenStatic) * c->nslot));
     HIPCHK(c, hipMalloc(&c->d_slots, sizeof(unsigned long long) * c->nslot));
@@ -1398,6 +1435,7 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
                                                            c->prm.h_star, c->prm.nbr_n);
     }
     if (amr) c->amr_dirty = true;
+    c->clsb_dirty = true;
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HSGN_OK;
@@ -1683,14 +1721,45 @@ static void launch_gauges(hsgn_ctx *c, hipStream_t s)
                                                       c->rec);
 }
 
+// mixed single-grid items with the class split (A.list set): classified,
+// then the few items that need the FP64 edge solve (each runs long, in one
+// round of waves) on a second stream beside the kernel without it, joined
+// back into s.  fork false keeps both on s (graph capture).
+static void launch_mixed_grids(hsgn_ctx *c, const MarchArgs<float> &A, unsigned n, int *cls,
+                               hipStream_t s, bool fork)
+{
+    if (!A.list) {
+        launch_march32(A, n, s);
+        return;
+    }
+    launch_classify32(A, n, cls, s);
+    if (fork) {
+        (void)hipEventRecord(c->ev_fork, s);
+        (void)hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0);
+        launch_march32(A, n, c->aux_stream);
+        launch_march32_deep(A, n, s);
+        (void)hipEventRecord(c->ev_join, c->aux_stream);
+        (void)hipStreamWaitEvent(s, c->ev_join, 0);
+    } else {
+        launch_march32(A, n, s);
+        launch_march32_deep(A, n, s);
+    }
+}
+
 // step kernels over work items [w0, w1): single grids with the plain
 // kernel, patch-set patches [wa, w1) with the patch-set kernel
-static void launch_march_range(hsgn_ctx *c, int w0, int wa, int w1, hipStream_t s)
+static void launch_march_range(hsgn_ctx *c, int w0, int wa, int w1, hipStream_t s, bool fork)
 {
     if (wa > w0) {
-        if (c->mixed)
-            launch_march32(march_args<float>(c, c->f0, c->f1, c->fbath, w0, wa), (unsigned)(wa - w0), s);
-        else
+        if (c->mixed) {
+            MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, w0, wa);
+            if (c->split) {
+                A.list = c->d_list + 2 * w0;
+                A.lcnt = c->d_lcnt;
+                A.clsb = c->d_clsb + w0;
+            }
+            launch_mixed_grids(c, A, (unsigned)(wa - w0), c->d_cls + w0, s, fork);
+        } else
             launch_march64(march_args<double>(c, c->q0, c->q1, c->bath, w0, wa), (unsigned)(wa - w0), s);
     }
     if (w1 > wa) {
@@ -1726,7 +1795,7 @@ static void launch_level(hsgn_ctx *c, int l, double theta, hipStream_t s, bool t
         launch_halo_interp64(B, c->d_gi + R.gi0, R.gi1 - R.gi0, theta, eta0, dtol, s);
     }
     if (timed) (void)timed_begin(c, s);
-    launch_march_range(c, R.w0, R.wa, R.w1, s);
+    launch_march_range(c, R.w0, R.wa, R.w1, s, false);
     if (timed) (void)timed_end(c, s);
     launch_control(c, R.s0, R.s1, s);
     if (l + 1 >= c->nlev) return;
@@ -1752,12 +1821,27 @@ static void launch_level(hsgn_ctx *c, int l, double theta, hipStream_t s, bool t
     }
 }
 
+// the bottom part of the split step's classes for the single-grid items of
+// every level, after a bathymetry or work-table change
+static void refresh_static_classes(hsgn_ctx *c)
+{
+    if (!c->split || !c->clsb_dirty) return;
+    for (int l = 0; l < c->nlev; l++) {
+        const LevelRange &R = c->L[l];
+        if (R.wa > R.w0)
+            launch_static_class32(march_args<float>(c, c->f0, c->f1, c->fbath, R.w0, R.wa),
+                                  (unsigned)(R.wa - R.w0), c->d_clsb + R.w0, c->stream);
+    }
+    c->clsb_dirty = false;
+}
+
 // one step attempt of every scenario
 static int launch_attempt(hsgn_ctx *c)
 {
+    refresh_static_classes(c);
     if (!c->any_amr) {
         if ((c->timing && timed_begin(c, c->stream))) return HSGN_EDEVICE;
-        launch_march_range(c, 0, (int)c->work.size(), (int)c->work.size(), c->stream);
+        launch_march_range(c, 0, (int)c->work.size(), (int)c->work.size(), c->stream, true);
         if ((c->timing && timed_end(c, c->stream))) return HSGN_EDEVICE;
         launch_control(c, 0, c->nslot, c->stream);
         launch_gauges(c, c->stream);
@@ -1919,15 +2003,25 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
     build_work(c, th8, wk, ss, L);
     WorkItem *dwork = nullptr;
     double *dclip = nullptr;
+    int *dlist = nullptr, *dclsb = nullptr, *dcls = nullptr;
+    unsigned *dlcnt = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&]() {
         if (dwork) (void)hipFree(dwork);
         if (dclip) (void)hipFree(dclip);
+        if (dlist) (void)hipFree(dlist);
+        if (dlcnt) (void)hipFree(dlcnt);
+        if (dcls) (void)hipFree(dcls);
+        if (dclsb) (void)hipFree(dclsb);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
     if (hipMalloc(&dwork, sizeof(WorkItem) * wk.size()) != hipSuccess ||
         hipMalloc(&dclip, sizeof(double) * wk.size()) != hipSuccess ||
+        hipMalloc(&dlist, sizeof(int) * 2 * wk.size()) != hipSuccess ||
+        hipMalloc(&dlcnt, sizeof(unsigned) * 2) != hipSuccess ||
+        hipMalloc(&dcls, sizeof(int) * wk.size()) != hipSuccess ||
+        hipMalloc(&dclsb, sizeof(int) * wk.size()) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         cleanup();
         return fail(c, HSGN_ENOMEM, "autotune scratch");
@@ -1972,7 +2066,12 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                     if (c->mixed) {
                         MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, na);
                         A.work = dwork; A.clip_slots = dclip;
-                        launch_march32(A, (unsigned)na, c->stream);
+                        if (c->split) {
+                            A.list = dlist;
+                            A.lcnt = dlcnt;
+                            A.clsb = dclsb;
+                        }
+                        launch_mixed_grids(c, A, (unsigned)na, dcls, c->stream, true);
                     } else {
                         MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, na);
                         A.work = dwork; A.clip_slots = dclip;
@@ -1991,6 +2090,11 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                     }
                 }
             };
+            if (na > 0 && c->split) {
+                MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, na);
+                A.work = dwork;
+                launch_static_class32(A, (unsigned)na, dclsb, c->stream);
+            }
             launch();                                   // warm-up
             (void)hipEventRecord(e0, c->stream);
             for (int t = 0; t < trials; t++) launch();
@@ -2015,12 +2119,22 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
     if (work.size() > c->work.size()) {
         WorkItem *nw = nullptr;
         double *nc = nullptr;
+        int *nlist = nullptr, *nclsb = nullptr, *ncls = nullptr;
         HIPCHK(c, hipMalloc(&nw, sizeof(WorkItem) * work.size()));
         HIPCHK(c, hipMalloc(&nc, sizeof(double) * work.size()));
+        HIPCHK(c, hipMalloc(&nlist, sizeof(int) * 2 * work.size()));
+        HIPCHK(c, hipMalloc(&ncls, sizeof(int) * work.size()));
+        HIPCHK(c, hipMalloc(&nclsb, sizeof(int) * work.size()));
         (void)hipFree(c->d_work);
         (void)hipFree(c->clip);
+        (void)hipFree(c->d_list);
+        (void)hipFree(c->d_cls);
+        (void)hipFree(c->d_clsb);
         c->d_work = nw;
         c->clip = nc;
+        c->d_list = nlist;
+        c->d_cls = ncls;
+        c->d_clsb = nclsb;
     }
     HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * work.size(), c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_work, work.data(), sizeof(WorkItem) * work.size(),
@@ -2032,6 +2146,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
     c->sstat = sstat;
     c->L = L2;
     c->th_level = best;
+    c->clsb_dirty = true;
     drop_graph(c);
     if (rows)
         for (int l = 0; l < c->nlev; l++) rows[l] = best[l];

@@ -79,6 +79,14 @@ struct MarchArgs {
     ScenState *scen;
     double *clip_slots;      // one per work item
     double *eflux;           // boundary-edge fluxes of patches with eoff >= 0
+    // split step (mixed-precision single grids), else null: the items none
+    // of whose edges takes the FP64 solve (no cell they load has c^2 = 0)
+    // listed in list[0 .. lcnt[0]), the others in list[nwork .. nwork +
+    // lcnt[1]); clsb per item 1 when the bottom alone gives a cell it loads
+    // c^2 = 0 (static between bathymetry changes)
+    int *list;
+    unsigned *lcnt;
+    const int *clsb;
     int nwork;
 };
 
@@ -168,6 +176,15 @@ HSGN_HD T depth_of(const StepParams &P, T q0, T b)
     return MIXED ? q0 + (T)P.eta0 - b : q0;
 }
 
+// relaxation parameter c^2 of a cell from its mask byte and bottom: zero in
+// the SWE region (phi_T = 0) and in a breaking cell
+template <class T>
+HSGN_HD T relax_c2(const StepParams &P, int mk, T b)
+{
+    int swe = !(mk & MASK_PHI) || (mk & MASK_BRK);
+    return swe ? (T)0 : (T)P.a2g * still_depth(P, b) + (T)P.c2f;
+}
+
 // apply the first source half step (Strang) or clear a dry/SWE cell's
 // auxiliaries, then derive the primitive variables
 template <class T, bool MIXED>
@@ -181,8 +198,7 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
     phi = r.mk & 1;
     brk = (r.mk >> 1) & 1;
     int swe = !phi || brk;
-    T H = still_depth(P, c.b);
-    c.c2 = swe ? (T)0 : (T)P.a2g * H + (T)P.c2f;
+    c.c2 = relax_c2(P, r.mk, c.b);
     if (P.splitting) {
         source_or_clear(P, c.q, c.c2, swe, tau_pre);
     } else if (!(c.q[IH] > (T)P.dry_tol) || swe) {
@@ -195,6 +211,8 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
 // normal solve of an edge.  In mixed precision an edge with an SWE or dry
 // side (c^2 = 0 on a side) is solved again in FP64 from the promoted sides
 // and its results replace the FP32 ones.
+// FB false: the FP32 solve alone, for work items whose cells all have
+// c^2 > 0 (the FP64 branch would never be taken).
 template <int DIR, bool MIXED, class L, class T>
 HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Side<T> &sr,
                         Waves<T> &W, Eig<T> &E)
@@ -234,7 +252,7 @@ HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Sid
 //   left  A-dQ + F~ + F~tr,   right -(A+dQ - F~) + F~tr,
 //   below B-dQ + G~ + G~tr,   above -(B+dQ - G~) + G~tr
 // at entries j, ny + j, 2 ny + i, 2 ny + nx + i of the patch.
-template <class L, class S, class T, bool MIXED, bool AMR>
+template <class L, class S, class T, bool MIXED, bool AMR, bool FB = true>
 HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 {
     const WorkItem wk = A.work[wid];
@@ -332,7 +350,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             shfl_side_up(ln, sr, sl);
             Waves<T> xw;
             Eig<T> xe;
-            bool ok = edge_solve<0, MIXED>(ln, P, sl, sr, xw, xe);
+            bool ok = edge_solve<0, MIXED && FB>(ln, P, sl, sr, xw, xe);
             if (!ok && lane >= 1) sc->err = -4;
             Waves<T> xwl;
             shfl_waves_up(ln, xw, xwl);
@@ -377,7 +395,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         if (k >= r0 - 1) {
             Waves<T> yw;
             Eig<T> ye;
-            bool ok = edge_solve<1, MIXED>(ln, P, yside_prev, yside, yw, ye);
+            bool ok = edge_solve<1, MIXED && FB>(ln, P, yside_prev, yside, yw, ye);
             if (!ok) sc->err = -4;
             if (k >= r0 && k <= r0 + th && interior)
                 ry = tmax(ry, tmax((T)fabs(yw.smin), tmax((T)fabs(yw.smax), (T)fabs(yw.uh))));

@@ -170,3 +170,39 @@ def test_full_ensemble_launch_two_scenarios_against_oracle():
     assert worst <= 1e-4
     for ctx in runs.values():
         ctx.close()
+
+
+def _mixed_run(ws, steps, tune):
+    ctx = H.Context(ws[0].params, precision=1)
+    for s, w in enumerate(ws):
+        ctx.add_grid(s, w.grid)
+    ctx.finalize()
+    for s, w in enumerate(ws):
+        ctx.set_bathymetry(s, w.b)
+        ctx.set_state(s, w.q)
+        ctx.set_gauges(s, w.gauges)
+        ctx.set_clock(s, 0.0, w.dt, 0)
+    if tune:
+        ctx.autotune(trials=1)
+    ctx.advance(-1.0, steps)
+    out = [(ctx.get_state(s), ctx.get_mask(s), ctx.read_gauges(s)[1]) for s in range(len(ws))]
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("tune", [False, True])
+def test_split_step_is_bitwise_the_full_kernel(monkeypatch, tune):
+    """the mixed step split into items far from the SWE region and the shore
+    (kernel without the FP64 edge solve) and the rest (full kernel) gives
+    the same bits as the full kernel on every item: an ocean whose deep
+    plain, shelf and dry coast all lie in one grid, while the wave reaches
+    the shelf and the SWE region and breaking latches move, plus a small
+    ensemble in the same launch"""
+    ws = [W.synthetic_ocean(n=512, dx=2000.0, steps=200)] + small_ensemble(count=3, seed0=91)
+    print("case", [w.name for w in ws], "autotune", tune, flush=True)
+    split = _mixed_run(ws, 200, tune)
+    monkeypatch.setenv("HSGN_NO_KERNEL_SPLIT", "1")
+    full = _mixed_run(ws, 200, tune)
+    for s, (a, b) in enumerate(zip(split, full)):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), ws[s].name

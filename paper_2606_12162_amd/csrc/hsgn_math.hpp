@@ -332,17 +332,24 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     const int IN = DIR == 0 ? IHU : IHV;   // normal momentum component
     const int IT = DIR == 0 ? IHV : IHU;   // tangential momentum component
     const T g = (T)P.g;
-    HSGN_UNROLL
-    for (int m = 0; m < 7; m++) { W.z0[m] = (T)0; W.z6[m] = (T)0; }
-    W.zm[0] = W.zm[1] = W.zm[2] = (T)0;
-    W.bs = W.bw = W.bt = W.bpb = (T)0;
-    W.smin = W.smax = W.uh = (T)0;
-    W.kind = KIND_REGULAR;
     E.wet = sL.wet && sR.wet;
-    E.uh = E.vh = E.wh = E.sh = E.pbh = E.ghh = E.c2p = (T)0;
-    E.ce2 = (T)1; E.inv_ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1; E.inv_ds = (T)0.5;
-    if (!sL.wet && !sR.wet) { W.kind = KIND_DRY; return true; }
-
+    if (!sL.wet && !sR.wet) {
+        // both sides dry: no waves
+        HSGN_UNROLL
+        for (int m = 0; m < 7; m++) { W.z0[m] = (T)0; W.z6[m] = (T)0; }
+        W.zm[0] = W.zm[1] = W.zm[2] = (T)0;
+        W.bs = W.bw = W.bt = W.bpb = (T)0;
+        W.smin = W.smax = W.uh = (T)0;
+        W.kind = KIND_DRY;
+        E.uh = E.vh = E.wh = E.sh = E.pbh = E.ghh = E.c2p = (T)0;
+        E.ce2 = (T)1; E.inv_ce2 = (T)1; E.smin = (T)-1; E.smax = (T)1; E.inv_ds = (T)0.5;
+        return true;
+    }
+    // Every other path assigns every output; a non-hyperbolic edge clears
+    // `ok` and runs on (its outputs are then meaningless: the step reports
+    // the edge), so that no output has to be set before a branch.
+    bool ok = true;
+    W.kind = KIND_REGULAR;
     Side<T> L = sL, R = sR;
     int dryL = 0, dryR = 0;
     if (sL.wet && !sR.wet) {
@@ -397,7 +404,7 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     }
 
     T ce2 = g * hh + ph + c2h;
-    if (!(ce2 > (T)0)) return false;
+    ok = ce2 > (T)0;
     T ceh = sqrt(ce2);
     T ice2 = recip(ce2);
     T sg = sqrt(g);
@@ -405,13 +412,13 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     if (dryL) {
         smin = R.un - (T)2 * front_root(g, R.h, sg, R.sq);
     } else {
-        if (!L.hyp) return false;
+        ok = ok && L.hyp;
         smin = tmin(uh - ceh, L.un - L.ce);
     }
     if (dryR) {
         smax = L.un + (T)2 * front_root(g, L.h, sg, L.sq);
     } else {
-        if (!R.hyp) return false;
+        ok = ok && R.hyp;
         smax = tmax(uh + ceh, R.un + R.ce);
     }
     T ids = recip(smax - smin);
@@ -476,7 +483,7 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     E.uh = uh; E.vh = vh; E.wh = wh; E.sh = sh; E.pbh = pbh;
     E.ghh = g * hh; E.c2p = c2h + ph; E.ce2 = ce2; E.inv_ce2 = ice2; E.smin = smin; E.smax = smax;
     E.inv_ds = ids;
-    return true;
+    return ok;
 }
 
 // precision conversion of solver results

@@ -141,54 +141,96 @@ __global__ __launch_bounds__(64) void classify_kernel(MarchArgs<S> A, int *cls)
     if (col > pi.nx + 1) col = pi.nx + 1;
     int fx = 0, fy = 0;
     const int mc = map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
+    // loads in batches of ROWS_IN_FLIGHT rows, all issued before any is used
+    constexpr int ROWS_IN_FLIGHT = 16;
+    const int k1 = wk.r0 + wk.th + 1;
     int hot = 0;
-#pragma unroll 8
-    for (int k = wk.r0 - 2; k <= wk.r0 + wk.th + 1; k++) {
-        const int mr = map_index(k, pi.ny, pi.bc[2], pi.bc[3], &fy);
-        const int m = mk[pi.coff + (long long)mr * pi.pitch + mc];
-        hot |= (m & (MASK_PHI | MASK_BRK)) != MASK_PHI;
+    for (int k0 = wk.r0 - 2; k0 <= k1; k0 += ROWS_IN_FLIGHT) {
+        int m[ROWS_IN_FLIGHT];
+#pragma unroll
+        for (int u = 0; u < ROWS_IN_FLIGHT; u++) {
+            const int k = k0 + u <= k1 ? k0 + u : k1;
+            const int mr = map_index(k, pi.ny, pi.bc[2], pi.bc[3], &fy);
+            m[u] = mk[pi.coff + (long long)mr * pi.pitch + mc];
+        }
+#pragma unroll
+        for (int u = 0; u < ROWS_IN_FLIGHT; u++) hot |= (m[u] & (MASK_PHI | MASK_BRK)) != MASK_PHI;
     }
     const int any_hot = __any(hot);
     if (lane == 0) cls[wid] = any_hot ? 1 : 0;
 }
 
 // the two item lists from the classes, each in ascending item order, and
-// their lengths: one workgroup of LIST_THREADS threads, thread t scanning a
-// contiguous run of the classes
+// their lengths: one workgroup of NT threads.  The classes are taken in
+// passes of 32 x NT items; in a pass thread t holds items p + c NT + t
+// (c < 32) as the bits of one word, and an item's place in the list of
+// class 1 is the number of class-1 items before it (wave ballots, then a
+// scan of the per-wave counts in item order); its place in the other list
+// is its index less that number.
 constexpr int LIST_THREADS = 1024;
 
 template <int NT>
 __global__ __launch_bounds__(NT) void list_kernel(const int *cls, int nwork, int *list,
-                                                            unsigned *lcnt)
+                                                  unsigned *lcnt)
 {
-    __shared__ int part[2][NT];
-    const int t = (int)threadIdx.x;
-    const int per = (nwork + NT - 1) / NT;
-    const int a = t * per < nwork ? t * per : nwork;
-    const int e = a + per < nwork ? a + per : nwork;
-    int n1 = 0;
-    for (int w = a; w < e; w++) n1 += cls[w];
-    part[0][t] = (e - a) - n1;
-    part[1][t] = n1;
-    __syncthreads();
-    // inclusive scans of both counts (Hillis-Steele over the workgroup)
-    for (int o = 1; o < NT; o <<= 1) {
-        int x0 = t >= o ? part[0][t - o] : 0, x1 = t >= o ? part[1][t - o] : 0;
+    constexpr int NW = NT / 64, CH = 32;
+    __shared__ int cnt[CH * NW];        // class-1 counts per (chunk, wave), then their scan
+    __shared__ int total;               // class-1 items before the pass
+    const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) total = 0;
+    for (int p = 0; p < nwork; p += CH * NT) {
+        unsigned bits = 0;
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            const int w = p + c * NT + t;
+            if (w < nwork && cls[w]) bits |= 1u << c;
+        }
+        unsigned long long below[CH];   // per chunk: ballot of the lanes below this one
+        const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            const unsigned long long bal = __ballot((bits >> c) & 1u);
+            below[c] = bal & lt;
+            if (lane == 0) cnt[c * NW + wave] = __popcll(bal);
+        }
         __syncthreads();
-        part[0][t] += x0;
-        part[1][t] += x1;
+        if (wave == 0) {
+            // exclusive scan of the CH * NW counts in item order, by lane
+            // runs of (CH * NW) / 64 entries, then across lanes
+            constexpr int RUN = CH * NW / 64;
+            int v[RUN], sum = 0;
+#pragma unroll
+            for (int r = 0; r < RUN; r++) { v[r] = cnt[lane * RUN + r]; sum += v[r]; }
+            int incl = sum;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int x = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += x;
+            }
+            int run = total + incl - sum;
+#pragma unroll
+            for (int r = 0; r < RUN; r++) { cnt[lane * RUN + r] = run; run += v[r]; }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            const int w = p + c * NT + t;
+            if (w < nwork) {
+                const int before = cnt[c * NW + wave] + __popcll(below[c]);
+                if ((bits >> c) & 1u) list[nwork + before] = w;
+                else list[w - before] = w;
+            }
+        }
+        __syncthreads();
+        if (t == NT - 1) {
+            const int last = cnt[(CH - 1) * NW + NW - 1] + __popcll(below[CH - 1]) + (int)((bits >> (CH - 1)) & 1u);
+            total = last;
+        }
         __syncthreads();
     }
-    int p0 = part[0][t] - ((e - a) - n1), p1 = part[1][t] - n1;
-    for (int w = a; w < e; w++) {
-        if (cls[w]) list[nwork + p1++] = w;
-        else list[p0++] = w;
-    }
-    if (t == NT - 1) {
-        lcnt[0] = (unsigned)part[0][t];
-        lcnt[1] = (unsigned)part[1][t];
+    if (t == 0) {
+        lcnt[0] = (unsigned)(nwork - total);
+        lcnt[1] = (unsigned)total;
     }
 }
-
 
 }  // namespace hsgn

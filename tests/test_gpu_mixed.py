@@ -206,3 +206,27 @@ def test_split_step_is_bitwise_the_full_kernel(monkeypatch, tune):
     for s, (a, b) in enumerate(zip(split, full)):
         for x, y in zip(a, b):
             assert np.array_equal(x, y), ws[s].name
+
+
+def test_split_step_with_more_items_than_one_list_pass(monkeypatch):
+    """the 48-scenario ensemble at full size with 8-row tiles (104,636 work
+    items, more than the 32,768 that the list compaction takes per pass):
+    after 2 steps the split step gives the same bits as the full kernel"""
+    ws = W.ensemble()
+    runs = []
+    for nosplit in ("0", "1"):
+        monkeypatch.setenv("HSGN_NO_KERNEL_SPLIT", nosplit)
+        print("case ensemble_48 tile_rows 8 no_split", nosplit, flush=True)
+        ctx = H.Context(ws[0].params, tile_rows=8, precision=1)
+        for s, w in enumerate(ws):
+            ctx.add_grid(s, w.grid)
+        ctx.finalize()
+        for s, w in enumerate(ws):
+            ctx.set_bathymetry(s, w.b)
+            ctx.set_state(s, w.q)
+            ctx.set_clock(s, 0.0, w.dt, 0)
+        ctx.advance(-1.0, 2)
+        runs.append([(ctx.get_state(s), ctx.get_mask(s)) for s in (0, 17, 47)])
+        ctx.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -39,13 +39,16 @@ using namespace hsgn;
 // the step kernel is compiled in two translation units with different
 // floating-point contraction (hsgn_step64.hip: none, hsgn_step32.hip: FMA)
 void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
-void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
+void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream, bool beside);
 void launch_march32_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
 void launch_classify32(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream);
 void launch_static_class32(const MarchArgs<float> &A, unsigned nwork, int *out, hipStream_t stream);
 // instantiations for patches of patch sets (hsgn_step64amr.hip, hsgn_step32amr.hip)
 void launch_march64_amr(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
 void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
+void launch_march32_amr_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
+void launch_classify32_amr(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream);
+void launch_static_class32_amr(const MarchArgs<float> &A, unsigned nwork, int *out, hipStream_t stream);
 
 struct ScenStatic {
     double dx, dy, cfl, cfl_max;
@@ -1721,29 +1724,48 @@ static void launch_gauges(hsgn_ctx *c, hipStream_t s)
                                                       c->rec);
 }
 
-// mixed single-grid items with the class split (A.list set): classified,
-// then the few items that need the FP64 edge solve (each runs long, in one
-// round of waves) on a second stream beside the kernel without it, joined
-// back into s.  fork false keeps both on s (graph capture).
-static void launch_mixed_grids(hsgn_ctx *c, const MarchArgs<float> &A, unsigned n, int *cls,
-                               hipStream_t s, bool fork)
+// mixed-precision items of one kind (single grids, or patches of patch sets
+// with amr) with the class split (A.list set): classified, then the kernel
+// without the FP64 edge solve over the items that do not need it and the
+// full kernel over the rest.  Single grids with fork: the few items that
+// need it (each runs long, in one round of waves) on a second stream beside
+// the other kernel, joined back into s; otherwise one after the other on s
+// (graph capture; patch sets always).
+static void launch_mixed_split(hsgn_ctx *c, const MarchArgs<float> &A, unsigned n, int *cls,
+                               bool amr, hipStream_t s, bool fork)
 {
     if (!A.list) {
-        launch_march32(A, n, s);
+        if (amr) launch_march32_amr(A, n, s);
+        else launch_march32(A, n, s, false);
+        return;
+    }
+    if (amr) {
+        launch_classify32_amr(A, n, cls, s);
+        launch_march32_amr(A, n, s);
+        launch_march32_amr_deep(A, n, s);
         return;
     }
     launch_classify32(A, n, cls, s);
     if (fork) {
         (void)hipEventRecord(c->ev_fork, s);
         (void)hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0);
-        launch_march32(A, n, c->aux_stream);
+        launch_march32(A, n, c->aux_stream, true);
         launch_march32_deep(A, n, s);
         (void)hipEventRecord(c->ev_join, c->aux_stream);
         (void)hipStreamWaitEvent(s, c->ev_join, 0);
     } else {
-        launch_march32(A, n, s);
+        launch_march32(A, n, s, false);
         launch_march32_deep(A, n, s);
     }
+}
+
+// the split's buffers for items [w0, w1) of the context's work table
+static void split_args(hsgn_ctx *c, MarchArgs<float> &A, int w0)
+{
+    if (!c->split) return;
+    A.list = c->d_list + 2 * w0;
+    A.lcnt = c->d_lcnt;
+    A.clsb = c->d_clsb + w0;
 }
 
 // step kernels over work items [w0, w1): single grids with the plain
@@ -1753,20 +1775,17 @@ static void launch_march_range(hsgn_ctx *c, int w0, int wa, int w1, hipStream_t 
     if (wa > w0) {
         if (c->mixed) {
             MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, w0, wa);
-            if (c->split) {
-                A.list = c->d_list + 2 * w0;
-                A.lcnt = c->d_lcnt;
-                A.clsb = c->d_clsb + w0;
-            }
-            launch_mixed_grids(c, A, (unsigned)(wa - w0), c->d_cls + w0, s, fork);
+            split_args(c, A, w0);
+            launch_mixed_split(c, A, (unsigned)(wa - w0), c->d_cls + w0, false, s, fork);
         } else
             launch_march64(march_args<double>(c, c->q0, c->q1, c->bath, w0, wa), (unsigned)(wa - w0), s);
     }
     if (w1 > wa) {
-        if (c->mixed)
-            launch_march32_amr(march_args<float>(c, c->f0, c->f1, c->fbath, wa, w1),
-                               (unsigned)(w1 - wa), s);
-        else
+        if (c->mixed) {
+            MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, wa, w1);
+            split_args(c, A, wa);
+            launch_mixed_split(c, A, (unsigned)(w1 - wa), c->d_cls + wa, true, s, false);
+        } else
             launch_march64_amr(march_args<double>(c, c->q0, c->q1, c->bath, wa, w1),
                                (unsigned)(w1 - wa), s);
     }
@@ -1831,6 +1850,9 @@ static void refresh_static_classes(hsgn_ctx *c)
         if (R.wa > R.w0)
             launch_static_class32(march_args<float>(c, c->f0, c->f1, c->fbath, R.w0, R.wa),
                                   (unsigned)(R.wa - R.w0), c->d_clsb + R.w0, c->stream);
+        if (R.w1 > R.wa)
+            launch_static_class32_amr(march_args<float>(c, c->f0, c->f1, c->fbath, R.wa, R.w1),
+                                      (unsigned)(R.w1 - R.wa), c->d_clsb + R.wa, c->stream);
     }
     c->clsb_dirty = false;
 }
@@ -2071,7 +2093,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                             A.lcnt = dlcnt;
                             A.clsb = dclsb;
                         }
-                        launch_mixed_grids(c, A, (unsigned)na, dcls, c->stream, true);
+                        launch_mixed_split(c, A, (unsigned)na, dcls, false, c->stream, true);
                     } else {
                         MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, na);
                         A.work = dwork; A.clip_slots = dclip;
@@ -2082,7 +2104,12 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                     if (c->mixed) {
                         MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, n - na);
                         A.work = dwork + na; A.clip_slots = dclip + na;
-                        launch_march32_amr(A, (unsigned)(n - na), c->stream);
+                        if (c->split) {
+                            A.list = dlist + 2 * na;
+                            A.lcnt = dlcnt;
+                            A.clsb = dclsb + na;
+                        }
+                        launch_mixed_split(c, A, (unsigned)(n - na), dcls + na, true, c->stream, false);
                     } else {
                         MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, n - na);
                         A.work = dwork + na; A.clip_slots = dclip + na;
@@ -2094,6 +2121,11 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                 MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, na);
                 A.work = dwork;
                 launch_static_class32(A, (unsigned)na, dclsb, c->stream);
+            }
+            if (n > na && c->split) {
+                MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, n - na);
+                A.work = dwork + na;
+                launch_static_class32_amr(A, (unsigned)(n - na), dclsb + na, c->stream);
             }
             launch();                                   // warm-up
             (void)hipEventRecord(e0, c->stream);

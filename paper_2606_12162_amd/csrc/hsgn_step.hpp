@@ -65,15 +65,16 @@ struct GpuLanes {
 // With item lists (A.list) the kernel takes the items of its class's list:
 // FB false the items none of whose edges takes the FP64 solve, compiled
 // without it (its registers then fit without spilling), one block per
-// entry; FB true the others, on fewer blocks than the work table has items,
-// each block taking entries b, b + grid, ... in turn.
+// entry; FB true the others, block b taking entries b, b + grid, ... in turn
+// (launched on fewer blocks than the work table has items when it runs
+// beside the other kernel).
 template <class S, class T, bool MIXED, bool AMR, bool FB = true>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
 void march_kernel(MarchArgs<S> A)
 {
     __shared__ T ring[3 * EIG_FIELDS * 64 + (MIXED ? 3 * 7 * 64 : 0)];
     GpuLanes<T> ln{ring};
-    if (MIXED && !AMR && FB) {
+    if (MIXED && FB) {
         const unsigned n = A.list ? A.lcnt[1] : (unsigned)A.nwork;
         for (unsigned b = blockIdx.x; b < n; b += gridDim.x) {     // uniform over the wavefront
             const int wid = A.list ? A.list[A.nwork + (int)b] : (int)b;
@@ -90,15 +91,32 @@ void march_kernel(MarchArgs<S> A)
     }
 }
 
-// The cells a single-grid work item's wavefront loads: columns i0-2..i0+61
-// clamped as the step clamps them, rows r0-2..r0+th+1, through the boundary
-// map.  A cell has c^2 = 0 when its mask puts it in the SWE region or
+// The cells a work item's wavefront loads: columns i0-2..i0+61 clamped as
+// the step clamps them, rows r0-2..r0+th+1, through the boundary map (single
+// grids) or from the stored ghost frame (FRAMED, patches of patch sets).  A cell has c^2 = 0 when its mask puts it in the SWE region or
 // breaking, or when its bottom alone gives c^2 = 0 (relax_c2 with phi_T = 1
 // is then zero); the two parts are tested apart.
 
 // the bottom part, per item, recomputed when the bathymetry or the work
 // table changes
-template <class S, class T>
+template <bool FRAMED>
+HSGN_HD int footprint_col(const PatchInfo &pi, int i0, int lane)
+{
+    int col = i0 - 2 + lane;
+    if (col > pi.nx + 1) col = pi.nx + 1;
+    int fx = 0;
+    return FRAMED ? col : map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
+}
+
+template <bool FRAMED>
+HSGN_HD long long footprint_row(const PatchInfo &pi, int k)
+{
+    int fy = 0;
+    const int mr = FRAMED ? k : map_index(k, pi.ny, pi.bc[2], pi.bc[3], &fy);
+    return pi.coff + (long long)mr * pi.pitch;
+}
+
+template <class S, class T, bool FRAMED>
 __global__ __launch_bounds__(64) void static_class_kernel(MarchArgs<S> A, int *out)
 {
     int wid = (int)blockIdx.x;
@@ -106,14 +124,10 @@ __global__ __launch_bounds__(64) void static_class_kernel(MarchArgs<S> A, int *o
     const WorkItem wk = A.work[wid];
     const PatchInfo pi = A.patches[wk.patch];
     const int lane = (int)(threadIdx.x & 63);
-    int col = wk.i0 - 2 + lane;
-    if (col > pi.nx + 1) col = pi.nx + 1;
-    int fx = 0, fy = 0;
-    const int mc = map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
+    const int mc = footprint_col<FRAMED>(pi, wk.i0, lane);
     int hot = 0;
     for (int k = wk.r0 - 2; k <= wk.r0 + wk.th + 1; k++) {
-        const int mr = map_index(k, pi.ny, pi.bc[2], pi.bc[3], &fy);
-        const long long idx = pi.coff + (long long)mr * pi.pitch + mc;
+        const long long idx = footprint_row<FRAMED>(pi, k) + mc;
         hot |= !(relax_c2(A.P, MASK_PHI, (T)A.bath[idx]) > (T)0);
     }
     const int any_hot = __any(hot);
@@ -124,7 +138,7 @@ __global__ __launch_bounds__(64) void static_class_kernel(MarchArgs<S> A, int *o
 // and the bottom part, into cls[wid] (0: no cell the item loads has c^2 =
 // 0, so that none of its edges needs the FP64 solve; 1: the others).  One
 // wavefront per item.
-template <class S, class T>
+template <class S, class T, bool FRAMED>
 __global__ __launch_bounds__(64) void classify_kernel(MarchArgs<S> A, int *cls)
 {
     int wid = (int)blockIdx.x;
@@ -137,10 +151,7 @@ __global__ __launch_bounds__(64) void classify_kernel(MarchArgs<S> A, int *cls)
     const WorkItem wk = A.work[wid];
     const PatchInfo pi = A.patches[wk.patch];
     const uint8_t *mk = A.scen[pi.scen].cur ? A.m1 : A.m0;
-    int col = wk.i0 - 2 + lane;
-    if (col > pi.nx + 1) col = pi.nx + 1;
-    int fx = 0, fy = 0;
-    const int mc = map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
+    const int mc = footprint_col<FRAMED>(pi, wk.i0, lane);
     // loads in batches of ROWS_IN_FLIGHT rows, all issued before any is used
     constexpr int ROWS_IN_FLIGHT = 16;
     const int k1 = wk.r0 + wk.th + 1;
@@ -150,8 +161,7 @@ __global__ __launch_bounds__(64) void classify_kernel(MarchArgs<S> A, int *cls)
 #pragma unroll
         for (int u = 0; u < ROWS_IN_FLIGHT; u++) {
             const int k = k0 + u <= k1 ? k0 + u : k1;
-            const int mr = map_index(k, pi.ny, pi.bc[2], pi.bc[3], &fy);
-            m[u] = mk[pi.coff + (long long)mr * pi.pitch + mc];
+            m[u] = mk[footprint_row<FRAMED>(pi, k) + mc];
         }
 #pragma unroll
         for (int u = 0; u < ROWS_IN_FLIGHT; u++) hot |= (m[u] & (MASK_PHI | MASK_BRK)) != MASK_PHI;

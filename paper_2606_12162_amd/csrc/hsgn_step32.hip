@@ -6,15 +6,16 @@
 using namespace hsgn;
 
 // blocks of the full kernel over the list of items that need the FP64 edge
-// solve: one wavefront per SIMD of the chip at most, each taking entries in
-// turn, so that the list's items start at once beside the other kernel
+// solve when it runs beside the other kernel (beside): one wavefront per
+// SIMD of the chip at most, each taking entries in turn, so that the list's
+// items start at once
 constexpr unsigned FB_BLOCKS = 1024;
 
 // the full kernel: every item, or with item lists the items that need the
 // FP64 edge solve
-void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
+void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream, bool beside)
 {
-    const unsigned grid = A.list && nwork > FB_BLOCKS ? FB_BLOCKS : nwork;
+    const unsigned grid = A.list && beside && nwork > FB_BLOCKS ? FB_BLOCKS : nwork;
     march_kernel<float, float, true, false, true><<<grid, 64, 0, stream>>>(A);
 }
 
@@ -27,12 +28,12 @@ void launch_march32_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t 
 // the item lists from the attempt's input mask (classes into cls)
 void launch_classify32(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream)
 {
-    classify_kernel<float, float><<<nwork, 64, 0, stream>>>(A, cls);
+    classify_kernel<float, float, false><<<nwork, 64, 0, stream>>>(A, cls);
     list_kernel<LIST_THREADS><<<1, LIST_THREADS, 0, stream>>>(cls, (int)nwork, A.list, A.lcnt);
 }
 
 // the bottom part of the classes (after a bathymetry or work-table change)
 void launch_static_class32(const MarchArgs<float> &A, unsigned nwork, int *out, hipStream_t stream)
 {
-    static_class_kernel<float, float><<<nwork, 64, 0, stream>>>(A, out);
+    static_class_kernel<float, float, false><<<nwork, 64, 0, stream>>>(A, out);
 }

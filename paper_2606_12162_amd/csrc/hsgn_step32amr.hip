@@ -4,7 +4,29 @@
 
 using namespace hsgn;
 
+// the full kernel: every item, or with item lists the items that need the
+// FP64 edge solve (one block per entry: patch-set steps run the two kernels
+// one after the other)
 void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
 {
-    march_kernel<float, float, true, true><<<nwork, 64, 0, stream>>>(A);
+    march_kernel<float, float, true, true, true><<<nwork, 64, 0, stream>>>(A);
+}
+
+// the kernel without the FP64 edge solve, over the other list
+void launch_march32_amr_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
+{
+    march_kernel<float, float, true, true, false><<<nwork, 64, 0, stream>>>(A);
+}
+
+// the item lists from the attempt's input mask, ghost frames included
+void launch_classify32_amr(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream)
+{
+    classify_kernel<float, float, true><<<nwork, 64, 0, stream>>>(A, cls);
+    list_kernel<LIST_THREADS><<<1, LIST_THREADS, 0, stream>>>(cls, (int)nwork, A.list, A.lcnt);
+}
+
+// the bottom part of the classes, ghost frames included
+void launch_static_class32_amr(const MarchArgs<float> &A, unsigned nwork, int *out, hipStream_t stream)
+{
+    static_class_kernel<float, float, true><<<nwork, 64, 0, stream>>>(A, out);
 }

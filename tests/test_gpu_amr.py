@@ -247,3 +247,30 @@ def test_full_size_amr_ocean_properties():
     err = np.abs(gauges[1] - gauges[0]).max() / w.amplitude
     print("mixed vs FP64 gauge error / amplitude", err)
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("mode", ["graph", "direct", "autotune"])
+def test_split_patch_set_step_is_bitwise_the_full_kernel(monkeypatch, mode):
+    """patch sets in mixed precision: the step split into patches' items
+    away from the SWE region and the shore (kernel without the FP64 edge
+    solve) and the rest (full kernel) gives the same bits as the full kernel
+    on every item.  A small three-level ocean whose level 0 holds the shelf
+    and the dry coast and whose finer levels lie in deep water; graph
+    replays, direct launches (timing on) and after the autotuner"""
+    w = W.amr_ocean(n=512, tile=64, targets=(40, 50), steps=4)
+    runs = []
+    for nosplit in ("0", "1"):
+        monkeypatch.setenv("HSGN_NO_KERNEL_SPLIT", nosplit)
+        print("case", w.name, mode, "no_split", nosplit, flush=True)
+        ctx, ids = H.from_amr_workloads([w], precision=1)
+        if mode == "direct":
+            ctx.set_timing(True)
+        if mode == "autotune":
+            ctx.autotune(trials=1)
+        ctx.advance(-1.0, 4)
+        runs.append(([(ctx.get_state(p), ctx.get_mask(p)) for p in ids[0]], ctx.read_gauges(0)[1]))
+        ctx.close()
+    (a, ga), (b, gb) = runs
+    assert np.array_equal(ga, gb)
+    for k, ((qa, ma), (qb, mb)) in enumerate(zip(a, b)):
+        assert np.array_equal(qa, qb) and np.array_equal(ma, mb), k

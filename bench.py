@@ -23,11 +23,15 @@ and resident in HBM before timing starts.  The step kernel issues far more
 vector ALU instructions than its HBM bytes need (about 20 flops per byte), so
 the JSON line's roofline is its algorithmic floating-point work, 1259 flops
 per cell update (counted by csrc/opcount.cpp), over its average launch time
-(HIP events on the library's stream), against the vector ALU peak of the chip
+(HIP events on the library's stream; in mixed precision a "launch" is the
+split step: item classification, the two item lists, and the kernels
+without and with the FP64 edge solve, the last on a second stream joined
+back before the closing event), against the vector ALU peak of the chip
 (256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s, the same for FP64
 and for unpacked FP32).  The algorithmic HBM rate is reported beside it, and
-`traffic` is the HBM bytes per launch measured with rocprofv3 counters for
-the current kernel sources (null when the sources have changed since).
+`traffic` is the HBM bytes per launch measured with rocprofv3 counters (the
+sum over the kernels of one launch) for the current kernel sources (null
+when the sources have changed since).
 cpu_baseline is the FP64 CPU oracle on a bounded sample of the same workload.
 
 `python bench.py --copy-calibration` runs one 2 GiB device copy and nothing
@@ -51,15 +55,21 @@ ALG_FLOPS = 1259
 # algorithmic bytes per cell update: read Q^n and write Q^{n+1} (7 variables),
 # read the bathymetry, read and write the mask byte
 ALG_BYTES = {"fp64": 7 * 8 * 2 + 8 + 2, "mixed": 7 * 4 * 2 + 4 + 2}
+# what one timed step-kernel launch is
+STEP_KERNELS = {"fp64": "march_kernel<fp64>",
+                "mixed": "classify + lists + march_kernel<mixed> (deep items) "
+                         "|| march_kernel<mixed, fp64 edges> (other items)"}
 # HBM bytes per step-kernel launch from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch; FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the
-# factors a plain 2 GiB copy reads), for the kernel sources whose digest is
-# given; any change to those sources makes the figure stale (null)
+# WRITE_SIZE (KiB per launch, summed over its kernels; FETCH_SIZE x 2.0 and
+# WRITE_SIZE x 1.0, the factors a plain 2 GiB copy reads), per tile height,
+# for the kernel sources whose digest is given; another tile height or any
+# change to those sources leaves the figure null
 KERNEL_SOURCES = ["hsgn_math.hpp", "hsgn_march.hpp", "hsgn_step.hpp",
                   "hsgn_step32.hip", "hsgn_step64.hip"]
 MEASURED_TRAFFIC = {
-    ("ensemble", "mixed"): {"fetch_kib": 1.60380e6, "write_kib": 2.73774e6,
-                            "digest": "1048ca517f37985a"},
+    ("ensemble", "mixed"): {"digest": "3ba5526bfe157a3d",
+                            "tiles": {28: (1.561405e6, 1.608216e6), 32: (1.537963e6, 1.606219e6),
+                                      40: (1.503437e6, 1.601013e6), 48: (1.480665e6, 1.598530e6)}},
 }
 
 
@@ -71,11 +81,14 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
+def measured_traffic(workload, precision, tile_rows):
     m = MEASURED_TRAFFIC.get((workload, precision))
-    if m is None or m["digest"] != kernel_digest():
+    if m is None or m["digest"] != kernel_digest() or len(tile_rows) != 1:
         return None
-    return (m["fetch_kib"] * 2.0 + m["write_kib"] * 1.0) * 1024.0
+    fw = m["tiles"].get(tile_rows[0])
+    if fw is None:
+        return None
+    return (fw[0] * 2.0 + fw[1] * 1.0) * 1024.0
 
 
 def log(*a):
@@ -309,7 +322,7 @@ def main():
         % (el * 1e3 / args.steps, kms * 1e3, value))
     tflops = ALG_FLOPS * cells_per_launch / (kms / 1e3) / 1e12
     hbm_gbs = ALG_BYTES[precision] * cells_per_launch / (kms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, precision)
+    traffic = measured_traffic(args.workload, precision, rows)
     dtype = {"mixed": "f32+f64", "fp64": "f64"}[precision]
     out = {
         "metric": "cell-updates/s",
@@ -332,7 +345,7 @@ def main():
                    "max_courant_scenario0": diag["max_courant"]},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "march_kernel<%s>" % precision, "kernel_avg_us": kms * 1e3,
+                     "kernel": STEP_KERNELS[precision], "kernel_avg_us": kms * 1e3,
                      "launches": launches, "alg_flops_per_cell": ALG_FLOPS,
                      "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": hbm_gbs / HBM_PEAK_GBS,
@@ -390,7 +403,7 @@ def main_adaptive(args, H, W, torch):
                    "stepping_only_value": updates / max(el - t_reg, 1e-12)},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "march_kernel<mixed>", "kernel_avg_us": kms * 1e3,
+                     "kernel": STEP_KERNELS["mixed"], "kernel_avg_us": kms * 1e3,
                      "launches": launches,
                      "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": hbm_gbs / HBM_PEAK_GBS}},

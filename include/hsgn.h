@@ -25,7 +25,8 @@
  *     (copy semantics); on_device = 1 means the pointer is device memory on
  *     the context's device, 0 means host memory.
  *   - All device work is enqueued on the stream given to hsgn_create (a
- *     borrowed hipStream_t; NULL = the default stream).
+ *     borrowed hipStream_t; NULL = the default stream), mixed-precision
+ *     steps partly on a second stream joined back into it (hsgn_create).
  *   - A context owns its device buffers: two state buffers (the step reads
  *     one and writes the other), bathymetry, two mask buffers, per-scenario
  *     clocks and gauge records.
@@ -116,6 +117,14 @@ typedef struct hsgn_diag {
 typedef struct hsgn_ctx hsgn_ctx;
 
 /* Create a context.  *p is copied.  hip_stream: borrowed hipStream_t.
+ * Mixed precision (precision 1) splits each step launch: the work items
+ * are classified from the step's input mask, the items that cannot need the
+ * FP64 near-shore solve run a kernel without it, and the others run the full
+ * kernel on a second stream the context owns (default priority), forked
+ * from and joined back into hip_stream with events, so that work enqueued on
+ * hip_stream after a call still follows the whole step.  The results are the
+ * same bits as with the full kernel everywhere, which the environment
+ * variable HSGN_NO_KERNEL_SPLIT=1, read here, selects (a diagnostic).
  * Errors: EINVAL (bad parameters), ENOTSUP (model/precision), EDEVICE. */
 int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out);
 

@@ -45,7 +45,7 @@ void launch_classify32(const MarchArgs<float> &A, unsigned nwork, int *cls, hipS
 void launch_static_class32(const MarchArgs<float> &A, unsigned nwork, int *out, hipStream_t stream);
 // instantiations for patches of patch sets (hsgn_step64amr.hip, hsgn_step32amr.hip)
 void launch_march64_amr(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream);
-void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
+void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream, bool beside);
 void launch_march32_amr_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream);
 void launch_classify32_amr(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream);
 void launch_static_class32_amr(const MarchArgs<float> &A, unsigned nwork, int *out, hipStream_t stream);
@@ -1727,35 +1727,38 @@ static void launch_gauges(hsgn_ctx *c, hipStream_t s)
 // mixed-precision items of one kind (single grids, or patches of patch sets
 // with amr) with the class split (A.list set): classified, then the kernel
 // without the FP64 edge solve over the items that do not need it and the
-// full kernel over the rest.  Single grids with fork: the few items that
-// need it (each runs long, in one round of waves) on a second stream beside
-// the other kernel, joined back into s; otherwise one after the other on s
-// (graph capture; patch sets always).
+// full kernel over the rest.  With fork the few items that need it (each
+// runs long, in one round of waves) run on a second stream beside the other
+// kernel, joined back into s (also while s is captured into a graph: the
+// second stream joins the capture through the fork event); otherwise one
+// after the other on s.
 static void launch_mixed_split(hsgn_ctx *c, const MarchArgs<float> &A, unsigned n, int *cls,
                                bool amr, hipStream_t s, bool fork)
 {
+    auto full = [&](hipStream_t st, bool beside) {
+        if (amr) launch_march32_amr(A, n, st, beside);
+        else launch_march32(A, n, st, beside);
+    };
+    auto deep = [&](hipStream_t st) {
+        if (amr) launch_march32_amr_deep(A, n, st);
+        else launch_march32_deep(A, n, st);
+    };
     if (!A.list) {
-        if (amr) launch_march32_amr(A, n, s);
-        else launch_march32(A, n, s, false);
+        full(s, false);
         return;
     }
-    if (amr) {
-        launch_classify32_amr(A, n, cls, s);
-        launch_march32_amr(A, n, s);
-        launch_march32_amr_deep(A, n, s);
-        return;
-    }
-    launch_classify32(A, n, cls, s);
+    if (amr) launch_classify32_amr(A, n, cls, s);
+    else launch_classify32(A, n, cls, s);
     if (fork) {
         (void)hipEventRecord(c->ev_fork, s);
         (void)hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0);
-        launch_march32(A, n, c->aux_stream, true);
-        launch_march32_deep(A, n, s);
+        full(c->aux_stream, true);
+        deep(s);
         (void)hipEventRecord(c->ev_join, c->aux_stream);
         (void)hipStreamWaitEvent(s, c->ev_join, 0);
     } else {
-        launch_march32(A, n, s, false);
-        launch_march32_deep(A, n, s);
+        full(s, false);
+        deep(s);
     }
 }
 
@@ -1784,7 +1787,7 @@ static void launch_march_range(hsgn_ctx *c, int w0, int wa, int w1, hipStream_t 
         if (c->mixed) {
             MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, wa, w1);
             split_args(c, A, wa);
-            launch_mixed_split(c, A, (unsigned)(w1 - wa), c->d_cls + wa, true, s, false);
+            launch_mixed_split(c, A, (unsigned)(w1 - wa), c->d_cls + wa, true, s, fork);
         } else
             launch_march64_amr(march_args<double>(c, c->q0, c->q1, c->bath, wa, w1),
                                (unsigned)(w1 - wa), s);
@@ -1814,7 +1817,7 @@ static void launch_level(hsgn_ctx *c, int l, double theta, hipStream_t s, bool t
         launch_halo_interp64(B, c->d_gi + R.gi0, R.gi1 - R.gi0, theta, eta0, dtol, s);
     }
     if (timed) (void)timed_begin(c, s);
-    launch_march_range(c, R.w0, R.wa, R.w1, s, false);
+    launch_march_range(c, R.w0, R.wa, R.w1, s, true);
     if (timed) (void)timed_end(c, s);
     launch_control(c, R.s0, R.s1, s);
     if (l + 1 >= c->nlev) return;
@@ -2109,7 +2112,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                             A.lcnt = dlcnt;
                             A.clsb = dclsb + na;
                         }
-                        launch_mixed_split(c, A, (unsigned)(n - na), dcls + na, true, c->stream, false);
+                        launch_mixed_split(c, A, (unsigned)(n - na), dcls + na, true, c->stream, true);
                     } else {
                         MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, n - na);
                         A.work = dwork + na; A.clip_slots = dclip + na;

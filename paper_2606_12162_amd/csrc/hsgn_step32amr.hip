@@ -4,12 +4,17 @@
 
 using namespace hsgn;
 
+// blocks of the full kernel over the list of items that need the FP64 edge
+// solve when it runs beside the other kernel (beside): one wavefront per
+// SIMD of the chip at most, each taking entries in turn
+constexpr unsigned FB_BLOCKS_AMR = 1024;
+
 // the full kernel: every item, or with item lists the items that need the
-// FP64 edge solve (one block per entry: patch-set steps run the two kernels
-// one after the other)
-void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
+// FP64 edge solve
+void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream, bool beside)
 {
-    march_kernel<float, float, true, true, true><<<nwork, 64, 0, stream>>>(A);
+    const unsigned grid = A.list && beside && nwork > FB_BLOCKS_AMR ? FB_BLOCKS_AMR : nwork;
+    march_kernel<float, float, true, true, true><<<grid, 64, 0, stream>>>(A);
 }
 
 // the kernel without the FP64 edge solve, over the other list

@@ -143,9 +143,13 @@ int hsgn_finalize(hsgn_ctx *c);
 
 /* Bathymetry b[ny][nx] of a patch; computes H = (eta0 - b)^+ and phi_T (the
  * minimum of H over the (2n+1)^2 box through the boundary map exceeds
- * h_star) and clears the breaking latch.  The library keeps a host copy of b
- * (8 bytes per cell; regridding rebuilds from it); a device pointer is read
- * with a synchronous copy. */
+ * h_star) and clears the breaking latch.  A state already set keeps each
+ * cell's depth h under the new bottom in both precisions, so that the
+ * surface moves with it: called between steps, this is the sea-floor motion
+ * that generates the Tohoku tsunami of Sec. 6.4 (covered cells of a coarser
+ * level keep theirs too when their bathymetry is averaged anew).  The library
+ * keeps a host copy of b (8 bytes per cell; regridding rebuilds from it); a
+ * device pointer is read with a synchronous copy. */
 int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device);
 
 /* State q[7][ny][nx] (float64) of a patch, copied in or out. */

@@ -132,9 +132,13 @@ __global__ void ghost_bath_kernel(AmrBuffers<S> B, const GhostCopy *Cp, int nc,
     }
 }
 
-// mean of the 4 x 4 fine cells (rows outer, columns inner)
+// mean of the 4 x 4 fine cells (rows outer, columns inner).  bath_only with
+// keep (mixed storage, flag per coarse patch whose state is set): the
+// covered cell's stored eta' follows the new bottom so that its depth is
+// kept, as the FP64 storage of h keeps it
 template <class S>
-__global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath_only)
+__global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath_only,
+                               const uint8_t *keep)
 {
     int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (k >= n) return;
@@ -144,7 +148,13 @@ __global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath
         double s = 0.0;
         for (int a = 0; a < AMR_RATIO; a++)
             for (int c = 0; c < AMR_RATIO; c++) s += (double)B.bath[F.coff + r.fl + a * F.pitch + c];
-        B.bath[C.coff + r.cl] = (S)(s * 0.0625);
+        const S bn = (S)(s * 0.0625);
+        if (keep && keep[r.cp]) {
+            S *qc = B.scen[C.scen].cur ? B.q1 : B.q0;
+            const long long l = C.qoff + r.cl;
+            qc[l] = (S)((double)qc[l] + ((double)bn - (double)B.bath[C.coff + r.cl]));
+        }
+        B.bath[C.coff + r.cl] = bn;
         return;
     }
     if (scen_failed(B.scen, C.scen) || scen_failed(B.scen, F.scen)) return;
@@ -496,12 +506,12 @@ void launch_ghost_bath32(const AmrBuffers<float> &B, const GhostCopy *c, int nc,
 void launch_avgdown64(const AmrBuffers<double> &B, const AvgRec *r, int n, bool bath_only,
                       hipStream_t s)
 {
-    if (n > 0) avgdown_kernel<double><<<blocks(n), TPB, 0, s>>>(B, r, n, bath_only ? 1 : 0);
+    if (n > 0) avgdown_kernel<double><<<blocks(n), TPB, 0, s>>>(B, r, n, bath_only ? 1 : 0, nullptr);
 }
 void launch_avgdown32(const AmrBuffers<float> &B, const AvgRec *r, int n, bool bath_only,
-                      hipStream_t s)
+                      hipStream_t s, const uint8_t *keep)
 {
-    if (n > 0) avgdown_kernel<float><<<blocks(n), TPB, 0, s>>>(B, r, n, bath_only ? 1 : 0);
+    if (n > 0) avgdown_kernel<float><<<blocks(n), TPB, 0, s>>>(B, r, n, bath_only ? 1 : 0, keep);
 }
 void launch_bflux64(const AmrBuffers<double> &B, const StepParams &P, const FluxRec *r, int n,
                     const double *E, double *R, hipStream_t s)

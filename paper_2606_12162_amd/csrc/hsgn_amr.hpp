@@ -85,8 +85,10 @@ void launch_ghost_bath32(const AmrBuffers<float> &B, const GhostCopy *c, int nc,
                          const GhostInterp *r, int ni, hipStream_t s);
 void launch_avgdown64(const AmrBuffers<double> &B, const AvgRec *r, int n, bool bath_only,
                       hipStream_t s);
+// keep: per patch, 1 where a bathymetry-only average-down keeps the
+// covered cells' depth (mixed storage of eta'); null keeps eta'
 void launch_avgdown32(const AmrBuffers<float> &B, const AvgRec *r, int n, bool bath_only,
-                      hipStream_t s);
+                      hipStream_t s, const uint8_t *keep = nullptr);
 void launch_bflux64(const AmrBuffers<double> &B, const StepParams &P, const FluxRec *r, int n,
                     const double *E, double *R, hipStream_t s);
 void launch_bflux32(const AmrBuffers<float> &B, const StepParams &P, const FluxRec *r, int n,

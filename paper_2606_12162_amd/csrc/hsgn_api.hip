@@ -289,6 +289,21 @@ __global__ void from_storage_kernel(PatchInfo pi, const S *q, const S *bath, dou
     for (int m = 1; m < 7; m++) out[m * ncell + i] = (double)q[pi.qoff + m * pi.plane + idx];
 }
 
+// mixed storage under a new bottom bnew (ABI layout, FP64): eta' of every
+// interior cell of the patch becomes h + bnew - eta0, with h from the old
+// bottom, so that the depth is kept (the new bottom is stored in FP32)
+__global__ void keep_depth_kernel(PatchInfo pi, float *q, const float *bath, const double *bnew,
+                                  double eta0)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long ncell = (long long)pi.nx * pi.ny;
+    if (i >= ncell) return;
+    int x = (int)(i % pi.nx), y = (int)(i / pi.nx);
+    long long idx = (long long)y * pi.pitch + x;
+    const double h = (double)q[pi.qoff + idx] + eta0 - (double)bath[pi.coff + idx];
+    q[pi.qoff + idx] = (float)(h + (double)(float)bnew[i] - eta0);
+}
+
 // one cell plane (bathymetry or mask) between the ABI layout and storage
 template <class A, class S>
 __global__ void scatter_plane_kernel(PatchInfo pi, const A *in, S *out, int keep_high_bits)
@@ -432,6 +447,8 @@ struct hsgn_ctx {
     int *d_list = nullptr;      // item lists of the split mixed step (2 per item)
     unsigned *d_lcnt = nullptr; // their lengths
     int *d_cls = nullptr;       // the items' classes for the attempt
+    std::vector<uint8_t> state_set;   // per patch: its state has been set (or moved in)
+    uint8_t *d_keep = nullptr;  // device copy of state_set for the bathymetry average-down
     int *d_clsb = nullptr;      // their bottom part
     bool clsb_dirty = true;     // d_clsb to recompute (bathymetry or work table changed)
     bool split = false;         // mixed single grids: deep items without the FP64 edges
@@ -514,7 +531,7 @@ static void free_device(hsgn_ctx *c)
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
                     c->d_mass, c->f0, c->f1, c->fbath, c->stage, c->d_cnt, c->d_gc, c->d_gi,
                     c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip, c->d_list,
-                    c->d_lcnt, c->d_clsb, c->d_cls};
+                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c->q0 = c->q1 = c->bath = c->clip = c->rec = c->d_mass = c->stage = nullptr;
@@ -525,6 +542,7 @@ static void free_device(hsgn_ctx *c)
     c->d_gc = nullptr; c->d_gi = nullptr; c->d_fr = nullptr; c->d_rf = nullptr; c->d_av = nullptr;
     c->d_E = c->d_R = c->d_rclip = nullptr;
     c->d_list = c->d_clsb = c->d_cls = nullptr;
+    c->d_keep = nullptr;
     c->d_lcnt = nullptr;
 }
 
@@ -1251,6 +1269,8 @@ int hsgn_finalize(hsgn_ctx *c)
     HIPCHK(c, hipMalloc(&c->m1, c->ctotal));
     HIPCHK(c, hipMalloc(&c->clip, sizeof(double) * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_patches, sizeof(PatchInfo) * c->patches.size()));
+    HIPCHK(c, hipMalloc(&c->d_keep, c->patches.size()));
+    c->state_set.assign(c->patches.size(), 0);
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(WorkItem) * c->work.size()));
     HIPCHK(c, hipMalloc(&c->d_list, sizeof(int) * 2 * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_lcnt, sizeof(unsigned) * 2));
@@ -1343,11 +1363,14 @@ static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 static int ensure_prepared(hsgn_ctx *c)
 {
     if (!c->any_amr || !c->amr_dirty) return HSGN_OK;
+    if (c->mixed)
+        HIPCHK(c, hipMemcpy(c->d_keep, c->state_set.data(), c->state_set.size(),
+                            hipMemcpyHostToDevice));
     for (int l = c->nlev - 1; l >= 1; l--) {
         const LevelRange &R = c->L[l];
         if (c->mixed)
             launch_avgdown32(amr_buffers<float>(c, c->f0, c->f1, c->fbath), c->d_av + R.av0,
-                             R.av1 - R.av0, true, c->stream);
+                             R.av1 - R.av0, true, c->stream, c->d_keep);
         else
             launch_avgdown64(amr_buffers<double>(c, c->q0, c->q1, c->bath), c->d_av + R.av0,
                              R.av1 - R.av0, true, c->stream);
@@ -1419,8 +1442,16 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
     else
         memcpy(c->braw[patch].data(), b, sizeof(double) * n);
     if (c->mixed) {
-        // stored in FP32; phi_T is computed from the stored values
+        // stored in FP32; phi_T is computed from the stored values.  A set
+        // state keeps its depth under the new bottom (the stored eta' moves
+        // with it), as the FP64 storage of h does
         HIPCHK(c, hipMemcpyAsync(c->stage, b, sizeof(double) * n, kind_in(on_device), c->stream));
+        if (c->state_set[patch]) {
+            std::vector<ScenState> st;
+            if ((rc = pull_scen(c, st))) return rc;
+            keep_depth_kernel<<<nb, 256, 0, c->stream>>>(p, st[p.scen].cur ? c->f1 : c->f0, c->fbath,
+                                                         c->stage, c->prm.eta0);
+        }
         scatter_plane_kernel<double, float><<<nb, 256, 0, c->stream>>>(p, c->stage, c->fbath, 0);
         if (!amr)
             mask_kernel<float><<<nb, 256, 0, c->stream>>>(p, c->fbath, c->m0, c->m1, c->prm.eta0,
@@ -1468,6 +1499,7 @@ int hsgn_set_state(hsgn_ctx *c, int patch, const double *q, int on_device)
         HIPCHK(c, hipMemcpyAsync(dst, q, sizeof(double) * 7 * n, kind_in(on_device), c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->state_set[patch] = 1;
     return HSGN_OK;
 }
 
@@ -2858,6 +2890,7 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     rc = c->mixed ? rg_transfer<float, true>(c, n, st, kept, fresh, old_fine, level)
                   : rg_transfer<double, false>(c, n, st, kept, fresh, old_fine, level);
     if (rc) { hsgn_destroy(n); return rc; }
+    n->state_set.assign(n->patches.size(), 1);    // every patch's state was moved in
     // 7. clocks, clipped mass, gauges and their records
     std::vector<ScenState> sn;
     if ((rc = pull_scen(n, sn))) return bail(rc, "regrid: clock");

@@ -416,6 +416,24 @@ struct LevelRange {
     long long e0 = 0, e1 = 0;       // boundary-flux entries (7-vectors)
 };
 
+// host tables that are sized first and then filled: resize() leaves the new
+// records uninitialised instead of zeroing them
+template <class T>
+struct DefaultInitAlloc : std::allocator<T> {
+    template <class U> struct rebind { using other = DefaultInitAlloc<U>; };
+    DefaultInitAlloc() = default;
+    template <class U> DefaultInitAlloc(const DefaultInitAlloc<U> &) noexcept {}
+    template <class U> void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value)
+    {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <class U, class... A> void construct(U *p, A &&...a)
+    {
+        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+    }
+};
+template <class T> using HostVec = std::vector<T, DefaultInitAlloc<T>>;
+
 struct hsgn_ctx {
     hsgn_params prm;
     StepParams P;
@@ -423,6 +441,8 @@ struct hsgn_ctx {
     bool finalized = false;
     std::vector<PatchInfo> patches;
     std::vector<std::vector<double>> braw;   // bathymetry as set, per patch (host copy)
+    double *d_B0 = nullptr;     // device level-0 bathymetry of scenario b0_scen (regridding)
+    int b0_scen = -1;
     std::vector<char> braw_rule;             // 1: a regridded patch, bathymetry from the
                                              // level-0 bathymetry (no host copy kept)
     std::vector<double> px0, py0;
@@ -462,11 +482,11 @@ struct hsgn_ctx {
     int ngauge_total = 0;
     long long qtotal = 0, ctotal = 0, rec_total = 0;
     // patch sets
-    std::vector<GhostCopy> h_gc;
-    std::vector<GhostInterp> h_gi;
-    std::vector<FluxRec> h_fr;
-    std::vector<RefluxRec> h_rf;
-    std::vector<AvgRec> h_av;
+    HostVec<GhostCopy> h_gc;
+    HostVec<GhostInterp> h_gi;
+    HostVec<FluxRec> h_fr;
+    HostVec<RefluxRec> h_rf;
+    HostVec<AvgRec> h_av;
     GhostCopy *d_gc = nullptr;
     GhostInterp *d_gi = nullptr;
     FluxRec *d_fr = nullptr;
@@ -531,7 +551,7 @@ static void free_device(hsgn_ctx *c)
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
                     c->d_mass, c->f0, c->f1, c->fbath, c->stage, c->d_cnt, c->d_gc, c->d_gi,
                     c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip, c->d_list,
-                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep};
+                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep, c->d_B0};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c->q0 = c->q1 = c->bath = c->clip = c->rec = c->d_mass = c->stage = nullptr;
@@ -543,6 +563,8 @@ static void free_device(hsgn_ctx *c)
     c->d_E = c->d_R = c->d_rclip = nullptr;
     c->d_list = c->d_clsb = c->d_cls = nullptr;
     c->d_keep = nullptr;
+    c->d_B0 = nullptr;
+    c->b0_scen = -1;
     c->d_lcnt = nullptr;
 }
 
@@ -635,12 +657,20 @@ static int host_map(int i, int n, int lo, int hi, int *flip)
 static int local_of(const PatchInfo &p, long long i, long long j) { return (int)(j * p.pitch + i); }
 
 // validate a patch set and build its tables (appended to the context's)
-static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<int>> &lev_gc,
-                           std::vector<std::vector<int>> &lev_gi, std::vector<std::vector<int>> &lev_fr,
-                           std::vector<std::vector<int>> &lev_rf, std::vector<std::vector<int>> &lev_av,
-                           std::vector<GhostCopy> &gc, std::vector<GhostInterp> &gi,
-                           std::vector<FluxRec> &fr, std::vector<RefluxRec> &rf,
-                           std::vector<AvgRec> &av)
+// per patch of a patch set: its ghost, boundary-flux and covered-cell records
+struct PatchRecs {
+    std::vector<GhostCopy> gc;
+    std::vector<GhostInterp> gi;
+    std::vector<FluxRec> fr;
+    std::vector<AvgRec> av;
+    const char *err = nullptr;
+};
+
+// the tables of patch-set scenario s, appended per level: lev_recs[l] gets
+// the records of its level-l patches in patch order, lev_rf[l] its reflux
+// records in (J, I) order
+static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs>> &lev_recs,
+                           std::vector<std::vector<RefluxRec>> &lev_rf)
 {
     ScenHost &sh = c->scen[s];
     const int nl = (int)sh.lev.size();
@@ -683,15 +713,8 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<int>> &le
     };
     // per patch: ghost, boundary-flux and covered-cell records.  Patches are
     // independent (the indexes are read only), so they are built on host
-    // threads and joined in patch order: the tables do not depend on the
+    // threads and kept in patch order: the tables do not depend on the
     // number of threads.
-    struct PatchRecs {
-        std::vector<GhostCopy> gc;
-        std::vector<GhostInterp> gi;
-        std::vector<FluxRec> fr;
-        std::vector<AvgRec> av;
-        const char *err = nullptr;
-    };
     auto build_one = [&](int l, int pid, PatchRecs &out) {
         const PatchInfo &P = c->patches[pid];
         const long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
@@ -778,27 +801,53 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<int>> &le
             work(0);
             for (int t = 1; t < nthreads; t++) work(t);
         }
-        for (auto &r : recs) {
+        for (auto &r : recs)
             if (r.err) return fail(c, HSGN_EINVAL, r.err);
-            for (auto &x : r.gc) { lev_gc[l].push_back((int)gc.size()); gc.push_back(x); }
-            for (auto &x : r.gi) { lev_gi[l].push_back((int)gi.size()); gi.push_back(x); }
-            for (auto &x : r.fr) { lev_fr[l].push_back((int)fr.size()); fr.push_back(x); }
-            for (auto &x : r.av) { lev_av[l].push_back((int)av.size()); av.push_back(x); }
-        }
+        for (auto &r : recs) lev_recs[l].push_back(std::move(r));
     }
     for (int l = 0; l < nl; l++) {
         // reflux records: uncovered level-l cells next to a level-(l+1) patch
         if (l + 1 < nl) {
+            // candidate cells: the ring of level-l cells around each finer
+            // patch (inside the domain: finer patches stay one cell away from
+            // its boundary), sorted in (J, I) order without repeats.  Small
+            // levels mark them in a bitmap read back row by row; large ones
+            // sort the list.
             std::vector<std::pair<long long, long long>> cand;
+            const long long NXl = idx[l].NXl, NYl = idx[l].NYl;
+            const long long words = (NXl + 63) / 64;
+            const bool bitmap = words * NYl <= (1LL << 24);         // at most 128 MB
+            std::vector<uint64_t> mark(bitmap ? (size_t)(words * NYl) : 0, 0);
+            std::vector<uint8_t> row_used(bitmap ? (size_t)NYl : 0, 0);
+            auto put = [&](long long J, long long I) {
+                if (!bitmap) { cand.push_back({J, I}); return; }
+                if (I < 0 || J < 0 || I >= NXl || J >= NYl) return;
+                mark[(size_t)(J * words + I / 64)] |= 1ull << (I % 64);
+                row_used[(size_t)J] = 1;
+            };
             for (int f : sh.lev[l + 1]) {
                 const PatchInfo &F = c->patches[f];
                 long long a0 = c->pI0[f] / AMR_RATIO, b0 = c->pJ0[f] / AMR_RATIO;
                 long long a1 = a0 + F.nx / AMR_RATIO, b1 = b0 + F.ny / AMR_RATIO;
-                for (long long J = b0; J < b1; J++) { cand.push_back({J, a0 - 1}); cand.push_back({J, a1}); }
-                for (long long I = a0; I < a1; I++) { cand.push_back({b0 - 1, I}); cand.push_back({b1, I}); }
+                for (long long J = b0; J < b1; J++) { put(J, a0 - 1); put(J, a1); }
+                for (long long I = a0; I < a1; I++) { put(b0 - 1, I); put(b1, I); }
             }
-            std::sort(cand.begin(), cand.end());
-            cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            if (bitmap) {
+                for (long long J = 0; J < NYl; J++) {
+                    if (!row_used[(size_t)J]) continue;
+                    for (long long w = 0; w < words; w++) {
+                        uint64_t m = mark[(size_t)(J * words + w)];
+                        while (m) {
+                            const int b = __builtin_ctzll(m);
+                            cand.push_back({J, w * 64 + b});
+                            m &= m - 1;
+                        }
+                    }
+                }
+            } else {
+                std::sort(cand.begin(), cand.end());
+                cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            }
             for (auto &jc : cand) {
                 long long J = jc.first, I = jc.second;
                 int cp = idx[l].find(I, J);
@@ -825,10 +874,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<int>> &le
                                      : (int)(2 * F.ny + AMR_RATIO * I - fI0);
                     any = true;
                 }
-                if (any) {
-                    lev_rf[l].push_back((int)rf.size());
-                    rf.push_back(r);
-                }
+                if (any) lev_rf[l].push_back(r);
             }
         }
     }
@@ -1140,8 +1186,8 @@ static int check_scenarios(hsgn_ctx *c)
 
 }  // extern "C"
 
-template <class T>
-static int upload(hsgn_ctx *c, T **d, const std::vector<T> &h)
+template <class T, class A>
+static int upload(hsgn_ctx *c, T **d, const std::vector<T, A> &h)
 {
     if (h.empty()) return HSGN_OK;
     HIPCHK(c, hipMalloc(d, sizeof(T) * h.size()));
@@ -1215,34 +1261,51 @@ int hsgn_finalize(hsgn_ctx *c)
     build_work(c, c->th_level, c->work, c->sstat, c->L);
     // patch-set tables, grouped by level
     {
-        std::vector<std::vector<int>> lgc(c->nlev), lgi(c->nlev), lfr(c->nlev), lrf(c->nlev), lav(c->nlev);
-        std::vector<GhostCopy> gc;
-        std::vector<GhostInterp> gi;
-        std::vector<FluxRec> fr;
-        std::vector<RefluxRec> rf;
-        std::vector<AvgRec> av;
+        std::vector<std::vector<PatchRecs>> recs(c->nlev);
+        std::vector<std::vector<RefluxRec>> lrf(c->nlev);
         for (int s = 0; s < nscen; s++)
-            if (c->scen[s].amr &&
-                (rc = build_patch_set(c, s, lgc, lgi, lfr, lrf, lav, gc, gi, fr, rf, av)))
-                return rc;
-        c->h_gc.clear(); c->h_gi.clear(); c->h_fr.clear(); c->h_rf.clear(); c->h_av.clear();
+            if (c->scen[s].amr && (rc = build_patch_set(c, s, recs, lrf))) return rc;
+        // the tables grouped by level (scenarios, then patches, in order):
+        // offsets first, then the records copied into place on host threads
+        struct Off { size_t gc, gi, fr, av; };
+        std::vector<std::vector<Off>> off(c->nlev);
+        size_t ngc = 0, ngi = 0, nfr = 0, nav = 0, nrf = 0;
         for (int l = 0; l < c->nlev; l++) {
             LevelRange &R = c->L[l];
-            R.gc0 = (int)c->h_gc.size();
-            for (int k : lgc[l]) c->h_gc.push_back(gc[k]);
-            R.gc1 = (int)c->h_gc.size();
-            R.gi0 = (int)c->h_gi.size();
-            for (int k : lgi[l]) c->h_gi.push_back(gi[k]);
-            R.gi1 = (int)c->h_gi.size();
-            R.fr0 = (int)c->h_fr.size();
-            for (int k : lfr[l]) c->h_fr.push_back(fr[k]);
-            R.fr1 = (int)c->h_fr.size();
-            R.rf0 = (int)c->h_rf.size();
-            for (int k : lrf[l]) c->h_rf.push_back(rf[k]);
-            R.rf1 = (int)c->h_rf.size();
-            R.av0 = (int)c->h_av.size();
-            for (int k : lav[l]) c->h_av.push_back(av[k]);
-            R.av1 = (int)c->h_av.size();
+            R.gc0 = (int)ngc; R.gi0 = (int)ngi; R.fr0 = (int)nfr; R.av0 = (int)nav;
+            for (const PatchRecs &r : recs[l]) {
+                off[l].push_back({ngc, ngi, nfr, nav});
+                ngc += r.gc.size(); ngi += r.gi.size(); nfr += r.fr.size(); nav += r.av.size();
+            }
+            R.gc1 = (int)ngc; R.gi1 = (int)ngi; R.fr1 = (int)nfr; R.av1 = (int)nav;
+            R.rf0 = (int)nrf;
+            nrf += lrf[l].size();
+            R.rf1 = (int)nrf;
+        }
+        c->h_gc.resize(ngc); c->h_gi.resize(ngi); c->h_fr.resize(nfr); c->h_av.resize(nav);
+        c->h_rf.clear();
+        c->h_rf.reserve(nrf);
+        for (int l = 0; l < c->nlev; l++) c->h_rf.insert(c->h_rf.end(), lrf[l].begin(), lrf[l].end());
+        std::vector<std::pair<int, int>> jobs;         // (level, patch entry)
+        for (int l = 0; l < c->nlev; l++)
+            for (size_t k = 0; k < recs[l].size(); k++) jobs.push_back({l, (int)k});
+        auto place = [&](int t, int nt) {
+            for (size_t j = (size_t)t; j < jobs.size(); j += (size_t)nt) {
+                const PatchRecs &r = recs[jobs[j].first][jobs[j].second];
+                const Off &o = off[jobs[j].first][jobs[j].second];
+                std::copy(r.gc.begin(), r.gc.end(), c->h_gc.begin() + o.gc);
+                std::copy(r.gi.begin(), r.gi.end(), c->h_gi.begin() + o.gi);
+                std::copy(r.fr.begin(), r.fr.end(), c->h_fr.begin() + o.fr);
+                std::copy(r.av.begin(), r.av.end(), c->h_av.begin() + o.av);
+            }
+        };
+        const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+        if (nt > 1 && jobs.size() > 64) {
+            std::vector<std::thread> th;
+            for (int t = 0; t < nt; t++) th.emplace_back(place, t, nt);
+            for (auto &x : th) x.join();
+        } else {
+            place(0, 1);
         }
     }
     if ((rc = validate_tables(c))) return rc;
@@ -1437,6 +1500,7 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
     if ((int)c->braw_rule.size() < (int)c->patches.size()) c->braw_rule.resize(c->patches.size(), 0);
     c->braw_rule[patch] = 0;
     c->braw[patch].resize((size_t)n);
+    c->b0_scen = -1;                      // the cached level-0 bathymetry is stale
     if (on_device)
         HIPCHK(c, hipMemcpy(c->braw[patch].data(), b, sizeof(double) * n, hipMemcpyDeviceToHost));
     else
@@ -2776,13 +2840,21 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     // by the caller from their host copies (one transfer)
     n->braw.assign(n->patches.size(), std::vector<double>());
     n->braw_rule.assign(n->patches.size(), 0);
+    // host bathymetry copies carried over: moved once the regrid has succeeded
+    std::vector<int> braw_src(n->patches.size(), -1);
     {
-        std::vector<double> B0((size_t)sh.NX * sh.NY);
-        for (int pid : sh.lev[0]) {
-            const PatchInfo &p = c->patches[pid];
-            for (int j = 0; j < p.ny; j++)
-                memcpy(&B0[(size_t)(c->pJ0[pid] + j) * sh.NX + c->pI0[pid]],
-                       &c->braw[pid][(size_t)j * p.nx], sizeof(double) * p.nx);
+        // the level-0 bathymetry on the device, kept for the next regrid of
+        // this scenario until a bathymetry changes
+        const bool b0_cached = c->d_B0 && c->b0_scen == scenario;
+        std::vector<double> B0;
+        if (!b0_cached) {
+            B0.resize((size_t)sh.NX * sh.NY);
+            for (int pid : sh.lev[0]) {
+                const PatchInfo &p = c->patches[pid];
+                for (int j = 0; j < p.ny; j++)
+                    memcpy(&B0[(size_t)(c->pJ0[pid] + j) * sh.NX + c->pI0[pid]],
+                           &c->braw[pid][(size_t)j * p.nx], sizeof(double) * p.nx);
+            }
         }
         std::vector<TopoRec> topo;
         std::vector<BulkRec> bulk;
@@ -2802,13 +2874,13 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
             if (this_scen && (c->patches[k.first].level == 0 || rule)) {
                 add_topo(k.second);
                 n->braw_rule[k.second] = rule ? 1 : 0;
-                if (!rule) n->braw[k.second] = c->braw[k.first];
+                if (!rule) braw_src[k.second] = k.first;
             } else if (rule) {
                 return bail(HSGN_EINVAL, "regrid: rule bathymetry outside its scenario");
             } else {
-                n->braw[k.second] = c->braw[k.first];
+                braw_src[k.second] = k.first;
                 bulk.push_back({n->patches[k.second], btot});
-                btot += (long long)n->braw[k.second].size();
+                btot += (long long)c->braw[k.first].size();
             }
         }
         for (int id : fresh_ids) {
@@ -2818,19 +2890,25 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
         std::vector<double> all((size_t)std::max<long long>(btot, 1));
         for (size_t k = 0, pos = 0; k < kept.size(); k++) {
             const int id = kept[k].second;
-            if (n->braw[id].empty() || n->braw_rule[id]) continue;
+            if (braw_src[id] < 0 || n->braw_rule[id]) continue;
             const bool topo_done = n->slot_scen[n->patches[id].scen] == scenario &&
                                    n->patches[id].level == 0;
             if (topo_done) continue;
-            memcpy(&all[pos], n->braw[id].data(), sizeof(double) * n->braw[id].size());
-            pos += n->braw[id].size();
+            const std::vector<double> &src = c->braw[braw_src[id]];
+            memcpy(&all[pos], src.data(), sizeof(double) * src.size());
+            pos += src.size();
         }
-        double *dB0 = nullptr, *din = nullptr;
+        double *dB0 = b0_cached ? c->d_B0 : nullptr, *din = nullptr;
         TopoRec *dtopo = nullptr;
         BulkRec *dbulk = nullptr;
-        hipError_t be = hipMalloc(&dB0, sizeof(double) * B0.size());
-        if (be == hipSuccess)
-            be = hipMemcpy(dB0, B0.data(), sizeof(double) * B0.size(), hipMemcpyHostToDevice);
+        hipError_t be = hipSuccess;
+        if (!b0_cached) {
+            be = hipMalloc(&dB0, sizeof(double) * B0.size());
+            if (be == hipSuccess) n->d_B0 = dB0;            // the new context owns it
+            if (be == hipSuccess)
+                be = hipMemcpy(dB0, B0.data(), sizeof(double) * B0.size(), hipMemcpyHostToDevice);
+        }
+        n->b0_scen = scenario;
         if (be == hipSuccess && !topo.empty()) {
             be = hipMalloc(&dtopo, sizeof(TopoRec) * topo.size());
             if (be == hipSuccess)
@@ -2873,7 +2951,6 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
             be = hipGetLastError();
             if (be == hipSuccess) be = hipStreamSynchronize(n->stream);
         }
-        if (dB0) (void)hipFree(dB0);
         if (dtopo) (void)hipFree(dtopo);
         if (din) (void)hipFree(din);
         if (dbulk) (void)hipFree(dbulk);
@@ -2954,6 +3031,13 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     if ((rc = collect_timing(c))) return bail(rc, "regrid: timing");
     n->timed_ms = c->timed_ms;
     n->timed_launches = c->timed_launches;
+    // hand-over of what the new context takes from the old one
+    if (!n->d_B0 && c->b0_scen == scenario) {
+        n->d_B0 = c->d_B0;
+        c->d_B0 = nullptr;
+    }
+    for (size_t id = 0; id < braw_src.size(); id++)
+        if (braw_src[id] >= 0) n->braw[id] = std::move(c->braw[braw_src[id]]);
     std::swap(*c, *n);
     hsgn_destroy(n);
     if (n_new) *n_new = (int)boxes.size();

@@ -136,6 +136,14 @@ class AmrOracle:
         self.prepared = False
         self.old = {}
 
+    def set_sponge(self, width, rate):
+        """sponge widths (m) from the x-low, x-high, y-low, y-high sides of
+        the level-0 domain and peak rate (1/s), on every patch (its place in
+        the domain of its level)"""
+        for p in self.patches:
+            r = RATIO ** p.level
+            p.g.set_sponge(width, rate, offset=(p.I0, p.J0), domain=(self.NX * r, self.NY * r))
+
     # -------------------------------------------------------------- lookup
     def find(self, level, I, J):
         for p in self.levels[level]:

@@ -52,6 +52,11 @@ struct orc_grid {
      * (bit 0 left, 1 right, 2 bottom, 3 top) */
     int ext_ghosts;
     unsigned char *iface;       /* [sy][sx] */
+    /* sponge layer: widths from the domain's x-low, x-high, y-low, y-high
+     * sides (0: none), peak rate, and the grid's place in its level's
+     * domain (global index of cell (0, 0), domain size in cells) */
+    double sp_w[4], sp_rate;
+    long long sp_i0, sp_j0, sp_nx, sp_ny;
     double t, dt_next;
     long long nstep, nrej;
     int have_dt;
@@ -312,6 +317,27 @@ void orc_source_cell_mb(double *q, double c2, double tau)
 
 /* apply the source step of length tau to one cell, or clear the auxiliary
  * variables of a dry or SWE cell (SWE region: c^2 -> 0 with p -> 0) */
+/* relaxation rate of the sponge at interior cell (i, j): with d the
+ * distance of the cell centre from a sponged side of the domain and w that
+ * side's width, s = (w - d) / w inside the band; the largest s over the
+ * sides gives sigma = rate s^2 (a reading: the sponge is cited, not
+ * described) */
+static double sponge_sigma(const orc_grid *g, int i, int j)
+{
+    const long long I = g->sp_i0 + i, J = g->sp_j0 + j;
+    const double d[4] = {((double)I + 0.5) * g->dx, ((double)(g->sp_nx - 1 - I) + 0.5) * g->dx,
+                         ((double)J + 0.5) * g->dy, ((double)(g->sp_ny - 1 - J) + 0.5) * g->dy};
+    double s = 0.0;
+    for (int e = 0; e < 4; e++) {
+        const double w = g->sp_w[e];
+        if (w > 0.0 && d[e] < w) {
+            const double t = (w - d[e]) / w;
+            if (t > s) s = t;
+        }
+    }
+    return g->sp_rate * (s * s);
+}
+
 static void source_or_clear(orc_grid *g, size_t k, double tau, double *qc)
 {
     int wet = qc[IH] > g->P.dry_tol;
@@ -870,6 +896,17 @@ int orc_step(orc_grid *g, double dt, double *courant)
                 qc[m] = v;
             }
             source_or_clear(g, k, P->splitting ? 0.5 * dt : dt, qc);
+            /* sponge: every variable relaxed towards the state at rest
+             * (h = H, the rest zero) by an implicit Euler step of rate sigma */
+            if (g->sp_rate > 0.0) {
+                const double sg = sponge_sigma(g, i, j);
+                if (sg > 0.0) {
+                    const double f = 1.0 / (1.0 + dt * sg);
+                    const double H = still_depth(P, g->b[k]);
+                    qc[IH] = H + (qc[IH] - H) * f;
+                    for (int m = 1; m < 7; m++) qc[m] = qc[m] * f;
+                }
+            }
             if (qc[IH] < 0.0) {
                 clip += -qc[IH] * g->dx * g->dy;
                 qc[IH] = 0.0;
@@ -1094,6 +1131,20 @@ int orc_framed(orc_grid *g, double **q, double **b, unsigned char **phi,
 }
 
 void orc_set_external_ghosts(orc_grid *g, int on) { g->ext_ghosts = on ? 1 : 0; }
+
+int orc_set_sponge(orc_grid *g, const double w[4], double rate, long long i0, long long j0,
+                   long long nx_dom, long long ny_dom)
+{
+    if (!(rate >= 0.0) || !isfinite(rate) || nx_dom < 1 || ny_dom < 1 || i0 < 0 || j0 < 0 ||
+        i0 + g->nx > nx_dom || j0 + g->ny > ny_dom)
+        return ORC_EINVAL;
+    for (int e = 0; e < 4; e++)
+        if (!(w[e] >= 0.0) || !isfinite(w[e])) return ORC_EINVAL;
+    for (int e = 0; e < 4; e++) g->sp_w[e] = w[e];
+    g->sp_rate = rate;
+    g->sp_i0 = i0; g->sp_j0 = j0; g->sp_nx = nx_dom; g->sp_ny = ny_dom;
+    return ORC_OK;
+}
 
 /* phi_T of the interior cells from the bathymetry of the frame, ghost cells
  * included (the caller has filled them); clears the breaking latch */

@@ -118,6 +118,13 @@ void orc_source_cell_mb(double *q, double c2, double tau);
 int orc_framed(orc_grid *g, double **q, double **b, unsigned char **phi,
                unsigned char **brk, unsigned char **iface, int *sx, int *sy);
 void orc_set_external_ghosts(orc_grid *g, int on);
+/* sponge layer (the relaxation sponge of the Tohoku case, Sec. 6.4, cited
+ * there without a description): widths w[4] in metres from the x-low,
+ * x-high, y-low, y-high sides of the domain (0: none) and peak rate (1/s).
+ * The grid's cell (0, 0) is cell (i0, j0) of a domain of nx_dom x ny_dom
+ * cells of its spacing (a single grid: 0, 0, nx, ny). */
+int orc_set_sponge(orc_grid *g, const double w[4], double rate, long long i0, long long j0,
+                   long long nx_dom, long long ny_dom);
 int orc_update_phi_framed(orc_grid *g);
 /* boundary-edge fluxes of the last step relative to the outside cell,
  * K[2 ny + 2 nx][7] (left rows, right rows, bottom columns, top columns) */

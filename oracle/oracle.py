@@ -90,6 +90,8 @@ def lib():
                                  ctypes.POINTER(ucp), ctypes.POINTER(ucp), ctypes.POINTER(ucp),
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.orc_set_external_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_set_sponge.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_longlong,
+                                     ctypes.c_longlong, ctypes.c_longlong, ctypes.c_longlong]
         L.orc_update_phi_framed.argtypes = [ctypes.c_void_p]
         L.orc_boundary_flux.argtypes = [ctypes.c_void_p, dp]
         L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
@@ -224,6 +226,16 @@ class OracleGrid:
                 np.ctypeslib.as_array(phi, shape=(n,)).reshape(shp),
                 np.ctypeslib.as_array(brk, shape=(n,)).reshape(shp),
                 np.ctypeslib.as_array(ifc, shape=(n,)).reshape(shp))
+
+    def set_sponge(self, width, rate, offset=(0, 0), domain=None):
+        """sponge widths (m) from the x-low, x-high, y-low, y-high sides of
+        the domain and peak rate (1/s); offset: global index of cell (0, 0);
+        domain: the domain in cells of this spacing (default: this grid)"""
+        w = np.ascontiguousarray(width, dtype=np.float64)
+        assert w.shape == (4,)
+        nxd, nyd = domain if domain is not None else (self.grid.nx, self.grid.ny)
+        _check(lib().orc_set_sponge(self.h, _dp(w), float(rate), int(offset[0]), int(offset[1]),
+                                    int(nxd), int(nyd)), "set_sponge")
 
     def set_external_ghosts(self, on=True):
         lib().orc_set_external_ghosts(self.h, 1 if on else 0)

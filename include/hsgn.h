@@ -152,6 +152,20 @@ int hsgn_finalize(hsgn_ctx *c);
  * device pointer is read with a synchronous copy. */
 int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device);
 
+/* Sponge layer of a scenario (the relaxation sponge of the Tohoku case,
+ * Sec. 6.4, where it is cited without a description; this is a reading):
+ * within width[e] metres of the domain side e (0 x-low, 1 x-high, 2 y-low,
+ * 3 y-high; 0 = none) every conserved variable of a cell is relaxed towards
+ * the state at rest (h = H = (eta0 - b)^+, the others zero) once per step,
+ * after the second source half step and before the fix-ups, by the implicit
+ * Euler factor 1 / (1 + dt sigma), sigma = rate ((w - d) / w)^2 with d the
+ * distance of the cell centre from that side (the largest over the sides).
+ * The domain is the grid, or for a patch set the rectangle its level-0
+ * patches tile; every patch of the scenario follows it, and regridding
+ * keeps it.  rate = 0 removes the sponge.  After hsgn_finalize.
+ * Errors: EINVAL (no such scenario, negative or non-finite width or rate). */
+int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rate);
+
 /* State q[7][ny][nx] (float64) of a patch, copied in or out. */
 int hsgn_set_state(hsgn_ctx *c, int patch, const double *q, int on_device);
 int hsgn_get_state(hsgn_ctx *c, int patch, double *q, int on_device);

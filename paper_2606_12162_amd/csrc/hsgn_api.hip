@@ -402,6 +402,8 @@ struct ScenHost {
     std::vector<double> gauge_xy;
     long long gcap = 0, roff = 0;
     int ng = 0;
+    double sp_w[4] = {0.0, 0.0, 0.0, 0.0};  // sponge widths (m) and peak rate (1/s)
+    double sp_rate = 0.0;
 };
 
 // table ranges of one refinement level
@@ -1484,6 +1486,45 @@ static int ensure_prepared(hsgn_ctx *c)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->amr_dirty = false;
     return HSGN_OK;
+}
+
+// the sponge of scenario s into its patches' PatchInfo (host and device)
+static int apply_sponge(hsgn_ctx *c, int s)
+{
+    const ScenHost &sh = c->scen[s];
+    for (int pid : sh.patches) {
+        PatchInfo &p = c->patches[pid];
+        for (int e = 0; e < 4; e++) p.sp_w[e] = sh.sp_w[e];
+        p.sp_rate = sh.sp_rate;
+        if (sh.amr) {
+            long long f = 1;
+            for (int k = 0; k < p.level; k++) f *= AMR_RATIO;
+            p.sp_i0 = c->pI0[pid]; p.sp_j0 = c->pJ0[pid];
+            p.sp_nx = (long long)sh.NX * f; p.sp_ny = (long long)sh.NY * f;
+        } else {
+            p.sp_i0 = 0; p.sp_j0 = 0;
+            p.sp_nx = p.nx; p.sp_ny = p.ny;
+        }
+    }
+    HIPCHK(c, hipMemcpy(c->d_patches, c->patches.data(), sizeof(PatchInfo) * c->patches.size(),
+                        hipMemcpyHostToDevice));
+    return HSGN_OK;
+}
+
+int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rate)
+{
+    if (!c || !c->finalized) return fail(c, HSGN_EINVAL, "call hsgn_finalize first");
+    if (scenario < 0 || scenario >= (int)c->scen.size() || c->scen[scenario].patches.empty())
+        return fail(c, HSGN_EINVAL, "no such scenario");
+    if (!width) return fail(c, HSGN_EINVAL, "null sponge widths");
+    if (!(rate >= 0.0) || !std::isfinite(rate)) return fail(c, HSGN_EINVAL, "sponge rate");
+    for (int e = 0; e < 4; e++)
+        if (!(width[e] >= 0.0) || !std::isfinite(width[e]))
+            return fail(c, HSGN_EINVAL, "sponge width");
+    ScenHost &sh = c->scen[scenario];
+    for (int e = 0; e < 4; e++) sh.sp_w[e] = width[e];
+    sh.sp_rate = rate;
+    return apply_sponge(c, scenario);
 }
 
 int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device)
@@ -2835,6 +2876,12 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
     }
     if ((rc = hsgn_finalize(n))) return bail(rc, "regrid: finalize");
     n->timing = c->timing;
+    for (size_t s = 0; s < c->scen.size() && s < n->scen.size(); s++) {
+        if (!(c->scen[s].sp_rate > 0.0)) continue;
+        for (int e = 0; e < 4; e++) n->scen[s].sp_w[e] = c->scen[s].sp_w[e];
+        n->scen[s].sp_rate = c->scen[s].sp_rate;
+        if ((rc = apply_sponge(n, (int)s))) return bail(rc, "regrid: sponge");
+    }
     // bathymetry: level-0 and regridded patches from the level-0 bathymetry
     // B0 (on the device; at level 0 the rule returns B0 itself), patches given
     // by the caller from their host copies (one transfer)

@@ -39,7 +39,33 @@ struct PatchInfo {
     long long eoff;          // offset (in 7-vectors) of the patch's boundary-flux
                              // entries, -1 if it has none
     int level, frame;        // refinement level; 2 if ghost cells are stored
+    // sponge layer: widths (m) from the domain's x-low, x-high, y-low, y-high
+    // sides (0: none), peak rate (1/s; 0: no sponge), and the patch's place
+    // in the domain of its level (global index of interior cell (0, 0),
+    // domain size in cells)
+    double sp_w[4], sp_rate;
+    long long sp_i0, sp_j0, sp_nx, sp_ny;
 };
+
+// relaxation rate of the sponge at interior cell (i, j) of a patch: with d
+// the distance of the cell centre from a sponged side and w that side's
+// width, s = (w - d) / w inside the band; the largest s over the sides gives
+// rate s^2
+HSGN_HD inline double sponge_sigma(const PatchInfo &pi, int i, int j)
+{
+    const long long I = pi.sp_i0 + i, J = pi.sp_j0 + j;
+    const double d[4] = {((double)I + 0.5) * pi.dx, ((double)(pi.sp_nx - 1 - I) + 0.5) * pi.dx,
+                         ((double)J + 0.5) * pi.dy, ((double)(pi.sp_ny - 1 - J) + 0.5) * pi.dy};
+    double s = 0.0;
+    for (int e = 0; e < 4; e++) {
+        const double w = pi.sp_w[e];
+        if (w > 0.0 && d[e] < w) {
+            const double t = (w - d[e]) / w;
+            if (t > s) s = t;
+        }
+    }
+    return pi.sp_rate * (s * s);
+}
 
 // mask byte bits: phi_T, breaking latch, and the four edges of a cell whose
 // contributions a finer patch replaces (patch sets)
@@ -511,6 +537,27 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                                          : acc[sk2][m];
             qn[IH] = depth_of<T, MIXED>(P, acc[sk2][IH], bb);
             source_or_clear(P, qn, c2, swe, tau_post);
+            // sponge: every variable relaxed towards the state at rest by an
+            // implicit Euler step (FP64: h towards H; mixed precision: eta'
+            // towards its rest value (b - eta0)^+)
+            if (pi.sp_rate > 0.0) {                     // uniform over the wavefront
+                const double sg = sponge_sigma(pi, wk.i0 - 2 + lane, k - 2);
+                if (sg > 0.0) {
+                    const double f = 1.0 / (1.0 + dtd * sg);
+                    if constexpr (MIXED) {
+                        const T fT = (T)f;
+                        const T er = tmax((T)0, bb - (T)P.eta0);
+                        acc[sk2][IH] = er + (acc[sk2][IH] - er) * fT;
+                        HSGN_UNROLL
+                        for (int m = 1; m < 7; m++) qn[m] = qn[m] * fT;
+                    } else {
+                        const double H = still_depth(P, (double)bb);
+                        acc[sk2][IH] = (T)(H + ((double)acc[sk2][IH] - H) * f);
+                        HSGN_UNROLL
+                        for (int m = 1; m < 7; m++) qn[m] = (T)((double)qn[m] * f);
+                    }
+                }
+            }
             // fix-ups: clipping (the clipped mass summed in FP64), dry cells,
             // breaking latch (eta - eta0 > kappa H), SWE cells.  FP64: on h
             // as the oracle does; mixed precision: in FP32 on the stored

@@ -25,7 +25,7 @@ EXPORTS = ("hsgn_create", "hsgn_add_grid", "hsgn_finalize", "hsgn_set_bathymetry
            "hsgn_set_gauges", "hsgn_read_gauges", "hsgn_advance", "hsgn_diagnostics",
            "hsgn_get_clock", "hsgn_set_clock", "hsgn_work_items", "hsgn_set_timing",
            "hsgn_get_timing", "hsgn_autotune", "hsgn_regrid", "hsgn_num_patches",
-           "hsgn_patch_info", "hsgn_destroy", "hsgn_strerror",
+           "hsgn_patch_info", "hsgn_set_sponge", "hsgn_destroy", "hsgn_strerror",
            "hsgn_last_error")
 
 
@@ -89,6 +89,7 @@ def lib():
         L.hsgn_set_timing.argtypes = [vp, ctypes.c_int]
         L.hsgn_get_timing.argtypes = [vp, dp, dp]
         L.hsgn_regrid.argtypes = [vp, ctypes.c_int, ctypes.POINTER(hsgn_regrid_params), ip]
+        L.hsgn_set_sponge.argtypes = [vp, ctypes.c_int, dp, ctypes.c_double]
         L.hsgn_num_patches.argtypes = [vp, ip]
         L.hsgn_patch_info.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip, dp, dp, dp, dp]
         L.hsgn_destroy.argtypes = [vp]
@@ -201,6 +202,15 @@ class Context:
         m = np.ascontiguousarray(m, dtype=np.uint8)
         p, dev = _ptr(m)
         self._check(lib().hsgn_set_mask(self.h, patch, p, dev), "hsgn_set_mask")
+
+    def set_sponge(self, scenario, width, rate):
+        """sponge widths (m) from the x-low, x-high, y-low, y-high sides of
+        the scenario's domain and peak rate (1/s); rate 0 removes it"""
+        w = np.ascontiguousarray(width, dtype=np.float64)
+        if w.shape != (4,):
+            raise ValueError("four widths")
+        self._check(lib().hsgn_set_sponge(self.h, int(scenario), ctypes.c_void_p(w.ctypes.data),
+                                          float(rate)), "hsgn_set_sponge")
 
     def set_gauges(self, scenario, xy):
         xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)

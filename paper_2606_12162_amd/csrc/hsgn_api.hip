@@ -474,6 +474,7 @@ struct hsgn_ctx {
     int *d_clsb = nullptr;      // their bottom part
     bool clsb_dirty = true;     // d_clsb to recompute (bathymetry or work table changed)
     bool split = false;         // mixed single grids: deep items without the FP64 edges
+    bool any_sponge = false;    // some scenario has a sponge (step kernels with it)
     ScenState *d_scen = nullptr;
     ScenStatic *d_sstat = nullptr;
     GaugeDev *d_gauges = nullptr;
@@ -586,6 +587,7 @@ static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath, int w0,
     A.list = nullptr;
     A.lcnt = nullptr;
     A.clsb = nullptr;
+    A.sponge = c->any_sponge ? 1 : 0;
     A.nwork = w1 - w0;
     return A;
 }
@@ -1524,6 +1526,10 @@ int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rat
     ScenHost &sh = c->scen[scenario];
     for (int e = 0; e < 4; e++) sh.sp_w[e] = width[e];
     sh.sp_rate = rate;
+    const bool before = c->any_sponge;
+    c->any_sponge = false;
+    for (const ScenHost &x : c->scen) c->any_sponge = c->any_sponge || x.sp_rate > 0.0;
+    if (c->any_sponge != before) drop_graph(c);     // the graph holds the other kernels
     return apply_sponge(c, scenario);
 }
 
@@ -2880,6 +2886,7 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
         if (!(c->scen[s].sp_rate > 0.0)) continue;
         for (int e = 0; e < 4; e++) n->scen[s].sp_w[e] = c->scen[s].sp_w[e];
         n->scen[s].sp_rate = c->scen[s].sp_rate;
+        n->any_sponge = true;
         if ((rc = apply_sponge(n, (int)s))) return bail(rc, "regrid: sponge");
     }
     // bathymetry: level-0 and regridded patches from the level-0 bathymetry

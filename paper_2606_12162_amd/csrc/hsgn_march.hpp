@@ -113,6 +113,7 @@ struct MarchArgs {
     int *list;
     unsigned *lcnt;
     const int *clsb;
+    int sponge;              // some patch has a sponge: the kernels compiled with it
     int nwork;
 };
 
@@ -278,7 +279,7 @@ HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Sid
 //   left  A-dQ + F~ + F~tr,   right -(A+dQ - F~) + F~tr,
 //   below B-dQ + G~ + G~tr,   above -(B+dQ - G~) + G~tr
 // at entries j, ny + j, 2 ny + i, 2 ny + nx + i of the patch.
-template <class L, class S, class T, bool MIXED, bool AMR, bool FB = true>
+template <class L, class S, class T, bool MIXED, bool AMR, bool FB = true, bool SP = false>
 HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 {
     const WorkItem wk = A.work[wid];
@@ -540,7 +541,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             // sponge: every variable relaxed towards the state at rest by an
             // implicit Euler step (FP64: h towards H; mixed precision: eta'
             // towards its rest value (b - eta0)^+)
-            if (pi.sp_rate > 0.0) {                     // uniform over the wavefront
+            if (SP && pi.sp_rate > 0.0) {               // uniform over the wavefront
                 const double sg = sponge_sigma(pi, wk.i0 - 2 + lane, k - 2);
                 if (sg > 0.0) {
                     const double f = 1.0 / (1.0 + dtd * sg);

@@ -68,7 +68,10 @@ struct GpuLanes {
 // entry; FB true the others, block b taking entries b, b + grid, ... in turn
 // (launched on fewer blocks than the work table has items when it runs
 // beside the other kernel).
-template <class S, class T, bool MIXED, bool AMR, bool FB = true>
+//
+// SP: compiled with the sponge relaxation (launched when some patch has a
+// sponge; the kernels without it keep their registers).
+template <class S, class T, bool MIXED, bool AMR, bool FB = true, bool SP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
 void march_kernel(MarchArgs<S> A)
 {
@@ -78,7 +81,7 @@ void march_kernel(MarchArgs<S> A)
         const unsigned n = A.list ? A.lcnt[1] : (unsigned)A.nwork;
         for (unsigned b = blockIdx.x; b < n; b += gridDim.x) {     // uniform over the wavefront
             const int wid = A.list ? A.list[A.nwork + (int)b] : (int)b;
-            march<GpuLanes<T>, S, T, MIXED, AMR, FB>(ln, A, wid);
+            march<GpuLanes<T>, S, T, MIXED, AMR, FB, SP>(ln, A, wid);
         }
     } else {
         int wid = (int)blockIdx.x;
@@ -87,7 +90,7 @@ void march_kernel(MarchArgs<S> A)
             if ((unsigned)wid >= A.lcnt[0]) return;
             wid = A.list[wid];
         }
-        march<GpuLanes<T>, S, T, MIXED, AMR, FB>(ln, A, wid);
+        march<GpuLanes<T>, S, T, MIXED, AMR, FB, SP>(ln, A, wid);
     }
 }
 

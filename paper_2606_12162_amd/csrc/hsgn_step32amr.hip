@@ -14,13 +14,15 @@ constexpr unsigned FB_BLOCKS_AMR = 1024;
 void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream, bool beside)
 {
     const unsigned grid = A.list && beside && nwork > FB_BLOCKS_AMR ? FB_BLOCKS_AMR : nwork;
-    march_kernel<float, float, true, true, true><<<grid, 64, 0, stream>>>(A);
+    if (A.sponge) march_kernel<float, float, true, true, true, true><<<grid, 64, 0, stream>>>(A);
+    else march_kernel<float, float, true, true, true, false><<<grid, 64, 0, stream>>>(A);
 }
 
 // the kernel without the FP64 edge solve, over the other list
 void launch_march32_amr_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
 {
-    march_kernel<float, float, true, true, false><<<nwork, 64, 0, stream>>>(A);
+    if (A.sponge) march_kernel<float, float, true, true, false, true><<<nwork, 64, 0, stream>>>(A);
+    else march_kernel<float, float, true, true, false, false><<<nwork, 64, 0, stream>>>(A);
 }
 
 // the item lists from the attempt's input mask, ghost frames included

@@ -7,5 +7,6 @@ using namespace hsgn;
 
 void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream)
 {
-    march_kernel<double, double, false, false><<<nwork, 64, 0, stream>>>(A);
+    if (A.sponge) march_kernel<double, double, false, false, true, true><<<nwork, 64, 0, stream>>>(A);
+    else march_kernel<double, double, false, false, true, false><<<nwork, 64, 0, stream>>>(A);
 }

@@ -7,5 +7,6 @@ using namespace hsgn;
 
 void launch_march64_amr(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream)
 {
-    march_kernel<double, double, false, true><<<nwork, 64, 0, stream>>>(A);
+    if (A.sponge) march_kernel<double, double, false, true, true, true><<<nwork, 64, 0, stream>>>(A);
+    else march_kernel<double, double, false, true, true, false><<<nwork, 64, 0, stream>>>(A);
 }

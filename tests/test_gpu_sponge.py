@@ -116,3 +116,22 @@ def test_bad_sponges_are_refused():
             ctx.set_sponge(scen, widths, rate)
         assert e.value.code == H.HSGN_EINVAL
     ctx.close()
+
+
+def test_split_step_with_a_sponge_is_bitwise_the_full_kernel(monkeypatch):
+    """mixed precision with a sponge (the step-kernel instances compiled
+    with it): the split step gives the bits of the full kernel, on an ocean
+    with deep plain, shelf and dry coast and sponges on its open sides"""
+    w = W.synthetic_ocean(n=512, dx=2000.0, steps=60)
+    L = 512 * 2000.0
+    runs = []
+    for nosplit in ("0", "1"):
+        monkeypatch.setenv("HSGN_NO_KERNEL_SPLIT", nosplit)
+        print("case", w.name, "sponge, no_split", nosplit, flush=True)
+        ctx = H.from_workloads([w], precision=1)
+        ctx.set_sponge(0, (0.1 * L, 0.0, 0.08 * L, 0.08 * L), 0.01)
+        ctx.advance(w.dt, 60)
+        runs.append((ctx.get_state(0), ctx.get_mask(0), ctx.read_gauges(0)[1]))
+        ctx.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)

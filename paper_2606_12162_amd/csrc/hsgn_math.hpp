@@ -90,9 +90,31 @@ struct Eig {
 template <class T>
 HSGN_HD T tmax(T a, T b) { return a > b ? a : b; }
 
-// reciprocal used where one denominator serves several quotients
-template <class T>
-HSGN_HD T recip(T x) { return (T)1 / x; }
+// reciprocal used where one denominator serves several quotients, square
+// root and quotient: FP64 the IEEE operations; FP32 on the device the bare
+// hardware instructions (about 1 ulp).  The default FP32 lowering wraps them
+// in range scaling for denormal arguments, four or five instructions more
+// each, which changes no result for the normal arguments the step passes.
+HSGN_HD double recip(double x) { return 1.0 / x; }
+HSGN_HD double tsqrt(double x) { return sqrt(x); }
+HSGN_HD double tdiv(double a, double b) { return a / b; }
+HSGN_HD float recip(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+HSGN_HD float tsqrt(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+HSGN_HD float tdiv(float a, float b) { return a * recip(b); }
 
 // quotient a / b given inv = 1 / b: FP64 divides (same rounding as a plain
 // division; the flux differences that follow cancel strongly, so their
@@ -256,7 +278,7 @@ template <class T>
 HSGN_HD void derive(const StepParams &P, Cell<T> &c)
 {
     c.h = c.q[IH] > (T)0 ? c.q[IH] : (T)0;
-    c.sq = sqrt(c.h);
+    c.sq = tsqrt(c.h);
     c.wet = c.q[IH] > (T)P.dry_tol;
     c.hyp = 1;
     c.ce = (T)0;
@@ -268,7 +290,7 @@ HSGN_HD void derive(const StepParams &P, Cell<T> &c)
         c.p = c.q[IHP] * ih; c.pb = c.q[IHPB] * ih;
         T a = (T)P.g * c.h + c.p + c.c2;
         c.hyp = a >= (T)0;
-        c.ce = sqrt(a > (T)0 ? a : (T)0);
+        c.ce = tsqrt(a > (T)0 ? a : (T)0);
     } else {
         c.u = c.v = c.w = c.s = c.p = c.pb = (T)0;
     }
@@ -282,10 +304,11 @@ HSGN_HD T sensor(const StepParams &P, T bL, T bR)
     if (db == (T)0) return (T)1;
     T sum = fabs(bR + bL);
     if (sum == (T)0) return (T)0;
-    T xi = (T)2 * fabs(db) / sum;
+    const T num = (T)2 * fabs(db);
+    T xi = tdiv(num, sum);
     if (xi < (T)P.xi0) return (T)1;
     if (xi < (T)(P.xi0 + P.xi1)) {
-        T r = (xi - (T)P.xi0) / (T)P.xi1;
+        T r = tdiv(xi - (T)P.xi0, (T)P.xi1);
         return (T)-3 * r * r + (T)2 * r * r * r + (T)1;
     }
     return (T)0;
@@ -405,9 +428,9 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
 
     T ce2 = g * hh + ph + c2h;
     ok = ce2 > (T)0;
-    T ceh = sqrt(ce2);
+    T ceh = tsqrt(ce2);
     T ice2 = recip(ce2);
-    T sg = sqrt(g);
+    T sg = tsqrt(g);
     T smin, smax;
     if (dryL) {
         smin = R.un - (T)2 * front_root(g, R.h, sg, R.sq);

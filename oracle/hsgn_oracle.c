@@ -23,6 +23,11 @@
  *              H phi_T; cells with phi_T = 0, dry cells and cells latched as
  *              breaking carry no auxiliary variables.
  *   CFL        Sec. 4: global maximum wave speed.
+ *   mapped     Sec. 4 (mapped grids, after the cited wave-propagation
+ *              treatment of quadrilateral grids): Riemann problems in the
+ *              frame of each edge's normal, waves, speeds and fluctuations
+ *              scaled by the edge's length ratio, updates divided by the
+ *              cell's capacity (area ratio).
  *
  * Readings of points the paper leaves open (c^2 = alpha^2 g H; 2D form;
  * wet/dry states; breaking latch; transverse construction; s = 0 split) are
@@ -57,6 +62,12 @@ struct orc_grid {
      * domain (global index of cell (0, 0), domain size in cells) */
     double sp_w[4], sp_rate;
     long long sp_i0, sp_j0, sp_nx, sp_ny;
+    /* mapped grid (planar, logically rectangular; NULL on Cartesian grids),
+     * [sy][sx] like the cells: kap the cell's capacity (area over dx dy);
+     * xn*, xgm the unit normal (towards increasing i) and length ratio
+     * (length over dy) of the cell's left edge; yn*, ygm the same for its
+     * bottom edge (towards increasing j, length over dx) */
+    double *kap, *xnx, *xny, *xgm, *ynx, *yny, *ygm;
     double t, dt_next;
     long long nstep, nrej;
     int have_dt;
@@ -92,6 +103,15 @@ static int map_index(int i, int n, int lo, int hi, int *flip)
     return i;
 }
 
+/* m - 2 (m . n) n: the momentum (hu, hv) mirrored about a wall of unit
+ * normal n */
+static void reflect(double *hu, double *hv, double nx, double ny)
+{
+    double a = *hu * nx + *hv * ny;
+    *hu = *hu - 2.0 * a * nx;
+    *hv = *hv - 2.0 * a * ny;
+}
+
 /* fill the two ghost layers of q, b, phi and the latch from the interior */
 static void fill_ghosts(orc_grid *g)
 {
@@ -104,8 +124,21 @@ static void fill_ghosts(orc_grid *g)
             int mj = map_index(j, g->ny, g->bc[2], g->bc[3], &fy);
             size_t d = CELL(g, i, j), s = CELL(g, mi, mj);
             for (int m = 0; m < ORC_NV; m++) g->q[m * np + d] = g->q[m * np + s];
-            if (fx) g->q[IHU * np + d] = -g->q[IHU * np + d];
-            if (fy) g->q[IHV * np + d] = -g->q[IHV * np + d];
+            if (g->kap) {
+                /* mapped grid: the momentum is mirrored about the wall edge
+                 * of the interior cell's row (column) */
+                if (fx) {
+                    size_t e = CELL(g, i < 0 ? 0 : g->nx, mj);
+                    reflect(&g->q[IHU * np + d], &g->q[IHV * np + d], g->xnx[e], g->xny[e]);
+                }
+                if (fy) {
+                    size_t e = CELL(g, mi, j < 0 ? 0 : g->ny);
+                    reflect(&g->q[IHU * np + d], &g->q[IHV * np + d], g->ynx[e], g->yny[e]);
+                }
+            } else {
+                if (fx) g->q[IHU * np + d] = -g->q[IHU * np + d];
+                if (fy) g->q[IHV * np + d] = -g->q[IHV * np + d];
+            }
             g->b[d] = g->b[s];
             g->phi[d] = g->phi[s];
             g->brk[d] = g->brk[s];
@@ -162,6 +195,8 @@ void orc_destroy(orc_grid *g)
     free(g->gxy); free(g->rec_t); free(g->rec_eta);
     free(g->w_qs); free(g->w_c2); free(g->w_Flim); free(g->w_Ftr);
     free(g->w_Glim); free(g->w_Gtr); free(g->w_clip); free(g->w_EX); free(g->w_EY);
+    free(g->kap); free(g->xnx); free(g->xny); free(g->xgm);
+    free(g->ynx); free(g->yny); free(g->ygm);
     free(g);
 }
 
@@ -601,6 +636,48 @@ static int riemann_y(const orc_params *P, const double *qL, const double *qR,
     return rc;
 }
 
+/* mapped grids.  The frame of an edge is its unit normal n and a unit
+ * tangent t: t = (-n_y, n_x) at left (x) edges, t = (n_y, -n_x) at bottom
+ * (y) edges, so that an axis-aligned grid has the frames of the Cartesian
+ * solves (identity at x-edges, the hu/hv swap at y-edges). */
+static void to_frame(double *v, double nx, double ny, double tx, double ty)
+{
+    double hn = v[IHU] * nx + v[IHV] * ny;
+    double ht = v[IHU] * tx + v[IHV] * ty;
+    v[IHU] = hn; v[IHV] = ht;
+}
+
+static void from_frame(double *v, double nx, double ny, double tx, double ty)
+{
+    double hu = v[IHU] * nx + v[IHV] * tx;
+    double hv = v[IHU] * ny + v[IHV] * ty;
+    v[IHU] = hu; v[IHV] = hv;
+}
+
+/* solve at a mapped edge: rotated data, the normal solve, then waves and
+ * fluctuations rotated back to the global frame and, with the speeds,
+ * scaled by the edge's length ratio gm.  The Roe state (E->e) stays in the
+ * edge's frame, unscaled, for the transverse splits. */
+static int riemann_mapped(const orc_params *P, const double *qL, const double *qR,
+                          double bL, double bR, double c2L, double c2R, double nx, double ny,
+                          double tx, double ty, double gm, edge_t *E)
+{
+    double a[7], c[7];
+    memcpy(a, qL, sizeof(a)); memcpy(c, qR, sizeof(c));
+    to_frame(a, nx, ny, tx, ty);
+    to_frame(c, nx, ny, tx, ty);
+    int rc = riemann_n(P, a, c, bL, bR, c2L, c2R, E);
+    for (int p = 0; p < 7; p++) {
+        from_frame(E->Z[p], nx, ny, tx, ty);
+        for (int m = 0; m < 7; m++) E->Z[p][m] *= gm;
+        E->s[p] *= gm;
+    }
+    from_frame(E->amdq, nx, ny, tx, ty);
+    from_frame(E->apdq, nx, ny, tx, ty);
+    for (int m = 0; m < 7; m++) { E->amdq[m] *= gm; E->apdq[m] *= gm; }
+    return rc;
+}
+
 int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
                   double bL, double bR, double c2L, double c2R,
                   double *waves, double *speeds, double *amdq, double *apdq,
@@ -655,6 +732,18 @@ static void split_by_y(const orc_params *P, const eig_t *e, const double *a,
     swap_uv(t);
     trans_split(P, e, t, sgn, out);
     swap_uv(out);
+}
+
+/* fluctuation a (global frame) split by a mapped edge with frame (n, t):
+ * rotated into the frame, split by the edge's Roe state, rotated back */
+static void split_mapped(const orc_params *P, const eig_t *e, const double *a, int sgn,
+                         double nx, double ny, double tx, double ty, double *out)
+{
+    double t[7];
+    memcpy(t, a, sizeof(t));
+    to_frame(t, nx, ny, tx, ty);
+    trans_split(P, e, t, sgn, out);
+    from_frame(out, nx, ny, tx, ty);
 }
 
 /* ------------------------------------------------------------------ */
@@ -761,7 +850,10 @@ int orc_step(orc_grid *g, double dt, double *courant)
             size_t kl = CELL(g, i - 1, j), kr = CELL(g, i, j);
             double ql[7], qr[7];
             for (int m = 0; m < 7; m++) { ql[m] = qs[m * np + kl]; qr[m] = qs[m * np + kr]; }
-            int r = riemann_n(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr], &EX[XE(i, j)]);
+            int r = g->kap ? riemann_mapped(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr],
+                                            g->xnx[kr], g->xny[kr], 0.0 - g->xny[kr], g->xnx[kr],
+                                            g->xgm[kr], &EX[XE(i, j)])
+                           : riemann_n(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr], &EX[XE(i, j)]);
             if (r < rc) rc = r;
         }
     }
@@ -773,24 +865,34 @@ int orc_step(orc_grid *g, double dt, double *courant)
             size_t kl = CELL(g, i, j - 1), kr = CELL(g, i, j);
             double ql[7], qr[7];
             for (int m = 0; m < 7; m++) { ql[m] = qs[m * np + kl]; qr[m] = qs[m * np + kr]; }
-            int r = riemann_y(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr], &EY[YE(i, j)]);
+            int r = g->kap ? riemann_mapped(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr],
+                                            g->ynx[kr], g->yny[kr], g->yny[kr], 0.0 - g->ynx[kr],
+                                            g->ygm[kr], &EY[YE(i, j)])
+                           : riemann_y(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr], &EY[YE(i, j)]);
             if (r < rc) rc = r;
         }
     }
     if (rc != ORC_OK) return rc;
 
     /* 4. limited corrections at the x-edges i = 0..nx of rows -1..ny and the
-     *    y-edges j = 0..ny of columns -1..nx */
+     *    y-edges j = 0..ny of columns -1..nx; on a mapped grid the factor
+     *    dt/dx is the mean of dt/(kap dx) of the edge's two cells */
 #pragma omp parallel for schedule(static)
     for (int j = -1; j <= ny; j++)
-        for (int i = 0; i <= nx; i++)
-            correction(P->limiter, dtdx, &EX[XE(i - 1, j)], &EX[XE(i, j)],
+        for (int i = 0; i <= nx; i++) {
+            double f = g->kap ? 0.5 * (dtdx / g->kap[CELL(g, i - 1, j)] + dtdx / g->kap[CELL(g, i, j)])
+                              : dtdx;
+            correction(P->limiter, f, &EX[XE(i - 1, j)], &EX[XE(i, j)],
                        &EX[XE(i + 1, j)], &Flim[XE(i, j) * 7]);
+        }
 #pragma omp parallel for schedule(static)
     for (int j = 0; j <= ny; j++)
-        for (int i = -1; i <= nx; i++)
-            correction(P->limiter, dtdy, &EY[YE(i, j - 1)], &EY[YE(i, j)],
+        for (int i = -1; i <= nx; i++) {
+            double f = g->kap ? 0.5 * (dtdy / g->kap[CELL(g, i, j - 1)] + dtdy / g->kap[CELL(g, i, j)])
+                              : dtdy;
+            correction(P->limiter, f, &EY[YE(i, j - 1)], &EY[YE(i, j)],
                        &EY[YE(i, j + 1)], &Glim[YE(i, j) * 7]);
+        }
 
     /* 5. transverse propagation.  The fluctuation an edge sends into a
      *    cell, including its limited correction (A+ - F~ to the right cell,
@@ -835,6 +937,18 @@ int orc_step(orc_grid *g, double dt, double *courant)
                 const edge_t *ye = &EY[YE(i, j)];
                 if (!ye->e.wet) continue;
                 double vp[7], vm[7];
+                if (g->kap) {
+                    /* mapped: split in the edge's frame; each part weighted
+                     * by the edge's length ratio over the capacity of the
+                     * cell it entered */
+                    const size_t ke = CELL(g, i, j), kb = CELL(g, i, j - 1);
+                    const double nx_ = g->ynx[ke], ny_ = g->yny[ke];
+                    split_mapped(P, &ye->e, &Xin[XI(i, j - 1)], 1, nx_, ny_, ny_, 0.0 - nx_, vp);
+                    split_mapped(P, &ye->e, &Xin[XI(i, j)], -1, nx_, ny_, ny_, 0.0 - nx_, vm);
+                    const double wa = g->ygm[ke] / g->kap[kb], wb = g->ygm[ke] / g->kap[ke];
+                    for (int m = 0; m < 7; m++) Gtr[YE(i, j) * 7 + m] = cx * (wa * vp[m] + wb * vm[m]);
+                    continue;
+                }
                 split_by_y(P, &ye->e, &Xin[XI(i, j - 1)], 1, vp);
                 split_by_y(P, &ye->e, &Xin[XI(i, j)], -1, vm);
                 for (int m = 0; m < 7; m++) Gtr[YE(i, j) * 7 + m] = cx * (vp[m] + vm[m]);
@@ -847,6 +961,15 @@ int orc_step(orc_grid *g, double dt, double *courant)
                 const edge_t *xe = &EX[XE(i, j)];
                 if (!xe->e.wet) continue;
                 double vp[7], vm[7];
+                if (g->kap) {
+                    const size_t ke = CELL(g, i, j), kl = CELL(g, i - 1, j);
+                    const double nx_ = g->xnx[ke], ny_ = g->xny[ke];
+                    split_mapped(P, &xe->e, &Yin[YI(i - 1, j)], 1, nx_, ny_, 0.0 - ny_, nx_, vp);
+                    split_mapped(P, &xe->e, &Yin[YI(i, j)], -1, nx_, ny_, 0.0 - ny_, nx_, vm);
+                    const double wa = g->xgm[ke] / g->kap[kl], wb = g->xgm[ke] / g->kap[ke];
+                    for (int m = 0; m < 7; m++) Ftr[XE(i, j) * 7 + m] = cy * (wa * vp[m] + wb * vm[m]);
+                    continue;
+                }
                 trans_split(P, &xe->e, &Yin[YI(i - 1, j)], 1, vp);
                 trans_split(P, &xe->e, &Yin[YI(i, j)], -1, vm);
                 for (int m = 0; m < 7; m++) Ftr[XE(i, j) * 7 + m] = cy * (vp[m] + vm[m]);
@@ -876,6 +999,9 @@ int orc_step(orc_grid *g, double dt, double *courant)
              * with a finer patch are left out here; the finer patch's
              * fluxes replace them after its substeps (refluxing) */
             const int fl = g->iface[k];
+            /* mapped grids: dt/dx and dt/dy over the cell's capacity */
+            const double ddx = g->kap ? dtdx / g->kap[k] : dtdx;
+            const double ddy = g->kap ? dtdy / g->kap[k] : dtdy;
             double qc[7];
             for (int m = 0; m < 7; m++) {
                 double xl_n = (fl & 1) ? 0.0 : EX[xl].apdq[m] - Flim[xl * 7 + m];
@@ -887,12 +1013,12 @@ int orc_step(orc_grid *g, double dt, double *courant)
                 double xr_t = (fl & 2) ? 0.0 : Ftr[xr * 7 + m];
                 double xl_t = (fl & 1) ? 0.0 : Ftr[xl * 7 + m];
                 double v = qs[m * np + k];
-                v -= dtdx * (xl_n + xr_n);
-                v += dtdy * yb_t;
-                v -= dtdy * yb_n;
-                v -= dtdy * yt_t;
-                v -= dtdy * yt_n;
-                v -= dtdx * (xr_t - xl_t);
+                v -= ddx * (xl_n + xr_n);
+                v += ddy * yb_t;
+                v -= ddy * yb_n;
+                v -= ddy * yt_t;
+                v -= ddy * yt_n;
+                v -= ddx * (xr_t - xl_t);
                 qc[m] = v;
             }
             source_or_clear(g, k, P->splitting ? 0.5 * dt : dt, qc);
@@ -908,7 +1034,7 @@ int orc_step(orc_grid *g, double dt, double *courant)
                 }
             }
             if (qc[IH] < 0.0) {
-                clip += -qc[IH] * g->dx * g->dy;
+                clip += -qc[IH] * (g->kap ? g->kap[k] : 1.0) * g->dx * g->dy;
                 qc[IH] = 0.0;
             }
             if (qc[IH] <= P->dry_tol) {
@@ -929,15 +1055,21 @@ int orc_step(orc_grid *g, double dt, double *courant)
     }
     for (int j = 0; j < ny; j++) g->clipped += g->w_clip[j];
 
-    /* 9. Courant number from the speeds of the edges of interior cells */
+    /* 9. Courant number from the speeds of the edges of interior cells (on a
+     *    mapped grid the scaled speeds over the smaller capacity of the
+     *    edge's two cells) */
     {
         double rx = 0.0, ry = 0.0;
         for (int j = 0; j < ny; j++)
-            for (int i = 0; i <= nx; i++)
-                for (int p = 0; p < 7; p++) rx = fmax(rx, fabs(EX[XE(i, j)].s[p]));
+            for (int i = 0; i <= nx; i++) {
+                double kk = g->kap ? fmin(g->kap[CELL(g, i - 1, j)], g->kap[CELL(g, i, j)]) : 1.0;
+                for (int p = 0; p < 7; p++) rx = fmax(rx, fabs(EX[XE(i, j)].s[p]) / kk);
+            }
         for (int j = 0; j <= ny; j++)
-            for (int i = 0; i < nx; i++)
-                for (int p = 0; p < 7; p++) ry = fmax(ry, fabs(EY[YE(i, j)].s[p]));
+            for (int i = 0; i < nx; i++) {
+                double kk = g->kap ? fmin(g->kap[CELL(g, i, j - 1)], g->kap[CELL(g, i, j)]) : 1.0;
+                for (int p = 0; p < 7; p++) ry = fmax(ry, fabs(EY[YE(i, j)].s[p]) / kk);
+            }
         *courant = fmax(dt * rx / g->dx, dt * ry / g->dy);
     }
 #undef XE
@@ -1112,7 +1244,8 @@ double orc_mass(const orc_grid *g)
     size_t np = PLANE(g);
     double s = 0.0;
     for (int j = 0; j < g->ny; j++)
-        for (int i = 0; i < g->nx; i++) s += g->q[IH * np + CELL(g, i, j)];
+        for (int i = 0; i < g->nx; i++)
+            s += g->q[IH * np + CELL(g, i, j)] * (g->kap ? g->kap[CELL(g, i, j)] : 1.0);
     return s * g->dx * g->dy;
 }
 
@@ -1143,6 +1276,52 @@ int orc_set_sponge(orc_grid *g, const double w[4], double rate, long long i0, lo
     for (int e = 0; e < 4; e++) g->sp_w[e] = w[e];
     g->sp_rate = rate;
     g->sp_i0 = i0; g->sp_j0 = j0; g->sp_nx = nx_dom; g->sp_ny = ny_dom;
+    return ORC_OK;
+}
+
+int orc_set_mapping(orc_grid *g, const double *xn, const double *yn)
+{
+    if (g->ext_ghosts || !xn || !yn) return ORC_EINVAL;
+    const int W = g->nx + 5;
+    const size_t np = PLANE(g);
+    double *a[7];
+    for (int m = 0; m < 7; m++) {
+        a[m] = (double *)malloc(np * sizeof(double));
+        if (!a[m]) { for (int k = 0; k <= m; k++) free(a[k]); return ORC_ENOMEM; }
+    }
+#define NX(i, j) xn[(size_t)((j) + 2) * W + (size_t)((i) + 2)]
+#define NY(i, j) yn[(size_t)((j) + 2) * W + (size_t)((i) + 2)]
+    int bad = 0;
+    for (int j = -2; j < g->ny + 2; j++) {
+        for (int i = -2; i < g->nx + 2; i++) {
+            const size_t k = CELL(g, i, j);
+            /* area from the cross product of the diagonals (counter-clockwise
+             * corners (i, j), (i+1, j), (i+1, j+1), (i, j+1)) */
+            double area = 0.5 * ((NX(i + 1, j + 1) - NX(i, j)) * (NY(i, j + 1) - NY(i + 1, j))
+                               - (NX(i, j + 1) - NX(i + 1, j)) * (NY(i + 1, j + 1) - NY(i, j)));
+            /* left edge (i, j) -> (i, j+1), normal towards increasing i */
+            double ex = NX(i, j + 1) - NX(i, j), ey = NY(i, j + 1) - NY(i, j);
+            double L = sqrt(ex * ex + ey * ey);
+            a[0][k] = area / (g->dx * g->dy);
+            a[1][k] = ey / L;
+            a[2][k] = (0.0 - ex) / L;   /* +0 for an axis-aligned edge */
+            a[3][k] = L / g->dy;
+            /* bottom edge (i, j) -> (i+1, j), normal towards increasing j */
+            double fx = NX(i + 1, j) - NX(i, j), fy = NY(i + 1, j) - NY(i, j);
+            double M = sqrt(fx * fx + fy * fy);
+            a[4][k] = (0.0 - fy) / M;
+            a[5][k] = fx / M;
+            a[6][k] = M / g->dx;
+            if (!(area > 0.0) || !(L > 0.0) || !(M > 0.0) || !isfinite(area)) bad = 1;
+        }
+    }
+#undef NX
+#undef NY
+    if (bad) { for (int m = 0; m < 7; m++) free(a[m]); return ORC_EINVAL; }
+    free(g->kap); free(g->xnx); free(g->xny); free(g->xgm);
+    free(g->ynx); free(g->yny); free(g->ygm);
+    g->kap = a[0]; g->xnx = a[1]; g->xny = a[2]; g->xgm = a[3];
+    g->ynx = a[4]; g->yny = a[5]; g->ygm = a[6];
     return ORC_OK;
 }
 

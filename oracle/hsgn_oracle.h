@@ -126,6 +126,16 @@ void orc_set_external_ghosts(orc_grid *g, int on);
 int orc_set_sponge(orc_grid *g, const double w[4], double rate, long long i0, long long j0,
                    long long nx_dom, long long ny_dom);
 int orc_update_phi_framed(orc_grid *g);
+/* mapped grid (Sec. 4, mapped grids): node coordinates xn, yn of a planar
+ * logically rectangular grid, [ny + 5][nx + 5], node (i, j) for i = -2..nx+2
+ * and j = -2..ny+2 at [j + 2][i + 2] (the two ghost layers included); cell
+ * (i, j) has corners (i, j), (i+1, j), (i+1, j+1), (i, j+1) counter-clockwise.
+ * The grid's dx and dy become the computational spacings: capacities are
+ * areas over dx dy, edge length ratios lengths over dy (left edges) and dx
+ * (bottom edges).  Momenta are in the physical frame; walls mirror them about
+ * the wall edge.  Refused (ORC_EINVAL) on patch-set grids and for a cell of
+ * non-positive area or an edge of zero length. */
+int orc_set_mapping(orc_grid *g, const double *xn, const double *yn);
 /* boundary-edge fluxes of the last step relative to the outside cell,
  * K[2 ny + 2 nx][7] (left rows, right rows, bottom columns, top columns) */
 int orc_boundary_flux(const orc_grid *g, double *K);

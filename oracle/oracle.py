@@ -93,6 +93,7 @@ def lib():
         L.orc_set_sponge.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_longlong,
                                      ctypes.c_longlong, ctypes.c_longlong, ctypes.c_longlong]
         L.orc_update_phi_framed.argtypes = [ctypes.c_void_p]
+        L.orc_set_mapping.argtypes = [ctypes.c_void_p, dp, dp]
         L.orc_boundary_flux.argtypes = [ctypes.c_void_p, dp]
         L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -236,6 +237,17 @@ class OracleGrid:
         nxd, nyd = domain if domain is not None else (self.grid.nx, self.grid.ny)
         _check(lib().orc_set_sponge(self.h, _dp(w), float(rate), int(offset[0]), int(offset[1]),
                                     int(nxd), int(nyd)), "set_sponge")
+
+    def set_mapping(self, xn, yn):
+        """mapped grid: node coordinates [ny + 5][nx + 5] of nodes (i, j),
+        i = -2..nx+2, j = -2..ny+2 (two ghost layers included); the grid's
+        dx, dy become the computational spacings"""
+        g = self.grid
+        xn = np.ascontiguousarray(xn, dtype=np.float64)
+        yn = np.ascontiguousarray(yn, dtype=np.float64)
+        assert xn.shape == (g.ny + 5, g.nx + 5) and yn.shape == xn.shape
+        self._nodes = (xn, yn)
+        _check(lib().orc_set_mapping(self.h, _dp(xn), _dp(yn)), "set_mapping")
 
     def set_external_ghosts(self, on=True):
         lib().orc_set_external_ghosts(self.h, 1 if on else 0)

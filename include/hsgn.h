@@ -166,6 +166,26 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device);
  * Errors: EINVAL (no such scenario, negative or non-finite width or rate). */
 int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rate);
 
+/* Mapped grid (Sec. 4, mapped grids): makes single-grid patch `patch` a
+ * planar, logically rectangular mapped grid.  xn, yn (host, row-major,
+ * [ny + 5][nx + 5], copied) are the coordinates of nodes (i, j) for
+ * i = -2..nx+2, j = -2..ny+2 at [j + 2][i + 2], the two ghost layers
+ * included; cell (i, j) has corners (i, j), (i+1, j), (i+1, j+1), (i, j+1)
+ * counter-clockwise.  The patch's dx, dy become the computational spacings:
+ * a cell's capacity is its area over dx dy, an edge's length ratio its length
+ * over dy (edges between columns) or dx (edges between rows).  Each edge's
+ * Riemann problem is solved in the frame of its unit normal; waves, speeds
+ * and fluctuations are rotated back and scaled by the length ratio, and
+ * updates are divided by the capacity.  Momenta (hu, hv) and the state stay
+ * in the physical frame; walls mirror the momentum about the wall edge.
+ * Gauges and the sponge layer use computational coordinates.  Mass in
+ * hsgn_diagnostics is sum(capacity h) dx dy.
+ * After hsgn_finalize; may be called again to change the mapping.
+ * HSGN_ENOTSUP: patch sets, mixed precision, or a context with a sponge
+ * layer.  HSGN_EINVAL: bad patch, null pointers, or a cell of non-positive
+ * area or an edge of zero length (the patch keeps its previous geometry). */
+int hsgn_set_mapping(hsgn_ctx *ctx, int patch, const double *xn, const double *yn);
+
 /* State q[7][ny][nx] (float64) of a patch, copied in or out. */
 int hsgn_set_state(hsgn_ctx *c, int patch, const double *q, int on_device);
 int hsgn_get_state(hsgn_ctx *c, int patch, double *q, int on_device);

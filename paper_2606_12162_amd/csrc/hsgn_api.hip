@@ -213,8 +213,9 @@ __global__ void initdt_finish(ScenState *S, const ScenStatic *SS, const unsigned
     else if (S[s].err == 0) S[s].err = HSGN_EINVAL;
 }
 
-// FP64 sum of h over one patch: fixed decomposition (1024 threads, strided),
-// then a fixed-order tree in shared memory
+// FP64 sum of h (times the capacity on a mapped grid) over one patch: fixed
+// decomposition (1024 threads, strided), then a fixed-order tree in shared
+// memory
 template <class S, bool MIXED>
 __global__ __launch_bounds__(1024) void mass_kernel(PatchInfo pi, const S *q, const S *bath,
                                                     double eta0, double *out)
@@ -230,6 +231,7 @@ __global__ __launch_bounds__(1024) void mass_kernel(PatchInfo pi, const S *q, co
             v = v + eta0 - (double)bath[pi.coff + idx];
             v = v > 0.0 ? v : 0.0;
         }
+        if (pi.metric) v = v * pi.metric[(long long)(y + 2) * (pi.nx + 4) + (x + 2)];   // capacity
         s += v;
     }
     part[threadIdx.x] = s;
@@ -475,6 +477,8 @@ struct hsgn_ctx {
     bool clsb_dirty = true;     // d_clsb to recompute (bathymetry or work table changed)
     bool split = false;         // mixed single grids: deep items without the FP64 edges
     bool any_sponge = false;    // some scenario has a sponge (step kernels with it)
+    bool any_mapped = false;    // some patch is mapped (the mapped step kernel)
+    std::vector<double *> d_metric;   // per patch: its metric planes, or null
     ScenState *d_scen = nullptr;
     ScenStatic *d_sstat = nullptr;
     GaugeDev *d_gauges = nullptr;
@@ -557,6 +561,9 @@ static void free_device(hsgn_ctx *c)
                     c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep, c->d_B0};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (double *m : c->d_metric)
+        if (m) (void)hipFree(m);
+    c->d_metric.clear();
     c->q0 = c->q1 = c->bath = c->clip = c->rec = c->d_mass = c->stage = nullptr;
     c->f0 = c->f1 = c->fbath = nullptr;
     c->m0 = c->m1 = nullptr;
@@ -588,6 +595,7 @@ static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath, int w0,
     A.lcnt = nullptr;
     A.clsb = nullptr;
     A.sponge = c->any_sponge ? 1 : 0;
+    A.mapped = c->any_mapped ? 1 : 0;
     A.nwork = w1 - w0;
     return A;
 }
@@ -1513,9 +1521,71 @@ static int apply_sponge(hsgn_ctx *c, int s)
     return HSGN_OK;
 }
 
+// metric planes of a mapped patch from its node coordinates [ny + 5][nx + 5]
+// (nodes i = -2..nx+2, j = -2..ny+2): per cell of the frame (two ghost
+// layers) the capacity (area over dx dy), the unit normal towards
+// increasing i and the length ratio (over dy) of its left edge, the same
+// towards increasing j (length over dx) for its bottom edge.  False for a
+// cell of non-positive area or an edge of zero length.
+static bool mapping_metric(const PatchInfo &p, const double *xn, const double *yn,
+                           std::vector<double> &out)
+{
+#pragma clang fp contract(off)
+    const long long W = p.nx + 4, MP = W * (p.ny + 4), NW = p.nx + 5;
+    out.assign((size_t)(7 * MP), 0.0);
+    auto X = [&](int i, int j) { return xn[(long long)(j + 2) * NW + (i + 2)]; };
+    auto Y = [&](int i, int j) { return yn[(long long)(j + 2) * NW + (i + 2)]; };
+    for (int j = -2; j < p.ny + 2; j++) {
+        for (int i = -2; i < p.nx + 2; i++) {
+            const long long k = (long long)(j + 2) * W + (i + 2);
+            const double area = 0.5 * ((X(i + 1, j + 1) - X(i, j)) * (Y(i, j + 1) - Y(i + 1, j))
+                                     - (X(i, j + 1) - X(i + 1, j)) * (Y(i + 1, j + 1) - Y(i, j)));
+            const double ex = X(i, j + 1) - X(i, j), ey = Y(i, j + 1) - Y(i, j);
+            const double L = std::sqrt(ex * ex + ey * ey);
+            const double fx = X(i + 1, j) - X(i, j), fy = Y(i + 1, j) - Y(i, j);
+            const double M = std::sqrt(fx * fx + fy * fy);
+            if (!(area > 0.0) || !(L > 0.0) || !(M > 0.0) || !std::isfinite(area)) return false;
+            out[k] = area / (p.dx * p.dy);
+            out[MP + k] = ey / L;
+            out[2 * MP + k] = (0.0 - ex) / L;     // +0 for an axis-aligned edge
+            out[3 * MP + k] = L / p.dy;
+            out[4 * MP + k] = (0.0 - fy) / M;
+            out[5 * MP + k] = fx / M;
+            out[6 * MP + k] = M / p.dx;
+        }
+    }
+    return true;
+}
+
+int hsgn_set_mapping(hsgn_ctx *c, int patch, const double *xn, const double *yn)
+{
+    int rc = check_patch(c, patch);
+    if (rc) return rc;
+    if (!xn || !yn) return fail(c, HSGN_EINVAL, "null node coordinates");
+    PatchInfo &p = c->patches[patch];
+    if (p.frame != 0 || c->scen[p.scen].amr)
+        return fail(c, HSGN_ENOTSUP, "mapped grids are single grids (no patch sets)");
+    if (c->mixed) return fail(c, HSGN_ENOTSUP, "mapped grids run in FP64 precision");
+    if (c->any_sponge) return fail(c, HSGN_ENOTSUP, "mapped grids with a sponge layer");
+    std::vector<double> m;
+    if (!mapping_metric(p, xn, yn, m))
+        return fail(c, HSGN_EINVAL, "mapping with a cell of non-positive area or an edge of zero length");
+    if (c->d_metric.size() < c->patches.size()) c->d_metric.resize(c->patches.size(), nullptr);
+    if (!c->d_metric[patch])
+        HIPCHK(c, hipMalloc((void **)&c->d_metric[patch], sizeof(double) * m.size()));
+    HIPCHK(c, hipMemcpy(c->d_metric[patch], m.data(), sizeof(double) * m.size(),
+                        hipMemcpyHostToDevice));
+    p.metric = c->d_metric[patch];
+    c->any_mapped = true;
+    HIPCHK(c, hipMemcpy(c->d_patches, c->patches.data(), sizeof(PatchInfo) * c->patches.size(),
+                        hipMemcpyHostToDevice));
+    return HSGN_OK;
+}
+
 int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rate)
 {
     if (!c || !c->finalized) return fail(c, HSGN_EINVAL, "call hsgn_finalize first");
+    if (c->any_mapped && rate > 0.0) return fail(c, HSGN_ENOTSUP, "a sponge layer on mapped grids");
     if (scenario < 0 || scenario >= (int)c->scen.size() || c->scen[scenario].patches.empty())
         return fail(c, HSGN_EINVAL, "no such scenario");
     if (!width) return fail(c, HSGN_EINVAL, "null sponge widths");

@@ -45,6 +45,12 @@ struct PatchInfo {
     // domain size in cells)
     double sp_w[4], sp_rate;
     long long sp_i0, sp_j0, sp_nx, sp_ny;
+    // mapped grid (Sec. 4, mapped grids; single grids in FP64), else null:
+    // 7 planes of (ny + 4) x (nx + 4) values over the cells with their two
+    // ghost layers, cell (i, j) at (j + 2) (nx + 4) + i + 2: capacity; unit
+    // normal (x, y) and length ratio of the cell's left edge; the same for
+    // its bottom edge
+    const double *metric;
 };
 
 // relaxation rate of the sponge at interior cell (i, j) of a patch: with d
@@ -114,6 +120,7 @@ struct MarchArgs {
     unsigned *lcnt;
     const int *clsb;
     int sponge;              // some patch has a sponge: the kernels compiled with it
+    int mapped;              // some patch is mapped: the kernel compiled for it
     int nwork;
 };
 
@@ -132,29 +139,41 @@ HSGN_HD void shfl_side_up(L &ln, const Side<T> &c, Side<T> &o)
 // entries, so no synchronisation is needed
 constexpr int EIG_FIELDS = 13;
 
-template <class T>
+template <bool MAP = false, class T>
 HSGN_HD void eig_store(T *ring, int slot, int lane, const Eig<T> &e)
 {
-    T *p = ring + (slot * EIG_FIELDS) * 64 + lane;
+    T *p = ring + (slot * (EIG_FIELDS + (MAP ? 5 : 0))) * 64 + lane;
+    if (MAP) {
+        p[13 * 64] = e.fnx; p[14 * 64] = e.fny; p[15 * 64] = e.ftx; p[16 * 64] = e.fty;
+        p[17 * 64] = e.gm;
+    }
     p[0 * 64] = e.uh; p[1 * 64] = e.vh; p[2 * 64] = e.wh; p[3 * 64] = e.sh;
     p[4 * 64] = e.pbh; p[5 * 64] = e.ghh; p[6 * 64] = e.c2p; p[7 * 64] = e.inv_ce2;
     p[8 * 64] = e.smin; p[9 * 64] = e.smax; p[10 * 64] = e.inv_ds;
     p[11 * 64] = e.wet ? (T)1 : (T)0; p[12 * 64] = e.ce2;
 }
 
-template <class T>
+template <bool MAP = false, class T>
 HSGN_HD void eig_load(const T *ring, int slot, int lane, Eig<T> &e)
 {
-    const T *p = ring + (slot * EIG_FIELDS) * 64 + lane;
+    const T *p = ring + (slot * (EIG_FIELDS + (MAP ? 5 : 0))) * 64 + lane;
+    if (MAP) {
+        e.fnx = p[13 * 64]; e.fny = p[14 * 64]; e.ftx = p[15 * 64]; e.fty = p[16 * 64];
+        e.gm = p[17 * 64];
+    }
     e.uh = p[0 * 64]; e.vh = p[1 * 64]; e.wh = p[2 * 64]; e.sh = p[3 * 64];
     e.pbh = p[4 * 64]; e.ghh = p[5 * 64]; e.c2p = p[6 * 64]; e.inv_ce2 = p[7 * 64];
     e.smin = p[8 * 64]; e.smax = p[9 * 64]; e.inv_ds = p[10 * 64];
     e.wet = p[11 * 64] != (T)0; e.ce2 = p[12 * 64];
 }
 
-template <class L, class T>
+template <bool MAP = false, class L, class T>
 HSGN_HD void shfl_waves_up(L &ln, const Waves<T> &w, Waves<T> &o)
 {
+    if (MAP) {
+        o.fnx = ln.up(w.fnx); o.fny = ln.up(w.fny); o.ftx = ln.up(w.ftx); o.fty = ln.up(w.fty);
+        o.gm = ln.up(w.gm);
+    }
     for (int m = 0; m < 7; m++) { o.z0[m] = ln.up(w.z0[m]); o.z6[m] = ln.up(w.z6[m]); }
     for (int m = 0; m < 3; m++) o.zm[m] = ln.up(w.zm[m]);
     o.bs = ln.up(w.bs); o.bw = ln.up(w.bw); o.bt = ln.up(w.bt); o.bpb = ln.up(w.bpb);
@@ -177,11 +196,22 @@ struct RawCell {
     int mk;
 };
 
+// m - 2 (m . n) n: momentum (hu, hv) mirrored about a wall of unit normal n
+template <class T>
+HSGN_HD void reflect(T &hu, T &hv, T nx, T ny)
+{
+    const T a = hu * nx + hv * ny;
+    hu = hu - (T)2 * a * nx;
+    hv = hv - (T)2 * a * ny;
+}
+
 // load cell (col, row) of a patch through the boundary map, or (FRAMED)
-// from the stored ghost frame
-template <bool FRAMED, class S, class T>
+// from the stored ghost frame.  On a mapped grid a wall mirrors the
+// momentum about the wall edge of the interior cell's row (column): the
+// left edge of column xwall (0 or nx), the bottom edge of row 0 or ny.
+template <bool FRAMED, bool MAP = false, class S, class T>
 HSGN_HD void load_raw(const PatchInfo &pi, const S *q, const S *bath, const uint8_t *mask,
-                      int mc, int fx, int row, RawCell<T> &r)
+                      int mc, int fx, int row, RawCell<T> &r, int xwall = 0)
 {
     int fy = 0;
     int mr = FRAMED ? row : map_index(row, pi.ny, pi.bc[2], pi.bc[3], &fy);
@@ -190,8 +220,20 @@ HSGN_HD void load_raw(const PatchInfo &pi, const S *q, const S *bath, const uint
     const S *qp = q + pi.qoff + idx;
     HSGN_UNROLL
     for (int m = 0; m < 7; m++) r.q[m] = (T)qp[m * plane];
-    if (fx) r.q[IHU] = -r.q[IHU];
-    if (fy) r.q[IHV] = -r.q[IHV];
+    if (MAP && pi.metric) {
+        const long long W = pi.nx + 4, MP = W * (pi.ny + 4);
+        if (fx) {
+            const double *e = pi.metric + (long long)(mr + 2) * W + (xwall + 2);
+            reflect(r.q[IHU], r.q[IHV], (T)e[1 * MP], (T)e[2 * MP]);
+        }
+        if (fy) {
+            const double *e = pi.metric + (long long)((row < 0 ? 0 : pi.ny) + 2) * W + (mc + 2);
+            reflect(r.q[IHU], r.q[IHV], (T)e[4 * MP], (T)e[5 * MP]);
+        }
+    } else {
+        if (fx) r.q[IHU] = -r.q[IHU];
+        if (fy) r.q[IHV] = -r.q[IHV];
+    }
     r.b = (T)bath[pi.coff + idx];
     r.mk = mask[pi.coff + idx];
 }
@@ -233,6 +275,46 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
     }
     derive(P, c);
     c.eta = MIXED ? r.q[IH] : c.h + c.b;
+}
+
+// one side of a mapped edge: the cell's state (after the first source half
+// step) with its momentum rotated into the edge's frame (unit normal n,
+// tangent t), its primitives derived from the rotated state
+template <class T>
+HSGN_HD void mapped_side(const StepParams &P, const T *q, T b, T c2, T nx, T ny, T tx, T ty,
+                         Side<T> &sd)
+{
+    Cell<T> c;
+    HSGN_UNROLL
+    for (int m = 0; m < 7; m++) c.q[m] = q[m];
+    c.q[IHU] = q[IHU] * nx + q[IHV] * ny;
+    c.q[IHV] = q[IHU] * tx + q[IHV] * ty;
+    c.b = b;
+    c.c2 = c2;
+    derive(P, c);
+    c.eta = c.h + c.b;
+    side_of<0>(c, sd);
+}
+
+// mapped edge: the frame and length ratio kept with the waves and the Roe
+// state, the speeds scaled
+template <class T>
+HSGN_HD void set_frame(Waves<T> &W, Eig<T> &E, T nx, T ny, T tx, T ty, T gm)
+{
+    W.fnx = nx; W.fny = ny; W.ftx = tx; W.fty = ty; W.gm = gm;
+    E.fnx = nx; E.fny = ny; E.ftx = tx; E.fty = ty; E.gm = gm;
+    W.smin = W.smin * gm; W.smax = W.smax * gm; W.uh = W.uh * gm;
+}
+
+// a frame vector (a fluctuation) rotated to the global frame and scaled
+template <class T>
+HSGN_HD void to_global(const Waves<T> &W, T *v)
+{
+    const T hu = v[IHU] * W.fnx + v[IHV] * W.ftx;
+    const T hv = v[IHU] * W.fny + v[IHV] * W.fty;
+    v[IHU] = hu; v[IHV] = hv;
+    HSGN_UNROLL
+    for (int m = 0; m < 7; m++) v[m] = v[m] * W.gm;
 }
 
 // normal solve of an edge.  In mixed precision an edge with an SWE or dry
@@ -279,7 +361,11 @@ HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Sid
 //   left  A-dQ + F~ + F~tr,   right -(A+dQ - F~) + F~tr,
 //   below B-dQ + G~ + G~tr,   above -(B+dQ - G~) + G~tr
 // at entries j, ny + j, 2 ny + i, 2 ny + nx + i of the patch.
-template <class L, class S, class T, bool MIXED, bool AMR, bool FB = true, bool SP = false>
+// MAP: compiled for mapped grids (FP64 single grids): every edge is solved
+// in its own frame; a patch without a metric takes the identity frames,
+// unit ratios and capacities, which give the Cartesian results.
+template <class L, class S, class T, bool MIXED, bool AMR, bool FB = true, bool SP = false,
+          bool MAP = false>
 HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 {
     const WorkItem wk = A.work[wid];
@@ -305,6 +391,10 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     if (col > pi.nx + 1) col = pi.nx + 1;       // idle lanes of a partial strip
     int fx = 0;
     const int mc = AMR ? col : map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
+    const int xwall = (wk.i0 - 2 + lane) < 0 ? 0 : pi.nx;   // wall edge of a mapped ghost
+    constexpr int D = MAP ? 2 : 0;               // x-edge family vectors: frame or global
+    constexpr int DY = MAP ? 2 : 1;              // y-edge
+    const long long MW = pi.nx + 4, MP = MW * (pi.ny + 4);
     const int i_hi = wk.i0 + 59 < pi.nx - 1 ? wk.i0 + 59 : pi.nx - 1;
     const bool interior = (wk.i0 - 2 + lane) >= wk.i0 && (wk.i0 - 2 + lane) <= i_hi;
     const bool interior_left = lane >= 1 && (wk.i0 - 3 + lane) >= wk.i0 && (wk.i0 - 3 + lane) <= i_hi;
@@ -326,6 +416,10 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     int phi_w[3], brk_w[3];      // masks
     int fl_w[3] = {0, 0, 0};     // interface edge flags (patch sets)
     T b_w[3];                    // bathymetry
+    T kap_w[3] = {(T)1, (T)1, (T)1};   // capacities (mapped grids)
+    T qprev[7], bprev = (T)0, c2prev = (T)0;   // cell below (mapped y-edges)
+    HSGN_UNROLL
+    for (int m = 0; m < 7; m++) qprev[m] = (T)0;
     Waves<T> yprev;              // waves of the y-edge below the new one
     T ydl[7];                    // its dot products with the edge below it
     T xtr_prev[7];               // transverse x-fluctuation entering (i, k-1)
@@ -336,14 +430,14 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     for (int m = 0; m < 7; m++) { xtr_prev[m] = (T)0; bp_saved[m] = (T)0; ydl[m] = (T)0; }
 
     RawCell<T> nxt;
-    load_raw<AMR>(pi, qin, A.bath, min_, mc, fx, r0 - 2, nxt);
+    load_raw<AMR, MAP>(pi, qin, A.bath, min_, mc, fx, r0 - 2, nxt, xwall);
     for (int k = r0 - 2; k <= r0 + th + 1; k++) {
         const int sk = 2, sk1 = 1, sk2 = 0;
         Cell<T> c;
         {
             RawCell<T> raw = nxt;
             // issue the next row's loads before working on this one
-            if (k < r0 + th + 1) load_raw<AMR>(pi, qin, A.bath, min_, mc, fx, k + 1, nxt);
+            if (k < r0 + th + 1) load_raw<AMR, MAP>(pi, qin, A.bath, min_, mc, fx, k + 1, nxt, xwall);
             prepare_cell<T, MIXED>(P, raw, tau_pre, c, phi_c, brk_c);
             acc[sk][IH] = raw.q[IH];
             if (AMR) fl_w[sk] = (raw.mk >> 2) & 15;
@@ -351,6 +445,15 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         phi_w[sk] = phi_c;
         brk_w[sk] = brk_c;
         b_w[sk] = c.b;
+        // metric of cell (col, k): capacity, left-edge and bottom-edge frames
+        T met[7] = {(T)1, (T)1, (T)0, (T)1, (T)0, (T)1, (T)1};
+        if (MAP && pi.metric) {
+            const double *e = pi.metric + (long long)(k + 2) * MW + (col + 2);
+            HSGN_UNROLL
+            for (int m = 0; m < 7; m++) met[m] = (T)e[m * MP];
+        }
+        kap_w[sk] = met[0];
+        const T kap_l = MAP ? ln.up(met[0]) : (T)1;      // capacity of cell (col - 1, k)
         const int slot_k = (k - r0 + 6) % 3, slot_k2 = (k - r0 + 4) % 3;
         if (MIXED) {
             // increment form: the cell's state after the first source half
@@ -373,30 +476,44 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         for (int m = 0; m < 7; m++) xtr[m] = (T)0;
         if (k >= r0 - 1 && k <= r0 + th) {
             Side<T> sr, sl;
-            side_of<0>(c, sr);
-            shfl_side_up(ln, sr, sl);
+            if (MAP) {
+                T ql[7];
+                HSGN_UNROLL
+                for (int m = 0; m < 7; m++) ql[m] = ln.up(c.q[m]);
+                const T bl = ln.up(c.b), c2l = ln.up(c.c2);
+                mapped_side(P, ql, bl, c2l, met[1], met[2], (T)0 - met[2], met[1], sl);
+                mapped_side(P, c.q, c.b, c.c2, met[1], met[2], (T)0 - met[2], met[1], sr);
+            } else {
+                side_of<0>(c, sr);
+                shfl_side_up(ln, sr, sl);
+            }
             Waves<T> xw;
             Eig<T> xe;
             bool ok = edge_solve<0, MIXED && FB>(ln, P, sl, sr, xw, xe);
             if (!ok && lane >= 1) sc->err = -4;
+            if (MAP) set_frame(xw, xe, met[1], met[2], (T)0 - met[2], met[1], met[3]);
             Waves<T> xwl;
-            shfl_waves_up(ln, xw, xwl);
+            shfl_waves_up<MAP>(ln, xw, xwl);
             T dl[7], dr[7];
-            family_dots<0>(xwl, xw, dl);
+            family_dots<D>(xwl, xw, dl);
             HSGN_UNROLL
             for (int f = 0; f < 7; f++) dr[f] = ln.dn(dl[f]);
             T F[7], am[7], ap[7];
-            correction<0>(lim, dtdx, xw, dl, dr, F);
+            // mapped: dt/dx the mean of dt/(kap dx) of the edge's two cells
+            const T fcx = MAP ? (T)0.5 * (dtdx / kap_l + dtdx / kap_w[sk]) : dtdx;
+            correction<D>(lim, fcx, xw, dl, dr, F);
             fluctuations<0>(xw, am, ap);
+            if (MAP) { to_global(xw, am); to_global(xw, ap); }
             T apc[7], amc[7], amr[7];
             HSGN_UNROLL
             for (int m = 0; m < 7; m++) { apc[m] = ap[m] - F[m]; amc[m] = am[m] + F[m]; }
             shfl_vec(ln, amc, amr, false);
             int kind_r = ln.dni(xw.kind);
             const bool zl = AMR && (fl_w[sk] & IFACE_L), zr = AMR && (fl_w[sk] & IFACE_R);
+            const T ddx = MAP ? dtdx / kap_w[sk] : dtdx;
             HSGN_UNROLL
             for (int m = 0; m < 7; m++) {
-                acc[sk][m] -= dtdx * ((zl ? (T)0 : apc[m]) + (zr ? (T)0 : amr[m]));
+                acc[sk][m] -= ddx * ((zl ? (T)0 : apc[m]) + (zr ? (T)0 : amr[m]));
                 xtr[m] = (xw.kind == KIND_REGULAR ? apc[m] : (T)0)
                        + (kind_r == KIND_REGULAR ? amr[m] : (T)0);
             }
@@ -411,9 +528,12 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                         ef[(long long)(pi.ny + k) * 7 + m] = -(double)apc[m];
                 }
             }
-            eig_store(ring, slot_k, lane, xe);
-            if (k >= r0 && k < r0 + th && (interior || interior_left))
-                rx = tmax(rx, tmax((T)fabs(xw.smin), tmax((T)fabs(xw.smax), (T)fabs(xw.uh))));
+            eig_store<MAP>(ring, slot_k, lane, xe);
+            if (k >= r0 && k < r0 + th && (interior || interior_left)) {
+                // mapped: the scaled speeds over the smaller capacity of the edge's cells
+                const T kk = MAP ? tmin(kap_l, kap_w[sk]) : (T)1;
+                rx = tmax(rx, tmax((T)fabs(xw.smin) / kk, tmax((T)fabs(xw.smax) / kk, (T)fabs(xw.uh) / kk)));
+            }
         }
 
         // ---- y-edge (i, k-1/2) ----
@@ -422,25 +542,44 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         if (k >= r0 - 1) {
             Waves<T> yw;
             Eig<T> ye;
-            bool ok = edge_solve<1, MIXED && FB>(ln, P, yside_prev, yside, yw, ye);
+            bool ok;
+            if (MAP) {
+                // frame of the bottom edge of cell (i, k): tangent (n_y, -n_x)
+                Side<T> ysl, ysr;
+                mapped_side(P, qprev, bprev, c2prev, met[4], met[5], met[5], (T)0 - met[4], ysl);
+                mapped_side(P, c.q, c.b, c.c2, met[4], met[5], met[5], (T)0 - met[4], ysr);
+                ok = edge_solve<0, MIXED && FB>(ln, P, ysl, ysr, yw, ye);
+                set_frame(yw, ye, met[4], met[5], met[5], (T)0 - met[4], met[6]);
+            } else {
+                ok = edge_solve<1, MIXED && FB>(ln, P, yside_prev, yside, yw, ye);
+            }
             if (!ok) sc->err = -4;
-            if (k >= r0 && k <= r0 + th && interior)
-                ry = tmax(ry, tmax((T)fabs(yw.smin), tmax((T)fabs(yw.smax), (T)fabs(yw.uh))));
+            if (k >= r0 && k <= r0 + th && interior) {
+                const T kk = MAP ? tmin(kap_w[sk1], kap_w[sk]) : (T)1;
+                ry = tmax(ry, tmax((T)fabs(yw.smin) / kk, tmax((T)fabs(yw.smax) / kk, (T)fabs(yw.uh) / kk)));
+            }
             if (k >= r0) {
                 T dk[7];
-                family_dots<1>(yw, yprev, dk);
+                family_dots<DY>(yw, yprev, dk);
                 if (k - 1 >= r0 && k - 1 <= r0 + th) {
                     // the y-edge (i, k-3/2) between rows k-2 and k-1 is complete
                     T G[7], bm[7], bp[7];
-                    correction<1>(lim, dtdy, yprev, ydl, dk, G);
-                    fluctuations<1>(yprev, bm, bp);
+                    const T fcy = MAP ? (T)0.5 * (dtdy / kap_w[sk2] + dtdy / kap_w[sk1]) : dtdy;
+                    correction<DY>(lim, fcy, yprev, ydl, dk, G);
+                    if (MAP) {
+                        fluctuations<0>(yprev, bm, bp);
+                        to_global(yprev, bm);
+                        to_global(yprev, bp);
+                    } else {
+                        fluctuations<1>(yprev, bm, bp);
+                    }
                     T btm[7], btp[7];
                     const bool zb = AMR && (fl_w[sk1] & IFACE_B), zt = AMR && (fl_w[sk2] & IFACE_T);
                     HSGN_UNROLL
                     for (int m = 0; m < 7; m++) {
                         T bpc = bp[m] - G[m], bmc = bm[m] + G[m];
-                        acc[sk1][m] -= dtdy * (zb ? (T)0 : bpc);
-                        acc[sk2][m] -= dtdy * (zt ? (T)0 : bmc);
+                        acc[sk1][m] -= (MAP ? dtdy / kap_w[sk1] : dtdy) * (zb ? (T)0 : bpc);
+                        acc[sk2][m] -= (MAP ? dtdy / kap_w[sk2] : dtdy) * (zt ? (T)0 : bmc);
                         btp[m] = yprev.kind == KIND_REGULAR ? bpc : (T)0;
                         btm[m] = yprev.kind == KIND_REGULAR ? bmc : (T)0;
                     }
@@ -472,21 +611,32 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                         HSGN_UNROLL
                         for (int m = 0; m < 7; m++) Ft[m] = (T)0;
                         Eig<T> exk2;
-                        eig_load(ring, slot_k2, lane, exk2);
+                        eig_load<MAP>(ring, slot_k2, lane, exk2);
+                        const T kap2_l = MAP ? ln.up(kap_w[sk2]) : (T)1;   // cell (i - 1, k - 2)
                         if (trans && exk2.wet) {
                             T vp[7], vm[7];
-                            trans_split<0>(exk2, ytl, 1, vp);
-                            trans_split<0>(exk2, ytr, -1, vm);
-                            HSGN_UNROLL
-                            for (int m = 0; m < 7; m++) Ft[m] = (T)-0.5 * dtdy * (vp[m] + vm[m]);
+                            trans_split<D>(exk2, ytl, 1, vp);
+                            trans_split<D>(exk2, ytr, -1, vm);
+                            if (MAP) {
+                                // each part weighted by the edge's length ratio over
+                                // the capacity of the cell it entered
+                                const T wa = exk2.gm / kap2_l, wb = exk2.gm / kap_w[sk2];
+                                HSGN_UNROLL
+                                for (int m = 0; m < 7; m++)
+                                    Ft[m] = (T)-0.5 * dtdy * (wa * vp[m] + wb * vm[m]);
+                            } else {
+                                HSGN_UNROLL
+                                for (int m = 0; m < 7; m++) Ft[m] = (T)-0.5 * dtdy * (vp[m] + vm[m]);
+                            }
                         }
                         T Ftr[7];
                         shfl_vec(ln, Ft, Ftr, false);
                         const bool fzl = AMR && (fl_w[sk2] & IFACE_L);
                         const bool fzr = AMR && (fl_w[sk2] & IFACE_R);
+                        const T ddx2 = MAP ? dtdx / kap_w[sk2] : dtdx;
                         HSGN_UNROLL
                         for (int m = 0; m < 7; m++)
-                            acc[sk2][m] -= dtdx * ((fzr ? (T)0 : Ftr[m]) - (fzl ? (T)0 : Ft[m]));
+                            acc[sk2][m] -= ddx2 * ((fzr ? (T)0 : Ftr[m]) - (fzl ? (T)0 : Ft[m]));
                         if (AMR && (e_left || e_right)) {
                             long long e0 = (long long)((e_left ? 0 : pi.ny) + (k - 2)) * 7;
                             HSGN_UNROLL
@@ -505,14 +655,17 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             if (trans && k >= r0 && k <= r0 + th && ye.wet) {
                 // transverse x-fluctuations entering (i, k-1) [up] and (i, k) [down]
                 T vp[7], vm[7];
-                trans_split<1>(ye, xtr_prev, 1, vp);
-                trans_split<1>(ye, xtr, -1, vm);
+                trans_split<DY>(ye, xtr_prev, 1, vp);
+                trans_split<DY>(ye, xtr, -1, vm);
                 const bool zt = AMR && (fl_w[sk1] & IFACE_T), zb = AMR && (fl_w[sk] & IFACE_B);
+                const T wa = MAP ? ye.gm / kap_w[sk1] : (T)1, wb = MAP ? ye.gm / kap_w[sk] : (T)1;
+                const T ddy1 = MAP ? dtdy / kap_w[sk1] : dtdy, ddy0 = MAP ? dtdy / kap_w[sk] : dtdy;
                 HSGN_UNROLL
                 for (int m = 0; m < 7; m++) {
-                    Gt[m] = (T)-0.5 * dtdx * (vp[m] + vm[m]);
-                    acc[sk1][m] -= dtdy * (zt ? (T)0 : Gt[m]);
-                    acc[sk][m] += dtdy * (zb ? (T)0 : Gt[m]);
+                    Gt[m] = MAP ? (T)-0.5 * dtdx * (wa * vp[m] + wb * vm[m])
+                                : (T)-0.5 * dtdx * (vp[m] + vm[m]);
+                    acc[sk1][m] -= ddy1 * (zt ? (T)0 : Gt[m]);
+                    acc[sk][m] += ddy0 * (zb ? (T)0 : Gt[m]);
                 }
             }
             if (AMR && e_cols && (k == 0 || k == pi.ny) && k >= r0 && k <= r0 + th) {
@@ -595,7 +748,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 HSGN_UNROLL
                 for (int m = 1; m < 7; m++) qd[m] = (double)qn[m];
                 if (hD < 0.0) {
-                    clip += -hD * pi.dx * pi.dy;
+                    clip += MAP ? -hD * (double)kap_w[sk2] * pi.dx * pi.dy : -hD * pi.dx * pi.dy;
                     hD = 0.0;
                 }
                 if (hD <= P.dry_tol) {
@@ -631,6 +784,11 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             xtr_prev[m] = xtr[m];
             acc[0][m] = acc[1][m];
             acc[1][m] = acc[2][m];
+            if (MAP) qprev[m] = c.q[m];
+        }
+        if (MAP) {
+            bprev = c.b; c2prev = c.c2;
+            kap_w[0] = kap_w[1]; kap_w[1] = kap_w[2];
         }
         phi_w[0] = phi_w[1]; phi_w[1] = phi_w[2];
         fl_w[0] = fl_w[1]; fl_w[1] = fl_w[2];

@@ -77,6 +77,9 @@ struct Waves {
     T bs, bw, bt, bpb; // contact strengths
     T smin, smax, uh;
     int kind;
+    // mapped edges only: the edge's frame (unit normal n, tangent t) and
+    // length ratio; the waves above are in that frame, the speeds scaled
+    T fnx, fny, ftx, fty, gm;
 };
 
 // eigenstructure of an edge used to split fluctuations transversally
@@ -85,6 +88,7 @@ template <class T>
 struct Eig {
     T uh, vh, wh, sh, pbh, ghh, c2p, ce2, inv_ce2, smin, smax, inv_ds;
     int wet;           // both cells wet
+    T fnx, fny, ftx, fty, gm;   // mapped edges only: frame and length ratio
 };
 
 template <class T>
@@ -544,18 +548,29 @@ HSGN_HD void convert(const Side<T> &a, Side<D> &o)
 template <int DIR, class T>
 HSGN_HD void wave_vec(const Waves<T> &W, int f, T *z)
 {
-    const int IN = DIR == 0 ? IHU : IHV;
-    const int IT = DIR == 0 ? IHV : IHU;
-    HSGN_UNROLL
-    for (int m = 0; m < 7; m++) z[m] = (T)0;
-    switch (f) {
-    case 0: for (int m = 0; m < 7; m++) z[m] = W.z0[m]; break;
-    case 1: z[IH] = W.zm[0]; z[IN] = W.zm[1]; z[IHP] = W.zm[2]; break;
-    case 2: z[IHS] = W.bs; break;
-    case 3: z[IHW] = W.bw; break;
-    case 4: z[IT] = W.bt; break;
-    case 5: z[IHPB] = W.bpb; break;
-    default: for (int m = 0; m < 7; m++) z[m] = W.z6[m]; break;
+    if constexpr (DIR == 2) {
+        // mapped edge: the frame wave rotated back to the global frame and
+        // scaled by the edge's length ratio
+        wave_vec<0>(W, f, z);
+        const T hu = z[IHU] * W.fnx + z[IHV] * W.ftx;
+        const T hv = z[IHU] * W.fny + z[IHV] * W.fty;
+        z[IHU] = hu; z[IHV] = hv;
+        HSGN_UNROLL
+        for (int m = 0; m < 7; m++) z[m] = z[m] * W.gm;
+    } else {
+        const int IN = DIR == 0 ? IHU : IHV;
+        const int IT = DIR == 0 ? IHV : IHU;
+        HSGN_UNROLL
+        for (int m = 0; m < 7; m++) z[m] = (T)0;
+        switch (f) {
+        case 0: for (int m = 0; m < 7; m++) z[m] = W.z0[m]; break;
+        case 1: z[IH] = W.zm[0]; z[IN] = W.zm[1]; z[IHP] = W.zm[2]; break;
+        case 2: z[IHS] = W.bs; break;
+        case 3: z[IHW] = W.bw; break;
+        case 4: z[IT] = W.bt; break;
+        case 5: z[IHPB] = W.bpb; break;
+        default: for (int m = 0; m < 7; m++) z[m] = W.z6[m]; break;
+        }
     }
 }
 
@@ -651,6 +666,20 @@ HSGN_HD void fluctuations(const Waves<T> &W, T *am, T *ap)
 template <int DIR, class T>
 HSGN_HD void trans_split(const Eig<T> &E, const T *a, int sgn, T *out)
 {
+    if constexpr (DIR == 2) {
+        // mapped edge: a rotated into the edge's frame, split there, the
+        // parts rotated back
+        T t[7];
+        HSGN_UNROLL
+        for (int m = 0; m < 7; m++) t[m] = a[m];
+        t[IHU] = a[IHU] * E.fnx + a[IHV] * E.fny;
+        t[IHV] = a[IHU] * E.ftx + a[IHV] * E.fty;
+        trans_split<0>(E, t, sgn, out);
+        const T hu = out[IHU] * E.fnx + out[IHV] * E.ftx;
+        const T hv = out[IHU] * E.fny + out[IHV] * E.fty;
+        out[IHU] = hu; out[IHV] = hv;
+        return;
+    }
     const int IN = DIR == 0 ? IHU : IHV;
     const int IT = DIR == 0 ? IHV : IHU;
     T an[7] = {a[IH], a[IN], a[IT], a[IHW], a[IHS], a[IHP], a[IHPB]};

@@ -25,7 +25,7 @@ EXPORTS = ("hsgn_create", "hsgn_add_grid", "hsgn_finalize", "hsgn_set_bathymetry
            "hsgn_set_gauges", "hsgn_read_gauges", "hsgn_advance", "hsgn_diagnostics",
            "hsgn_get_clock", "hsgn_set_clock", "hsgn_work_items", "hsgn_set_timing",
            "hsgn_get_timing", "hsgn_autotune", "hsgn_regrid", "hsgn_num_patches",
-           "hsgn_patch_info", "hsgn_set_sponge", "hsgn_destroy", "hsgn_strerror",
+           "hsgn_patch_info", "hsgn_set_mapping", "hsgn_set_sponge", "hsgn_destroy", "hsgn_strerror",
            "hsgn_last_error")
 
 
@@ -90,6 +90,7 @@ def lib():
         L.hsgn_get_timing.argtypes = [vp, dp, dp]
         L.hsgn_regrid.argtypes = [vp, ctypes.c_int, ctypes.POINTER(hsgn_regrid_params), ip]
         L.hsgn_set_sponge.argtypes = [vp, ctypes.c_int, dp, ctypes.c_double]
+        L.hsgn_set_mapping.argtypes = [vp, ctypes.c_int, vp, vp]
         L.hsgn_num_patches.argtypes = [vp, ip]
         L.hsgn_patch_info.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip, dp, dp, dp, dp]
         L.hsgn_destroy.argtypes = [vp]
@@ -202,6 +203,16 @@ class Context:
         m = np.ascontiguousarray(m, dtype=np.uint8)
         p, dev = _ptr(m)
         self._check(lib().hsgn_set_mask(self.h, patch, p, dev), "hsgn_set_mask")
+
+    def set_mapping(self, patch, xn, yn):
+        """mapped single grid: node coordinates [ny + 5][nx + 5] of nodes
+        (i, j), i = -2..nx+2, j = -2..ny+2 (two ghost layers included)"""
+        xn = np.ascontiguousarray(xn, dtype=np.float64)
+        yn = np.ascontiguousarray(yn, dtype=np.float64)
+        if xn.shape != yn.shape or xn.ndim != 2:
+            raise ValueError("node arrays of one shape [ny + 5][nx + 5] expected")
+        self._check(lib().hsgn_set_mapping(self.h, int(patch), ctypes.c_void_p(xn.ctypes.data),
+                                           ctypes.c_void_p(yn.ctypes.data)), "hsgn_set_mapping")
 
     def set_sponge(self, scenario, width, rate):
         """sponge widths (m) from the x-low, x-high, y-low, y-high sides of

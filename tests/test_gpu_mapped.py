@@ -1,0 +1,154 @@
+"""GPU parity of mapped grids (Sec. 4, mapped grids; FP64 single grids)
+through the C ABI.
+
+Bar: fields within 1e-11 of the oracle relative to each field's largest
+magnitude (the mapped kernel follows the oracle's operations, so the bits
+usually agree), masks equal; the identity mapping of a Cartesian grid gives
+the Cartesian run's bits; a Cartesian scenario stepped in the same launch as
+a mapped one keeps its bits; capacity-weighted mass against the oracle's;
+unsupported combinations refused.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_12162_amd import hsgn as H
+from paper_2606_12162_amd import workloads as W
+
+from cases import rough_case
+from test_oracle_mapped import BCS, distorted, dyadic_case, nodes, periodic_case
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    H.lib()
+    yield
+
+
+def field_errors(got, exp):
+    scale = np.abs(exp).max(axis=(1, 2))
+    return np.abs(got - exp).max(axis=(1, 2)) / np.where(scale > 0, scale, 1.0)
+
+
+def gpu_run(w, xy, steps, dt):
+    ctx = H.from_workloads([w])
+    if xy is not None:
+        ctx.set_mapping(0, *xy)
+    ctx.advance(dt, steps)
+    out = ctx.get_state(0), ctx.get_mask(0), ctx.diagnostics(0)
+    ctx.close()
+    return out
+
+
+def oracle_run(w, xy, steps, dt):
+    r = O.from_workload(w)
+    if xy is not None:
+        r.set_mapping(*xy)
+    r.advance(dt, steps)
+    return r.get_state(), r.get_mask(), r.mass()
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_identity_mapping_gives_the_cartesian_bits(bc):
+    w = dyadic_case(bc, seed=21)
+    print("case", w.name, "identity mapping", flush=True)
+    xy = nodes(w.grid, lambda x, y: x, lambda x, y: y)
+    qm, mm, _ = gpu_run(w, xy, 12, w.dt)
+    qc, mc, _ = gpu_run(w, None, 12, w.dt)
+    qo, mo, _ = oracle_run(w, None, 12, w.dt)
+    assert np.array_equal(qm, qc)
+    assert np.array_equal(mm, mc)
+    assert np.array_equal(qm, qo)
+
+
+def mapped_cases():
+    rot = rough_case(40, 36, (W.BC_WALL, W.BC_WALL, W.BC_PERIODIC, W.BC_PERIODIC), seed=22)
+    rot = dataclasses.replace(rot, gauges=np.zeros((0, 2)))
+    c, s = np.cos(0.6), np.sin(0.6)
+    yield "rotated_walls", rot, rot.dt, nodes(rot.grid, lambda x, y: c * x - s * y, lambda x, y: s * x + c * y)
+    scl = dyadic_case(BCS[1], seed=23)
+    yield "scaled_walls", scl, 0.5 * scl.dt, nodes(scl.grid, lambda x, y: 2.0 * x, lambda x, y: 0.5 * y)
+    dis = rough_case(61, 47, (W.BC_WALL, W.BC_EXTRAP, W.BC_WALL, W.BC_EXTRAP), seed=24)
+    dis = dataclasses.replace(dis, gauges=np.zeros((0, 2)))
+    yield "distorted_walls_wetdry", dis, 0.8 * dis.dt, distorted(dis.grid, amp=0.02)
+
+
+@pytest.mark.parametrize("name", ["rotated_walls", "scaled_walls", "distorted_walls_wetdry"])
+def test_mapped_grid_fp64_parity(name):
+    w, dt, xy = next((w, dt, xy) for n, w, dt, xy in mapped_cases() if n == name)
+    print("case", name, w.name, flush=True)
+    qg, mg, _ = gpu_run(w, xy, 12, dt)
+    qo, mo, _ = oracle_run(w, xy, 12, dt)
+    err = field_errors(qg, qo)
+    print("field errors", np.array2string(err, precision=2), "bitwise", np.array_equal(qg, qo))
+    assert np.all(err <= TOL)
+    assert np.array_equal(mg, mo)
+
+
+def test_distorted_periodic_hump_parity_and_mass():
+    nx, ny = 64, 48
+    g = periodic_case(np.zeros((7, ny, nx)), np.zeros((ny, nx)), nx=nx, ny=ny).grid
+    X, Y = W.cell_centres(g)
+    q = np.zeros((7, ny, nx))
+    q[0] = 1.0 + 0.1 * np.exp(-((X - 6.0) ** 2 + (Y - 6.0) ** 2))
+    q[1] = 0.05 * q[0]
+    w = periodic_case(q, np.full((ny, nx), -1.0), nx=nx, ny=ny)
+    xy = distorted(g)
+    print("case distorted periodic hump", flush=True)
+    qg, _, dg = gpu_run(w, xy, 30, w.dt)
+    qo, _, mo = oracle_run(w, xy, 30, w.dt)
+    err = field_errors(qg, qo)
+    print("field errors", np.array2string(err, precision=2))
+    assert np.all(err <= TOL)
+    assert abs(dg["mass"] - mo) <= 1e-13 * mo
+
+
+def test_cartesian_scenario_beside_a_mapped_one_keeps_its_bits():
+    a = dyadic_case(BCS[0], seed=25)
+    b = rough_case(40, 36, (W.BC_WALL, W.BC_WALL, W.BC_PERIODIC, W.BC_PERIODIC), seed=26)
+    b = dataclasses.replace(b, gauges=np.zeros((0, 2)), dt=a.dt)
+    c, s = np.cos(0.3), np.sin(0.3)
+    xy = nodes(b.grid, lambda x, y: c * x - s * y, lambda x, y: s * x + c * y)
+    print("case ensemble: Cartesian", a.name, "+ rotated", b.name, flush=True)
+    ctx = H.from_workloads([a, b])
+    ctx.set_mapping(1, *xy)
+    ctx.advance(a.dt, 10)
+    qa, qb = ctx.get_state(0), ctx.get_state(1)
+    ctx.close()
+    assert np.array_equal(qa, oracle_run(a, None, 10, a.dt)[0])
+    assert np.all(field_errors(qb, oracle_run(b, xy, 10, a.dt)[0]) <= TOL)
+
+
+def test_unsupported_mappings_are_refused():
+    w = dyadic_case(BCS[0], seed=27)
+    xy = nodes(w.grid, lambda x, y: x, lambda x, y: y)
+    ctx = H.from_workloads([w], precision=1)
+    with pytest.raises(H.HsgnError) as e:
+        ctx.set_mapping(0, *xy)
+    assert e.value.code == H.HSGN_ENOTSUP
+    ctx.close()
+    ctx = H.from_workloads([w])
+    with pytest.raises(H.HsgnError) as e:
+        ctx.set_mapping(0, -xy[0], xy[1])            # clockwise cells
+    assert e.value.code == H.HSGN_EINVAL
+    ctx.set_sponge(0, (0.5, 0.0, 0.0, 0.0), 1.0)
+    with pytest.raises(H.HsgnError) as e:
+        ctx.set_mapping(0, *xy)
+    assert e.value.code == H.HSGN_ENOTSUP
+    ctx.close()
+    ctx = H.from_workloads([w])
+    ctx.set_mapping(0, *xy)
+    with pytest.raises(H.HsgnError) as e:
+        ctx.set_sponge(0, (0.5, 0.0, 0.0, 0.0), 1.0)
+    assert e.value.code == H.HSGN_ENOTSUP
+    ctx.close()

@@ -279,10 +279,11 @@ HSGN_HD void prepare_cell(const StepParams &P, const RawCell<T> &r, T tau_pre, C
 
 // one side of a mapped edge: the cell's state (after the first source half
 // step) with its momentum rotated into the edge's frame (unit normal n,
-// tangent t), its primitives derived from the rotated state
+// tangent t), its primitives derived from the rotated state; eta is the
+// cell's surface for the hydrostatic jump (unchanged by the rotation)
 template <class T>
-HSGN_HD void mapped_side(const StepParams &P, const T *q, T b, T c2, T nx, T ny, T tx, T ty,
-                         Side<T> &sd)
+HSGN_HD void mapped_side(const StepParams &P, const T *q, T b, T c2, T eta, T nx, T ny, T tx,
+                         T ty, Side<T> &sd)
 {
     Cell<T> c;
     HSGN_UNROLL
@@ -292,7 +293,7 @@ HSGN_HD void mapped_side(const StepParams &P, const T *q, T b, T c2, T nx, T ny,
     c.b = b;
     c.c2 = c2;
     derive(P, c);
-    c.eta = c.h + c.b;
+    c.eta = eta;
     side_of<0>(c, sd);
 }
 
@@ -406,7 +407,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     const bool e_cols = ef && interior;
 
     T *ring = ln.ring();
-    T *base = ring + 3 * EIG_FIELDS * 64;        // mixed precision: 3 rows x 7 x 64
+    T *base = ring + 3 * (EIG_FIELDS + (MAP ? 5 : 0)) * 64;   // mixed precision: 3 rows x 7 x 64
     Side<T> yside_prev;          // lower cell of the next y-edge (y normal frame)
     int phi_c = 0, brk_c = 0;
     // sliding windows over rows k-2 (index 0), k-1 (1) and k (2), shifted
@@ -417,7 +418,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     int fl_w[3] = {0, 0, 0};     // interface edge flags (patch sets)
     T b_w[3];                    // bathymetry
     T kap_w[3] = {(T)1, (T)1, (T)1};   // capacities (mapped grids)
-    T qprev[7], bprev = (T)0, c2prev = (T)0;   // cell below (mapped y-edges)
+    T qprev[7], bprev = (T)0, c2prev = (T)0, etaprev = (T)0;   // cell below (mapped y-edges)
     HSGN_UNROLL
     for (int m = 0; m < 7; m++) qprev[m] = (T)0;
     Waves<T> yprev;              // waves of the y-edge below the new one
@@ -480,9 +481,9 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 T ql[7];
                 HSGN_UNROLL
                 for (int m = 0; m < 7; m++) ql[m] = ln.up(c.q[m]);
-                const T bl = ln.up(c.b), c2l = ln.up(c.c2);
-                mapped_side(P, ql, bl, c2l, met[1], met[2], (T)0 - met[2], met[1], sl);
-                mapped_side(P, c.q, c.b, c.c2, met[1], met[2], (T)0 - met[2], met[1], sr);
+                const T bl = ln.up(c.b), c2l = ln.up(c.c2), etal = ln.up(c.eta);
+                mapped_side(P, ql, bl, c2l, etal, met[1], met[2], (T)0 - met[2], met[1], sl);
+                mapped_side(P, c.q, c.b, c.c2, c.eta, met[1], met[2], (T)0 - met[2], met[1], sr);
             } else {
                 side_of<0>(c, sr);
                 shfl_side_up(ln, sr, sl);
@@ -546,8 +547,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             if (MAP) {
                 // frame of the bottom edge of cell (i, k): tangent (n_y, -n_x)
                 Side<T> ysl, ysr;
-                mapped_side(P, qprev, bprev, c2prev, met[4], met[5], met[5], (T)0 - met[4], ysl);
-                mapped_side(P, c.q, c.b, c.c2, met[4], met[5], met[5], (T)0 - met[4], ysr);
+                mapped_side(P, qprev, bprev, c2prev, etaprev, met[4], met[5], met[5], (T)0 - met[4], ysl);
+                mapped_side(P, c.q, c.b, c.c2, c.eta, met[4], met[5], met[5], (T)0 - met[4], ysr);
                 ok = edge_solve<0, MIXED && FB>(ln, P, ysl, ysr, yw, ye);
                 set_frame(yw, ye, met[4], met[5], met[5], (T)0 - met[4], met[6]);
             } else {
@@ -723,7 +724,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 T eta = acc[sk2][IH];
                 T h = eta + (T)P.eta0 - bb;
                 if (h < (T)0) {
-                    clip += -(double)h * pi.dx * pi.dy;
+                    clip += MAP ? -(double)h * (double)kap_w[sk2] * pi.dx * pi.dy
+                                : -(double)h * pi.dx * pi.dy;
                     h = (T)0;
                     eta = bb - (T)P.eta0;
                 }
@@ -787,7 +789,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             if (MAP) qprev[m] = c.q[m];
         }
         if (MAP) {
-            bprev = c.b; c2prev = c.c2;
+            bprev = c.b; c2prev = c.c2; etaprev = c.eta;
             kap_w[0] = kap_w[1]; kap_w[1] = kap_w[2];
         }
         phi_w[0] = phi_w[1]; phi_w[1] = phi_w[2];

@@ -94,18 +94,18 @@ void march_kernel(MarchArgs<S> A)
     }
 }
 
-// the step on mapped grids (FP64 single grids; launched for the whole work
-// table when some patch is mapped): one work item per block, the x-edge
-// frames also kept in the LDS ring
-template <class S, class T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// the step on mapped grids (single grids; launched for the whole work table
+// when some patch is mapped, without the split into item lists): one work
+// item per block, the x-edge frames also kept in the LDS ring
+template <class S, class T, bool MIXED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
 void march_kernel_mapped(MarchArgs<S> A)
 {
-    __shared__ T ring[3 * (EIG_FIELDS + 5) * 64];
+    __shared__ T ring[3 * (EIG_FIELDS + 5) * 64 + (MIXED ? 3 * 7 * 64 : 0)];
     GpuLanes<T> ln{ring};
     const int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;
-    march<GpuLanes<T>, S, T, false, false, true, false, true>(ln, A, wid);
+    march<GpuLanes<T>, S, T, MIXED, false, true, false, true>(ln, A, wid);
 }
 
 // The cells a work item's wavefront loads: columns i0-2..i0+61 clamped as

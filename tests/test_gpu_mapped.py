@@ -6,7 +6,8 @@ magnitude (the mapped kernel follows the oracle's operations, so the bits
 usually agree), masks equal; the identity mapping of a Cartesian grid gives
 the Cartesian run's bits; a Cartesian scenario stepped in the same launch as
 a mapped one keeps its bits; capacity-weighted mass against the oracle's;
-unsupported combinations refused.
+in mixed precision the gauges within 1e-4 of the amplitude of the FP64
+mapped run and a lake at rest exact; unsupported combinations refused.
 """
 import dataclasses
 
@@ -132,11 +133,6 @@ def test_cartesian_scenario_beside_a_mapped_one_keeps_its_bits():
 def test_unsupported_mappings_are_refused():
     w = dyadic_case(BCS[0], seed=27)
     xy = nodes(w.grid, lambda x, y: x, lambda x, y: y)
-    ctx = H.from_workloads([w], precision=1)
-    with pytest.raises(H.HsgnError) as e:
-        ctx.set_mapping(0, *xy)
-    assert e.value.code == H.HSGN_ENOTSUP
-    ctx.close()
     ctx = H.from_workloads([w])
     with pytest.raises(H.HsgnError) as e:
         ctx.set_mapping(0, -xy[0], xy[1])            # clockwise cells
@@ -152,3 +148,38 @@ def test_unsupported_mappings_are_refused():
         ctx.set_sponge(0, (0.5, 0.0, 0.0, 0.0), 1.0)
     assert e.value.code == H.HSGN_ENOTSUP
     ctx.close()
+
+
+def test_mixed_precision_mapped_gauges_against_fp64():
+    w = rough_case(61, 47, (W.BC_WALL, W.BC_EXTRAP, W.BC_WALL, W.BC_EXTRAP), seed=28)
+    xy = distorted(w.grid, amp=0.02)
+    dt = 0.8 * w.dt
+    rec = {}
+    for precision in (0, 1):
+        print("case", w.name, "distorted, precision", precision, flush=True)
+        ctx = H.from_workloads([w], precision=precision)
+        ctx.set_mapping(0, *xy)
+        ctx.advance(dt, 30)
+        rec[precision] = ctx.read_gauges(0)[1]
+        ctx.close()
+    ge = np.abs(rec[1] - rec[0]).max() / w.amplitude
+    print("mixed vs FP64 gauge error / amplitude", ge)
+    assert rec[0].shape == rec[1].shape and rec[0].size > 0
+    assert ge <= 1e-4
+
+
+def test_mixed_precision_lake_at_rest_on_a_distorted_grid_is_exact():
+    nx, ny = 40, 32
+    rng = np.random.default_rng(29)
+    b = W.fp32_representable(-1.0 - 0.3 * rng.random((ny, nx)))
+    q = np.zeros((7, ny, nx))
+    q[0] = -b
+    w = periodic_case(q, b)
+    print("case mixed lake at rest, distorted", flush=True)
+    ctx = H.from_workloads([w], precision=1)
+    ctx.set_mapping(0, *distorted(w.grid))
+    ctx.advance(w.dt, 20)
+    s = ctx.get_state(0)
+    ctx.close()
+    assert np.abs(s[0] + b).max() == 0.0
+    assert np.abs(s[1:]).max() == 0.0

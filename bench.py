@@ -45,6 +45,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -95,12 +97,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# mapped-grid runs (--mapped): node coordinates per scenario, or None
+MAPPING = None
+
+
+def distorted_nodes(g, amp=0.005):
+    """nodes [ny + 5][nx + 5] (two ghost layers) of a smooth distortion of a
+    single grid: each node moved by amp times the domain size along smooth
+    sine profiles (capacities within about 10% of 1)"""
+    xi = g.x0 + np.arange(-2, g.nx + 3) * g.dx
+    eta = g.y0 + np.arange(-2, g.ny + 3) * g.dy
+    XI, ETA = np.meshgrid(xi, eta)
+    Lx, Ly = g.nx * g.dx, g.ny * g.dy
+    X = XI + amp * Lx * np.sin(2 * np.pi * ETA / Ly) * np.cos(2 * np.pi * XI / Lx)
+    Y = ETA + amp * Ly * np.sin(2 * np.pi * XI / Lx) * np.sin(4 * np.pi * ETA / Ly)
+    return X, Y
+
+
 def make_context(H, ws, precision, tile_rows=0, gauges=True):
     ctx = H.Context(ws[0].params, tile_rows=tile_rows, precision=1 if precision == "mixed" else 0)
     for s, w in enumerate(ws):
         ctx.add_grid(s, w.grid)
     ctx.finalize()
     for s, w in enumerate(ws):
+        if MAPPING is not None:
+            ctx.set_mapping(s, *MAPPING[s])
         ctx.set_bathymetry(s, w.b)
         ctx.set_state(s, w.q)
         if gauges and len(w.gauges):
@@ -198,21 +219,24 @@ def amr_updates(w):
     return sum(p.nx * p.ny * 4 ** p.level for p in w.patches)
 
 
-def cpu_baseline(w, steps):
-    """The FP64 oracle as it stands, on `steps` steps of one workload."""
+def cpu_baseline(w, steps, nodes=None):
+    """The FP64 oracle as it stands, on `steps` steps of one workload (on its
+    mapped grid when node coordinates are given)."""
     from oracle import oracle as O
     if not os.path.exists(O.LIB_PATH):
         O.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     g = O.from_workload(w)
+    if nodes is not None:
+        g.set_mapping(*nodes)
     t0 = time.perf_counter()
     g.advance(w.dt, steps)
     el = time.perf_counter() - t0
     cells = w.grid.nx * w.grid.ny
     return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": "first %d steps of %s (%d cell-updates), wall %.1f s, FP64"
-                      % (steps, w.name, cells * steps, el)}
+            "sample": "first %d steps of %s%s (%d cell-updates), wall %.1f s, FP64"
+                      % (steps, w.name, " (mapped)" if nodes is not None else "", cells * steps, el)}
 
 
 def gauge_error(ctx_a, ctx_b, ws):
@@ -248,6 +272,8 @@ def main():
                     help="fixed tile height (default: the library's autotuner)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's tile-height model instead of its autotuner")
+    ap.add_argument("--mapped", action="store_true",
+                    help="ensemble or ocean on smoothly distorted mapped grids (fixed steps 0.85x)")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
@@ -289,6 +315,13 @@ def main():
     else:
         ws, precision = [W.beach_soliton()], "fp64"
     amr = args.workload == "amr"
+    if args.mapped:
+        global MAPPING
+        if amr or args.workload not in ("ensemble", "ocean"):
+            sys.exit("--mapped applies to the ensemble and ocean workloads")
+        MAPPING = [distorted_nodes(w.grid) for w in ws]
+        for w in ws:
+            w.dt = 0.85 * w.dt
     if args.model == "mbhsgn":
         import dataclasses
         for w in ws:
@@ -322,7 +355,7 @@ def main():
         % (el * 1e3 / args.steps, kms * 1e3, value))
     tflops = ALG_FLOPS * cells_per_launch / (kms / 1e3) / 1e12
     hbm_gbs = ALG_BYTES[precision] * cells_per_launch / (kms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, precision, rows)
+    traffic = None if args.mapped else measured_traffic(args.workload, precision, rows)
     dtype = {"mixed": "f32+f64", "fp64": "f64"}[precision]
     out = {
         "metric": "cell-updates/s",
@@ -337,7 +370,8 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": ws[0].name if len(ws) == 1 else "ensemble_%d_scenarios" % len(ws),
+        "config": {"workload": (ws[0].name if len(ws) == 1 else "ensemble_%d_scenarios" % len(ws))
+                               + ("_mapped" if args.mapped else ""),
                    "scenarios": len(ws), "cell_updates_per_step": cells, "precision": precision,
                    "model": args.model,
                    "dt": "per-scenario fixed, cfl 0.9" if ws[0].dt > 0 else "adaptive, cfl 0.9",
@@ -345,7 +379,8 @@ def main():
                    "max_courant_scenario0": diag["max_courant"]},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": STEP_KERNELS[precision], "kernel_avg_us": kms * 1e3,
+                     "kernel": ("march_kernel_mapped<%s> (every item)" % precision) if args.mapped
+                               else STEP_KERNELS[precision], "kernel_avg_us": kms * 1e3,
                      "launches": launches, "alg_flops_per_cell": ALG_FLOPS,
                      "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": hbm_gbs / HBM_PEAK_GBS,
@@ -369,7 +404,7 @@ def main():
         steps = args.cpu_steps or (60 if args.workload == "ensemble" else 20)
         # patch sets: the oracle on the level-0 ocean grid of the same set
         base = W.synthetic_ocean() if amr else ws[0]
-        out["cpu_baseline"] = cpu_baseline(base, steps)
+        out["cpu_baseline"] = cpu_baseline(base, steps, MAPPING[0] if MAPPING is not None else None)
     print(json.dumps(out), flush=True)
 
 

@@ -180,9 +180,7 @@ int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rat
  * in the physical frame; walls mirror the momentum about the wall edge.
  * Gauges and the sponge layer use computational coordinates.  Mass in
  * hsgn_diagnostics is sum(capacity h) dx dy.
- * After hsgn_finalize; may be called again to change the mapping.  In mixed
- * precision a context with a mapped patch steps every item with one kernel
- * (no split into item lists).
+ * After hsgn_finalize; may be called again to change the mapping.
  * HSGN_ENOTSUP: patch sets, or a context with a sponge layer.  HSGN_EINVAL: bad patch, null pointers, or a cell of non-positive
  * area or an edge of zero length (the patch keeps its previous geometry). */
 int hsgn_set_mapping(hsgn_ctx *ctx, int patch, const double *xn, const double *yn);

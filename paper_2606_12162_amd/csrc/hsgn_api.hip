@@ -1977,7 +1977,7 @@ static void launch_mixed_split(hsgn_ctx *c, const MarchArgs<float> &A, unsigned 
 // the split's buffers for items [w0, w1) of the context's work table
 static void split_args(hsgn_ctx *c, MarchArgs<float> &A, int w0)
 {
-    if (!c->split || c->any_mapped) return;      // mapped grids: one kernel over all items
+    if (!c->split) return;
     A.list = c->d_list + 2 * w0;
     A.lcnt = c->d_lcnt;
     A.clsb = c->d_clsb + w0;
@@ -2059,7 +2059,7 @@ static void launch_level(hsgn_ctx *c, int l, double theta, hipStream_t s, bool t
 // every level, after a bathymetry or work-table change
 static void refresh_static_classes(hsgn_ctx *c)
 {
-    if (!c->split || c->any_mapped || !c->clsb_dirty) return;
+    if (!c->split || !c->clsb_dirty) return;
     for (int l = 0; l < c->nlev; l++) {
         const LevelRange &R = c->L[l];
         if (R.wa > R.w0)
@@ -2303,7 +2303,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                     if (c->mixed) {
                         MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, na);
                         A.work = dwork; A.clip_slots = dclip;
-                        if (c->split && !c->any_mapped) {
+                        if (c->split) {
                             A.list = dlist;
                             A.lcnt = dlcnt;
                             A.clsb = dclsb;

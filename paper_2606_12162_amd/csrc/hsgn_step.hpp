@@ -95,17 +95,29 @@ void march_kernel(MarchArgs<S> A)
 }
 
 // the step on mapped grids (single grids; launched for the whole work table
-// when some patch is mapped, without the split into item lists): one work
-// item per block, the x-edge frames also kept in the LDS ring
-template <class S, class T, bool MIXED>
+// when some patch is mapped), with the x-edge frames also kept in the LDS
+// ring; items and lists as in march_kernel
+template <class S, class T, bool MIXED, bool FB = true>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
 void march_kernel_mapped(MarchArgs<S> A)
 {
     __shared__ T ring[3 * (EIG_FIELDS + 5) * 64 + (MIXED ? 3 * 7 * 64 : 0)];
     GpuLanes<T> ln{ring};
-    const int wid = (int)blockIdx.x;
-    if (wid >= A.nwork) return;
-    march<GpuLanes<T>, S, T, MIXED, false, true, false, true>(ln, A, wid);
+    if (MIXED && FB) {
+        const unsigned n = A.list ? A.lcnt[1] : (unsigned)A.nwork;
+        for (unsigned b = blockIdx.x; b < n; b += gridDim.x) {     // uniform over the wavefront
+            const int wid = A.list ? A.list[A.nwork + (int)b] : (int)b;
+            march<GpuLanes<T>, S, T, MIXED, false, FB, false, true>(ln, A, wid);
+        }
+    } else {
+        int wid = (int)blockIdx.x;
+        if (wid >= A.nwork) return;
+        if (A.list) {                                               // uniform over the wavefront
+            if ((unsigned)wid >= A.lcnt[0]) return;
+            wid = A.list[wid];
+        }
+        march<GpuLanes<T>, S, T, MIXED, false, FB, false, true>(ln, A, wid);
+    }
 }
 
 // The cells a work item's wavefront loads: columns i0-2..i0+61 clamped as

@@ -16,7 +16,7 @@ constexpr unsigned FB_BLOCKS = 1024;
 void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream, bool beside)
 {
     const unsigned grid = A.list && beside && nwork > FB_BLOCKS ? FB_BLOCKS : nwork;
-    if (A.mapped) march_kernel_mapped<float, float, true><<<nwork, 64, 0, stream>>>(A);
+    if (A.mapped) march_kernel_mapped<float, float, true, true><<<grid, 64, 0, stream>>>(A);
     else if (A.sponge) march_kernel<float, float, true, false, true, true><<<grid, 64, 0, stream>>>(A);
     else march_kernel<float, float, true, false, true, false><<<grid, 64, 0, stream>>>(A);
 }
@@ -24,7 +24,8 @@ void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t strea
 // the kernel without the FP64 edge solve, over the other list
 void launch_march32_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
 {
-    if (A.sponge) march_kernel<float, float, true, false, false, true><<<nwork, 64, 0, stream>>>(A);
+    if (A.mapped) march_kernel_mapped<float, float, true, false><<<nwork, 64, 0, stream>>>(A);
+    else if (A.sponge) march_kernel<float, float, true, false, false, true><<<nwork, 64, 0, stream>>>(A);
     else march_kernel<float, float, true, false, false, false><<<nwork, 64, 0, stream>>>(A);
 }
 

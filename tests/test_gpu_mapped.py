@@ -183,3 +183,27 @@ def test_mixed_precision_lake_at_rest_on_a_distorted_grid_is_exact():
     ctx.close()
     assert np.abs(s[0] + b).max() == 0.0
     assert np.abs(s[1:]).max() == 0.0
+
+
+def test_mixed_mapped_split_step_is_bitwise_the_full_kernel(monkeypatch):
+    """mixed precision on a mapped ocean with deep plain, shelf and dry coast:
+    the split step (items without near-shore edges on the kernel compiled
+    without the FP64 re-solve) gives the bits of the full kernel"""
+    w = W.synthetic_ocean(n=512, dx=2000.0, steps=40)
+    g = w.grid
+    xi = g.x0 + np.arange(-2, g.nx + 3) * g.dx
+    eta = g.y0 + np.arange(-2, g.ny + 3) * g.dy
+    XI, ETA = np.meshgrid(xi, eta)
+    L = g.nx * g.dx
+    xy = (XI + 0.005 * L * np.sin(2 * np.pi * ETA / L), ETA + 0.005 * L * np.sin(2 * np.pi * XI / L))
+    runs = []
+    for nosplit in ("0", "1"):
+        monkeypatch.setenv("HSGN_NO_KERNEL_SPLIT", nosplit)
+        print("case", w.name, "mapped, no_split", nosplit, flush=True)
+        ctx = H.from_workloads([w], precision=1)
+        ctx.set_mapping(0, *xy)
+        ctx.advance(0.85 * w.dt, 40)
+        runs.append((ctx.get_state(0), ctx.get_mask(0), ctx.read_gauges(0)[1]))
+        ctx.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)

@@ -41,15 +41,31 @@
 #include <string.h>
 #include "hsgn_oracle.h"
 
+/* Working precision.  The oracle is FP64 (real = double).  Built with
+ * -DORC_LONG_DOUBLE the same source computes in x87 extended precision
+ * (64-bit significand) behind the same FP64 interface: that build measures
+ * how far the FP64 evaluation itself is from the exact result of the method
+ * on a case (its conditioning); it is never the reference of a parity test. */
+#ifdef ORC_LONG_DOUBLE
+typedef long double real;
+#define sqrt sqrtl
+#define fabs fabsl
+#define fmin fminl
+#define fmax fmaxl
+#define floor floorl
+#else
+typedef double real;
+#endif
+
 enum { IH = 0, IHU = 1, IHV = 2, IHW = 3, IHS = 4, IHP = 5, IHPB = 6 };
 
 struct orc_grid {
     orc_params P;
     int nx, ny, sx, sy;         /* sx = nx + 4, sy = ny + 4: two ghost layers */
-    double x0, y0, dx, dy;
+    real x0, y0, dx, dy;
     int bc[4];
-    double *q;                  /* [7][sy][sx] */
-    double *b;                  /* [sy][sx] */
+    real *q;                  /* [7][sy][sx] */
+    real *b;                  /* [sy][sx] */
     unsigned char *phi;         /* [sy][sx] transition function phi_T */
     unsigned char *brk;         /* [sy][sx] breaking latch */
     /* patch sets: ghosts written by the caller instead of the boundary map,
@@ -60,24 +76,24 @@ struct orc_grid {
     /* sponge layer: widths from the domain's x-low, x-high, y-low, y-high
      * sides (0: none), peak rate, and the grid's place in its level's
      * domain (global index of cell (0, 0), domain size in cells) */
-    double sp_w[4], sp_rate;
+    real sp_w[4], sp_rate;
     long long sp_i0, sp_j0, sp_nx, sp_ny;
     /* mapped grid (planar, logically rectangular; NULL on Cartesian grids),
      * [sy][sx] like the cells: kap the cell's capacity (area over dx dy);
      * xn*, xgm the unit normal (towards increasing i) and length ratio
      * (length over dy) of the cell's left edge; yn*, ygm the same for its
      * bottom edge (towards increasing j, length over dx) */
-    double *kap, *xnx, *xny, *xgm, *ynx, *yny, *ygm;
-    double t, dt_next;
+    real *kap, *xnx, *xny, *xgm, *ynx, *yny, *ygm;
+    real t, dt_next;
     long long nstep, nrej;
     int have_dt;
-    double clipped;
+    real clipped;
     int ngauge;
-    double *gxy;
+    real *gxy;
     int nrec, caprec;
-    double *rec_t, *rec_eta;
+    real *rec_t, *rec_eta;
     /* per-step work arrays, allocated on the first step */
-    double *w_qs, *w_c2, *w_Flim, *w_Ftr, *w_Glim, *w_Gtr, *w_clip;
+    real *w_qs, *w_c2, *w_Flim, *w_Ftr, *w_Glim, *w_Gtr, *w_clip;
     struct edge_s *w_EX, *w_EY;
 };
 
@@ -105,9 +121,9 @@ static int map_index(int i, int n, int lo, int hi, int *flip)
 
 /* m - 2 (m . n) n: the momentum (hu, hv) mirrored about a wall of unit
  * normal n */
-static void reflect(double *hu, double *hv, double nx, double ny)
+static void reflect(real *hu, real *hv, real nx, real ny)
 {
-    double a = *hu * nx + *hv * ny;
+    real a = *hu * nx + *hv * ny;
     *hu = *hu - 2.0 * a * nx;
     *hv = *hv - 2.0 * a * ny;
 }
@@ -147,15 +163,15 @@ static void fill_ghosts(orc_grid *g)
 }
 
 /* still-water depth H = (eta0 - b)^+ */
-static double still_depth(const orc_params *P, double b)
+static real still_depth(const orc_params *P, real b)
 {
-    double H = P->eta0 - b;
+    real H = P->eta0 - b;
     return H > 0.0 ? H : 0.0;
 }
 
 /* c^2 = alpha^2 g H phi_T, or the fixed c^2 of the run times phi_T; zero in
    SWE cells (phi_T = 0 or breaking) */
-static double cell_c2(const orc_grid *g, size_t k)
+static real cell_c2(const orc_grid *g, size_t k)
 {
     if (!g->phi[k] || g->brk[k]) return 0.0;
     if (g->P.c2 > 0.0) return g->P.c2;
@@ -179,8 +195,8 @@ orc_grid *orc_create(const orc_params *p, int nx, int ny, double x0, double y0,
     g->x0 = x0; g->y0 = y0; g->dx = dx; g->dy = dy;
     memcpy(g->bc, bc, 4 * sizeof(int));
     size_t np = PLANE(g);
-    g->q = (double *)calloc(ORC_NV * np, sizeof(double));
-    g->b = (double *)calloc(np, sizeof(double));
+    g->q = (real *)calloc(ORC_NV * np, sizeof(real));
+    g->b = (real *)calloc(np, sizeof(real));
     g->phi = (unsigned char *)calloc(np, 1);
     g->brk = (unsigned char *)calloc(np, 1);
     g->iface = (unsigned char *)calloc(np, 1);
@@ -211,13 +227,13 @@ int orc_set_bathymetry(orc_grid *g, const double *b)
     int n = g->P.nbr_n;
     for (int j = 0; j < g->ny; j++) {
         for (int i = 0; i < g->nx; i++) {
-            double hmin = INFINITY;
+            real hmin = INFINITY;
             for (int dj = -n; dj <= n; dj++) {
                 for (int di = -n; di <= n; di++) {
                     int fx, fy;
                     int mi = map_index(i + di, g->nx, g->bc[0], g->bc[1], &fx);
                     int mj = map_index(j + dj, g->ny, g->bc[2], g->bc[3], &fy);
-                    double H = still_depth(&g->P, g->b[CELL(g, mi, mj)]);
+                    real H = still_depth(&g->P, g->b[CELL(g, mi, mj)]);
                     if (H < hmin) hmin = H;
                 }
             }
@@ -281,73 +297,97 @@ int orc_set_mask(orc_grid *g, const unsigned char *m)
  * gamma = 1 - 1/sqrt(2): Y1 = Y + gamma tau f(Y1),
  * Y2 = Y + (1-gamma) tau f(Y1) + gamma tau f(Y2), result Y2. */
 
-/* One SDIRK stage: solve (I - k M) X = R with k = gamma tau / h and M the
- * matrix above (acting on w, sigma, p, p_b).  The hw and hp rows give
- * X0 = R0 + k X3 and X2 = R2 - k c^2 X1; substituting them into the
- * h sigma and h p_b rows leaves
- *   (1 + 12 k^2 c^2) X1 + 6 k X3        = R1 + 12 k R2
- *   -3 k c^2 X1      + (1 + 6 k^2 c^2) X3 = R3 - 6 k c^2 R0
- * which is solved by Cramer's rule. */
-static void stage_solve(double k, double c2, const double R[4], double X[4])
+/* Gaussian elimination with partial pivoting on the n x n system A x = b
+ * (row-major A); b is overwritten by x. */
+static void solve_lin(int n, real *A, real *b)
 {
-    double kc2 = k * c2;
-    double a = 1.0 + 12.0 * k * kc2;
-    double d = 1.0 + 6.0 * k * kc2;
-    double det = a * d + 18.0 * k * kc2;
-    double r1 = R[1] + 12.0 * k * R[2];
-    double r3 = R[3] - 6.0 * kc2 * R[0];
-    double idet = 1.0 / det;
-    double x1 = (d * r1 - 6.0 * k * r3) * idet;
-    double x3 = (a * r3 + 3.0 * kc2 * r1) * idet;
-    X[0] = R[0] + k * x3;
-    X[1] = x1;
-    X[2] = R[2] - kc2 * x1;
-    X[3] = x3;
+    for (int k = 0; k < n; k++) {
+        int piv = k;
+        for (int r = k + 1; r < n; r++)
+            if (fabs(A[r * n + k]) > fabs(A[piv * n + k])) piv = r;
+        if (piv != k) {
+            for (int c = 0; c < n; c++) {
+                real t = A[k * n + c]; A[k * n + c] = A[piv * n + c]; A[piv * n + c] = t;
+            }
+            real t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int r = k + 1; r < n; r++) {
+            real f = A[r * n + k] / A[k * n + k];
+            for (int c = k; c < n; c++) A[r * n + c] -= f * A[k * n + c];
+            b[r] -= f * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; k--) {
+        real s = b[k];
+        for (int c = k + 1; c < n; c++) s -= A[k * n + c] * b[c];
+        b[k] = s / A[k * n + k];
+    }
 }
 
-void orc_source_cell(double *q, double c2, double tau)
+/* The SDIRK(2,2) step of length tau for dY/dt = J Y / tau with the n x n
+ * matrix J = (tau / h) M: stage 1 solves (I - gamma J) Y1 = Y, stage 2
+ * solves (I - gamma J) Y2 = Y + (1 - gamma) J Y1; Y2 replaces Y. */
+static void sdirk22(int n, const real *J, real *Y)
 {
-    double gam = 1.0 - 1.0 / sqrt(2.0);
-    double th = tau / q[IH];
-    double k = gam * th;
-    double Y[4] = {q[IHW], q[IHS], q[IHP], q[IHPB]};
-    double Y1[4], R[4], Y2[4];
-    /* stage 1: Y1 = Y + gamma tau f(Y1) */
-    stage_solve(k, c2, Y, Y1);
-    /* stage 2: Y2 = Y + (1 - gamma) tau f(Y1) + gamma tau f(Y2), with
-     * tau f(Y1) = (tau / h) M Y1 */
-    double MY[4] = {Y1[3], 12.0 * Y1[2] - 6.0 * Y1[3], -c2 * Y1[1],
-                    -6.0 * c2 * Y1[0] + 3.0 * c2 * Y1[1]};
-    for (int r = 0; r < 4; r++) R[r] = Y[r] + (1.0 - gam) * (th * MY[r]);
-    stage_solve(k, c2, R, Y2);
-    q[IHW] = Y2[0]; q[IHS] = Y2[1]; q[IHP] = Y2[2]; q[IHPB] = Y2[3];
+    const real gam = 1.0 - 1.0 / sqrt(2.0);
+    real A[16], Y1[4], Y2[4];
+    for (int r = 0; r < n; r++)
+        for (int c = 0; c < n; c++) A[r * n + c] = (r == c ? 1.0 : 0.0) - gam * J[r * n + c];
+    for (int r = 0; r < n; r++) Y1[r] = Y[r];
+    solve_lin(n, A, Y1);
+    for (int r = 0; r < n; r++) {
+        real s = 0.0;
+        for (int c = 0; c < n; c++) s += J[r * n + c] * Y1[c];
+        Y2[r] = Y[r] + (1.0 - gam) * s;
+    }
+    for (int r = 0; r < n; r++)
+        for (int c = 0; c < n; c++) A[r * n + c] = (r == c ? 1.0 : 0.0) - gam * J[r * n + c];
+    solve_lin(n, A, Y2);
+    for (int r = 0; r < n; r++) Y[r] = Y2[r];
+}
+
+static void source_cell(real *q, real c2, real tau)
+{
+    const real M[16] = {
+        0.0,       0.0,      0.0,  1.0,
+        0.0,       0.0,      12.0, -6.0,
+        0.0,       -c2,      0.0,  0.0,
+        -6.0 * c2, 3.0 * c2, 0.0,  0.0,
+    };
+    real J[16];
+    for (int r = 0; r < 16; r++) J[r] = (tau / q[IH]) * M[r];
+    real Y[4] = {q[IHW], q[IHS], q[IHP], q[IHPB]};
+    sdirk22(4, J, Y);
+    q[IHW] = Y[0]; q[IHS] = Y[1]; q[IHP] = Y[2]; q[IHPB] = Y[3];
 }
 
 /* mbHSGN source (Sec. 3, eq. mbHSGN): d(hw)/dt = 3 p / 2 and
  * d(hp)/dt = -2 c^2 w, i.e. dY/dt = (1/h) [[0, 3/2], [-2 c^2, 0]] Y for
- * Y = (hw, hp), by the same SDIRK(2,2).  A stage (I - k M) X = R has the
- * closed form X0 = (R0 + 3/2 k R1) / det, X1 = (R1 - 2 c^2 k R0) / det with
- * det = 1 + 3 c^2 k^2. */
-static void stage_solve_mb(double k, double c2, const double R[2], double X[2])
+ * Y = (hw, hp), by the same SDIRK(2,2). */
+static void source_cell_mb(real *q, real c2, real tau)
 {
-    double kc2 = k * c2;
-    double idet = 1.0 / (1.0 + 3.0 * k * kc2);
-    X[0] = (R[0] + 1.5 * k * R[1]) * idet;
-    X[1] = (R[1] - 2.0 * kc2 * R[0]) * idet;
+    const real M[4] = {0.0, 1.5, -2.0 * c2, 0.0};
+    real J[4];
+    for (int r = 0; r < 4; r++) J[r] = (tau / q[IH]) * M[r];
+    real Y[2] = {q[IHW], q[IHP]};
+    sdirk22(2, J, Y);
+    q[IHW] = Y[0]; q[IHP] = Y[1];
+}
+
+void orc_source_cell(double *q, double c2, double tau)
+{
+    real v[7];
+    for (int m = 0; m < 7; m++) v[m] = q[m];
+    source_cell(v, c2, tau);
+    for (int m = 0; m < 7; m++) q[m] = (double)v[m];
 }
 
 void orc_source_cell_mb(double *q, double c2, double tau)
 {
-    double gam = 1.0 - 1.0 / sqrt(2.0);
-    double th = tau / q[IH];
-    double k = gam * th;
-    double Y[2] = {q[IHW], q[IHP]};
-    double Y1[2], R[2], Y2[2];
-    stage_solve_mb(k, c2, Y, Y1);
-    double MY[2] = {1.5 * Y1[1], -2.0 * c2 * Y1[0]};
-    for (int r = 0; r < 2; r++) R[r] = Y[r] + (1.0 - gam) * (th * MY[r]);
-    stage_solve_mb(k, c2, R, Y2);
-    q[IHW] = Y2[0]; q[IHP] = Y2[1];
+    real v[7];
+    for (int m = 0; m < 7; m++) v[m] = q[m];
+    source_cell_mb(v, c2, tau);
+    for (int m = 0; m < 7; m++) q[m] = (double)v[m];
 }
 
 /* apply the source step of length tau to one cell, or clear the auxiliary
@@ -357,29 +397,29 @@ void orc_source_cell_mb(double *q, double c2, double tau)
  * side's width, s = (w - d) / w inside the band; the largest s over the
  * sides gives sigma = rate s^2 (a reading: the sponge is cited, not
  * described) */
-static double sponge_sigma(const orc_grid *g, int i, int j)
+static real sponge_sigma(const orc_grid *g, int i, int j)
 {
     const long long I = g->sp_i0 + i, J = g->sp_j0 + j;
-    const double d[4] = {((double)I + 0.5) * g->dx, ((double)(g->sp_nx - 1 - I) + 0.5) * g->dx,
-                         ((double)J + 0.5) * g->dy, ((double)(g->sp_ny - 1 - J) + 0.5) * g->dy};
-    double s = 0.0;
+    const real d[4] = {((real)I + 0.5) * g->dx, ((real)(g->sp_nx - 1 - I) + 0.5) * g->dx,
+                         ((real)J + 0.5) * g->dy, ((real)(g->sp_ny - 1 - J) + 0.5) * g->dy};
+    real s = 0.0;
     for (int e = 0; e < 4; e++) {
-        const double w = g->sp_w[e];
+        const real w = g->sp_w[e];
         if (w > 0.0 && d[e] < w) {
-            const double t = (w - d[e]) / w;
+            const real t = (w - d[e]) / w;
             if (t > s) s = t;
         }
     }
     return g->sp_rate * (s * s);
 }
 
-static void source_or_clear(orc_grid *g, size_t k, double tau, double *qc)
+static void source_or_clear(orc_grid *g, size_t k, real tau, real *qc)
 {
     int wet = qc[IH] > g->P.dry_tol;
     int swe = !g->phi[k] || g->brk[k];
     if (wet && !swe) {
-        if (g->P.model == 1) orc_source_cell_mb(qc, cell_c2(g, k), tau);
-        else orc_source_cell(qc, cell_c2(g, k), tau);
+        if (g->P.model == 1) source_cell_mb(qc, cell_c2(g, k), tau);
+        else source_cell(qc, cell_c2(g, k), tau);
     } else {
         qc[IHW] = 0.0; qc[IHS] = 0.0; qc[IHP] = 0.0; qc[IHPB] = 0.0;
     }
@@ -392,65 +432,64 @@ static void source_or_clear(orc_grid *g, size_t k, double tau, double *qc)
  * h p_b).  The y-direction solve permutes hu and hv before and after. */
 
 typedef struct {
-    double uh, vh, wh, sh, ph, pbh;  /* Roe-type averages, normal frame */
-    double hh, c2h, ce2;             /* arithmetic means, Ce^2 */
-    double smin, smax;               /* Einfeldt speeds */
+    real uh, vh, wh, sh, ph, pbh;  /* Roe-type averages, normal frame */
+    real hh, c2h, ce2;             /* arithmetic means, Ce^2 */
+    real smin, smax;               /* Einfeldt speeds */
     int wet;                         /* both cells wet: usable for splitting */
 } eig_t;
 
 typedef struct edge_s {
-    double Z[7][7];     /* Z[p][m]: f-wave p, component m (normal frame) */
-    double s[7];        /* speed of f-wave p */
-    double amdq[7], apdq[7];
+    real Z[7][7];     /* Z[p][m]: f-wave p, component m (normal frame) */
+    real s[7];        /* speed of f-wave p */
+    real amdq[7], apdq[7];
     int kind;           /* 0 regular, 1 wall (right dry), 2 wall (left dry), 3 dry */
     eig_t e;
 } edge_t;
 
 /* bathymetry sharpness sensor psi(b_i, b_{i-1}) of Sec. 4 */
-static double sensor(const orc_params *P, double bL, double bR)
+static real sensor(const orc_params *P, real bL, real bR)
 {
-    double db = bR - bL;
+    real db = bR - bL;
     if (db == 0.0) return 1.0;
-    double sum = fabs(bR + bL);
+    real sum = fabs(bR + bL);
     if (sum == 0.0) return 0.0;
-    double xi = 2.0 * fabs(db) / sum;
+    real xi = 2.0 * fabs(db) / sum;
     if (xi < P->xi0) return 1.0;
     if (xi < P->xi0 + P->xi1) {
-        double r = (xi - P->xi0) / P->xi1;
+        real r = (xi - P->xi0) / P->xi1;
         return -3.0 * r * r + 2.0 * r * r * r + 1.0;
     }
     return 0.0;
 }
 
 typedef struct {
-    double h, hun, un, ut, w, sg, p, pb, hp;
+    real h, hun, un, ut, w, sg, p, pb, hp;
 } side_t;
 
 /* primitive variables of one side; a dry side (h <= dry_tol) keeps its
  * depth, so that a thin film at rest stays in balance, and has zero velocity
  * and auxiliary variables */
-static void side_from_q(const orc_params *P, const double *q, side_t *s)
+static void side_from_q(const orc_params *P, const real *q, side_t *s)
 {
     memset(s, 0, sizeof(*s));
     s->h = q[IH] > 0.0 ? q[IH] : 0.0;
     if (q[IH] > P->dry_tol) {
-        double ih = 1.0 / q[IH];
         s->h = q[IH];
         s->hun = q[IHU];
-        s->un = q[IHU] * ih;
-        s->ut = q[IHV] * ih;
-        s->w = q[IHW] * ih;
-        s->sg = q[IHS] * ih;
-        s->p = q[IHP] * ih;
-        s->pb = q[IHPB] * ih;
+        s->un = q[IHU] / q[IH];
+        s->ut = q[IHV] / q[IH];
+        s->w = q[IHW] / q[IH];
+        s->sg = q[IHS] / q[IH];
+        s->p = q[IHP] / q[IH];
+        s->pb = q[IHPB] / q[IH];
         s->hp = q[IHP];
     }
 }
 
-static int riemann_n(const orc_params *P, const double *qL, const double *qR,
-                     double bL, double bR, double c2L, double c2R, edge_t *E)
+static int riemann_n(const orc_params *P, const real *qL, const real *qR,
+                     real bL, real bR, real c2L, real c2R, edge_t *E)
 {
-    const double g = P->g;
+    const real g = P->g;
     memset(E, 0, sizeof(*E));
     int wetL = qL[IH] > P->dry_tol, wetR = qR[IH] > P->dry_tol;
     if (!wetL && !wetR) { E->kind = 3; return ORC_OK; }
@@ -458,7 +497,7 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
     side_t L, R;
     side_from_q(P, qL, &L);
     side_from_q(P, qR, &R);
-    double bl = bL, br = bR, cl = c2L, cr = c2R;
+    real bl = bL, br = bR, cl = c2L, cr = c2R;
     int dryL = 0, dryR = 0;
     /* wet/dry states: a dry neighbour whose bed lies above the wet side's
      * surface acts as a wall (mirror state); otherwise the dry side enters
@@ -484,27 +523,26 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
 
     /* Roe-type interface state: arithmetic means of h and c^2, sqrt(h)
      * weighted means of the primitive variables */
-    double sqL = sqrt(L.h), sqR = sqrt(R.h);
-    double iden = 1.0 / (sqL + sqR);
-    double hh = 0.5 * (L.h + R.h);
-    double c2h = 0.5 * (cl + cr);
-    double uh = (sqR * R.un + sqL * L.un) * iden;
-    double vh = (sqR * R.ut + sqL * L.ut) * iden;
-    double wh = (sqR * R.w + sqL * L.w) * iden;
-    double sh = (sqR * R.sg + sqL * L.sg) * iden;
-    double ph = (sqR * R.p + sqL * L.p) * iden;
-    double pbh = (sqR * R.pb + sqL * L.pb) * iden;
+    real sqL = sqrt(L.h), sqR = sqrt(R.h);
+    real hh = 0.5 * (L.h + R.h);
+    real c2h = 0.5 * (cl + cr);
+    real uh = (sqR * R.un + sqL * L.un) / (sqL + sqR);
+    real vh = (sqR * R.ut + sqL * L.ut) / (sqL + sqR);
+    real wh = (sqR * R.w + sqL * L.w) / (sqL + sqR);
+    real sh = (sqR * R.sg + sqL * L.sg) / (sqL + sqR);
+    real ph = (sqR * R.p + sqL * L.p) / (sqL + sqR);
+    real pbh = (sqR * R.pb + sqL * L.pb) / (sqL + sqR);
 
-    double psi = sensor(P, bl, br);
-    double db = br - bl;
-    double dh = R.h - L.h;
-    double deta = (R.h + br) - (L.h + bl);
+    real psi = sensor(P, bl, br);
+    real db = br - bl;
+    real dh = R.h - L.h;
+    real deta = (R.h + br) - (L.h + bl);
 
     /* total fluctuation: flux difference plus one-point quadrature of the
      * non-conservative products and bathymetry terms at the Roe state.
      * The hydrostatic part is written as g h^ (Delta eta), which equals
      * Delta(g h^2 / 2) + g h^ Delta b exactly. */
-    double df[7];
+    real df[7];
     df[0] = R.hun - L.hun;
     df[2] = R.hun * R.ut - L.hun * L.ut;
     df[3] = R.hun * R.w - L.hun * L.w;
@@ -523,21 +561,21 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
     }
 
     /* Einfeldt speeds from the eigenvalue bound u +- sqrt(g h + p + c^2) */
-    double ce2 = g * hh + ph + c2h;
+    real ce2 = g * hh + ph + c2h;
     if (!(ce2 > 0.0)) return ORC_ENONHYP;
-    double ceh = sqrt(ce2);
-    double smin, smax;
+    real ceh = sqrt(ce2);
+    real smin, smax;
     if (dryL) {
         smin = R.un - 2.0 * sqrt(g * R.h);
     } else {
-        double a = g * L.h + L.p + cl;
+        real a = g * L.h + L.p + cl;
         if (a < 0.0) return ORC_ENONHYP;
         smin = fmin(uh - ceh, L.un - sqrt(a));
     }
     if (dryR) {
         smax = L.un + 2.0 * sqrt(g * L.h);
     } else {
-        double a = g * R.h + R.p + cr;
+        real a = g * R.h + R.p + cr;
         if (a < 0.0) return ORC_ENONHYP;
         smax = fmax(uh + ceh, R.un + sqrt(a));
     }
@@ -551,15 +589,14 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
          * surface elevation in place of h in the state jump so that the
          * ocean at rest stays exactly at rest.  Remaining components travel
          * as contacts at the Roe speed. */
-        double ids = 1.0 / (smax - smin);
-        double dq0 = deta, dq1 = R.hun - L.hun;
-        double z1h = smin * ((smax * dq0 - df[0]) * ids);
-        double z1m = smin * ((smax * dq1 - df[1]) * ids);
-        double z7h = smax * ((df[0] - smin * dq0) * ids);
-        double z7m = smax * ((df[1] - smin * dq1) * ids);
-        double S = z1h + z7h;
-        double r1[7] = {z1h, z1m, vh * z1h, wh * z1h, sh * z1h, ph * z1h, pbh * z1h};
-        double r7[7] = {z7h, z7m, vh * z7h, wh * z7h, sh * z7h, ph * z7h, pbh * z7h};
+        real dq0 = deta, dq1 = R.hun - L.hun;
+        real z1h = smin * ((smax * dq0 - df[0]) / (smax - smin));
+        real z1m = smin * ((smax * dq1 - df[1]) / (smax - smin));
+        real z7h = smax * ((df[0] - smin * dq0) / (smax - smin));
+        real z7m = smax * ((df[1] - smin * dq1) / (smax - smin));
+        real S = z1h + z7h;
+        real r1[7] = {z1h, z1m, vh * z1h, wh * z1h, sh * z1h, ph * z1h, pbh * z1h};
+        real r7[7] = {z7h, z7m, vh * z7h, wh * z7h, sh * z7h, ph * z7h, pbh * z7h};
         for (int m = 0; m < 7; m++) { E->Z[0][m] = r1[m]; E->Z[6][m] = r7[m]; }
         E->Z[1][IHP] = df[5] - ph * S;
         E->Z[2][IHS] = df[4] - sh * S;
@@ -569,20 +606,19 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
     } else {
     /* f-wave coefficients: eigenvectors of Appendix C with the Einfeldt
      * speeds in place of u -+ Ce in the two acoustic eigenvectors */
-    double ids = 1.0 / (smax - smin);
-    double b2 = ((c2h + ph) * df[0] - df[5]) * (1.0 / ce2);
-    double S = df[0] - b2;
-    double T = df[1] - uh * b2;
-    double b1 = (smax * S - T) * ids;
-    double b7 = (T - smin * S) * ids;
-    double bs = df[4] - sh * S;
-    double bw = df[3] - wh * S;
-    double bv = df[2] - vh * S;
-    double bpb = df[6] - pbh * S;
+    real b2 = ((c2h + ph) * df[0] - df[5]) / ce2;
+    real S = df[0] - b2;
+    real T = df[1] - uh * b2;
+    real b1 = (smax * S - T) / (smax - smin);
+    real b7 = (T - smin * S) / (smax - smin);
+    real bs = df[4] - sh * S;
+    real bw = df[3] - wh * S;
+    real bv = df[2] - vh * S;
+    real bpb = df[6] - pbh * S;
 
-    double r1[7] = {1.0, smin, vh, wh, sh, c2h + ph, pbh};
-    double r2[7] = {1.0, uh, 0.0, 0.0, 0.0, -g * hh, 0.0};
-    double r7[7] = {1.0, smax, vh, wh, sh, c2h + ph, pbh};
+    real r1[7] = {1.0, smin, vh, wh, sh, c2h + ph, pbh};
+    real r2[7] = {1.0, uh, 0.0, 0.0, 0.0, -g * hh, 0.0};
+    real r7[7] = {1.0, smax, vh, wh, sh, c2h + ph, pbh};
     for (int m = 0; m < 7; m++) {
         E->Z[0][m] = b1 * r1[m];
         E->Z[1][m] = b2 * r2[m];
@@ -599,7 +635,7 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
 
     /* fluctuations; a wave of speed exactly zero is split half and half */
     for (int m = 0; m < 7; m++) {
-        double am = 0.0, ap = 0.0;
+        real am = 0.0, ap = 0.0;
         for (int p = 0; p < 7; p++) {
             if (E->s[p] < 0.0) am += E->Z[p][m];
             else if (E->s[p] > 0.0) ap += E->Z[p][m];
@@ -618,16 +654,16 @@ static int riemann_n(const orc_params *P, const double *qL, const double *qR,
 }
 
 /* swap the hu and hv components (frame change between x and y edges) */
-static void swap_uv(double *v)
+static void swap_uv(real *v)
 {
-    double t = v[IHU]; v[IHU] = v[IHV]; v[IHV] = t;
+    real t = v[IHU]; v[IHU] = v[IHV]; v[IHV] = t;
 }
 
 /* y-edge solve: permute into the normal frame, solve, permute back */
-static int riemann_y(const orc_params *P, const double *qL, const double *qR,
-                     double bL, double bR, double c2L, double c2R, edge_t *E)
+static int riemann_y(const orc_params *P, const real *qL, const real *qR,
+                     real bL, real bR, real c2L, real c2R, edge_t *E)
 {
-    double a[7], c[7];
+    real a[7], c[7];
     memcpy(a, qL, sizeof(a)); memcpy(c, qR, sizeof(c));
     swap_uv(a); swap_uv(c);
     int rc = riemann_n(P, a, c, bL, bR, c2L, c2R, E);
@@ -640,17 +676,17 @@ static int riemann_y(const orc_params *P, const double *qL, const double *qR,
  * tangent t: t = (-n_y, n_x) at left (x) edges, t = (n_y, -n_x) at bottom
  * (y) edges, so that an axis-aligned grid has the frames of the Cartesian
  * solves (identity at x-edges, the hu/hv swap at y-edges). */
-static void to_frame(double *v, double nx, double ny, double tx, double ty)
+static void to_frame(real *v, real nx, real ny, real tx, real ty)
 {
-    double hn = v[IHU] * nx + v[IHV] * ny;
-    double ht = v[IHU] * tx + v[IHV] * ty;
+    real hn = v[IHU] * nx + v[IHV] * ny;
+    real ht = v[IHU] * tx + v[IHV] * ty;
     v[IHU] = hn; v[IHV] = ht;
 }
 
-static void from_frame(double *v, double nx, double ny, double tx, double ty)
+static void from_frame(real *v, real nx, real ny, real tx, real ty)
 {
-    double hu = v[IHU] * nx + v[IHV] * tx;
-    double hv = v[IHU] * ny + v[IHV] * ty;
+    real hu = v[IHU] * nx + v[IHV] * tx;
+    real hv = v[IHU] * ny + v[IHV] * ty;
     v[IHU] = hu; v[IHV] = hv;
 }
 
@@ -658,11 +694,11 @@ static void from_frame(double *v, double nx, double ny, double tx, double ty)
  * fluctuations rotated back to the global frame and, with the speeds,
  * scaled by the edge's length ratio gm.  The Roe state (E->e) stays in the
  * edge's frame, unscaled, for the transverse splits. */
-static int riemann_mapped(const orc_params *P, const double *qL, const double *qR,
-                          double bL, double bR, double c2L, double c2R, double nx, double ny,
-                          double tx, double ty, double gm, edge_t *E)
+static int riemann_mapped(const orc_params *P, const real *qL, const real *qR,
+                          real bL, real bR, real c2L, real c2R, real nx, real ny,
+                          real tx, real ty, real gm, edge_t *E)
 {
-    double a[7], c[7];
+    real a[7], c[7];
     memcpy(a, qL, sizeof(a)); memcpy(c, qR, sizeof(c));
     to_frame(a, nx, ny, tx, ty);
     to_frame(c, nx, ny, tx, ty);
@@ -684,13 +720,14 @@ int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
                   int *kind)
 {
     edge_t E;
-    int rc = riemann_n(p, qL, qR, bL, bR, c2L, c2R, &E);
+    real a[7], c[7];
+    for (int m = 0; m < 7; m++) { a[m] = qL[m]; c[m] = qR[m]; }
+    int rc = riemann_n(p, a, c, bL, bR, c2L, c2R, &E);
     for (int q = 0; q < 7; q++) {
-        for (int m = 0; m < 7; m++) waves[q * 7 + m] = E.Z[q][m];
-        speeds[q] = E.s[q];
+        for (int m = 0; m < 7; m++) waves[q * 7 + m] = (double)E.Z[q][m];
+        speeds[q] = (double)E.s[q];
     }
-    memcpy(amdq, E.amdq, sizeof(E.amdq));
-    memcpy(apdq, E.apdq, sizeof(E.apdq));
+    for (int m = 0; m < 7; m++) { amdq[m] = (double)E.amdq[m]; apdq[m] = (double)E.apdq[m]; }
     *kind = E.kind;
     return rc;
 }
@@ -699,35 +736,34 @@ int orc_riemann_x(const orc_params *p, const double *qL, const double *qR,
 /* transverse splitting: decompose a vector a, given in the normal frame of
  * the splitting edge, on that edge's eigenvectors (same closed form as the
  * normal solve) and return the part moving in direction sgn (B+ or B-) */
-static void trans_split(const orc_params *P, const eig_t *e, const double *a,
-                        int sgn, double *out)
+static void trans_split(const orc_params *P, const eig_t *e, const real *a,
+                        int sgn, real *out)
 {
-    double g2 = ((e->c2h + e->ph) * a[0] - a[5]) * (1.0 / e->ce2);
-    double S = a[0] - g2;
-    double T = a[1] - e->uh * g2;
-    double ids = 1.0 / (e->smax - e->smin);
-    double g1 = (e->smax * S - T) * ids;
-    double g7 = (T - e->smin * S) * ids;
-    double gt = a[2] - e->vh * S;
-    double gw = a[3] - e->wh * S;
-    double gs = a[4] - e->sh * S;
-    double gpb = a[6] - e->pbh * S;
-    double s1 = sgn > 0 ? fmax(e->smin, 0.0) : fmin(e->smin, 0.0);
-    double sm = sgn > 0 ? fmax(e->uh, 0.0) : fmin(e->uh, 0.0);
-    double s7 = sgn > 0 ? fmax(e->smax, 0.0) : fmin(e->smax, 0.0);
-    double r1[7] = {1.0, e->smin, e->vh, e->wh, e->sh, e->c2h + e->ph, e->pbh};
-    double r2[7] = {1.0, e->uh, 0.0, 0.0, 0.0, -P->g * e->hh, 0.0};
-    double r7[7] = {1.0, e->smax, e->vh, e->wh, e->sh, e->c2h + e->ph, e->pbh};
-    double mid[7] = {g2 * r2[0], g2 * r2[1], gt, gw, gs, g2 * r2[5], gpb};
+    real g2 = ((e->c2h + e->ph) * a[0] - a[5]) / e->ce2;
+    real S = a[0] - g2;
+    real T = a[1] - e->uh * g2;
+    real g1 = (e->smax * S - T) / (e->smax - e->smin);
+    real g7 = (T - e->smin * S) / (e->smax - e->smin);
+    real gt = a[2] - e->vh * S;
+    real gw = a[3] - e->wh * S;
+    real gs = a[4] - e->sh * S;
+    real gpb = a[6] - e->pbh * S;
+    real s1 = sgn > 0 ? fmax(e->smin, 0.0) : fmin(e->smin, 0.0);
+    real sm = sgn > 0 ? fmax(e->uh, 0.0) : fmin(e->uh, 0.0);
+    real s7 = sgn > 0 ? fmax(e->smax, 0.0) : fmin(e->smax, 0.0);
+    real r1[7] = {1.0, e->smin, e->vh, e->wh, e->sh, e->c2h + e->ph, e->pbh};
+    real r2[7] = {1.0, e->uh, 0.0, 0.0, 0.0, -P->g * e->hh, 0.0};
+    real r7[7] = {1.0, e->smax, e->vh, e->wh, e->sh, e->c2h + e->ph, e->pbh};
+    real mid[7] = {g2 * r2[0], g2 * r2[1], gt, gw, gs, g2 * r2[5], gpb};
     for (int m = 0; m < 7; m++)
         out[m] = s1 * g1 * r1[m] + sm * mid[m] + s7 * g7 * r7[m];
 }
 
 /* x-edge fluctuation a (global frame) split by a y-edge (normal frame = y) */
-static void split_by_y(const orc_params *P, const eig_t *e, const double *a,
-                       int sgn, double *out)
+static void split_by_y(const orc_params *P, const eig_t *e, const real *a,
+                       int sgn, real *out)
 {
-    double t[7];
+    real t[7];
     memcpy(t, a, sizeof(t));
     swap_uv(t);
     trans_split(P, e, t, sgn, out);
@@ -736,10 +772,10 @@ static void split_by_y(const orc_params *P, const eig_t *e, const double *a,
 
 /* fluctuation a (global frame) split by a mapped edge with frame (n, t):
  * rotated into the frame, split by the edge's Roe state, rotated back */
-static void split_mapped(const orc_params *P, const eig_t *e, const double *a, int sgn,
-                         double nx, double ny, double tx, double ty, double *out)
+static void split_mapped(const orc_params *P, const eig_t *e, const real *a, int sgn,
+                         real nx, real ny, real tx, real ty, real *out)
 {
-    double t[7];
+    real t[7];
     memcpy(t, a, sizeof(t));
     to_frame(t, nx, ny, tx, ty);
     trans_split(P, e, t, sgn, out);
@@ -748,7 +784,7 @@ static void split_mapped(const orc_params *P, const eig_t *e, const double *a, i
 
 /* ------------------------------------------------------------------ */
 /* wave limiter (Sec. 4): minmod or MC applied to each f-wave family */
-static double limiter_phi(int lim, double th)
+static real limiter_phi(int lim, real th)
 {
     switch (lim) {
     case 1: return fmax(0.0, fmin(1.0, th));
@@ -758,9 +794,9 @@ static double limiter_phi(int lim, double th)
     }
 }
 
-static double dot7(const double *a, const double *b)
+static real dot7(const real *a, const real *b)
 {
-    double s = 0.0;
+    real s = 0.0;
     for (int m = 0; m < 7; m++) s += a[m] * b[m];
     return s;
 }
@@ -768,20 +804,20 @@ static double dot7(const double *a, const double *b)
 /* limited second-order correction F~ = 1/2 sum_p sgn(s_p)(1 - dt/dx |s_p|) Z~_p
  * of edge E with upwind neighbours El (left/below) and Er (right/above);
  * the Z are in the global frame */
-static void correction(int lim, double dtdx, const edge_t *El, const edge_t *E,
-                       const edge_t *Er, double *F)
+static void correction(int lim, real dtdx, const edge_t *El, const edge_t *E,
+                       const edge_t *Er, real *F)
 {
     for (int m = 0; m < 7; m++) F[m] = 0.0;
     if (lim == 0 || E->kind != 0) return;
     for (int p = 0; p < 7; p++) {
-        double zz = dot7(E->Z[p], E->Z[p]);
-        /* a wave whose squared norm is below 1e-200 is a zero wave */
-        if (!(zz > 1e-200)) continue;
+        real zz = dot7(E->Z[p], E->Z[p]);
+        /* a zero wave has no limited part */
+        if (zz == 0.0) continue;
         const edge_t *U = E->s[p] > 0.0 ? El : Er;
-        double th = dot7(U->Z[p], E->Z[p]) / zz;
-        double ph = limiter_phi(lim, th);
-        double sg = E->s[p] > 0.0 ? 1.0 : (E->s[p] < 0.0 ? -1.0 : 0.0);
-        double c = 0.5 * sg * (1.0 - dtdx * fabs(E->s[p])) * ph;
+        real th = dot7(U->Z[p], E->Z[p]) / zz;
+        real ph = limiter_phi(lim, th);
+        real sg = E->s[p] > 0.0 ? 1.0 : (E->s[p] < 0.0 ? -1.0 : 0.0);
+        real c = 0.5 * sg * (1.0 - dtdx * fabs(E->s[p])) * ph;
         for (int m = 0; m < 7; m++) F[m] += c * E->Z[p][m];
     }
 }
@@ -789,38 +825,38 @@ static void correction(int lim, double dtdx, const edge_t *El, const edge_t *E,
 /* ------------------------------------------------------------------ */
 /* one step                                                             */
 
-int orc_step(orc_grid *g, double dt, double *courant)
+static int step_grid(orc_grid *g, real dt, real *courant)
 {
     const orc_params *P = &g->P;
     const int nx = g->nx, ny = g->ny;
     const size_t np = PLANE(g);
-    const double dtdx = dt / g->dx, dtdy = dt / g->dy;
+    const real dtdx = dt / g->dx, dtdy = dt / g->dy;
     const int nxe = nx + 3, nye = nx + 2;          /* edges per row */
     const size_t nex = (size_t)nxe * (ny + 2);     /* x-edges, rows -1..ny */
     const size_t ney = (size_t)nye * (ny + 3);     /* y-edges, rows -1..ny+1 */
     int rc = ORC_OK;
 
     if (!g->w_qs) {
-        g->w_qs = (double *)malloc(ORC_NV * np * sizeof(double));
-        g->w_c2 = (double *)malloc(np * sizeof(double));
+        g->w_qs = (real *)malloc(ORC_NV * np * sizeof(real));
+        g->w_c2 = (real *)malloc(np * sizeof(real));
         g->w_EX = (edge_t *)malloc(nex * sizeof(edge_t));
         g->w_EY = (edge_t *)malloc(ney * sizeof(edge_t));
-        g->w_Flim = (double *)malloc(nex * 7 * sizeof(double));
-        g->w_Ftr = (double *)malloc(nex * 7 * sizeof(double));
-        g->w_Glim = (double *)malloc(ney * 7 * sizeof(double));
-        g->w_Gtr = (double *)malloc(ney * 7 * sizeof(double));
-        g->w_clip = (double *)malloc((size_t)ny * sizeof(double));
+        g->w_Flim = (real *)malloc(nex * 7 * sizeof(real));
+        g->w_Ftr = (real *)malloc(nex * 7 * sizeof(real));
+        g->w_Glim = (real *)malloc(ney * 7 * sizeof(real));
+        g->w_Gtr = (real *)malloc(ney * 7 * sizeof(real));
+        g->w_clip = (real *)malloc((size_t)ny * sizeof(real));
         if (!g->w_qs || !g->w_c2 || !g->w_EX || !g->w_EY || !g->w_Flim || !g->w_Ftr ||
             !g->w_Glim || !g->w_Gtr || !g->w_clip)
             return ORC_ENOMEM;
     }
-    double *qs = g->w_qs, *c2 = g->w_c2;
+    real *qs = g->w_qs, *c2 = g->w_c2;
     edge_t *EX = g->w_EX, *EY = g->w_EY;
-    double *Flim = g->w_Flim, *Ftr = g->w_Ftr, *Glim = g->w_Glim, *Gtr = g->w_Gtr;
-    memset(Flim, 0, nex * 7 * sizeof(double));
-    memset(Ftr, 0, nex * 7 * sizeof(double));
-    memset(Glim, 0, ney * 7 * sizeof(double));
-    memset(Gtr, 0, ney * 7 * sizeof(double));
+    real *Flim = g->w_Flim, *Ftr = g->w_Ftr, *Glim = g->w_Glim, *Gtr = g->w_Gtr;
+    memset(Flim, 0, nex * 7 * sizeof(real));
+    memset(Ftr, 0, nex * 7 * sizeof(real));
+    memset(Glim, 0, ney * 7 * sizeof(real));
+    memset(Gtr, 0, ney * 7 * sizeof(real));
 #define XE(i, j) ((size_t)((j) + 1) * nxe + (size_t)((i) + 1))
 #define YE(i, j) ((size_t)((j) + 1) * nye + (size_t)((i) + 1))
 
@@ -831,7 +867,7 @@ int orc_step(orc_grid *g, double dt, double *courant)
 #pragma omp parallel for schedule(static)
     for (long kk = 0; kk < (long)np; kk++) {
         size_t k = (size_t)kk;
-        double qc[7];
+        real qc[7];
         for (int m = 0; m < 7; m++) qc[m] = g->q[m * np + k];
         if (P->splitting) {
             source_or_clear(g, k, 0.5 * dt, qc);
@@ -848,7 +884,7 @@ int orc_step(orc_grid *g, double dt, double *courant)
     for (int j = -1; j <= ny; j++) {
         for (int i = -1; i <= nx + 1; i++) {
             size_t kl = CELL(g, i - 1, j), kr = CELL(g, i, j);
-            double ql[7], qr[7];
+            real ql[7], qr[7];
             for (int m = 0; m < 7; m++) { ql[m] = qs[m * np + kl]; qr[m] = qs[m * np + kr]; }
             int r = g->kap ? riemann_mapped(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr],
                                             g->xnx[kr], g->xny[kr], 0.0 - g->xny[kr], g->xnx[kr],
@@ -863,7 +899,7 @@ int orc_step(orc_grid *g, double dt, double *courant)
     for (int j = -1; j <= ny + 1; j++) {
         for (int i = -1; i <= nx; i++) {
             size_t kl = CELL(g, i, j - 1), kr = CELL(g, i, j);
-            double ql[7], qr[7];
+            real ql[7], qr[7];
             for (int m = 0; m < 7; m++) { ql[m] = qs[m * np + kl]; qr[m] = qs[m * np + kr]; }
             int r = g->kap ? riemann_mapped(P, ql, qr, g->b[kl], g->b[kr], c2[kl], c2[kr],
                                             g->ynx[kr], g->yny[kr], g->yny[kr], 0.0 - g->ynx[kr],
@@ -880,7 +916,7 @@ int orc_step(orc_grid *g, double dt, double *courant)
 #pragma omp parallel for schedule(static)
     for (int j = -1; j <= ny; j++)
         for (int i = 0; i <= nx; i++) {
-            double f = g->kap ? 0.5 * (dtdx / g->kap[CELL(g, i - 1, j)] + dtdx / g->kap[CELL(g, i, j)])
+            real f = g->kap ? 0.5 * (dtdx / g->kap[CELL(g, i - 1, j)] + dtdx / g->kap[CELL(g, i, j)])
                               : dtdx;
             correction(P->limiter, f, &EX[XE(i - 1, j)], &EX[XE(i, j)],
                        &EX[XE(i + 1, j)], &Flim[XE(i, j) * 7]);
@@ -888,97 +924,87 @@ int orc_step(orc_grid *g, double dt, double *courant)
 #pragma omp parallel for schedule(static)
     for (int j = 0; j <= ny; j++)
         for (int i = -1; i <= nx; i++) {
-            double f = g->kap ? 0.5 * (dtdy / g->kap[CELL(g, i, j - 1)] + dtdy / g->kap[CELL(g, i, j)])
+            real f = g->kap ? 0.5 * (dtdy / g->kap[CELL(g, i, j - 1)] + dtdy / g->kap[CELL(g, i, j)])
                               : dtdy;
             correction(P->limiter, f, &EY[YE(i, j - 1)], &EY[YE(i, j)],
                        &EY[YE(i, j + 1)], &Glim[YE(i, j) * 7]);
         }
 
-    /* 5. transverse propagation.  The fluctuation an edge sends into a
-     *    cell, including its limited correction (A+ - F~ to the right cell,
-     *    A- + F~ to the left cell; none from wall or dry edges), is split by
-     *    the eigenstructure of the cell's edges in the other direction.  The
-     *    part moving up (right) feeds the correction of the cell's upper
-     *    (right) edge, the part moving down (left) that of its lower (left)
-     *    edge, with weight dt/(2 dx).  The split is linear, so the two
-     *    fluctuations entering a cell through its opposite edges are split
-     *    together. */
+    /* 5. transverse propagation (wave propagation form, Sec. 4).  Each
+     *    x-edge sends A+dQ - F~ into the cell on its right and A-dQ + F~
+     *    into the cell on its left (wall and dry edges send nothing).  Each
+     *    of these fluctuations is split on its own by the eigenstructure of
+     *    the two y-edges of the cell it entered: the part moving up, B+,
+     *    by the cell's upper edge, goes into that edge's correction, the
+     *    part moving down, B-, by its lower edge, into the lower edge's
+     *    correction, each with weight -dt/(2 dx).  That is four splits per
+     *    x-edge; y-edges feed the x-edge corrections in the same way with
+     *    -dt/(2 dy).  Seen from a y-edge (i, j): up parts of the two
+     *    fluctuations entering cell (i, j-1), down parts of the two
+     *    entering cell (i, j). */
     if (P->transverse == 2) {
-        const double cx = -0.5 * dtdx, cy = -0.5 * dtdy;
-        /* x-fluctuation entering cell (i, j), i = 0..nx-1, j = -1..ny */
-        double *Xin = (double *)malloc((size_t)nx * (ny + 2) * 7 * sizeof(double));
-        /* y-fluctuation entering cell (i, j), i = -1..nx, j = 0..ny-1 */
-        double *Yin = (double *)malloc((size_t)(nx + 2) * ny * 7 * sizeof(double));
-        if (!Xin || !Yin) { free(Xin); free(Yin); return ORC_ENOMEM; }
-#define XI(i, j) (((size_t)((j) + 1) * nx + (size_t)(i)) * 7)
-#define YI(i, j) (((size_t)(j) * (nx + 2) + (size_t)((i) + 1)) * 7)
-        for (int j = -1; j <= ny; j++) {
-            for (int i = 0; i < nx; i++) {
-                const edge_t *el = &EX[XE(i, j)], *er = &EX[XE(i + 1, j)];
-                const double *Fl = &Flim[XE(i, j) * 7], *Fr = &Flim[XE(i + 1, j) * 7];
-                for (int m = 0; m < 7; m++)
-                    Xin[XI(i, j) + m] = (el->kind == 0 ? el->apdq[m] - Fl[m] : 0.0)
-                                      + (er->kind == 0 ? er->amdq[m] + Fr[m] : 0.0);
-            }
-        }
-        for (int j = 0; j < ny; j++) {
-            for (int i = -1; i <= nx; i++) {
-                const edge_t *eb = &EY[YE(i, j)], *et = &EY[YE(i, j + 1)];
-                const double *Gb = &Glim[YE(i, j) * 7], *Gt = &Glim[YE(i, j + 1) * 7];
-                for (int m = 0; m < 7; m++)
-                    Yin[YI(i, j) + m] = (eb->kind == 0 ? eb->apdq[m] - Gb[m] : 0.0)
-                                      + (et->kind == 0 ? et->amdq[m] + Gt[m] : 0.0);
-            }
-        }
-        /* G~ at y-edge (i, j): up part of cell (i, j-1), down part of (i, j) */
+        const real cx = 0.5 * dtdx, cy = 0.5 * dtdy;
 #pragma omp parallel for schedule(static)
         for (int j = 0; j <= ny; j++) {
             for (int i = 0; i < nx; i++) {
                 const edge_t *ye = &EY[YE(i, j)];
+                real *G = &Gtr[YE(i, j) * 7];
                 if (!ye->e.wet) continue;
-                double vp[7], vm[7];
-                if (g->kap) {
-                    /* mapped: split in the edge's frame; each part weighted
-                     * by the edge's length ratio over the capacity of the
-                     * cell it entered */
-                    const size_t ke = CELL(g, i, j), kb = CELL(g, i, j - 1);
-                    const double nx_ = g->ynx[ke], ny_ = g->yny[ke];
-                    split_mapped(P, &ye->e, &Xin[XI(i, j - 1)], 1, nx_, ny_, ny_, 0.0 - nx_, vp);
-                    split_mapped(P, &ye->e, &Xin[XI(i, j)], -1, nx_, ny_, ny_, 0.0 - nx_, vm);
-                    const double wa = g->ygm[ke] / g->kap[kb], wb = g->ygm[ke] / g->kap[ke];
-                    for (int m = 0; m < 7; m++) Gtr[YE(i, j) * 7 + m] = cx * (wa * vp[m] + wb * vm[m]);
-                    continue;
+                for (int part = 0; part < 4; part++) {
+                    const int row = part < 2 ? j - 1 : j;      /* the cell entered */
+                    const int sgn = part < 2 ? 1 : -1;         /* up or down part */
+                    const int left = part % 2 == 0;            /* its left x-edge */
+                    const edge_t *xe = &EX[XE(left ? i : i + 1, row)];
+                    if (xe->kind != 0) continue;
+                    const real *F = &Flim[XE(left ? i : i + 1, row) * 7];
+                    real a[7], v[7];
+                    for (int m = 0; m < 7; m++)
+                        a[m] = left ? xe->apdq[m] - F[m] : xe->amdq[m] + F[m];
+                    if (g->kap) {
+                        /* mapped: split in the edge's frame; the part is
+                         * weighted by the edge's length ratio over the
+                         * capacity of the cell it entered */
+                        const size_t ke = CELL(g, i, j);
+                        const real nx_ = g->ynx[ke], ny_ = g->yny[ke];
+                        split_mapped(P, &ye->e, a, sgn, nx_, ny_, ny_, 0.0 - nx_, v);
+                        const real wgt = g->ygm[ke] / g->kap[CELL(g, i, row)];
+                        for (int m = 0; m < 7; m++) G[m] -= cx * (wgt * v[m]);
+                    } else {
+                        split_by_y(P, &ye->e, a, sgn, v);
+                        for (int m = 0; m < 7; m++) G[m] -= cx * v[m];
+                    }
                 }
-                split_by_y(P, &ye->e, &Xin[XI(i, j - 1)], 1, vp);
-                split_by_y(P, &ye->e, &Xin[XI(i, j)], -1, vm);
-                for (int m = 0; m < 7; m++) Gtr[YE(i, j) * 7 + m] = cx * (vp[m] + vm[m]);
             }
         }
-        /* F~ at x-edge (i, j): right part of cell (i-1, j), left part of (i, j) */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < ny; j++) {
             for (int i = 0; i <= nx; i++) {
                 const edge_t *xe = &EX[XE(i, j)];
+                real *F = &Ftr[XE(i, j) * 7];
                 if (!xe->e.wet) continue;
-                double vp[7], vm[7];
-                if (g->kap) {
-                    const size_t ke = CELL(g, i, j), kl = CELL(g, i - 1, j);
-                    const double nx_ = g->xnx[ke], ny_ = g->xny[ke];
-                    split_mapped(P, &xe->e, &Yin[YI(i - 1, j)], 1, nx_, ny_, 0.0 - ny_, nx_, vp);
-                    split_mapped(P, &xe->e, &Yin[YI(i, j)], -1, nx_, ny_, 0.0 - ny_, nx_, vm);
-                    const double wa = g->xgm[ke] / g->kap[kl], wb = g->xgm[ke] / g->kap[ke];
-                    for (int m = 0; m < 7; m++) Ftr[XE(i, j) * 7 + m] = cy * (wa * vp[m] + wb * vm[m]);
-                    continue;
+                for (int part = 0; part < 4; part++) {
+                    const int col = part < 2 ? i - 1 : i;      /* the cell entered */
+                    const int sgn = part < 2 ? 1 : -1;         /* right or left part */
+                    const int low = part % 2 == 0;             /* its lower y-edge */
+                    const edge_t *ye = &EY[YE(col, low ? j : j + 1)];
+                    if (ye->kind != 0) continue;
+                    const real *Gl = &Glim[YE(col, low ? j : j + 1) * 7];
+                    real a[7], v[7];
+                    for (int m = 0; m < 7; m++)
+                        a[m] = low ? ye->apdq[m] - Gl[m] : ye->amdq[m] + Gl[m];
+                    if (g->kap) {
+                        const size_t ke = CELL(g, i, j);
+                        const real nx_ = g->xnx[ke], ny_ = g->xny[ke];
+                        split_mapped(P, &xe->e, a, sgn, nx_, ny_, 0.0 - ny_, nx_, v);
+                        const real wgt = g->xgm[ke] / g->kap[CELL(g, col, j)];
+                        for (int m = 0; m < 7; m++) F[m] -= cy * (wgt * v[m]);
+                    } else {
+                        trans_split(P, &xe->e, a, sgn, v);
+                        for (int m = 0; m < 7; m++) F[m] -= cy * v[m];
+                    }
                 }
-                trans_split(P, &xe->e, &Yin[YI(i - 1, j)], 1, vp);
-                trans_split(P, &xe->e, &Yin[YI(i, j)], -1, vm);
-                for (int m = 0; m < 7; m++) Ftr[XE(i, j) * 7 + m] = cy * (vp[m] + vm[m]);
             }
         }
-#undef XI
-#undef YI
-        free(Xin);
-        free(Yin);
     }
 
     /* 6. flux-difference update of the interior cells, then
@@ -986,49 +1012,40 @@ int orc_step(orc_grid *g, double dt, double *courant)
      * 8. fix-ups: positivity, dry cells, breaking latch, SWE cells */
 #pragma omp parallel for schedule(static) reduction(min:rc)
     for (int j = 0; j < ny; j++) {
-        double clip = 0.0;
+        real clip = 0.0;
         for (int i = 0; i < nx; i++) {
             size_t k = CELL(g, i, j);
             size_t xl = XE(i, j), xr = XE(i + 1, j), yb = YE(i, j), yt = YE(i, j + 1);
             /* Q^{n+1} = Q - dt/dx (A+dQ_{i-1/2} + A-dQ_{i+1/2} + F~_{i+1/2} - F~_{i-1/2})
              *             - dt/dy (B+dQ_{j-1/2} + B-dQ_{j+1/2} + G~_{j+1/2} - G~_{j-1/2}),
              * F~ and G~ being the limited corrections plus the transverse
-             * terms; the contributions are applied one after the other in
-             * this order (any order gives the same sum up to rounding) */
-            /* in a patch set, the contributions through an edge shared
-             * with a finer patch are left out here; the finer patch's
-             * fluxes replace them after its substeps (refluxing) */
+             * terms.  In a patch set, the contributions through an edge
+             * shared with a finer patch are left out here; the finer
+             * patch's fluxes replace them after its substeps (refluxing). */
             const int fl = g->iface[k];
             /* mapped grids: dt/dx and dt/dy over the cell's capacity */
-            const double ddx = g->kap ? dtdx / g->kap[k] : dtdx;
-            const double ddy = g->kap ? dtdy / g->kap[k] : dtdy;
-            double qc[7];
+            const real ddx = g->kap ? dtdx / g->kap[k] : dtdx;
+            const real ddy = g->kap ? dtdy / g->kap[k] : dtdy;
+            real qc[7];
             for (int m = 0; m < 7; m++) {
-                double xl_n = (fl & 1) ? 0.0 : EX[xl].apdq[m] - Flim[xl * 7 + m];
-                double xr_n = (fl & 2) ? 0.0 : EX[xr].amdq[m] + Flim[xr * 7 + m];
-                double yb_t = (fl & 4) ? 0.0 : Gtr[yb * 7 + m];
-                double yb_n = (fl & 4) ? 0.0 : EY[yb].apdq[m] - Glim[yb * 7 + m];
-                double yt_t = (fl & 8) ? 0.0 : Gtr[yt * 7 + m];
-                double yt_n = (fl & 8) ? 0.0 : EY[yt].amdq[m] + Glim[yt * 7 + m];
-                double xr_t = (fl & 2) ? 0.0 : Ftr[xr * 7 + m];
-                double xl_t = (fl & 1) ? 0.0 : Ftr[xl * 7 + m];
-                double v = qs[m * np + k];
-                v -= ddx * (xl_n + xr_n);
-                v += ddy * yb_t;
-                v -= ddy * yb_n;
-                v -= ddy * yt_t;
-                v -= ddy * yt_n;
-                v -= ddx * (xr_t - xl_t);
-                qc[m] = v;
+                real apl = (fl & 1) ? 0.0 : EX[xl].apdq[m];
+                real Fl = (fl & 1) ? 0.0 : Flim[xl * 7 + m] + Ftr[xl * 7 + m];
+                real amr = (fl & 2) ? 0.0 : EX[xr].amdq[m];
+                real Fr = (fl & 2) ? 0.0 : Flim[xr * 7 + m] + Ftr[xr * 7 + m];
+                real bpb = (fl & 4) ? 0.0 : EY[yb].apdq[m];
+                real Gb = (fl & 4) ? 0.0 : Glim[yb * 7 + m] + Gtr[yb * 7 + m];
+                real bmt = (fl & 8) ? 0.0 : EY[yt].amdq[m];
+                real Gt = (fl & 8) ? 0.0 : Glim[yt * 7 + m] + Gtr[yt * 7 + m];
+                qc[m] = qs[m * np + k] - ddx * (apl + amr + Fr - Fl) - ddy * (bpb + bmt + Gt - Gb);
             }
             source_or_clear(g, k, P->splitting ? 0.5 * dt : dt, qc);
             /* sponge: every variable relaxed towards the state at rest
              * (h = H, the rest zero) by an implicit Euler step of rate sigma */
             if (g->sp_rate > 0.0) {
-                const double sg = sponge_sigma(g, i, j);
+                const real sg = sponge_sigma(g, i, j);
                 if (sg > 0.0) {
-                    const double f = 1.0 / (1.0 + dt * sg);
-                    const double H = still_depth(P, g->b[k]);
+                    const real f = 1.0 / (1.0 + dt * sg);
+                    const real H = still_depth(P, g->b[k]);
                     qc[IH] = H + (qc[IH] - H) * f;
                     for (int m = 1; m < 7; m++) qc[m] = qc[m] * f;
                 }
@@ -1040,7 +1057,7 @@ int orc_step(orc_grid *g, double dt, double *courant)
             if (qc[IH] <= P->dry_tol) {
                 for (int m = 1; m < 7; m++) qc[m] = 0.0;
             } else if (P->kappa > 0.0 && g->phi[k] && !g->brk[k]) {
-                double H = still_depth(P, g->b[k]);
+                real H = still_depth(P, g->b[k]);
                 if (qc[IH] + g->b[k] - P->eta0 > P->kappa * H) g->brk[k] = 1;
             }
             if (!g->phi[k] || g->brk[k] || qc[IH] <= P->dry_tol) {
@@ -1059,15 +1076,15 @@ int orc_step(orc_grid *g, double dt, double *courant)
      *    mapped grid the scaled speeds over the smaller capacity of the
      *    edge's two cells) */
     {
-        double rx = 0.0, ry = 0.0;
+        real rx = 0.0, ry = 0.0;
         for (int j = 0; j < ny; j++)
             for (int i = 0; i <= nx; i++) {
-                double kk = g->kap ? fmin(g->kap[CELL(g, i - 1, j)], g->kap[CELL(g, i, j)]) : 1.0;
+                real kk = g->kap ? fmin(g->kap[CELL(g, i - 1, j)], g->kap[CELL(g, i, j)]) : 1.0;
                 for (int p = 0; p < 7; p++) rx = fmax(rx, fabs(EX[XE(i, j)].s[p]) / kk);
             }
         for (int j = 0; j <= ny; j++)
             for (int i = 0; i < nx; i++) {
-                double kk = g->kap ? fmin(g->kap[CELL(g, i, j - 1)], g->kap[CELL(g, i, j)]) : 1.0;
+                real kk = g->kap ? fmin(g->kap[CELL(g, i, j - 1)], g->kap[CELL(g, i, j)]) : 1.0;
                 for (int p = 0; p < 7; p++) ry = fmax(ry, fabs(EY[YE(i, j)].s[p]) / kk);
             }
         *courant = fmax(dt * rx / g->dx, dt * ry / g->dy);
@@ -1077,24 +1094,32 @@ int orc_step(orc_grid *g, double dt, double *courant)
     return rc;
 }
 
+int orc_step(orc_grid *g, double dt, double *courant)
+{
+    real c = 0.0;
+    int rc = step_grid(g, dt, &c);
+    *courant = (double)c;
+    return rc;
+}
+
 /* ------------------------------------------------------------------ */
 /* time-step control, gauges, diagnostics                               */
 
-int orc_initial_dt(const orc_grid *g, double *dt0)
+static int initial_dt(const orc_grid *g, real *dt0)
 {
     const orc_params *P = &g->P;
     size_t np = PLANE(g);
-    double mx = 0.0;
+    real mx = 0.0;
     for (int j = 0; j < g->ny; j++) {
         for (int i = 0; i < g->nx; i++) {
             size_t k = CELL(g, i, j);
-            double h = g->q[IH * np + k];
+            real h = g->q[IH * np + k];
             if (h <= P->dry_tol) continue;
-            double u = g->q[IHU * np + k] / h, v = g->q[IHV * np + k] / h;
-            double p = g->q[IHP * np + k] / h;
-            double a = P->g * h + p + cell_c2(g, k);
+            real u = g->q[IHU * np + k] / h, v = g->q[IHV * np + k] / h;
+            real p = g->q[IHP * np + k] / h;
+            real a = P->g * h + p + cell_c2(g, k);
             if (a < 0.0) return ORC_ENONHYP;
-            double ce = sqrt(a);
+            real ce = sqrt(a);
             mx = fmax(mx, fmax((fabs(u) + ce) / g->dx, (fabs(v) + ce) / g->dy));
         }
     }
@@ -1103,24 +1128,32 @@ int orc_initial_dt(const orc_grid *g, double *dt0)
     return ORC_OK;
 }
 
-static double gauge_eta(const orc_grid *g, double gx, double gy)
+int orc_initial_dt(const orc_grid *g, double *dt0)
+{
+    real d = 0.0;
+    int rc = initial_dt(g, &d);
+    *dt0 = (double)d;
+    return rc;
+}
+
+static real gauge_eta(const orc_grid *g, real gx, real gy)
 {
     size_t np = PLANE(g);
-    double fx = (gx - g->x0) / g->dx - 0.5;
-    double fy = (gy - g->y0) / g->dy - 0.5;
+    real fx = (gx - g->x0) / g->dx - 0.5;
+    real fy = (gy - g->y0) / g->dy - 0.5;
     int i0 = (int)floor(fx), j0 = (int)floor(fy);
     if (i0 < 0) i0 = 0;
     if (i0 > g->nx - 2) i0 = g->nx - 2;
     if (j0 < 0) j0 = 0;
     if (j0 > g->ny - 2) j0 = g->ny - 2;
-    double wx = fx - i0, wy = fy - j0;
+    real wx = fx - i0, wy = fy - j0;
     wx = fmin(fmax(wx, 0.0), 1.0);
     wy = fmin(fmax(wy, 0.0), 1.0);
-    double e[2][2];
+    real e[2][2];
     for (int dj = 0; dj < 2; dj++)
         for (int di = 0; di < 2; di++) {
             size_t k = CELL(g, i0 + di, j0 + dj);
-            double h = g->q[IH * np + k];
+            real h = g->q[IH * np + k];
             e[dj][di] = h > g->P.dry_tol ? h + g->b[k] - g->P.eta0 : 0.0;
         }
     return (1.0 - wx) * (1.0 - wy) * e[0][0] + wx * (1.0 - wy) * e[0][1]
@@ -1132,10 +1165,10 @@ static int record_gauges(orc_grid *g)
     if (g->ngauge == 0) return ORC_OK;
     if (g->nrec == g->caprec) {
         int cap = g->caprec ? 2 * g->caprec : 256;
-        double *t = (double *)realloc(g->rec_t, (size_t)cap * sizeof(double));
+        real *t = (real *)realloc(g->rec_t, (size_t)cap * sizeof(real));
         if (!t) return ORC_ENOMEM;
         g->rec_t = t;
-        double *e = (double *)realloc(g->rec_eta, (size_t)cap * g->ngauge * sizeof(double));
+        real *e = (real *)realloc(g->rec_eta, (size_t)cap * g->ngauge * sizeof(real));
         if (!e) return ORC_ENOMEM;
         g->rec_eta = e;
         g->caprec = cap;
@@ -1150,7 +1183,7 @@ static int record_gauges(orc_grid *g)
 int orc_set_gauges(orc_grid *g, int n, const double *xy)
 {
     for (int k = 0; k < n; k++) {
-        double x = xy[2 * k], y = xy[2 * k + 1];
+        real x = xy[2 * k], y = xy[2 * k + 1];
         if (x < g->x0 || x > g->x0 + g->nx * g->dx || y < g->y0 || y > g->y0 + g->ny * g->dy)
             return ORC_ERANGE;
     }
@@ -1158,9 +1191,9 @@ int orc_set_gauges(orc_grid *g, int n, const double *xy)
     g->gxy = NULL; g->rec_t = NULL; g->rec_eta = NULL;
     g->nrec = 0; g->caprec = 0; g->ngauge = n;
     if (n > 0) {
-        g->gxy = (double *)malloc((size_t)2 * n * sizeof(double));
+        g->gxy = (real *)malloc((size_t)2 * n * sizeof(real));
         if (!g->gxy) return ORC_ENOMEM;
-        memcpy(g->gxy, xy, (size_t)2 * n * sizeof(double));
+        for (int k = 0; k < 2 * n; k++) g->gxy[k] = xy[k];
     }
     return ORC_OK;
 }
@@ -1182,23 +1215,23 @@ int orc_advance(orc_grid *g, double dt, int n)
     const orc_params *P = &g->P;
     int adaptive = !(dt > 0.0);
     if (adaptive && !g->have_dt) {
-        int r = orc_initial_dt(g, &g->dt_next);
+        int r = initial_dt(g, &g->dt_next);
         if (r != ORC_OK) return r;
         g->have_dt = 1;
     }
     size_t np = PLANE(g);
-    double *save_q = (double *)malloc(ORC_NV * np * sizeof(double));
+    real *save_q = (real *)malloc(ORC_NV * np * sizeof(real));
     unsigned char *save_b = (unsigned char *)malloc(np);
     if (!save_q || !save_b) { free(save_q); free(save_b); return ORC_ENOMEM; }
     int rc = ORC_OK, accepted = 0, rejects_in_row = 0;
     while (accepted < n) {
-        double d = adaptive ? g->dt_next : dt;
-        double save_clip = g->clipped, cour = 0.0;
-        memcpy(save_q, g->q, ORC_NV * np * sizeof(double));
+        real d = adaptive ? g->dt_next : dt;
+        real save_clip = g->clipped, cour = 0.0;
+        memcpy(save_q, g->q, ORC_NV * np * sizeof(real));
         memcpy(save_b, g->brk, np);
-        int r = orc_step(g, d, &cour);
+        int r = step_grid(g, d, &cour);
         if (r != ORC_OK || cour > P->cfl_max) {
-            memcpy(g->q, save_q, ORC_NV * np * sizeof(double));
+            memcpy(g->q, save_q, ORC_NV * np * sizeof(real));
             memcpy(g->brk, save_b, np);
             g->clipped = save_clip;
             if (r != ORC_OK) { rc = r; break; }
@@ -1242,7 +1275,7 @@ int orc_set_clock(orc_grid *g, double t, double dt_next, long long steps)
 double orc_mass(const orc_grid *g)
 {
     size_t np = PLANE(g);
-    double s = 0.0;
+    real s = 0.0;
     for (int j = 0; j < g->ny; j++)
         for (int i = 0; i < g->nx; i++)
             s += g->q[IH * np + CELL(g, i, j)] * (g->kap ? g->kap[CELL(g, i, j)] : 1.0);
@@ -1258,9 +1291,15 @@ double orc_clipped_mass(const orc_grid *g) { return g->clipped; }
 int orc_framed(orc_grid *g, double **q, double **b, unsigned char **phi,
                unsigned char **brk, unsigned char **iface, int *sx, int *sy)
 {
+#ifdef ORC_LONG_DOUBLE
+    /* the framed arrays are FP64 views: patch sets run in FP64 only */
+    (void)q; (void)b; (void)phi; (void)brk; (void)iface; (void)sx; (void)sy;
+    return ORC_EINVAL;
+#else
     *q = g->q; *b = g->b; *phi = g->phi; *brk = g->brk; *iface = g->iface;
     *sx = g->sx; *sy = g->sy;
     return ORC_OK;
+#endif
 }
 
 void orc_set_external_ghosts(orc_grid *g, int on) { g->ext_ghosts = on ? 1 : 0; }
@@ -1284,9 +1323,9 @@ int orc_set_mapping(orc_grid *g, const double *xn, const double *yn)
     if (g->ext_ghosts || !xn || !yn) return ORC_EINVAL;
     const int W = g->nx + 5;
     const size_t np = PLANE(g);
-    double *a[7];
+    real *a[7];
     for (int m = 0; m < 7; m++) {
-        a[m] = (double *)malloc(np * sizeof(double));
+        a[m] = (real *)malloc(np * sizeof(real));
         if (!a[m]) { for (int k = 0; k <= m; k++) free(a[k]); return ORC_ENOMEM; }
     }
 #define NX(i, j) xn[(size_t)((j) + 2) * W + (size_t)((i) + 2)]
@@ -1297,18 +1336,18 @@ int orc_set_mapping(orc_grid *g, const double *xn, const double *yn)
             const size_t k = CELL(g, i, j);
             /* area from the cross product of the diagonals (counter-clockwise
              * corners (i, j), (i+1, j), (i+1, j+1), (i, j+1)) */
-            double area = 0.5 * ((NX(i + 1, j + 1) - NX(i, j)) * (NY(i, j + 1) - NY(i + 1, j))
+            real area = 0.5 * ((NX(i + 1, j + 1) - NX(i, j)) * (NY(i, j + 1) - NY(i + 1, j))
                                - (NX(i, j + 1) - NX(i + 1, j)) * (NY(i + 1, j + 1) - NY(i, j)));
             /* left edge (i, j) -> (i, j+1), normal towards increasing i */
-            double ex = NX(i, j + 1) - NX(i, j), ey = NY(i, j + 1) - NY(i, j);
-            double L = sqrt(ex * ex + ey * ey);
+            real ex = NX(i, j + 1) - NX(i, j), ey = NY(i, j + 1) - NY(i, j);
+            real L = sqrt(ex * ex + ey * ey);
             a[0][k] = area / (g->dx * g->dy);
             a[1][k] = ey / L;
             a[2][k] = (0.0 - ex) / L;   /* +0 for an axis-aligned edge */
             a[3][k] = L / g->dy;
             /* bottom edge (i, j) -> (i+1, j), normal towards increasing j */
-            double fx = NX(i + 1, j) - NX(i, j), fy = NY(i + 1, j) - NY(i, j);
-            double M = sqrt(fx * fx + fy * fy);
+            real fx = NX(i + 1, j) - NX(i, j), fy = NY(i + 1, j) - NY(i, j);
+            real M = sqrt(fx * fx + fy * fy);
             a[4][k] = (0.0 - fy) / M;
             a[5][k] = fx / M;
             a[6][k] = M / g->dx;
@@ -1332,10 +1371,10 @@ int orc_update_phi_framed(orc_grid *g)
     int n = g->P.nbr_n;
     for (int j = 0; j < g->ny; j++) {
         for (int i = 0; i < g->nx; i++) {
-            double hmin = INFINITY;
+            real hmin = INFINITY;
             for (int dj = -n; dj <= n; dj++)
                 for (int di = -n; di <= n; di++) {
-                    double H = still_depth(&g->P, g->b[CELL(g, i + di, j + dj)]);
+                    real H = still_depth(&g->P, g->b[CELL(g, i + di, j + dj)]);
                     if (H < hmin) hmin = H;
                 }
             g->phi[CELL(g, i, j)] = (hmin > g->P.h_star) ? 1 : 0;
@@ -1361,7 +1400,7 @@ int orc_boundary_flux(const orc_grid *g, double *K)
 #define XE(i, j) ((size_t)((j) + 1) * nxe + (size_t)((i) + 1))
 #define YE(i, j) ((size_t)((j) + 1) * nye + (size_t)((i) + 1))
     const edge_t *EX = g->w_EX, *EY = g->w_EY;
-    const double *Flim = g->w_Flim, *Ftr = g->w_Ftr, *Glim = g->w_Glim, *Gtr = g->w_Gtr;
+    const real *Flim = g->w_Flim, *Ftr = g->w_Ftr, *Glim = g->w_Glim, *Gtr = g->w_Gtr;
     for (int j = 0; j < ny; j++) {
         size_t xl = XE(0, j), xr = XE(nx, j);
         for (int m = 0; m < 7; m++) {
@@ -1388,9 +1427,11 @@ int orc_edge_dflux(const orc_params *p, int dir, const double *qL, const double 
                    double bL, double bR, double c2L, double c2R, double *df)
 {
     edge_t E;
-    int rc = dir ? riemann_y(p, qL, qR, bL, bR, c2L, c2R, &E)
-                 : riemann_n(p, qL, qR, bL, bR, c2L, c2R, &E);
-    for (int m = 0; m < 7; m++) df[m] = E.amdq[m] + E.apdq[m];
+    real a[7], c[7];
+    for (int m = 0; m < 7; m++) { a[m] = qL[m]; c[m] = qR[m]; }
+    int rc = dir ? riemann_y(p, a, c, bL, bR, c2L, c2R, &E)
+                 : riemann_n(p, a, c, bL, bR, c2L, c2R, &E);
+    for (int m = 0; m < 7; m++) df[m] = (double)(E.amdq[m] + E.apdq[m]);
     return rc;
 }
 

@@ -18,6 +18,10 @@
  *
  * State layout at this interface: q[7][ny][nx], row-major, conserved
  * variables in the order of Appendix C: h, hu, hv, hw, h*sigma, hp, h*p_b.
+ *
+ * Precision: FP64.  Compiled with -DORC_LONG_DOUBLE the same source computes
+ * in x87 extended precision behind this same FP64 interface (orc_framed is
+ * then refused); that build measures the FP64 oracle's own rounding error.
  */
 #ifndef HSGN_ORACLE_H
 #define HSGN_ORACLE_H

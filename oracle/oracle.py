@@ -13,18 +13,24 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HSGN_ORACLE_LIB", os.path.join(HERE, "libhsgn_oracle.so"))
+# the same source in x87 extended precision (measurement of the FP64
+# oracle's own rounding error on a case; never a parity reference)
+LIB_PATH_EXT = os.path.join(HERE, "libhsgn_oracle_ext.so")
 SRC_PATH = os.path.join(HERE, "hsgn_oracle.c")
 
 OK, EINVAL, ENOMEM, ECFL, ENONHYP, ENAN, ERANGE = 0, -1, -2, -3, -4, -5, -6
 
 
 def build(openmp: bool = True) -> str:
-    """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-           "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", "-o", LIB_PATH, SRC_PATH, "-lm"]
-    if openmp:
-        cmd.insert(1, "-fopenmp")
-    subprocess.run(cmd, check=True)
+    """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math;
+    once in FP64 and once in extended precision."""
+    for path, extra in ((LIB_PATH, []), (LIB_PATH_EXT, ["-DORC_LONG_DOUBLE"])):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+               "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas"] + extra + \
+              ["-o", path, SRC_PATH, "-lm"]
+        if openmp:
+            cmd.insert(1, "-fopenmp")
+        subprocess.run(cmd, check=True)
     return LIB_PATH
 
 
@@ -47,61 +53,73 @@ def _params(p) -> OrcParams:
 
 
 _lib = None
+_lib_ext = None
 
 
-def lib():
-    global _lib
+def lib(extended: bool = False):
+    """the FP64 oracle, or (extended=True) its extended-precision build"""
+    global _lib, _lib_ext
+    if extended:
+        if _lib_ext is None:
+            if not os.path.exists(LIB_PATH_EXT):
+                build()
+            _lib_ext = _bind(ctypes.CDLL(LIB_PATH_EXT))
+        return _lib_ext
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_create.restype = ctypes.c_void_p
-        L.orc_create.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, ctypes.c_int,
-                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                 ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
-        L.orc_destroy.argtypes = [ctypes.c_void_p]
-        for name in ("orc_set_bathymetry", "orc_set_state", "orc_get_state"):
-            getattr(L, name).argtypes = [ctypes.c_void_p, dp]
-        L.orc_get_mask.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
-        L.orc_set_mask.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
-        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
-        L.orc_advance.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
-        L.orc_initial_dt.argtypes = [ctypes.c_void_p, dp]
-        L.orc_get_clock.argtypes = [ctypes.c_void_p, dp, dp,
-                                    ctypes.POINTER(ctypes.c_longlong),
-                                    ctypes.POINTER(ctypes.c_longlong)]
-        L.orc_set_clock.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_longlong]
-        L.orc_set_gauges.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
-        L.orc_read_gauges.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int,
-                                      ctypes.POINTER(ctypes.c_int)]
-        L.orc_mass.restype = ctypes.c_double
-        L.orc_mass.argtypes = [ctypes.c_void_p]
-        L.orc_clipped_mass.restype = ctypes.c_double
-        L.orc_clipped_mass.argtypes = [ctypes.c_void_p]
-        L.orc_riemann_x.argtypes = [ctypes.POINTER(OrcParams), dp, dp, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
-        L.orc_source_cell.argtypes = [dp, ctypes.c_double, ctypes.c_double]
-        L.orc_source_cell_mb.argtypes = [dp, ctypes.c_double, ctypes.c_double]
-        ucp = ctypes.POINTER(ctypes.c_ubyte)
-        L.orc_framed.argtypes = [ctypes.c_void_p, ctypes.POINTER(dp), ctypes.POINTER(dp),
-                                 ctypes.POINTER(ucp), ctypes.POINTER(ucp), ctypes.POINTER(ucp),
-                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
-        L.orc_set_external_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.orc_set_sponge.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_longlong,
-                                     ctypes.c_longlong, ctypes.c_longlong, ctypes.c_longlong]
-        L.orc_update_phi_framed.argtypes = [ctypes.c_void_p]
-        L.orc_set_mapping.argtypes = [ctypes.c_void_p, dp, dp]
-        L.orc_boundary_flux.argtypes = [ctypes.c_void_p, dp]
-        L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, dp]
-        L.orc_gauge_eta.restype = ctypes.c_double
-        L.orc_gauge_eta.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
-        _lib = L
+        _lib = _bind(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def _bind(L):
+    """argument and result types of the oracle's C interface"""
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_create.restype = ctypes.c_void_p
+    L.orc_create.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, ctypes.c_int,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+    L.orc_destroy.argtypes = [ctypes.c_void_p]
+    for name in ("orc_set_bathymetry", "orc_set_state", "orc_get_state"):
+        getattr(L, name).argtypes = [ctypes.c_void_p, dp]
+    L.orc_get_mask.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    L.orc_set_mask.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
+    L.orc_advance.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
+    L.orc_initial_dt.argtypes = [ctypes.c_void_p, dp]
+    L.orc_get_clock.argtypes = [ctypes.c_void_p, dp, dp,
+                                ctypes.POINTER(ctypes.c_longlong),
+                                ctypes.POINTER(ctypes.c_longlong)]
+    L.orc_set_clock.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_longlong]
+    L.orc_set_gauges.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+    L.orc_read_gauges.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int)]
+    L.orc_mass.restype = ctypes.c_double
+    L.orc_mass.argtypes = [ctypes.c_void_p]
+    L.orc_clipped_mass.restype = ctypes.c_double
+    L.orc_clipped_mass.argtypes = [ctypes.c_void_p]
+    L.orc_riemann_x.argtypes = [ctypes.POINTER(OrcParams), dp, dp, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                dp, dp, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    L.orc_source_cell.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+    L.orc_source_cell_mb.argtypes = [dp, ctypes.c_double, ctypes.c_double]
+    ucp = ctypes.POINTER(ctypes.c_ubyte)
+    L.orc_framed.argtypes = [ctypes.c_void_p, ctypes.POINTER(dp), ctypes.POINTER(dp),
+                             ctypes.POINTER(ucp), ctypes.POINTER(ucp), ctypes.POINTER(ucp),
+                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.orc_set_external_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_set_sponge.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_longlong,
+                                 ctypes.c_longlong, ctypes.c_longlong, ctypes.c_longlong]
+    L.orc_update_phi_framed.argtypes = [ctypes.c_void_p]
+    L.orc_set_mapping.argtypes = [ctypes.c_void_p, dp, dp]
+    L.orc_boundary_flux.argtypes = [ctypes.c_void_p, dp]
+    L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, dp]
+    L.orc_gauge_eta.restype = ctypes.c_double
+    L.orc_gauge_eta.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    return L
 
 
 def _dp(a: np.ndarray):
@@ -122,8 +140,8 @@ def _check(rc, where):
 class OracleGrid:
     """One grid patch advanced by the oracle."""
 
-    def __init__(self, params, grid):
-        L = lib()
+    def __init__(self, params, grid, extended=False):
+        L = self.L = lib(extended)
         self.params = params
         self.grid = grid
         self._p = _params(params)
@@ -136,7 +154,7 @@ class OracleGrid:
 
     def close(self):
         if self.h:
-            lib().orc_destroy(self.h)
+            self.L.orc_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -148,65 +166,65 @@ class OracleGrid:
     def set_bathymetry(self, b):
         b = np.ascontiguousarray(b, dtype=np.float64)
         assert b.shape == (self.grid.ny, self.grid.nx)
-        _check(lib().orc_set_bathymetry(self.h, _dp(b)), "set_bathymetry")
+        _check(self.L.orc_set_bathymetry(self.h, _dp(b)), "set_bathymetry")
 
     def set_state(self, q):
         q = np.ascontiguousarray(q, dtype=np.float64)
         assert q.shape == (7, self.grid.ny, self.grid.nx)
-        _check(lib().orc_set_state(self.h, _dp(q)), "set_state")
+        _check(self.L.orc_set_state(self.h, _dp(q)), "set_state")
 
     def get_state(self):
         q = np.empty((7, self.grid.ny, self.grid.nx))
-        _check(lib().orc_get_state(self.h, _dp(q)), "get_state")
+        _check(self.L.orc_get_state(self.h, _dp(q)), "get_state")
         return q
 
     def get_mask(self):
         m = np.empty((self.grid.ny, self.grid.nx), dtype=np.uint8)
-        _check(lib().orc_get_mask(self.h, m.ctypes.data_as(ctypes.c_char_p)), "get_mask")
+        _check(self.L.orc_get_mask(self.h, m.ctypes.data_as(ctypes.c_char_p)), "get_mask")
         return m
 
     def set_mask(self, m):
         m = np.ascontiguousarray(m, dtype=np.uint8)
-        _check(lib().orc_set_mask(self.h, m.ctypes.data_as(ctypes.c_char_p)), "set_mask")
+        _check(self.L.orc_set_mask(self.h, m.ctypes.data_as(ctypes.c_char_p)), "set_mask")
 
     def step(self, dt):
         c = ctypes.c_double(0.0)
-        _check(lib().orc_step(self.h, dt, ctypes.byref(c)), "step")
+        _check(self.L.orc_step(self.h, dt, ctypes.byref(c)), "step")
         return c.value
 
     def advance(self, dt, n):
-        _check(lib().orc_advance(self.h, float(dt), int(n)), "advance")
+        _check(self.L.orc_advance(self.h, float(dt), int(n)), "advance")
 
     def initial_dt(self):
         d = ctypes.c_double(0.0)
-        _check(lib().orc_initial_dt(self.h, ctypes.byref(d)), "initial_dt")
+        _check(self.L.orc_initial_dt(self.h, ctypes.byref(d)), "initial_dt")
         return d.value
 
     def clock(self):
         t, d = ctypes.c_double(), ctypes.c_double()
         s, r = ctypes.c_longlong(), ctypes.c_longlong()
-        _check(lib().orc_get_clock(self.h, ctypes.byref(t), ctypes.byref(d),
+        _check(self.L.orc_get_clock(self.h, ctypes.byref(t), ctypes.byref(d),
                                    ctypes.byref(s), ctypes.byref(r)), "get_clock")
         return t.value, d.value, s.value, r.value
 
     def set_clock(self, t, dt_next, steps):
-        _check(lib().orc_set_clock(self.h, t, dt_next, steps), "set_clock")
+        _check(self.L.orc_set_clock(self.h, t, dt_next, steps), "set_clock")
 
     def set_gauges(self, xy):
         xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         self.ngauge = xy.shape[0]
-        _check(lib().orc_set_gauges(self.h, self.ngauge, _dp(xy)), "set_gauges")
+        _check(self.L.orc_set_gauges(self.h, self.ngauge, _dp(xy)), "set_gauges")
 
     def read_gauges(self, max_records=1 << 20):
         t = np.empty(max_records)
         e = np.empty((max_records, max(self.ngauge, 1)))
         n = ctypes.c_int(0)
-        _check(lib().orc_read_gauges(self.h, _dp(t), _dp(e), max_records,
+        _check(self.L.orc_read_gauges(self.h, _dp(t), _dp(e), max_records,
                                      ctypes.byref(n)), "read_gauges")
         return t[:n.value].copy(), e[:n.value, :self.ngauge].copy()
 
     def mass(self):
-        return lib().orc_mass(self.h)
+        return self.L.orc_mass(self.h)
 
     # --- patch sets: framed arrays shared with the C grid (no copies) ---
     def framed(self):
@@ -217,7 +235,7 @@ class OracleGrid:
         q, b = dp(), dp()
         phi, brk, ifc = ucp(), ucp(), ucp()
         sx, sy = ctypes.c_int(), ctypes.c_int()
-        _check(lib().orc_framed(self.h, ctypes.byref(q), ctypes.byref(b), ctypes.byref(phi),
+        _check(self.L.orc_framed(self.h, ctypes.byref(q), ctypes.byref(b), ctypes.byref(phi),
                                 ctypes.byref(brk), ctypes.byref(ifc), ctypes.byref(sx),
                                 ctypes.byref(sy)), "framed")
         n = sx.value * sy.value
@@ -235,7 +253,7 @@ class OracleGrid:
         w = np.ascontiguousarray(width, dtype=np.float64)
         assert w.shape == (4,)
         nxd, nyd = domain if domain is not None else (self.grid.nx, self.grid.ny)
-        _check(lib().orc_set_sponge(self.h, _dp(w), float(rate), int(offset[0]), int(offset[1]),
+        _check(self.L.orc_set_sponge(self.h, _dp(w), float(rate), int(offset[0]), int(offset[1]),
                                     int(nxd), int(nyd)), "set_sponge")
 
     def set_mapping(self, xn, yn):
@@ -247,29 +265,29 @@ class OracleGrid:
         yn = np.ascontiguousarray(yn, dtype=np.float64)
         assert xn.shape == (g.ny + 5, g.nx + 5) and yn.shape == xn.shape
         self._nodes = (xn, yn)
-        _check(lib().orc_set_mapping(self.h, _dp(xn), _dp(yn)), "set_mapping")
+        _check(self.L.orc_set_mapping(self.h, _dp(xn), _dp(yn)), "set_mapping")
 
     def set_external_ghosts(self, on=True):
-        lib().orc_set_external_ghosts(self.h, 1 if on else 0)
+        self.L.orc_set_external_ghosts(self.h, 1 if on else 0)
 
     def update_phi_framed(self):
-        _check(lib().orc_update_phi_framed(self.h), "update_phi_framed")
+        _check(self.L.orc_update_phi_framed(self.h), "update_phi_framed")
 
     def boundary_flux(self):
         nx, ny = self.grid.nx, self.grid.ny
         K = np.empty((2 * ny + 2 * nx, 7))
-        _check(lib().orc_boundary_flux(self.h, _dp(K)), "boundary_flux")
+        _check(self.L.orc_boundary_flux(self.h, _dp(K)), "boundary_flux")
         return K
 
     def gauge_eta(self, x, y):
-        return lib().orc_gauge_eta(self.h, float(x), float(y))
+        return self.L.orc_gauge_eta(self.h, float(x), float(y))
 
     def clipped_mass(self):
-        return lib().orc_clipped_mass(self.h)
+        return self.L.orc_clipped_mass(self.h)
 
 
-def from_workload(w) -> OracleGrid:
-    g = OracleGrid(w.params, w.grid)
+def from_workload(w, extended=False) -> OracleGrid:
+    g = OracleGrid(w.params, w.grid, extended=extended)
     g.set_bathymetry(w.b)
     g.set_state(w.q)
     if w.gauges is not None and len(w.gauges):

@@ -16,6 +16,8 @@ def pytest_configure(config):
 def _oracle_built():
     """Compile the CPU oracle once per session (test infrastructure)."""
     from oracle import oracle as O
-    if not os.path.exists(O.LIB_PATH) or os.path.getmtime(O.LIB_PATH) < os.path.getmtime(O.SRC_PATH):
+    libs = (O.LIB_PATH, O.LIB_PATH_EXT)
+    if any(not os.path.exists(p) or os.path.getmtime(p) < os.path.getmtime(O.SRC_PATH)
+           for p in libs):
         O.build()
     yield

@@ -1,10 +1,11 @@
 """GPU parity of static patch sets (AMR) against the FP64 oracle.
 
 Bar (FP64): every field of every patch within 1e-11 of the oracle relative
-to that field's largest magnitude on the patch, masks equal, gauges within
-1e-11 of the amplitude.  Both sides evaluate the same formulas in the same
-order without fused multiply-add.  Mixed precision: gauges within 1e-4 of
-the amplitude.  The level-0 step of a patch set is replayed from a HIP
+to that field's largest magnitude on the patch, or, on the deep basin, within
+ten times the oracle's own spread under one-ulp changes of the depths
+(parity.py); masks equal, gauges within 1e-11 of the amplitude.  The two
+sides evaluate the method in independent operation orders.  Mixed
+precision: gauges within 1e-4 of the amplitude.  The level-0 step of a patch set is replayed from a HIP
 graph; the runs below replay it several times with host reads in between
 and compare every intermediate state.
 """
@@ -19,11 +20,10 @@ from paper_2606_12162_amd import hsgn as H
 from paper_2606_12162_amd import workloads as W
 
 from cases import rough_case
+from oracle.parity import TOL, field_errors, oracle_bars
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-TOL = 1e-11
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -35,18 +35,23 @@ def _gpu():
     yield
 
 
-def field_errors(got, exp):
-    scale = np.abs(exp).max(axis=(1, 2))
-    err = np.abs(got - exp).max(axis=(1, 2))
-    return np.where(scale > 0, err / np.where(scale > 0, scale, 1.0), err)
+def amr_states(w, chunks):
+    """oracle states of every patch after each chunk of level-0 steps"""
+    o = A.from_workload(w)
+    out = []
+    for c in chunks:
+        o.advance(w.dt, c)
+        out += [o.get_state(k) for k in range(len(w.patches))]
+    return out
 
 
-def compare(ctx, ids, o, w, what):
+def compare(ctx, ids, o, w, what, bars):
     worst = 0.0
     for pid, k in zip(ids, range(len(w.patches))):
         e = field_errors(ctx.get_state(pid), o.get_state(k))
-        assert np.all(e <= TOL), "%s patch %d (level %d): %s" % (
-            what, k, w.patches[k].level, np.array2string(e, precision=2))
+        assert np.all(e <= bars[k]), "%s patch %d (level %d): %s bars %s" % (
+            what, k, w.patches[k].level, np.array2string(e, precision=2),
+            np.array2string(bars[k], precision=2))
         assert np.array_equal(ctx.get_mask(pid), o.get_mask(k)), (what, k)
         worst = max(worst, float(e.max()))
     return worst
@@ -75,12 +80,15 @@ def test_three_levels_fp64_parity_across_graph_replays():
     w = W.amr_small(steps=6)
     print("case", w.name, flush=True)
     ctx, ids = H.from_amr_workloads([w])
+    _, bars = oracle_bars(lambda x: amr_states(x, (1, 2, 3)), w)
+    npch = len(w.patches)
     o = A.from_workload(w)
     worst = 0.0
-    for chunk in (1, 2, 3):                    # graph replays with host reads between
+    for c, chunk in enumerate((1, 2, 3)):      # graph replays with host reads between
         ctx.advance(-1.0, chunk)
         o.advance(w.dt, chunk)
-        worst = max(worst, compare(ctx, ids[0], o, w, "after %d more steps" % chunk))
+        worst = max(worst, compare(ctx, ids[0], o, w, "after %d more steps" % chunk,
+                                   bars[c * npch:(c + 1) * npch]))
         t, dtn, steps = ctx.clock(0)
         assert abs(t - o.t) <= 1e-12 * o.t and steps == o.steps
     print("worst relative field error", worst)
@@ -179,15 +187,20 @@ def test_patch_sets_and_single_grids_in_one_context():
     ctx.set_clock(0, 0.0, a.dt, 0)
     ctx.set_clock(1, 0.0, g.dt, 0)
     ctx.advance(-1.0, 2)
+    _, bars = oracle_bars(lambda x: amr_states(x, (2,)), a)
     o = A.from_workload(a)
     o.advance(a.dt, 2)
-    compare(ctx, ids, o, a, "patch set")
-    r = O.OracleGrid(g.params, g.grid)
-    r.set_bathymetry(g.b)
-    r.set_state(g.q)
-    r.advance(g.dt, 2)
-    e = field_errors(ctx.get_state(gid), r.get_state())
-    assert np.all(e <= TOL), e
+    compare(ctx, ids, o, a, "patch set", bars)
+
+    def grid_run(x):
+        r = O.OracleGrid(x.params, x.grid)
+        r.set_bathymetry(x.b)
+        r.set_state(x.q)
+        r.advance(x.dt, 2)
+        return [r.get_state()]
+    exp, gbar = oracle_bars(grid_run, g)
+    e = field_errors(ctx.get_state(gid), exp[0])
+    assert np.all(e <= gbar[0]), (e, gbar[0])
     ctx.close()
 
 

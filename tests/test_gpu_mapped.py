@@ -2,10 +2,10 @@
 through the C ABI.
 
 Bar: fields within 1e-11 of the oracle relative to each field's largest
-magnitude (the mapped kernel follows the oracle's operations, so the bits
-usually agree), masks equal; the identity mapping of a Cartesian grid gives
-the Cartesian run's bits; a Cartesian scenario stepped in the same launch as
-a mapped one keeps its bits; capacity-weighted mass against the oracle's;
+magnitude (the two sides evaluate the method in independent operation
+orders), masks equal; on the GPU the identity mapping of a Cartesian grid
+gives the Cartesian run's bits, and a Cartesian scenario stepped in the same
+launch as a mapped one keeps the bits it has alone; capacity-weighted mass against the oracle's;
 in mixed precision the gauges within 1e-4 of the amplitude of the FP64
 mapped run and a lake at rest exact; unsupported combinations refused.
 """
@@ -69,7 +69,8 @@ def test_identity_mapping_gives_the_cartesian_bits(bc):
     qo, mo, _ = oracle_run(w, None, 12, w.dt)
     assert np.array_equal(qm, qc)
     assert np.array_equal(mm, mc)
-    assert np.array_equal(qm, qo)
+    assert np.all(field_errors(qm, qo) <= TOL)
+    assert np.array_equal(mm, mo)
 
 
 def mapped_cases():
@@ -126,7 +127,8 @@ def test_cartesian_scenario_beside_a_mapped_one_keeps_its_bits():
     ctx.advance(a.dt, 10)
     qa, qb = ctx.get_state(0), ctx.get_state(1)
     ctx.close()
-    assert np.array_equal(qa, oracle_run(a, None, 10, a.dt)[0])
+    assert np.array_equal(qa, gpu_run(a, None, 10, a.dt)[0])
+    assert np.all(field_errors(qa, oracle_run(a, None, 10, a.dt)[0]) <= TOL)
     assert np.all(field_errors(qb, oracle_run(b, xy, 10, a.dt)[0]) <= TOL)
 
 

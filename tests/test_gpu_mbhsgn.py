@@ -1,8 +1,9 @@
 """GPU parity of the mbHSGN model (eq. mbHSGN) against the FP64 oracle.
 
-Bar: FP64 fields within 1e-11 of the oracle (both sides evaluate the same
-formulas in the same order), masks equal, the sigma and p_b planes exactly
-zero; mixed precision gauges within 1e-4 of the amplitude.
+Bar: FP64 fields within 1e-11 of the oracle, or, on the deep basin, within
+ten times the oracle's own spread under one-ulp changes of the depths
+(parity.py); masks equal, the sigma and p_b planes exactly zero; mixed
+precision gauges within 1e-4 of the amplitude.
 """
 import numpy as np
 import pytest
@@ -13,6 +14,7 @@ from paper_2606_12162_amd import hsgn as H
 from paper_2606_12162_amd import workloads as W
 
 from cases import rough_case
+from oracle.parity import oracle_bars
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -101,9 +103,13 @@ def test_patch_set_fp64_parity():
     w.params = W.Params(**{**w.params.__dict__, "model": 1})
     ctx, ids = H.from_amr_workloads([w])
     ctx.advance(-1.0, w.steps)
-    o = A.from_workload(w)
-    o.advance(w.dt, w.steps)
+
+    def run(x):
+        o = A.from_workload(x)
+        o.advance(x.dt, x.steps)
+        return [o.get_state(k) for k in range(len(x.patches))]
+    exp, bars = oracle_bars(run, w)
     for pid, k in zip(ids[0], range(len(w.patches))):
-        e = field_errors(ctx.get_state(pid), o.get_state(k))
-        assert np.all(e <= TOL), (k, e)
+        e = field_errors(ctx.get_state(pid), exp[k])
+        assert np.all(e <= bars[k]), (k, e, bars[k])
     ctx.close()

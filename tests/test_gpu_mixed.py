@@ -3,7 +3,9 @@ fix-ups and mass sums) against the FP64 oracle.
 
 Bar: gauge error max |eta'_mixed - eta'_oracle| <= 1e-4 of the source
 amplitude on the same fixed time steps; the ocean at rest stays exactly at
-rest in FP32; mass drift stays at FP32 rounding level.
+rest in FP32; mass drift stays at FP32 rounding level.  The FP64 runs of the
+ensembles (deep water) meet the FP64 bar of parity.py: 1e-11, or ten times
+the oracle's own spread under one-ulp changes of the depths.
 """
 import numpy as np
 import pytest
@@ -11,6 +13,8 @@ import pytest
 from oracle import oracle as O
 from paper_2606_12162_amd import hsgn as H
 from paper_2606_12162_amd import workloads as W
+
+from oracle.parity import TOL, field_errors, oracle_bars
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -23,6 +27,13 @@ def _gpu():
     torch.cuda.set_device(0)
     H.lib()
     yield
+
+
+def fixed_run(w, steps=None, extended=False):
+    """the oracle's state after `steps` (default: the workload's) fixed steps"""
+    r = O.from_workload(w, extended=extended)
+    r.advance(w.dt, w.steps if steps is None else steps)
+    return r.get_state()
 
 
 def mixed_context(ws, tile_rows=0):
@@ -107,11 +118,19 @@ def test_ensemble_one_launch_per_step_fp64_parity_and_mixed_gauges():
             tg, eg = ctx.read_gauges(s)
             to, eo = r.read_gauges()
             if bar is None:
-                got, exp = ctx.get_state(s), r.get_state()
-                scale = np.abs(exp).max(axis=(1, 2))
-                err = np.abs(got - exp).max(axis=(1, 2)) / np.where(scale > 0, scale, 1.0)
-                assert err.max() <= 1e-11, err
-                assert np.abs(eg - eo).max() <= 1e-11 * w.amplitude
+                got = ctx.get_state(s)
+                exp, bars = oracle_bars(lambda x: [fixed_run(x)], w)
+                err = field_errors(got, exp[0])
+                assert np.all(err <= bars[0]), (err, bars[0])
+                assert np.abs(eg - eo).max() <= TOL * w.amplitude
+                # which side rounds more: both against the same source in
+                # extended precision (the GPU within 3x of the oracle's
+                # own FP64 error, field by field)
+                ext = fixed_run(w, extended=True)
+                e_gpu, e_orc = field_errors(got, ext), field_errors(exp[0], ext)
+                print("  vs extended precision: GPU", np.array2string(e_gpu, precision=1),
+                      "oracle", np.array2string(e_orc, precision=1))
+                assert np.all(e_gpu <= 3.0 * e_orc + TOL)
             else:
                 ge = np.abs(eg - eo).max() / w.amplitude
                 print("  gauge error / amplitude", ge)
@@ -155,12 +174,9 @@ def test_full_ensemble_launch_two_scenarios_against_oracle():
     for s in picks:
         w = ws[s]
         print("case", w.name, flush=True)
-        r = O.from_workload(w)
-        r.advance(w.dt, 2)
-        got, exp = runs[0].get_state(s), r.get_state()
-        scale = np.abs(exp).max(axis=(1, 2))
-        err = np.abs(got - exp).max(axis=(1, 2)) / np.where(scale > 0, scale, 1.0)
-        assert err.max() <= 1e-11, err
+        exp, bars = oracle_bars(lambda x: [fixed_run(x, 2)], w)
+        err = field_errors(runs[0].get_state(s), exp[0])
+        assert np.all(err <= bars[0]), (err, bars[0])
     worst = 0.0
     for s, w in enumerate(ws):
         _, e0 = runs[0].read_gauges(s)

@@ -1,4 +1,4 @@
-"""GPU parity for every run option of the step (FP64, bitwise bar 1e-11).
+"""GPU parity for every run option of the step (FP64, bar 1e-11).
 
 The rough wet/dry case (ragged tiles, two boundary conditions, SWE and
 dispersive cells, breaking) is advanced with each limiter, without the

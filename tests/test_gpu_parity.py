@@ -3,10 +3,14 @@
 Bar: every conserved field within 1e-11 of the oracle relative to that
 field's largest magnitude, masks (transition function and breaking latch)
 equal, clocks equal to 1e-12, gauges within 1e-11 of the wave amplitude.
-Both sides compute in FP64 without fused multiply-add; they differ only in
-summation order (the kernel regroups the transverse split per cell and
-solves the source step's 4x4 systems in closed form), so results agree to a
-few ulps per step.
+Both sides compute in FP64 without fused multiply-add, in independent
+operation orders: the oracle splits each edge's transverse fluctuations on
+their own, applies the update formula as written, divides where the method
+divides and solves the source stages by Gaussian elimination; the kernel
+splits the sum of a cell's entering fluctuations once, adds contributions in
+its own order, shares reciprocals and solves the stages in closed form.  The
+cases here are shallow (depths of order 1), where the two agree to about
+1e-12 after hundreds of steps.
 """
 import numpy as np
 import pytest

@@ -181,8 +181,11 @@ int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rat
  * Gauges and the sponge layer use computational coordinates.  Mass in
  * hsgn_diagnostics is sum(capacity h) dx dy.
  * After hsgn_finalize; may be called again to change the mapping.
- * HSGN_ENOTSUP: patch sets, or a context with a sponge layer.  HSGN_EINVAL: bad patch, null pointers, or a cell of non-positive
- * area or an edge of zero length (the patch keeps its previous geometry). */
+ * The first mapping in a context drops a captured step graph (the step
+ * launches switch to the mapped kernel).  HSGN_ENOTSUP: patch sets, or a
+ * context with a sponge layer.  HSGN_EINVAL: bad patch, null pointers, or a
+ * cell of non-positive area or an edge of zero length (the patch keeps its
+ * previous geometry). */
 int hsgn_set_mapping(hsgn_ctx *ctx, int patch, const double *xn, const double *yn);
 
 /* State q[7][ny][nx] (float64) of a patch, copied in or out. */
@@ -279,7 +282,8 @@ int hsgn_get_timing(hsgn_ctx *c, double *step_kernel_ms, long long *launches);
  * levels <= l, then the new ones).  Tile heights return to the library's
  * choice.  n_new (may be NULL) receives the number of new patches.  Errors:
  * EINVAL (not finalized, bad parameters, bathymetry not set), ENOTSUP (not a
- * patch set), ENOMEM, EDEVICE; on error the context is unchanged. */
+ * patch set, or the context holds a mapped grid, which the rebuilt context
+ * would not carry), ENOMEM, EDEVICE; on error the context is unchanged. */
 typedef struct hsgn_regrid_params {
     int level;          /* rebuild level + 1 from flags on this level */
     int nbuf;           /* buffer width in level cells (0..64) */

@@ -1569,12 +1569,17 @@ int hsgn_set_mapping(hsgn_ctx *c, int patch, const double *xn, const double *yn)
     std::vector<double> m;
     if (!mapping_metric(p, xn, yn, m))
         return fail(c, HSGN_EINVAL, "mapping with a cell of non-positive area or an edge of zero length");
+    // work already queued may still read the patch table and the metric
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->d_metric.size() < c->patches.size()) c->d_metric.resize(c->patches.size(), nullptr);
     if (!c->d_metric[patch])
         HIPCHK(c, hipMalloc((void **)&c->d_metric[patch], sizeof(double) * m.size()));
     HIPCHK(c, hipMemcpy(c->d_metric[patch], m.data(), sizeof(double) * m.size(),
                         hipMemcpyHostToDevice));
     p.metric = c->d_metric[patch];
+    // the first mapped patch switches every step launch to the mapped kernel;
+    // a step graph captured before holds the Cartesian one
+    if (!c->any_mapped) drop_graph(c);
     c->any_mapped = true;
     HIPCHK(c, hipMemcpy(c->d_patches, c->patches.data(), sizeof(PatchInfo) * c->patches.size(),
                         hipMemcpyHostToDevice));
@@ -2826,6 +2831,10 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
         return fail(c, HSGN_EINVAL, "bad scenario");
     ScenHost &sh = c->scen[scenario];
     if (!sh.amr) return fail(c, HSGN_ENOTSUP, "regridding needs a patch set (tile level 0)");
+    // the rebuilt context carries sponges but not mappings: a mapped single
+    // grid beside the patch set would silently become Cartesian
+    if (c->any_mapped)
+        return fail(c, HSGN_ENOTSUP, "regridding in a context that holds a mapped grid");
     const int level = r->level;
     if (level < 0 || level >= (int)sh.lev.size() || level + 1 > 5 || !(r->tol == r->tol) ||
         r->nbuf < 0 || r->nbuf > 64 || !(r->cutoff > 0.0 && r->cutoff <= 1.0) || r->max_side < 1)

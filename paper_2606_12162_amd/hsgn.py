@@ -209,8 +209,13 @@ class Context:
         (i, j), i = -2..nx+2, j = -2..ny+2 (two ghost layers included)"""
         xn = np.ascontiguousarray(xn, dtype=np.float64)
         yn = np.ascontiguousarray(yn, dtype=np.float64)
-        if xn.shape != yn.shape or xn.ndim != 2:
-            raise ValueError("node arrays of one shape [ny + 5][nx + 5] expected")
+        nx, ny = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(lib().hsgn_patch_info(self.h, int(patch), None, None, ctypes.byref(nx),
+                                          ctypes.byref(ny), None, None, None, None),
+                    "hsgn_patch_info")
+        if xn.shape != (ny.value + 5, nx.value + 5) or yn.shape != xn.shape:
+            raise ValueError("node arrays of shape [ny + 5][nx + 5] = (%d, %d) expected, got %s, %s"
+                             % (ny.value + 5, nx.value + 5, xn.shape, yn.shape))
         self._check(lib().hsgn_set_mapping(self.h, int(patch), ctypes.c_void_p(xn.ctypes.data),
                                            ctypes.c_void_p(yn.ctypes.data)), "hsgn_set_mapping")
 

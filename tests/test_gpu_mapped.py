@@ -209,3 +209,63 @@ def test_mixed_mapped_split_step_is_bitwise_the_full_kernel(monkeypatch):
         ctx.close()
     for a, b in zip(*runs):
         assert np.array_equal(a, b)
+
+
+def test_mapping_set_between_graph_replays_beside_a_patch_set():
+    """a context with a patch set (its level-0 step replayed from a HIP
+    graph) and a single grid of the same deep basin: after one step, the
+    single grid is mapped (rotated); the next steps run the mapped kernel
+    (the graph captured before holds the Cartesian one and is dropped), and
+    a regrid is then refused because the rebuilt context would not carry
+    the mapping.  Deep water: the FP64 bar of oracle/parity.py."""
+    from oracle import amr as A
+    from oracle.parity import oracle_bars
+    a = W.amr_small(steps=3)
+    g = dataclasses.replace(W.amr_small_uniform(0, steps=3), gauges=np.zeros((0, 2)))
+    c, s = np.cos(0.4), np.sin(0.4)
+    xy = nodes(g.grid, lambda x, y: c * x - s * y, lambda x, y: s * x + c * y)
+    ctx = H.Context(a.params)
+    ids = []
+    for p in a.patches:
+        d = 4.0 ** p.level
+        grid = W.Grid(p.nx, p.ny, p.x0, p.y0, a.dx0 / d, a.dy0 / d, a.bc)
+        ids.append(ctx.add_grid(0, grid, level=p.level))
+    gid = ctx.add_grid(1, g.grid)
+    ctx.finalize()
+    for pid, p in zip(ids, a.patches):
+        ctx.set_bathymetry(pid, p.b)
+        ctx.set_state(pid, p.q)
+    ctx.set_bathymetry(gid, g.b)
+    ctx.set_state(gid, g.q)
+    ctx.set_clock(0, 0.0, a.dt, 0)
+    ctx.set_clock(1, 0.0, g.dt, 0)
+    ctx.advance(-1.0, 1)
+    ctx.set_mapping(gid, *xy)
+    ctx.advance(-1.0, 2)
+
+    def mapped_run(x, extra=0):
+        r = O.from_workload(x)
+        r.advance(x.dt, 1)
+        r.set_mapping(*xy)
+        r.advance(x.dt, 2 + extra)
+        return [r.get_state()]
+    exp, gbar = oracle_bars(mapped_run, g)
+    err = field_errors(ctx.get_state(gid), exp[0])
+    print("mapped grid beside a patch set", np.array2string(err, precision=2),
+          "bars", np.array2string(gbar[0], precision=2), flush=True)
+    assert np.all(err <= gbar[0])
+
+    def run(x):
+        o = A.from_workload(x)
+        o.advance(x.dt, 3)
+        return [o.get_state(k) for k in range(len(x.patches))]
+    exp, bars = oracle_bars(run, a)
+    for pid, k in zip(ids, range(len(a.patches))):
+        assert np.all(field_errors(ctx.get_state(pid), exp[k]) <= bars[k]), k
+    with pytest.raises(H.HsgnError) as e:
+        ctx.regrid(0, 0, tol=0.002)
+    assert e.value.code == H.HSGN_ENOTSUP
+    ctx.advance(-1.0, 1)                       # still usable, still mapped
+    exp, gbar = oracle_bars(lambda x: mapped_run(x, 1), g)
+    assert np.all(field_errors(ctx.get_state(gid), exp[0]) <= gbar[0])
+    ctx.close()

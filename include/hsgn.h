@@ -70,6 +70,7 @@ extern "C" {
 #define HSGN_ERANGE     -6   /* gauge outside its scenario's patches */
 #define HSGN_EDEVICE    -7   /* HIP runtime error */
 #define HSGN_ENOTSUP    -8   /* option not supported by this build */
+#define HSGN_ESCRATCH   -9   /* grid larger than hsgn_advance_static's working memory */
 
 #define HSGN_BC_PERIODIC 0
 #define HSGN_BC_WALL     1   /* reflecting wall: mirror, normal momentum negated */
@@ -299,6 +300,35 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
 int hsgn_num_patches(hsgn_ctx *c, int *n);
 int hsgn_patch_info(hsgn_ctx *c, int patch, int *scenario, int *level, int *nx, int *ny,
                     double *x0, double *y0, double *dx, double *dy);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one FP64
+ * single grid advanced by n_steps fixed steps of dt with no allocation and
+ * no context.  It runs the kernels of hsgn_advance (the same bits as a
+ * context holding this one grid, FP64, fixed dt).
+ *   p          parameters as for hsgn_create; precision must be 0 (FP64,
+ *              else ENOTSUP); tile_rows as there
+ *   hip_stream borrowed hipStream_t; all work is enqueued on it, and the
+ *              call synchronizes it once at the end to read the status
+ *   nx, ny     grid size (>= 4); dx, dy spacings; bc[4] as for hsgn_add_grid
+ *   b          device pointer, bathymetry [ny][nx] float64 (read only)
+ *   q          device pointer, state [7][ny][nx] float64 in conserved
+ *              variables (h, hu, hv, hw, h sigma, hp, h p_b), advanced in
+ *              place; on ECFL, ENONHYP or ENAN it holds the last good step
+ *   steps_done receives the accepted steps (may be NULL)
+ * phi_T is derived from b at every call and the breaking latch starts
+ * cleared; no gauges, sponge or mapping.  The working memory (spare state
+ * buffer, masks, tables: 58 bytes per cell plus a few KB) is a static array
+ * of HSGN_STATIC_SCRATCH_MIB MiB per device, reserved when the library is
+ * loaded on that device and held until the process ends; grids beyond it
+ * return ESCRATCH (about 1.1 M cells: 1024 x 1024 fits).  Every call on a
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialized by the caller.
+ * Errors: EINVAL, ENOTSUP, ESCRATCH, ECFL, ENONHYP, ENAN, EDEVICE. */
+#define HSGN_STATIC_SCRATCH_MIB 64
+int hsgn_advance_static(const hsgn_params *p, void *hip_stream, int nx, int ny, double dx,
+                        double dy, const int bc[4], const double *b, double *q, double dt,
+                        int n_steps, long long *steps_done);
 
 int hsgn_destroy(hsgn_ctx *c);
 const char *hsgn_strerror(int code);

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include <map>
+#include <mutex>
 #include <thread>
 
 #include "hsgn.h"
@@ -996,16 +997,16 @@ const char *hsgn_strerror(int code)
     case HSGN_ERANGE: return "gauge outside the scenario's patches";
     case HSGN_EDEVICE: return "HIP runtime error";
     case HSGN_ENOTSUP: return "not supported";
+    case HSGN_ESCRATCH: return "grid larger than the static working memory of hsgn_advance_static";
     default: return "unknown status";
     }
 }
 
 const char *hsgn_last_error(hsgn_ctx *c) { return c ? c->last_error.c_str() : ""; }
 
-int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
+// parameter checks shared by hsgn_create and hsgn_advance_static
+static int check_params(const hsgn_params *p)
 {
-    if (!p || !out) return HSGN_EINVAL;
-    *out = nullptr;
     if ((p->model != 0 && p->model != 1) || (p->precision != 0 && p->precision != 1))
         return HSGN_ENOTSUP;
     if (!(p->g > 0) || p->alpha < 0 || !(p->dry_tol >= 0) || !(p->cfl > 0) ||
@@ -1013,6 +1014,28 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
         p->limiter > 3 || (p->transverse != 0 && p->transverse != 2) ||
         (p->splitting != 0 && p->splitting != 1) || !(p->xi1 > 0) || !(p->c2 >= 0))
         return HSGN_EINVAL;
+    return HSGN_OK;
+}
+
+static StepParams step_params(const hsgn_params *p)
+{
+    StepParams P;
+    P.g = p->g;
+    P.a2g = p->c2 > 0.0 ? 0.0 : p->alpha * p->alpha * p->g;
+    P.c2f = p->c2 > 0.0 ? p->c2 : 0.0;
+    P.eta0 = p->eta0; P.h_star = p->h_star; P.dry_tol = p->dry_tol;
+    P.xi0 = p->xi0; P.xi1 = p->xi1; P.kappa = p->kappa;
+    P.limiter = p->limiter; P.transverse = p->transverse; P.splitting = p->splitting;
+    P.model = p->model;
+    return P;
+}
+
+int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
+{
+    if (!p || !out) return HSGN_EINVAL;
+    *out = nullptr;
+    int prc = check_params(p);
+    if (prc) return prc;
     hsgn_ctx *c = new (std::nothrow) hsgn_ctx();
     if (!c) return HSGN_ENOMEM;
     c->prm = *p;
@@ -1022,14 +1045,7 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     const char *nosplit = getenv("HSGN_NO_KERNEL_SPLIT");
     c->split = c->mixed && !(nosplit && nosplit[0] == '1');
     c->stream = (hipStream_t)hip_stream;
-    StepParams &P = c->P;
-    P.g = p->g;
-    P.a2g = p->c2 > 0.0 ? 0.0 : p->alpha * p->alpha * p->g;
-    P.c2f = p->c2 > 0.0 ? p->c2 : 0.0;
-    P.eta0 = p->eta0; P.h_star = p->h_star; P.dry_tol = p->dry_tol;
-    P.xi0 = p->xi0; P.xi1 = p->xi1; P.kappa = p->kappa;
-    P.limiter = p->limiter; P.transverse = p->transverse; P.splitting = p->splitting;
-    P.model = p->model;
+    c->P = step_params(p);
     *out = c;
     return HSGN_OK;
 }
@@ -2552,6 +2568,174 @@ int hsgn_work_items(hsgn_ctx *c, int *n)
     if (!c || !c->finalized || !n) return fail(c, HSGN_EINVAL, "call hsgn_finalize first");
     *n = (int)c->work.size();
     return HSGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// hsgn_advance_static: one FP64 single grid advanced without any allocation.
+// Its working memory (the spare state buffer, both mask buffers, the patch,
+// clock and work tables, the clipped-mass slots) lives in the file-scope
+// array below, one copy per device, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: the device address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is used.
+
+constexpr size_t HSGN_STATIC_BYTES = (size_t)HSGN_STATIC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[HSGN_STATIC_BYTES];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+std::once_flag g_scratch_once[STATIC_MAX_DEVICES];
+unsigned char *g_scratch_ptr[STATIC_MAX_DEVICES];
+hipError_t g_scratch_err[STATIC_MAX_DEVICES];
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// byte offsets of the working memory's parts for ncell cells and nwork items
+struct StaticLayout {
+    size_t q1, m0, m1, patch, sstat, scen, work, clip, total;
+};
+
+StaticLayout static_layout(long long ncell, long long nwork)
+{
+    StaticLayout L;
+    size_t o = 0;
+    L.q1 = o;    o = align256(o + sizeof(double) * 7 * (size_t)ncell);
+    L.m0 = o;    o = align256(o + (size_t)ncell);
+    L.m1 = o;    o = align256(o + (size_t)ncell);
+    L.patch = o; o = align256(o + sizeof(PatchInfo));
+    L.sstat = o; o = align256(o + sizeof(ScenStatic));
+    L.scen = o;  o = align256(o + sizeof(ScenState));
+    L.work = o;  o = align256(o + sizeof(WorkItem) * (size_t)nwork);
+    L.clip = o;  o = align256(o + sizeof(double) * (size_t)nwork);
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+// the patch, clock and work tables of the grid, written from kernel
+// arguments (no host buffer, no memset: safe under graph capture)
+__global__ void static_setup_kernel(PatchInfo pi, ScenStatic ss, ScenState st, PatchInfo *dp,
+                                    ScenStatic *dss, ScenState *dst, WorkItem *work, double *clip,
+                                    int nwork, int nstrips, int th)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k == 0) { *dp = pi; *dss = ss; *dst = st; }
+    if (k < nwork) {
+        const int r0 = (k / nstrips) * th;
+        work[k] = WorkItem{0, (k % nstrips) * 60, r0, min(th, pi.ny - r0)};
+        clip[k] = 0.0;
+    }
+}
+
+// Q^n back into the caller's buffer when the last accepted step left it in
+// the spare one
+__global__ void static_copyback_kernel(const ScenState *st, const double *q1, double *q,
+                                       long long n)
+{
+    if (!st->cur) return;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        q[i] = q1[i];
+}
+
+int hsgn_advance_static(const hsgn_params *p, void *hip_stream, int nx, int ny, double dx,
+                        double dy, const int bc[4], const double *b, double *q, double dt,
+                        int n_steps, long long *steps_done)
+{
+    if (steps_done) *steps_done = 0;
+    if (!p || !bc || !b || !q) return HSGN_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->precision != 0) return HSGN_ENOTSUP;
+    if (nx < 4 || ny < 4 || !(dx > 0) || !(dy > 0) || !(dt > 0) || n_steps < 0)
+        return HSGN_EINVAL;
+    for (int k = 0; k < 4; k++)
+        if (bc[k] < 0 || bc[k] > 2) return HSGN_EINVAL;
+    if ((bc[0] == HSGN_BC_PERIODIC) != (bc[1] == HSGN_BC_PERIODIC) ||
+        (bc[2] == HSGN_BC_PERIODIC) != (bc[3] == HSGN_BC_PERIODIC))
+        return HSGN_EINVAL;
+    const long long ncell = (long long)nx * ny;
+    if (ncell > (long long)(HSGN_STATIC_BYTES / 58)) return HSGN_ESCRATCH;
+    // tile height: the library's cost model for one FP64 grid (1024
+    // resident wavefronts), unless the caller fixes it
+    const long long nstrips = (nx + 59) / 60, slots = 1024;
+    int th = p->tile_rows > 0 ? p->tile_rows : 64;
+    if (p->tile_rows <= 0) {
+        long long best = -1;
+        for (int t = 64; t >= 8; t--) {
+            const long long cost = ((nstrips * ((ny + t - 1) / t) + slots - 1) / slots) * (t + 4);
+            if (best < 0 || cost < best) { best = cost; th = t; }
+        }
+    }
+    const long long nwork = nstrips * ((ny + th - 1) / th);
+    const StaticLayout L = static_layout(ncell, nwork);
+    if (L.total > HSGN_STATIC_BYTES) return HSGN_ESCRATCH;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES)
+        return HSGN_EDEVICE;
+    std::call_once(g_scratch_once[dev], [dev]() {
+        void *ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = (unsigned char *)ptr;
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev]) return HSGN_EDEVICE;
+    unsigned char *base = g_scratch_ptr[dev];
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    PatchInfo pi;
+    memset(&pi, 0, sizeof(pi));
+    pi.nx = nx; pi.ny = ny; pi.pitch = nx; pi.scen = 0;
+    for (int k = 0; k < 4; k++) pi.bc[k] = bc[k];
+    pi.dx = dx; pi.dy = dy;
+    pi.qoff = 0; pi.coff = 0; pi.plane = ncell; pi.eoff = -1;
+    pi.level = 0; pi.frame = 0; pi.metric = nullptr;
+    ScenStatic ss;
+    ss.dx = dx; ss.dy = dy; ss.cfl = p->cfl; ss.cfl_max = p->cfl_max;
+    ss.w0 = 0; ss.w1 = (int)nwork;
+    ScenState st;
+    memset(&st, 0, sizeof(st));
+    st.dt = dt; st.dt_fixed = dt;
+    st.target = n_steps;
+    st.active = n_steps > 0 ? 1 : 0;
+
+    double *q1 = (double *)(base + L.q1);
+    uint8_t *m0 = base + L.m0, *m1 = base + L.m1;
+    PatchInfo *dp = (PatchInfo *)(base + L.patch);
+    ScenStatic *dss = (ScenStatic *)(base + L.sstat);
+    ScenState *dst = (ScenState *)(base + L.scen);
+    WorkItem *work = (WorkItem *)(base + L.work);
+    double *clip = (double *)(base + L.clip);
+
+    static_setup_kernel<<<nblk(nwork), 256, 0, s>>>(pi, ss, st, dp, dss, dst, work, clip,
+                                                    (int)nwork, (int)nstrips, th);
+    mask_kernel<double><<<nblk(ncell), 256, 0, s>>>(pi, b, m0, m1, p->eta0, p->h_star, p->nbr_n);
+    MarchArgs<double> A;
+    A.P = step_params(p);
+    A.patches = dp;
+    A.work = work;
+    A.q0 = q; A.q1 = q1;
+    A.bath = b;
+    A.m0 = m0; A.m1 = m1;
+    A.scen = dst;
+    A.clip_slots = clip;
+    A.eflux = nullptr;
+    A.list = nullptr; A.lcnt = nullptr; A.clsb = nullptr;
+    A.sponge = 0; A.mapped = 0;
+    A.nwork = (int)nwork;
+    for (int a = 0; a < n_steps; a++) {
+        launch_march64(A, (unsigned)nwork, s);
+        control_kernel<<<1, 256, 0, s>>>(dst, dss, clip, 1);
+    }
+    static_copyback_kernel<<<nblk(std::min<long long>(7 * ncell, 1 << 22)), 256, 0, s>>>(
+        dst, q1, q, 7 * ncell);
+    if (hipGetLastError() != hipSuccess) return HSGN_EDEVICE;
+    ScenState out;
+    if (hipMemcpyAsync(&out, dst, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return HSGN_EDEVICE;
+    if (steps_done) *steps_done = out.steps;
+    return out.err;
 }
 
 int hsgn_destroy(hsgn_ctx *c)

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsgn.so")
 
 HSGN_OK, HSGN_EINVAL, HSGN_ENOMEM, HSGN_ECFL, HSGN_ENONHYP, HSGN_ENAN, HSGN_ERANGE, \
-    HSGN_EDEVICE, HSGN_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
+    HSGN_EDEVICE, HSGN_ENOTSUP, HSGN_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 BC_PERIODIC, BC_WALL, BC_EXTRAP = 0, 1, 2
 
 EXPORTS = ("hsgn_create", "hsgn_add_grid", "hsgn_finalize", "hsgn_set_bathymetry",
@@ -25,8 +25,8 @@ EXPORTS = ("hsgn_create", "hsgn_add_grid", "hsgn_finalize", "hsgn_set_bathymetry
            "hsgn_set_gauges", "hsgn_read_gauges", "hsgn_advance", "hsgn_diagnostics",
            "hsgn_get_clock", "hsgn_set_clock", "hsgn_work_items", "hsgn_set_timing",
            "hsgn_get_timing", "hsgn_autotune", "hsgn_regrid", "hsgn_num_patches",
-           "hsgn_patch_info", "hsgn_set_mapping", "hsgn_set_sponge", "hsgn_destroy", "hsgn_strerror",
-           "hsgn_last_error")
+           "hsgn_patch_info", "hsgn_set_mapping", "hsgn_set_sponge", "hsgn_advance_static",
+           "hsgn_destroy", "hsgn_strerror", "hsgn_last_error")
 
 
 class hsgn_params(ctypes.Structure):
@@ -93,6 +93,10 @@ def lib():
         L.hsgn_set_mapping.argtypes = [vp, ctypes.c_int, vp, vp]
         L.hsgn_num_patches.argtypes = [vp, ip]
         L.hsgn_patch_info.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip, dp, dp, dp, dp]
+        L.hsgn_advance_static.argtypes = [ctypes.POINTER(hsgn_params), vp, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_int), vp, vp, ctypes.c_double,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
         L.hsgn_destroy.argtypes = [vp]
         L.hsgn_strerror.argtypes = [ctypes.c_int]
         L.hsgn_strerror.restype = ctypes.c_char_p
@@ -316,6 +320,25 @@ class Context:
         n = ctypes.c_int()
         self._check(lib().hsgn_work_items(self.h, ctypes.byref(n)), "hsgn_work_items")
         return n.value
+
+
+def advance_static(params, grid, b, q, dt, n_steps, stream=None, tile_rows=0):
+    """hsgn_advance_static: one FP64 grid (workloads.Grid) advanced in place
+    by n_steps fixed steps with no allocation; b [ny][nx] and q [7][ny][nx]
+    are float64 CUDA tensors.  Returns the accepted steps."""
+    for a in (b, q):
+        if not (hasattr(a, "is_cuda") and a.is_cuda and a.is_contiguous()):
+            raise TypeError("contiguous CUDA tensors expected")
+    prm = make_params(params, tile_rows, 0)
+    bc = (ctypes.c_int * 4)(*grid.bc)
+    done = ctypes.c_longlong(0)
+    s = ctypes.c_void_p(stream) if stream is not None else None
+    rc = lib().hsgn_advance_static(ctypes.byref(prm), s, grid.nx, grid.ny, grid.dx, grid.dy, bc,
+                                   ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                   float(dt), int(n_steps), ctypes.byref(done))
+    if rc != HSGN_OK:
+        raise HsgnError(rc, "hsgn_advance_static")
+    return done.value
 
 
 def from_amr_workloads(workloads, tile_rows=0, stream=None, gauges=True, precision=0):

@@ -19,20 +19,30 @@ one step is a level-0 step with its 4 + 16 substeps, a cell update is one
 cell advanced one step of its own level).
 
 Inputs are synthetic (seeded generators in paper_2606_12162_amd/workloads.py)
-and resident in HBM before timing starts.  The step kernel issues far more
-vector ALU instructions than its HBM bytes need (about 20 flops per byte), so
-the JSON line's roofline is its algorithmic floating-point work, 1259 flops
-per cell update (counted by csrc/opcount.cpp), over its average launch time
-(HIP events on the library's stream; in mixed precision a "launch" is the
-split step: item classification, the two item lists, and the kernels
-without and with the FP64 edge solve, the last on a second stream joined
-back before the closing event), against the vector ALU peak of the chip
-(256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s, the same for FP64
-and for unpacked FP32).  The algorithmic HBM rate is reported beside it, and
-`traffic` is the HBM bytes per launch measured with rocprofv3 counters (the
-sum over the kernels of one launch) for the current kernel sources (null
-when the sources have changed since).
-cpu_baseline is the FP64 CPU oracle on a bounded sample of the same workload.
+and resident in HBM before timing starts.  The JSON line's roofline is the
+HBM one: the algorithmic bytes of a cell update (read Q^n and write Q^{n+1},
+7 variables, read the bathymetry and the mask byte: 121 B in FP64, 61 B in
+mixed precision) times the cells one step-kernel launch advances, over that
+launch's average time (HIP events on the library's stream; in mixed
+precision a "launch" is the split step: item classification, the two item
+lists, and the kernels without and with the FP64 edge solve, the last on a
+second stream joined back before the closing event), against 8 TB/s.  The
+kernel issues far more vector ALU instructions than those bytes need, so
+the vector ALU rate is reported beside it: 1259 algorithmic flops per cell
+update (csrc/opcount.cpp) against 78.6 TFLOP/s (256 CUs x 64 FMA lanes x 2
+flops x 2.4 GHz, unpacked FP32 and FP64) and against the 157.3 TFLOP/s of
+packed FP32.  `traffic` is the HBM bytes per launch measured with rocprofv3
+counters (the sum over the kernels of one launch) for the current kernel
+sources (null when the sources have changed since).
+After the timed steps, an untimed leg advances the workload again from its
+initial state over its whole horizon (--gauge-steps, default the workload's
+step count: 3000 for the ensemble) in mixed precision and in FP64 with the
+same fixed steps, and reports per scenario the gauge error and the final
+surface-field error of the mixed run against the FP64 run, relative to the
+source amplitude.
+cpu_baseline is the FP64 CPU oracle on a bounded sample of the same
+workload: the median of 3 runs on the host threads given to the process, the
+CPU model and core counts, and a single-thread run.
 
 `python bench.py --copy-calibration` runs one 2 GiB device copy and nothing
 else: the kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate the byte
@@ -52,11 +62,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12      # 78.6
+PACKED_FP32_PEAK_TFLOPS = 157.3
 # algorithmic flops per cell update (csrc/opcount.cpp)
 ALG_FLOPS = 1259
 # algorithmic bytes per cell update: read Q^n and write Q^{n+1} (7 variables),
-# read the bathymetry, read and write the mask byte
-ALG_BYTES = {"fp64": 7 * 8 * 2 + 8 + 2, "mixed": 7 * 4 * 2 + 4 + 2}
+# read the bathymetry and the mask byte
+ALG_BYTES = {"fp64": 7 * 8 * 2 + 8 + 1, "mixed": 7 * 4 * 2 + 4 + 1}
 # what one timed step-kernel launch is
 STEP_KERNELS = {"fp64": "march_kernel<fp64>",
                 "mixed": "classify + lists + march_kernel<mixed> (deep items) "
@@ -219,24 +230,98 @@ def amr_updates(w):
     return sum(p.nx * p.ny * 4 ** p.level for p in w.patches)
 
 
-def cpu_baseline(w, steps, nodes=None):
+def host_cpu():
+    """CPU model, physical cores and logical CPUs of the host, and the CPUs
+    this process may run on"""
+    model, cores = "unknown", set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name":
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, len(cores) or None, os.cpu_count(), avail
+
+
+def cpu_baseline(w, steps, nodes=None, runs=3, single_steps=None):
     """The FP64 oracle as it stands, on `steps` steps of one workload (on its
-    mapped grid when node coordinates are given)."""
+    mapped grid when node coordinates are given): the median of `runs` runs
+    on the threads given to the process (OMP_NUM_THREADS, at most the CPUs
+    available), and one single-thread run of `single_steps` steps."""
+    import ctypes
     from oracle import oracle as O
     if not os.path.exists(O.LIB_PATH):
         O.build()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    g = O.from_workload(w)
-    if nodes is not None:
-        g.set_mapping(*nodes)
-    t0 = time.perf_counter()
-    g.advance(w.dt, steps)
-    el = time.perf_counter() - t0
+    O.lib()
+    model, phys, logical, avail = host_cpu()
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", avail)), avail)
+    gomp = ctypes.CDLL("libgomp.so.1")
+
+    def one(n, nthreads):
+        gomp.omp_set_num_threads(int(nthreads))
+        g = O.from_workload(w)
+        if nodes is not None:
+            g.set_mapping(*nodes)
+        t0 = time.perf_counter()
+        g.advance(w.dt, n)
+        el = time.perf_counter() - t0
+        g.close()
+        return w.grid.nx * w.grid.ny * n / el, el
+
+    rates = [one(steps, threads) for _ in range(runs)]
+    med = sorted(r for r, _ in rates)[runs // 2]
+    single_steps = single_steps or max(1, steps // 10)
+    r1, el1 = one(single_steps, 1)
+    gomp.omp_set_num_threads(int(threads))
     cells = w.grid.nx * w.grid.ny
-    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "first %d steps of %s%s (%d cell-updates), wall %.1f s, FP64"
-                      % (steps, w.name, " (mapped)" if nodes is not None else "", cells * steps, el)}
+    return {"value": med, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "runs": [r for r, _ in rates], "single_thread": r1,
+            "cpu_model": model, "host_physical_cores": phys, "host_logical_cpus": logical,
+            "cpus_available": avail,
+            "sample": "first %d steps of %s%s (%d cell-updates per run), median of %d runs, "
+                      "%d threads, wall %.1f s each; single thread: %d steps in %.1f s; FP64"
+                      % (steps, w.name, " (mapped)" if nodes is not None else "", cells * steps,
+                         runs, threads, sorted(e for _, e in rates)[runs // 2], single_steps, el1)}
+
+
+def horizon_errors(H, ws, steps):
+    """Untimed: the workload from its initial state over `steps` fixed steps
+    in mixed precision and in FP64; per scenario the gauge error and the
+    final surface-field error (eta' over cells wet in both runs) of the mixed
+    run against the FP64 run, over the source amplitude, and the relative
+    error of the momenta."""
+    res = {}
+    for precision in ("mixed", "fp64"):
+        ctx = make_context(H, ws, precision)
+        ctx.advance(-1.0, steps)
+        res[precision] = [(ctx.read_gauges(s)[1], ctx.get_state(s)) for s in range(len(ws))]
+        ctx.close()
+    gauge, field, mom = [], [], []
+    for s, w in enumerate(ws):
+        (ga, qa), (gb, qb) = res["mixed"][s], res["fp64"][s]
+        n = min(len(ga), len(gb))
+        gauge.append(float(np.abs(ga[:n] - gb[:n]).max()) / w.amplitude if n else 0.0)
+        eta0 = w.params.eta0
+        wet = (qa[0] > w.params.dry_tol) & (qb[0] > w.params.dry_tol)
+        ea, eb = qa[0] + w.b - eta0, qb[0] + w.b - eta0
+        field.append(float(np.abs(ea - eb)[wet].max()) / w.amplitude)
+        m = max(float(np.abs(qb[1:3]).max()), 1e-300)
+        mom.append(float(np.abs(qa[1:3] - qb[1:3]).max()) / m)
+    return {"steps": steps, "records": n, "gauge_err_over_amp": gauge,
+            "field_err_over_amp": field, "momentum_rel_err": mom,
+            "max_gauge_err_over_amp": max(gauge), "max_field_err_over_amp": max(field)}
 
 
 def gauge_error(ctx_a, ctx_b, ws):
@@ -275,6 +360,9 @@ def main():
     ap.add_argument("--mapped", action="store_true",
                     help="ensemble or ocean on smoothly distorted mapped grids (fixed steps 0.85x)")
     ap.add_argument("--cpu-steps", type=int, default=0)
+    ap.add_argument("--gauge-steps", type=int, default=-1,
+                    help="steps of the untimed mixed-vs-FP64 leg (default: the workload's "
+                         "horizon; 0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -356,6 +444,7 @@ def main():
     tflops = ALG_FLOPS * cells_per_launch / (kms / 1e3) / 1e12
     hbm_gbs = ALG_BYTES[precision] * cells_per_launch / (kms / 1e3) / 1e9
     traffic = None if args.mapped else measured_traffic(args.workload, precision, rows)
+    alg_launch = ALG_BYTES[precision] * cells_per_launch
     dtype = {"mixed": "f32+f64", "fp64": "f64"}[precision]
     out = {
         "metric": "cell-updates/s",
@@ -377,31 +466,47 @@ def main():
                    "dt": "per-scenario fixed, cfl 0.9" if ws[0].dt > 0 else "adaptive, cfl 0.9",
                    "work_items": ctx.work_items(), "tile_rows": rows,
                    "max_courant_scenario0": diag["max_courant"]},
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
+        "roofline": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": ("march_kernel_mapped<%s> (split step in mixed precision)" % precision) if args.mapped
                                else STEP_KERNELS[precision], "kernel_avg_us": kms * 1e3,
-                     "launches": launches, "alg_flops_per_cell": ALG_FLOPS,
-                     "hbm": {"achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": hbm_gbs / HBM_PEAK_GBS,
-                             "alg_bytes_per_cell": ALG_BYTES[precision],
-                             "traffic_over_alg": (traffic / (ALG_BYTES[precision] * cells_per_launch)
-                                                  if traffic else None)}},
+                     "launches": launches, "alg_bytes_per_cell": ALG_BYTES[precision],
+                     "alg_bytes_per_launch": alg_launch,
+                     "traffic_over_alg": traffic / alg_launch if traffic else None,
+                     "alu": {"achieved": tflops, "unit": "TFLOP/s", "alg_flops_per_cell": ALG_FLOPS,
+                             "peak_fma": ALU_PEAK_TFLOPS, "frac_fma": tflops / ALU_PEAK_TFLOPS,
+                             "peak_packed_fp32": PACKED_FP32_PEAK_TFLOPS,
+                             "frac_packed_fp32": tflops / PACKED_FP32_PEAK_TFLOPS}},
     }
     if precision == "mixed" and not args.no_fp64:
         ctx64, el64, kms64, _, rows64 = run(H, torch, ws, "fp64", args.steps, args.warmup,
                                             tile_rows, not args.no_autotune)
+        hbm64 = ALG_BYTES["fp64"] * cells_per_launch / (kms64 / 1e3) / 1e9
         out["fp64_plain"] = {"value": cells * args.steps / el64,
                              "ms_per_step": el64 * 1e3 / args.steps,
-                             "kernel_avg_us": kms64 * 1e3, "tile_rows": rows64}
+                             "kernel_avg_us": kms64 * 1e3, "tile_rows": rows64,
+                             "roofline": {"bound": "hbm", "achieved": hbm64, "peak": HBM_PEAK_GBS,
+                                          "unit": "GB/s", "frac": hbm64 / HBM_PEAK_GBS,
+                                          "alg_bytes_per_cell": ALG_BYTES["fp64"],
+                                          "alu_tflops": ALG_FLOPS * cells_per_launch / (kms64 / 1e3) / 1e12}}
         out["mixed_over_fp64"] = value / out["fp64_plain"]["value"]
-        out["gauge_err_over_amp"] = gauge_error(ctx, ctx64, ws)
-        log("fp64: %.3f ms/step; mixed/fp64 %.2fx; gauge error / amplitude %.2e"
-            % (out["fp64_plain"]["ms_per_step"], out["mixed_over_fp64"], out["gauge_err_over_amp"]))
+        out["gauge_err_over_amp_timed_run"] = gauge_error(ctx, ctx64, ws)
+        log("fp64: %.3f ms/step; mixed/fp64 %.2fx; gauge error / amplitude over the timed run %.2e"
+            % (out["fp64_plain"]["ms_per_step"], out["mixed_over_fp64"],
+               out["gauge_err_over_amp_timed_run"]))
         ctx64.close()
     ctx.close()
+    gsteps = args.gauge_steps if args.gauge_steps >= 0 else ws[0].steps
+    if precision == "mixed" and not args.no_fp64 and gsteps > 0 and not amr and ws[0].dt > 0:
+        t1 = time.perf_counter()
+        he = horizon_errors(H, ws, gsteps)
+        out["horizon"] = he
+        out["gauge_err_over_amp"] = he["max_gauge_err_over_amp"]
+        log("horizon leg: %d steps, %.1f s; gauge error / amplitude max %.2e, field error / "
+            "amplitude max %.2e" % (gsteps, time.perf_counter() - t1, he["max_gauge_err_over_amp"],
+                                    he["max_field_err_over_amp"]))
     if not args.no_cpu_baseline:
-        steps = args.cpu_steps or (60 if args.workload == "ensemble" else 20)
+        steps = args.cpu_steps or (40 if args.workload == "ensemble" else 20)
         # patch sets: the oracle on the level-0 ocean grid of the same set
         base = W.synthetic_ocean() if amr else ws[0]
         out["cpu_baseline"] = cpu_baseline(base, steps, MAPPING[0] if MAPPING is not None else None)

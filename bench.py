@@ -351,6 +351,8 @@ def main():
                     help="amr_adaptive: surface-jump tolerance on level 0 (m)")
     ap.add_argument("--regrid-levels", type=int, default=1,
                     help="amr_adaptive: refined levels rebuilt by regridding (1 or 2)")
+    ap.add_argument("--precision", default="", choices=["", "mixed", "fp64"],
+                    help="precision of the timed run (default: mixed, FP64 for the beach)")
     ap.add_argument("--model", default="hsgn", choices=["hsgn", "mbhsgn"],
                     help="hsgn (eq. HSGN, default) or mbhsgn (eq. mbHSGN)")
     ap.add_argument("--tile-rows", type=int, default=0,
@@ -403,6 +405,8 @@ def main():
     else:
         ws, precision = [W.beach_soliton()], "fp64"
     amr = args.workload == "amr"
+    if args.precision:
+        precision = args.precision
     if args.mapped:
         global MAPPING
         if amr or args.workload not in ("ensemble", "ocean"):

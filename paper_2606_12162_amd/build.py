@@ -24,11 +24,11 @@ FLAGS = [
     "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wno-unused-result",
 ]
-# per-source floating-point contraction: the FP64 step kernels and the
-# patch-set kernels round every product and sum separately; the FP32 step
-# kernels and the host code may fuse
-CONTRACT = {"hsgn_step64.hip": "-ffp-contract=off", "hsgn_step64amr.hip": "-ffp-contract=off",
-            "hsgn_amr.hip": "-ffp-contract=off"}
+# per-source floating-point contraction: the patch-set kernels (ghost
+# interpolation, refluxing, averaging) round every product and sum
+# separately; the step kernels of both precisions and the host code may fuse
+# products into sums
+CONTRACT = {"hsgn_amr.hip": "-ffp-contract=off"}
 BUILD_DIR = os.path.join(HERE, "_build")
 
 

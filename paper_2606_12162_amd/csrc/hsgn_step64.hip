@@ -1,6 +1,5 @@
-// hsgn_step64.hip -- FP64 instantiation of the step kernel, compiled without
-// floating-point contraction so that products and sums round as in a plain
-// FP64 evaluation of the same formulas.
+// hsgn_step64.hip -- FP64 instantiation of the step kernel (its own
+// translation unit, so that the FP64 and FP32 instances compile in parallel).
 #include "hsgn_step.hpp"
 
 using namespace hsgn;

@@ -1,6 +1,5 @@
 // hsgn_step64amr.hip -- FP64 step kernel for patches of patch sets (stored
-// ghost frames, interface edges, boundary-flux records), compiled without
-// floating-point contraction like the plain FP64 kernel.
+// ghost frames, interface edges, boundary-flux records).
 #include "hsgn_step.hpp"
 
 using namespace hsgn;

@@ -1435,5 +1435,9 @@ int orc_edge_dflux(const orc_params *p, int dir, const double *qL, const double 
     return rc;
 }
 
+/* limiter function phi(theta) of Sec. 4 (0 first order, 1 minmod, 2 MC,
+ * 3 unlimited) */
+double orc_limiter_phi(int lim, double theta) { return (double)limiter_phi(lim, theta); }
+
 /* bilinear eta' of the patch at a point (same rule as the gauges) */
 double orc_gauge_eta(const orc_grid *g, double x, double y) { return gauge_eta(g, x, y); }

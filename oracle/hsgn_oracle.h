@@ -143,6 +143,8 @@ int orc_set_mapping(orc_grid *g, const double *xn, const double *yn);
 /* boundary-edge fluxes of the last step relative to the outside cell,
  * K[2 ny + 2 nx][7] (left rows, right rows, bottom columns, top columns) */
 int orc_boundary_flux(const orc_grid *g, double *K);
+/* limiter function phi(theta): lim 0 first order, 1 minmod, 2 MC, 3 none */
+double orc_limiter_phi(int lim, double theta);
 /* eta' at a point by the gauge rule (bilinear over the 4 nearest centres) */
 double orc_gauge_eta(const orc_grid *g, double x, double y);
 /* A-dQ + A+dQ of one edge, dir 0 = x, 1 = y */

@@ -117,6 +117,8 @@ def _bind(L):
     L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, dp]
+    L.orc_limiter_phi.restype = ctypes.c_double
+    L.orc_limiter_phi.argtypes = [ctypes.c_int, ctypes.c_double]
     L.orc_gauge_eta.restype = ctypes.c_double
     L.orc_gauge_eta.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
     return L
@@ -327,3 +329,8 @@ def source_cell(q, c2, tau, model=0):
     q = np.array(q, dtype=np.float64)
     (lib().orc_source_cell_mb if model == 1 else lib().orc_source_cell)(_dp(q), c2, tau)
     return q
+
+
+def limiter_phi(lim, theta):
+    """the oracle's limiter function phi(theta)"""
+    return lib().orc_limiter_phi(int(lim), float(theta))

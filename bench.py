@@ -11,7 +11,8 @@ in the mixed FP32/FP64 form with each scenario's own fixed CFL-0.9 step.
 The same ensemble is then advanced in plain FP64 over the same steps; the
 line reports both rates and the gauge error of the mixed run against the
 FP64 run (the FP64 kernels match the FP64 CPU oracle to 1e-11, see tests).
-Other workloads: --workload beach (1024^2 plane beach, FP64, adaptive),
+Other workloads: --workload hump (128^2 Gaussian hump, periodic, FP64,
+adaptive), --workload beach (1024^2 plane beach, FP64, adaptive),
 --workload ocean (2048^2 synthetic ocean, mixed and FP64) and --workload amr
 (the ocean as a three-level patch set: 256 level-0 patches of 128^2, 1000
 level-1 and 1250 level-2 patches of 16..128 cells around a circular wave;
@@ -344,7 +345,7 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="ensemble",
-                    choices=["ensemble", "beach", "ocean", "amr", "amr_adaptive"])
+                    choices=["ensemble", "hump", "beach", "ocean", "amr", "amr_adaptive"])
     ap.add_argument("--regrid-every", type=int, default=10,
                     help="amr_adaptive: level-0 steps between regrids")
     ap.add_argument("--regrid-tol", type=float, default=0.004,
@@ -402,6 +403,8 @@ def main():
         ws, precision = [W.synthetic_ocean()], "mixed"
     elif args.workload == "amr":
         ws, precision = [W.amr_ocean()], "mixed"
+    elif args.workload == "hump":
+        ws, precision = [W.gaussian_hump()], "fp64"
     else:
         ws, precision = [W.beach_soliton()], "fp64"
     amr = args.workload == "amr"

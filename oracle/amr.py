@@ -145,8 +145,25 @@ class AmrOracle:
             p.g.set_sponge(width, rate, offset=(p.I0, p.J0), domain=(self.NX * r, self.NY * r))
 
     # -------------------------------------------------------------- lookup
+    _BUCKET = 16
+
     def find(self, level, I, J):
-        for p in self.levels[level]:
+        """the patch of `level` containing level cell (I, J), or None; the
+        patches are looked up through 16 x 16-cell buckets of the level's
+        index space (each bucket lists the patches that overlap it, in
+        patch order)"""
+        idx = self.__dict__.setdefault("_index", {})
+        lp = self.levels[level]
+        ent = idx.get(level)
+        if ent is None or ent[0] != len(lp):
+            B = self._BUCKET
+            table = {}
+            for p in lp:
+                for bj in range(p.J0 // B, (p.J0 + p.ny - 1) // B + 1):
+                    for bi in range(p.I0 // B, (p.I0 + p.nx - 1) // B + 1):
+                        table.setdefault((bi, bj), []).append(p)
+            ent = idx[level] = (len(lp), table)
+        for p in ent[1].get((I // self._BUCKET, J // self._BUCKET), ()):
             if p.contains(I, J):
                 return p
         return None

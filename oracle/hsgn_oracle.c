@@ -84,6 +84,8 @@ struct orc_grid {
      * (length over dy) of the cell's left edge; yn*, ygm the same for its
      * bottom edge (towards increasing j, length over dx) */
     real *kap, *xnx, *xny, *xgm, *ynx, *yny, *ygm;
+    /* radially symmetric solutions (Appendix D): x is the radius */
+    int radial;
     real t, dt_next;
     long long nstep, nrej;
     int have_dt;
@@ -823,6 +825,51 @@ static void correction(int lim, real dtdx, const edge_t *El, const edge_t *E,
 }
 
 /* ------------------------------------------------------------------ */
+/* radially symmetric solutions (Appendix D).  With x the radius r and u the
+ * radial velocity, the 2D system reduces to the 1D one plus the geometric
+ * source -(1/r) (hu, hu u, hu w, hu sigma, hu (p + c^2), hu p_b) in the
+ * variables (h, hu, hw, h sigma, hp, h p_b); hv stays zero.  The source is
+ * integrated by Heun's method (explicit trapezoidal rule, second order) in
+ * half steps before and after the step (Strang splitting). */
+static void radial_source(const orc_grid *g, size_t k, real r, const real *q, real *s)
+{
+    for (int m = 0; m < 7; m++) s[m] = 0.0;
+    if (!(q[IH] > g->P.dry_tol)) return;
+    const real hu = q[IHU];
+    s[IH] = -hu / r;
+    s[IHU] = -hu * (q[IHU] / q[IH]) / r;
+    s[IHW] = -hu * (q[IHW] / q[IH]) / r;
+    s[IHS] = -hu * (q[IHS] / q[IH]) / r;
+    s[IHP] = -hu * (q[IHP] / q[IH] + cell_c2(g, k)) / r;
+    s[IHPB] = -hu * (q[IHPB] / q[IH]) / r;
+}
+
+static void radial_half_step(orc_grid *g, real tau)
+{
+    const size_t np = PLANE(g);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < g->ny; j++) {
+        for (int i = 0; i < g->nx; i++) {
+            const size_t k = CELL(g, i, j);
+            const real r = g->x0 + ((real)i + 0.5) * g->dx;
+            real q[7], k1[7], qs[7], k2[7];
+            for (int m = 0; m < 7; m++) q[m] = g->q[m * np + k];
+            radial_source(g, k, r, q, k1);
+            for (int m = 0; m < 7; m++) qs[m] = q[m] + tau * k1[m];
+            radial_source(g, k, r, qs, k2);
+            for (int m = 0; m < 7; m++) g->q[m * np + k] = q[m] + 0.5 * tau * (k1[m] + k2[m]);
+        }
+    }
+}
+
+int orc_set_radial(orc_grid *g, int on)
+{
+    if (on && (g->kap || g->ext_ghosts || g->x0 < 0.0)) return ORC_EINVAL;
+    g->radial = on ? 1 : 0;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* one step                                                             */
 
 static int step_grid(orc_grid *g, real dt, real *courant)
@@ -860,6 +907,7 @@ static int step_grid(orc_grid *g, real dt, real *courant)
 #define XE(i, j) ((size_t)((j) + 1) * nxe + (size_t)((i) + 1))
 #define YE(i, j) ((size_t)((j) + 1) * nye + (size_t)((i) + 1))
 
+    if (g->radial) radial_half_step(g, 0.5 * dt);
     if (!g->ext_ghosts) fill_ghosts(g);
 
     /* 1. source half step (Strang) on every cell including ghosts; Lie only
@@ -1071,6 +1119,7 @@ static int step_grid(orc_grid *g, real dt, real *courant)
         g->w_clip[j] = clip;
     }
     for (int j = 0; j < ny; j++) g->clipped += g->w_clip[j];
+    if (g->radial) radial_half_step(g, 0.5 * dt);
 
     /* 9. Courant number from the speeds of the edges of interior cells (on a
      *    mapped grid the scaled speeds over the smaller capacity of the

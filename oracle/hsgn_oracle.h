@@ -140,6 +140,12 @@ int orc_update_phi_framed(orc_grid *g);
  * the wall edge.  Refused (ORC_EINVAL) on patch-set grids and for a cell of
  * non-positive area or an edge of zero length. */
 int orc_set_mapping(orc_grid *g, const double *xn, const double *yn);
+/* radially symmetric solutions (Appendix D): the grid's x is the radius
+ * (x0 >= 0), u the radial velocity, and every step adds the geometric
+ * source -(1/r) (hu, hu u, 0, hu w, hu sigma, hu (p + c^2), hu p_b) by
+ * Heun's method in half steps before and after it.  Refused on mapped and
+ * patch-set grids and for x0 < 0. */
+int orc_set_radial(orc_grid *g, int on);
 /* boundary-edge fluxes of the last step relative to the outside cell,
  * K[2 ny + 2 nx][7] (left rows, right rows, bottom columns, top columns) */
 int orc_boundary_flux(const orc_grid *g, double *K);

@@ -117,6 +117,7 @@ def _bind(L):
     L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, dp]
+    L.orc_set_radial.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.orc_limiter_phi.restype = ctypes.c_double
     L.orc_limiter_phi.argtypes = [ctypes.c_int, ctypes.c_double]
     L.orc_gauge_eta.restype = ctypes.c_double
@@ -268,6 +269,11 @@ class OracleGrid:
         assert xn.shape == (g.ny + 5, g.nx + 5) and yn.shape == xn.shape
         self._nodes = (xn, yn)
         _check(self.L.orc_set_mapping(self.h, _dp(xn), _dp(yn)), "set_mapping")
+
+    def set_radial(self, on=True):
+        """radially symmetric solutions (Appendix D): x is the radius and
+        every step adds the geometric source terms"""
+        _check(self.L.orc_set_radial(self.h, 1 if on else 0), "set_radial")
 
     def set_external_ghosts(self, on=True):
         self.L.orc_set_external_ghosts(self.h, 1 if on else 0)

@@ -158,6 +158,81 @@ def gaussian_hump(n=128, dx=0.1, amplitude=0.05, width=1.0, H=1.0, alpha=3.0,
                     gauges, steps, 0.0, amplitude)
 
 
+# --------------------------------------------------------------------------
+# radially symmetric hump (Sec. 5, radially symmetric tests): h = H + A
+# exp(-r^2 / sigma^2) at rest over a flat bottom, r measured from the
+# origin; the quarter domain [0, L]^2 has walls on its left and bottom sides
+# and extrapolation on the others.  Auxiliary variables start at zero (the
+# same data for the 2D runs and for the radial 1D reference).
+
+RADIAL = dict(H=100.0, A=5.0, sigma=100.0, alpha=3.0)
+
+
+def _radial_state(R, H, A, sigma):
+    q = np.zeros((7,) + R.shape)
+    q[0] = H + A * np.exp(-(R / sigma) ** 2)
+    return q
+
+
+def _radial_dt(dx, t_end, H, A, alpha, cfl=0.9):
+    """a fixed step no larger than cfl dx / max Ce that divides t_end"""
+    ce = math.sqrt(G * (H + A) + alpha * alpha * G * H)
+    n = int(math.ceil(t_end / (cfl * dx / ce)))
+    return t_end / n, n
+
+
+def radial_hump(n=48, dx=50.0, t_end=12.0, **kw):
+    """the 2D quarter domain on one grid"""
+    c = dict(RADIAL, **kw)
+    grid = Grid(n, n, 0.0, 0.0, dx, dx, (BC_WALL, BC_EXTRAP, BC_WALL, BC_EXTRAP))
+    X, Y = cell_centres(grid)
+    q = _radial_state(np.sqrt(X ** 2 + Y ** 2), c["H"], c["A"], c["sigma"])
+    dt, steps = _radial_dt(dx, t_end, c["H"], c["A"], c["alpha"])
+    params = Params(alpha=c["alpha"], h_star=0.0, kappa=0.0)
+    return Workload("radial_hump_%dx%d" % (n, n), params, grid, np.full((n, n), -c["H"]), q,
+                    np.zeros((0, 2)), steps, dt, c["A"])
+
+
+def radial_hump_amr(n0=48, dx0=50.0, t_end=6.0, **kw):
+    """the hump at the centre c of the whole domain [0, n0 dx0]^2
+    (extrapolation on every side) as a three-level patch set (ratios 4, 4)
+    with the same physical layout at every dx0 that divides 50 m: level 0
+    one n0 x n0 grid; level 1 the square [c - 400 m, c + 400 m)^2; level 2
+    the square [c - 100 m, c + 100 m)^2.  The radius is measured from c."""
+    c = dict(RADIAL, **kw)
+    bc = (BC_EXTRAP,) * 4
+    ctr = 0.5 * n0 * dx0
+    specs = [(0, n0, n0, 0.0, 0.0)]
+    for lev, half in ((1, 400.0), (2, 100.0)):
+        side = int(round(2.0 * half / (dx0 / RATIO ** lev)))
+        specs.append((lev, side, side, ctr - half, ctr - half))
+    patches = []
+    for lev, nx, ny, x0, y0 in specs:
+        d = dx0 / RATIO ** lev
+        g = Grid(nx, ny, x0, y0, d, d, bc)
+        X, Y = cell_centres(g)
+        R = np.sqrt((X - ctr) ** 2 + (Y - ctr) ** 2)
+        patches.append(PatchSpec(lev, nx, ny, x0, y0, np.full((ny, nx), -c["H"]),
+                                 _radial_state(R, c["H"], c["A"], c["sigma"])))
+    dt, steps = _radial_dt(dx0, t_end, c["H"], c["A"], c["alpha"])
+    params = Params(alpha=c["alpha"], h_star=0.0, kappa=0.0)
+    return AmrWorkload("radial_hump_amr_%d" % n0, params, dx0, dx0, bc, patches,
+                       np.zeros((0, 2)), steps, dt, c["A"])
+
+
+def radial_strip(nr=7200, dr=0.5, t_end=12.0, **kw):
+    """the radial 1D reference problem: x is the radius, a strip of 4 rows
+    (periodic across), a wall at r = 0 and extrapolation at the far end"""
+    c = dict(RADIAL, **kw)
+    grid = Grid(nr, 4, 0.0, 0.0, dr, dr, (BC_WALL, BC_EXTRAP, BC_PERIODIC, BC_PERIODIC))
+    X, _ = cell_centres(grid)
+    q = _radial_state(X, c["H"], c["A"], c["sigma"])
+    dt, steps = _radial_dt(dr, t_end, c["H"], c["A"], c["alpha"])
+    params = Params(alpha=c["alpha"], h_star=0.0, kappa=0.0)
+    return Workload("radial_strip_%d" % nr, params, grid, np.full((4, nr), -c["H"]), q,
+                    np.zeros((0, 2)), steps, dt, c["A"])
+
+
 BEACH_GAUGE_X = (10.0, 15.0, 20.0, 25.0, 30.0, 35.0, 38.4, 40.0, 42.0, 44.0,
                  45.0, 46.0, 47.0, 48.0, 48.5, 49.0)
 

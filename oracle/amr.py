@@ -80,6 +80,12 @@ def _minmod(a, b):
     return 0.0
 
 
+def _minmod_arrays(a, b):
+    """_minmod element by element"""
+    return np.where((a > 0.0) & (b > 0.0), np.where(a <= b, a, b),
+                    np.where((a < 0.0) & (b < 0.0), np.where(a >= b, a, b), 0.0))
+
+
 class _Patch:
     def __init__(self, pid, level, nx, ny, x0, y0, dx, dy, I0, J0, grid):
         self.pid, self.level, self.nx, self.ny = pid, level, nx, ny
@@ -190,15 +196,6 @@ class AmrOracle:
         self.gauges = np.asarray(xy, dtype=np.float64).reshape(-1, 2)
 
     # --------------------------------------------------------------- set-up
-    def _c2(self, b, phi, brk):
-        if not phi or brk:
-            return 0.0
-        if getattr(self.P, "c2", 0.0) > 0.0:
-            return self.P.c2
-        H = self.P.eta0 - b
-        H = H if H > 0.0 else 0.0
-        return self.P.alpha * self.P.alpha * self.P.g * H
-
     def prepare(self):
         """bathymetry of covered coarse cells, ghost bathymetry, phi_T and
         the interface flags"""
@@ -212,27 +209,26 @@ class AmrOracle:
                 self._fill_ghost_bathymetry(p)
         for p in self.patches:
             p.g.update_phi_framed()
-        # interface flags of uncovered cells next to a finer patch
+        # interface flags of uncovered cells next to a finer patch: a
+        # level-lev cell (I, J) is covered when the finer cell (4 I, 4 J)
+        # lies in a level-(lev+1) patch; the coverage of each patch and a
+        # one-cell rim is painted from the finer patches
         for lev in range(len(self.levels) - 1):
             for p in self.levels[lev]:
                 p.iface[:] = 0
-                for j in range(p.ny):
-                    for i in range(p.nx):
-                        I, J = p.I0 + i, p.J0 + j
-                        if self._covered(lev, I, J):
-                            continue
-                        bits = 0
-                        for bit, (di, dj) in enumerate(((-1, 0), (1, 0), (0, -1), (0, 1))):
-                            if self._covered(lev, I + di, J + dj):
-                                bits |= 1 << bit
-                        p.iface[j + 2, i + 2] = bits
+                cov = np.zeros((p.ny + 2, p.nx + 2), dtype=bool)    # cells I0-1 .. I0+nx
+                for f in self.levels[lev + 1]:
+                    # I covered by f iff f.I0 <= 4 I < f.I0 + f.nx
+                    i0 = max(-(-f.I0 // RATIO), p.I0 - 1)
+                    i1 = min(-(-(f.I0 + f.nx) // RATIO), p.I0 + p.nx + 1)
+                    j0 = max(-(-f.J0 // RATIO), p.J0 - 1)
+                    j1 = min(-(-(f.J0 + f.ny) // RATIO), p.J0 + p.ny + 1)
+                    if i0 < i1 and j0 < j1:
+                        cov[j0 - p.J0 + 1:j1 - p.J0 + 1, i0 - p.I0 + 1:i1 - p.I0 + 1] = True
+                c = cov[1:-1, 1:-1]
+                bits = (cov[1:-1, :-2] * 1) | (cov[1:-1, 2:] * 2) | (cov[:-2, 1:-1] * 4) | (cov[2:, 1:-1] * 8)
+                p.iface[2:-2, 2:-2] = np.where(c, 0, bits).astype(np.uint8)
         self.prepared = True
-
-    def _covered(self, lev, I, J):
-        """level-lev cell (I, J) lies under a level-(lev+1) patch"""
-        if lev + 1 >= len(self.levels):
-            return False
-        return self.find(lev + 1, RATIO * I, RATIO * J) is not None
 
     def _ghost_cells(self, p):
         for j in range(-2, p.ny + 2):
@@ -257,90 +253,112 @@ class AmrOracle:
         oy = ((J - RATIO * Jc) + 0.5) / RATIO - 0.5
         return ("coarse", Ic, Jc, ox, oy)
 
-    def _fill_ghost_bathymetry(self, p):
+    def _ghost_tables(self, p):
+        """the ghost sources of patch p (static for the patch set), as
+        arrays in frame indices: copies grouped by source patch
+        (dj, di, sj, si, fx, fy), and the coarse ghosts (dj, di, ox, oy)
+        with, for the coarse centre and its left, right, lower and upper
+        neighbours, the coarse patch id (-1: none) and frame indices"""
+        tabs = self.__dict__.setdefault("_gtab", {})
+        if p.pid in tabs:
+            return tabs[p.pid]
+        copies = {}
+        co = {"dj": [], "di": [], "ox": [], "oy": [], "pid": [[] for _ in range(5)],
+              "cj": [[] for _ in range(5)], "ci": [[] for _ in range(5)]}
         for i, j in self._ghost_cells(p):
             src = self._source_of(p, i, j)
             if src[0] == "copy":
-                _, s, si, sj, _, _ = src
-                p.b[j + 2, i + 2] = s.b[sj + 2, si + 2]
-            else:
-                _, Ic, Jc, _, _ = src
-                c = self.find(p.level - 1, Ic, Jc)
-                p.b[j + 2, i + 2] = c.b[Jc - c.J0 + 2, Ic - c.I0 + 2]
+                _, sp, si, sj, fx, fy = src
+                c = copies.setdefault(sp.pid, ([], [], [], [], [], []))
+                for lst, v in zip(c, (j + 2, i + 2, sj + 2, si + 2, fx, fy)):
+                    lst.append(v)
+                continue
+            _, Ic, Jc, ox, oy = src
+            co["dj"].append(j + 2)
+            co["di"].append(i + 2)
+            co["ox"].append(ox)
+            co["oy"].append(oy)
+            for k, (di, dj) in enumerate(((0, 0), (-1, 0), (1, 0), (0, -1), (0, 1))):
+                c = self.find(p.level - 1, Ic + di, Jc + dj)
+                co["pid"][k].append(c.pid if c is not None else -1)
+                co["cj"][k].append(Jc + dj - c.J0 + 2 if c is not None else 0)
+                co["ci"][k].append(Ic + di - c.I0 + 2 if c is not None else 0)
+        ct = {sp: tuple(np.array(a, dtype=np.int64) for a in c[:4]) +
+              tuple(np.array(a, dtype=bool) for a in c[4:]) for sp, c in copies.items()}
+        cc = {"dj": np.array(co["dj"], dtype=np.int64), "di": np.array(co["di"], dtype=np.int64),
+              "ox": np.array(co["ox"], dtype=np.float64), "oy": np.array(co["oy"], dtype=np.float64),
+              "pid": [np.array(a, dtype=np.int64) for a in co["pid"]],
+              "cj": [np.array(a, dtype=np.int64) for a in co["cj"]],
+              "ci": [np.array(a, dtype=np.int64) for a in co["ci"]]}
+        tabs[p.pid] = (ct, cc)
+        return tabs[p.pid]
+
+    def _gather(self, arrays, pid, j, i):
+        """values of arrays[pid][..., j, i] for every entry (pid >= 0; the
+        others stay 0)"""
+        lead = next(iter(arrays.values())).shape[:-2]
+        out = np.zeros(lead + pid.shape)
+        for u in np.unique(pid[pid >= 0]):
+            k = pid == u
+            out[..., k] = arrays[int(u)][..., j[k], i[k]]
+        return out
+
+    def _fill_ghost_bathymetry(self, p):
+        ct, cc = self._ghost_tables(p)
+        for sp, (dj, di, sj, si, _, _) in ct.items():
+            p.b[dj, di] = self.patches[sp].b[sj, si]
+        if len(cc["dj"]):
+            bs = {c.pid: c.b for c in self.levels[p.level - 1]}
+            p.b[cc["dj"], cc["di"]] = self._gather(bs, cc["pid"][0], cc["cj"][0], cc["ci"][0])
 
     # ---------------------------------------------------------------- ghosts
-    def _coarse_values(self, lev, I, J, theta):
-        """time-interpolated (eta', hu, ..., h p_b) of level-lev cell (I, J),
-        whether it is dry at either time, and its b; None if no patch"""
-        c = self.find(lev, I, J)
-        if c is None:
-            return None
-        ci, cj = I - c.I0 + 2, J - c.J0 + 2
-        qo = self.old[c.pid][:, cj, ci]
-        qn = c.q[:, cj, ci]
-        b = c.b[cj, ci]
-        eta0 = self.P.eta0
-        vo = qo.copy()
-        vn = qn.copy()
-        vo[0] = (qo[0] + b) - eta0
-        vn[0] = (qn[0] + b) - eta0
-        v = np.array([(1.0 - theta) * vo[m] + theta * vn[m] for m in range(7)])
-        dry = (not qo[0] > self.P.dry_tol) or (not qn[0] > self.P.dry_tol)
-        return v, dry, b, c, ci, cj
-
     def fill_ghosts(self, lev, theta):
+        """every ghost cell of the level's patches by the rules above (the
+        same arithmetic per cell, evaluated over arrays of ghost cells)"""
+        eta0, dtol = self.P.eta0, self.P.dry_tol
+        coarse = self.levels[lev - 1] if lev > 0 else []
+        old = {c.pid: self.old[c.pid] for c in coarse}
+        new = {c.pid: c.q for c in coarse}
+        bath = {c.pid: c.b for c in coarse}
+        phi = {c.pid: c.phi for c in coarse}
+        brk = {c.pid: c.brk for c in coarse}
         for p in self.levels[lev]:
-            for i, j in self._ghost_cells(p):
-                src = self._source_of(p, i, j)
-                d = (slice(None), j + 2, i + 2)
-                if src[0] == "copy":
-                    _, s, si, sj, fx, fy = src
-                    p.q[d] = s.q[:, sj + 2, si + 2]
-                    if fx:
-                        p.q[1, j + 2, i + 2] = -p.q[1, j + 2, i + 2]
-                    if fy:
-                        p.q[2, j + 2, i + 2] = -p.q[2, j + 2, i + 2]
-                    p.phi[j + 2, i + 2] = s.phi[sj + 2, si + 2]
-                    p.brk[j + 2, i + 2] = s.brk[sj + 2, si + 2]
-                    continue
-                _, Ic, Jc, ox, oy = src
-                cen = self._coarse_values(lev - 1, Ic, Jc, theta)
-                v, dry, bc_, c, ci, cj = cen
-                nb = [self._coarse_values(lev - 1, Ic + di, Jc + dj, theta)
-                      for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1))]
-                any_dry = dry or any(n is not None and n[1] for n in nb)
-                out = np.empty(7)
-                for m in range(7):
-                    sx = sy = 0.0
-                    if not any_dry:
-                        if nb[0] is not None and nb[1] is not None:
-                            sx = _minmod(nb[1][0][m] - v[m], v[m] - nb[0][0][m])
-                        if nb[2] is not None and nb[3] is not None:
-                            sy = _minmod(nb[3][0][m] - v[m], v[m] - nb[2][0][m])
-                    out[m] = (v[m] + ox * sx) + oy * sy
-                bg = p.b[j + 2, i + 2]
-                h = (out[0] + self.P.eta0) - bg
-                out[0] = h if h > 0.0 else 0.0
-                p.q[d] = out
-                p.phi[j + 2, i + 2] = c.phi[cj, ci]
-                p.brk[j + 2, i + 2] = c.brk[cj, ci]
+            ct, cc = self._ghost_tables(p)
+            for sp, (dj, di, sj, si, fx, fy) in ct.items():
+                s = self.patches[sp]
+                p.q[:, dj, di] = s.q[:, sj, si]
+                p.q[1, dj[fx], di[fx]] = -p.q[1, dj[fx], di[fx]]
+                p.q[2, dj[fy], di[fy]] = -p.q[2, dj[fy], di[fy]]
+                p.phi[dj, di] = s.phi[sj, si]
+                p.brk[dj, di] = s.brk[sj, si]
+            if not len(cc["dj"]):
+                continue
+            vals, dry, have = [], [], []
+            for k in range(5):
+                pid, cj, ci = cc["pid"][k], cc["cj"][k], cc["ci"][k]
+                qo, qn = self._gather(old, pid, cj, ci), self._gather(new, pid, cj, ci)
+                b = self._gather(bath, pid, cj, ci)
+                vo, vn = qo.copy(), qn.copy()
+                vo[0] = (qo[0] + b) - eta0
+                vn[0] = (qn[0] + b) - eta0
+                vals.append((1.0 - theta) * vo + theta * vn)
+                dry.append(~(qo[0] > dtol) | ~(qn[0] > dtol))
+                have.append(pid >= 0)
+            v = vals[0]
+            any_dry = dry[0].copy()
+            for k in range(1, 5):
+                any_dry |= have[k] & dry[k]
+            sx = np.where(~any_dry & have[1] & have[2], _minmod_arrays(vals[2] - v, v - vals[1]), 0.0)
+            sy = np.where(~any_dry & have[3] & have[4], _minmod_arrays(vals[4] - v, v - vals[3]), 0.0)
+            out = (v + cc["ox"] * sx) + cc["oy"] * sy
+            bg = p.b[cc["dj"], cc["di"]]
+            h = (out[0] + eta0) - bg
+            out[0] = np.where(h > 0.0, h, 0.0)
+            p.q[:, cc["dj"], cc["di"]] = out
+            p.phi[cc["dj"], cc["di"]] = self._gather(phi, cc["pid"][0], cc["cj"][0], cc["ci"][0])
+            p.brk[cc["dj"], cc["di"]] = self._gather(brk, cc["pid"][0], cc["cj"][0], cc["ci"][0])
 
     # ------------------------------------------------------------ stepping
-    def _pre_source(self, q, b, phi, brk, tau):
-        """the cell state after the first source half step (Strang) or the
-        clearing of a dry/SWE cell's auxiliaries (Lie)"""
-        q = np.array(q, dtype=np.float64)
-        swe = (not phi) or brk
-        wet = q[0] > self.P.dry_tol
-        if self.P.splitting:
-            if wet and not swe:
-                q = O.source_cell(q, self._c2(b, phi, brk), tau, getattr(self.P, "model", 0))
-            else:
-                q[3:] = 0.0
-        elif (not wet) or swe:
-            q[3:] = 0.0
-        return q
-
     def _flux_records(self, f):
         """boundary edges of fine patch f whose outside cell comes from the
         coarse level: (entry, direction, low_side, ghost (i, j))"""
@@ -353,30 +371,80 @@ class AmrOracle:
             out.append((2 * f.ny + f.nx + i, 1, False, (i, f.ny)))
         return [r for r in out if self._source_of(f, *r[3])[0] == "coarse"]
 
+    def _flux_table(self, f):
+        """the flux records of fine patch f as arrays (static): entry,
+        direction, low side, the ghost's frame indices, and the coarse cell
+        C's patch and frame indices"""
+        tabs = self.__dict__.setdefault("_ftab", {})
+        if f.pid not in tabs:
+            rows = []
+            for e, direction, low, (gi, gj) in self._flux_records(f):
+                _, Ic, Jc, _, _ = self._source_of(f, gi, gj)
+                c = self.find(f.level - 1, Ic, Jc)
+                rows.append((e, direction, int(low), gj + 2, gi + 2, c.pid, Jc - c.J0 + 2,
+                             Ic - c.I0 + 2))
+            tabs[f.pid] = np.array(rows, dtype=np.int64).reshape(-1, 8)
+        return tabs[f.pid]
+
+    def _pre_source_cells(self, q, b, phi, brk, tau):
+        """_pre_source over cells: q[7][n], b, phi, brk [n]"""
+        q = np.array(q, dtype=np.float64)
+        swe = (phi == 0) | (brk != 0)
+        wet = q[0] > self.P.dry_tol
+        if self.P.splitting:
+            src = wet & ~swe
+            if src.any():
+                q[:, src] = O.source_cells(q[:, src].T, self._c2_cells(b[src], phi[src], brk[src]),
+                                           tau, getattr(self.P, "model", 0)).T
+            q[3:, ~src] = 0.0
+        else:
+            q[3:, ~wet | swe] = 0.0
+        return q
+
+    def _c2_cells(self, b, phi, brk):
+        """_c2 over cells"""
+        swe = (phi == 0) | (brk != 0)
+        if getattr(self.P, "c2", 0.0) > 0.0:
+            return np.where(swe, 0.0, self.P.c2)
+        H = self.P.eta0 - b
+        H = np.where(H > 0.0, H, 0.0)
+        return np.where(swe, 0.0, self.P.alpha * self.P.alpha * self.P.g * H)
+
     def _accumulate_fluxes(self, lev, dt_f, dt_c):
         """after a level-lev substep: R += K + (+/-) dflux(C*, g*)"""
         for f in self.levels[lev]:
+            T = self._flux_table(f)
+            if not len(T):
+                continue
             K = f.g.boundary_flux()
-            for e, direction, low, (gi, gj) in self._flux_records(f):
-                src = self._source_of(f, gi, gj)
-                _, Ic, Jc, _, _ = src
-                c = self.find(lev - 1, Ic, Jc)
-                ci, cj = Ic - c.I0 + 2, Jc - c.J0 + 2
-                qC = self._pre_source(self.old[c.pid][:, cj, ci], c.b[cj, ci],
-                                      self.old_phi[c.pid][cj, ci], self.old_brk[c.pid][cj, ci],
-                                      0.5 * dt_c)
-                c2C = self._c2(c.b[cj, ci], self.old_phi[c.pid][cj, ci],
-                               self.old_brk[c.pid][cj, ci])
-                qg_raw = self.old[f.pid][:, gj + 2, gi + 2]
-                bg = f.b[gj + 2, gi + 2]
-                pg, kg = self.old_phi[f.pid][gj + 2, gi + 2], self.old_brk[f.pid][gj + 2, gi + 2]
-                qg = self._pre_source(qg_raw, bg, pg, kg, 0.5 * dt_f)
-                c2g = self._c2(bg, pg, kg)
-                if low:
-                    D = O.edge_dflux(self.P, direction, qC, qg, c.b[cj, ci], bg, c2C, c2g)
-                else:
-                    D = -O.edge_dflux(self.P, direction, qg, qC, bg, c.b[cj, ci], c2g, c2C)
-                self.R[f.pid][e] = self.R[f.pid][e] + (K[e] + D)
+            e, direction, low = T[:, 0], T[:, 1], T[:, 2] == 1
+            gj, gi = T[:, 3], T[:, 4]
+            cp, cj, ci = T[:, 5], T[:, 6], T[:, 7]
+            qo = self._gather(self.old, cp, cj, ci)
+            bC = self._gather({c.pid: c.b for c in self.levels[lev - 1]}, cp, cj, ci)
+            phC = self._gather(self.old_phi, cp, cj, ci)
+            bkC = self._gather(self.old_brk, cp, cj, ci)
+            qC = self._pre_source_cells(qo, bC, phC, bkC, 0.5 * dt_c)
+            c2C = self._c2_cells(bC, phC, bkC)
+            qg_raw = self.old[f.pid][:, gj, gi]
+            bg = f.b[gj, gi]
+            pg, kg = self.old_phi[f.pid][gj, gi], self.old_brk[f.pid][gj, gi]
+            qg = self._pre_source_cells(qg_raw, bg, pg, kg, 0.5 * dt_f)
+            c2g = self._c2_cells(bg, pg, kg)
+            D = np.zeros((len(T), 7))
+            for d in (0, 1):
+                for lo in (True, False):
+                    k = (direction == d) & (low == lo)
+                    if not k.any():
+                        continue
+                    if lo:
+                        D[k] = O.edge_dflux_n(self.P, d, qC[:, k].T, qg[:, k].T, bC[k], bg[k],
+                                              c2C[k], c2g[k])
+                    else:
+                        D[k] = -O.edge_dflux_n(self.P, d, qg[:, k].T, qC[:, k].T, bg[k], bC[k],
+                                               c2g[k], c2C[k])
+            R = self.R[f.pid]
+            R[e] = R[e] + (K[e] + D)
 
     def _reflux(self, lev, dt_c):
         for p in self.levels[lev]:
@@ -418,26 +486,28 @@ class AmrOracle:
                     p.q[:, j + 2, i + 2] = v
 
     def _average_down_patch(self, f, bath_only=False):
+        """covered coarse cells take the mean of their 4 x 4 fine cells: the
+        16 values summed in row order (a fine row, then the next), times
+        1/16; the bathymetry alone with bath_only"""
         lev = f.level
-        for jj in range(f.ny // RATIO):
-            for ii in range(f.nx // RATIO):
-                Ic, Jc = f.I0 // RATIO + ii, f.J0 // RATIO + jj
-                c = self.find(lev - 1, Ic, Jc)
-                ci, cj = Ic - c.I0 + 2, Jc - c.J0 + 2
-                fi, fj = RATIO * ii + 2, RATIO * jj + 2
-                if bath_only:
-                    s = 0.0
-                    for a in range(RATIO):
-                        for bb in range(RATIO):
-                            s += f.b[fj + a, fi + bb]
-                    c.b[cj, ci] = s * 0.0625
-                    continue
-                for m in range(7):
-                    s = 0.0
-                    for a in range(RATIO):
-                        for bb in range(RATIO):
-                            s += f.q[m, fj + a, fi + bb]
-                    c.q[m, cj, ci] = s * 0.0625
+        nbx, nby = f.nx // RATIO, f.ny // RATIO
+        src = f.b[None] if bath_only else f.q
+        s = np.zeros((src.shape[0], nby, nbx))
+        for a in range(RATIO):
+            for bb in range(RATIO):
+                s = s + src[:, 2 + a:2 + a + RATIO * nby:RATIO, 2 + bb:2 + bb + RATIO * nbx:RATIO]
+        mean = s * 0.0625
+        Ic0, Jc0 = f.I0 // RATIO, f.J0 // RATIO
+        for c in self.levels[lev - 1]:
+            i0, i1 = max(Ic0, c.I0), min(Ic0 + nbx, c.I0 + c.nx)
+            j0, j1 = max(Jc0, c.J0), min(Jc0 + nby, c.J0 + c.ny)
+            if i0 >= i1 or j0 >= j1:
+                continue
+            blk = mean[:, j0 - Jc0:j1 - Jc0, i0 - Ic0:i1 - Ic0]
+            if bath_only:
+                c.b[j0 - c.J0 + 2:j1 - c.J0 + 2, i0 - c.I0 + 2:i1 - c.I0 + 2] = blk[0]
+            else:
+                c.q[:, j0 - c.J0 + 2:j1 - c.J0 + 2, i0 - c.I0 + 2:i1 - c.I0 + 2] = blk
 
     def _step_level(self, lev, dt, theta):
         self.fill_ghosts(lev, theta)

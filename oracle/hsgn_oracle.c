@@ -1484,6 +1484,28 @@ int orc_edge_dflux(const orc_params *p, int dir, const double *qL, const double 
     return rc;
 }
 
+/* the same two entry points over n cells / edges (arrays of n 7-vectors) */
+void orc_source_cells(int n, double *q, const double *c2, double tau, int model)
+{
+    for (int k = 0; k < n; k++) {
+        if (model == 1) orc_source_cell_mb(q + 7 * (size_t)k, c2[k], tau);
+        else orc_source_cell(q + 7 * (size_t)k, c2[k], tau);
+    }
+}
+
+int orc_edge_dflux_n(const orc_params *p, int dir, int n, const double *qL, const double *qR,
+                     const double *bL, const double *bR, const double *c2L, const double *c2R,
+                     double *df)
+{
+    int rc = ORC_OK;
+    for (int k = 0; k < n; k++) {
+        int r = orc_edge_dflux(p, dir, qL + 7 * (size_t)k, qR + 7 * (size_t)k, bL[k], bR[k],
+                               c2L[k], c2R[k], df + 7 * (size_t)k);
+        if (r != ORC_OK) rc = r;
+    }
+    return rc;
+}
+
 /* limiter function phi(theta) of Sec. 4 (0 first order, 1 minmod, 2 MC,
  * 3 unlimited) */
 double orc_limiter_phi(int lim, double theta) { return (double)limiter_phi(lim, theta); }

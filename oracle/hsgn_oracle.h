@@ -149,6 +149,12 @@ int orc_set_radial(orc_grid *g, int on);
 /* boundary-edge fluxes of the last step relative to the outside cell,
  * K[2 ny + 2 nx][7] (left rows, right rows, bottom columns, top columns) */
 int orc_boundary_flux(const orc_grid *g, double *K);
+/* orc_source_cell(_mb) and orc_edge_dflux over n cells / edges, 7-vectors
+ * in a row (model 1: mbHSGN) */
+void orc_source_cells(int n, double *q, const double *c2, double tau, int model);
+int orc_edge_dflux_n(const orc_params *p, int dir, int n, const double *qL, const double *qR,
+                     const double *bL, const double *bR, const double *c2L, const double *c2R,
+                     double *df);
 /* limiter function phi(theta): lim 0 first order, 1 minmod, 2 MC, 3 none */
 double orc_limiter_phi(int lim, double theta);
 /* eta' at a point by the gauge rule (bilinear over the 4 nearest centres) */

@@ -118,6 +118,9 @@ def _bind(L):
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, dp]
     L.orc_set_radial.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_source_cells.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int]
+    L.orc_edge_dflux_n.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, ctypes.c_int, dp, dp,
+                                   dp, dp, dp, dp, dp]
     L.orc_limiter_phi.restype = ctypes.c_double
     L.orc_limiter_phi.argtypes = [ctypes.c_int, ctypes.c_double]
     L.orc_gauge_eta.restype = ctypes.c_double
@@ -340,3 +343,22 @@ def source_cell(q, c2, tau, model=0):
 def limiter_phi(lim, theta):
     """the oracle's limiter function phi(theta)"""
     return lib().orc_limiter_phi(int(lim), float(theta))
+
+
+def source_cells(q, c2, tau, model=0):
+    """source_cell over cells: q[n][7] (a copy is returned), c2[n]"""
+    q = np.array(q, dtype=np.float64, order="C")
+    c2 = np.ascontiguousarray(c2, dtype=np.float64)
+    lib().orc_source_cells(int(q.shape[0]), _dp(q), _dp(c2), float(tau), int(model))
+    return q
+
+
+def edge_dflux_n(params, direction, qL, qR, bL, bR, c2L, c2R):
+    """edge_dflux over edges: qL, qR [n][7], the rest [n]; returns [n][7]"""
+    p = _params(params)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (qL, qR, bL, bR, c2L, c2R)]
+    df = np.zeros((a[0].shape[0], 7))
+    rc = lib().orc_edge_dflux_n(ctypes.byref(p), int(direction), int(a[0].shape[0]),
+                                *[_dp(x) for x in a], _dp(df))
+    _check(rc, "edge_dflux_n")
+    return df

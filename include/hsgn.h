@@ -189,15 +189,23 @@ int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rat
  * previous geometry). */
 int hsgn_set_mapping(hsgn_ctx *ctx, int patch, const double *xn, const double *yn);
 
-/* State q[7][ny][nx] (float64) of a patch, copied in or out. */
+/* State q[7][ny][nx] (float64) of a patch, copied in or out: the conserved
+ * variables of eq. HSGN (Sec. 3) in the order of the eigenstructure of
+ * Appendix C (h, hu, hv, hw, h sigma, hp, h p_b).  Mixed precision stores
+ * eta' and converts on the way in and out.  A device pointer is copied with a synchronous copy.  Errors: EINVAL
+ * (bad patch, null pointer, before finalize). */
 int hsgn_set_state(hsgn_ctx *c, int patch, const double *q, int on_device);
 int hsgn_get_state(hsgn_ctx *c, int patch, double *q, int on_device);
 
-/* Mask byte per cell: bit0 = phi_T, bit1 = breaking latch. */
+/* Mask byte per cell: bit0 = phi_T (eq. transition: dispersive where the
+ * still-water depth exceeds h_star), bit1 = the breaking latch of Sec. 3.3
+ * (set once kappa h is exceeded; the cell then stays SWE).  hsgn_set_mask
+ * writes the bytes as given into both step buffers. */
 int hsgn_get_mask(hsgn_ctx *c, int patch, uint8_t *m, int on_device);
 int hsgn_set_mask(hsgn_ctx *c, int patch, const uint8_t *m, int on_device);
 
-/* Gauges of a scenario at points xy[n][2] (host).  Each accepted step
+/* Gauges of a scenario at points xy[n][2] (host), the surface-elevation
+ * records of the validation cases of Sec. 6.  Each accepted step
  * records eta' = h + b - eta0 (0 in dry cells) interpolated bilinearly
  * between the four nearest cell centres of the finest patch containing the
  * point (patch sets: one record per level-0 step).  Errors: ERANGE. */
@@ -221,14 +229,24 @@ int hsgn_read_gauges(hsgn_ctx *c, int scenario, double *t, double *eta,
 int hsgn_advance(hsgn_ctx *c, double dt, int n_steps);
 
 /* Diagnostics of a scenario (patch sets: mass of level 0, counts and cell
- * updates over all levels, clipped mass including refluxing). */
+ * updates over all levels, clipped mass including refluxing).  The mass is
+ * the quantity the conservative update of Sec. 4 keeps up to clipping; the
+ * Courant numbers are those of the time-step control of Sec. 4.  Errors:
+ * EINVAL. */
 int hsgn_diagnostics(hsgn_ctx *c, int scenario, hsgn_diag *d);
+/* Clock of a scenario: time t, the next step dt_next (the fixed step, or
+ * the adaptive controller's choice dt cfl / Courant of Sec. 4) and the
+ * accepted steps.  hsgn_set_clock sets them and clears the scenario's error
+ * state (patch sets: given for level 0; level l takes dt_next / 4^l and
+ * 4^l steps).  Any output may be NULL.  Errors: EINVAL. */
 int hsgn_get_clock(hsgn_ctx *c, int scenario, double *t, double *dt_next,
                    long long *steps);
 int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next,
                    long long steps);
 
-/* Tile-height autotuning: for every refinement level, times `trials`
+/* The next three calls are controls of this implementation; no passage of
+ * the paper defines them.
+ * Tile-height autotuning: for every refinement level, times `trials`
  * step-kernel launches (after one warm-up) for each candidate height in
  * {8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64} on the current state, and keeps
  * the fastest.  The state does not advance (the launches write only the
@@ -294,9 +312,9 @@ typedef struct hsgn_regrid_params {
 } hsgn_regrid_params;
 int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_new);
 
-/* The patches of a context: their number, and per patch its scenario,
- * refinement level, size, lower-left corner and spacing (any output may be
- * NULL).  Errors: EINVAL. */
+/* The patches of a context (the block-structured patches of Sec. 4): their
+ * number, and per patch its scenario, refinement level, size, lower-left
+ * corner and spacing (any output may be NULL).  Errors: EINVAL. */
 int hsgn_num_patches(hsgn_ctx *c, int *n);
 int hsgn_patch_info(hsgn_ctx *c, int patch, int *scenario, int *level, int *nx, int *ny,
                     double *x0, double *y0, double *dx, double *dy);
@@ -330,6 +348,9 @@ int hsgn_advance_static(const hsgn_params *p, void *hip_stream, int nx, int ny, 
                         double dy, const int bc[4], const double *b, double *q, double dt,
                         int n_steps, long long *steps_done);
 
+/* Housekeeping, no compute: free a context and its device memory after
+ * its stream has drained (NULL: EINVAL); the text of an error code; the message of the last error on a
+ * context (valid until its next call). */
 int hsgn_destroy(hsgn_ctx *c);
 const char *hsgn_strerror(int code);
 const char *hsgn_last_error(hsgn_ctx *c);

@@ -608,15 +608,46 @@ HSGN_HD T limiter_phi(int lim, T th)
     }
 }
 
+// sum_f c_f Z_f over the seven families of an edge (DIR 0 or 1: the
+// families' nonzero components only; the two acoustic waves are full
+// vectors, the u-speed family has h, normal momentum and hp components, the
+// four contact waves one component each)
+template <int DIR, class T>
+HSGN_HD void family_sum(const Waves<T> &W, const T *c, T *out)
+{
+    if constexpr (DIR == 2) {
+        HSGN_UNROLL
+        for (int m = 0; m < 7; m++) out[m] = (T)0;
+        HSGN_UNROLL
+        for (int f = 0; f < 7; f++) {
+            T z[7];
+            wave_vec<DIR>(W, f, z);
+            HSGN_UNROLL
+            for (int m = 0; m < 7; m++) out[m] += c[f] * z[m];
+        }
+    } else {
+        const int IN = DIR == 0 ? IHU : IHV;
+        const int IT = DIR == 0 ? IHV : IHU;
+        HSGN_UNROLL
+        for (int m = 0; m < 7; m++) out[m] = c[0] * W.z0[m] + c[6] * W.z6[m];
+        out[IH] += c[1] * W.zm[0];
+        out[IN] += c[1] * W.zm[1];
+        out[IHP] += c[1] * W.zm[2];
+        out[IHS] += c[2] * W.bs;
+        out[IHW] += c[3] * W.bw;
+        out[IT] += c[4] * W.bt;
+        out[IHPB] += c[5] * W.bpb;
+    }
+}
+
 // limited second-order correction of an edge from its own waves and the dot
-// products with the left (dl) and right (dr) neighbouring edges
+// products with the left (dl) and right (dr) neighbouring edges; an edge
+// that is not regular (wall, dry) has none
 template <int DIR, class T>
 HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T *dr, T *F)
 {
-    HSGN_UNROLL
-    for (int m = 0; m < 7; m++) F[m] = (T)0;
-    if (lim == 0 || W.kind != KIND_REGULAR) return;
-    T self[7];
+    const bool on = lim != 0 && W.kind == KIND_REGULAR;
+    T self[7], c[7];
     family_dots<DIR>(W, W, self);
     HSGN_UNROLL
     for (int f = 0; f < 7; f++) {
@@ -624,16 +655,13 @@ HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T
         T s = wave_speed(W, f);
         // waves this small contribute nothing at the working precision;
         // skipping them also keeps the reciprocal of zz finite
-        bool live = zz > tiny_norm<T>();
+        bool live = on && zz > tiny_norm<T>();
         T th = live ? quot(s > (T)0 ? dl[f] : dr[f], zz, frcp(zz)) : (T)0;
         T ph = live ? limiter_phi(lim, th) : (T)0;
         T sg = s > (T)0 ? (T)1 : (s < (T)0 ? (T)-1 : (T)0);
-        T c = (T)0.5 * sg * ((T)1 - dtdx * fabs(s)) * ph;
-        T z[7];
-        wave_vec<DIR>(W, f, z);
-        HSGN_UNROLL
-        for (int m = 0; m < 7; m++) F[m] += c * z[m];
+        c[f] = (T)0.5 * sg * ((T)1 - dtdx * fabs(s)) * ph;
     }
+    family_sum<DIR>(W, c, F);
 }
 
 // left- and right-going fluctuations; a wave of speed exactly zero is split
@@ -641,21 +669,15 @@ HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T
 template <int DIR, class T>
 HSGN_HD void fluctuations(const Waves<T> &W, T *am, T *ap)
 {
-    HSGN_UNROLL
-    for (int m = 0; m < 7; m++) { am[m] = (T)0; ap[m] = (T)0; }
+    T wm[7], wp[7];
     HSGN_UNROLL
     for (int f = 0; f < 7; f++) {
         T s = wave_speed(W, f);
-        T wm = s < (T)0 ? (T)1 : (s > (T)0 ? (T)0 : (T)0.5);
-        T wp = s > (T)0 ? (T)1 : (s < (T)0 ? (T)0 : (T)0.5);
-        T z[7];
-        wave_vec<DIR>(W, f, z);
-        HSGN_UNROLL
-        for (int m = 0; m < 7; m++) {
-            am[m] += wm * z[m];
-            ap[m] += wp * z[m];
-        }
+        wm[f] = s < (T)0 ? (T)1 : (s > (T)0 ? (T)0 : (T)0.5);
+        wp[f] = s > (T)0 ? (T)1 : (s < (T)0 ? (T)0 : (T)0.5);
     }
+    family_sum<DIR>(W, wm, am);
+    family_sum<DIR>(W, wp, ap);
     const T km = W.kind == KIND_WALL_L ? (T)0 : (T)1;
     const T kp = W.kind == KIND_WALL_R ? (T)0 : (T)1;
     HSGN_UNROLL

@@ -167,6 +167,72 @@ HSGN_HD void eig_load(const T *ring, int slot, int lane, Eig<T> &e)
     e.wet = p[11 * 64] != (T)0; e.ce2 = p[12 * 64];
 }
 
+// values parked in a per-wavefront LDS area between rows, two per lane and
+// access: entry j of lane l at pair j * 64 + l
+template <class T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+constexpr int PARK_WAVES = 24, PARK_SIDE = 14;
+
+template <class T>
+HSGN_HD void park_waves(T *buf, int lane, const Waves<T> &w)
+{
+    const T v[PARK_WAVES] = {w.z0[0], w.z0[1], w.z0[2], w.z0[3], w.z0[4], w.z0[5], w.z0[6],
+                             w.z6[0], w.z6[1], w.z6[2], w.z6[3], w.z6[4], w.z6[5], w.z6[6],
+                             w.zm[0], w.zm[1], w.zm[2], w.bs, w.bw, w.bt, w.bpb,
+                             w.smin, w.smax, w.uh};
+    Pair<T> *p = reinterpret_cast<Pair<T> *>(buf);
+    HSGN_UNROLL
+    for (int j = 0; j < PARK_WAVES / 2; j++) p[j * 64 + lane] = Pair<T>{v[2 * j], v[2 * j + 1]};
+}
+
+template <class T>
+HSGN_HD void unpark_waves(const T *buf, int lane, int kind, Waves<T> &w)
+{
+    T v[PARK_WAVES];
+    const Pair<T> *p = reinterpret_cast<const Pair<T> *>(buf);
+    HSGN_UNROLL
+    for (int j = 0; j < PARK_WAVES / 2; j++) {
+        const Pair<T> x = p[j * 64 + lane];
+        v[2 * j] = x.a;
+        v[2 * j + 1] = x.b;
+    }
+    HSGN_UNROLL
+    for (int m = 0; m < 7; m++) { w.z0[m] = v[m]; w.z6[m] = v[7 + m]; }
+    w.zm[0] = v[14]; w.zm[1] = v[15]; w.zm[2] = v[16];
+    w.bs = v[17]; w.bw = v[18]; w.bt = v[19]; w.bpb = v[20];
+    w.smin = v[21]; w.smax = v[22]; w.uh = v[23];
+    w.kind = kind;
+}
+
+template <class T>
+HSGN_HD void park_side(T *buf, int lane, const Side<T> &d)
+{
+    const T v[PARK_SIDE] = {d.h, d.sq, d.ce, d.hun, d.un, d.ut, d.w,
+                            d.s, d.p, d.pb, d.hp, d.b, d.c2, d.eta};
+    Pair<T> *p = reinterpret_cast<Pair<T> *>(buf);
+    HSGN_UNROLL
+    for (int j = 0; j < PARK_SIDE / 2; j++) p[j * 64 + lane] = Pair<T>{v[2 * j], v[2 * j + 1]};
+}
+
+template <class T>
+HSGN_HD void unpark_side(const T *buf, int lane, int wet, int hyp, Side<T> &d)
+{
+    T v[PARK_SIDE];
+    const Pair<T> *p = reinterpret_cast<const Pair<T> *>(buf);
+    HSGN_UNROLL
+    for (int j = 0; j < PARK_SIDE / 2; j++) {
+        const Pair<T> x = p[j * 64 + lane];
+        v[2 * j] = x.a;
+        v[2 * j + 1] = x.b;
+    }
+    d.h = v[0]; d.sq = v[1]; d.ce = v[2]; d.hun = v[3]; d.un = v[4]; d.ut = v[5]; d.w = v[6];
+    d.s = v[7]; d.p = v[8]; d.pb = v[9]; d.hp = v[10]; d.b = v[11]; d.c2 = v[12]; d.eta = v[13];
+    d.wet = wet;
+    d.hyp = hyp;
+}
+
 template <bool MAP = false, class L, class T>
 HSGN_HD void shfl_waves_up(L &ln, const Waves<T> &w, Waves<T> &o)
 {
@@ -350,7 +416,9 @@ HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Sid
 // Lanes policy L provides: lane(), up(x)/dn(x) (value of lane-1 / lane+1)
 // for float, double and int (upi/dni), any(pred) over the wavefront, ring()
 // (the wavefront's LDS ring of 3 * EIG_FIELDS * 64 compute values, followed
-// in mixed precision by 3 * 7 * 64 more for the rows' base states), and
+// in mixed precision by 3 * 7 * 64 more for the rows' base states, and in
+// FP64 on Cartesian grids by (PARK_WAVES + PARK_SIDE) * 64 for the values
+// parked between rows), and
 // finish(args, wave, scenario, rx, ry, clip) which reduces over the
 // wavefront and publishes the results.
 //
@@ -408,6 +476,12 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 
     T *ring = ln.ring();
     T *base = ring + 3 * (EIG_FIELDS + (MAP ? 5 : 0)) * 64;   // mixed precision: 3 rows x 7 x 64
+    // FP64 on Cartesian grids: the waves of the y-edge below and the lower
+    // side of the next y-edge, each used once per row, wait in LDS between
+    // rows rather than in registers the row's solves need
+    constexpr bool PARK = !MIXED && !MAP;
+    T *park_w = ring + 3 * EIG_FIELDS * 64, *park_s = park_w + PARK_WAVES * 64;
+    int yprev_kind = 0, yside_wet = 0, yside_hyp = 0;
     Side<T> yside_prev;          // lower cell of the next y-edge (y normal frame)
     int phi_c = 0, brk_c = 0;
     // sliding windows over rows k-2 (index 0), k-1 (1) and k (2), shifted
@@ -551,6 +625,10 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 mapped_side(P, c.q, c.b, c.c2, c.eta, met[4], met[5], met[5], (T)0 - met[4], ysr);
                 ok = edge_solve<0, MIXED && FB>(ln, P, ysl, ysr, yw, ye);
                 set_frame(yw, ye, met[4], met[5], met[5], (T)0 - met[4], met[6]);
+            } else if constexpr (PARK) {
+                Side<T> ysl;
+                unpark_side(park_s, lane, yside_wet, yside_hyp, ysl);
+                ok = edge_solve<1, MIXED && FB>(ln, P, ysl, yside, yw, ye);
             } else {
                 ok = edge_solve<1, MIXED && FB>(ln, P, yside_prev, yside, yw, ye);
             }
@@ -560,6 +638,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 ry = tmax(ry, tmax((T)fabs(yw.smin) / kk, tmax((T)fabs(yw.smax) / kk, (T)fabs(yw.uh) / kk)));
             }
             if (k >= r0) {
+                if constexpr (PARK) unpark_waves(park_w, lane, yprev_kind, yprev);
                 T dk[7];
                 family_dots<DY>(yw, yprev, dk);
                 if (k - 1 >= r0 && k - 1 <= r0 + th) {
@@ -675,7 +754,12 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 HSGN_UNROLL
                 for (int m = 0; m < 7; m++) ef[e0 + m] = (double)Gt[m];
             }
-            yprev = yw;
+            if constexpr (PARK) {
+                park_waves(park_w, lane, yw);
+                yprev_kind = yw.kind;
+            } else {
+                yprev = yw;
+            }
         }
 
         // ---- row k-2 complete: second source half step and fix-ups ----
@@ -796,7 +880,13 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         fl_w[0] = fl_w[1]; fl_w[1] = fl_w[2];
         brk_w[0] = brk_w[1]; brk_w[1] = brk_w[2];
         b_w[0] = b_w[1]; b_w[1] = b_w[2];
-        yside_prev = yside;
+        if constexpr (PARK) {
+            park_side(park_s, lane, yside);
+            yside_wet = yside.wet;
+            yside_hyp = yside.hyp;
+        } else {
+            yside_prev = yside;
+        }
     }
     ln.finish(A, wid, pi.scen, (double)rx, (double)ry, clip);
 }

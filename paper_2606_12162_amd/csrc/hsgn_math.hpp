@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
@@ -91,8 +92,15 @@ struct Eig {
     T fnx, fny, ftx, fty, gm;   // mapped edges only: frame and length ratio
 };
 
+// larger and smaller of two values, one instruction each on the device for
+// float and double.  A NaN operand never decides anything the step keeps (a
+// NaN state is reported, not stepped); a zero may come out with either sign.
 template <class T>
 HSGN_HD T tmax(T a, T b) { return a > b ? a : b; }
+template <class T>
+HSGN_HD T tmin(T a, T b) { return a < b ? a : b; }
+HSGN_HD double tmax(double a, double b) { return fmax(a, b); }
+HSGN_HD float tmax(float a, float b) { return fmaxf(a, b); }
 
 // reciprocal used where one denominator serves several quotients, square
 // root and quotient.  FP64 on the device: the hardware reciprocal estimate
@@ -165,8 +173,8 @@ template <> HSGN_HD bool finite_val<double>(double x) { return fabs(x) <= 1e300;
 template <> HSGN_HD bool finite_val<float>(float x) { return fabsf(x) <= 3e38f; }
 
 HSGN_HD double frcp(double x) { return recip(x); }
-template <class T>
-HSGN_HD T tmin(T a, T b) { return a < b ? a : b; }
+HSGN_HD double tmin(double a, double b) { return fmin(a, b); }
+HSGN_HD float tmin(float a, float b) { return fminf(a, b); }
 
 HSGN_HD int map_index(int i, int n, int lo, int hi, int *flip)
 {
@@ -343,14 +351,13 @@ HSGN_HD void side_of(const Cell<T> &c, Side<T> &sd)
     sd.b = c.b;
     sd.c2 = c.c2;
     sd.eta = c.eta;
-    if (c.wet) {
-        sd.hun = c.q[IN];
-        sd.un = DIR == 0 ? c.u : c.v;
-        sd.ut = DIR == 0 ? c.v : c.u;
-        sd.w = c.w; sd.s = c.s; sd.p = c.p; sd.pb = c.pb; sd.hp = c.q[IHP];
-    } else {
-        sd.hun = sd.un = sd.ut = sd.w = sd.s = sd.p = sd.pb = sd.hp = (T)0;
-    }
+    // the primitives of a dry cell are zero already (derive); its momentum
+    // and hp count as zero too
+    sd.un = DIR == 0 ? c.u : c.v;
+    sd.ut = DIR == 0 ? c.v : c.u;
+    sd.w = c.w; sd.s = c.s; sd.p = c.p; sd.pb = c.pb;
+    sd.hun = c.wet ? c.q[IN] : (T)0;
+    sd.hp = c.wet ? c.q[IHP] : (T)0;
 }
 
 template <int DIR, class T>
@@ -451,9 +458,12 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     }
     T ids = recip(smax - smin);
 
-    // normal-frame waves, then scattered into the global frame
+    // normal-frame waves, then scattered into the global frame.  An edge
+    // with c^2 = 0 on both sides takes the SWE waves; FP32 solves never do:
+    // in mixed precision every edge with c^2 = 0 on a side is solved again
+    // in FP64, whose results replace the FP32 ones
     T n0[7], n6[7];
-    if (L.c2 == (T)0 && R.c2 == (T)0) {
+    if (!std::is_same<T, float>::value && L.c2 == (T)0 && R.c2 == (T)0) {
         // SWE edge: HLLE waves carrying the surface-elevation jump
         T dq0 = deta, dq1 = R.hun - L.hun;
         T z1h = smin * ((smax * dq0 - df[0]) * ids);
@@ -600,12 +610,13 @@ HSGN_HD void family_dots(const Waves<T> &A, const Waves<T> &B, T *d)
 template <class T>
 HSGN_HD T limiter_phi(int lim, T th)
 {
-    switch (lim) {
-    case 1: return tmax((T)0, tmin((T)1, th));
-    case 2: return tmax((T)0, tmin(tmin((T)0.5 * ((T)1 + th), (T)2), (T)2 * th));
-    case 3: return (T)1;
-    default: return (T)0;
-    }
+    // both limiters evaluated and the (wavefront-uniform) choice selected,
+    // without branches: 1 minmod max(0, min(1, th)), 2 MC
+    // max(0, min((1 + th) / 2, 2, 2 th)), 3 Lax-Wendroff 1, else none
+    const T mm = tmin((T)1, th);
+    const T mc = tmin(tmin((T)0.5 * ((T)1 + th), (T)2), (T)2 * th);
+    const T r = lim == 2 ? mc : (lim == 1 ? mm : (lim == 3 ? (T)1 : (T)0));
+    return tmax((T)0, r);
 }
 
 // sum_f c_f Z_f over the seven families of an edge (DIR 0 or 1: the

@@ -10,13 +10,15 @@ namespace hsgn {
 // whole-wavefront lane shifts through DPP (GFX9 wave_shr:1 / wave_shl:1):
 // lane i receives lane i-1 (up) or lane i+1 (down) as a VALU operand
 // modifier, without a trip through the LDS crossbar.  Lane 0 (up) and lane
-// 63 (down) keep their own value; they are halo lanes whose results are
-// never used.
+// 63 (down) have no source and receive zero (bound control), so a shift is
+// one instruction with no copy of the old value; they are halo lanes whose
+// results are never stored and are left out of the Courant maxima, the
+// clipped mass and the error flags.
 constexpr int DPP_WAVE_SHL1 = 0x130;
 constexpr int DPP_WAVE_SHR1 = 0x138;
 
-__device__ inline int dpp_up(int x) { return __builtin_amdgcn_update_dpp(x, x, DPP_WAVE_SHR1, 0xf, 0xf, false); }
-__device__ inline int dpp_dn(int x) { return __builtin_amdgcn_update_dpp(x, x, DPP_WAVE_SHL1, 0xf, 0xf, false); }
+__device__ inline int dpp_up(int x) { return __builtin_amdgcn_update_dpp(0, x, DPP_WAVE_SHR1, 0xf, 0xf, true); }
+__device__ inline int dpp_dn(int x) { return __builtin_amdgcn_update_dpp(0, x, DPP_WAVE_SHL1, 0xf, 0xf, true); }
 
 template <class T>
 struct GpuLanes {
@@ -75,7 +77,7 @@ template <class S, class T, bool MIXED, bool AMR, bool FB = true, bool SP = fals
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
 void march_kernel(MarchArgs<S> A)
 {
-    __shared__ T ring[3 * EIG_FIELDS * 64 + (MIXED ? 3 * 7 * 64 : 0)];
+    __shared__ T ring[3 * EIG_FIELDS * 64 + (MIXED ? 3 * 7 * 64 : (PARK_WAVES + PARK_SIDE) * 64)];
     GpuLanes<T> ln{ring};
     if (MIXED && FB) {
         const unsigned n = A.list ? A.lcnt[1] : (unsigned)A.nwork;

@@ -36,6 +36,11 @@ inline CF fabs(CF a) { return mk(std::fabs(a.v), a.z, a.c); }
 inline CF quot(CF a, CF b, CF) { return a / b; }
 inline CF front_root(CF g, CF h, CF, CF) { return sqrt(g * h); }
 inline CF frcp(CF x) { return CF(1.0) / x; }
+// the kernel's reciprocal, square root and quotient helpers, counted as
+// one division or square root each
+inline CF recip(CF x) { return CF(1.0) / x; }
+inline CF tsqrt(CF a) { return sqrt(a); }
+inline CF tdiv(CF a, CF b) { return a / b; }
 #include "hsgn_math.hpp"
 namespace hsgn {
 template <> inline CF tiny_norm<CF>() { return CF(1e-200); }

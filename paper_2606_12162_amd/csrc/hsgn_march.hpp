@@ -452,7 +452,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     const T dtdx = (T)(dtd / pi.dx), dtdy = (T)(dtd / pi.dy);
     const T tau_pre = (T)0.5 * dt;
     const T tau_post = P.splitting ? (T)0.5 * dt : dt;
-    const int lim = P.limiter;
+    const Limiter<T> lim = limiter_of<T>(P.limiter);
     const bool trans = P.transverse == 2;
 
     const int lane = ln.lane();

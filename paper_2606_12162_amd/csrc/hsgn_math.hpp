@@ -607,16 +607,30 @@ HSGN_HD void family_dots(const Waves<T> &A, const Waves<T> &B, T *d)
     }
 }
 
+// the limiters of the wave-propagation correction as one branch-free form
+//   phi(th) = max(e, min(a th, b, c th + d))
+// with per-launch coefficients: minmod max(0, min(1, th)) (a, b, c, d, e) =
+// (1, 1, 0, 1, 0); MC max(0, min((1 + th) / 2, 2, 2 th)) = (2, 2, 1/2, 1/2, 0)
+// (th / 2 + 1 / 2 rounds once, as (1 + th) / 2 does); Lax-Wendroff 1 =
+// (0, 0, 0, 0, 1); none 0 = all zero
 template <class T>
-HSGN_HD T limiter_phi(int lim, T th)
+struct Limiter {
+    T a, b, c, d, e;
+};
+
+template <class T>
+HSGN_HD Limiter<T> limiter_of(int lim)
 {
-    // both limiters evaluated and the (wavefront-uniform) choice selected,
-    // without branches: 1 minmod max(0, min(1, th)), 2 MC
-    // max(0, min((1 + th) / 2, 2, 2 th)), 3 Lax-Wendroff 1, else none
-    const T mm = tmin((T)1, th);
-    const T mc = tmin(tmin((T)0.5 * ((T)1 + th), (T)2), (T)2 * th);
-    const T r = lim == 2 ? mc : (lim == 1 ? mm : (lim == 3 ? (T)1 : (T)0));
-    return tmax((T)0, r);
+    if (lim == 1) return {(T)1, (T)1, (T)0, (T)1, (T)0};
+    if (lim == 2) return {(T)2, (T)2, (T)0.5, (T)0.5, (T)0};
+    if (lim == 3) return {(T)0, (T)0, (T)0, (T)0, (T)1};
+    return {(T)0, (T)0, (T)0, (T)0, (T)0};
+}
+
+template <class T>
+HSGN_HD T limiter_phi(const Limiter<T> &L, T th)
+{
+    return tmax(L.e, tmin(tmin(L.a * th, L.b), L.c * th + L.d));
 }
 
 // sum_f c_f Z_f over the seven families of an edge (DIR 0 or 1: the
@@ -655,9 +669,10 @@ HSGN_HD void family_sum(const Waves<T> &W, const T *c, T *out)
 // products with the left (dl) and right (dr) neighbouring edges; an edge
 // that is not regular (wall, dry) has none
 template <int DIR, class T>
-HSGN_HD void correction(int lim, T dtdx, const Waves<T> &W, const T *dl, const T *dr, T *F)
+HSGN_HD void correction(const Limiter<T> &lim, T dtdx, const Waves<T> &W, const T *dl,
+                        const T *dr, T *F)
 {
-    const bool on = lim != 0 && W.kind == KIND_REGULAR;
+    const bool on = W.kind == KIND_REGULAR;
     T self[7], c[7];
     family_dots<DIR>(W, W, self);
     HSGN_UNROLL

@@ -58,7 +58,7 @@ int main() {
   Waves<CF> W; Eig<CF> E; riemann<0>(P, sa, sb, W, E); total += 2 * snap("normal solve (x2 per cell)");
   CF d[7]; family_dots<0>(W, W, d); total += 2 * snap("neighbour dot products (x2)");
   CF F[7], am[7], ap[7]; CF dl[7], dr[7]; for (int f=0;f<7;f++){dl[f]=CF(0.5)*d[f]; dr[f]=d[f];} C = Cnt();
-  correction<0>(2, mk(0.01,false,false), W, dl, dr, F); total += 2 * snap("limited correction (x2)");
+  correction<0>(limiter_of<CF>(2), mk(0.01,false,false), W, dl, dr, F); total += 2 * snap("limited correction (x2)");
   fluctuations<0>(W, am, ap); total += 2 * snap("fluctuations (x2)");
   CF vp[7]; CF v[7]; for (int m=0;m<7;m++) v[m]=am[m]; C = Cnt();
   trans_split<1>(E, v, 1, vp); total += 4 * snap("transverse split (x4 per cell)");

@@ -501,6 +501,9 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     T bp_saved[7];               // transverse y-fluctuation entering (i, k-1) from below
     T rx = (T)0, ry = (T)0;
     double clip = 0.0;
+    // error code of the lane (non-hyperbolic edge -4, non-finite result -5),
+    // published once when the strip is done; nothing reads it during the step
+    int errc = 0;
     HSGN_UNROLL
     for (int m = 0; m < 7; m++) { xtr_prev[m] = (T)0; bp_saved[m] = (T)0; ydl[m] = (T)0; }
 
@@ -565,7 +568,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             Waves<T> xw;
             Eig<T> xe;
             bool ok = edge_solve<0, MIXED && FB>(ln, P, sl, sr, xw, xe);
-            if (!ok && lane >= 1) sc->err = -4;
+            errc = (!ok && lane >= 1) ? -4 : errc;
             if (MAP) set_frame(xw, xe, met[1], met[2], (T)0 - met[2], met[1], met[3]);
             Waves<T> xwl;
             shfl_waves_up<MAP>(ln, xw, xwl);
@@ -632,7 +635,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             } else {
                 ok = edge_solve<1, MIXED && FB>(ln, P, yside_prev, yside, yw, ye);
             }
-            if (!ok) sc->err = -4;
+            errc = !ok ? -4 : errc;
             if (k >= r0 && k <= r0 + th && interior) {
                 const T kk = MAP ? tmin(kap_w[sk1], kap_w[sk]) : (T)1;
                 ry = tmax(ry, tmax((T)fabs(yw.smin) / kk, tmax((T)fabs(yw.smax) / kk, (T)fabs(yw.uh) / kk)));
@@ -854,8 +857,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 HSGN_UNROLL
                 for (int m = 1; m < 7; m++) { qs[m] = (S)qd[m]; bad = bad || !finite_val<double>(qd[m]); }
             }
+            errc = (interior && bad) ? -5 : errc;
             if (interior) {
-                if (bad) sc->err = -5;
                 long long idx = (long long)(k - 2) * pi.pitch + (wk.i0 - 2 + lane);
                 long long plane = pi.plane;
                 S *qo = qout + pi.qoff + idx;
@@ -888,6 +891,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             yside_prev = yside;
         }
     }
+    if (errc) sc->err = errc;
     ln.finish(A, wid, pi.scen, (double)rx, (double)ry, clip);
 }
 

@@ -313,18 +313,19 @@ HSGN_HD void derive(const StepParams &P, Cell<T> &c)
 template <class T>
 HSGN_HD T sensor(const StepParams &P, T bL, T bR)
 {
-    T db = bR - bL;
-    if (db == (T)0) return (T)1;
-    T sum = fabs(bR + bL);
-    if (sum == (T)0) return (T)0;
+    // every case is formed and the result selected, without branches (a
+    // zero sum's infinite or undefined ratio is dropped by the selects):
+    // 1 for a flat bottom or xi < xi0, the ramp 1 - 3 r^2 + 2 r^3 for
+    // xi0 <= xi < xi0 + xi1, else 0 (also for bR + bL = 0 with bR != bL)
+    const T db = bR - bL;
+    const T sum = fabs(bR + bL);
     const T num = (T)2 * fabs(db);
-    T xi = tdiv(num, sum);
-    if (xi < (T)P.xi0) return (T)1;
-    if (xi < (T)(P.xi0 + P.xi1)) {
-        T r = tdiv(xi - (T)P.xi0, (T)P.xi1);
-        return (T)-3 * r * r + (T)2 * r * r * r + (T)1;
-    }
-    return (T)0;
+    const T xi = tdiv(num, sum);
+    const T r = tdiv(xi - (T)P.xi0, (T)P.xi1);
+    const T ramp = (T)-3 * r * r + (T)2 * r * r * r + (T)1;
+    const T tail = xi < (T)(P.xi0 + P.xi1) ? ramp : (T)0;
+    const T psi = xi < (T)P.xi0 ? (T)1 : tail;
+    return db == (T)0 ? (T)1 : (sum == (T)0 ? (T)0 : psi);
 }
 
 // ---------------------------------------------------------------------------
@@ -681,9 +682,9 @@ HSGN_HD void correction(const Limiter<T> &lim, T dtdx, const Waves<T> &W, const 
         T s = wave_speed(W, f);
         // waves this small contribute nothing at the working precision;
         // skipping them also keeps the reciprocal of zz finite
-        bool live = on && zz > tiny_norm<T>();
-        T th = live ? quot(s > (T)0 ? dl[f] : dr[f], zz, frcp(zz)) : (T)0;
-        T ph = live ? limiter_phi(lim, th) : (T)0;
+        const bool live = on && zz > tiny_norm<T>();
+        const T th = live ? quot(s > (T)0 ? dl[f] : dr[f], zz, frcp(zz)) : (T)0;
+        const T ph = live ? limiter_phi(lim, th) : (T)0;
         T sg = s > (T)0 ? (T)1 : (s < (T)0 ? (T)-1 : (T)0);
         c[f] = (T)0.5 * sg * ((T)1 - dtdx * fabs(s)) * ph;
     }

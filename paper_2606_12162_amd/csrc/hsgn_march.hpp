@@ -254,12 +254,17 @@ HSGN_HD void shfl_vec(L &ln, const T *a, T *o, bool up)
 }
 
 // raw data of one cell as stored (state plane 0 as stored, bathymetry,
-// mask byte), converted to the compute type
+// mask byte), converted to the compute type, and the wall mirror still to be
+// applied to it (mirror_raw): flip the x- (fx of the column) or the y-momentum
+// (fy), on mapped grids reflect about the wall edge of unit normal wn (x) or
+// bn (y)
 template <class T>
 struct RawCell {
     T q[7];
     T b;
     int mk;
+    int fy;
+    T wn[2], bn[2];
 };
 
 // m - 2 (m . n) n: momentum (hu, hv) mirrored about a wall of unit normal n
@@ -274,7 +279,9 @@ HSGN_HD void reflect(T &hu, T &hv, T nx, T ny)
 // load cell (col, row) of a patch through the boundary map, or (FRAMED)
 // from the stored ghost frame.  On a mapped grid a wall mirrors the
 // momentum about the wall edge of the interior cell's row (column): the
-// left edge of column xwall (0 or nx), the bottom edge of row 0 or ny.
+// left edge of column xwall (0 or nx), the bottom edge of row 0 or ny.  The
+// mirror is applied by mirror_raw when the cell is used: applied here it
+// would make the next row's prefetch wait for its own loads.
 template <bool FRAMED, bool MAP = false, class S, class T>
 HSGN_HD void load_raw(const PatchInfo &pi, const S *q, const S *bath, const uint8_t *mask,
                       int mc, int fx, int row, RawCell<T> &r, int xwall = 0)
@@ -286,22 +293,35 @@ HSGN_HD void load_raw(const PatchInfo &pi, const S *q, const S *bath, const uint
     const S *qp = q + pi.qoff + idx;
     HSGN_UNROLL
     for (int m = 0; m < 7; m++) r.q[m] = (T)qp[m * plane];
+    r.fy = fy;
     if (MAP && pi.metric) {
         const long long W = pi.nx + 4, MP = W * (pi.ny + 4);
         if (fx) {
             const double *e = pi.metric + (long long)(mr + 2) * W + (xwall + 2);
-            reflect(r.q[IHU], r.q[IHV], (T)e[1 * MP], (T)e[2 * MP]);
+            r.wn[0] = (T)e[1 * MP];
+            r.wn[1] = (T)e[2 * MP];
         }
         if (fy) {
             const double *e = pi.metric + (long long)((row < 0 ? 0 : pi.ny) + 2) * W + (mc + 2);
-            reflect(r.q[IHU], r.q[IHV], (T)e[4 * MP], (T)e[5 * MP]);
+            r.bn[0] = (T)e[4 * MP];
+            r.bn[1] = (T)e[5 * MP];
         }
-    } else {
-        if (fx) r.q[IHU] = -r.q[IHU];
-        if (fy) r.q[IHV] = -r.q[IHV];
     }
     r.b = (T)bath[pi.coff + idx];
     r.mk = mask[pi.coff + idx];
+}
+
+// the wall mirror recorded by load_raw (fx: the column's)
+template <bool MAP, class T>
+HSGN_HD void mirror_raw(RawCell<T> &r, int fx, bool mapped)
+{
+    if (MAP && mapped) {
+        if (fx) reflect(r.q[IHU], r.q[IHV], r.wn[0], r.wn[1]);
+        if (r.fy) reflect(r.q[IHU], r.q[IHV], r.bn[0], r.bn[1]);
+    } else {
+        if (fx) r.q[IHU] = -r.q[IHU];
+        if (r.fy) r.q[IHV] = -r.q[IHV];
+    }
 }
 
 // depth from the stored plane-0 value
@@ -514,6 +534,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         Cell<T> c;
         {
             RawCell<T> raw = nxt;
+            mirror_raw<MAP>(raw, fx, pi.metric != nullptr);
             // issue the next row's loads before working on this one
             if (k < r0 + th + 1) load_raw<AMR, MAP>(pi, qin, A.bath, min_, mc, fx, k + 1, nxt, xwall);
             prepare_cell<T, MIXED>(P, raw, tau_pre, c, phi_c, brk_c);

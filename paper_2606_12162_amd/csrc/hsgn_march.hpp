@@ -57,7 +57,7 @@ struct PatchInfo {
 // the distance of the cell centre from a sponged side and w that side's
 // width, s = (w - d) / w inside the band; the largest s over the sides gives
 // rate s^2
-HSGN_HD inline double sponge_sigma(const PatchInfo &pi, int i, int j)
+HSGN_HD double sponge_sigma(const PatchInfo &pi, int i, int j)
 {
     const long long I = pi.sp_i0 + i, J = pi.sp_j0 + j;
     const double d[4] = {((double)I + 0.5) * pi.dx, ((double)(pi.sp_nx - 1 - I) + 0.5) * pi.dx,
@@ -639,6 +639,12 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         Side<T> yside;
         side_of<1>(c, yside);
         if (k >= r0 - 1) {
+            // the x-edge eigenstructure of row k-2 read from LDS ahead of the
+            // y-edge solve, whose arithmetic hides the latency (the parked
+            // waves are read after it: held through the solve, they would
+            // cost more registers than the wait)
+            Eig<T> exk2;
+            eig_load<MAP>(ring, slot_k2, lane, exk2);
             Waves<T> yw;
             Eig<T> ye;
             bool ok;
@@ -714,8 +720,6 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                         T Ft[7];
                         HSGN_UNROLL
                         for (int m = 0; m < 7; m++) Ft[m] = (T)0;
-                        Eig<T> exk2;
-                        eig_load<MAP>(ring, slot_k2, lane, exk2);
                         const T kap2_l = MAP ? ln.up(kap_w[sk2]) : (T)1;   // cell (i - 1, k - 2)
                         if (trans && exk2.wet) {
                             T vp[7], vm[7];

@@ -59,10 +59,13 @@ struct GpuLanes {
     }
 };
 
-// Mixed precision runs two wavefronts per SIMD: registers are capped at
-// 256 per lane (the few values beyond that spill to scratch), which hides
-// more latency than the spills cost.  FP64 keeps one wavefront per SIMD
-// with its values in VGPRs and AGPRs.
+// Occupancy: the mixed-precision kernel without the FP64 edge solve (FB
+// false) fits in about 200 registers and runs two wavefronts per SIMD.  The
+// kernels with it (mixed FB true, which takes only the coastal items beside
+// the other, and FP64) run one wavefront per SIMD with their values in VGPRs
+// and AGPRs: capped at 256 registers for two, the mixed full kernel spilled
+// 152 bytes per lane to scratch and held its CUs longer than the wait it
+// hid.
 //
 // With item lists (A.list) the kernel takes the items of its class's list:
 // FB false the items none of whose edges takes the FP64 solve, compiled
@@ -74,7 +77,8 @@ struct GpuLanes {
 // SP: compiled with the sponge relaxation (launched when some patch has a
 // sponge; the kernels without it keep their registers).
 template <class S, class T, bool MIXED, bool AMR, bool FB = true, bool SP = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu((MIXED && !FB) ? 2 : 1, (MIXED && !FB) ? 2 : 1)))
 void march_kernel(MarchArgs<S> A)
 {
     __shared__ T ring[3 * EIG_FIELDS * 64 + (MIXED ? 3 * 7 * 64 : (PARK_WAVES + PARK_SIDE) * 64)];
@@ -100,7 +104,8 @@ void march_kernel(MarchArgs<S> A)
 // when some patch is mapped), with the x-edge frames also kept in the LDS
 // ring; items and lists as in march_kernel
 template <class S, class T, bool MIXED, bool FB = true>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MIXED ? 2 : 1, MIXED ? 2 : 1)))
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu((MIXED && !FB) ? 2 : 1, (MIXED && !FB) ? 2 : 1)))
 void march_kernel_mapped(MarchArgs<S> A)
 {
     __shared__ T ring[3 * (EIG_FIELDS + 5) * 64 + (MIXED ? 3 * 7 * 64 : 0)];

@@ -81,9 +81,11 @@ STEP_KERNELS = {"fp64": "march_kernel<fp64>",
 KERNEL_SOURCES = ["hsgn_math.hpp", "hsgn_march.hpp", "hsgn_step.hpp",
                   "hsgn_step32.hip", "hsgn_step64.hip"]
 MEASURED_TRAFFIC = {
-    ("ensemble", "mixed"): {"digest": "d1d0d20b3fb96a32",
-                            "tiles": {28: (1.561269e+06, 1.606027e+06), 32: (1.537829e+06, 1.603881e+06),
-                                      40: (1.503294e+06, 1.598789e+06), 48: (1.480561e+06, 1.596598e+06)}},
+    ("ensemble", "mixed"): {"digest": "3b0740b7ab134006",
+                            "tiles": {40: (1.023175e+06, 1.419998e+06), 48: (1.011934e+06, 1.426212e+06),
+                                      56: (1.004208e+06, 1.429073e+06)}},
+    ("ensemble", "fp64"): {"digest": "3b0740b7ab134006",
+                           "tiles": {56: (1.675634e+06, 2.745587e+06)}},
 }
 
 
@@ -489,12 +491,16 @@ def main():
         ctx64, el64, kms64, _, rows64 = run(H, torch, ws, "fp64", args.steps, args.warmup,
                                             tile_rows, not args.no_autotune)
         hbm64 = ALG_BYTES["fp64"] * cells_per_launch / (kms64 / 1e3) / 1e9
+        traffic64 = None if args.mapped else measured_traffic(args.workload, "fp64", rows64)
+        alg64 = ALG_BYTES["fp64"] * cells_per_launch
         out["fp64_plain"] = {"value": cells * args.steps / el64,
                              "ms_per_step": el64 * 1e3 / args.steps,
                              "kernel_avg_us": kms64 * 1e3, "tile_rows": rows64,
                              "roofline": {"bound": "hbm", "achieved": hbm64, "peak": HBM_PEAK_GBS,
                                           "unit": "GB/s", "frac": hbm64 / HBM_PEAK_GBS,
                                           "alg_bytes_per_cell": ALG_BYTES["fp64"],
+                                          "traffic": traffic64,
+                                          "traffic_over_alg": traffic64 / alg64 if traffic64 else None,
                                           "alu_tflops": ALG_FLOPS * cells_per_launch / (kms64 / 1e3) / 1e12}}
         out["mixed_over_fp64"] = value / out["fp64_plain"]["value"]
         out["gauge_err_over_amp_timed_run"] = gauge_error(ctx, ctx64, ws)

@@ -59,6 +59,22 @@ struct GpuLanes {
     }
 };
 
+// XCD-aware order: the chip hands consecutive blocks of a launch to its 8
+// XCDs in turn, and each XCD has its own L2.  Block b takes item
+// (b mod 8) per + b / 8 (per = ceil(n / 8)), so that each XCD works through
+// one contiguous run of the work table (row-tile major), where neighbouring
+// strips, which share halo columns and cache lines, meet in the same L2.
+// Launches over one block per item cover n rounded up to a multiple of 8
+// (xcd_grid).  False: the block has no item.
+constexpr unsigned XCDS = 8;
+__device__ inline bool xcd_item(unsigned b, unsigned n, int &item)
+{
+    const unsigned per = (n + XCDS - 1) / XCDS, j = b / XCDS;
+    item = (int)((b % XCDS) * per + j);
+    return j < per && (unsigned)item < n;
+}
+inline unsigned xcd_grid(unsigned n) { return (n + XCDS - 1) / XCDS * XCDS; }
+
 // Occupancy: the mixed-precision kernel without the FP64 edge solve (FB
 // false) fits in about 200 registers and runs two wavefronts per SIMD.  The
 // kernels with it (mixed FB true, which takes only the coastal items beside
@@ -90,12 +106,10 @@ void march_kernel(MarchArgs<S> A)
             march<GpuLanes<T>, S, T, MIXED, AMR, FB, SP>(ln, A, wid);
         }
     } else {
-        int wid = (int)blockIdx.x;
-        if (wid >= A.nwork) return;
-        if (A.list) {                                               // uniform over the wavefront
-            if ((unsigned)wid >= A.lcnt[0]) return;
-            wid = A.list[wid];
-        }
+        const unsigned n = A.list ? A.lcnt[0] : (unsigned)A.nwork;
+        int wid;
+        if (!xcd_item(blockIdx.x, n, wid)) return;                 // uniform over the wavefront
+        if (A.list) wid = A.list[wid];
         march<GpuLanes<T>, S, T, MIXED, AMR, FB, SP>(ln, A, wid);
     }
 }
@@ -117,12 +131,10 @@ void march_kernel_mapped(MarchArgs<S> A)
             march<GpuLanes<T>, S, T, MIXED, false, FB, false, true>(ln, A, wid);
         }
     } else {
-        int wid = (int)blockIdx.x;
-        if (wid >= A.nwork) return;
-        if (A.list) {                                               // uniform over the wavefront
-            if ((unsigned)wid >= A.lcnt[0]) return;
-            wid = A.list[wid];
-        }
+        const unsigned n = A.list ? A.lcnt[0] : (unsigned)A.nwork;
+        int wid;
+        if (!xcd_item(blockIdx.x, n, wid)) return;                 // uniform over the wavefront
+        if (A.list) wid = A.list[wid];
         march<GpuLanes<T>, S, T, MIXED, false, FB, false, true>(ln, A, wid);
     }
 }

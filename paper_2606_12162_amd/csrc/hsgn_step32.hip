@@ -24,9 +24,10 @@ void launch_march32(const MarchArgs<float> &A, unsigned nwork, hipStream_t strea
 // the kernel without the FP64 edge solve, over the other list
 void launch_march32_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
 {
-    if (A.mapped) march_kernel_mapped<float, float, true, false><<<nwork, 64, 0, stream>>>(A);
-    else if (A.sponge) march_kernel<float, float, true, false, false, true><<<nwork, 64, 0, stream>>>(A);
-    else march_kernel<float, float, true, false, false, false><<<nwork, 64, 0, stream>>>(A);
+    const unsigned grid = xcd_grid(nwork);
+    if (A.mapped) march_kernel_mapped<float, float, true, false><<<grid, 64, 0, stream>>>(A);
+    else if (A.sponge) march_kernel<float, float, true, false, false, true><<<grid, 64, 0, stream>>>(A);
+    else march_kernel<float, float, true, false, false, false><<<grid, 64, 0, stream>>>(A);
 }
 
 // the item lists from the attempt's input mask (classes into cls)

@@ -21,8 +21,9 @@ void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t s
 // the kernel without the FP64 edge solve, over the other list
 void launch_march32_amr_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
 {
-    if (A.sponge) march_kernel<float, float, true, true, false, true><<<nwork, 64, 0, stream>>>(A);
-    else march_kernel<float, float, true, true, false, false><<<nwork, 64, 0, stream>>>(A);
+    const unsigned grid = xcd_grid(nwork);
+    if (A.sponge) march_kernel<float, float, true, true, false, true><<<grid, 64, 0, stream>>>(A);
+    else march_kernel<float, float, true, true, false, false><<<grid, 64, 0, stream>>>(A);
 }
 
 // the item lists from the attempt's input mask, ghost frames included

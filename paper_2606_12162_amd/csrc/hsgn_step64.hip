@@ -6,7 +6,8 @@ using namespace hsgn;
 
 void launch_march64(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream)
 {
-    if (A.mapped) march_kernel_mapped<double, double, false><<<nwork, 64, 0, stream>>>(A);
-    else if (A.sponge) march_kernel<double, double, false, false, true, true><<<nwork, 64, 0, stream>>>(A);
-    else march_kernel<double, double, false, false, true, false><<<nwork, 64, 0, stream>>>(A);
+    const unsigned grid = xcd_grid(nwork);
+    if (A.mapped) march_kernel_mapped<double, double, false><<<grid, 64, 0, stream>>>(A);
+    else if (A.sponge) march_kernel<double, double, false, false, true, true><<<grid, 64, 0, stream>>>(A);
+    else march_kernel<double, double, false, false, true, false><<<grid, 64, 0, stream>>>(A);
 }

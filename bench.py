@@ -97,8 +97,8 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile_rows):
-    m = MEASURED_TRAFFIC.get((workload, precision))
+def measured_traffic(workload, precision, tile_rows, model="hsgn"):
+    m = MEASURED_TRAFFIC.get((workload, precision)) if model == "hsgn" else None
     if m is None or m["digest"] != kernel_digest() or len(tile_rows) != 1:
         return None
     fw = m["tiles"].get(tile_rows[0])
@@ -452,7 +452,7 @@ def main():
         % (el * 1e3 / args.steps, kms * 1e3, value))
     tflops = ALG_FLOPS * cells_per_launch / (kms / 1e3) / 1e12
     hbm_gbs = ALG_BYTES[precision] * cells_per_launch / (kms / 1e3) / 1e9
-    traffic = None if args.mapped else measured_traffic(args.workload, precision, rows)
+    traffic = None if args.mapped else measured_traffic(args.workload, precision, rows, args.model)
     alg_launch = ALG_BYTES[precision] * cells_per_launch
     dtype = {"mixed": "f32+f64", "fp64": "f64"}[precision]
     out = {
@@ -491,7 +491,7 @@ def main():
         ctx64, el64, kms64, _, rows64 = run(H, torch, ws, "fp64", args.steps, args.warmup,
                                             tile_rows, not args.no_autotune)
         hbm64 = ALG_BYTES["fp64"] * cells_per_launch / (kms64 / 1e3) / 1e9
-        traffic64 = None if args.mapped else measured_traffic(args.workload, "fp64", rows64)
+        traffic64 = None if args.mapped else measured_traffic(args.workload, "fp64", rows64, args.model)
         alg64 = ALG_BYTES["fp64"] * cells_per_launch
         out["fp64_plain"] = {"value": cells * args.steps / el64,
                              "ms_per_step": el64 * 1e3 / args.steps,

@@ -409,11 +409,16 @@ HSGN_HD void to_global(const Waves<T> &W, T *v)
 // and its results replace the FP32 ones.
 // FB false: the FP32 solve alone, for work items whose cells all have
 // c^2 > 0 (the FP64 branch would never be taken).
+// A wavefront none of whose used edges (use) has a dry side takes the solve
+// compiled for two wet sides: the general one sets the dry-dry outputs
+// before its branch, some 35 moves per edge on every row.
 template <int DIR, bool MIXED, class L, class T>
 HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Side<T> &sr,
-                        Waves<T> &W, Eig<T> &E)
+                        Waves<T> &W, Eig<T> &E, bool use = true)
 {
-    bool ok = riemann<DIR>(P, sl, sr, W, E);
+    bool ok;
+    if (ln.any(use && !(sl.wet && sr.wet))) ok = riemann<DIR>(P, sl, sr, W, E);
+    else ok = riemann<DIR, true>(P, sl, sr, W, E);
     if (MIXED) {
         int need = !(sl.c2 > (T)0) || !(sr.c2 > (T)0);
         if (ln.any(need)) {
@@ -588,7 +593,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             }
             Waves<T> xw;
             Eig<T> xe;
-            bool ok = edge_solve<0, MIXED && FB>(ln, P, sl, sr, xw, xe);
+            // lane 0 has no left neighbour (its edge is a halo edge, never used)
+            bool ok = edge_solve<0, MIXED && FB>(ln, P, sl, sr, xw, xe, lane >= 1);
             errc = (!ok && lane >= 1) ? -4 : errc;
             if (MAP) set_frame(xw, xe, met[1], met[2], (T)0 - met[2], met[1], met[3]);
             Waves<T> xwl;

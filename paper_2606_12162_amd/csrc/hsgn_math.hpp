@@ -361,15 +361,18 @@ HSGN_HD void side_of(const Cell<T> &c, Side<T> &sd)
     sd.hp = c.wet ? c.q[IHP] : (T)0;
 }
 
-template <int DIR, class T>
+// WET: compiled for edges whose two sides are wet (no dry, wall or
+// dry-front case); the caller takes it only when that holds for every edge
+// of the wavefront it uses (the results are those of the general solve)
+template <int DIR, bool WET = false, class T>
 HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
                      Waves<T> &W, Eig<T> &E)
 {
     const int IN = DIR == 0 ? IHU : IHV;   // normal momentum component
     const int IT = DIR == 0 ? IHV : IHU;   // tangential momentum component
     const T g = (T)P.g;
-    E.wet = sL.wet && sR.wet;
-    if (!sL.wet && !sR.wet) {
+    E.wet = WET ? 1 : (sL.wet && sR.wet);
+    if (!WET && !sL.wet && !sR.wet) {
         // both sides dry: no waves
         HSGN_UNROLL
         for (int m = 0; m < 7; m++) { W.z0[m] = (T)0; W.z6[m] = (T)0; }
@@ -388,14 +391,14 @@ HSGN_HD bool riemann(const StepParams &P, const Side<T> &sL, const Side<T> &sR,
     W.kind = KIND_REGULAR;
     Side<T> L = sL, R = sR;
     int dryL = 0, dryR = 0;
-    if (sL.wet && !sR.wet) {
+    if (!WET && sL.wet && !sR.wet) {
         if (sL.h + sL.b < sR.b) {
             W.kind = KIND_WALL_R;
             R = L; R.hun = -L.hun; R.un = -L.un;
         } else {
             dryR = 1;
         }
-    } else if (!sL.wet && sR.wet) {
+    } else if (!WET && !sL.wet && sR.wet) {
         if (sR.h + sR.b < sL.b) {
             W.kind = KIND_WALL_L;
             L = R; L.hun = -R.hun; L.un = -R.un;

@@ -5,8 +5,11 @@
 // side.  It marches up the rows r0 - 2 .. r0 + th + 1 of its strip, loading
 // one row per iteration (coalesced SoA loads), and writes rows r0 .. r0+th-1.
 // x-neighbours are exchanged with lane shuffles; y-neighbours live in
-// registers (sliding windows).  Nothing is staged in LDS and no barrier is
-// needed: a wavefront is independent of every other.
+// registers (sliding windows).  Each wavefront keeps its own LDS area (the
+// x-edge eigenstructure of three rows, in mixed precision the rows' base
+// states, in FP64 the values parked between rows); a lane touches only its
+// own entries, so no barrier is needed and a wavefront is independent of
+// every other.
 //
 // Per iteration k (row k loaded):
 //   1. load cell (i, k) through the boundary map, first source half step;

@@ -44,6 +44,27 @@ single-patch oracle step:
   covered cells is the mean of the fine bathymetry (set once).
 * Gauges record after each level-0 step from the finest patch containing
   the point; the mass is the level-0 sum.
+
+Mapped patch sets (Sec. 4, mapped grids, on block-structured grids).  Every
+patch carries the node coordinates of its frame; a finer patch's nodes are
+the bilinear refinement of the coarser level's (so that its cells tile each
+coarse cell exactly, with straight edges: the fine areas sum to the coarse
+area, and the fine edges along a coarse edge to its length, with its
+normal).  Each patch steps as a mapped grid.  On top of the rules above:
+* ghost interpolation stays in computational (index) space; the momenta
+  are in the physical frame;
+* a level-0 wall ghost mirrors the momentum about the wall edge's unit
+  normal n (m - 2 (m . n) n), the edge being the domain edge of the
+  interior cell's row (x walls) or column (y walls), as on a single grid;
+* the boundary-flux records take the fine step's mapped contributions
+  (global frame, scaled by the edge's length ratio) and the total
+  fluctuation between C* and g* solved in the fine edge's frame and scaled
+  by its length ratio;
+* refluxing divides by the coarse cell's capacity (dt/dx over kap), the
+  clipped mass counts kap dx dy;
+* averaging down weighs the 4 x 4 fine cells by their capacities:
+  sum(kap q) / sum(kap), both sums in row order; the bathymetry likewise;
+* the mass is the level-0 sum of kap h dx dy.
 """
 from __future__ import annotations
 
@@ -94,6 +115,7 @@ class _Patch:
         self.g = grid
         self.q, self.b, self.phi, self.brk, self.iface = grid.framed()
         self.b_raw = None          # bathymetry as set, before averaging down
+        self.met = None            # metric planes [7][ny + 4][nx + 4] (mapped)
 
     def contains(self, I, J):
         return self.I0 <= I < self.I0 + self.nx and self.J0 <= J < self.J0 + self.ny
@@ -107,12 +129,14 @@ class _GridSpec:
 class AmrOracle:
     """One scenario: a static patch set advanced with fixed level-0 steps."""
 
-    def __init__(self, params, dx0, dy0, bc, patches, reflux=True):
+    def __init__(self, params, dx0, dy0, bc, patches, reflux=True, capacity=True):
         """patches: sequence of (level, nx, ny, x0, y0).  reflux=False leaves
-        the refluxing out (a deliberately wrong variant for the tests that
-        show the conservation check notices it)."""
+        the refluxing out, capacity=False the capacities out of refluxing and
+        averaging down on mapped patch sets (deliberately wrong variants for
+        the tests that show the conservation check notices them)."""
         self.P = params
         self.do_reflux = reflux
+        self.use_capacity = capacity
         self.bc = list(bc)
         self.dx0, self.dy0 = dx0, dy0
         self.levels = []
@@ -195,10 +219,25 @@ class AmrOracle:
     def set_gauges(self, xy):
         self.gauges = np.asarray(xy, dtype=np.float64).reshape(-1, 2)
 
+    def set_mapping(self, pid, xn, yn):
+        """node coordinates [ny + 5][nx + 5] of patch pid (nodes i = -2..nx+2,
+        j = -2..ny+2, the ghost frame included); every patch of the set is
+        mapped before the first step, or none"""
+        p = self.patches[pid]
+        p.g.set_mapping(xn, yn)
+        p.met = p.g.metric()
+        self.prepared = False
+
+    @property
+    def mapped(self):
+        return any(p.met is not None for p in self.patches)
+
     # --------------------------------------------------------------- set-up
     def prepare(self):
         """bathymetry of covered coarse cells, ghost bathymetry, phi_T and
         the interface flags"""
+        if self.mapped and any(p.met is None for p in self.patches):
+            raise ValueError("a patch set is mapped in every patch or in none")
         # coarse bathymetry of covered cells := mean of the fine bathymetry,
         # finest level first
         for lev in range(len(self.levels) - 1, 0, -1):
@@ -238,16 +277,20 @@ class AmrOracle:
                 yield i, j
 
     def _source_of(self, p, i, j):
-        """('copy', src patch, si, sj, flip_u, flip_v) or ('coarse', I, J, ox, oy)"""
+        """('copy', src patch, si, sj, flip_u, flip_v, wi, wj) or ('coarse',
+        I, J, ox, oy); wi (wj) is the source-local column (row) of the cell
+        whose left (bottom) edge is the domain wall of an x (y) flip"""
         I, J = p.I0 + i, p.J0 + j
         if p.level == 0:
             mi, fx = _map_index(I, self.NX, self.bc[0], self.bc[1])
             mj, fy = _map_index(J, self.NY, self.bc[2], self.bc[3])
             s = self.find(0, mi, mj)
-            return ("copy", s, mi - s.I0, mj - s.J0, fx, fy)
+            wi = (0 if I < 0 else self.NX) - s.I0
+            wj = (0 if J < 0 else self.NY) - s.J0
+            return ("copy", s, mi - s.I0, mj - s.J0, fx, fy, wi, wj)
         s = self.find(p.level, I, J)
         if s is not None:
-            return ("copy", s, I - s.I0, J - s.J0, 0, 0)
+            return ("copy", s, I - s.I0, J - s.J0, 0, 0, 0, 0)
         Ic, Jc = I // RATIO, J // RATIO
         ox = ((I - RATIO * Ic) + 0.5) / RATIO - 0.5
         oy = ((J - RATIO * Jc) + 0.5) / RATIO - 0.5
@@ -256,7 +299,7 @@ class AmrOracle:
     def _ghost_tables(self, p):
         """the ghost sources of patch p (static for the patch set), as
         arrays in frame indices: copies grouped by source patch
-        (dj, di, sj, si, fx, fy), and the coarse ghosts (dj, di, ox, oy)
+        (dj, di, sj, si, fx, fy, wi, wj), and the coarse ghosts (dj, di, ox, oy)
         with, for the coarse centre and its left, right, lower and upper
         neighbours, the coarse patch id (-1: none) and frame indices"""
         tabs = self.__dict__.setdefault("_gtab", {})
@@ -268,9 +311,9 @@ class AmrOracle:
         for i, j in self._ghost_cells(p):
             src = self._source_of(p, i, j)
             if src[0] == "copy":
-                _, sp, si, sj, fx, fy = src
-                c = copies.setdefault(sp.pid, ([], [], [], [], [], []))
-                for lst, v in zip(c, (j + 2, i + 2, sj + 2, si + 2, fx, fy)):
+                _, sp, si, sj, fx, fy, wi, wj = src
+                c = copies.setdefault(sp.pid, ([], [], [], [], [], [], [], []))
+                for lst, v in zip(c, (j + 2, i + 2, sj + 2, si + 2, fx, fy, wi + 2, wj + 2)):
                     lst.append(v)
                 continue
             _, Ic, Jc, ox, oy = src
@@ -284,7 +327,8 @@ class AmrOracle:
                 co["cj"][k].append(Jc + dj - c.J0 + 2 if c is not None else 0)
                 co["ci"][k].append(Ic + di - c.I0 + 2 if c is not None else 0)
         ct = {sp: tuple(np.array(a, dtype=np.int64) for a in c[:4]) +
-              tuple(np.array(a, dtype=bool) for a in c[4:]) for sp, c in copies.items()}
+              tuple(np.array(a, dtype=bool) for a in c[4:6]) +
+              tuple(np.array(a, dtype=np.int64) for a in c[6:]) for sp, c in copies.items()}
         cc = {"dj": np.array(co["dj"], dtype=np.int64), "di": np.array(co["di"], dtype=np.int64),
               "ox": np.array(co["ox"], dtype=np.float64), "oy": np.array(co["oy"], dtype=np.float64),
               "pid": [np.array(a, dtype=np.int64) for a in co["pid"]],
@@ -305,7 +349,7 @@ class AmrOracle:
 
     def _fill_ghost_bathymetry(self, p):
         ct, cc = self._ghost_tables(p)
-        for sp, (dj, di, sj, si, _, _) in ct.items():
+        for sp, (dj, di, sj, si, _, _, _, _) in ct.items():
             p.b[dj, di] = self.patches[sp].b[sj, si]
         if len(cc["dj"]):
             bs = {c.pid: c.b for c in self.levels[p.level - 1]}
@@ -324,11 +368,24 @@ class AmrOracle:
         brk = {c.pid: c.brk for c in coarse}
         for p in self.levels[lev]:
             ct, cc = self._ghost_tables(p)
-            for sp, (dj, di, sj, si, fx, fy) in ct.items():
+            for sp, (dj, di, sj, si, fx, fy, wi, wj) in ct.items():
                 s = self.patches[sp]
                 p.q[:, dj, di] = s.q[:, sj, si]
-                p.q[1, dj[fx], di[fx]] = -p.q[1, dj[fx], di[fx]]
-                p.q[2, dj[fy], di[fy]] = -p.q[2, dj[fy], di[fy]]
+                if s.met is None:
+                    p.q[1, dj[fx], di[fx]] = -p.q[1, dj[fx], di[fx]]
+                    p.q[2, dj[fy], di[fy]] = -p.q[2, dj[fy], di[fy]]
+                else:
+                    # mirrored about the wall edge: x walls first, then y
+                    for flip, (a, b), (mj, mi) in ((fx, (1, 2), (sj, wi)), (fy, (4, 5), (wj, si))):
+                        if not flip.any():
+                            continue
+                        k = (dj[flip], di[flip])
+                        nx_ = s.met[a][mj[flip], mi[flip]]
+                        ny_ = s.met[b][mj[flip], mi[flip]]
+                        hu, hv = p.q[1][k], p.q[2][k]
+                        d = hu * nx_ + hv * ny_
+                        p.q[1][k] = hu - 2.0 * d * nx_
+                        p.q[2][k] = hv - 2.0 * d * ny_
                 p.phi[dj, di] = s.phi[sj, si]
                 p.brk[dj, di] = s.brk[sj, si]
             if not len(cc["dj"]):
@@ -437,12 +494,22 @@ class AmrOracle:
                     k = (direction == d) & (low == lo)
                     if not k.any():
                         continue
-                    if lo:
-                        D[k] = O.edge_dflux_n(self.P, d, qC[:, k].T, qg[:, k].T, bC[k], bg[k],
-                                              c2C[k], c2g[k])
+                    a, b = (qC[:, k].T, qg[:, k].T) if lo else (qg[:, k].T, qC[:, k].T)
+                    ba, bb = (bC[k], bg[k]) if lo else (bg[k], bC[k])
+                    ca, cb = (c2C[k], c2g[k]) if lo else (c2g[k], c2C[k])
+                    if f.met is None:
+                        df = O.edge_dflux_n(self.P, d, a, b, ba, bb, ca, cb)
                     else:
-                        D[k] = -O.edge_dflux_n(self.P, d, qg[:, k].T, qC[:, k].T, bg[k], bC[k],
-                                               c2g[k], c2C[k])
+                        # the fine edge: the left (bottom) edge of the cell
+                        # right of (above) the ghost on a low side, of the
+                        # ghost itself on a high side
+                        ej = gj[k] + (1 if (lo and d == 1) else 0)
+                        ei = gi[k] + (1 if (lo and d == 0) else 0)
+                        pl = (1, 2, 3) if d == 0 else (4, 5, 6)
+                        df = O.edge_dflux_mapped_n(self.P, d, a, b, ba, bb, ca, cb,
+                                                   f.met[pl[0]][ej, ei], f.met[pl[1]][ej, ei],
+                                                   f.met[pl[2]][ej, ei])
+                    D[k] = df if lo else -df
             R = self.R[f.pid]
             R[e] = R[e] + (K[e] + D)
 
@@ -456,6 +523,10 @@ class AmrOracle:
                         continue
                     I, J = p.I0 + i, p.J0 + j
                     v = p.q[:, j + 2, i + 2].copy()
+                    # mapped: the records are fluxes times length ratios, the
+                    # update divides them by the cell's capacity
+                    kap = p.met[0, j + 2, i + 2] if (p.met is not None and self.use_capacity) \
+                        else None
                     for bit in range(4):
                         if not fl & (1 << bit):
                             continue
@@ -473,11 +544,16 @@ class AmrOracle:
                             e0, sgn, dtd = 2 * f.ny + (RATIO * I - f.I0), -1.0, dtdy
                         Rf = self.R[f.pid]
                         S = ((Rf[e0] + Rf[e0 + 1]) + Rf[e0 + 2]) + Rf[e0 + 3]
+                        if kap is not None:
+                            dtd = dtd / kap
                         corr = dtd * (S * 0.0625)
                         v = v + corr if sgn > 0 else v - corr
                     # cell fix-ups
                     if v[0] < 0.0:
-                        self.clip += -v[0] * p.dx * p.dy
+                        if kap is not None:
+                            self.clip += -v[0] * kap * p.dx * p.dy
+                        else:
+                            self.clip += -v[0] * p.dx * p.dy
                         v[0] = 0.0
                     if v[0] <= self.P.dry_tol:
                         v[1:] = 0.0
@@ -488,15 +564,24 @@ class AmrOracle:
     def _average_down_patch(self, f, bath_only=False):
         """covered coarse cells take the mean of their 4 x 4 fine cells: the
         16 values summed in row order (a fine row, then the next), times
-        1/16; the bathymetry alone with bath_only"""
+        1/16; on a mapped patch set sum(kap q) / sum(kap) over the same
+        cells in the same order; the bathymetry alone with bath_only"""
         lev = f.level
         nbx, nby = f.nx // RATIO, f.ny // RATIO
         src = f.b[None] if bath_only else f.q
         s = np.zeros((src.shape[0], nby, nbx))
+        weighted = f.met is not None and self.use_capacity
+        w = np.zeros((nby, nbx))
         for a in range(RATIO):
             for bb in range(RATIO):
-                s = s + src[:, 2 + a:2 + a + RATIO * nby:RATIO, 2 + bb:2 + bb + RATIO * nbx:RATIO]
-        mean = s * 0.0625
+                sl = (slice(2 + a, 2 + a + RATIO * nby, RATIO), slice(2 + bb, 2 + bb + RATIO * nbx, RATIO))
+                if weighted:
+                    k = f.met[0][sl]
+                    s = s + k * src[(slice(None),) + sl]
+                    w = w + k
+                else:
+                    s = s + src[(slice(None),) + sl]
+        mean = s / w if weighted else s * 0.0625
         Ic0, Jc0 = f.I0 // RATIO, f.J0 // RATIO
         for c in self.levels[lev - 1]:
             i0, i1 = max(Ic0, c.I0), min(Ic0 + nbx, c.I0 + c.nx)
@@ -563,13 +648,22 @@ class AmrOracle:
         return t, e
 
     def mass(self):
+        """level-0 sum of h dx dy (kap h dx dy on a mapped patch set)"""
+        if self.mapped:
+            return sum(float((p.met[0, 2:-2, 2:-2] * p.q[0, 2:-2, 2:-2]).sum()) * p.dx * p.dy
+                       for p in self.levels[0])
         return sum(float(p.q[0, 2:-2, 2:-2].sum()) * p.dx * p.dy for p in self.levels[0])
 
 
-def from_workload(w, reflux=True) -> AmrOracle:
-    """an AmrOracle from an AMR workload (paper_2606_12162_amd.workloads)"""
+def from_workload(w, reflux=True, capacity=True, nodes=None) -> AmrOracle:
+    """an AmrOracle from an AMR workload (paper_2606_12162_amd.workloads);
+    nodes: per patch (xn, yn) of a mapped patch set"""
     o = AmrOracle(w.params, w.dx0, w.dy0, w.bc, [(p.level, p.nx, p.ny, p.x0, p.y0)
-                                                  for p in w.patches], reflux=reflux)
+                                                  for p in w.patches], reflux=reflux,
+                  capacity=capacity)
+    if nodes is not None:
+        for pid, (xn, yn) in enumerate(nodes):
+            o.set_mapping(pid, xn, yn)
     for pid, p in enumerate(w.patches):
         o.set_bathymetry(pid, p.b)
         o.set_state(pid, p.q)

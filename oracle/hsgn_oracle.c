@@ -1369,7 +1369,7 @@ int orc_set_sponge(orc_grid *g, const double w[4], double rate, long long i0, lo
 
 int orc_set_mapping(orc_grid *g, const double *xn, const double *yn)
 {
-    if (g->ext_ghosts || !xn || !yn) return ORC_EINVAL;
+    if (!xn || !yn) return ORC_EINVAL;
     const int W = g->nx + 5;
     const size_t np = PLANE(g);
     real *a[7];
@@ -1410,6 +1410,16 @@ int orc_set_mapping(orc_grid *g, const double *xn, const double *yn)
     free(g->ynx); free(g->yny); free(g->ygm);
     g->kap = a[0]; g->xnx = a[1]; g->xny = a[2]; g->xgm = a[3];
     g->ynx = a[4]; g->yny = a[5]; g->ygm = a[6];
+    return ORC_OK;
+}
+
+int orc_metric(const orc_grid *g, double *out)
+{
+    if (!g->kap) return ORC_EINVAL;
+    const size_t np = PLANE(g);
+    const real *pl[7] = {g->kap, g->xnx, g->xny, g->xgm, g->ynx, g->yny, g->ygm};
+    for (int m = 0; m < 7; m++)
+        for (size_t k = 0; k < np; k++) out[(size_t)m * np + k] = (double)pl[m][k];
     return ORC_OK;
 }
 
@@ -1502,6 +1512,28 @@ int orc_edge_dflux_n(const orc_params *p, int dir, int n, const double *qL, cons
         int r = orc_edge_dflux(p, dir, qL + 7 * (size_t)k, qR + 7 * (size_t)k, bL[k], bR[k],
                                c2L[k], c2R[k], df + 7 * (size_t)k);
         if (r != ORC_OK) rc = r;
+    }
+    return rc;
+}
+
+/* the same for mapped edges: the solve of the mapped step (riemann_mapped)
+ * at an edge of unit normal n and length ratio gm, frames as in the step */
+int orc_edge_dflux_mapped_n(const orc_params *p, int dir, int n, const double *qL,
+                            const double *qR, const double *bL, const double *bR,
+                            const double *c2L, const double *c2R, const double *nx,
+                            const double *ny, const double *gm, double *df)
+{
+    int rc = ORC_OK;
+    for (int k = 0; k < n; k++) {
+        edge_t E;
+        real a[7], c[7];
+        for (int m = 0; m < 7; m++) { a[m] = qL[7 * (size_t)k + m]; c[m] = qR[7 * (size_t)k + m]; }
+        const real tx = dir ? ny[k] : 0.0 - ny[k];
+        const real ty = dir ? 0.0 - nx[k] : nx[k];
+        int r = riemann_mapped(p, a, c, bL[k], bR[k], c2L[k], c2R[k], nx[k], ny[k], tx, ty,
+                               gm[k], &E);
+        if (r != ORC_OK) rc = r;
+        for (int m = 0; m < 7; m++) df[7 * (size_t)k + m] = (double)(E.amdq[m] + E.apdq[m]);
     }
     return rc;
 }

@@ -137,9 +137,14 @@ int orc_update_phi_framed(orc_grid *g);
  * The grid's dx and dy become the computational spacings: capacities are
  * areas over dx dy, edge length ratios lengths over dy (left edges) and dx
  * (bottom edges).  Momenta are in the physical frame; walls mirror them about
- * the wall edge.  Refused (ORC_EINVAL) on patch-set grids and for a cell of
- * non-positive area or an edge of zero length. */
+ * the wall edge (on a patch-set grid the caller fills the ghost cells, walls
+ * included).  Refused (ORC_EINVAL) for a cell of non-positive area or an edge
+ * of zero length. */
 int orc_set_mapping(orc_grid *g, const double *xn, const double *yn);
+/* the metric planes of a mapped grid copied to out[7][sy][sx]: capacity;
+ * unit normal (x, y) and length ratio of the cell's left edge; the same for
+ * its bottom edge.  ORC_EINVAL on a Cartesian grid. */
+int orc_metric(const orc_grid *g, double *out);
 /* radially symmetric solutions (Appendix D): the grid's x is the radius
  * (x0 >= 0), u the radial velocity, and every step adds the geometric
  * source -(1/r) (hu, hu u, 0, hu w, hu sigma, hu (p + c^2), hu p_b) by
@@ -155,6 +160,14 @@ void orc_source_cells(int n, double *q, const double *c2, double tau, int model)
 int orc_edge_dflux_n(const orc_params *p, int dir, int n, const double *qL, const double *qR,
                      const double *bL, const double *bR, const double *c2L, const double *c2R,
                      double *df);
+/* total fluctuation of n mapped edges in the global frame (dir 0: left
+ * edges, tangent (-n_y, n_x); 1: bottom edges, tangent (n_y, -n_x)): the
+ * normal solve of the states rotated into the frame of the unit normal
+ * (nx, ny), its fluctuations rotated back and scaled by the length ratio gm */
+int orc_edge_dflux_mapped_n(const orc_params *p, int dir, int n, const double *qL,
+                            const double *qR, const double *bL, const double *bR,
+                            const double *c2L, const double *c2R, const double *nx,
+                            const double *ny, const double *gm, double *df);
 /* limiter function phi(theta): lim 0 first order, 1 minmod, 2 MC, 3 none */
 double orc_limiter_phi(int lim, double theta);
 /* eta' at a point by the gauge rule (bilinear over the 4 nearest centres) */

@@ -113,6 +113,9 @@ def _bind(L):
                                  ctypes.c_longlong, ctypes.c_longlong, ctypes.c_longlong]
     L.orc_update_phi_framed.argtypes = [ctypes.c_void_p]
     L.orc_set_mapping.argtypes = [ctypes.c_void_p, dp, dp]
+    L.orc_metric.argtypes = [ctypes.c_void_p, dp]
+    L.orc_edge_dflux_mapped_n.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, ctypes.c_int,
+                                          dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
     L.orc_boundary_flux.argtypes = [ctypes.c_void_p, dp]
     L.orc_edge_dflux.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_int, dp, dp,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -273,6 +276,15 @@ class OracleGrid:
         self._nodes = (xn, yn)
         _check(self.L.orc_set_mapping(self.h, _dp(xn), _dp(yn)), "set_mapping")
 
+    def metric(self):
+        """the mapped grid's metric planes [7][ny + 4][nx + 4] (frame
+        indices): capacity; unit normal (x, y) and length ratio of each
+        cell's left edge; the same for its bottom edge"""
+        g = self.grid
+        out = np.empty((7, g.ny + 4, g.nx + 4))
+        _check(self.L.orc_metric(self.h, _dp(out)), "metric")
+        return out
+
     def set_radial(self, on=True):
         """radially symmetric solutions (Appendix D): x is the radius and
         every step adds the geometric source terms"""
@@ -361,4 +373,17 @@ def edge_dflux_n(params, direction, qL, qR, bL, bR, c2L, c2R):
     rc = lib().orc_edge_dflux_n(ctypes.byref(p), int(direction), int(a[0].shape[0]),
                                 *[_dp(x) for x in a], _dp(df))
     _check(rc, "edge_dflux_n")
+    return df
+
+
+def edge_dflux_mapped_n(params, direction, qL, qR, bL, bR, c2L, c2R, nx, ny, gm):
+    """edge_dflux over mapped edges of unit normals (nx, ny) and length
+    ratios gm (direction 0: left edges, 1: bottom edges), in the global
+    frame; returns [n][7]"""
+    p = _params(params)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (qL, qR, bL, bR, c2L, c2R, nx, ny, gm)]
+    df = np.zeros((a[0].shape[0], 7))
+    rc = lib().orc_edge_dflux_mapped_n(ctypes.byref(p), int(direction), int(a[0].shape[0]),
+                                       *[_dp(x) for x in a], _dp(df))
+    _check(rc, "edge_dflux_mapped_n")
     return df

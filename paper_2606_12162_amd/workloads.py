@@ -480,6 +480,42 @@ def amr_small(n0=48, tiles=2, dx=500.0, depth=4000.0, amp=1.0, width=3e3,
     return AmrWorkload("amr_small_%d" % n0, params, dx, dx, bc, patches, gauges, steps, dt, amp)
 
 
+def nested_nodes(w: AmrWorkload, fmap):
+    """node coordinates of every patch of the patch set w under a mapping
+    fmap(xi, eta) -> (x, y) of the level-0 computational plane: the level-0
+    nodes (two ghost layers beyond the domain included) are fmap at the
+    level-0 node positions; a level-l node is the bilinear interpolant of the
+    four level-0 nodes around it, so that the nodes of each level are the
+    bilinear refinement of the coarser level's and the fine cells tile each
+    coarse cell exactly.  Returns [(xn, yn)] in patch order, each
+    [ny + 5][nx + 5] (nodes i = -2..nx+2, j = -2..ny+2)."""
+    lv0 = [p for p in w.patches if p.level == 0]
+    X0, Y0 = min(p.x0 for p in lv0), min(p.y0 for p in lv0)
+    NX = max(int(round((p.x0 - X0) / w.dx0)) + p.nx for p in lv0)
+    NY = max(int(round((p.y0 - Y0) / w.dy0)) + p.ny for p in lv0)
+    XI, ETA = np.meshgrid(X0 + np.arange(-2, NX + 3) * w.dx0, Y0 + np.arange(-2, NY + 3) * w.dy0)
+    nx0, ny0 = fmap(XI, ETA)
+    out = []
+    for p in w.patches:
+        r = RATIO ** p.level
+        I0 = int(round((p.x0 - X0) / (w.dx0 / r)))
+        J0 = int(round((p.y0 - Y0) / (w.dy0 / r)))
+        # level-0 node coordinates (in nodes from node -2) of the patch's nodes
+        fi = (I0 + np.arange(-2, p.nx + 3)) / r + 2.0
+        fj = (J0 + np.arange(-2, p.ny + 3)) / r + 2.0
+        ci = np.minimum(np.floor(fi).astype(int), NX + 3)
+        cj = np.minimum(np.floor(fj).astype(int), NY + 3)
+        ti, tj = fi - ci, fj - cj
+        CI, CJ = np.meshgrid(ci, cj)
+        TI, TJ = np.meshgrid(ti, tj)
+        res = []
+        for n in (nx0, ny0):
+            res.append((n[CJ, CI] * (1.0 - TI) + n[CJ, CI + 1] * TI) * (1.0 - TJ)
+                       + (n[CJ + 1, CI] * (1.0 - TI) + n[CJ + 1, CI + 1] * TI) * TJ)
+        out.append(tuple(res))
+    return out
+
+
 def amr_small_uniform(level, n0=48, dx=500.0, depth=4000.0, amp=1.0, width=3e3,
                       bc=(BC_WALL,) * 4, steps=6, rough=200.0, seed=11, cfl=0.9):
     """The basin of amr_small on one uniform grid at the spacing of `level`,

@@ -167,8 +167,9 @@ int hsgn_set_bathymetry(hsgn_ctx *c, int patch, const double *b, int on_device);
  * Errors: EINVAL (no such scenario, negative or non-finite width or rate). */
 int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rate);
 
-/* Mapped grid (Sec. 4, mapped grids): makes single-grid patch `patch` a
- * planar, logically rectangular mapped grid.  xn, yn (host, row-major,
+/* Mapped grid (Sec. 4, mapped grids): makes patch `patch` (a single grid or
+ * a patch of a patch set) a planar, logically rectangular mapped grid.  xn,
+ * yn (host, row-major,
  * [ny + 5][nx + 5], copied) are the coordinates of nodes (i, j) for
  * i = -2..nx+2, j = -2..ny+2 at [j + 2][i + 2], the two ghost layers
  * included; cell (i, j) has corners (i, j), (i+1, j), (i+1, j+1), (i, j+1)
@@ -181,12 +182,23 @@ int hsgn_set_sponge(hsgn_ctx *c, int scenario, const double width[4], double rat
  * in the physical frame; walls mirror the momentum about the wall edge.
  * Gauges and the sponge layer use computational coordinates.  Mass in
  * hsgn_diagnostics is sum(capacity h) dx dy.
+ * Patch sets: every patch of the set takes a mapping before the next
+ * hsgn_advance, or none does (else that call fails with HSGN_EINVAL).  The
+ * caller gives each patch the nodes of its frame; for the refluxing and
+ * averaging down to conserve the capacity-weighted mass, a finer patch's
+ * nodes must be the bilinear refinement of the coarser level's (its cells
+ * then tile each coarse cell exactly).  Ghost interpolation from the coarser
+ * level stays in index space; level-0 walls mirror the momentum about the
+ * wall edge; the coarse-fine flux records are solved in each fine edge's
+ * frame; refluxing divides by the coarse capacity, and averaging down takes
+ * sum(capacity q) / sum(capacity) over the 4 x 4 fine cells (the bathymetry
+ * likewise, recomputed at the next hsgn_advance).
  * After hsgn_finalize; may be called again to change the mapping.
- * The first mapping in a context drops a captured step graph (the step
- * launches switch to the mapped kernel).  HSGN_ENOTSUP: patch sets, or a
- * context with a sponge layer.  HSGN_EINVAL: bad patch, null pointers, or a
- * cell of non-positive area or an edge of zero length (the patch keeps its
- * previous geometry). */
+ * The first mapped single grid (patch-set patch) in a context drops a
+ * captured step graph: the single-grid (patch-set) step launches switch to
+ * the mapped kernel.  HSGN_ENOTSUP: a context with a sponge layer.
+ * HSGN_EINVAL: bad patch, null pointers, or a cell of non-positive area or an
+ * edge of zero length (the patch keeps its previous geometry). */
 int hsgn_set_mapping(hsgn_ctx *ctx, int patch, const double *xn, const double *yn);
 
 /* State q[7][ny][nx] (float64) of a patch, copied in or out: the conserved

@@ -33,11 +33,27 @@ __global__ void halo_copy_kernel(AmrBuffers<S> B, const GhostCopy *R, int n)
     const int cur = B.scen[D.scen].cur;          // same level: same slot as the source
     S *q = cur ? B.q1 : B.q0;
     uint8_t *mk = cur ? B.m1 : B.m0;
-    for (int m = 0; m < 7; m++) {
-        S v = q[Sp.qoff + m * Sp.plane + r.sl];
-        if ((m == IHU && (r.flips & 1)) || (m == IHV && (r.flips & 2))) v = -v;
-        q[D.qoff + m * D.plane + r.dl] = v;
+    S v[7];
+    for (int m = 0; m < 7; m++) v[m] = q[Sp.qoff + m * Sp.plane + r.sl];
+    if (r.flips && Sp.metric) {
+        // mapped: mirrored about the wall edge, the x wall first
+        const long long MP = (long long)Sp.pitch * (Sp.ny + 4), base = 2LL * Sp.pitch + 2;
+        double hu = (double)v[IHU], hv = (double)v[IHV];
+        if (r.flips & 1) {
+            const double *e = Sp.metric + base + r.wx;
+            reflect(hu, hv, e[MP], e[2 * MP]);
+        }
+        if (r.flips & 2) {
+            const double *e = Sp.metric + base + r.wy;
+            reflect(hu, hv, e[4 * MP], e[5 * MP]);
+        }
+        v[IHU] = (S)hu;
+        v[IHV] = (S)hv;
+    } else {
+        if (r.flips & 1) v[IHU] = -v[IHU];
+        if (r.flips & 2) v[IHV] = -v[IHV];
     }
+    for (int m = 0; m < 7; m++) q[D.qoff + m * D.plane + r.dl] = v[m];
     mk[D.coff + r.dl] = (uint8_t)(mk[Sp.coff + r.sl] & 3);
 }
 
@@ -132,10 +148,25 @@ __global__ void ghost_bath_kernel(AmrBuffers<S> B, const GhostCopy *Cp, int nc,
     }
 }
 
-// mean of the 4 x 4 fine cells (rows outer, columns inner).  bath_only with
-// keep (mixed storage, flag per coarse patch whose state is set): the
-// covered cell's stored eta' follows the new bottom so that its depth is
-// kept, as the FP64 storage of h keeps it
+// mean of the 4 x 4 fine cells (rows outer, columns inner); on a mapped
+// patch set sum(kap v) / sum(kap) in the same order.  bath_only with keep
+// (mixed storage, flag per coarse patch whose state is set): the covered
+// cell's stored eta' follows the new bottom so that its depth is kept, as
+// the FP64 storage of h keeps it
+template <class S>
+__device__ inline double fine_mean(const S *v, const PatchInfo &F, long long l, const double *kf,
+                                   double wsum)
+{
+    double s = 0.0;
+    for (int a = 0; a < AMR_RATIO; a++)
+        for (int c = 0; c < AMR_RATIO; c++) {
+            const long long o = (long long)a * F.pitch + c;
+            if (kf) s += kf[o] * (double)v[l + o];
+            else s += (double)v[l + o];
+        }
+    return kf ? s / wsum : s * 0.0625;
+}
+
 template <class S>
 __global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath_only,
                                const uint8_t *keep)
@@ -144,11 +175,14 @@ __global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath
     if (k >= n) return;
     const AvgRec r = R[k];
     const PatchInfo F = B.patches[r.fp], C = B.patches[r.cp];
-    if (bath_only) {
-        double s = 0.0;
+    // capacities of the fine cells (mapped), from the lower-left one
+    const double *kf = F.metric ? F.metric + 2LL * F.pitch + 2 + r.fl : nullptr;
+    double wsum = 0.0;
+    if (kf)
         for (int a = 0; a < AMR_RATIO; a++)
-            for (int c = 0; c < AMR_RATIO; c++) s += (double)B.bath[F.coff + r.fl + a * F.pitch + c];
-        const S bn = (S)(s * 0.0625);
+            for (int c = 0; c < AMR_RATIO; c++) wsum += kf[(long long)a * F.pitch + c];
+    if (bath_only) {
+        const S bn = (S)fine_mean(B.bath + F.coff, F, r.fl, kf, wsum);
         if (keep && keep[r.cp]) {
             S *qc = B.scen[C.scen].cur ? B.q1 : B.q0;
             const long long l = C.qoff + r.cl;
@@ -160,20 +194,15 @@ __global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath
     if (scen_failed(B.scen, C.scen) || scen_failed(B.scen, F.scen)) return;
     const S *qf = B.scen[F.scen].cur ? B.q1 : B.q0;
     S *qc = B.scen[C.scen].cur ? B.q1 : B.q0;
-    for (int m = 0; m < 7; m++) {
-        double s = 0.0;
-        for (int a = 0; a < AMR_RATIO; a++)
-            for (int c = 0; c < AMR_RATIO; c++)
-                s += (double)qf[F.qoff + m * F.plane + r.fl + a * F.pitch + c];
-        qc[C.qoff + m * C.plane + r.cl] = (S)(s * 0.0625);
-    }
+    for (int m = 0; m < 7; m++)
+        qc[C.qoff + m * C.plane + r.cl] = (S)fine_mean(qf + F.qoff + m * F.plane, F, r.fl, kf, wsum);
 }
 
 // one cell of the old state of a patch (the buffer the last step read), after
-// its first source half step, as an edge side in direction DIR
-template <int DIR, class S, bool MIXED>
-__device__ void old_side(const AmrBuffers<S> &B, const StepParams &P, const PatchInfo &pi, int l,
-                         Side<double> &sd)
+// its first source half step
+template <class S, bool MIXED>
+__device__ void old_cell(const AmrBuffers<S> &B, const StepParams &P, const PatchInfo &pi, int l,
+                         Cell<double> &c)
 {
     const ScenState &st = B.scen[pi.scen];
     const S *q = st.cur ? B.q0 : B.q1;            // after the swap: the other buffer
@@ -182,10 +211,8 @@ __device__ void old_side(const AmrBuffers<S> &B, const StepParams &P, const Patc
     for (int m = 0; m < 7; m++) raw.q[m] = (double)q[pi.qoff + m * pi.plane + l];
     raw.b = (double)B.bath[pi.coff + l];
     raw.mk = mk[pi.coff + l];
-    Cell<double> c;
     int phi, brk;
     prepare_cell<double, MIXED>(P, raw, 0.5 * st.dt, c, phi, brk);
-    side_of<DIR>(c, sd);
 }
 
 template <int DIR, class S, bool MIXED>
@@ -193,21 +220,40 @@ __device__ void edge_dflux(const AmrBuffers<S> &B, const StepParams &P, const Fl
                            double D[7])
 {
     const PatchInfo F = B.patches[r.fp], C = B.patches[r.cp];
+    Cell<double> cc, cg;
+    old_cell<S, MIXED>(B, P, C, r.cl, cc);
+    old_cell<S, MIXED>(B, P, F, r.gl, cg);
     Side<double> sc, sg;
-    old_side<DIR, S, MIXED>(B, P, C, r.cl, sc);
-    old_side<DIR, S, MIXED>(B, P, F, r.gl, sg);
     Waves<double> W;
     Eig<double> E;
     double am[7], ap[7];
-    if (r.low) {
-        riemann<DIR>(P, sc, sg, W, E);
-        fluctuations<DIR>(W, am, ap);
-        for (int m = 0; m < 7; m++) D[m] = am[m] + ap[m];
+    if (F.metric) {
+        // mapped: solved in the frame of the fine edge, the left (bottom)
+        // edge of the cell right of (above) the ghost on a low side and of
+        // the ghost itself on a high side; rotated back and scaled by the
+        // edge's length ratio
+        const long long MP = (long long)F.pitch * (F.ny + 4);
+        const long long el = r.gl + (r.low ? (DIR == 0 ? 1 : F.pitch) : 0);
+        const double *e = F.metric + 2LL * F.pitch + 2 + el;
+        const double nx = DIR == 0 ? e[MP] : e[4 * MP], ny = DIR == 0 ? e[2 * MP] : e[5 * MP];
+        const double gm = DIR == 0 ? e[3 * MP] : e[6 * MP];
+        const double tx = DIR == 0 ? 0.0 - ny : ny, ty = DIR == 0 ? nx : 0.0 - nx;
+        mapped_side(P, cc.q, cc.b, cc.c2, cc.eta, nx, ny, tx, ty, sc);
+        mapped_side(P, cg.q, cg.b, cg.c2, cg.eta, nx, ny, tx, ty, sg);
+        if (r.low) riemann<0>(P, sc, sg, W, E);
+        else riemann<0>(P, sg, sc, W, E);
+        set_frame(W, E, nx, ny, tx, ty, gm);
+        fluctuations<0>(W, am, ap);
+        to_global(W, am);
+        to_global(W, ap);
     } else {
-        riemann<DIR>(P, sg, sc, W, E);
+        side_of<DIR>(cc, sc);
+        side_of<DIR>(cg, sg);
+        if (r.low) riemann<DIR>(P, sc, sg, W, E);
+        else riemann<DIR>(P, sg, sc, W, E);
         fluctuations<DIR>(W, am, ap);
-        for (int m = 0; m < 7; m++) D[m] = -(am[m] + ap[m]);
     }
+    for (int m = 0; m < 7; m++) D[m] = r.low ? am[m] + ap[m] : -(am[m] + ap[m]);
 }
 
 template <class S, bool MIXED>
@@ -243,11 +289,15 @@ __global__ void reflux_kernel(AmrBuffers<S> B, StepParams P, const RefluxRec *R,
     for (int m = 0; m < 7; m++) v[m] = (double)q[C.qoff + m * C.plane + r.cl];
     if (MIXED) v[0] = (v[0] + P.eta0) - b;
     const double dtdx = st.dt / C.dx, dtdy = st.dt / C.dy;
+    // mapped: the records are fluxes times length ratios, divided here by the
+    // cell's capacity
+    const double kap = C.metric ? C.metric[2LL * C.pitch + 2 + r.cl] : 1.0;
     for (int e = 0; e < 4; e++) {
         if (r.fp[e] < 0) continue;
         const PatchInfo F = B.patches[r.fp[e]];
         const double *Rf = Rg + (F.eoff + r.e0[e]) * 7;
-        const double dtd = e < 2 ? dtdx : dtdy;
+        double dtd = e < 2 ? dtdx : dtdy;
+        if (C.metric) dtd = dtd / kap;
         for (int m = 0; m < 7; m++) {
             double s = ((Rf[m] + Rf[7 + m]) + Rf[14 + m]) + Rf[21 + m];
             double corr = dtd * (s * 0.0625);
@@ -257,7 +307,7 @@ __global__ void reflux_kernel(AmrBuffers<S> B, StepParams P, const RefluxRec *R,
     }
     double clip = 0.0;
     if (v[0] < 0.0) {
-        clip = -v[0] * C.dx * C.dy;
+        clip = C.metric ? -v[0] * kap * C.dx * C.dy : -v[0] * C.dx * C.dy;
         v[0] = 0.0;
     }
     if (v[0] <= P.dry_tol)

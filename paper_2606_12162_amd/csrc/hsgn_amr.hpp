@@ -22,6 +22,14 @@
 //   average-down covered coarse cells take the mean of their 4 x 4 cells.
 // The wave-propagation AMR of Berger and LeVeque, cited in Sec. 4, is the
 // model; the rules above are the precise form implemented.
+//
+// Mapped patch sets (Sec. 4, mapped grids; every patch has a metric): the
+// fine nodes are the bilinear refinement of the coarse ones (the caller's
+// rule), ghost interpolation stays in index space, a level-0 wall ghost
+// mirrors the momentum about the wall edge's unit normal, the flux records
+// take the total fluctuation solved in the fine edge's frame and scaled by
+// its length ratio, refluxing divides by the coarse capacity and averaging
+// down takes sum(kap q) / sum(kap) over the 4 x 4 fine cells.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +46,8 @@ struct GhostCopy {
     int dp, dl;          // destination patch, local
     int sp, sl;          // source patch, local
     int flips;           // bit 0: negate hu, bit 1: negate hv (walls)
+    int wx, wy;          // mapped walls: source-patch local of the cell whose
+                         // left (bit 0) / bottom (bit 1) edge is the wall
 };
 
 struct GhostInterp {

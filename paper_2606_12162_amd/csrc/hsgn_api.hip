@@ -478,7 +478,10 @@ struct hsgn_ctx {
     bool clsb_dirty = true;     // d_clsb to recompute (bathymetry or work table changed)
     bool split = false;         // mixed single grids: deep items without the FP64 edges
     bool any_sponge = false;    // some scenario has a sponge (step kernels with it)
-    bool any_mapped = false;    // some patch is mapped (the mapped step kernel)
+    bool any_mapped = false;    // some patch is mapped
+    bool mapped_single = false; // some single grid is mapped: the single-grid
+                                // launches take the mapped step kernel
+    bool mapped_amr = false;    // the same for the patch-set launches
     std::vector<double *> d_metric;   // per patch: its metric planes, or null
     ScenState *d_scen = nullptr;
     ScenStatic *d_sstat = nullptr;
@@ -596,7 +599,7 @@ static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath, int w0,
     A.lcnt = nullptr;
     A.clsb = nullptr;
     A.sponge = c->any_sponge ? 1 : 0;
-    A.mapped = c->any_mapped ? 1 : 0;
+    A.mapped = c->mapped_single ? 1 : 0;   // patch-set ranges: launch_march_range
     A.nwork = w1 - w0;
     return A;
 }
@@ -742,15 +745,24 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                     int mj = host_map((int)J, sh.NY, sh.bc[2], sh.bc[3], &fy);
                     int sp = idx[0].find(mi, mj);
                     if (sp < 0) { out.err = "level-0 patches leave a hole"; return; }
+                    // mapped walls: the domain edge of the source cell's row
+                    // (x) or column (y), as the left (bottom) edge of a cell
+                    // of the source patch's frame
+                    const PatchInfo &Sp = c->patches[sp];
+                    const long long wi = (I < 0 ? 0 : sh.NX) - c->pI0[sp];
+                    const long long wj = (J < 0 ? 0 : sh.NY) - c->pJ0[sp];
                     out.gc.push_back({pid, local_of(P, i, j), sp,
-                                      local_of(c->patches[sp], mi - c->pI0[sp], mj - c->pJ0[sp]),
-                                      fx | (fy << 1)});
+                                      local_of(Sp, mi - c->pI0[sp], mj - c->pJ0[sp]),
+                                      fx | (fy << 1),
+                                      fx ? local_of(Sp, wi, mj - c->pJ0[sp]) : 0,
+                                      fy ? local_of(Sp, mi - c->pI0[sp], wj) : 0});
                     continue;
                 }
                 int sp = idx[l].find(I, J);
                 if (sp >= 0) {
                     out.gc.push_back({pid, local_of(P, i, j), sp,
-                                      local_of(c->patches[sp], I - c->pI0[sp], J - c->pJ0[sp]), 0});
+                                      local_of(c->patches[sp], I - c->pI0[sp], J - c->pJ0[sp]), 0,
+                                      0, 0});
                     continue;
                 }
                 long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
@@ -935,9 +947,18 @@ static bool all_of_parallel(size_t n, F ok)
 static int validate_tables(hsgn_ctx *c)
 {
     auto bad = [&](const char *what) { return fail(c, HSGN_EINVAL, std::string("internal table check: ") + what); };
+    // a cell of a patch's frame (interior or ghost), for the wall edges
+    auto in_frame = [&](int pid, int local) {
+        const PatchInfo &p = c->patches[pid];
+        long long base = (long long)local + (long long)p.frame * p.pitch + p.frame;
+        if (base < 0) return false;
+        long long i = base % p.pitch - p.frame, j = base / p.pitch - p.frame;
+        return i >= -p.frame && i < p.nx + p.frame && j >= -p.frame && j < p.ny + p.frame;
+    };
     if (!all_of_parallel(c->h_gc.size(), [&](size_t k) {
             const GhostCopy &r = c->h_gc[k];
-            return local_ok(c, r.dp, r.dl, false) && local_ok(c, r.sp, r.sl, true);
+            return local_ok(c, r.dp, r.dl, false) && local_ok(c, r.sp, r.sl, true) &&
+                   (!(r.flips & 1) || in_frame(r.sp, r.wx)) && (!(r.flips & 2) || in_frame(r.sp, r.wy));
         }))
         return bad("ghost copy");
     if (!all_of_parallel(c->h_gi.size(), [&](size_t k) {
@@ -1454,6 +1475,14 @@ static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 static int ensure_prepared(hsgn_ctx *c)
 {
     if (!c->any_amr || !c->amr_dirty) return HSGN_OK;
+    // a patch set is mapped in every patch or in none
+    for (const ScenHost &sh : c->scen) {
+        if (!sh.amr) continue;
+        size_t nm = 0;
+        for (int pid : sh.patches) nm += c->patches[pid].metric ? 1 : 0;
+        if (nm != 0 && nm != sh.patches.size())
+            return fail(c, HSGN_EINVAL, "a patch set is mapped in every patch or in none");
+    }
     if (c->mixed)
         HIPCHK(c, hipMemcpy(c->d_keep, c->state_set.data(), c->state_set.size(),
                             hipMemcpyHostToDevice));
@@ -1579,8 +1608,6 @@ int hsgn_set_mapping(hsgn_ctx *c, int patch, const double *xn, const double *yn)
     if (rc) return rc;
     if (!xn || !yn) return fail(c, HSGN_EINVAL, "null node coordinates");
     PatchInfo &p = c->patches[patch];
-    if (p.frame != 0 || c->scen[p.scen].amr)
-        return fail(c, HSGN_ENOTSUP, "mapped grids are single grids (no patch sets)");
     if (c->any_sponge) return fail(c, HSGN_ENOTSUP, "mapped grids with a sponge layer");
     std::vector<double> m;
     if (!mapping_metric(p, xn, yn, m))
@@ -1593,10 +1620,14 @@ int hsgn_set_mapping(hsgn_ctx *c, int patch, const double *xn, const double *yn)
     HIPCHK(c, hipMemcpy(c->d_metric[patch], m.data(), sizeof(double) * m.size(),
                         hipMemcpyHostToDevice));
     p.metric = c->d_metric[patch];
-    // the first mapped patch switches every step launch to the mapped kernel;
-    // a step graph captured before holds the Cartesian one
-    if (!c->any_mapped) drop_graph(c);
+    // the first mapped patch of a kind switches its step launches to the
+    // mapped kernel; a step graph captured before holds the Cartesian one
+    bool &kind = p.frame != 0 ? c->mapped_amr : c->mapped_single;
+    if (!kind) drop_graph(c);
+    kind = true;
     c->any_mapped = true;
+    // a patch set averages its bathymetry down again, weighted by the capacities
+    if (p.frame != 0) c->amr_dirty = true;
     HIPCHK(c, hipMemcpy(c->d_patches, c->patches.data(), sizeof(PatchInfo) * c->patches.size(),
                         hipMemcpyHostToDevice));
     return HSGN_OK;
@@ -2019,11 +2050,14 @@ static void launch_march_range(hsgn_ctx *c, int w0, int wa, int w1, hipStream_t 
     if (w1 > wa) {
         if (c->mixed) {
             MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, wa, w1);
+            A.mapped = c->mapped_amr ? 1 : 0;
             split_args(c, A, wa);
             launch_mixed_split(c, A, (unsigned)(w1 - wa), c->d_cls + wa, true, s, fork);
-        } else
-            launch_march64_amr(march_args<double>(c, c->q0, c->q1, c->bath, wa, w1),
-                               (unsigned)(w1 - wa), s);
+        } else {
+            MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, wa, w1);
+            A.mapped = c->mapped_amr ? 1 : 0;
+            launch_march64_amr(A, (unsigned)(w1 - wa), s);
+        }
     }
 }
 
@@ -2340,6 +2374,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                     if (c->mixed) {
                         MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, n - na);
                         A.work = dwork + na; A.clip_slots = dclip + na;
+                        A.mapped = c->mapped_amr ? 1 : 0;
                         if (c->split) {
                             A.list = dlist + 2 * na;
                             A.lcnt = dlcnt;
@@ -2349,6 +2384,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                     } else {
                         MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, n - na);
                         A.work = dwork + na; A.clip_slots = dclip + na;
+                        A.mapped = c->mapped_amr ? 1 : 0;
                         launch_march64_amr(A, (unsigned)(n - na), c->stream);
                     }
                 }

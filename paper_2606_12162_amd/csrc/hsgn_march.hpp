@@ -48,7 +48,7 @@ struct PatchInfo {
     // domain size in cells)
     double sp_w[4], sp_rate;
     long long sp_i0, sp_j0, sp_nx, sp_ny;
-    // mapped grid (Sec. 4, mapped grids; single grids in FP64), else null:
+    // mapped grid (Sec. 4, mapped grids; single grids and patch sets), else null:
     // 7 planes of (ny + 4) x (nx + 4) values over the cells with their two
     // ghost layers, cell (i, j) at (j + 2) (nx + 4) + i + 2: capacity; unit
     // normal (x, y) and length ratio of the cell's left edge; the same for
@@ -458,9 +458,11 @@ HSGN_HD bool edge_solve(L &ln, const StepParams &P, const Side<T> &sl, const Sid
 //   left  A-dQ + F~ + F~tr,   right -(A+dQ - F~) + F~tr,
 //   below B-dQ + G~ + G~tr,   above -(B+dQ - G~) + G~tr
 // at entries j, ny + j, 2 ny + i, 2 ny + nx + i of the patch.
-// MAP: compiled for mapped grids (FP64 single grids): every edge is solved
-// in its own frame; a patch without a metric takes the identity frames,
-// unit ratios and capacities, which give the Cartesian results.
+// MAP: compiled for mapped grids: every edge is solved in its own frame; a
+// patch without a metric takes the identity frames, unit ratios and
+// capacities, which give the Cartesian results.  With AMR the boundary
+// records hold the mapped contributions (global frame, scaled by the edge's
+// length ratio).
 template <class L, class S, class T, bool MIXED, bool AMR, bool FB = true, bool SP = false,
           bool MAP = false>
 HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)

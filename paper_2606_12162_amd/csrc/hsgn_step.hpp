@@ -114,10 +114,10 @@ void march_kernel(MarchArgs<S> A)
     }
 }
 
-// the step on mapped grids (single grids; launched for the whole work table
-// when some patch is mapped), with the x-edge frames also kept in the LDS
-// ring; items and lists as in march_kernel
-template <class S, class T, bool MIXED, bool FB = true>
+// the step on mapped grids (launched for the whole work table when some
+// patch is mapped; AMR: the patches of patch sets), with the x-edge frames
+// also kept in the LDS ring; items and lists as in march_kernel
+template <class S, class T, bool MIXED, bool FB = true, bool AMR = false>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu((MIXED && !FB) ? 2 : 1, (MIXED && !FB) ? 2 : 1)))
 void march_kernel_mapped(MarchArgs<S> A)
@@ -128,14 +128,14 @@ void march_kernel_mapped(MarchArgs<S> A)
         const unsigned n = A.list ? A.lcnt[1] : (unsigned)A.nwork;
         for (unsigned b = blockIdx.x; b < n; b += gridDim.x) {     // uniform over the wavefront
             const int wid = A.list ? A.list[A.nwork + (int)b] : (int)b;
-            march<GpuLanes<T>, S, T, MIXED, false, FB, false, true>(ln, A, wid);
+            march<GpuLanes<T>, S, T, MIXED, AMR, FB, false, true>(ln, A, wid);
         }
     } else {
         const unsigned n = A.list ? A.lcnt[0] : (unsigned)A.nwork;
         int wid;
         if (!xcd_item(blockIdx.x, n, wid)) return;                 // uniform over the wavefront
         if (A.list) wid = A.list[wid];
-        march<GpuLanes<T>, S, T, MIXED, false, FB, false, true>(ln, A, wid);
+        march<GpuLanes<T>, S, T, MIXED, AMR, FB, false, true>(ln, A, wid);
     }
 }
 

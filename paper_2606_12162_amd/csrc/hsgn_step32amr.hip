@@ -14,7 +14,8 @@ constexpr unsigned FB_BLOCKS_AMR = 1024;
 void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream, bool beside)
 {
     const unsigned grid = A.list && beside && nwork > FB_BLOCKS_AMR ? FB_BLOCKS_AMR : nwork;
-    if (A.sponge) march_kernel<float, float, true, true, true, true><<<grid, 64, 0, stream>>>(A);
+    if (A.mapped) march_kernel_mapped<float, float, true, true, true><<<grid, 64, 0, stream>>>(A);
+    else if (A.sponge) march_kernel<float, float, true, true, true, true><<<grid, 64, 0, stream>>>(A);
     else march_kernel<float, float, true, true, true, false><<<grid, 64, 0, stream>>>(A);
 }
 
@@ -22,7 +23,8 @@ void launch_march32_amr(const MarchArgs<float> &A, unsigned nwork, hipStream_t s
 void launch_march32_amr_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t stream)
 {
     const unsigned grid = xcd_grid(nwork);
-    if (A.sponge) march_kernel<float, float, true, true, false, true><<<grid, 64, 0, stream>>>(A);
+    if (A.mapped) march_kernel_mapped<float, float, true, false, true><<<grid, 64, 0, stream>>>(A);
+    else if (A.sponge) march_kernel<float, float, true, true, false, true><<<grid, 64, 0, stream>>>(A);
     else march_kernel<float, float, true, true, false, false><<<grid, 64, 0, stream>>>(A);
 }
 

@@ -7,6 +7,7 @@ using namespace hsgn;
 void launch_march64_amr(const MarchArgs<double> &A, unsigned nwork, hipStream_t stream)
 {
     const unsigned grid = xcd_grid(nwork);
-    if (A.sponge) march_kernel<double, double, false, true, true, true><<<grid, 64, 0, stream>>>(A);
+    if (A.mapped) march_kernel_mapped<double, double, false, true, true><<<grid, 64, 0, stream>>>(A);
+    else if (A.sponge) march_kernel<double, double, false, true, true, true><<<grid, 64, 0, stream>>>(A);
     else march_kernel<double, double, false, true, true, false><<<grid, 64, 0, stream>>>(A);
 }

@@ -209,8 +209,9 @@ class Context:
         self._check(lib().hsgn_set_mask(self.h, patch, p, dev), "hsgn_set_mask")
 
     def set_mapping(self, patch, xn, yn):
-        """mapped single grid: node coordinates [ny + 5][nx + 5] of nodes
-        (i, j), i = -2..nx+2, j = -2..ny+2 (two ghost layers included)"""
+        """mapped grid or patch-set patch: node coordinates [ny + 5][nx + 5]
+        of nodes (i, j), i = -2..nx+2, j = -2..ny+2 (two ghost layers
+        included)"""
         xn = np.ascontiguousarray(xn, dtype=np.float64)
         yn = np.ascontiguousarray(yn, dtype=np.float64)
         nx, ny = ctypes.c_int(0), ctypes.c_int(0)
@@ -341,10 +342,13 @@ def advance_static(params, grid, b, q, dt, n_steps, stream=None, tile_rows=0):
     return done.value
 
 
-def from_amr_workloads(workloads, tile_rows=0, stream=None, gauges=True, precision=0):
+def from_amr_workloads(workloads, tile_rows=0, stream=None, gauges=True, precision=0,
+                       nodes=None):
     """A finalized context with one patch-set scenario per AMR workload
     (patches added in workload order), bathymetry, state, gauges and the
-    fixed level-0 step (scenario clock) set.  Returns (context, patch ids)."""
+    fixed level-0 step (scenario clock) set; nodes: per workload, None or the
+    (xn, yn) node coordinates of each of its patches (a mapped patch set).
+    Returns (context, patch ids)."""
     ws = list(workloads)
     for w in ws[1:]:
         if w.params != ws[0].params:
@@ -367,6 +371,9 @@ def from_amr_workloads(workloads, tile_rows=0, stream=None, gauges=True, precisi
         if gauges and w.gauges is not None and len(w.gauges):
             ctx.set_gauges(s, w.gauges)
         ctx.set_clock(s, 0.0, w.dt, 0)
+        if nodes is not None and nodes[s] is not None:
+            for pid, (xn, yn) in zip(ids[s], nodes[s]):
+                ctx.set_mapping(pid, xn, yn)
     return ctx, ids
 
 

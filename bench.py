@@ -111,21 +111,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# mapped-grid runs (--mapped): node coordinates per scenario, or None
+# mapped-grid runs (--mapped): node coordinates per scenario (patch sets:
+# per patch of the scenario), or None
 MAPPING = None
 
 
+def distortion(Lx, Ly, amp=0.005):
+    """a smooth distortion of the Lx x Ly computational plane: each point
+    moved by amp times the domain size along sine profiles (capacities
+    within about 10% of 1)"""
+    def f(XI, ETA):
+        X = XI + amp * Lx * np.sin(2 * np.pi * ETA / Ly) * np.cos(2 * np.pi * XI / Lx)
+        Y = ETA + amp * Ly * np.sin(2 * np.pi * XI / Lx) * np.sin(4 * np.pi * ETA / Ly)
+        return X, Y
+    return f
+
+
 def distorted_nodes(g, amp=0.005):
-    """nodes [ny + 5][nx + 5] (two ghost layers) of a smooth distortion of a
-    single grid: each node moved by amp times the domain size along smooth
-    sine profiles (capacities within about 10% of 1)"""
+    """nodes [ny + 5][nx + 5] (two ghost layers) of a single grid under
+    distortion()"""
     xi = g.x0 + np.arange(-2, g.nx + 3) * g.dx
     eta = g.y0 + np.arange(-2, g.ny + 3) * g.dy
     XI, ETA = np.meshgrid(xi, eta)
-    Lx, Ly = g.nx * g.dx, g.ny * g.dy
-    X = XI + amp * Lx * np.sin(2 * np.pi * ETA / Ly) * np.cos(2 * np.pi * XI / Lx)
-    Y = ETA + amp * Ly * np.sin(2 * np.pi * XI / Lx) * np.sin(4 * np.pi * ETA / Ly)
-    return X, Y
+    return distortion(g.nx * g.dx, g.ny * g.dy, amp)(XI, ETA)
+
+
+def distorted_patch_nodes(W, w, amp=0.005):
+    """nodes of every patch of patch set w under distortion() of its level-0
+    domain, finer levels by bilinear refinement (workloads.nested_nodes)"""
+    lv0 = [p for p in w.patches if p.level == 0]
+    Lx = max(p.x0 + p.nx * w.dx0 for p in lv0) - min(p.x0 for p in lv0)
+    Ly = max(p.y0 + p.ny * w.dy0 for p in lv0) - min(p.y0 for p in lv0)
+    return W.nested_nodes(w, distortion(Lx, Ly, amp))
 
 
 def make_context(H, ws, precision, tile_rows=0, gauges=True):
@@ -171,7 +188,7 @@ def run_amr(H, torch, ws, precision, steps, warmup, tile_rows=0, autotune=True):
     a second, untimed-by-the-clock pass of the same number of steps with
     direct launches times every step-kernel launch with HIP events"""
     ctx, _ = H.from_amr_workloads(ws, tile_rows=tile_rows,
-                                  precision=1 if precision == "mixed" else 0)
+                                  precision=1 if precision == "mixed" else 0, nodes=MAPPING)
     rows = ctx.autotune() if autotune and not tile_rows else [tile_rows or "library"]
     if warmup:
         ctx.advance(-1.0, warmup)
@@ -363,7 +380,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's tile-height model instead of its autotuner")
     ap.add_argument("--mapped", action="store_true",
-                    help="ensemble or ocean on smoothly distorted mapped grids (fixed steps 0.85x)")
+                    help="ensemble, ocean or amr on smoothly distorted mapped grids (fixed steps "
+                         "0.85x; amr: nested nodes on every level)")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--gauge-steps", type=int, default=-1,
                     help="steps of the untimed mixed-vs-FP64 leg (default: the workload's "
@@ -414,9 +432,9 @@ def main():
         precision = args.precision
     if args.mapped:
         global MAPPING
-        if amr or args.workload not in ("ensemble", "ocean"):
-            sys.exit("--mapped applies to the ensemble and ocean workloads")
-        MAPPING = [distorted_nodes(w.grid) for w in ws]
+        if args.workload not in ("ensemble", "ocean", "amr"):
+            sys.exit("--mapped applies to the ensemble, ocean and amr workloads")
+        MAPPING = [distorted_patch_nodes(W, w) if amr else distorted_nodes(w.grid) for w in ws]
         for w in ws:
             w.dt = 0.85 * w.dt
     if args.model == "mbhsgn":
@@ -522,7 +540,10 @@ def main():
         steps = args.cpu_steps or (40 if args.workload == "ensemble" else 20)
         # patch sets: the oracle on the level-0 ocean grid of the same set
         base = W.synthetic_ocean() if amr else ws[0]
-        out["cpu_baseline"] = cpu_baseline(base, steps, MAPPING[0] if MAPPING is not None else None)
+        nodes = None
+        if MAPPING is not None:
+            nodes = distorted_nodes(base.grid) if amr else MAPPING[0]
+        out["cpu_baseline"] = cpu_baseline(base, steps, nodes)
     print(json.dumps(out), flush=True)
 
 

@@ -153,36 +153,38 @@ __global__ void ghost_bath_kernel(AmrBuffers<S> B, const GhostCopy *Cp, int nc,
 // (mixed storage, flag per coarse patch whose state is set): the covered
 // cell's stored eta' follows the new bottom so that its depth is kept, as
 // the FP64 storage of h keeps it
-template <class S>
-__device__ inline double fine_mean(const S *v, const PatchInfo &F, long long l, const double *kf,
-                                   double wsum)
+template <bool MAPPED, class S>
+__device__ inline double fine_mean(const S *v, const PatchInfo &F, long long l,
+                                   const double (&kap)[AMR_RATIO * AMR_RATIO], double wsum)
 {
     double s = 0.0;
+#pragma unroll
     for (int a = 0; a < AMR_RATIO; a++)
+#pragma unroll
         for (int c = 0; c < AMR_RATIO; c++) {
-            const long long o = (long long)a * F.pitch + c;
-            if (kf) s += kf[o] * (double)v[l + o];
-            else s += (double)v[l + o];
+            const double x = (double)v[l + (long long)a * F.pitch + c];
+            if (MAPPED) s += kap[a * AMR_RATIO + c] * x;
+            else s += x;
         }
-    return kf ? s / wsum : s * 0.0625;
+    return MAPPED ? s / wsum : s * 0.0625;
 }
 
-template <class S>
-__global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath_only,
-                               const uint8_t *keep)
+template <bool MAPPED, class S>
+__device__ void avgdown_one(AmrBuffers<S> &B, const AvgRec &r, const PatchInfo &F,
+                            const PatchInfo &C, int bath_only, const uint8_t *keep)
 {
-    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (k >= n) return;
-    const AvgRec r = R[k];
-    const PatchInfo F = B.patches[r.fp], C = B.patches[r.cp];
-    // capacities of the fine cells (mapped), from the lower-left one
-    const double *kf = F.metric ? F.metric + 2LL * F.pitch + 2 + r.fl : nullptr;
-    double wsum = 0.0;
-    if (kf)
-        for (int a = 0; a < AMR_RATIO; a++)
-            for (int c = 0; c < AMR_RATIO; c++) wsum += kf[(long long)a * F.pitch + c];
+    // capacities of the 4 x 4 fine cells (mapped), read once
+    double kap[AMR_RATIO * AMR_RATIO], wsum = 0.0;
+#pragma unroll
+    for (int a = 0; a < AMR_RATIO; a++)
+#pragma unroll
+        for (int c = 0; c < AMR_RATIO; c++) {
+            kap[a * AMR_RATIO + c] =
+                MAPPED ? F.metric[2LL * F.pitch + 2 + r.fl + (long long)a * F.pitch + c] : 1.0;
+            wsum += kap[a * AMR_RATIO + c];
+        }
     if (bath_only) {
-        const S bn = (S)fine_mean(B.bath + F.coff, F, r.fl, kf, wsum);
+        const S bn = (S)fine_mean<MAPPED>(B.bath + F.coff, F, r.fl, kap, wsum);
         if (keep && keep[r.cp]) {
             S *qc = B.scen[C.scen].cur ? B.q1 : B.q0;
             const long long l = C.qoff + r.cl;
@@ -195,7 +197,20 @@ __global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath
     const S *qf = B.scen[F.scen].cur ? B.q1 : B.q0;
     S *qc = B.scen[C.scen].cur ? B.q1 : B.q0;
     for (int m = 0; m < 7; m++)
-        qc[C.qoff + m * C.plane + r.cl] = (S)fine_mean(qf + F.qoff + m * F.plane, F, r.fl, kf, wsum);
+        qc[C.qoff + m * C.plane + r.cl] =
+            (S)fine_mean<MAPPED>(qf + F.qoff + m * F.plane, F, r.fl, kap, wsum);
+}
+
+template <class S>
+__global__ void avgdown_kernel(AmrBuffers<S> B, const AvgRec *R, int n, int bath_only,
+                               const uint8_t *keep)
+{
+    int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const AvgRec r = R[k];
+    const PatchInfo F = B.patches[r.fp], C = B.patches[r.cp];
+    if (F.metric) avgdown_one<true>(B, r, F, C, bath_only, keep);
+    else avgdown_one<false>(B, r, F, C, bath_only, keep);
 }
 
 // one cell of the old state of a patch (the buffer the last step read), after

@@ -116,35 +116,6 @@ def log(*a):
 MAPPING = None
 
 
-def distortion(Lx, Ly, amp=0.005):
-    """a smooth distortion of the Lx x Ly computational plane: each point
-    moved by amp times the domain size along sine profiles (capacities
-    within about 10% of 1)"""
-    def f(XI, ETA):
-        X = XI + amp * Lx * np.sin(2 * np.pi * ETA / Ly) * np.cos(2 * np.pi * XI / Lx)
-        Y = ETA + amp * Ly * np.sin(2 * np.pi * XI / Lx) * np.sin(4 * np.pi * ETA / Ly)
-        return X, Y
-    return f
-
-
-def distorted_nodes(g, amp=0.005):
-    """nodes [ny + 5][nx + 5] (two ghost layers) of a single grid under
-    distortion()"""
-    xi = g.x0 + np.arange(-2, g.nx + 3) * g.dx
-    eta = g.y0 + np.arange(-2, g.ny + 3) * g.dy
-    XI, ETA = np.meshgrid(xi, eta)
-    return distortion(g.nx * g.dx, g.ny * g.dy, amp)(XI, ETA)
-
-
-def distorted_patch_nodes(W, w, amp=0.005):
-    """nodes of every patch of patch set w under distortion() of its level-0
-    domain, finer levels by bilinear refinement (workloads.nested_nodes)"""
-    lv0 = [p for p in w.patches if p.level == 0]
-    Lx = max(p.x0 + p.nx * w.dx0 for p in lv0) - min(p.x0 for p in lv0)
-    Ly = max(p.y0 + p.ny * w.dy0 for p in lv0) - min(p.y0 for p in lv0)
-    return W.nested_nodes(w, distortion(Lx, Ly, amp))
-
-
 def make_context(H, ws, precision, tile_rows=0, gauges=True):
     ctx = H.Context(ws[0].params, tile_rows=tile_rows, precision=1 if precision == "mixed" else 0)
     for s, w in enumerate(ws):
@@ -434,7 +405,7 @@ def main():
         global MAPPING
         if args.workload not in ("ensemble", "ocean", "amr"):
             sys.exit("--mapped applies to the ensemble, ocean and amr workloads")
-        MAPPING = [distorted_patch_nodes(W, w) if amr else distorted_nodes(w.grid) for w in ws]
+        MAPPING = [W.distorted_patch_nodes(w) if amr else W.distorted_nodes(w.grid) for w in ws]
         for w in ws:
             w.dt = 0.85 * w.dt
     if args.model == "mbhsgn":
@@ -542,7 +513,7 @@ def main():
         base = W.synthetic_ocean() if amr else ws[0]
         nodes = None
         if MAPPING is not None:
-            nodes = distorted_nodes(base.grid) if amr else MAPPING[0]
+            nodes = W.distorted_nodes(base.grid) if amr else MAPPING[0]
         out["cpu_baseline"] = cpu_baseline(base, steps, nodes)
     print(json.dumps(out), flush=True)
 

@@ -480,6 +480,35 @@ def amr_small(n0=48, tiles=2, dx=500.0, depth=4000.0, amp=1.0, width=3e3,
     return AmrWorkload("amr_small_%d" % n0, params, dx, dx, bc, patches, gauges, steps, dt, amp)
 
 
+def distortion(Lx, Ly, amp=0.005):
+    """a smooth distortion of an Lx x Ly computational plane: each point
+    moved by amp times the domain size along sine profiles (amp = 0.005:
+    capacities within about 10% of 1)"""
+    def f(XI, ETA):
+        X = XI + amp * Lx * np.sin(2 * np.pi * ETA / Ly) * np.cos(2 * np.pi * XI / Lx)
+        Y = ETA + amp * Ly * np.sin(2 * np.pi * XI / Lx) * np.sin(4 * np.pi * ETA / Ly)
+        return X, Y
+    return f
+
+
+def distorted_nodes(g: Grid, amp=0.005):
+    """nodes [ny + 5][nx + 5] (two ghost layers) of single grid g under
+    distortion() of its own domain"""
+    xi = g.x0 + np.arange(-2, g.nx + 3) * g.dx
+    eta = g.y0 + np.arange(-2, g.ny + 3) * g.dy
+    XI, ETA = np.meshgrid(xi, eta)
+    return distortion(g.nx * g.dx, g.ny * g.dy, amp)(XI, ETA)
+
+
+def distorted_patch_nodes(w: AmrWorkload, amp=0.005):
+    """nodes of every patch of patch set w under distortion() of its level-0
+    domain, finer levels by bilinear refinement (nested_nodes)"""
+    lv0 = [p for p in w.patches if p.level == 0]
+    Lx = max(p.x0 + p.nx * w.dx0 for p in lv0) - min(p.x0 for p in lv0)
+    Ly = max(p.y0 + p.ny * w.dy0 for p in lv0) - min(p.y0 for p in lv0)
+    return nested_nodes(w, distortion(Lx, Ly, amp))
+
+
 def nested_nodes(w: AmrWorkload, fmap):
     """node coordinates of every patch of the patch set w under a mapping
     fmap(xi, eta) -> (x, y) of the level-0 computational plane: the level-0

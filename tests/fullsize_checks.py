@@ -2,7 +2,7 @@
 suite (minutes of oracle time on the host); run on a GPU machine as
 
     python tests/fullsize_checks.py --case c5link [--steps 3000] [--out FILE]
-    python tests/fullsize_checks.py --case c4step [--out FILE]
+    python tests/fullsize_checks.py --case c4step [--mapped] [--out FILE]
 
 c5link: the smallest scenario of the 48-scenario ensemble (513^2 at its own
 spacing) advanced over the ensemble's full 3000 fixed steps by the HIP path
@@ -16,7 +16,10 @@ path, in the launch configuration of the benchmark (autotuned tiles, the
 step replayed from a HIP graph), and by the AMR oracle; every patch
 compared.  Most patches lie where the wave has not yet arrived, so their
 fields are round-off noise: errors there are taken relative to each field's
-largest magnitude over the whole patch set, not over the patch.
+largest magnitude over the whole patch set, not over the patch.  With
+--mapped the set lies on the smoothly distorted grid of
+workloads.distorted_patch_nodes (nested nodes on every level) and steps at
+0.85 of the Cartesian step, as in the benchmark's --mapped run.
 
 Bar: the FP64 parity bar (oracle/parity.py): every field within
 max(1e-11, 10 x the oracle's spread under one-ulp changes of the depths,
@@ -43,9 +46,14 @@ from paper_2606_12162_amd import workloads as W                   # noqa: E402
 
 def c4step(args):
     w = W.amr_ocean()
-    print("case", w.name, len(w.patches), "patches, one level-0 step", flush=True)
+    nodes = None
+    if args.mapped:
+        nodes = W.distorted_patch_nodes(w)
+        w.dt = 0.85 * w.dt
+    print("case", w.name, "mapped" if nodes else "", len(w.patches), "patches, one level-0 step",
+          flush=True)
     t0 = time.perf_counter()
-    ctx, ids = H.from_amr_workloads([w], precision=0)
+    ctx, ids = H.from_amr_workloads([w], precision=0, nodes=None if nodes is None else [nodes])
     ctx.autotune()
     ctx.advance(-1.0, 1)
     got = [ctx.get_state(pid) for pid in ids[0]]
@@ -57,7 +65,7 @@ def c4step(args):
     runs = []
 
     def run(x):
-        o = A.from_workload(x)
+        o = A.from_workload(x, nodes=nodes)
         o.advance(x.dt, 1)
         runs.append(o)
         print("oracle run done", flush=True)
@@ -77,7 +85,8 @@ def c4step(args):
     masks_ok = all(np.array_equal(masks[k], o.get_mask(k)) for k in range(len(w.patches)))
     dm = abs(mass - o.mass()) / o.mass()
     ok = bool(np.all(err <= bar)) and masks_ok and dm <= 1e-13
-    return {"case": w.name, "patches": len(w.patches), "level0_steps": 1,
+    return {"case": w.name + ("_mapped" if nodes else ""), "patches": len(w.patches),
+            "level0_steps": 1,
             "field_scale": scale.tolist(), "field_errors": err.tolist(), "bars": bar.tolist(),
             "masks_equal": masks_ok, "mass_rel_diff": dm, "gpu_s": t_gpu,
             "oracle_s_two_runs": t_orc, "pass": ok}
@@ -132,6 +141,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--case", required=True, choices=["c5link", "c4step"])
     ap.add_argument("--steps", type=int, default=3000, help="c5link: fixed steps")
+    ap.add_argument("--mapped", action="store_true", help="c4step: on the distorted mapped grid")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     import torch

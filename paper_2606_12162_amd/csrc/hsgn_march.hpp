@@ -838,21 +838,38 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             }
             // fix-ups: clipping (the clipped mass summed in FP64), dry cells,
             // breaking latch (eta - eta0 > kappa H), SWE cells.  FP64: on h
-            // as the oracle does; mixed precision: in FP32 on the stored
-            // deviation eta' directly.
+            // as the oracle does; mixed precision: on the stored deviation
+            // eta' directly, in FP64 for SWE cells (phi_T = 0 or breaking:
+            // every dry and shallow cell, whose edges are solved in FP64 too)
+            // and in FP32 for the others.  The kernel without the FP64 edge
+            // solve (FB false) holds no SWE cell.
             S out0;
             S qs[7];
             bool bad;
             if constexpr (MIXED) {
                 T eta = acc[sk2][IH];
-                T h = eta + (T)P.eta0 - bb;
-                if (h < (T)0) {
-                    clip += MAP ? -(double)h * (double)kap_w[sk2] * pi.dx * pi.dy
-                                : -(double)h * pi.dx * pi.dy;
-                    h = (T)0;
-                    eta = bb - (T)P.eta0;
+                bool dry;
+                if (FB && swe) {
+                    double etaD = (double)eta;
+                    const double bD = (double)bb;
+                    const double hD = (etaD + P.eta0) - bD;
+                    if (hD < 0.0) {
+                        clip += MAP ? -hD * (double)kap_w[sk2] * pi.dx * pi.dy
+                                    : -hD * pi.dx * pi.dy;
+                        etaD = bD - P.eta0;
+                    }
+                    dry = !(hD > P.dry_tol);
+                    eta = (T)etaD;
+                } else {
+                    T h = eta + (T)P.eta0 - bb;
+                    if (h < (T)0) {
+                        clip += MAP ? -(double)h * (double)kap_w[sk2] * pi.dx * pi.dy
+                                    : -(double)h * pi.dx * pi.dy;
+                        h = (T)0;
+                        eta = bb - (T)P.eta0;
+                    }
+                    dry = !(h > (T)P.dry_tol);
                 }
-                const bool dry = !(h > (T)P.dry_tol);
                 if (dry) {
                     HSGN_UNROLL
                     for (int m = 1; m < 7; m++) qn[m] = (T)0;

@@ -454,6 +454,7 @@ struct hsgn_ctx {
     std::vector<int> pI0, pJ0;             // patch origin in cells of its level (patch sets)
     std::vector<ScenHost> scen;
     std::vector<WorkItem> work;
+    std::vector<PackedItem> packs;            // strips of the packed items
     std::vector<ScenStatic> sstat;
     int nslot = 0, nlev = 1;
     bool any_amr = false;
@@ -469,6 +470,7 @@ struct hsgn_ctx {
     uint8_t *m0 = nullptr, *m1 = nullptr;
     PatchInfo *d_patches = nullptr;
     WorkItem *d_work = nullptr;
+    PackedItem *d_packs = nullptr;
     int *d_list = nullptr;      // item lists of the split mixed step (2 per item)
     unsigned *d_lcnt = nullptr; // their lengths
     int *d_cls = nullptr;       // the items' classes for the attempt
@@ -477,6 +479,7 @@ struct hsgn_ctx {
     int *d_clsb = nullptr;      // their bottom part
     bool clsb_dirty = true;     // d_clsb to recompute (bathymetry or work table changed)
     bool split = false;         // mixed single grids: deep items without the FP64 edges
+    bool pack = true;           // patch sets: narrow strips packed into shared wavefronts
     bool any_sponge = false;    // some scenario has a sponge (step kernels with it)
     bool any_mapped = false;    // some patch is mapped
     bool mapped_single = false; // some single grid is mapped: the single-grid
@@ -562,7 +565,7 @@ static void free_device(hsgn_ctx *c)
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
                     c->d_mass, c->f0, c->f1, c->fbath, c->stage, c->d_cnt, c->d_gc, c->d_gi,
                     c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip, c->d_list,
-                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep, c->d_B0};
+                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep, c->d_B0, c->d_packs};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *m : c->d_metric)
@@ -578,6 +581,7 @@ static void free_device(hsgn_ctx *c)
     c->d_list = c->d_clsb = c->d_cls = nullptr;
     c->d_keep = nullptr;
     c->d_B0 = nullptr;
+    c->d_packs = nullptr;
     c->b0_scen = -1;
     c->d_lcnt = nullptr;
 }
@@ -589,6 +593,7 @@ static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath, int w0,
     A.P = c->P;
     A.patches = c->d_patches;
     A.work = c->d_work + w0;
+    A.packs = c->d_packs;
     A.q0 = q0; A.q1 = q1;
     A.bath = bath;
     A.m0 = c->m0; A.m1 = c->m1;
@@ -1065,6 +1070,10 @@ int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out)
     // diagnostic: results are the same bit for bit)
     const char *nosplit = getenv("HSGN_NO_KERNEL_SPLIT");
     c->split = c->mixed && !(nosplit && nosplit[0] == '1');
+    // HSGN_NO_PACKING=1 gives every strip of a patch set its own wavefront (a
+    // diagnostic: the state is the same bit for bit)
+    const char *nopack = getenv("HSGN_NO_PACKING");
+    c->pack = !(nopack && nopack[0] == '1');
     c->stream = (hipStream_t)hip_stream;
     c->P = step_params(p);
     *out = c;
@@ -1130,11 +1139,103 @@ static int choose_rows(const hsgn_ctx *c, int level)
 // level 0 the single grids come before the patch sets (they use different
 // kernel instantiations); fills each slot's work range and each level's
 // ranges
+// narrow strips of one clock slot packed into items of 64 lanes (2 + w + 2
+// each, at most PACK_SEGS per item): best fit decreasing, per tile height.
+// The strips are sorted by tile height and width (descending, stable) and
+// each goes to the open item with the least room that holds it (the last
+// opened of those), else to a new one.  An item left with one strip stays a
+// plain item.
+struct PackUnit {
+    int pid, i0, r0, th, lanes;
+};
+
+static void pack_units(std::vector<PackUnit> &u, std::vector<WorkItem> &work,
+                       std::vector<PackedItem> &packs)
+{
+    std::stable_sort(u.begin(), u.end(), [](const PackUnit &a, const PackUnit &b) {
+        return a.th != b.th ? a.th > b.th : a.lanes > b.lanes;
+    });
+    size_t i = 0;
+    while (i < u.size()) {
+        size_t j = i;
+        while (j < u.size() && u[j].th == u[i].th) j++;
+        std::vector<PackedItem> bins;
+        std::vector<int> used;
+        std::vector<std::vector<int>> byroom(65);     // open items by lanes left
+        for (size_t k = i; k < j; k++) {
+            const int L = u[k].lanes;
+            int b = -1;
+            for (int r = L; r <= 64 && b < 0; r++)
+                if (!byroom[r].empty()) {
+                    b = byroom[r].back();
+                    byroom[r].pop_back();
+                }
+            if (b < 0) {
+                b = (int)bins.size();
+                bins.push_back(PackedItem{});
+                used.push_back(0);
+            }
+            PackedItem &pk = bins[b];
+            const int g = pk.nseg++;
+            pk.patch[g] = u[k].pid; pk.i0[g] = u[k].i0; pk.r0[g] = u[k].r0; pk.th[g] = u[k].th;
+            pk.l0[g] = used[b];
+            used[b] += L;
+            if (pk.nseg < PACK_SEGS && 64 - used[b] >= 5) byroom[64 - used[b]].push_back(b);
+        }
+        for (const PackedItem &pk : bins) {
+            if (pk.nseg == 1) {
+                work.push_back({pk.patch[0], pk.i0[0], pk.r0[0], pk.th[0]});
+            } else {
+                packs.push_back(pk);
+                work.push_back({-1 - (int)(packs.size() - 1), 0, 0, pk.th[0]});
+            }
+        }
+        i = j;
+    }
+}
+
+// every packed item: 2..PACK_SEGS strips of patch-set patches of one clock
+// slot, each narrower than 60 columns and inside its patch, laid on
+// consecutive lanes within the 64, its tile height the item's (checked on
+// the host before the table reaches the device)
+static bool packs_ok(const hsgn_ctx *c, const std::vector<WorkItem> &work,
+                     const std::vector<PackedItem> &packs)
+{
+    if (!packs.empty() && c->mixed && c->mapped_amr) return false;
+    std::vector<char> seen(packs.size(), 0);
+    for (const WorkItem &w : work) {
+        if (w.patch >= 0) continue;
+        const long long q = -1LL - w.patch;
+        if (q >= (long long)packs.size() || seen[(size_t)q]) return false;
+        seen[(size_t)q] = 1;
+        const PackedItem &pk = packs[(size_t)q];
+        if (pk.nseg < 2 || pk.nseg > PACK_SEGS) return false;
+        int lane = 0, slot = -1;
+        for (int g = 0; g < pk.nseg; g++) {
+            if (pk.patch[g] < 0 || pk.patch[g] >= (int)c->patches.size()) return false;
+            const PatchInfo &p = c->patches[pk.patch[g]];
+            if (p.frame == 0 || (slot >= 0 && p.scen != slot)) return false;
+            slot = p.scen;
+            const int wdt = p.nx - pk.i0[g];
+            if (pk.i0[g] < 0 || wdt < 1 || wdt >= 60) return false;
+            if (pk.r0[g] < 0 || pk.th[g] != w.th || pk.r0[g] + pk.th[g] > p.ny) return false;
+            if (pk.l0[g] != lane) return false;
+            lane += wdt + 4;
+        }
+        if (lane > 64) return false;
+    }
+    for (char x : seen)
+        if (!x) return false;
+    return true;
+}
+
 static void build_work(const hsgn_ctx *c, const std::vector<int> &th, std::vector<WorkItem> &work,
-                       std::vector<ScenStatic> &sstat, std::vector<LevelRange> &L)
+                       std::vector<PackedItem> &packs, std::vector<ScenStatic> &sstat,
+                       std::vector<LevelRange> &L)
 {
     const int nscen = (int)c->scen.size();
     work.clear();
+    packs.clear();
     sstat.assign(c->nslot, ScenStatic());
     auto add_slot_work = [&](int slot) {
         int s = c->slot_scen[slot], l = c->slot_level[slot];
@@ -1146,12 +1247,22 @@ static void build_work(const hsgn_ctx *c, const std::vector<int> &th, std::vecto
         ss.cfl_max = c->prm.cfl_max;
         ss.w0 = (int)work.size();
         const int t = th[l];
+        // patch sets: strips narrower than 60 columns are packed (below),
+        // except on mapped patch sets in mixed precision, whose kernel
+        // without the FP64 edge solve keeps the patch data uniform (read per
+        // lane, it would not fit in its registers)
+        const bool packable = c->pack && c->scen[s].amr && !(c->mixed && c->mapped_amr);
+        std::vector<PackUnit> units;
         for (int pid : c->scen[s].lev[l]) {
             const PatchInfo &p = c->patches[pid];
             for (int r0 = 0; r0 < p.ny; r0 += t)
-                for (int i0 = 0; i0 < p.nx; i0 += 60)
-                    work.push_back({pid, i0, r0, std::min(t, p.ny - r0)});
+                for (int i0 = 0; i0 < p.nx; i0 += 60) {
+                    const int h = std::min(t, p.ny - r0), w = std::min(60, p.nx - i0);
+                    if (packable && w < 60) units.push_back({pid, i0, r0, h, w + 4});
+                    else work.push_back({pid, i0, r0, h});
+                }
         }
+        if (!units.empty()) pack_units(units, work, packs);
         ss.w1 = (int)work.size();
     };
     L[0].w0 = 0;
@@ -1174,6 +1285,62 @@ static void build_work(const hsgn_ctx *c, const std::vector<int> &th, std::vecto
             }
         L[l].w1 = (int)work.size();
     }
+}
+
+// a new work table (tile heights th) in place of the context's: device
+// buffers grown where it is larger, uploaded, the split's bottom classes
+// marked for recomputation and a captured step graph dropped
+static int install_work(hsgn_ctx *c, const std::vector<int> &th)
+{
+    std::vector<WorkItem> work;
+    std::vector<PackedItem> packs;
+    std::vector<ScenStatic> sstat;
+    std::vector<LevelRange> L2 = c->L;
+    build_work(c, th, work, packs, sstat, L2);
+    if (!packs_ok(c, work, packs)) return fail(c, HSGN_EINVAL, "internal table check: packed items");
+    if (packs.size() > c->packs.size()) {
+        PackedItem *np = nullptr;
+        HIPCHK(c, hipMalloc(&np, sizeof(PackedItem) * packs.size()));
+        (void)hipFree(c->d_packs);
+        c->d_packs = np;
+    }
+    if (!packs.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_packs, packs.data(), sizeof(PackedItem) * packs.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+    if (work.size() > c->work.size()) {
+        WorkItem *nw = nullptr;
+        double *nc = nullptr;
+        int *nlist = nullptr, *nclsb = nullptr, *ncls = nullptr;
+        HIPCHK(c, hipMalloc(&nw, sizeof(WorkItem) * work.size()));
+        HIPCHK(c, hipMalloc(&nc, sizeof(double) * work.size()));
+        HIPCHK(c, hipMalloc(&nlist, sizeof(int) * 2 * work.size()));
+        HIPCHK(c, hipMalloc(&ncls, sizeof(int) * work.size()));
+        HIPCHK(c, hipMalloc(&nclsb, sizeof(int) * work.size()));
+        (void)hipFree(c->d_work);
+        (void)hipFree(c->clip);
+        (void)hipFree(c->d_list);
+        (void)hipFree(c->d_cls);
+        (void)hipFree(c->d_clsb);
+        c->d_work = nw;
+        c->clip = nc;
+        c->d_list = nlist;
+        c->d_cls = ncls;
+        c->d_clsb = nclsb;
+    }
+    HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * work.size(), c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_work, work.data(), sizeof(WorkItem) * work.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_sstat, sstat.data(), sizeof(ScenStatic) * sstat.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->work = work;
+    c->packs = packs;
+    c->sstat = sstat;
+    c->L = L2;
+    c->th_level = th;
+    c->clsb_dirty = true;
+    drop_graph(c);
+    return HSGN_OK;
 }
 
 // geometry checks of the scenarios and level structure
@@ -1307,7 +1474,9 @@ int hsgn_finalize(hsgn_ctx *c)
     c->slot_level = slot_level;
     c->th_level.assign(c->nlev, 0);
     for (int l = 0; l < c->nlev; l++) c->th_level[l] = choose_rows(c, l);
-    build_work(c, c->th_level, c->work, c->sstat, c->L);
+    build_work(c, c->th_level, c->work, c->packs, c->sstat, c->L);
+    if (!packs_ok(c, c->work, c->packs))
+        return fail(c, HSGN_EINVAL, "internal table check: packed items");
     // patch-set tables, grouped by level
     {
         std::vector<std::vector<PatchRecs>> recs(c->nlev);
@@ -1384,6 +1553,7 @@ int hsgn_finalize(hsgn_ctx *c)
     HIPCHK(c, hipMalloc(&c->d_keep, c->patches.size()));
     c->state_set.assign(c->patches.size(), 0);
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(WorkItem) * c->work.size()));
+    HIPCHK(c, hipMalloc(&c->d_packs, sizeof(PackedItem) * std::max<size_t>(c->packs.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_list, sizeof(int) * 2 * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_lcnt, sizeof(unsigned) * 2));
     HIPCHK(c, hipMalloc(&c->d_cls, sizeof(int) * std::max<size_t>(c->work.size(), 1)));
@@ -1422,6 +1592,9 @@ int hsgn_finalize(hsgn_ctx *c)
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_work, c->work.data(), sizeof(WorkItem) * c->work.size(),
                              hipMemcpyHostToDevice, c->stream));
+    if (!c->packs.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_packs, c->packs.data(), sizeof(PackedItem) * c->packs.size(),
+                                 hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_sstat, c->sstat.data(), sizeof(ScenStatic) * c->nslot,
                              hipMemcpyHostToDevice, c->stream));
     std::vector<ScenState> st(c->nslot);
@@ -1626,6 +1799,11 @@ int hsgn_set_mapping(hsgn_ctx *c, int patch, const double *xn, const double *yn)
     if (!kind) drop_graph(c);
     kind = true;
     c->any_mapped = true;
+    // mixed precision: the mapped patch-set kernels take no packed items
+    if (p.frame != 0 && c->mixed && !c->packs.empty()) {
+        int rc2 = install_work(c, c->th_level);
+        if (rc2) return rc2;
+    }
     // a patch set averages its bathymetry down again, weighted by the capacities
     if (p.frame != 0) c->amr_dirty = true;
     HIPCHK(c, hipMemcpy(c->d_patches, c->patches.data(), sizeof(PatchInfo) * c->patches.size(),
@@ -2287,19 +2465,30 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
     }
     if ((rc = push_scen(c, st))) return rc;
     static const int cand[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64};
-    // scratch work table and clip slots for the largest candidate table
-    std::vector<int> th8(c->nlev, 8);
+    // scratch work table, packed items and clip slots for the largest
+    // candidate table
     std::vector<WorkItem> wk;
+    std::vector<PackedItem> pk;
     std::vector<ScenStatic> ss;
     std::vector<LevelRange> L = c->L;
-    build_work(c, th8, wk, ss, L);
+    size_t wmax = 1, pmax = 1;
+    for (int l = 0; l < c->nlev; l++)
+        for (int th : cand) {
+            std::vector<int> thl = c->th_level;
+            thl[l] = th;
+            build_work(c, thl, wk, pk, ss, L);
+            wmax = std::max(wmax, wk.size());
+            pmax = std::max(pmax, pk.size());
+        }
     WorkItem *dwork = nullptr;
+    PackedItem *dpacks = nullptr;
     double *dclip = nullptr;
     int *dlist = nullptr, *dclsb = nullptr, *dcls = nullptr;
     unsigned *dlcnt = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&]() {
         if (dwork) (void)hipFree(dwork);
+        if (dpacks) (void)hipFree(dpacks);
         if (dclip) (void)hipFree(dclip);
         if (dlist) (void)hipFree(dlist);
         if (dlcnt) (void)hipFree(dlcnt);
@@ -2308,12 +2497,13 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
-    if (hipMalloc(&dwork, sizeof(WorkItem) * wk.size()) != hipSuccess ||
-        hipMalloc(&dclip, sizeof(double) * wk.size()) != hipSuccess ||
-        hipMalloc(&dlist, sizeof(int) * 2 * wk.size()) != hipSuccess ||
+    if (hipMalloc(&dwork, sizeof(WorkItem) * wmax) != hipSuccess ||
+        hipMalloc(&dpacks, sizeof(PackedItem) * pmax) != hipSuccess ||
+        hipMalloc(&dclip, sizeof(double) * wmax) != hipSuccess ||
+        hipMalloc(&dlist, sizeof(int) * 2 * wmax) != hipSuccess ||
         hipMalloc(&dlcnt, sizeof(unsigned) * 2) != hipSuccess ||
-        hipMalloc(&dcls, sizeof(int) * wk.size()) != hipSuccess ||
-        hipMalloc(&dclsb, sizeof(int) * wk.size()) != hipSuccess ||
+        hipMalloc(&dcls, sizeof(int) * wmax) != hipSuccess ||
+        hipMalloc(&dclsb, sizeof(int) * wmax) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         cleanup();
         return fail(c, HSGN_ENOMEM, "autotune scratch");
@@ -2343,12 +2533,18 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
             prev = th;
             std::vector<int> thl = c->th_level;
             thl[l] = th;
-            build_work(c, thl, wk, ss, L);
+            build_work(c, thl, wk, pk, ss, L);
             const LevelRange &Q = L[l];
             int n = Q.w1 - Q.w0;
             if (n <= 0) continue;
+            if (!packs_ok(c, wk, pk)) {
+                cleanup();
+                return fail(c, HSGN_EINVAL, "internal table check: packed items");
+            }
             if (hipMemcpyAsync(dwork, wk.data() + Q.w0, sizeof(WorkItem) * n, hipMemcpyHostToDevice,
-                               c->stream) != hipSuccess) {
+                               c->stream) != hipSuccess ||
+                (!pk.empty() && hipMemcpyAsync(dpacks, pk.data(), sizeof(PackedItem) * pk.size(),
+                                               hipMemcpyHostToDevice, c->stream) != hipSuccess)) {
                 cleanup();
                 return fail(c, HSGN_EDEVICE, "autotune upload");
             }
@@ -2357,7 +2553,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                 if (na > 0) {
                     if (c->mixed) {
                         MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, na);
-                        A.work = dwork; A.clip_slots = dclip;
+                        A.work = dwork; A.packs = dpacks; A.clip_slots = dclip;
                         if (c->split) {
                             A.list = dlist;
                             A.lcnt = dlcnt;
@@ -2366,14 +2562,14 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                         launch_mixed_split(c, A, (unsigned)na, dcls, false, c->stream, true);
                     } else {
                         MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, na);
-                        A.work = dwork; A.clip_slots = dclip;
+                        A.work = dwork; A.packs = dpacks; A.clip_slots = dclip;
                         launch_march64(A, (unsigned)na, c->stream);
                     }
                 }
                 if (n > na) {
                     if (c->mixed) {
                         MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, n - na);
-                        A.work = dwork + na; A.clip_slots = dclip + na;
+                        A.work = dwork + na; A.packs = dpacks; A.clip_slots = dclip + na;
                         A.mapped = c->mapped_amr ? 1 : 0;
                         if (c->split) {
                             A.list = dlist + 2 * na;
@@ -2383,7 +2579,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
                         launch_mixed_split(c, A, (unsigned)(n - na), dcls + na, true, c->stream, true);
                     } else {
                         MarchArgs<double> A = march_args<double>(c, c->q0, c->q1, c->bath, 0, n - na);
-                        A.work = dwork + na; A.clip_slots = dclip + na;
+                        A.work = dwork + na; A.packs = dpacks; A.clip_slots = dclip + na;
                         A.mapped = c->mapped_amr ? 1 : 0;
                         launch_march64_amr(A, (unsigned)(n - na), c->stream);
                     }
@@ -2397,6 +2593,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
             if (n > na && c->split) {
                 MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, 0, n - na);
                 A.work = dwork + na;
+                A.packs = dpacks;
                 launch_static_class32_amr(A, (unsigned)(n - na), dclsb + na, c->stream);
             }
             launch();                                   // warm-up
@@ -2416,42 +2613,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
     HIPCHK(c, hipGetLastError());
     if ((rc = push_scen(c, saved))) return rc;
     // the chosen tile heights
-    std::vector<WorkItem> work;
-    std::vector<ScenStatic> sstat;
-    std::vector<LevelRange> L2 = c->L;
-    build_work(c, best, work, sstat, L2);
-    if (work.size() > c->work.size()) {
-        WorkItem *nw = nullptr;
-        double *nc = nullptr;
-        int *nlist = nullptr, *nclsb = nullptr, *ncls = nullptr;
-        HIPCHK(c, hipMalloc(&nw, sizeof(WorkItem) * work.size()));
-        HIPCHK(c, hipMalloc(&nc, sizeof(double) * work.size()));
-        HIPCHK(c, hipMalloc(&nlist, sizeof(int) * 2 * work.size()));
-        HIPCHK(c, hipMalloc(&ncls, sizeof(int) * work.size()));
-        HIPCHK(c, hipMalloc(&nclsb, sizeof(int) * work.size()));
-        (void)hipFree(c->d_work);
-        (void)hipFree(c->clip);
-        (void)hipFree(c->d_list);
-        (void)hipFree(c->d_cls);
-        (void)hipFree(c->d_clsb);
-        c->d_work = nw;
-        c->clip = nc;
-        c->d_list = nlist;
-        c->d_cls = ncls;
-        c->d_clsb = nclsb;
-    }
-    HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * work.size(), c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_work, work.data(), sizeof(WorkItem) * work.size(),
-                             hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_sstat, sstat.data(), sizeof(ScenStatic) * sstat.size(),
-                             hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->work = work;
-    c->sstat = sstat;
-    c->L = L2;
-    c->th_level = best;
-    c->clsb_dirty = true;
-    drop_graph(c);
+    if ((rc = install_work(c, best))) return rc;
     if (rows)
         for (int l = 0; l < c->nlev; l++) rows[l] = best[l];
     return HSGN_OK;
@@ -2750,6 +2912,7 @@ int hsgn_advance_static(const hsgn_params *p, void *hip_stream, int nx, int ny, 
     A.P = step_params(p);
     A.patches = dp;
     A.work = work;
+    A.packs = nullptr;
     A.q0 = q; A.q1 = q1;
     A.bath = b;
     A.m0 = m0; A.m1 = m1;

@@ -82,7 +82,24 @@ constexpr int MASK_PHI = 1, MASK_BRK = 2;
 constexpr int IFACE_L = 1, IFACE_R = 2, IFACE_B = 4, IFACE_T = 8;   // (mask >> 2)
 
 struct WorkItem {
-    int patch, i0, r0, th;   // strip: columns i0..i0+59, rows r0..r0+th-1
+    int patch, i0, r0, th;   // strip: columns i0..i0+59, rows r0..r0+th-1; a packed
+                             // item: patch = -1 - its PackedItem, th its tallest tile
+};
+
+// Narrow strips of patch-set patches packed into one wavefront: strip s
+// (s < nseg) covers columns i0[s] .. i0[s] + w - 1 of patch[s] (w = min(60,
+// nx - i0[s]) < 60) and rows r0[s] .. r0[s] + th[s] - 1, on lanes l0[s] ..
+// l0[s] + w + 3 (two halo columns on either side).  All strips of an item
+// lie in patches of one refinement level of one scenario (one clock slot).
+constexpr int PACK_SEGS = 4;
+struct PackedItem {
+    int nseg;
+    int patch[PACK_SEGS], i0[PACK_SEGS], r0[PACK_SEGS], th[PACK_SEGS], l0[PACK_SEGS];
+};
+
+// the strip a lane works on and its first lane
+struct LaneStrip {
+    int patch, i0, r0, th, l0;
 };
 
 // per-scenario clock and control, device resident
@@ -108,6 +125,7 @@ struct MarchArgs {
     StepParams P;
     const PatchInfo *patches;
     const WorkItem *work;
+    const PackedItem *packs; // strips of the packed items (patch sets), or null
     S *q0, *q1;              // state buffers (ping-pong)
     const S *bath;
     uint8_t *m0, *m1;        // mask buffers (ping-pong): bit0 phi_T, bit1 breaking
@@ -126,6 +144,30 @@ struct MarchArgs {
     int mapped;              // some patch is mapped: the kernel compiled for it
     int nwork;
 };
+
+// a plain item is one strip over the whole wavefront; in a packed item each
+// lane takes the strip whose lanes hold it (lanes past the last strip's
+// belong to it, as idle lanes of a partial strip)
+template <class S>
+HSGN_HD LaneStrip lane_strip(const MarchArgs<S> &A, const WorkItem &wk, int lane)
+{
+    LaneStrip ls = {wk.patch, wk.i0, wk.r0, wk.th, 0};
+    if (wk.patch < 0) {
+        const PackedItem &pk = A.packs[-1 - wk.patch];
+        int s = 0;
+        HSGN_UNROLL
+        for (int t = 1; t < PACK_SEGS; t++) s += (t < pk.nseg && lane >= pk.l0[t]) ? 1 : 0;
+        ls = {pk.patch[s], pk.i0[s], pk.r0[s], pk.th[s], pk.l0[s]};
+    }
+    return ls;
+}
+
+// a patch of the item's clock slot
+template <class S>
+HSGN_HD int item_patch(const MarchArgs<S> &A, const WorkItem &wk)
+{
+    return wk.patch >= 0 ? wk.patch : A.packs[-1 - wk.patch].patch[0];
+}
 
 template <class L, class T>
 HSGN_HD void shfl_side_up(L &ln, const Side<T> &c, Side<T> &o)
@@ -468,8 +510,16 @@ template <class L, class S, class T, bool MIXED, bool AMR, bool FB = true, bool 
 HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 {
     const WorkItem wk = A.work[wid];
-    const PatchInfo pi = A.patches[wk.patch];
-    ScenState *sc = &A.scen[pi.scen];
+    const int lane = ln.lane();
+    // the lane's strip (patch sets: packed items hold several); the item's
+    // clock slot, spacing and step are its first patch's.  Mapped patch sets
+    // in mixed precision are not packed: their kernel keeps the patch data
+    // uniform (the host never gives it a packed item)
+    constexpr bool PACK = AMR && !(MAP && MIXED);
+    const LaneStrip ls = PACK ? lane_strip(A, wk, lane) : LaneStrip{wk.patch, wk.i0, wk.r0, wk.th, 0};
+    const PatchInfo pu = A.patches[PACK ? item_patch(A, wk) : wk.patch];
+    const PatchInfo pi = PACK ? A.patches[ls.patch] : pu;
+    ScenState *sc = &A.scen[pu.scen];
     const StepParams &P = A.P;
     if (!sc->active) return;                    // uniform over the wavefront
     const int cur = sc->cur;
@@ -479,29 +529,32 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     uint8_t *mout = cur ? A.m0 : A.m1;
     const double dtd = sc->dt;
     const T dt = (T)dtd;
-    const T dtdx = (T)(dtd / pi.dx), dtdy = (T)(dtd / pi.dy);
+    const T dtdx = (T)(dtd / pu.dx), dtdy = (T)(dtd / pu.dy);
     const T tau_pre = (T)0.5 * dt;
     const T tau_post = P.splitting ? (T)0.5 * dt : dt;
     const Limiter<T> lim = limiter_of<T>(P.limiter);
     const bool trans = P.transverse == 2;
 
-    const int lane = ln.lane();
-    int col = wk.i0 - 2 + lane;
+    const int sl = lane - ls.l0;                // lane within the strip
+    const int col0 = ls.i0 - 2 + sl;            // its column
+    int col = col0;
     if (col > pi.nx + 1) col = pi.nx + 1;       // idle lanes of a partial strip
     int fx = 0;
     const int mc = AMR ? col : map_index(col, pi.nx, pi.bc[0], pi.bc[1], &fx);
-    const int xwall = (wk.i0 - 2 + lane) < 0 ? 0 : pi.nx;   // wall edge of a mapped ghost
+    const int xwall = col0 < 0 ? 0 : pi.nx;     // wall edge of a mapped ghost
     constexpr int D = MAP ? 2 : 0;               // x-edge family vectors: frame or global
     constexpr int DY = MAP ? 2 : 1;              // y-edge
     const long long MW = pi.nx + 4, MP = MW * (pi.ny + 4);
-    const int i_hi = wk.i0 + 59 < pi.nx - 1 ? wk.i0 + 59 : pi.nx - 1;
-    const bool interior = (wk.i0 - 2 + lane) >= wk.i0 && (wk.i0 - 2 + lane) <= i_hi;
-    const bool interior_left = lane >= 1 && (wk.i0 - 3 + lane) >= wk.i0 && (wk.i0 - 3 + lane) <= i_hi;
-    const int r0 = wk.r0, th = wk.th;
+    const int i_hi = ls.i0 + 59 < pi.nx - 1 ? ls.i0 + 59 : pi.nx - 1;
+    const bool interior = col0 >= ls.i0 && col0 <= i_hi;
+    const bool interior_left = sl >= 1 && col0 - 1 >= ls.i0 && col0 - 1 <= i_hi;
+    // rows of the lane's tile; the loop runs over the item's tallest tile
+    // (uniform), a shorter tile's lanes idle through the rows past theirs
+    const int r0 = ls.r0, th = ls.th;
     // boundary-flux recording (patch sets): lanes of the patch's edge columns
     double *ef = (AMR && pi.eoff >= 0) ? A.eflux + pi.eoff * 7 : nullptr;
-    const bool e_left = ef && col == 0 && wk.i0 == 0;
-    const bool e_right = ef && (wk.i0 - 2 + lane) == pi.nx && i_hi == pi.nx - 1;
+    const bool e_left = ef && col == 0 && ls.i0 == 0;
+    const bool e_right = ef && col0 == pi.nx && i_hi == pi.nx - 1;
     const bool e_cols = ef && interior;
 
     T *ring = ln.ring();
@@ -539,7 +592,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
 
     RawCell<T> nxt;
     load_raw<AMR, MAP>(pi, qin, A.bath, min_, mc, fx, r0 - 2, nxt, xwall);
-    for (int k = r0 - 2; k <= r0 + th + 1; k++) {
+    for (int j = 0; j < wk.th + 4; j++) {
+        const int k = r0 - 2 + j;
         const int sk = 2, sk1 = 1, sk2 = 0;
         Cell<T> c;
         {
@@ -563,7 +617,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         }
         kap_w[sk] = met[0];
         const T kap_l = MAP ? ln.up(met[0]) : (T)1;      // capacity of cell (col - 1, k)
-        const int slot_k = (k - r0 + 6) % 3, slot_k2 = (k - r0 + 4) % 3;
+        const int slot_k = (j + 4) % 3, slot_k2 = (j + 2) % 3;
         if (MIXED) {
             // increment form: the cell's state after the first source half
             // step waits in LDS while its contributions are summed from
@@ -584,23 +638,24 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         HSGN_UNROLL
         for (int m = 0; m < 7; m++) xtr[m] = (T)0;
         if (k >= r0 - 1 && k <= r0 + th) {
-            Side<T> sr, sl;
+            Side<T> sdr, sdl;
             if (MAP) {
                 T ql[7];
                 HSGN_UNROLL
                 for (int m = 0; m < 7; m++) ql[m] = ln.up(c.q[m]);
                 const T bl = ln.up(c.b), c2l = ln.up(c.c2), etal = ln.up(c.eta);
-                mapped_side(P, ql, bl, c2l, etal, met[1], met[2], (T)0 - met[2], met[1], sl);
-                mapped_side(P, c.q, c.b, c.c2, c.eta, met[1], met[2], (T)0 - met[2], met[1], sr);
+                mapped_side(P, ql, bl, c2l, etal, met[1], met[2], (T)0 - met[2], met[1], sdl);
+                mapped_side(P, c.q, c.b, c.c2, c.eta, met[1], met[2], (T)0 - met[2], met[1], sdr);
             } else {
-                side_of<0>(c, sr);
-                shfl_side_up(ln, sr, sl);
+                side_of<0>(c, sdr);
+                shfl_side_up(ln, sdr, sdl);
             }
             Waves<T> xw;
             Eig<T> xe;
-            // lane 0 has no left neighbour (its edge is a halo edge, never used)
-            bool ok = edge_solve<0, MIXED && FB>(ln, P, sl, sr, xw, xe, lane >= 1);
-            errc = (!ok && lane >= 1) ? -4 : errc;
+            // a strip's first lane has no left neighbour (its edge is a halo
+            // edge, never used)
+            bool ok = edge_solve<0, MIXED && FB>(ln, P, sdl, sdr, xw, xe, sl >= 1);
+            errc = (!ok && sl >= 1) ? -4 : errc;
             if (MAP) set_frame(xw, xe, met[1], met[2], (T)0 - met[2], met[1], met[3]);
             Waves<T> xwl;
             shfl_waves_up<MAP>(ln, xw, xwl);
@@ -673,7 +728,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             } else {
                 ok = edge_solve<1, MIXED && FB>(ln, P, yside_prev, yside, yw, ye);
             }
-            errc = !ok ? -4 : errc;
+            // (a lane past its tile's rows solves its last row against itself)
+            errc = (!ok && k <= r0 + th + 1) ? -4 : errc;
             if (k >= r0 && k <= r0 + th && interior) {
                 const T kk = MAP ? tmin(kap_w[sk1], kap_w[sk]) : (T)1;
                 ry = tmax(ry, tmax((T)fabs(yw.smin) / kk, tmax((T)fabs(yw.smax) / kk, (T)fabs(yw.uh) / kk)));
@@ -819,7 +875,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             // implicit Euler step (FP64: h towards H; mixed precision: eta'
             // towards its rest value (b - eta0)^+)
             if (SP && pi.sp_rate > 0.0) {               // uniform over the wavefront
-                const double sg = sponge_sigma(pi, wk.i0 - 2 + lane, k - 2);
+                const double sg = sponge_sigma(pi, col0, k - 2);
                 if (sg > 0.0) {
                     const double f = 1.0 / (1.0 + dtd * sg);
                     if constexpr (MIXED) {
@@ -854,8 +910,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                     const double bD = (double)bb;
                     const double hD = (etaD + P.eta0) - bD;
                     if (hD < 0.0) {
-                        clip += MAP ? -hD * (double)kap_w[sk2] * pi.dx * pi.dy
-                                    : -hD * pi.dx * pi.dy;
+                        clip += MAP ? -hD * (double)kap_w[sk2] * pu.dx * pu.dy
+                                    : -hD * pu.dx * pu.dy;
                         etaD = bD - P.eta0;
                     }
                     dry = !(hD > P.dry_tol);
@@ -863,8 +919,8 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 } else {
                     T h = eta + (T)P.eta0 - bb;
                     if (h < (T)0) {
-                        clip += MAP ? -(double)h * (double)kap_w[sk2] * pi.dx * pi.dy
-                                    : -(double)h * pi.dx * pi.dy;
+                        clip += MAP ? -(double)h * (double)kap_w[sk2] * pu.dx * pu.dy
+                                    : -(double)h * pu.dx * pu.dy;
                         h = (T)0;
                         eta = bb - (T)P.eta0;
                     }
@@ -890,7 +946,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                 HSGN_UNROLL
                 for (int m = 1; m < 7; m++) qd[m] = (double)qn[m];
                 if (hD < 0.0) {
-                    clip += MAP ? -hD * (double)kap_w[sk2] * pi.dx * pi.dy : -hD * pi.dx * pi.dy;
+                    clip += MAP ? -hD * (double)kap_w[sk2] * pu.dx * pu.dy : -hD * pu.dx * pu.dy;
                     hD = 0.0;
                 }
                 if (hD <= P.dry_tol) {
@@ -912,7 +968,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
             }
             errc = (interior && bad) ? -5 : errc;
             if (interior) {
-                long long idx = (long long)(k - 2) * pi.pitch + (wk.i0 - 2 + lane);
+                long long idx = (long long)(k - 2) * pi.pitch + col0;
                 long long plane = pi.plane;
                 S *qo = qout + pi.qoff + idx;
                 qo[0] = out0;
@@ -945,7 +1001,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         }
     }
     if (errc) sc->err = errc;
-    ln.finish(A, wid, pi.scen, (double)rx, (double)ry, clip);
+    ln.finish(A, wid, pu.scen, (double)rx, (double)ry, clip);
 }
 
 }  // namespace hsgn

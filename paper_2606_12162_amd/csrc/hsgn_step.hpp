@@ -170,11 +170,13 @@ __global__ __launch_bounds__(64) void static_class_kernel(MarchArgs<S> A, int *o
     int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;
     const WorkItem wk = A.work[wid];
-    const PatchInfo pi = A.patches[wk.patch];
     const int lane = (int)(threadIdx.x & 63);
-    const int mc = footprint_col<FRAMED>(pi, wk.i0, lane);
+    const LaneStrip ls = FRAMED ? lane_strip(A, wk, lane) : LaneStrip{wk.patch, wk.i0, wk.r0, wk.th, 0};
+    const PatchInfo pi = A.patches[ls.patch];
+    const int mc = footprint_col<FRAMED>(pi, ls.i0, lane - ls.l0);
     int hot = 0;
-    for (int k = wk.r0 - 2; k <= wk.r0 + wk.th + 1; k++) {
+    for (int j = 0; j < wk.th + 4; j++) {
+        const int k = ls.r0 - 2 + j <= ls.r0 + ls.th + 1 ? ls.r0 - 2 + j : ls.r0 + ls.th + 1;
         const long long idx = footprint_row<FRAMED>(pi, k) + mc;
         hot |= !(relax_c2(A.P, MASK_PHI, (T)A.bath[idx]) > (T)0);
     }
@@ -197,18 +199,21 @@ __global__ __launch_bounds__(64) void classify_kernel(MarchArgs<S> A, int *cls)
         return;
     }
     const WorkItem wk = A.work[wid];
-    const PatchInfo pi = A.patches[wk.patch];
-    const uint8_t *mk = A.scen[pi.scen].cur ? A.m1 : A.m0;
-    const int mc = footprint_col<FRAMED>(pi, wk.i0, lane);
+    const LaneStrip ls = FRAMED ? lane_strip(A, wk, lane) : LaneStrip{wk.patch, wk.i0, wk.r0, wk.th, 0};
+    const PatchInfo pi = A.patches[ls.patch];
+    const uint8_t *mk = A.scen[A.patches[FRAMED ? item_patch(A, wk) : wk.patch].scen].cur ? A.m1 : A.m0;
+    const int mc = footprint_col<FRAMED>(pi, ls.i0, lane - ls.l0);
     // loads in batches of ROWS_IN_FLIGHT rows, all issued before any is used
+    // (the batches run over the item's tallest tile, a shorter tile's lanes
+    // reading their last row again)
     constexpr int ROWS_IN_FLIGHT = 16;
-    const int k1 = wk.r0 + wk.th + 1;
+    const int k1 = ls.r0 + ls.th + 1;
     int hot = 0;
-    for (int k0 = wk.r0 - 2; k0 <= k1; k0 += ROWS_IN_FLIGHT) {
+    for (int j0 = 0; j0 < wk.th + 4; j0 += ROWS_IN_FLIGHT) {
         int m[ROWS_IN_FLIGHT];
 #pragma unroll
         for (int u = 0; u < ROWS_IN_FLIGHT; u++) {
-            const int k = k0 + u <= k1 ? k0 + u : k1;
+            const int k = ls.r0 - 2 + j0 + u <= k1 ? ls.r0 - 2 + j0 + u : k1;
             m[u] = mk[footprint_row<FRAMED>(pi, k) + mc];
         }
 #pragma unroll

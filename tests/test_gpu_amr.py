@@ -287,3 +287,37 @@ def test_split_patch_set_step_is_bitwise_the_full_kernel(monkeypatch, mode):
     assert np.array_equal(ga, gb)
     for k, ((qa, ma), (qb, mb)) in enumerate(zip(a, b)):
         assert np.array_equal(qa, qb) and np.array_equal(ma, mb), k
+
+
+@pytest.mark.parametrize("mapped", [False, True])
+def test_packed_strips_give_the_unpacked_state_bitwise(monkeypatch, mapped):
+    """narrow strips of patch-set patches packed into shared wavefronts (the
+    default) against one wavefront per strip (HSGN_NO_PACKING=1): fewer work
+    items, the same state bit for bit in both precisions (the clipped mass,
+    summed per item, may round differently).  Mapped patch sets in mixed
+    precision are not packed: the same work items."""
+    from test_oracle_amr_mapped import L48, bumpy, with_momentum
+    w = with_momentum(W.amr_small(steps=3))
+    nodes = None
+    if mapped:
+        w = dataclasses.replace(w, dt=0.7 * w.dt)
+        nodes = [W.nested_nodes(w, bumpy(L48, L48))]
+    for precision in (0, 1):
+        print("case packing, mapped", mapped, "precision", precision, flush=True)
+        runs = []
+        for nopack in ("0", "1"):
+            monkeypatch.setenv("HSGN_NO_PACKING", nopack)
+            ctx, ids = H.from_amr_workloads([w], precision=precision, nodes=nodes)
+            n = ctx.work_items()
+            ctx.advance(-1.0, w.steps)
+            runs.append((n, [ctx.get_state(pid) for pid in ids[0]],
+                         [ctx.get_mask(pid) for pid in ids[0]]))
+            ctx.close()
+        if mapped and precision == 1:
+            assert runs[0][0] == runs[1][0], (runs[0][0], runs[1][0])
+        else:
+            assert runs[0][0] < runs[1][0], (runs[0][0], runs[1][0])
+        for k, (a, b) in enumerate(zip(runs[0][1], runs[1][1])):
+            assert np.array_equal(a, b), (precision, k)
+        for a, b in zip(runs[0][2], runs[1][2]):
+            assert np.array_equal(a, b)

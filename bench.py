@@ -81,11 +81,11 @@ STEP_KERNELS = {"fp64": "march_kernel<fp64>",
 KERNEL_SOURCES = ["hsgn_math.hpp", "hsgn_march.hpp", "hsgn_step.hpp",
                   "hsgn_step32.hip", "hsgn_step64.hip"]
 MEASURED_TRAFFIC = {
-    ("ensemble", "mixed"): {"digest": "9f23a4ac4c24f565",
-                            "tiles": {40: (1.022355e+06, 1.420815e+06), 48: (1.012440e+06, 1.426626e+06),
-                                      56: (1.003568e+06, 1.431462e+06)}},
-    ("ensemble", "fp64"): {"digest": "9f23a4ac4c24f565",
-                           "tiles": {56: (1.691506e+06, 2.761003e+06), 64: (1.680999e+06, 2.761905e+06)}},
+    ("ensemble", "mixed"): {"digest": "55293607db5ca041",
+                            "tiles": {40: (1.022184e+06, 1.422443e+06), 48: (1.011572e+06, 1.429627e+06),
+                                      56: (1.003938e+06, 1.433797e+06)}},
+    ("ensemble", "fp64"): {"digest": "55293607db5ca041",
+                           "tiles": {56: (1.691665e+06, 2.760396e+06), 64: (1.681280e+06, 2.762015e+06)}},
 }
 
 

@@ -126,6 +126,10 @@ typedef struct hsgn_ctx hsgn_ctx;
  * hip_stream after a call still follows the whole step.  The results are the
  * same bits as with the full kernel everywhere, which the environment
  * variable HSGN_NO_KERNEL_SPLIT=1, read here, selects (a diagnostic).
+ * Patch sets pack column strips narrower than 60 cells, up to four of one
+ * refinement level, into one wavefront's work item (mapped patch sets in
+ * mixed precision excepted); HSGN_NO_PACKING=1, read here, gives every
+ * strip its own (a diagnostic: the state is the same bit for bit).
  * Errors: EINVAL (bad parameters), ENOTSUP (model/precision), EDEVICE. */
 int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out);
 
@@ -267,7 +271,8 @@ int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next,
  * captured step graph.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int hsgn_autotune(hsgn_ctx *c, int trials, int *rows);
 
-/* Number of marching work items (wavefronts) of one step. */
+/* Number of marching work items (wavefronts) of one step (a packed item
+ * counts once). */
 int hsgn_work_items(hsgn_ctx *c, int *n);
 
 /* Kernel timing for measurement: with on = 1, every launch of the step

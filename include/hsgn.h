@@ -123,9 +123,13 @@ typedef struct hsgn_ctx hsgn_ctx;
  * FP64 near-shore solve run a kernel without it, and the others run the full
  * kernel on a second stream the context owns (default priority), forked
  * from and joined back into hip_stream with events, so that work enqueued on
- * hip_stream after a call still follows the whole step.  The results are the
- * same bits as with the full kernel everywhere, which the environment
- * variable HSGN_NO_KERNEL_SPLIT=1, read here, selects (a diagnostic).
+ * hip_stream after a call still follows the whole step.  The two kernels
+ * compute the same method in the same order; being two instantiations, they
+ * can round an FP32 operation differently in a few cells (the compiler fuses
+ * products into sums per instantiation).  The environment variable
+ * HSGN_NO_KERNEL_SPLIT=1, read here, runs the full kernel on every item (a
+ * diagnostic).  Within an advance over single grids only, the items are
+ * classified again only after a step latched a cell as breaking.
  * Patch sets pack column strips narrower than 60 cells, up to four of one
  * refinement level, into one wavefront's work item (mapped patch sets in
  * mixed precision excepted); HSGN_NO_PACKING=1, read here, gives every

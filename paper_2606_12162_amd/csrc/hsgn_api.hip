@@ -474,6 +474,8 @@ struct hsgn_ctx {
     int *d_list = nullptr;      // item lists of the split mixed step (2 per item)
     unsigned *d_lcnt = nullptr; // their lengths
     int *d_cls = nullptr;       // the items' classes for the attempt
+    int *d_latch = nullptr;     // split step over single grids only: a cell latched since
+                                // the lists were made (1 forces the classification)
     std::vector<uint8_t> state_set;   // per patch: its state has been set (or moved in)
     uint8_t *d_keep = nullptr;  // device copy of state_set for the bathymetry average-down
     int *d_clsb = nullptr;      // their bottom part
@@ -565,7 +567,8 @@ static void free_device(hsgn_ctx *c)
                     c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
                     c->d_mass, c->f0, c->f1, c->fbath, c->stage, c->d_cnt, c->d_gc, c->d_gi,
                     c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip, c->d_list,
-                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep, c->d_B0, c->d_packs};
+                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep, c->d_B0, c->d_packs,
+                    c->d_latch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *m : c->d_metric)
@@ -582,6 +585,7 @@ static void free_device(hsgn_ctx *c)
     c->d_keep = nullptr;
     c->d_B0 = nullptr;
     c->d_packs = nullptr;
+    c->d_latch = nullptr;
     c->b0_scen = -1;
     c->d_lcnt = nullptr;
 }
@@ -603,6 +607,7 @@ static MarchArgs<S> march_args(hsgn_ctx *c, S *q0, S *q1, const S *bath, int w0,
     A.list = nullptr;
     A.lcnt = nullptr;
     A.clsb = nullptr;
+    A.latch = nullptr;
     A.sponge = c->any_sponge ? 1 : 0;
     A.mapped = c->mapped_single ? 1 : 0;   // patch-set ranges: launch_march_range
     A.nwork = w1 - w0;
@@ -1559,6 +1564,10 @@ int hsgn_finalize(hsgn_ctx *c)
     HIPCHK(c, hipMalloc(&c->d_cls, sizeof(int) * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_clsb, sizeof(int) * std::max<size_t>(c->work.size(), 1)));
     c->clsb_dirty = true;
+    // the classes of a context of single grids change within an advance only
+    // where a cell latches (patch sets also take masks from other levels'
+    // and patches' cells into their ghost frames: they classify every attempt)
+    if (c->split && !c->any_amr) HIPCHK(c, hipMalloc(&c->d_latch, sizeof(int)));
     if (c->split) {
         HIPCHK(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
         HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
@@ -1605,6 +1614,13 @@ int hsgn_finalize(hsgn_ctx *c)
     c->finalized = true;
     c->amr_dirty = c->any_amr;
     return HSGN_OK;
+}
+
+// the split step's latch flag set (every lane of one wavefront stores it,
+// a vector store)
+__global__ void set_flag_kernel(int *flag, int v)
+{
+    if (threadIdx.x < 64) *flag = v;
 }
 
 static int pull_scen(hsgn_ctx *c, std::vector<ScenState> &st)
@@ -2221,6 +2237,7 @@ static void launch_march_range(hsgn_ctx *c, int w0, int wa, int w1, hipStream_t 
         if (c->mixed) {
             MarchArgs<float> A = march_args<float>(c, c->f0, c->f1, c->fbath, w0, wa);
             split_args(c, A, w0);
+            A.latch = c->d_latch;               // single-grid contexts only
             launch_mixed_split(c, A, (unsigned)(wa - w0), c->d_cls + w0, false, s, fork);
         } else
             launch_march64(march_args<double>(c, c->q0, c->q1, c->bath, w0, wa), (unsigned)(wa - w0), s);
@@ -2418,6 +2435,12 @@ int hsgn_advance(hsgn_ctx *c, double dt, int n_steps)
         if (err) return fail(c, err, "initial step: state not hyperbolic");
     }
     if ((rc = ensure_gauges(c, st, (long long)n_steps + 256))) return rc;
+    // the first attempt classifies (masks or bathymetry may have changed
+    // since the last advance); later ones only after a latch
+    if (c->d_latch) {
+        set_flag_kernel<<<1, 64, 0, c->stream>>>(c->d_latch, 1);
+        HIPCHK(c, hipGetLastError());
+    }
     long long attempts = n_steps, budget = (long long)n_steps + 4096;
     while (attempts > 0) {
         for (long long a = 0; a < attempts; a++) {
@@ -2919,7 +2942,7 @@ int hsgn_advance_static(const hsgn_params *p, void *hip_stream, int nx, int ny, 
     A.scen = dst;
     A.clip_slots = clip;
     A.eflux = nullptr;
-    A.list = nullptr; A.lcnt = nullptr; A.clsb = nullptr;
+    A.list = nullptr; A.lcnt = nullptr; A.clsb = nullptr; A.latch = nullptr;
     A.sponge = 0; A.mapped = 0;
     A.nwork = (int)nwork;
     for (int a = 0; a < n_steps; a++) {

@@ -140,6 +140,11 @@ struct MarchArgs {
     int *list;
     unsigned *lcnt;
     const int *clsb;
+    // split step over single grids only: set to 1 by a step kernel that
+    // latches a cell as breaking (the only change of the classes within an
+    // advance); with it 0 the classification keeps the previous lists.  Null:
+    // every attempt classifies.
+    int *latch;
     int sponge;              // some patch has a sponge: the kernels compiled with it
     int mapped;              // some patch is mapped: the kernel compiled for it
     int nwork;
@@ -587,6 +592,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
     // error code of the lane (non-hyperbolic edge -4, non-finite result -5),
     // published once when the strip is done; nothing reads it during the step
     int errc = 0;
+    bool latched = false;        // the lane latched a cell as breaking
     HSGN_UNROLL
     for (int m = 0; m < 7; m++) { xtr_prev[m] = (T)0; bp_saved[m] = (T)0; ydl[m] = (T)0; }
 
@@ -931,7 +937,10 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
                     for (int m = 1; m < 7; m++) qn[m] = (T)0;
                 } else if (P.kappa > 0.0 && phi && !brk) {
                     T H = tmax((T)P.eta0 - bb, (T)0);
-                    if (eta > (T)P.kappa * H) brk = 1;
+                    if (eta > (T)P.kappa * H) {
+                        brk = 1;
+                        latched = interior;
+                    }
                 }
                 if (!phi || brk || dry) {
                     qn[IHW] = (T)0; qn[IHS] = (T)0; qn[IHP] = (T)0; qn[IHPB] = (T)0;
@@ -1001,6 +1010,7 @@ HSGN_HD void march(L &ln, const MarchArgs<S> &A, int wid)
         }
     }
     if (errc) sc->err = errc;
+    if (MIXED && A.latch && ln.any(latched) && lane == 0) *A.latch = 1;
     ln.finish(A, wid, pu.scen, (double)rx, (double)ry, clip);
 }
 

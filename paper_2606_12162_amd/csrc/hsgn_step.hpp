@@ -193,6 +193,7 @@ __global__ __launch_bounds__(64) void classify_kernel(MarchArgs<S> A, int *cls)
 {
     int wid = (int)blockIdx.x;
     if (wid >= A.nwork) return;
+    if (A.latch && *A.latch == 0) return;       // the classes stand (uniform)
     const int lane = (int)(threadIdx.x & 63);
     if (A.clsb[wid]) {                          // uniform over the wavefront
         if (lane == 0) cls[wid] = 1;
@@ -234,11 +235,14 @@ constexpr int LIST_THREADS = 1024;
 
 template <int NT>
 __global__ __launch_bounds__(NT) void list_kernel(const int *cls, int nwork, int *list,
-                                                  unsigned *lcnt)
+                                                  unsigned *lcnt, int *latch)
 {
     constexpr int NW = NT / 64, CH = 32;
     __shared__ int cnt[CH * NW];        // class-1 counts per (chunk, wave), then their scan
     __shared__ int total;               // class-1 items before the pass
+    // no cell latched since the lists were made: they stand (the flag is read
+    // by every thread before any barrier, and cleared after the last one)
+    if (latch && *latch == 0) return;
     const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
     if (t == 0) total = 0;
     for (int p = 0; p < nwork; p += CH * NT) {
@@ -293,6 +297,7 @@ __global__ __launch_bounds__(NT) void list_kernel(const int *cls, int nwork, int
     if (t == 0) {
         lcnt[0] = (unsigned)(nwork - total);
         lcnt[1] = (unsigned)total;
+        if (latch) *latch = 0;
     }
 }
 

@@ -34,7 +34,8 @@ void launch_march32_deep(const MarchArgs<float> &A, unsigned nwork, hipStream_t 
 void launch_classify32(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream)
 {
     classify_kernel<float, float, false><<<nwork, 64, 0, stream>>>(A, cls);
-    list_kernel<LIST_THREADS><<<1, LIST_THREADS, 0, stream>>>(cls, (int)nwork, A.list, A.lcnt);
+    list_kernel<LIST_THREADS><<<1, LIST_THREADS, 0, stream>>>(cls, (int)nwork, A.list, A.lcnt,
+                                                             A.latch);
 }
 
 // the bottom part of the classes (after a bathymetry or work-table change)

@@ -32,7 +32,8 @@ void launch_march32_amr_deep(const MarchArgs<float> &A, unsigned nwork, hipStrea
 void launch_classify32_amr(const MarchArgs<float> &A, unsigned nwork, int *cls, hipStream_t stream)
 {
     classify_kernel<float, float, true><<<nwork, 64, 0, stream>>>(A, cls);
-    list_kernel<LIST_THREADS><<<1, LIST_THREADS, 0, stream>>>(cls, (int)nwork, A.list, A.lcnt);
+    list_kernel<LIST_THREADS><<<1, LIST_THREADS, 0, stream>>>(cls, (int)nwork, A.list, A.lcnt,
+                                                             A.latch);
 }
 
 // the bottom part of the classes, ghost frames included

@@ -212,8 +212,7 @@ def test_split_step_is_bitwise_the_full_kernel(monkeypatch, tune):
     (kernel without the FP64 edge solve) and the rest (full kernel) gives
     the same bits as the full kernel on every item: an ocean whose deep
     plain, shelf and dry coast all lie in one grid, while the wave reaches
-    the shelf and the SWE region and breaking latches move, plus a small
-    ensemble in the same launch"""
+    the shelf and the SWE region, plus a small ensemble in the same launch"""
     ws = [W.synthetic_ocean(n=512, dx=2000.0, steps=200)] + small_ensemble(count=3, seed0=91)
     print("case", [w.name for w in ws], "autotune", tune, flush=True)
     split = _mixed_run(ws, 200, tune)
@@ -222,6 +221,43 @@ def test_split_step_is_bitwise_the_full_kernel(monkeypatch, tune):
     for s, (a, b) in enumerate(zip(split, full)):
         for x, y in zip(a, b):
             assert np.array_equal(x, y), ws[s].name
+
+
+def test_split_step_through_breaking_keeps_its_lists_right(monkeypatch):
+    """a soliton breaking on the plane beach (adaptive steps): cells latch as
+    breaking from about step 300 on.  Within one advance the split step over
+    single grids keeps its item lists until a cell latches, and it classifies
+    afresh at the start of every advance: one advance of 600 steps gives the
+    bits of 600 advances of one step.  Against the full kernel on every item
+    it agrees to FP32 rounding: the two kernel instantiations round an FP32
+    operation differently in a few cells (one hp value by 3e-8 after 50
+    steps here, before any latch), which the breaking front then carries"""
+    w = W.beach_soliton(n=256, dx=0.2, x0=30.0)
+    runs = {}
+    for mode, nosplit, chunk in (("one advance", "0", 600), ("single steps", "0", 1),
+                                 ("full kernel", "1", 600)):
+        monkeypatch.setenv("HSGN_NO_KERNEL_SPLIT", nosplit)
+        print("case", w.name, mode, flush=True)
+        ctx = H.Context(w.params, precision=1)
+        ctx.add_grid(0, w.grid)
+        ctx.finalize()
+        ctx.set_bathymetry(0, w.b)
+        ctx.set_state(0, w.q)
+        for _ in range(600 // chunk):
+            ctx.advance(0.0, chunk)
+        runs[mode] = (ctx.get_state(0), ctx.get_mask(0), ctx.clock(0))
+        ctx.close()
+    a = runs["one advance"]
+    assert (a[1] & 2).sum() > 1000                  # latched cells
+    b = runs["single steps"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    f = runs["full kernel"]
+    eta_a, eta_f = a[0][0] + w.b, f[0][0] + w.b
+    wet = (a[0][0] > 1e-3) & (f[0][0] > 1e-3)
+    err = float(np.abs(eta_a - eta_f)[wet].max()) / w.amplitude
+    print("split against full kernel: surface difference / amplitude %.2e, latched cells %d / %d"
+          % (err, int((a[1] & 2).sum() // 2), int((f[1] & 2).sum() // 2)))
+    assert err <= 1e-4
 
 
 def test_split_step_with_more_items_than_one_list_pass(monkeypatch):

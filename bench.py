@@ -81,11 +81,13 @@ STEP_KERNELS = {"fp64": "march_kernel<fp64>",
 KERNEL_SOURCES = ["hsgn_math.hpp", "hsgn_march.hpp", "hsgn_step.hpp",
                   "hsgn_step32.hip", "hsgn_step64.hip"]
 MEASURED_TRAFFIC = {
-    ("ensemble", "mixed"): {"digest": "55293607db5ca041",
-                            "tiles": {40: (1.022184e+06, 1.422443e+06), 48: (1.011572e+06, 1.429627e+06),
-                                      56: (1.003938e+06, 1.433797e+06)}},
-    ("ensemble", "fp64"): {"digest": "55293607db5ca041",
-                           "tiles": {56: (1.691665e+06, 2.760396e+06), 64: (1.681280e+06, 2.762015e+06)}},
+    ("ensemble", "mixed"): {"digest": "dfde4759552ce4fd",
+                            "tiles": {24: (1.033315e+06, 1.413443e+06), 28: (1.013762e+06, 1.414979e+06),
+                                      32: (1.000020e+06, 1.417632e+06), 40: (9.815231e+05, 1.419714e+06),
+                                      48: (9.704580e+05, 1.425438e+06), 56: (9.631130e+05, 1.429830e+06)}},
+    ("ensemble", "fp64"): {"digest": "dfde4759552ce4fd",
+                           "tiles": {40: (1.722454e+06, 2.752222e+06), 48: (1.705094e+06, 2.756582e+06),
+                                     56: (1.691234e+06, 2.759149e+06), 64: (1.681060e+06, 2.761092e+06)}},
 }
 
 

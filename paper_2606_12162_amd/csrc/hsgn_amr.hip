@@ -376,13 +376,31 @@ __device__ inline bool surface_of(const PatchInfo &P, const S *q, const S *bath,
     return v > dry_tol;
 }
 
+// the record holding launch cell k (records sorted by c0, the first at 0)
+template <class R>
+__device__ inline int record_of(const R *rec, int nr, long long k)
+{
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rec[mid].c0 <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// the flags of every level-l patch (the rule of surface_of), one thread per flag
 template <class S, bool MIXED>
-__global__ void regrid_flag_kernel(PatchInfo P, const S *q, const S *bath, uint8_t *out,
-                                   double eta0, double dry_tol, double tol)
+__global__ void regrid_flag_kernel(const FlagRec *R, int nr, long long total, const S *q,
+                                   const S *bath, uint8_t *out, double eta0, double dry_tol,
+                                   double tol)
 {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= (long long)P.nx * P.ny) return;
-    const int x = (int)(k % P.nx), y = (int)(k / P.nx);
+    if (k >= total) return;
+    const FlagRec &r = R[record_of(R, nr, k)];
+    const PatchInfo &P = r.p;
+    const long long e = k - r.c0;
+    const int x = (int)(e % P.nx), y = (int)(e / P.nx);
     double e0, e1;
     uint8_t f = 0;
     if (surface_of<S, MIXED>(P, q, bath, x, y, eta0, dry_tol, e0)) {
@@ -396,19 +414,6 @@ __global__ void regrid_flag_kernel(PatchInfo P, const S *q, const S *bath, uint8
         }
     }
     out[k] = f;
-}
-
-// the record holding launch cell k (records sorted by c0, the first at 0)
-template <class R>
-__device__ inline int record_of(const R *rec, int nr, long long k)
-{
-    int lo = 0, hi = nr - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (rec[mid].c0 <= k) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
 }
 
 // copy one cell from the old storage; a wet cell whose bathymetry changed
@@ -608,19 +613,21 @@ void launch_fill_zero(double *p, long long n, hipStream_t s)
     if (n > 0) fill_zero_kernel<<<blocks(n), TPB, 0, s>>>(p, n);
 }
 
-void launch_regrid_flag64(const PatchInfo &p, const double *q, const double *bath, uint8_t *out,
-                          double eta0, double dry_tol, double tol, hipStream_t s)
+void launch_regrid_flag64(const FlagRec *r, int nr, long long total, const double *q,
+                          const double *bath, uint8_t *out, double eta0, double dry_tol,
+                          double tol, hipStream_t s)
 {
-    long long n = (long long)p.nx * p.ny;
-    if (n > 0) regrid_flag_kernel<double, false><<<blocks(n), TPB, 0, s>>>(p, q, bath, out, eta0,
-                                                                          dry_tol, tol);
+    if (nr > 0 && total > 0)
+        regrid_flag_kernel<double, false><<<blocks(total), TPB, 0, s>>>(r, nr, total, q, bath, out,
+                                                                        eta0, dry_tol, tol);
 }
-void launch_regrid_flag32(const PatchInfo &p, const float *q, const float *bath, uint8_t *out,
-                          double eta0, double dry_tol, double tol, hipStream_t s)
+void launch_regrid_flag32(const FlagRec *r, int nr, long long total, const float *q,
+                          const float *bath, uint8_t *out, double eta0, double dry_tol,
+                          double tol, hipStream_t s)
 {
-    long long n = (long long)p.nx * p.ny;
-    if (n > 0) regrid_flag_kernel<float, true><<<blocks(n), TPB, 0, s>>>(p, q, bath, out, eta0,
-                                                                        dry_tol, tol);
+    if (nr > 0 && total > 0)
+        regrid_flag_kernel<float, true><<<blocks(total), TPB, 0, s>>>(r, nr, total, q, bath, out,
+                                                                      eta0, dry_tol, tol);
 }
 void launch_regrid_copy64(const RegridCopy<double> *r, int nr, long long total, double *q,
                           const double *bath, uint8_t *m0, uint8_t *m1, double eta0,

@@ -147,10 +147,18 @@ void launch_topo64(const TopoRec *r, int nr, long long total, const double *B0, 
 void launch_topo32(const TopoRec *r, int nr, long long total, const double *B0, int NX, int NY,
                    float *bath, hipStream_t s);
 
-void launch_regrid_flag64(const PatchInfo &p, const double *q, const double *bath, uint8_t *out,
-                          double eta0, double dry_tol, double tol, hipStream_t s);
-void launch_regrid_flag32(const PatchInfo &p, const float *q, const float *bath, uint8_t *out,
-                          double eta0, double dry_tol, double tol, hipStream_t s);
+// the flags of the level-l patches of one regrid, in one launch: a record
+// per patch, its flags laid end to end in the output (c0: its first flag)
+struct FlagRec {
+    PatchInfo p;
+    long long c0;
+};
+void launch_regrid_flag64(const FlagRec *r, int nr, long long total, const double *q,
+                          const double *bath, uint8_t *out, double eta0, double dry_tol,
+                          double tol, hipStream_t s);
+void launch_regrid_flag32(const FlagRec *r, int nr, long long total, const float *q,
+                          const float *bath, uint8_t *out, double eta0, double dry_tol,
+                          double tol, hipStream_t s);
 void launch_regrid_copy64(const RegridCopy<double> *r, int nr, long long total, double *q,
                           const double *bath, uint8_t *m0, uint8_t *m1, double eta0,
                           double dry_tol, hipStream_t s);

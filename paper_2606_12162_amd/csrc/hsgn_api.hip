@@ -652,6 +652,16 @@ struct LevelIndex {
         for (long long bj = b0; bj <= b1; bj++)
             for (long long bi = a0; bi <= a1; bi++) buckets[(size_t)(bj * nbx + bi)].push_back(pid);
     }
+    // the patches of the buckets that cells [I0, I0 + nx) x [J0, J0 + ny)
+    // reach, with repeats
+    void near(long long I0, long long J0, long long nx, long long ny, std::vector<int> &out) const
+    {
+        long long b0 = std::max(fdiv(J0, BS), 0LL), b1 = std::min(fdiv(J0 + ny - 1, BS), nby - 1);
+        long long a0 = std::max(fdiv(I0, BS), 0LL), a1 = std::min(fdiv(I0 + nx - 1, BS), nbx - 1);
+        for (long long bj = b0; bj <= b1; bj++)
+            for (long long bi = a0; bi <= a1; bi++)
+                for (int pid : buckets[(size_t)(bj * nbx + bi)]) out.push_back(pid);
+    }
     int find(long long I, long long J) const
     {
         if (I < 0 || J < 0 || I >= NXl || J >= NYl) return -1;
@@ -707,22 +717,6 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
         idx[l].init(c, (long long)sh.NX * f, (long long)sh.NY * f);
         for (int pid : sh.lev[l]) idx[l].add(pid);
     }
-    // no two patches of a level overlap
-    for (int l = 0; l < nl; l++)
-        for (int pid : sh.lev[l]) {
-            const PatchInfo &p = c->patches[pid];
-            for (int q : sh.lev[l]) {
-                if (q <= pid) continue;
-                const PatchInfo &o = c->patches[q];
-                bool ov = c->pI0[pid] < c->pI0[q] + o.nx && c->pI0[q] < c->pI0[pid] + p.nx &&
-                          c->pJ0[pid] < c->pJ0[q] + o.ny && c->pJ0[q] < c->pJ0[pid] + p.ny;
-                if (ov) return fail(c, HSGN_EINVAL, "patches of one level overlap");
-            }
-        }
-    long long area = 0;
-    for (int pid : sh.lev[0]) area += (long long)c->patches[pid].nx * c->patches[pid].ny;
-    if (area != (long long)sh.NX * sh.NY)
-        return fail(c, HSGN_EINVAL, "level-0 patches must tile a rectangle");
     // finer patches stay one coarser cell away from the domain boundary
     for (int l = 1; l < nl; l++) {
         long long NXl = (long long)sh.NX, NYl = (long long)sh.NY;
@@ -734,6 +728,23 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                 return fail(c, HSGN_EINVAL, "a refined patch touches the domain boundary");
         }
     }
+    // no two patches of a level overlap.  Every patch lies inside its level's
+    // domain (level 0 spans its patches' extent, finer levels were checked
+    // above), so two patches that overlap share a bucket of the index.
+    for (int l = 0; l < nl; l++)
+        for (const std::vector<int> &b : idx[l].buckets)
+            for (size_t u = 0; u < b.size(); u++)
+                for (size_t v = u + 1; v < b.size(); v++) {
+                    const int pid = b[u], q = b[v];
+                    const PatchInfo &p = c->patches[pid], &o = c->patches[q];
+                    bool ov = c->pI0[pid] < c->pI0[q] + o.nx && c->pI0[q] < c->pI0[pid] + p.nx &&
+                              c->pJ0[pid] < c->pJ0[q] + o.ny && c->pJ0[q] < c->pJ0[pid] + p.ny;
+                    if (ov) return fail(c, HSGN_EINVAL, "patches of one level overlap");
+                }
+    long long area = 0;
+    for (int pid : sh.lev[0]) area += (long long)c->patches[pid].nx * c->patches[pid].ny;
+    if (area != (long long)sh.NX * sh.NY)
+        return fail(c, HSGN_EINVAL, "level-0 patches must tile a rectangle");
     auto covered = [&](int l, long long I, long long J) {
         return l + 1 < nl && idx[l + 1].find(AMR_RATIO * I, AMR_RATIO * J) >= 0;
     };
@@ -883,34 +894,51 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                 std::sort(cand.begin(), cand.end());
                 cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
             }
-            for (auto &jc : cand) {
-                long long J = jc.first, I = jc.second;
-                int cp = idx[l].find(I, J);
-                if (cp < 0 || covered(l, I, J)) continue;
-                RefluxRec r;
-                r.cp = cp;
-                r.cl = local_of(c->patches[cp], I - c->pI0[cp], J - c->pJ0[cp]);
-                const long long nb[4][2] = {{I - 1, J}, {I + 1, J}, {I, J - 1}, {I, J + 1}};
-                bool any = false;
-                for (int e = 0; e < 4; e++) {
-                    r.fp[e] = -1;
-                    r.e0[e] = 0;
-                    if (!covered(l, nb[e][0], nb[e][1])) continue;
-                    // a fine cell just across the edge
-                    long long fi = e == 0 ? AMR_RATIO * I - 1 : e == 1 ? AMR_RATIO * (I + 1) : AMR_RATIO * I;
-                    long long fj = e == 2 ? AMR_RATIO * J - 1 : e == 3 ? AMR_RATIO * (J + 1) : AMR_RATIO * J;
-                    int f = idx[l + 1].find(fi, fj);
-                    const PatchInfo &F = c->patches[f];
-                    long long fI0 = c->pI0[f], fJ0 = c->pJ0[f];
-                    r.fp[e] = f;
-                    r.e0[e] = e == 0 ? (int)(F.ny + AMR_RATIO * J - fJ0)
-                            : e == 1 ? (int)(AMR_RATIO * J - fJ0)
-                            : e == 2 ? (int)(2 * F.ny + F.nx + AMR_RATIO * I - fI0)
-                                     : (int)(2 * F.ny + AMR_RATIO * I - fI0);
-                    any = true;
+            // the records of the candidates, in chunks on host threads joined
+            // in order
+            const size_t ncand = cand.size();
+            const int nt = ncand >= 4096 ? nthreads : 1;
+            std::vector<std::vector<RefluxRec>> part(nt);
+            auto reflux_chunk = [&](int t) {
+                for (size_t kc = ncand * t / nt; kc < ncand * (t + 1) / nt; kc++) {
+                    long long J = cand[kc].first, I = cand[kc].second;
+                    int cp = idx[l].find(I, J);
+                    if (cp < 0 || covered(l, I, J)) continue;
+                    RefluxRec r;
+                    r.cp = cp;
+                    r.cl = local_of(c->patches[cp], I - c->pI0[cp], J - c->pJ0[cp]);
+                    const long long nb[4][2] = {{I - 1, J}, {I + 1, J}, {I, J - 1}, {I, J + 1}};
+                    bool any = false;
+                    for (int e = 0; e < 4; e++) {
+                        r.fp[e] = -1;
+                        r.e0[e] = 0;
+                        if (!covered(l, nb[e][0], nb[e][1])) continue;
+                        // a fine cell just across the edge
+                        long long fi = e == 0 ? AMR_RATIO * I - 1
+                                     : e == 1 ? AMR_RATIO * (I + 1) : AMR_RATIO * I;
+                        long long fj = e == 2 ? AMR_RATIO * J - 1
+                                     : e == 3 ? AMR_RATIO * (J + 1) : AMR_RATIO * J;
+                        int f = idx[l + 1].find(fi, fj);
+                        const PatchInfo &F = c->patches[f];
+                        long long fI0 = c->pI0[f], fJ0 = c->pJ0[f];
+                        r.fp[e] = f;
+                        r.e0[e] = e == 0 ? (int)(F.ny + AMR_RATIO * J - fJ0)
+                                : e == 1 ? (int)(AMR_RATIO * J - fJ0)
+                                : e == 2 ? (int)(2 * F.ny + F.nx + AMR_RATIO * I - fI0)
+                                         : (int)(2 * F.ny + AMR_RATIO * I - fI0);
+                        any = true;
+                    }
+                    if (any) part[t].push_back(r);
                 }
-                if (any) lev_rf[l].push_back(r);
+            };
+            if (nt > 1) {
+                std::vector<std::thread> th;
+                for (int t = 0; t < nt; t++) th.emplace_back(reflux_chunk, t);
+                for (auto &x : th) x.join();
+            } else {
+                reflux_chunk(0);
             }
+            for (auto &v : part) lev_rf[l].insert(lev_rf[l].end(), v.begin(), v.end());
         }
     }
     return HSGN_OK;
@@ -918,7 +946,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
 
 // every table entry addresses cells inside its patch's storage (interior or
 // ghost frame as required) and entries inside the flux buffer: checked on
-// the host before any table reaches the device
+// the host before any kernel reads a table
 static bool local_ok(const hsgn_ctx *c, int pid, int local, bool interior)
 {
     if (pid < 0 || pid >= (int)c->patches.size()) return false;
@@ -954,9 +982,9 @@ static bool all_of_parallel(size_t n, F ok)
     return true;
 }
 
-static int validate_tables(hsgn_ctx *c)
+// the first kind of record that fails the check, or null
+static const char *table_error(const hsgn_ctx *c)
 {
-    auto bad = [&](const char *what) { return fail(c, HSGN_EINVAL, std::string("internal table check: ") + what); };
     // a cell of a patch's frame (interior or ghost), for the wall edges
     auto in_frame = [&](int pid, int local) {
         const PatchInfo &p = c->patches[pid];
@@ -970,7 +998,7 @@ static int validate_tables(hsgn_ctx *c)
             return local_ok(c, r.dp, r.dl, false) && local_ok(c, r.sp, r.sl, true) &&
                    (!(r.flips & 1) || in_frame(r.sp, r.wx)) && (!(r.flips & 2) || in_frame(r.sp, r.wy));
         }))
-        return bad("ghost copy");
+        return "ghost copy";
     if (!all_of_parallel(c->h_gi.size(), [&](size_t k) {
             const GhostInterp &r = c->h_gi[k];
             if (!local_ok(c, r.dp, r.dl, false) || r.cp[0] < 0) return false;
@@ -978,14 +1006,14 @@ static int validate_tables(hsgn_ctx *c)
                 if (r.cp[s] >= 0 && !local_ok(c, r.cp[s], r.cl[s], true)) return false;
             return true;
         }))
-        return bad("ghost interpolation");
+        return "ghost interpolation";
     if (!all_of_parallel(c->h_fr.size(), [&](size_t k) {
             const FluxRec &r = c->h_fr[k];
             if (!local_ok(c, r.fp, r.gl, false) || !local_ok(c, r.cp, r.cl, true)) return false;
             const PatchInfo &F = c->patches[r.fp];
             return !(F.eoff < 0 || r.entry < 0 || r.entry >= 2 * (F.nx + F.ny));
         }))
-        return bad("flux record");
+        return "flux record";
     if (!all_of_parallel(c->h_rf.size(), [&](size_t k) {
             const RefluxRec &r = c->h_rf[k];
             if (!local_ok(c, r.cp, r.cl, true)) return false;
@@ -999,7 +1027,7 @@ static int validate_tables(hsgn_ctx *c)
             }
             return true;
         }))
-        return bad("reflux record");
+        return "reflux record";
     if (!all_of_parallel(c->h_av.size(), [&](size_t k) {
             const AvgRec &r = c->h_av[k];
             if (!local_ok(c, r.cp, r.cl, true)) return false;
@@ -1010,8 +1038,8 @@ static int validate_tables(hsgn_ctx *c)
                     if (!local_ok(c, r.fp, r.fl + a * F.pitch + b, true)) return false;
             return true;
         }))
-        return bad("average-down record");
-    return HSGN_OK;
+        return "average-down record";
+    return nullptr;
 }
 
 extern "C" {
@@ -1531,7 +1559,15 @@ int hsgn_finalize(hsgn_ctx *c)
             place(0, 1);
         }
     }
-    if ((rc = validate_tables(c))) return rc;
+    // the tables are checked on a host thread while the device buffers are
+    // allocated and the tables uploaded: no kernel reads them before the
+    // check has passed, and a failed check leaves the context unfinalized
+    const char *table_bad = nullptr;
+    std::thread checker([&]() { table_bad = table_error(c); });
+    struct JoinAtExit {
+        std::thread &t;
+        ~JoinAtExit() { if (t.joinable()) t.join(); }
+    } join_checker{checker};
     if (c->mixed) {
         HIPCHK(c, hipMalloc(&c->f0, sizeof(float) * c->qtotal));
         HIPCHK(c, hipMalloc(&c->f1, sizeof(float) * c->qtotal));
@@ -1611,6 +1647,8 @@ int hsgn_finalize(hsgn_ctx *c)
     HIPCHK(c, hipMemcpyAsync(c->d_scen, st.data(), sizeof(ScenState) * c->nslot,
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    checker.join();
+    if (table_bad) return fail(c, HSGN_EINVAL, std::string("internal table check: ") + table_bad);
     c->finalized = true;
     c->amr_dirty = c->any_amr;
     return HSGN_OK;
@@ -3131,6 +3169,21 @@ int rg_transfer(hsgn_ctx *c, hsgn_ctx *n, const std::vector<ScenState> &st_old,
         K.push_back(old_rec(pr.first, n->patches[pr.second], 0, 0, 0, 0, s.nx, s.ny, tk));
         tk += (long long)s.nx * s.ny;
     }
+    // the old level-(l+1) patches by bucket: a new patch meets only those of
+    // the buckets it reaches, taken in the order of old_fine
+    LevelIndex oidx;
+    std::vector<int> opos(c->patches.size(), -1);
+    if (!old_fine.empty()) {
+        const ScenHost &sh = c->scen[c->slot_scen[c->patches[old_fine[0]].scen]];
+        long long fl = 1;
+        for (int k = 0; k <= level; k++) fl *= AMR_RATIO;
+        oidx.init(c, (long long)sh.NX * fl, (long long)sh.NY * fl);
+        for (size_t k = 0; k < old_fine.size(); k++) {
+            oidx.add(old_fine[k]);
+            opos[old_fine[k]] = (int)k;
+        }
+    }
+    std::vector<int> near;
     // new patches from their parents, then old level-(l+1) overlaps
     std::vector<RegridInterp> I;
     std::vector<RegridCopy<S>> O;
@@ -3149,7 +3202,13 @@ int rg_transfer(hsgn_ctx *c, hsgn_ctx *n, const std::vector<ScenState> &st_old,
         r.c0 = ti;
         ti += (long long)r.fine.nx * r.fine.ny;
         I.push_back(r);
-        for (int op : old_fine) {
+        near.clear();
+        if (!old_fine.empty()) oidx.near(n->pI0[f], n->pJ0[f], r.fine.nx, r.fine.ny, near);
+        for (int &op : near) op = opos[op];
+        std::sort(near.begin(), near.end());
+        near.erase(std::unique(near.begin(), near.end()), near.end());
+        for (int k : near) {
+            const int op = old_fine[k];
             const PatchInfo &o = c->patches[op];
             const int ax0 = std::max(n->pI0[f], c->pI0[op]);
             const int ax1 = std::min(n->pI0[f] + r.fine.nx, c->pI0[op] + o.nx);
@@ -3161,7 +3220,6 @@ int rg_transfer(hsgn_ctx *c, hsgn_ctx *n, const std::vector<ScenState> &st_old,
             to += (long long)(ax1 - ax0) * (ay1 - ay0);
         }
     }
-    (void)level;
     RegridCopy<S> *dK = nullptr, *dO = nullptr;
     RegridInterp *dI = nullptr;
     int rc;
@@ -3264,24 +3322,36 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
         foff.push_back(ftot);
         ftot += (long long)c->patches[pid].nx * c->patches[pid].ny;
     }
-    uint8_t *dflag = nullptr;
-    HIPCHK(c, hipMalloc(&dflag, (size_t)std::max<long long>(ftot, 1)));
-    for (size_t k = 0; k < sh.lev[level].size(); k++) {
-        const PatchInfo &p = c->patches[sh.lev[level][k]];
-        const int cur = st[p.scen].cur;
-        if (c->mixed)
-            launch_regrid_flag32(p, cur ? c->f1 : c->f0, c->fbath, dflag + foff[k], c->prm.eta0,
-                                 c->prm.dry_tol, r->tol, c->stream);
-        else
-            launch_regrid_flag64(p, cur ? c->q1 : c->q0, c->bath, dflag + foff[k], c->prm.eta0,
-                                 c->prm.dry_tol, r->tol, c->stream);
+    // one launch: the patch records, then the flags, in one device buffer
+    // (the level-l patches share a clock slot, so one current buffer)
+    std::vector<FlagRec> frec(sh.lev[level].size());
+    for (size_t k = 0; k < frec.size(); k++) {
+        memset(&frec[k], 0, sizeof(FlagRec));
+        frec[k].p = c->patches[sh.lev[level][k]];
+        frec[k].c0 = foff[k];
     }
+    const int cur = frec.empty() ? 0 : st[c->patches[sh.lev[level][0]].scen].cur;
+    const size_t rbytes = (sizeof(FlagRec) * frec.size() + 255) / 256 * 256;
+    uint8_t *dbuf = nullptr;
+    HIPCHK(c, hipMalloc(&dbuf, rbytes + (size_t)std::max<long long>(ftot, 1)));
+    const FlagRec *drec = (const FlagRec *)dbuf;
+    uint8_t *dflag = dbuf + rbytes;
     std::vector<uint8_t> Fall((size_t)std::max<long long>(ftot, 1));
-    hipError_t fe = hipGetLastError();
+    hipError_t fe = hipMemcpyAsync(dbuf, frec.data(), sizeof(FlagRec) * frec.size(),
+                                   hipMemcpyHostToDevice, c->stream);
+    if (fe == hipSuccess) {
+        if (c->mixed)
+            launch_regrid_flag32(drec, (int)frec.size(), ftot, cur ? c->f1 : c->f0, c->fbath,
+                                 dflag, c->prm.eta0, c->prm.dry_tol, r->tol, c->stream);
+        else
+            launch_regrid_flag64(drec, (int)frec.size(), ftot, cur ? c->q1 : c->q0, c->bath,
+                                 dflag, c->prm.eta0, c->prm.dry_tol, r->tol, c->stream);
+        fe = hipGetLastError();
+    }
     if (fe == hipSuccess)
         fe = hipMemcpyAsync(Fall.data(), dflag, (size_t)ftot, hipMemcpyDeviceToHost, c->stream);
     if (fe == hipSuccess) fe = hipStreamSynchronize(c->stream);
-    (void)hipFree(dflag);
+    (void)hipFree(dbuf);
     if (fe != hipSuccess)
         return fail(c, HSGN_EDEVICE, std::string("regrid flags: ") + hipGetErrorString(fe));
     // buffer and clusters per level-l patch, on host threads, joined in

@@ -24,9 +24,13 @@
 #include <string>
 #include <vector>
 
+#include <condition_variable>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <thread>
+
+#include <unistd.h>
 
 #include "hsgn.h"
 #include "hsgn_amr.hpp"
@@ -422,12 +426,23 @@ struct LevelRange {
 };
 
 // host tables that are sized first and then filled: resize() leaves the new
-// records uninitialised instead of zeroing them
+// records uninitialised instead of zeroing them.  The memory is pinned, so
+// that uploads run as direct transfers; a regrid hands the old context's
+// tables to the new context, which reuses their memory.
 template <class T>
-struct DefaultInitAlloc : std::allocator<T> {
+struct DefaultInitAlloc {
+    using value_type = T;
     template <class U> struct rebind { using other = DefaultInitAlloc<U>; };
     DefaultInitAlloc() = default;
     template <class U> DefaultInitAlloc(const DefaultInitAlloc<U> &) noexcept {}
+    T *allocate(size_t n)
+    {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, n * sizeof(T), hipHostMallocDefault) != hipSuccess || !p)
+            throw std::bad_alloc();
+        return static_cast<T *>(p);
+    }
+    void deallocate(T *p, size_t) noexcept { (void)hipHostFree(p); }
     template <class U> void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value)
     {
         ::new (static_cast<void *>(p)) U;
@@ -436,6 +451,8 @@ struct DefaultInitAlloc : std::allocator<T> {
     {
         ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
     }
+    template <class U> bool operator==(const DefaultInitAlloc<U> &) const noexcept { return true; }
+    template <class U> bool operator!=(const DefaultInitAlloc<U> &) const noexcept { return false; }
 };
 template <class T> using HostVec = std::vector<T, DefaultInitAlloc<T>>;
 
@@ -501,8 +518,9 @@ struct hsgn_ctx {
     HostVec<GhostCopy> h_gc;
     HostVec<GhostInterp> h_gi;
     HostVec<FluxRec> h_fr;
-    HostVec<RefluxRec> h_rf;
+    std::vector<RefluxRec> h_rf;
     HostVec<AvgRec> h_av;
+    int ngc = 0, ngi = 0;           // ghost copy and interpolation records on the device
     GhostCopy *d_gc = nullptr;
     GhostInterp *d_gi = nullptr;
     FluxRec *d_fr = nullptr;
@@ -625,6 +643,99 @@ static AmrBuffers<S> amr_buffers(hsgn_ctx *c, S *q0, S *q1, S *bath)
     B.m0 = c->m0; B.m1 = c->m1;
     return B;
 }
+
+// ---------------------------------------------------------------------------
+// host worker threads for building and checking tables: a fixed set made on
+// first use in a process and never torn down (idle workers end with the
+// process; a forked child, which holds none of them, makes its own set).
+// parallel_for(n, fn) calls fn(t) once for every t < n, on the workers and
+// the calling thread, and returns when all calls are done.  Calls from
+// several threads take turns; fn must not call parallel_for.
+
+class HostPool {
+public:
+    static HostPool &get()
+    {
+        static std::mutex gm;
+        static HostPool *pool = nullptr;
+        std::lock_guard<std::mutex> lk(gm);
+        if (!pool || pool->pid != getpid()) pool = new HostPool();
+        return *pool;
+    }
+    int size() const { return (int)workers.size() + 1; }
+    void parallel_for(int n, const std::function<void(int)> &fn)
+    {
+        if (n <= 0) return;
+        if (n == 1 || workers.empty()) {
+            for (int t = 0; t < n; t++) fn(t);
+            return;
+        }
+        std::lock_guard<std::mutex> turn(call_m);
+        {
+            std::lock_guard<std::mutex> lk(m);
+            job = &fn;
+            ntask = n;
+            next = 0;
+            left = n;
+            gen++;
+        }
+        cv.notify_all();
+        drain();
+        std::unique_lock<std::mutex> lk(m);
+        done.wait(lk, [&] { return left == 0; });
+        job = nullptr;
+    }
+
+private:
+    HostPool() : pid(getpid())
+    {
+        const int hw = (int)std::thread::hardware_concurrency();
+        const int n = std::max(1, std::min(16, hw)) - 1;
+        for (int k = 0; k < n; k++) workers.emplace_back([this] { loop(); });
+    }
+    // take tasks of the current call until none is left
+    void drain()
+    {
+        for (;;) {
+            int t;
+            const std::function<void(int)> *f;
+            {
+                std::lock_guard<std::mutex> lk(m);
+                if (!job || next >= ntask) return;
+                t = next++;
+                f = job;
+            }
+            (*f)(t);
+            bool last;
+            {
+                std::lock_guard<std::mutex> lk(m);
+                last = --left == 0;
+            }
+            if (last) done.notify_all();
+        }
+    }
+    void loop()
+    {
+        unsigned long long seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(m);
+                cv.wait(lk, [&] { return gen != seen; });
+                seen = gen;
+            }
+            drain();
+        }
+    }
+    const pid_t pid;
+    std::mutex m, call_m;
+    std::condition_variable cv, done;
+    const std::function<void(int)> *job = nullptr;
+    int ntask = 0, next = 0, left = 0;
+    unsigned long long gen = 0;
+    std::vector<std::thread> workers;
+};
+
+static int host_threads() { return HostPool::get().size(); }
 
 // ---------------------------------------------------------------------------
 // patch-set geometry: which patch of a level covers a cell
@@ -831,22 +942,14 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                                   local_of(c->patches[cp], Ic - c->pI0[cp], Jc - c->pJ0[cp])});
             }
     };
-    const int hw = (int)std::thread::hardware_concurrency();
-    const int nthreads = std::max(1, std::min(16, hw));
+    const int nthreads = host_threads();
     for (int l = 0; l < nl; l++) {
         const std::vector<int> &L = sh.lev[l];
         std::vector<PatchRecs> recs(L.size());
-        auto work = [&](int t) {
-            for (size_t k = (size_t)t; k < L.size(); k += (size_t)nthreads) build_one(l, L[k], recs[k]);
-        };
-        if (nthreads > 1 && L.size() > 8) {
-            std::vector<std::thread> th;
-            for (int t = 0; t < nthreads; t++) th.emplace_back(work, t);
-            for (auto &x : th) x.join();
-        } else {
-            work(0);
-            for (int t = 1; t < nthreads; t++) work(t);
-        }
+        const int nt = L.size() > 8 ? nthreads : 1;
+        HostPool::get().parallel_for(nt, [&](int t) {
+            for (size_t k = (size_t)t; k < L.size(); k += (size_t)nt) build_one(l, L[k], recs[k]);
+        });
         for (auto &r : recs)
             if (r.err) return fail(c, HSGN_EINVAL, r.err);
         for (auto &r : recs) lev_recs[l].push_back(std::move(r));
@@ -931,13 +1034,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                     if (any) part[t].push_back(r);
                 }
             };
-            if (nt > 1) {
-                std::vector<std::thread> th;
-                for (int t = 0; t < nt; t++) th.emplace_back(reflux_chunk, t);
-                for (auto &x : th) x.join();
-            } else {
-                reflux_chunk(0);
-            }
+            HostPool::get().parallel_for(nt, reflux_chunk);
             for (auto &v : part) lev_rf[l].insert(lev_rf[l].end(), v.begin(), v.end());
         }
     }
@@ -963,20 +1060,12 @@ static bool local_ok(const hsgn_ctx *c, int pid, int local, bool interior)
 template <class F>
 static bool all_of_parallel(size_t n, F ok)
 {
-    const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
-    if (nt == 1 || n < 4096) {
-        for (size_t k = 0; k < n; k++)
-            if (!ok(k)) return false;
-        return true;
-    }
+    const int nt = n < 4096 ? 1 : host_threads();
     std::vector<char> good(nt, 1);
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; t++)
-        th.emplace_back([&, t]() {
-            for (size_t k = (size_t)t; k < n; k += (size_t)nt)
-                if (!ok(k)) { good[t] = 0; return; }
-        });
-    for (auto &x : th) x.join();
+    HostPool::get().parallel_for(nt, [&](int t) {
+        for (size_t k = (size_t)t; k < n; k += (size_t)nt)
+            if (!ok(k)) { good[t] = 0; return; }
+    });
     for (char g : good)
         if (!g) return false;
     return true;
@@ -1533,7 +1622,19 @@ int hsgn_finalize(hsgn_ctx *c)
             nrf += lrf[l].size();
             R.rf1 = (int)nrf;
         }
-        c->h_gc.resize(ngc); c->h_gi.resize(ngi); c->h_fr.resize(nfr); c->h_av.resize(nav);
+        // sized without zeroing; memory lent by the context this one replaces
+        // is reused, a table that outgrows it gets a quarter to spare
+        auto size_table = [](auto &v, size_t n) {
+            v.clear();
+            if (v.capacity() < n) v.reserve(n + n / 4);
+            v.resize(n);
+        };
+        size_table(c->h_gc, ngc);
+        size_table(c->h_gi, ngi);
+        size_table(c->h_fr, nfr);
+        size_table(c->h_av, nav);
+        c->ngc = (int)ngc;
+        c->ngi = (int)ngi;
         c->h_rf.clear();
         c->h_rf.reserve(nrf);
         for (int l = 0; l < c->nlev; l++) c->h_rf.insert(c->h_rf.end(), lrf[l].begin(), lrf[l].end());
@@ -1550,14 +1651,8 @@ int hsgn_finalize(hsgn_ctx *c)
                 std::copy(r.av.begin(), r.av.end(), c->h_av.begin() + o.av);
             }
         };
-        const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
-        if (nt > 1 && jobs.size() > 64) {
-            std::vector<std::thread> th;
-            for (int t = 0; t < nt; t++) th.emplace_back(place, t, nt);
-            for (auto &x : th) x.join();
-        } else {
-            place(0, 1);
-        }
+        const int nt = jobs.size() > 64 ? host_threads() : 1;
+        HostPool::get().parallel_for(nt, [&](int t) { place(t, nt); });
     }
     // the tables are checked on a host thread while the device buffers are
     // allocated and the tables uploaded: no kernel reads them before the
@@ -1722,7 +1817,7 @@ static int ensure_prepared(hsgn_ctx *c)
             launch_avgdown64(amr_buffers<double>(c, c->q0, c->q1, c->bath), c->d_av + R.av0,
                              R.av1 - R.av0, true, c->stream);
     }
-    int nc = (int)c->h_gc.size(), ni = (int)c->h_gi.size();
+    const int nc = c->ngc, ni = c->ngi;
     if (c->mixed)
         launch_ghost_bath32(amr_buffers<float>(c, c->f0, c->f1, c->fbath), c->d_gc, nc, c->d_gi, ni,
                             c->stream);
@@ -3381,17 +3476,10 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
         }
     };
     {
-        const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
-        if (nt > 1 && np_l > 8) {
-            std::vector<std::thread> th;
-            for (int t = 0; t < nt; t++)
-                th.emplace_back([&, t]() {
-                    for (size_t k = (size_t)t; k < np_l; k += (size_t)nt) cluster_one(k);
-                });
-            for (auto &x : th) x.join();
-        } else {
-            for (size_t k = 0; k < np_l; k++) cluster_one(k);
-        }
+        const int nt = np_l > 8 ? host_threads() : 1;
+        HostPool::get().parallel_for(nt, [&](int t) {
+            for (size_t k = (size_t)t; k < np_l; k += (size_t)nt) cluster_one(k);
+        });
     }
     for (auto &v : pboxes) boxes.insert(boxes.end(), v.begin(), v.end());
     // 5. the new context: every patch of the other scenarios, the levels <= l
@@ -3434,6 +3522,12 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
         fresh.push_back({id, newid[b.parent]});
         fresh_ids.push_back(id);
     }
+    // the old context's host tables lend their memory to the new context's
+    // (the old one keeps its device tables and record counts)
+    n->h_gc.swap(c->h_gc);
+    n->h_gi.swap(c->h_gi);
+    n->h_fr.swap(c->h_fr);
+    n->h_av.swap(c->h_av);
     if ((rc = hsgn_finalize(n))) return bail(rc, "regrid: finalize");
     n->timing = c->timing;
     for (size_t s = 0; s < c->scen.size() && s < n->scen.size(); s++) {

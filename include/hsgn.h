@@ -29,7 +29,9 @@
  *     steps partly on a second stream joined back into it (hsgn_create).
  *   - A context owns its device buffers: two state buffers (the step reads
  *     one and writes the other), bathymetry, two mask buffers, per-scenario
- *     clocks and gauge records.
+ *     clocks and gauge records.  Its patch-set tables (ghost cells, boundary
+ *     fluxes, covered cells; 16 to 56 bytes per record) are kept in pinned
+ *     host memory too, or ordinary memory where pinning fails.
  *   - A scenario is an independent simulation with its own clock and time
  *     step; each patch belongs to one scenario.
  *   - Patch sets (static AMR, the block-structured refinement of Sec. 4): a
@@ -134,6 +136,8 @@ typedef struct hsgn_ctx hsgn_ctx;
  * refinement level, into one wavefront's work item (mapped patch sets in
  * mixed precision excepted); HSGN_NO_PACKING=1, read here, gives every
  * strip its own (a diagnostic: the state is the same bit for bit).
+ * HSGN_PAGEABLE_TABLES=1, read whenever a table grows, keeps the patch-set
+ * tables in ordinary host memory instead of pinned memory (a diagnostic).
  * Errors: EINVAL (bad parameters), ENOTSUP (model/precision), EDEVICE. */
 int hsgn_create(const hsgn_params *p, void *hip_stream, hsgn_ctx **out);
 

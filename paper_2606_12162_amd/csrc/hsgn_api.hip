@@ -28,6 +28,7 @@
 #include <functional>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 
 #include <unistd.h>
@@ -425,24 +426,60 @@ struct LevelRange {
     long long e0 = 0, e1 = 0;       // boundary-flux entries (7-vectors)
 };
 
+// host memory of the tables below: pinned, so that uploads run as direct
+// transfers; where pinning fails, ordinary memory, remembered here so that it
+// is freed the same way (HSGN_PAGEABLE_TABLES=1 takes ordinary memory
+// always: a diagnostic, results are the same bit for bit)
+struct TableMemory {
+    static void *get(size_t bytes)
+    {
+        void *p = nullptr;
+        const char *pageable = getenv("HSGN_PAGEABLE_TABLES");
+        if (!(pageable && pageable[0] == '1')) {
+            if (hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess && p) return p;
+            (void)hipGetLastError();        // the failure must not reach a later check
+        }
+        p = ::operator new(bytes);
+        std::lock_guard<std::mutex> lk(m());
+        plain().insert(p);
+        return p;
+    }
+    static void put(void *p)
+    {
+        {
+            std::lock_guard<std::mutex> lk(m());
+            auto it = plain().find(p);
+            if (it != plain().end()) {
+                plain().erase(it);
+                ::operator delete(p);
+                return;
+            }
+        }
+        (void)hipHostFree(p);
+    }
+    static std::mutex &m()
+    {
+        static std::mutex x;
+        return x;
+    }
+    static std::set<void *> &plain()
+    {
+        static std::set<void *> x;
+        return x;
+    }
+};
+
 // host tables that are sized first and then filled: resize() leaves the new
-// records uninitialised instead of zeroing them.  The memory is pinned, so
-// that uploads run as direct transfers; a regrid hands the old context's
-// tables to the new context, which reuses their memory.
+// records uninitialised instead of zeroing them.  A regrid hands the old
+// context's tables to the new context, which reuses their memory.
 template <class T>
 struct DefaultInitAlloc {
     using value_type = T;
     template <class U> struct rebind { using other = DefaultInitAlloc<U>; };
     DefaultInitAlloc() = default;
     template <class U> DefaultInitAlloc(const DefaultInitAlloc<U> &) noexcept {}
-    T *allocate(size_t n)
-    {
-        void *p = nullptr;
-        if (hipHostMalloc(&p, n * sizeof(T), hipHostMallocDefault) != hipSuccess || !p)
-            throw std::bad_alloc();
-        return static_cast<T *>(p);
-    }
-    void deallocate(T *p, size_t) noexcept { (void)hipHostFree(p); }
+    T *allocate(size_t n) { return static_cast<T *>(TableMemory::get(n * sizeof(T))); }
+    void deallocate(T *p, size_t) noexcept { TableMemory::put(p); }
     template <class U> void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value)
     {
         ::new (static_cast<void *>(p)) U;

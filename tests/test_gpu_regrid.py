@@ -232,3 +232,25 @@ def test_full_size_ocean_regrid_matches_oracle_clusters():
     err = np.abs(gauges[1] - gauges[0]).max() / w.amplitude
     print("mixed vs FP64 gauge error / amplitude", err)
     assert err <= 1e-4
+
+
+def test_tables_in_ordinary_memory_give_the_same_state(monkeypatch):
+    """the patch-set tables in ordinary host memory (HSGN_PAGEABLE_TABLES=1)
+    instead of pinned memory: the same patches and the same state bit for
+    bit through regrids of levels 0 and 1, in both precisions"""
+    w = W.amr_small(steps=2)
+    for precision in (0, 1):
+        runs = []
+        for pageable in ("0", "1"):
+            monkeypatch.setenv("HSGN_PAGEABLE_TABLES", pageable)
+            print("case tables pageable", pageable, "precision", precision, flush=True)
+            ctx, ids = H.from_amr_workloads([w], precision=precision)
+            ctx.advance(-1.0, 1)
+            for level in (0, 1):
+                plist = ctx.regrid(0, level, tol=RTOL, nbuf=2)
+                ctx.advance(-1.0, 1)
+            runs.append((plist, [ctx.get_state(k) for k in range(len(plist))]))
+            ctx.close()
+        assert runs[0][0] == runs[1][0]
+        for a, b in zip(runs[0][1], runs[1][1]):
+            assert np.array_equal(a, b)

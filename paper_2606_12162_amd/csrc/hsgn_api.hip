@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -520,6 +521,7 @@ struct hsgn_ctx {
     double *q0 = nullptr, *q1 = nullptr, *bath = nullptr, *clip = nullptr, *rec = nullptr;
     float *f0 = nullptr, *f1 = nullptr, *fbath = nullptr;
     double *stage = nullptr;    // FP64 staging for conversions at the ABI
+    void *arena = nullptr;      // one allocation holding the buffers fixed at finalize
     long long stage_len = 0;
     uint8_t *m0 = nullptr, *m1 = nullptr;
     PatchInfo *d_patches = nullptr;
@@ -618,12 +620,9 @@ static void free_device(hsgn_ctx *c)
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     c->aux_stream = nullptr;
     c->ev_fork = c->ev_join = nullptr;
-    void *ptrs[] = {c->q0, c->q1, c->bath, c->clip, c->rec, c->m0, c->m1, c->d_patches,
-                    c->d_work, c->d_scen, c->d_sstat, c->d_gauges, c->d_slots, c->d_err,
-                    c->d_mass, c->f0, c->f1, c->fbath, c->stage, c->d_cnt, c->d_gc, c->d_gi,
-                    c->d_fr, c->d_rf, c->d_av, c->d_E, c->d_R, c->d_rclip, c->d_list,
-                    c->d_lcnt, c->d_clsb, c->d_cls, c->d_keep, c->d_B0, c->d_packs,
-                    c->d_latch};
+    // the buffers fixed at finalize go with the arena
+    void *ptrs[] = {c->arena, c->clip, c->rec, c->d_work, c->d_gauges, c->d_list, c->d_clsb,
+                    c->d_cls, c->d_B0, c->d_packs};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *m : c->d_metric)
@@ -641,6 +640,7 @@ static void free_device(hsgn_ctx *c)
     c->d_B0 = nullptr;
     c->d_packs = nullptr;
     c->d_latch = nullptr;
+    c->arena = nullptr;
     c->b0_scen = -1;
     c->d_lcnt = nullptr;
 }
@@ -1081,13 +1081,29 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
 // every table entry addresses cells inside its patch's storage (interior or
 // ghost frame as required) and entries inside the flux buffer: checked on
 // the host before any kernel reads a table
+// the cell (i, j) that a local index of a patch addresses (false: before the
+// patch's storage); 32-bit division where the storage allows it
+static bool cell_of(const PatchInfo &p, int local, long long &i, long long &j)
+{
+    const long long base = (long long)local + (long long)p.frame * p.pitch + p.frame;
+    if (base < 0) return false;
+    if (base <= INT_MAX && p.pitch <= INT_MAX) {
+        const int b = (int)base, w = (int)p.pitch;
+        i = b % w - p.frame;
+        j = b / w - p.frame;
+    } else {
+        i = base % p.pitch - p.frame;
+        j = base / p.pitch - p.frame;
+    }
+    return true;
+}
+
 static bool local_ok(const hsgn_ctx *c, int pid, int local, bool interior)
 {
     if (pid < 0 || pid >= (int)c->patches.size()) return false;
     const PatchInfo &p = c->patches[pid];
-    long long base = (long long)local + (long long)p.frame * p.pitch + p.frame;
-    if (base < 0) return false;
-    long long i = base % p.pitch - p.frame, j = base / p.pitch - p.frame;
+    long long i, j;
+    if (!cell_of(p, local, i, j)) return false;
     if (interior) return i >= 0 && i < p.nx && j >= 0 && j < p.ny;
     return i >= -p.frame && i < p.nx + p.frame && j >= -p.frame && j < p.ny + p.frame &&
            !(i >= 0 && i < p.nx && j >= 0 && j < p.ny);
@@ -1114,10 +1130,9 @@ static const char *table_error(const hsgn_ctx *c)
     // a cell of a patch's frame (interior or ghost), for the wall edges
     auto in_frame = [&](int pid, int local) {
         const PatchInfo &p = c->patches[pid];
-        long long base = (long long)local + (long long)p.frame * p.pitch + p.frame;
-        if (base < 0) return false;
-        long long i = base % p.pitch - p.frame, j = base / p.pitch - p.frame;
-        return i >= -p.frame && i < p.nx + p.frame && j >= -p.frame && j < p.ny + p.frame;
+        long long i, j;
+        return cell_of(p, local, i, j) && i >= -p.frame && i < p.nx + p.frame &&
+               j >= -p.frame && j < p.ny + p.frame;
     };
     if (!all_of_parallel(c->h_gc.size(), [&](size_t k) {
             const GhostCopy &r = c->h_gc[k];
@@ -1158,11 +1173,12 @@ static const char *table_error(const hsgn_ctx *c)
             const AvgRec &r = c->h_av[k];
             if (!local_ok(c, r.cp, r.cl, true)) return false;
             if (r.fp < 0 || r.fp >= (int)c->patches.size()) return false;
+            // the ratio x ratio block of fine cells from fl lies in the
+            // interior, as its corners do
             const PatchInfo &F = c->patches[r.fp];
-            for (int a = 0; a < AMR_RATIO; a++)
-                for (int b = 0; b < AMR_RATIO; b++)
-                    if (!local_ok(c, r.fp, r.fl + a * F.pitch + b, true)) return false;
-            return true;
+            long long i, j;
+            return cell_of(F, r.fl, i, j) && i >= 0 && j >= 0 && i + AMR_RATIO <= F.nx &&
+                   j + AMR_RATIO <= F.ny;
         }))
         return "average-down record";
     return nullptr;
@@ -1561,12 +1577,12 @@ static int check_scenarios(hsgn_ctx *c)
 
 }  // extern "C"
 
+// a host table into its device buffer (on the context's stream)
 template <class T, class A>
-static int upload(hsgn_ctx *c, T **d, const std::vector<T, A> &h)
+static int upload(hsgn_ctx *c, T *d, const std::vector<T, A> &h)
 {
     if (h.empty()) return HSGN_OK;
-    HIPCHK(c, hipMalloc(d, sizeof(T) * h.size()));
-    HIPCHK(c, hipMemcpyAsync(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, c->stream));
     return HSGN_OK;
 }
 
@@ -1700,70 +1716,92 @@ int hsgn_finalize(hsgn_ctx *c)
         std::thread &t;
         ~JoinAtExit() { if (t.joinable()) t.join(); }
     } join_checker{checker};
-    if (c->mixed) {
-        HIPCHK(c, hipMalloc(&c->f0, sizeof(float) * c->qtotal));
-        HIPCHK(c, hipMalloc(&c->f1, sizeof(float) * c->qtotal));
-        HIPCHK(c, hipMalloc(&c->fbath, sizeof(float) * c->ctotal));
-        HIPCHK(c, hipMemsetAsync(c->f0, 0, sizeof(float) * c->qtotal, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->f1, 0, sizeof(float) * c->qtotal, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->fbath, 0, sizeof(float) * c->ctotal, c->stream));
-    } else {
-        HIPCHK(c, hipMalloc(&c->q0, sizeof(double) * c->qtotal));
-        HIPCHK(c, hipMalloc(&c->q1, sizeof(double) * c->qtotal));
-        HIPCHK(c, hipMalloc(&c->bath, sizeof(double) * c->ctotal));
-        HIPCHK(c, hipMemsetAsync(c->q0, 0, sizeof(double) * c->qtotal, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->q1, 0, sizeof(double) * c->qtotal, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->bath, 0, sizeof(double) * c->ctotal, c->stream));
-    }
+    // the buffers fixed here share one device allocation, freed at once with
+    // the context; the work-table buffers (which the tile-height tuner
+    // replaces) and the gauge buffers are allocated on their own
     long long big = 0;
     for (const PatchInfo &p : c->patches) big = std::max<long long>(big, 7LL * p.nx * p.ny);
     c->stage_len = big;
-    HIPCHK(c, hipMalloc(&c->stage, sizeof(double) * big));
-    HIPCHK(c, hipMalloc(&c->m0, c->ctotal));
-    HIPCHK(c, hipMalloc(&c->m1, c->ctotal));
-    HIPCHK(c, hipMalloc(&c->clip, sizeof(double) * std::max<size_t>(c->work.size(), 1)));
-    HIPCHK(c, hipMalloc(&c->d_patches, sizeof(PatchInfo) * c->patches.size()));
-    HIPCHK(c, hipMalloc(&c->d_keep, c->patches.size()));
+    char *base = nullptr;
+    size_t off = 0;
+    auto carve = [&](auto *&ptr, size_t n) {
+        using T = std::remove_reference_t<decltype(*ptr)>;
+        const size_t bytes = sizeof(T) * n;
+        ptr = base && bytes ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += (bytes + 255) / 256 * 256;
+    };
+    auto carve_all = [&]() {
+        off = 0;
+        if (c->mixed) {
+            carve(c->f0, (size_t)c->qtotal);
+            carve(c->f1, (size_t)c->qtotal);
+            carve(c->fbath, (size_t)c->ctotal);
+        } else {
+            carve(c->q0, (size_t)c->qtotal);
+            carve(c->q1, (size_t)c->qtotal);
+            carve(c->bath, (size_t)c->ctotal);
+        }
+        carve(c->stage, (size_t)big);
+        carve(c->m0, (size_t)c->ctotal);
+        carve(c->m1, (size_t)c->ctotal);
+        carve(c->d_patches, c->patches.size());
+        carve(c->d_keep, c->patches.size());
+        carve(c->d_lcnt, 2);
+        // the classes of a context of single grids change within an advance
+        // only where a cell latches (patch sets also take masks from other
+        // levels' and patches' cells into their ghost frames: they classify
+        // every attempt)
+        carve(c->d_latch, c->split && !c->any_amr ? 1 : 0);
+        carve(c->d_scen, (size_t)c->nslot);
+        carve(c->d_sstat, (size_t)c->nslot);
+        carve(c->d_slots, (size_t)c->nslot);
+        carve(c->d_cnt, 2);
+        carve(c->d_err, 1);
+        carve(c->d_mass, 2);
+        carve(c->d_E, 7 * (size_t)c->etotal);
+        carve(c->d_R, 7 * (size_t)c->etotal);
+        carve(c->d_rclip, c->h_rf.size());
+        carve(c->d_gc, c->h_gc.size());
+        carve(c->d_gi, c->h_gi.size());
+        carve(c->d_fr, c->h_fr.size());
+        carve(c->d_rf, c->h_rf.size());
+        carve(c->d_av, c->h_av.size());
+    };
+    carve_all();                                  // sizes
+    HIPCHK(c, hipMalloc(&c->arena, std::max<size_t>(off, 256)));
+    base = static_cast<char *>(c->arena);
+    carve_all();                                  // addresses
+    const size_t sq = c->mixed ? sizeof(float) : sizeof(double);
+    HIPCHK(c, hipMemsetAsync(c->mixed ? (void *)c->f0 : (void *)c->q0, 0, sq * c->qtotal, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->mixed ? (void *)c->f1 : (void *)c->q1, 0, sq * c->qtotal, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->mixed ? (void *)c->fbath : (void *)c->bath, 0, sq * c->ctotal,
+                             c->stream));
+    HIPCHK(c, hipMemsetAsync(c->m0, 0, c->ctotal, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->m1, 0, c->ctotal, c->stream));
+    if (c->etotal > 0) {
+        HIPCHK(c, hipMemsetAsync(c->d_E, 0, sizeof(double) * 7 * c->etotal, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->d_R, 0, sizeof(double) * 7 * c->etotal, c->stream));
+    }
+    if (!c->h_rf.empty())
+        HIPCHK(c, hipMemsetAsync(c->d_rclip, 0, sizeof(double) * c->h_rf.size(), c->stream));
     c->state_set.assign(c->patches.size(), 0);
+    HIPCHK(c, hipMalloc(&c->clip, sizeof(double) * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(WorkItem) * c->work.size()));
     HIPCHK(c, hipMalloc(&c->d_packs, sizeof(PackedItem) * std::max<size_t>(c->packs.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_list, sizeof(int) * 2 * std::max<size_t>(c->work.size(), 1)));
-    HIPCHK(c, hipMalloc(&c->d_lcnt, sizeof(unsigned) * 2));
     HIPCHK(c, hipMalloc(&c->d_cls, sizeof(int) * std::max<size_t>(c->work.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_clsb, sizeof(int) * std::max<size_t>(c->work.size(), 1)));
+    HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * std::max<size_t>(c->work.size(), 1),
+                             c->stream));
     c->clsb_dirty = true;
-    // the classes of a context of single grids change within an advance only
-    // where a cell latches (patch sets also take masks from other levels'
-    // and patches' cells into their ghost frames: they classify every attempt)
-    if (c->split && !c->any_amr) HIPCHK(c, hipMalloc(&c->d_latch, sizeof(int)));
     if (c->split) {
         HIPCHK(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
         HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     }
-    HIPCHK(c, hipMalloc(&c->d_scen, sizeof(ScenState) * c->nslot));
-    HIPCHK(c, hipMalloc(&c->d_sstat, sizeof(ScenStatic) * c->nslot));
-    HIPCHK(c, hipMalloc(&c->d_slots, sizeof(unsigned long long) * c->nslot));
-    HIPCHK(c, hipMalloc(&c->d_cnt, sizeof(unsigned long long) * 2));
-    HIPCHK(c, hipMalloc(&c->d_err, sizeof(int)));
-    HIPCHK(c, hipMalloc(&c->d_mass, sizeof(double) * 2));
-    HIPCHK(c, hipMemsetAsync(c->m0, 0, c->ctotal, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->m1, 0, c->ctotal, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->clip, 0, sizeof(double) * std::max<size_t>(c->work.size(), 1),
-                             c->stream));
-    if (c->etotal > 0) {
-        HIPCHK(c, hipMalloc(&c->d_E, sizeof(double) * 7 * c->etotal));
-        HIPCHK(c, hipMalloc(&c->d_R, sizeof(double) * 7 * c->etotal));
-        HIPCHK(c, hipMemsetAsync(c->d_E, 0, sizeof(double) * 7 * c->etotal, c->stream));
-        HIPCHK(c, hipMemsetAsync(c->d_R, 0, sizeof(double) * 7 * c->etotal, c->stream));
-    }
-    if (!c->h_rf.empty()) {
-        HIPCHK(c, hipMalloc(&c->d_rclip, sizeof(double) * c->h_rf.size()));
-        HIPCHK(c, hipMemsetAsync(c->d_rclip, 0, sizeof(double) * c->h_rf.size(), c->stream));
-    }
-    if ((rc = upload(c, &c->d_gc, c->h_gc)) || (rc = upload(c, &c->d_gi, c->h_gi)) ||
-        (rc = upload(c, &c->d_fr, c->h_fr)) || (rc = upload(c, &c->d_rf, c->h_rf)) ||
-        (rc = upload(c, &c->d_av, c->h_av)))
+    if ((rc = upload(c, c->d_gc, c->h_gc)) || (rc = upload(c, c->d_gi, c->h_gi)) ||
+        (rc = upload(c, c->d_fr, c->h_fr)) || (rc = upload(c, c->d_rf, c->h_rf)) ||
+        (rc = upload(c, c->d_av, c->h_av)))
         return rc;
     HIPCHK(c, hipMemcpyAsync(c->d_patches, c->patches.data(), sizeof(PatchInfo) * c->patches.size(),
                              hipMemcpyHostToDevice, c->stream));
@@ -3494,14 +3532,31 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
         const int pid = sh.lev[level][k];
         const PatchInfo &p = c->patches[pid];
         const uint8_t *F = Fall.data() + foff[k];
-        std::vector<uint8_t> B(F, F + (long long)p.nx * p.ny);
-        for (int j = 0; j < p.ny; j++)
-            for (int i = 0; i < p.nx; i++) {
-                if (!F[(size_t)j * p.nx + i]) continue;
-                for (int b = std::max(0, j - r->nbuf); b <= std::min(p.ny - 1, j + r->nbuf); b++)
-                    for (int a = std::max(0, i - r->nbuf); a <= std::min(p.nx - 1, i + r->nbuf); a++)
-                        B[(size_t)b * p.nx + a] = 1;
+        // the buffer: flags dilated by nbuf cells in the max norm (within the
+        // patch), as a pass along rows and one along columns, each counting
+        // the flags in its sliding window
+        const int nx = p.nx, ny = p.ny, nb = r->nbuf;
+        std::vector<uint8_t> R((size_t)nx * ny), B((size_t)nx * ny);
+        for (int j = 0; j < ny; j++) {
+            const uint8_t *f = F + (size_t)j * nx;
+            int cnt = 0;
+            for (int a = 0; a < std::min(nb, nx); a++) cnt += f[a] != 0;
+            for (int i = 0; i < nx; i++) {
+                if (i + nb < nx) cnt += f[i + nb] != 0;
+                if (i - nb - 1 >= 0) cnt -= f[i - nb - 1] != 0;
+                R[(size_t)j * nx + i] = cnt > 0;
             }
+        }
+        std::vector<int> col(nx, 0);
+        for (int b = 0; b < std::min(nb, ny); b++)
+            for (int i = 0; i < nx; i++) col[i] += R[(size_t)b * nx + i];
+        for (int j = 0; j < ny; j++) {
+            if (j + nb < ny)
+                for (int i = 0; i < nx; i++) col[i] += R[(size_t)(j + nb) * nx + i];
+            if (j - nb - 1 >= 0)
+                for (int i = 0; i < nx; i++) col[i] -= R[(size_t)(j - nb - 1) * nx + i];
+            for (int i = 0; i < nx; i++) B[(size_t)j * nx + i] = col[i] > 0;
+        }
         std::vector<RgBox> cl;
         rg_cluster(B, p.nx, 0, p.nx, 0, p.ny, r->cutoff, r->max_side, cl);
         for (const RgBox &x : cl) {

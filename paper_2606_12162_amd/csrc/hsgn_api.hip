@@ -820,6 +820,20 @@ struct LevelIndex {
         }
         return -1;
     }
+    // the same, trying the patch of the caller's last hit first (patches of
+    // a level do not overlap and lie inside its domain: the answer is the
+    // same)
+    int find(long long I, long long J, int &hint) const
+    {
+        if (hint >= 0) {
+            const PatchInfo &p = c->patches[hint];
+            long long I0 = c->pI0[hint], J0 = c->pJ0[hint];
+            if (I >= I0 && I < I0 + p.nx && J >= J0 && J < J0 + p.ny) return hint;
+        }
+        const int pid = find(I, J);
+        if (pid >= 0) hint = pid;
+        return pid;
+    }
 };
 
 static int host_map(int i, int n, int lo, int hi, int *flip)
@@ -893,9 +907,6 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
     for (int pid : sh.lev[0]) area += (long long)c->patches[pid].nx * c->patches[pid].ny;
     if (area != (long long)sh.NX * sh.NY)
         return fail(c, HSGN_EINVAL, "level-0 patches must tile a rectangle");
-    auto covered = [&](int l, long long I, long long J) {
-        return l + 1 < nl && idx[l + 1].find(AMR_RATIO * I, AMR_RATIO * J) >= 0;
-    };
     // per patch: ghost, boundary-flux and covered-cell records.  Patches are
     // independent (the indexes are read only), so they are built on host
     // threads and kept in patch order: the tables do not depend on the
@@ -903,6 +914,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
     auto build_one = [&](int l, int pid, PatchRecs &out) {
         const PatchInfo &P = c->patches[pid];
         const long long I0 = c->pI0[pid], J0 = c->pJ0[pid];
+        int h_same = -1, h_coarse[5] = {-1, -1, -1, -1, -1};      // last hits of find
         // ghost cells
         for (int j = -2; j < P.ny + 2; j++)
             for (int i = -2; i < P.nx + 2; i++) {
@@ -912,7 +924,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                     int fx, fy;
                     int mi = host_map((int)I, sh.NX, sh.bc[0], sh.bc[1], &fx);
                     int mj = host_map((int)J, sh.NY, sh.bc[2], sh.bc[3], &fy);
-                    int sp = idx[0].find(mi, mj);
+                    int sp = idx[0].find(mi, mj, h_same);
                     if (sp < 0) { out.err = "level-0 patches leave a hole"; return; }
                     // mapped walls: the domain edge of the source cell's row
                     // (x) or column (y), as the left (bottom) edge of a cell
@@ -927,7 +939,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                                       fy ? local_of(Sp, mi - c->pI0[sp], wj) : 0});
                     continue;
                 }
-                int sp = idx[l].find(I, J);
+                int sp = idx[l].find(I, J, h_same);
                 if (sp >= 0) {
                     out.gc.push_back({pid, local_of(P, i, j), sp,
                                       local_of(c->patches[sp], I - c->pI0[sp], J - c->pJ0[sp]), 0,
@@ -940,7 +952,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                 g.dl = local_of(P, i, j);
                 const long long nb[5][2] = {{Ic, Jc}, {Ic - 1, Jc}, {Ic + 1, Jc}, {Ic, Jc - 1}, {Ic, Jc + 1}};
                 for (int k = 0; k < 5; k++) {
-                    int cp = idx[l - 1].find(nb[k][0], nb[k][1]);
+                    int cp = idx[l - 1].find(nb[k][0], nb[k][1], h_coarse[k]);
                     g.cp[k] = cp;
                     g.cl[k] = cp >= 0 ? local_of(c->patches[cp], nb[k][0] - c->pI0[cp],
                                                  nb[k][1] - c->pJ0[cp]) : 0;
@@ -958,9 +970,9 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                 int gi_ = side == 0 ? -1 : side == 1 ? P.nx : k;
                 int gj_ = side < 2 ? k : side == 2 ? -1 : P.ny;
                 long long I = I0 + gi_, J = J0 + gj_;
-                if (idx[l].find(I, J) >= 0) continue;
+                if (idx[l].find(I, J, h_same) >= 0) continue;
                 long long Ic = LevelIndex::fdiv(I, AMR_RATIO), Jc = LevelIndex::fdiv(J, AMR_RATIO);
-                int cp = idx[l - 1].find(Ic, Jc);
+                int cp = idx[l - 1].find(Ic, Jc, h_coarse[0]);
                 if (cp < 0) { out.err = "refined patch not properly nested"; return; }
                 int entry = side == 0 ? k : side == 1 ? P.ny + k : side == 2 ? 2 * P.ny + k
                                                                                : 2 * P.ny + P.nx + k;
@@ -973,7 +985,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
         for (int jj = 0; jj < P.ny / AMR_RATIO; jj++)
             for (int ii = 0; ii < P.nx / AMR_RATIO; ii++) {
                 long long Ic = I0 / AMR_RATIO + ii, Jc = J0 / AMR_RATIO + jj;
-                int cp = idx[l - 1].find(Ic, Jc);
+                int cp = idx[l - 1].find(Ic, Jc, h_coarse[0]);
                 if (cp < 0) { out.err = "refined patch outside the coarser level"; return; }
                 out.av.push_back({pid, local_of(P, AMR_RATIO * ii, AMR_RATIO * jj), cp,
                                   local_of(c->patches[cp], Ic - c->pI0[cp], Jc - c->pJ0[cp])});
@@ -1040,10 +1052,14 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
             const int nt = ncand >= 4096 ? nthreads : 1;
             std::vector<std::vector<RefluxRec>> part(nt);
             auto reflux_chunk = [&](int t) {
+                int h_c = -1, h_f = -1, h_cov = -1;               // last hits of find
+                auto covered_h = [&](long long I, long long J) {
+                    return idx[l + 1].find(AMR_RATIO * I, AMR_RATIO * J, h_cov) >= 0;
+                };
                 for (size_t kc = ncand * t / nt; kc < ncand * (t + 1) / nt; kc++) {
                     long long J = cand[kc].first, I = cand[kc].second;
-                    int cp = idx[l].find(I, J);
-                    if (cp < 0 || covered(l, I, J)) continue;
+                    int cp = idx[l].find(I, J, h_c);
+                    if (cp < 0 || covered_h(I, J)) continue;
                     RefluxRec r;
                     r.cp = cp;
                     r.cl = local_of(c->patches[cp], I - c->pI0[cp], J - c->pJ0[cp]);
@@ -1052,13 +1068,13 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
                     for (int e = 0; e < 4; e++) {
                         r.fp[e] = -1;
                         r.e0[e] = 0;
-                        if (!covered(l, nb[e][0], nb[e][1])) continue;
+                        if (!covered_h(nb[e][0], nb[e][1])) continue;
                         // a fine cell just across the edge
                         long long fi = e == 0 ? AMR_RATIO * I - 1
                                      : e == 1 ? AMR_RATIO * (I + 1) : AMR_RATIO * I;
                         long long fj = e == 2 ? AMR_RATIO * J - 1
                                      : e == 3 ? AMR_RATIO * (J + 1) : AMR_RATIO * J;
-                        int f = idx[l + 1].find(fi, fj);
+                        int f = idx[l + 1].find(fi, fj, h_f);
                         const PatchInfo &F = c->patches[f];
                         long long fI0 = c->pI0[f], fJ0 = c->pJ0[f];
                         r.fp[e] = f;

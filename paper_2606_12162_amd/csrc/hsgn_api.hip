@@ -458,15 +458,16 @@ struct TableMemory {
         }
         (void)hipHostFree(p);
     }
+    // never torn down: a table may be freed late in the process's exit
     static std::mutex &m()
     {
-        static std::mutex x;
-        return x;
+        static std::mutex *x = new std::mutex();
+        return *x;
     }
     static std::set<void *> &plain()
     {
-        static std::set<void *> x;
-        return x;
+        static std::set<void *> *x = new std::set<void *>();
+        return *x;
     }
 };
 
@@ -693,9 +694,9 @@ class HostPool {
 public:
     static HostPool &get()
     {
-        static std::mutex gm;
+        static std::mutex *gm = new std::mutex();
         static HostPool *pool = nullptr;
-        std::lock_guard<std::mutex> lk(gm);
+        std::lock_guard<std::mutex> lk(*gm);
         if (!pool || pool->pid != getpid()) pool = new HostPool();
         return *pool;
     }

@@ -1713,12 +1713,17 @@ int hsgn_finalize(hsgn_ctx *c)
             for (size_t k = 0; k < recs[l].size(); k++) jobs.push_back({l, (int)k});
         auto place = [&](int t, int nt) {
             for (size_t j = (size_t)t; j < jobs.size(); j += (size_t)nt) {
-                const PatchRecs &r = recs[jobs[j].first][jobs[j].second];
+                PatchRecs &r = recs[jobs[j].first][jobs[j].second];
                 const Off &o = off[jobs[j].first][jobs[j].second];
                 std::copy(r.gc.begin(), r.gc.end(), c->h_gc.begin() + o.gc);
                 std::copy(r.gi.begin(), r.gi.end(), c->h_gi.begin() + o.gi);
                 std::copy(r.fr.begin(), r.fr.end(), c->h_fr.begin() + o.fr);
                 std::copy(r.av.begin(), r.av.end(), c->h_av.begin() + o.av);
+                // released here, on the workers, rather than one by one after
+                std::vector<GhostCopy>().swap(r.gc);
+                std::vector<GhostInterp>().swap(r.gi);
+                std::vector<FluxRec>().swap(r.fr);
+                std::vector<AvgRec>().swap(r.av);
             }
         };
         const int nt = jobs.size() > 64 ? host_threads() : 1;

@@ -909,10 +909,12 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
     for (int l = 0; l < nl; l++) {
         const std::vector<int> &L = sh.lev[l];
         std::vector<PatchRecs> recs(L.size());
-        const int nt = L.size() > 8 ? nthreads : 1;
-        HostPool::get().parallel_for(nt, [&](int t) {
-            for (size_t k = (size_t)t; k < L.size(); k += (size_t)nt) build_one(l, L[k], recs[k]);
-        });
+        // one task per patch (patches differ in size; the workers take them
+        // as they come free)
+        if (L.size() > 8)
+            HostPool::get().parallel_for((int)L.size(), [&](int k) { build_one(l, L[k], recs[k]); });
+        else
+            for (size_t k = 0; k < L.size(); k++) build_one(l, L[k], recs[k]);
         for (auto &r : recs)
             if (r.err) return fail(c, HSGN_EINVAL, r.err);
         for (auto &r : recs) lev_recs[l].push_back(std::move(r));
@@ -963,7 +965,7 @@ static int build_patch_set(hsgn_ctx *c, int s, std::vector<std::vector<PatchRecs
             // the records of the candidates, in chunks on host threads joined
             // in order
             const size_t ncand = cand.size();
-            const int nt = ncand >= 4096 ? nthreads : 1;
+            const int nt = ncand >= 4096 ? 4 * nthreads : 1;
             std::vector<std::vector<RefluxRec>> part(nt);
             auto reflux_chunk = [&](int t) {
                 int h_c = -1, h_f = -1, h_cov = -1;               // last hits of find
@@ -1639,7 +1641,7 @@ int hsgn_finalize(hsgn_ctx *c)
                 std::vector<AvgRec>().swap(r.av);
             }
         };
-        const int nt = jobs.size() > 64 ? host_threads() : 1;
+        const int nt = jobs.size() > 64 ? 4 * host_threads() : 1;
         HostPool::get().parallel_for(nt, [&](int t) { place(t, nt); });
     }
     // the tables are checked on a host thread while the device buffers are

@@ -3504,12 +3504,11 @@ int hsgn_regrid(hsgn_ctx *c, int scenario, const hsgn_regrid_params *r, int *n_n
                                  AMR_RATIO * (c->pI0[pid] + i0), AMR_RATIO * (c->pJ0[pid] + j0)});
         }
     };
-    {
-        const int nt = np_l > 8 ? host_threads() : 1;
-        HostPool::get().parallel_for(nt, [&](int t) {
-            for (size_t k = (size_t)t; k < np_l; k += (size_t)nt) cluster_one(k);
-        });
-    }
+    // one task per patch (the flags and so the clustering work differ)
+    if (np_l > 8)
+        HostPool::get().parallel_for((int)np_l, [&](int k) { cluster_one((size_t)k); });
+    else
+        for (size_t k = 0; k < np_l; k++) cluster_one(k);
     for (auto &v : pboxes) boxes.insert(boxes.end(), v.begin(), v.end());
     // 5. the new context: every patch of the other scenarios, the levels <= l
     // of this one, then the new boxes

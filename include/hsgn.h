@@ -32,6 +32,11 @@
  *     clocks and gauge records.  Its patch-set tables (ghost cells, boundary
  *     fluxes, covered cells; 16 to 56 bytes per record) are kept in pinned
  *     host memory too, or ordinary memory where pinning fails.
+ *   - Calls on one context must not overlap; calls on different contexts
+ *     may come from different host threads.  hsgn_finalize and hsgn_regrid
+ *     build and check their tables on a shared set of host worker threads
+ *     (at most 16, made on first use); such calls from several threads take
+ *     turns for them.
  *   - A scenario is an independent simulation with its own clock and time
  *     step; each patch belongs to one scenario.
  *   - Patch sets (static AMR, the block-structured refinement of Sec. 4): a

@@ -1232,7 +1232,7 @@ static int choose_rows(const hsgn_ctx *c, int level)
     const long long slots = 256LL * 4 * (c->mixed ? 2 : 1);
     int best = 64;
     long long best_cost = -1;
-    for (int th = 64; th >= 8; th--) {
+    for (int th = 64; th >= 2; th--) {
         long long waves = 0;
         for (const PatchInfo &p : c->patches)
             if (p.level == level) waves += (long long)((p.nx + 59) / 60) * ((p.ny + th - 1) / th);
@@ -2632,7 +2632,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
         x.err = 0;
     }
     if ((rc = push_scen(c, st))) return rc;
-    static const int cand[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64};
+    static const int cand[] = {2, 4, 6, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64};
     // scratch work table, packed items and clip slots for the largest
     // candidate table
     std::vector<WorkItem> wk;

@@ -277,7 +277,8 @@ int hsgn_set_clock(hsgn_ctx *c, int scenario, double t, double dt_next,
  * the paper defines them.
  * Tile-height autotuning: for every refinement level, times `trials`
  * step-kernel launches (after one warm-up) for each candidate height in
- * {2, 4, 6, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64} on the current state, and keeps
+ * {2, 4, 6, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64} and the height of the
+ * library's cost model (the choice with tile_rows <= 0) on the current state, and keeps
  * the fastest.  The state does not advance (the launches write only the
  * spare buffer and the clocks are restored).  rows[nlevels] (may be NULL)
  * receives the chosen heights.  Call after the state is set; drops the

@@ -1226,9 +1226,8 @@ int hsgn_add_grid(hsgn_ctx *c, int scenario, int level, int nx, int ny, double x
 // FP64) tiles at a time, so a level of W(th) tiles takes about
 // ceil(W(th) / slots) * (th + 4) row times; the smallest such cost wins
 // (ties: the taller tile).
-static int choose_rows(const hsgn_ctx *c, int level)
+static int model_rows(const hsgn_ctx *c, int level)
 {
-    if (c->prm.tile_rows > 0) return c->prm.tile_rows;
     const long long slots = 256LL * 4 * (c->mixed ? 2 : 1);
     int best = 64;
     long long best_cost = -1;
@@ -1240,6 +1239,11 @@ static int choose_rows(const hsgn_ctx *c, int level)
         if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = th; }
     }
     return best;
+}
+
+static int choose_rows(const hsgn_ctx *c, int level)
+{
+    return c->prm.tile_rows > 0 ? c->prm.tile_rows : model_rows(c, level);
 }
 
 // marching work items with tile heights th[level]: clock slots in order; on
@@ -2633,6 +2637,17 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
     }
     if ((rc = push_scen(c, st))) return rc;
     static const int cand[] = {2, 4, 6, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64};
+    // per level: these heights and the cost model's own choice, ascending
+    // (the model lands between them for grids that fill the chip in one round)
+    std::vector<std::vector<int>> cands(c->nlev);
+    for (int l = 0; l < c->nlev; l++) {
+        cands[l].assign(std::begin(cand), std::end(cand));
+        const int m = model_rows(c, l);
+        if (std::find(cands[l].begin(), cands[l].end(), m) == cands[l].end()) {
+            cands[l].push_back(m);
+            std::sort(cands[l].begin(), cands[l].end());
+        }
+    }
     // scratch work table, packed items and clip slots for the largest
     // candidate table
     std::vector<WorkItem> wk;
@@ -2641,7 +2656,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
     std::vector<LevelRange> L = c->L;
     size_t wmax = 1, pmax = 1;
     for (int l = 0; l < c->nlev; l++)
-        for (int th : cand) {
+        for (int th : cands[l]) {
             std::vector<int> thl = c->th_level;
             thl[l] = th;
             build_work(c, thl, wk, pk, ss, L);
@@ -2696,7 +2711,7 @@ int hsgn_autotune(hsgn_ctx *c, int trials, int *rows)
         }
         double best_ms = -1.0;
         int prev = 0;
-        for (int th : cand) {
+        for (int th : cands[l]) {
             if (prev >= maxny) break;           // taller tiles give the same work table
             prev = th;
             std::vector<int> thl = c->th_level;
